@@ -1,0 +1,232 @@
+/*
+ * libkkt -- Newton-step KKT solves for dynamic nonlinear programs on one MI355X.
+ *
+ * The interior-point method of Pacaud & Shin (arXiv 2403.15913) needs, at every
+ * iteration, the solution of the condensed KKT system (eq. (kkt:condensed)).
+ * This library provides its two hybrid forms:
+ *
+ *   Lifted-KKT (section "Solution 1: Lifted-KKT", eq. (liftedkkt)): every
+ *     constraint is relaxed to an inequality, the condensed matrix
+ *         K = W + diag(Sigma_x) + J^T diag(Sigma_s) J
+ *     is symmetric positive definite and K x = b is solved by sparse Cholesky
+ *     followed by Richardson iterative refinement (section "Hybrid linear
+ *     solver").
+ *   HyKKT (section "Solution 2: HyKKT", eqs. (hykkt) and (schurcomp)):
+ *         K_gamma = W + diag(Sigma_x) + gamma J^T J
+ *     is factored by sparse Cholesky and
+ *         [[W + Sigma_x, J^T], [J, 0]] [dx; dy] = [f; g]
+ *     is solved by conjugate gradient on the Schur complement
+ *     S_gamma = J K_gamma^{-1} J^T, applied matrix-free.
+ *
+ * The pattern of K is fixed across interior-point iterations, so the symbolic
+ * analysis (ordering, elimination tree, supernodes) runs once per pattern and
+ * is reused by every refactorisation (section "Hybrid linear solver").
+ *
+ * Notation (paper -> library): the Hessian W_k -> W; the Jacobian of the
+ * relaxed constraints H_k (Lifted-KKT) or of the equality constraints G_k
+ * (HyKKT) -> J; the slack diagonal D_s = S^{-1} V -> Sigma_s; the primal
+ * regularisation delta_x I plus bound terms -> Sigma_x.
+ *
+ * Conventions shared by every entry point:
+ *   - Index arrays (patterns) are HOST memory, 0-based int32 CSR, read during
+ *     the call only. W is given by its lower triangle (col <= row), every row
+ *     with strictly ascending columns; J is m x n with strictly ascending
+ *     columns in each row. The diagonal of K is always part of its pattern.
+ *   - Value, Sigma, right-hand-side and solution arrays are DEVICE pointers
+ *     (FP64) in the entry order fixed by the pattern. The caller owns them and
+ *     must keep inputs alive until the stream has passed the call.
+ *   - The library owns the symbolic objects, factors and all workspaces.
+ *   - Calls that take a `stream` (a hipStream_t; NULL = the default stream)
+ *     enqueue their work on it and return without waiting, except that an
+ *     entry point given a non-NULL info pointer synchronises the stream and
+ *     fills the info.
+ *   - No exception crosses the ABI. Host-side validation errors return at
+ *     once; errors found on the device (a non-positive pivot, non-finite
+ *     values) are latched in the factor and returned by the next
+ *     synchronising call.
+ *   - The right-hand-side sign is positive (K x = b); a caller holding the
+ *     paper's -r negates it.
+ *   - A symbolic object is immutable and may be shared between factors and
+ *     threads; a factor is used by one host thread / stream at a time.
+ */
+#ifndef KKT_H
+#define KKT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t kkt_status;
+#define KKT_OK 0
+#define KKT_ERR_INVALID_ARG 1   /* NULL pointer, negative size, bad option */
+#define KKT_ERR_PATTERN 2       /* malformed CSR, duplicate entries, unsupported front size */
+#define KKT_ERR_STATE 3         /* call not valid in the object's state (e.g. solve on a failed factor) */
+#define KKT_ERR_NOT_SPD 4       /* a pivot of K (or K_gamma) was not positive */
+#define KKT_ERR_NONFINITE 5     /* NaN or Inf in the values */
+#define KKT_ERR_NOT_CONVERGED 6 /* refinement or CG reached its iteration limit */
+#define KKT_ERR_BREAKDOWN 7     /* CG found p^T S p <= 0 (J rank deficient or K_gamma not SPD) */
+#define KKT_ERR_OOM 8           /* device allocation failed */
+#define KKT_ERR_BUDGET 9        /* request does not fit the server's memory budget */
+#define KKT_ERR_DEVICE 10       /* HIP runtime error */
+
+#define KKT_ORDER_AUTO 0
+#define KKT_ORDER_NATURAL 1
+#define KKT_ORDER_ND 2
+
+typedef struct kkt_options {
+    int32_t ordering;      /* KKT_ORDER_*; AUTO picks nested dissection for large patterns */
+    int32_t nd_leaf;       /* nested dissection stops splitting parts of at most this many variables (0: auto) */
+    int32_t max_super;     /* widest supernode in columns (0: 96) */
+    int32_t relax_small;   /* supernodes up to this width always amalgamate (0: 16, <0: none) */
+    double relax_frac;     /* amalgamation may add up to this fraction of explicit zeros (<0: 0.5) */
+} kkt_options;
+
+typedef struct kkt_symbolic_stats {
+    int32_t n, m;
+    int32_t nsuper;        /* supernodes */
+    int32_t levels;        /* depth of the supernode tree */
+    int32_t max_rows;      /* largest front (rows) */
+    int32_t max_cols;      /* widest supernode */
+    int64_t nnz_k;         /* entries of the lower triangle of K */
+    int64_t nnz_l;         /* stored entries of L (dense supernode panels, diagonal included) */
+    int64_t nnz_l_exact;   /* entries of the exact Cholesky structure, diagonal included */
+    int64_t n_pairs;       /* J^T J contribution products per assembly */
+    double flops;          /* dense front work of one factorisation */
+    double flops_exact;    /* sum over columns of (column count)^2 */
+    double analyze_seconds;
+} kkt_symbolic_stats;
+
+typedef struct kkt_refine_opts {
+    int32_t max_iter;      /* Richardson corrections after the first solve (default 10) */
+    double tol;            /* stop when the componentwise backward error omega <= tol (default 1e-14) */
+} kkt_refine_opts;
+
+typedef struct kkt_solve_info {
+    int32_t status;        /* KKT_OK, KKT_ERR_NOT_SPD (factor failed), KKT_ERR_NOT_CONVERGED */
+    int32_t iters;         /* corrections applied */
+    double eta;            /* normwise backward error ||b-Kx||_inf / (||K||_inf ||x||_inf + ||b||_inf) */
+    double omega;          /* componentwise backward error max_i |b-Kx|_i / (|K||x|+|b|)_i */
+    double relres;         /* ||b-Kx||_inf / ||b||_inf */
+} kkt_solve_info;
+
+typedef struct kkt_cg_info {
+    int32_t status;        /* KKT_OK, KKT_ERR_NOT_CONVERGED, KKT_ERR_BREAKDOWN, KKT_ERR_NOT_SPD */
+    int32_t iters;         /* CG iterations */
+    double rel_res;        /* recurrence residual ||r||_2 / ||c||_2 at exit */
+} kkt_cg_info;
+
+typedef struct kkt_factor_info {
+    int32_t status;        /* KKT_OK, KKT_ERR_NOT_SPD, KKT_ERR_NONFINITE */
+    int32_t bad_col;       /* original index of the first failing pivot in elimination order, else -1 */
+} kkt_factor_info;
+
+typedef struct kkt_symbolic kkt_symbolic;
+typedef struct kkt_factor kkt_factor;
+typedef struct kkt_batch kkt_batch;
+typedef struct kkt_server kkt_server;
+
+/* Fills *opt with the defaults. */
+void kkt_options_default(kkt_options* opt);
+
+/* Human-readable name of a status code (static string). */
+const char* kkt_status_string(kkt_status s);
+
+/* Message of the last error raised on the calling thread (static per thread). */
+const char* kkt_last_error(void);
+
+/*
+ * Symbolic analysis of K = W + Sigma_x + J^T d J (section "Hybrid linear
+ * solver": computed once per pattern and reused by every refactorisation).
+ * n variables, m rows of J; patterns as described above (host, int32 CSR,
+ * w_rowptr has n+1 entries, j_rowptr m+1). opt may be NULL (defaults).
+ * On success *out owns the analysis; release it with kkt_symbolic_destroy.
+ * Errors: INVALID_ARG (NULL out, negative sizes), PATTERN (malformed CSR,
+ * a front larger than one workgroup's LDS can hold). Host only.
+ */
+kkt_status kkt_symbolic_analyze(int32_t n, int32_t m,
+                                const int32_t* w_rowptr, const int32_t* w_colind,
+                                const int32_t* j_rowptr, const int32_t* j_colind,
+                                const kkt_options* opt, kkt_symbolic** out);
+
+/* Statistics of an analysis (host only). */
+kkt_status kkt_symbolic_get_stats(const kkt_symbolic* sym, kkt_symbolic_stats* out);
+
+/* perm[k] = original index of the k-th pivot (host array of n entries). */
+kkt_status kkt_symbolic_get_perm(const kkt_symbolic* sym, int32_t* perm);
+
+/* Supernode partition: col_ptr (nsuper+1: first pivot of each supernode),
+ * parent (nsuper: parent supernode or -1), nrows (nsuper: front rows).
+ * Any pointer may be NULL. Host only. */
+kkt_status kkt_symbolic_get_supernodes(const kkt_symbolic* sym, int32_t* col_ptr, int32_t* parent, int32_t* nrows);
+
+void kkt_symbolic_destroy(kkt_symbolic* sym);
+
+/*
+ * Device storage for one numeric factorisation of a pattern: the supernode
+ * panels of L, the update matrices of the multifrontal assembly, the
+ * assembled values of K and solve workspaces. The symbolic object must
+ * outlive the factor. Errors: INVALID_ARG, OOM, DEVICE.
+ */
+kkt_status kkt_factor_create(const kkt_symbolic* sym, kkt_factor** out);
+void kkt_factor_destroy(kkt_factor* f);
+
+/*
+ * Numeric refactorisation with new values (same pattern).
+ *   w_vals  (nnz_W)  lower-triangle values of W, CSR entry order
+ *   j_vals  (nnz_J)  values of J, CSR entry order
+ *   sigma_x (n)      primal diagonal
+ *   gamma == 0, sigma_s (m) slack diagonal -> Lifted-KKT: K = W + Sx + J^T diag(sigma_s) J
+ *                           (sigma_s may be NULL only when m == 0)
+ *   gamma > 0, sigma_s NULL                -> HyKKT:      K_gamma = W + Sx + gamma J^T J
+ * Device pointers; asynchronous on `stream`. A non-positive or non-finite pivot
+ * is latched (see kkt_status_sync). Errors returned at once: INVALID_ARG
+ * (NULL pointers, negative or non-finite gamma, sigma_s given with gamma > 0), DEVICE.
+ */
+kkt_status kkt_refactor(kkt_factor* f, const double* w_vals, const double* j_vals,
+                        const double* sigma_x, const double* sigma_s, double gamma, void* stream);
+
+/*
+ * Waits for the stream work of the factor and reports the latched status:
+ * KKT_OK, KKT_ERR_NOT_SPD (info->bad_col = original index of the first
+ * failing pivot in elimination order) or KKT_ERR_NONFINITE. info may be NULL.
+ */
+kkt_status kkt_status_sync(kkt_factor* f, kkt_factor_info* info);
+
+/*
+ * Solves K x = b (Lifted-KKT) or K_gamma x = b (HyKKT factor) with the current
+ * factor: a forward and backward sweep, then Richardson refinement
+ * r = b - K x, x += K^{-1} r, stopping when omega <= ro->tol, after
+ * ro->max_iter corrections, or when omega fails to halve; the iterate with the
+ * smaller omega of the last two is returned. b and x are device arrays of n
+ * (x may not alias b). ro may be NULL (defaults). With info == NULL the call
+ * is asynchronous; otherwise it synchronises and returns KKT_ERR_NOT_SPD if
+ * the factor failed or KKT_ERR_NOT_CONVERGED if omega > tol at exit (x still
+ * holds the best iterate).
+ */
+kkt_status kkt_solve(kkt_factor* f, const double* b, double* x, const kkt_refine_opts* ro,
+                     kkt_solve_info* info, void* stream);
+
+/*
+ * HyKKT (eqs. (hykkt), (schurcomp)): with f factored as K_gamma (sigma_s NULL,
+ * gamma > 0), solves [[W + Sx, J^T], [J, 0]] [dx; dy] = [fv; g]:
+ *   f_gamma = fv + gamma J^T g;  c = J K_gamma^{-1} f_gamma - g;
+ *   CG from dy = 0 on S_gamma dy = c, S_gamma = J K_gamma^{-1} J^T (matrix-free),
+ *   until ||r||_2 <= tol ||c||_2 or maxit iterations;
+ *   dx = K_gamma^{-1}(f_gamma - J^T dy).
+ * fv (n), g (m), dx (n), dy (m) are device arrays. Returns STATE on a
+ * Lifted-KKT factor. With info == NULL the call is asynchronous; otherwise it
+ * synchronises and reports NOT_SPD / NOT_CONVERGED / BREAKDOWN.
+ */
+kkt_status kkt_cg_schur(kkt_factor* f, const double* fv, const double* g, double tol, int32_t maxit,
+                        double* dx, double* dy, kkt_cg_info* info, void* stream);
+
+/* Matrix-vector product y = K x with the assembled K of the current factor
+ * (device arrays of n). Asynchronous. Used to evaluate residuals. */
+kkt_status kkt_matvec(kkt_factor* f, const double* x, double* y, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KKT_H */

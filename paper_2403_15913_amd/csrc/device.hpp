@@ -1,0 +1,94 @@
+// Device-side descriptors shared by the host orchestration (api.cpp) and the
+// HIP kernels (kernels.hip). Plain structs of device pointers: one PatDev per
+// uploaded symbolic analysis, one InstDev per numeric instance (a factor, or
+// one member of a batch). Kernels receive an array of InstDev and a work list
+// of (instance, supernode) or (instance, row block) pairs, so the single
+// instance, the batched and the served forms run the same kernels.
+#pragma once
+#include <cstdint>
+
+namespace kkt {
+
+struct PatDev {
+    int n, m, ns;
+    int nlevels;
+    const int* sn_col0;     // ns+1
+    const int* sn_ncol;
+    const int* sn_nrow;
+    const int64_t* sn_rowofs;
+    const int64_t* sn_lofs;
+    const int64_t* sn_uofs;
+    const int64_t* sn_vofs;
+    const int* rows;
+    const int* rel;
+    const int* ch_ptr;
+    const int* ch_list;
+    const int64_t* k_snptr;
+    const int* k_loc;
+    const int* k_w;
+    const int* k_diag;
+    const int64_t* k_pptr;
+    const int* pair_a;
+    const int* pair_b;
+    const int* jrow;
+    const int* perm;
+    const int* iperm;
+    const int64_t* sp_ptr;
+    const int* sp_e;
+    const int* sp_col;
+    const int* j_ptr;
+    const int* j_col;
+    const int* jt_ptr;
+    const int* jt_e;
+    const int* jt_row;
+};
+
+// Ordered-bits accumulators: a non-negative double compares like its bit
+// pattern read as an unsigned integer, so max-reductions use integer atomics
+// and are independent of the order in which blocks arrive.
+enum { ACC_RMAX = 0, ACC_OMEGA, ACC_KNORM, ACC_XMAX, ACC_BMAX, ACC_N };
+
+struct RefineState {
+    unsigned long long acc[ACC_N];
+    double omega, omega_prev, eta, eta_prev, relres, relres_prev;
+    double tol;
+    int maxit;
+    int it;        // corrections applied so far
+    int done;      // 1: stop refining this instance
+    int revert;    // 1: the previous iterate is the better one
+};
+
+// Conjugate-gradient scalars of one instance (eq. (schurcomp)).
+struct CgState {
+    double rr, rr_new, pq, cnorm, alpha, beta, tol;
+    int it, maxit, done, status;
+};
+
+struct InstDev {
+    PatDev P;
+    // numeric storage owned by the factor
+    double* L;          // supernode panels, column-major, leading dimension = front rows
+    double* U;          // update matrices, column-major u x u
+    double* V;          // solve update vectors
+    double* kval;       // assembled lower-triangle entries of K (grouped by supernode)
+    double* y;          // permuted work vector (n)
+    double* r;          // residual (n)
+    double* xprev;      // previous refinement iterate (n)
+    double* tn;         // scratch (n)
+    double* fg;         // HyKKT f_gamma (n)
+    double* cvec;       // HyKKT Schur right-hand side c (m)
+    double* rvec;       // CG residual (m)
+    double* pvec;       // CG direction (m)
+    double* qvec;       // S_gamma p (m)
+    double* red;        // per-block partial sums (deterministic reductions)
+    int* status;        // [0] latched status, [1] first failing pivot (permuted index)
+    RefineState* rs;
+    CgState* cg;
+};
+
+struct WorkItem {
+    int inst;
+    int id;   // supernode, or first row of a block
+};
+
+}  // namespace kkt

@@ -1,0 +1,64 @@
+// Host-callable launch wrappers for the HIP kernels in kernels.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace kkt {
+
+// Per-call caller pointers of one instance (values of a refactorisation and
+// the vectors of a solve). Passed by value for a single instance, or as a
+// device array for batches.
+struct CallPtrs {
+    const double* w;
+    const double* jv;
+    const double* sx;
+    const double* ss;   // NULL -> K_gamma with row weight gamma
+    double gamma;
+    const double* b;    // Lifted-KKT solve
+    double* x;
+    const double* f;    // HyKKT solve
+    const double* g;
+    double* dx;
+    double* dy;
+};
+
+struct Calls {
+    const CallPtrs* arr;  // device array indexed by instance, or NULL
+    CallPtrs one;         // used when arr is NULL
+};
+
+constexpr int kBlock = 256;
+
+hipError_t set_kernel_attributes();
+
+void launch_fill_i32(int* p, int v, int64_t n, hipStream_t st);
+void launch_assemble(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st);
+void launch_factor(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, hipStream_t st);
+void launch_fwd(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, hipStream_t st);
+void launch_bwd(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, hipStream_t st);
+
+// permutation modes
+enum { PIN_B = 0, PIN_R = 1, PIN_TN = 2, PIN_FG = 3 };
+enum { POUT_X = 0, POUT_X_UPDATE = 1, POUT_TN = 2, POUT_DX = 3 };
+void launch_perm_in(const InstDev* insts, const Calls& C, const WorkItem* rows, int nitems, int mode, hipStream_t st);
+void launch_perm_out(const InstDev* insts, const Calls& C, const WorkItem* rows, int nitems, int mode, hipStream_t st);
+
+void launch_refine_reset(const InstDev* insts, int ninst, double tol, int maxit, hipStream_t st);
+void launch_residual(const InstDev* insts, const Calls& C, const WorkItem* rows, int nitems, hipStream_t st);
+void launch_refine_decide(const InstDev* insts, int ninst, int* ndone, hipStream_t st);
+void launch_refine_revert(const InstDev* insts, const Calls& C, const WorkItem* rows, int nitems, hipStream_t st);
+void launch_matvec(const InstDev* insts, const double* x, double* y, const WorkItem* rows, int nitems, hipStream_t st);
+
+// Schur-complement CG (one instance per CgState)
+void launch_cg_fgamma(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, hipStream_t st);
+void launch_cg_init(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, hipStream_t st);
+void launch_cg_start(const InstDev* insts, int ninst, double tol, int maxit, int* ndone, hipStream_t st);
+void launch_cg_jt(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, int dx_rhs, hipStream_t st);
+void launch_cg_jq(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, hipStream_t st);
+void launch_cg_alpha(const InstDev* insts, int ninst, int* ndone, hipStream_t st);
+void launch_cg_update(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, hipStream_t st);
+void launch_cg_beta(const InstDev* insts, int ninst, int* ndone, hipStream_t st);
+void launch_cg_p(const InstDev* insts, const WorkItem* mrows, int nitems, hipStream_t st);
+
+}  // namespace kkt

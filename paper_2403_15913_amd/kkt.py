@@ -1,0 +1,300 @@
+"""Python binding of libkkt (include/kkt.h): argument marshalling only.
+
+Every step of the solve runs in the library's HIP kernels; this module only
+converts NumPy index arrays and torch device tensors into the pointers the C
+ABI takes. It raises if the library has not been built -- there is no
+fallback path.
+
+Functions carry the C names (``kkt_symbolic_analyze``, ``kkt_refactor``,
+``kkt_solve``, ``kkt_cg_schur`` ...); ``Symbolic`` and ``Factor`` wrap the
+handles for convenience.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkkt.so")
+
+KKT_OK = 0
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "PATTERN", 3: "STATE", 4: "NOT_SPD", 5: "NONFINITE",
+                6: "NOT_CONVERGED", 7: "BREAKDOWN", 8: "OOM", 9: "BUDGET", 10: "DEVICE"}
+ORDER_AUTO, ORDER_NATURAL, ORDER_ND = 0, 1, 2
+
+
+class KKTError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Options(C.Structure):
+    _fields_ = [("ordering", C.c_int32), ("nd_leaf", C.c_int32), ("max_super", C.c_int32),
+                ("relax_small", C.c_int32), ("relax_frac", C.c_double)]
+
+
+class SymbolicStats(C.Structure):
+    _fields_ = [("n", C.c_int32), ("m", C.c_int32), ("nsuper", C.c_int32), ("levels", C.c_int32),
+                ("max_rows", C.c_int32), ("max_cols", C.c_int32), ("nnz_k", C.c_int64), ("nnz_l", C.c_int64),
+                ("nnz_l_exact", C.c_int64), ("n_pairs", C.c_int64), ("flops", C.c_double),
+                ("flops_exact", C.c_double), ("analyze_seconds", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class RefineOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("tol", C.c_double)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("eta", C.c_double), ("omega", C.c_double),
+                ("relres", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class CgInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("rel_res", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class FactorInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("bad_col", C.c_int32)]
+
+
+# Names and signatures of every exported entry point (checked by the tests
+# against include/*.h).
+P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+SIGNATURES = {
+    "kkt_options_default": (None, [P]),
+    "kkt_status_string": (C.c_char_p, [I32]),
+    "kkt_last_error": (C.c_char_p, []),
+    "kkt_symbolic_analyze": (I32, [I32, I32, P, P, P, P, P, P]),
+    "kkt_symbolic_get_stats": (I32, [P, P]),
+    "kkt_symbolic_get_perm": (I32, [P, P]),
+    "kkt_symbolic_get_supernodes": (I32, [P, P, P, P]),
+    "kkt_symbolic_destroy": (None, [P]),
+    "kkt_factor_create": (I32, [P, P]),
+    "kkt_factor_destroy": (None, [P]),
+    "kkt_refactor": (I32, [P, P, P, P, P, D, P]),
+    "kkt_status_sync": (I32, [P, P]),
+    "kkt_solve": (I32, [P, P, P, P, P, P]),
+    "kkt_cg_schur": (I32, [P, P, P, D, I32, P, P, P, P]),
+    "kkt_matvec": (I32, [P, P, P, P]),
+}
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libkkt.so (built by paper_2403_15913_amd.build); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2403_15913_amd.build")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _err(st: int):
+    if st != KKT_OK:
+        raise KKTError(st, lib().kkt_last_error().decode())
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _ptr_np(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (float64, contiguous, on the GPU), or None."""
+    if t is None:
+        return None
+    if not (t.is_cuda and t.is_contiguous()):
+        raise ValueError("expected a contiguous GPU tensor")
+    import torch
+    if t.dtype != torch.float64:
+        raise ValueError("expected float64")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# functions with the C names
+# ---------------------------------------------------------------------------
+
+def kkt_options_default() -> Options:
+    o = Options()
+    lib().kkt_options_default(C.byref(o))
+    return o
+
+
+def kkt_symbolic_analyze(n, m, w_rowptr, w_colind, j_rowptr, j_colind, opt: Options | None = None):
+    wr, wc, jr, jc = _i32(w_rowptr), _i32(w_colind), _i32(j_rowptr), _i32(j_colind)
+    h = C.c_void_p()
+    st = lib().kkt_symbolic_analyze(n, m, _ptr_np(wr), _ptr_np(wc), _ptr_np(jr), _ptr_np(jc),
+                                    C.byref(opt) if opt is not None else None, C.byref(h))
+    _err(st)
+    return h
+
+
+def kkt_symbolic_get_stats(h) -> dict:
+    s = SymbolicStats()
+    _err(lib().kkt_symbolic_get_stats(h, C.byref(s)))
+    return s.as_dict()
+
+
+def kkt_symbolic_get_perm(h, n: int) -> np.ndarray:
+    out = np.empty(n, dtype=np.int32)
+    _err(lib().kkt_symbolic_get_perm(h, _ptr_np(out)))
+    return out
+
+
+def kkt_symbolic_get_supernodes(h, nsuper: int):
+    cp = np.empty(nsuper + 1, dtype=np.int32)
+    par = np.empty(nsuper, dtype=np.int32)
+    nr = np.empty(nsuper, dtype=np.int32)
+    _err(lib().kkt_symbolic_get_supernodes(h, _ptr_np(cp), _ptr_np(par), _ptr_np(nr)))
+    return cp, par, nr
+
+
+def kkt_symbolic_destroy(h):
+    lib().kkt_symbolic_destroy(h)
+
+
+def kkt_factor_create(sym_h):
+    h = C.c_void_p()
+    _err(lib().kkt_factor_create(sym_h, C.byref(h)))
+    return h
+
+
+def kkt_factor_destroy(h):
+    lib().kkt_factor_destroy(h)
+
+
+def kkt_refactor(h, w_vals, j_vals, sigma_x, sigma_s=None, gamma: float = 0.0, stream=None):
+    _err(lib().kkt_refactor(h, _dptr(w_vals), _dptr(j_vals), _dptr(sigma_x), _dptr(sigma_s), float(gamma),
+                            _stream(stream)))
+
+
+def kkt_status_sync(h):
+    fi = FactorInfo()
+    st = lib().kkt_status_sync(h, C.byref(fi))
+    return st, fi.bad_col
+
+
+def kkt_solve(h, b, x, max_iter: int = 10, tol: float = 1e-14, info: bool = True, stream=None):
+    ro = RefineOpts(max_iter, tol)
+    si = SolveInfo()
+    st = lib().kkt_solve(h, _dptr(b), _dptr(x), C.byref(ro), C.byref(si) if info else None, _stream(stream))
+    if st not in (KKT_OK, 6):
+        _err(st)
+    return si.as_dict() if info else None
+
+
+def kkt_cg_schur(h, f, g, dx, dy, tol: float = 1e-10, maxit: int = 200, info: bool = True, stream=None):
+    ci = CgInfo()
+    st = lib().kkt_cg_schur(h, _dptr(f), _dptr(g), float(tol), int(maxit), _dptr(dx), _dptr(dy),
+                            C.byref(ci) if info else None, _stream(stream))
+    if st not in (KKT_OK, 6, 7):
+        _err(st)
+    return ci.as_dict() if info else None
+
+
+def kkt_matvec(h, x, y, stream=None):
+    _err(lib().kkt_matvec(h, _dptr(x), _dptr(y), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# handle wrappers
+# ---------------------------------------------------------------------------
+
+class Symbolic:
+    """Symbolic analysis of one (W, J) pattern (host only)."""
+
+    def __init__(self, n, m, w_rowptr, w_colind, j_rowptr, j_colind, ordering=ORDER_AUTO, nd_leaf=0,
+                 max_super=0, relax_small=0, relax_frac=-1.0):
+        opt = Options(ordering, nd_leaf, max_super, relax_small, relax_frac)
+        self.n, self.m = int(n), int(m)
+        self.h = kkt_symbolic_analyze(self.n, self.m, w_rowptr, w_colind, j_rowptr, j_colind, opt)
+
+    @classmethod
+    def from_pattern(cls, pat, **kw):
+        return cls(pat.n, pat.m, pat.w_rowptr, pat.w_colind, pat.j_rowptr, pat.j_colind, **kw)
+
+    def stats(self) -> dict:
+        return kkt_symbolic_get_stats(self.h)
+
+    def perm(self) -> np.ndarray:
+        return kkt_symbolic_get_perm(self.h, self.n)
+
+    def supernodes(self):
+        return kkt_symbolic_get_supernodes(self.h, self.stats()["nsuper"])
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            kkt_symbolic_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Factor:
+    """Device factor of one pattern (keeps a reference to its Symbolic)."""
+
+    def __init__(self, sym: Symbolic):
+        self.sym = sym
+        self.h = kkt_factor_create(sym.h)
+
+    def refactor(self, w_vals, j_vals, sigma_x, sigma_s=None, gamma=0.0, stream=None):
+        kkt_refactor(self.h, w_vals, j_vals, sigma_x, sigma_s, gamma, stream)
+
+    def status(self):
+        return kkt_status_sync(self.h)
+
+    def solve(self, b, x, max_iter=10, tol=1e-14, info=True, stream=None):
+        return kkt_solve(self.h, b, x, max_iter, tol, info, stream)
+
+    def cg_schur(self, f, g, dx, dy, tol=1e-10, maxit=200, info=True, stream=None):
+        return kkt_cg_schur(self.h, f, g, dx, dy, tol, maxit, info, stream)
+
+    def matvec(self, x, y, stream=None):
+        kkt_matvec(self.h, x, y, stream)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            kkt_factor_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
