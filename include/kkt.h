@@ -226,6 +226,29 @@ kkt_status kkt_cg_schur(kkt_factor* f, const double* fv, const double* g, double
  * (device arrays of n). Asynchronous. Used to evaluate residuals. */
 kkt_status kkt_matvec(kkt_factor* f, const double* x, double* y, void* stream);
 
+/* Kernel phases timed by the per-launch event timers. */
+#define KKT_PHASE_ASSEMBLE 0  /* K = W + Sigma_x + J^T d J */
+#define KKT_PHASE_FACTOR 1    /* supernodal Cholesky (one launch per tree level) */
+#define KKT_PHASE_FWD 2       /* forward sweep L y = P b */
+#define KKT_PHASE_BWD 3       /* backward sweep L^T z = y */
+#define KKT_PHASE_RESIDUAL 4  /* r = b - K x and backward-error reductions */
+#define KKT_PHASE_PERMUTE 5   /* gathers between original and pivot order */
+#define KKT_PHASE_CG 6        /* Schur-complement CG vector kernels (J^T p, J t, dots, axpys) */
+#define KKT_PHASE_CONTROL 7   /* small control kernels (fills, refinement / CG decisions) */
+#define KKT_NPHASES 8
+
+typedef struct kkt_timing {
+    double ms[KKT_NPHASES];        /* summed kernel time per phase (HIP events around every launch) */
+    int32_t launches[KKT_NPHASES]; /* number of launches per phase */
+} kkt_timing;
+
+/* Enables (1) or disables (0) per-launch HIP event timing for this factor. */
+kkt_status kkt_factor_set_timing(kkt_factor* f, int32_t enable);
+
+/* Synchronises the last stream used, returns the times accumulated since the
+ * previous read (or since timing was enabled) and resets them. */
+kkt_status kkt_factor_read_timing(kkt_factor* f, kkt_timing* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,6 +16,14 @@
 
 using namespace kkt;
 
+// Launch `expr` on stream `st`, bracketed by timer events when timing is on.
+#define TL(ph, expr)                               \
+    do {                                           \
+        if (f->timer.on) f->timer.begin(ph, st);   \
+        expr;                                      \
+        if (f->timer.on) f->timer.end(st);         \
+    } while (0)
+
 namespace kkt {
 
 thread_local std::string g_last_error;
@@ -61,6 +69,45 @@ static hipError_t upload(DevBuf& b, const std::vector<T>& v) {
     if (e != hipSuccess) return e;
     if (!v.empty()) e = hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
     return e;
+}
+
+LaunchTimer::~LaunchTimer() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
+void LaunchTimer::begin(int ph, hipStream_t st) {
+    if (used >= 100000) return;  // bounded: read the timers regularly
+    while (pool.size() < 2 * (used + 1)) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        pool.push_back(e);
+    }
+    if (phase.size() < used + 1) phase.resize(used + 1);
+    phase[used] = ph;
+    cur = pool[2 * used];
+    (void)hipEventRecord(cur, st);
+}
+
+void LaunchTimer::end(hipStream_t st) {
+    if (!cur) return;
+    (void)hipEventRecord(pool[2 * used + 1], st);
+    cur = nullptr;
+    used++;
+}
+
+hipError_t LaunchTimer::read(double* ms, int* launches, int nph) {
+    for (int q = 0; q < nph; q++) { ms[q] = 0.0; launches[q] = 0; }
+    if (used == 0) return hipSuccess;
+    hipError_t e = hipEventSynchronize(pool[2 * used - 1]);
+    if (e != hipSuccess) return e;
+    for (size_t q = 0; q < used; q++) {
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, pool[2 * q], pool[2 * q + 1]);
+        if (e != hipSuccess) return e;
+        if (phase[q] >= 0 && phase[q] < nph) { ms[phase[q]] += t; launches[phase[q]]++; }
+    }
+    used = 0;
+    return hipSuccess;
 }
 
 hipError_t DevPattern::build(const Symbolic& S) {
@@ -301,13 +348,13 @@ kkt_status kkt_refactor(kkt_factor* f, const double* w_vals, const double* j_val
     C.one.w = w_vals; C.one.jv = j_vals; C.one.sx = sigma_x; C.one.ss = sigma_s; C.one.gamma = gamma;
     const InstDev* di = (const InstDev*)f->dinst.p;
     int* status = (int*)f->status.p;
-    launch_fill_i32(status, 0, 1, st);
-    launch_fill_i32(status + 1, INT_MAX, 1, st);
-    launch_assemble(di, C, (const WorkItem*)f->pat.b_kitems.p, f->pat.n_kitems, st);
+    TL(KKT_PHASE_CONTROL, launch_fill_i32(status, 0, 1, st));
+    TL(KKT_PHASE_CONTROL, launch_fill_i32(status + 1, INT_MAX, 1, st));
+    TL(KKT_PHASE_ASSEMBLE, launch_assemble(di, C, (const WorkItem*)f->pat.b_kitems.p, f->pat.n_kitems, st));
     const WorkItem* items = (const WorkItem*)f->pat.b_snitems.p;
     for (size_t l = 0; l + 1 < f->pat.lvl_ptr.size(); l++) {
         int a = f->pat.lvl_ptr[l], b = f->pat.lvl_ptr[l + 1];
-        launch_factor(di, items + a, b - a, f->pat.lds_factor, st);
+        TL(KKT_PHASE_FACTOR, launch_factor(di, items + a, b - a, f->pat.lds_factor, st));
     }
     if (!lifted && S.nnz_j > 0) {
         hipError_t e = hipMemcpyAsync(f->jcopy.p, j_vals, S.nnz_j * 8, hipMemcpyDeviceToDevice, st);
@@ -344,8 +391,8 @@ void sweeps(kkt_factor* f, hipStream_t st) {
     const WorkItem* items = (const WorkItem*)f->pat.b_snitems.p;
     const auto& lp = f->pat.lvl_ptr;
     const int nl = (int)lp.size() - 1;
-    for (int l = 0; l < nl; l++) launch_fwd(di, items + lp[l], lp[l + 1] - lp[l], f->pat.lds_solve, st);
-    for (int l = nl - 1; l >= 0; l--) launch_bwd(di, items + lp[l], lp[l + 1] - lp[l], f->pat.lds_solve, st);
+    for (int l = 0; l < nl; l++) TL(KKT_PHASE_FWD, launch_fwd(di, items + lp[l], lp[l + 1] - lp[l], f->pat.lds_solve, st));
+    for (int l = nl - 1; l >= 0; l--) TL(KKT_PHASE_BWD, launch_bwd(di, items + lp[l], lp[l + 1] - lp[l], f->pat.lds_solve, st));
 }
 
 }  // namespace kkt
@@ -372,26 +419,26 @@ kkt_status kkt_solve(kkt_factor* f, const double* b, double* x, const kkt_refine
     const WorkItem* nit = (const WorkItem*)f->pat.b_nitems.p;
     const int nn = f->pat.n_nitems;
     int* ndone = (int*)f->ndone.p;
-    launch_refine_reset(di, 1, tol, maxit, st);
-    launch_fill_i32(ndone, 0, 1, st);
-    launch_perm_in(di, C, nit, nn, PIN_B, st);
+    TL(KKT_PHASE_CONTROL, launch_refine_reset(di, 1, tol, maxit, st));
+    TL(KKT_PHASE_CONTROL, launch_fill_i32(ndone, 0, 1, st));
+    TL(KKT_PHASE_PERMUTE, launch_perm_in(di, C, nit, nn, PIN_B, st));
     sweeps(f, st);
-    launch_perm_out(di, C, nit, nn, POUT_X, st);
+    TL(KKT_PHASE_PERMUTE, launch_perm_out(di, C, nit, nn, POUT_X, st));
     int* hp = (int*)f->hpin;
     for (int iter = 0; iter <= maxit + 1; iter++) {
-        launch_residual(di, C, nit, nn, st);
-        launch_refine_decide(di, 1, ndone, st);
+        TL(KKT_PHASE_RESIDUAL, launch_residual(di, C, nit, nn, st));
+        TL(KKT_PHASE_CONTROL, launch_refine_decide(di, 1, ndone, st));
         hipError_t e = hipMemcpyAsync(hp, ndone, 4, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipMemcpyAsync(hp + 1, f->status.p, 4, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "refinement control");
         if (hp[1] != 0) return fail(hp[1], "factor failed; solve refused");
         if (hp[0] >= 1) break;
-        launch_perm_in(di, C, nit, nn, PIN_R, st);
+        TL(KKT_PHASE_PERMUTE, launch_perm_in(di, C, nit, nn, PIN_R, st));
         sweeps(f, st);
-        launch_perm_out(di, C, nit, nn, POUT_X_UPDATE, st);
+        TL(KKT_PHASE_PERMUTE, launch_perm_out(di, C, nit, nn, POUT_X_UPDATE, st));
     }
-    launch_refine_revert(di, C, nit, nn, st);
+    TL(KKT_PHASE_PERMUTE, launch_refine_revert(di, C, nit, nn, st));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "solve launch");
     if (!info) return KKT_OK;
@@ -429,36 +476,36 @@ kkt_status kkt_cg_schur(kkt_factor* f, const double* fv, const double* g, double
     const int nn = f->pat.n_nitems, nm = f->pat.n_mitems;
     int* ndone = (int*)f->ndone.p;
     int* hp = (int*)f->hpin;
-    launch_fill_i32(ndone, 0, 1, st);
-    launch_cg_fgamma(di, C, nit, nn, st);
-    launch_perm_in(di, C, nit, nn, PIN_FG, st);
+    TL(KKT_PHASE_CONTROL, launch_fill_i32(ndone, 0, 1, st));
+    TL(KKT_PHASE_CG, launch_cg_fgamma(di, C, nit, nn, st));
+    TL(KKT_PHASE_PERMUTE, launch_perm_in(di, C, nit, nn, PIN_FG, st));
     sweeps(f, st);
-    launch_perm_out(di, C, nit, nn, POUT_TN, st);
-    launch_cg_init(di, C, mit, nm, st);
-    launch_cg_start(di, 1, tol, maxit, ndone, st);
+    TL(KKT_PHASE_PERMUTE, launch_perm_out(di, C, nit, nn, POUT_TN, st));
+    TL(KKT_PHASE_CG, launch_cg_init(di, C, mit, nm, st));
+    TL(KKT_PHASE_CONTROL, launch_cg_start(di, 1, tol, maxit, ndone, st));
     hipError_t e = hipMemcpyAsync(hp, ndone, 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipMemcpyAsync(hp + 1, f->status.p, 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "cg control");
     if (hp[1] != 0) return fail(hp[1], "factor failed; solve refused");
     for (int it = 0; hp[0] == 0 && it < maxit; it++) {
-        launch_cg_jt(di, C, nit, nn, 0, st);
-        launch_perm_in(di, C, nit, nn, PIN_TN, st);
+        TL(KKT_PHASE_CG, launch_cg_jt(di, C, nit, nn, 0, st));
+        TL(KKT_PHASE_PERMUTE, launch_perm_in(di, C, nit, nn, PIN_TN, st));
         sweeps(f, st);
-        launch_perm_out(di, C, nit, nn, POUT_TN, st);
-        launch_cg_jq(di, C, mit, nm, st);
-        launch_cg_alpha(di, 1, ndone, st);
-        launch_cg_update(di, C, mit, nm, st);
-        launch_cg_beta(di, 1, ndone, st);
-        launch_cg_p(di, mit, nm, st);
+        TL(KKT_PHASE_PERMUTE, launch_perm_out(di, C, nit, nn, POUT_TN, st));
+        TL(KKT_PHASE_CG, launch_cg_jq(di, C, mit, nm, st));
+        TL(KKT_PHASE_CONTROL, launch_cg_alpha(di, 1, ndone, st));
+        TL(KKT_PHASE_CG, launch_cg_update(di, C, mit, nm, st));
+        TL(KKT_PHASE_CONTROL, launch_cg_beta(di, 1, ndone, st));
+        TL(KKT_PHASE_CG, launch_cg_p(di, mit, nm, st));
         e = hipMemcpyAsync(hp, ndone, 4, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "cg control");
     }
-    launch_cg_jt(di, C, nit, nn, 1, st);
-    launch_perm_in(di, C, nit, nn, PIN_TN, st);
+    TL(KKT_PHASE_CG, launch_cg_jt(di, C, nit, nn, 1, st));
+    TL(KKT_PHASE_PERMUTE, launch_perm_in(di, C, nit, nn, PIN_TN, st));
     sweeps(f, st);
-    launch_perm_out(di, C, nit, nn, POUT_DX, st);
+    TL(KKT_PHASE_PERMUTE, launch_perm_out(di, C, nit, nn, POUT_DX, st));
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "cg launch");
     if (!info) return KKT_OK;
@@ -477,9 +524,25 @@ kkt_status kkt_matvec(kkt_factor* f, const double* x, double* y, void* stream) {
     if (!f || (!x && f->sym->S.n > 0) || (!y && f->sym->S.n > 0)) return fail(KKT_ERR_INVALID_ARG, "NULL argument");
     if (!f->factored) return fail(KKT_ERR_STATE, "matvec before refactor");
     hipStream_t st = (hipStream_t)stream;
-    launch_matvec((const InstDev*)f->dinst.p, x, y, (const WorkItem*)f->pat.b_nitems.p, f->pat.n_nitems, st);
+    TL(KKT_PHASE_RESIDUAL,
+       launch_matvec((const InstDev*)f->dinst.p, x, y, (const WorkItem*)f->pat.b_nitems.p, f->pat.n_nitems, st));
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? KKT_OK : hip_fail(e, "matvec launch");
+}
+
+kkt_status kkt_factor_set_timing(kkt_factor* f, int32_t enable) {
+    if (!f) return fail(KKT_ERR_INVALID_ARG, "NULL factor");
+    f->timer.on = enable != 0;
+    return KKT_OK;
+}
+
+kkt_status kkt_factor_read_timing(kkt_factor* f, kkt_timing* out) {
+    if (!f || !out) return fail(KKT_ERR_INVALID_ARG, "NULL argument");
+    int launches[KKT_NPHASES];
+    hipError_t e = f->timer.read(out->ms, launches, KKT_NPHASES);
+    if (e != hipSuccess) return hip_fail(e, "timer read");
+    for (int q = 0; q < KKT_NPHASES; q++) out->launches[q] = launches[q];
+    return KKT_OK;
 }
 
 }  // extern "C"

@@ -43,6 +43,20 @@ struct DevPattern {
     hipError_t build(const Symbolic& S);
 };
 
+// Per-launch HIP event timers, grouped by phase.
+struct LaunchTimer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<int> phase;     // phase of event pair q (events 2q, 2q+1)
+    size_t used = 0;            // pairs recorded since the last read
+    hipEvent_t cur = nullptr;
+    int cur_phase = 0;
+    ~LaunchTimer();
+    void begin(int ph, hipStream_t st);
+    void end(hipStream_t st);
+    hipError_t read(double* ms, int* launches, int nph);
+};
+
 }  // namespace kkt
 
 struct kkt_symbolic {
@@ -59,6 +73,7 @@ struct kkt_factor {
     int mode = 0;                  // 0 none, 1 Lifted-KKT, 2 HyKKT (K_gamma)
     double gamma = 0.0;
     bool factored = false;
+    kkt::LaunchTimer timer;
     ~kkt_factor() {
         if (hpin) (void)hipHostFree(hpin);
     }

@@ -69,6 +69,16 @@ class FactorInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("bad_col", C.c_int32)]
 
 
+PHASES = ["assemble", "factor", "fwd", "bwd", "residual", "permute", "cg", "control"]
+
+
+class Timing(C.Structure):
+    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int32 * 8)]
+
+    def as_dict(self):
+        return {p: dict(ms=self.ms[i], launches=self.launches[i]) for i, p in enumerate(PHASES)}
+
+
 # Names and signatures of every exported entry point (checked by the tests
 # against include/*.h).
 P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
@@ -88,6 +98,8 @@ SIGNATURES = {
     "kkt_solve": (I32, [P, P, P, P, P, P]),
     "kkt_cg_schur": (I32, [P, P, P, D, I32, P, P, P, P]),
     "kkt_matvec": (I32, [P, P, P, P]),
+    "kkt_factor_set_timing": (I32, [P, I32]),
+    "kkt_factor_read_timing": (I32, [P, P]),
 }
 
 _lib = None
@@ -228,6 +240,16 @@ def kkt_matvec(h, x, y, stream=None):
     _err(lib().kkt_matvec(h, _dptr(x), _dptr(y), _stream(stream)))
 
 
+def kkt_factor_set_timing(h, enable: bool):
+    _err(lib().kkt_factor_set_timing(h, 1 if enable else 0))
+
+
+def kkt_factor_read_timing(h) -> dict:
+    t = Timing()
+    _err(lib().kkt_factor_read_timing(h, C.byref(t)))
+    return t.as_dict()
+
+
 # ---------------------------------------------------------------------------
 # handle wrappers
 # ---------------------------------------------------------------------------
@@ -287,6 +309,12 @@ class Factor:
 
     def matvec(self, x, y, stream=None):
         kkt_matvec(self.h, x, y, stream)
+
+    def set_timing(self, enable=True):
+        kkt_factor_set_timing(self.h, enable)
+
+    def read_timing(self) -> dict:
+        return kkt_factor_read_timing(self.h)
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
