@@ -249,6 +249,104 @@ kkt_status kkt_factor_set_timing(kkt_factor* f, int32_t enable);
  * previous read (or since timing was enabled) and resets them. */
 kkt_status kkt_factor_read_timing(kkt_factor* f, kkt_timing* out);
 
+/*
+ * Batched form: many independent instances (each with its own pattern; the
+ * same symbolic object may appear several times) refactored and solved by
+ * the same launches. Every launch covers one tree level of all instances, so
+ * small NMPC-sized fronts from different instances share the GPU.
+ *
+ * Values and vectors are concatenated in instance order: instance q owns
+ * w_vals[w_ofs[q] .. w_ofs[q+1]), j_vals[j_ofs[q] ..), sigma_x / b / x
+ * [n_ofs[q] ..) and sigma_s [m_ofs[q] ..), as reported by kkt_batch_offsets.
+ * The symbolic objects must outlive the batch. Lifted-KKT only.
+ */
+kkt_status kkt_batch_create(int32_t count, const kkt_symbolic* const* syms, kkt_batch** out);
+void kkt_batch_destroy(kkt_batch* b);
+
+/* Prefix offsets (count+1 entries each; any pointer may be NULL). Host only. */
+kkt_status kkt_batch_offsets(const kkt_batch* b, int64_t* n_ofs, int64_t* m_ofs, int64_t* w_ofs, int64_t* j_ofs);
+
+/* Refactors every instance: K_q = W_q + Sx_q + J_q^T diag(Ss_q) J_q. Device
+ * arrays, asynchronous on `stream`; per-instance failures are latched. */
+kkt_status kkt_batch_refactor(kkt_batch* b, const double* w_vals, const double* j_vals,
+                              const double* sigma_x, const double* sigma_s, void* stream);
+
+/* Solves every instance with Richardson refinement (per-instance stop rule as
+ * in kkt_solve; instances that have stopped skip the remaining sweeps).
+ * infos, when non-NULL, receives `count` entries. Synchronises the stream.
+ * Returns NOT_SPD / NONFINITE if any factor failed, NOT_CONVERGED if any
+ * instance ended above tol, else OK. */
+kkt_status kkt_batch_solve(kkt_batch* b, const double* rhs, double* x, const kkt_refine_opts* ro,
+                           kkt_solve_info* infos, void* stream);
+
+/* Waits and reports each instance's factor status and failing column (original
+ * index, -1 if none); either array (count entries) may be NULL. */
+kkt_status kkt_batch_status(kkt_batch* b, int32_t* status, int32_t* bad_col);
+
+kkt_status kkt_batch_set_timing(kkt_batch* b, int32_t enable);
+kkt_status kkt_batch_read_timing(kkt_batch* b, kkt_timing* out);
+
+/*
+ * Served form: a request loop over resident sparsity patterns. A registered
+ * pattern's analysis stays on the device; each request is a refactor with new
+ * values plus a refined solve (the analysis is reused, section "Hybrid linear
+ * solver"). Requests queue FIFO; `workers` threads, each with its own HIP
+ * stream and an HBM arena of hbm_budget / workers bytes, repeatedly take the
+ * longest queue prefix that fits their arena (at most max_wave requests),
+ * gather its inputs, refactor + solve it as one batch and scatter the
+ * solutions. Requests arriving while waves run join the next free worker's
+ * wave, so waves overlap on the GPU. A request's result does not depend on
+ * the wave it rides in (no cross-request reductions).
+ */
+typedef struct kkt_server_opts {
+    int64_t hbm_budget;      /* bytes of device workspace for all workers (default 8 GiB) */
+    int32_t max_wave;        /* most requests per wave (default 64) */
+    int32_t workers;         /* waves in flight at once, 1..8 (default 2) */
+    int32_t refine_max_iter; /* Richardson corrections (default 10) */
+    double refine_tol;       /* omega target (default 1e-14) */
+    double linger_us;        /* a worker may wait this long for a fuller wave (default 0) */
+} kkt_server_opts;
+
+typedef struct kkt_server_stats {
+    int64_t submitted, completed, rejected, waves;
+    double mean_wave;        /* requests per wave */
+    double p50_s, p99_s;     /* latency from submit to result ready */
+    double mean_queue_s;     /* submit -> wave start */
+    double mean_service_s;   /* wave start -> result ready */
+    double throughput;       /* completed / window_s */
+    double window_s;         /* first submit -> last completion */
+} kkt_server_stats;
+
+void kkt_server_opts_default(kkt_server_opts* o);
+
+/* Creates the server, its worker threads, streams and arenas (device memory
+ * of hbm_budget bytes is allocated here). Errors: INVALID_ARG, OOM, DEVICE. */
+kkt_status kkt_server_create(const kkt_server_opts* opt, kkt_server** out);
+
+/* Uploads the pattern's analysis; *pattern_id names it in submissions. The
+ * symbolic object must outlive the server. BUDGET if one request of this
+ * pattern cannot fit a worker's arena. */
+kkt_status kkt_server_register(kkt_server* s, const kkt_symbolic* sym, int32_t* pattern_id);
+
+/* Queues one Lifted-KKT refactor+solve: device arrays in the pattern's entry
+ * order (w_vals, j_vals, sigma_x, sigma_s, b) and the output x (n). They must
+ * stay valid (inputs unchanged) until kkt_server_wait returns for *ticket.
+ * Returns at once. */
+kkt_status kkt_server_submit(kkt_server* s, int32_t pattern_id, const double* w_vals, const double* j_vals,
+                             const double* sigma_x, const double* sigma_s, const double* b, double* x,
+                             int64_t* ticket);
+
+/* Blocks until the request is done; returns its status (NOT_SPD, NONFINITE,
+ * NOT_CONVERGED or OK) and fills its solve info and latency (may be NULL).
+ * A ticket can be waited for once. */
+kkt_status kkt_server_wait(kkt_server* s, int64_t ticket, kkt_solve_info* info, double* latency_s);
+
+kkt_status kkt_server_get_stats(kkt_server* s, kkt_server_stats* out);
+kkt_status kkt_server_reset_stats(kkt_server* s);
+
+/* Finishes the queued requests, stops the workers and frees everything. */
+void kkt_server_destroy(kkt_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,13 +1,14 @@
 // C ABI of libkkt (declared in include/kkt.h): symbolic objects, device
-// factors, the Lifted-KKT solve with Richardson refinement and the HyKKT
-// Schur-complement CG (Pacaud & Shin, arXiv 2403.15913, sections "Condensed
-// KKT system" and "Hybrid linear solver").
+// factors and batches, the Lifted-KKT solve with Richardson refinement and
+// the HyKKT Schur-complement CG (Pacaud & Shin, arXiv 2403.15913, sections
+// "Condensed KKT system" and "Hybrid linear solver").
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -17,11 +18,11 @@
 using namespace kkt;
 
 // Launch `expr` on stream `st`, bracketed by timer events when timing is on.
-#define TL(ph, expr)                               \
-    do {                                           \
-        if (f->timer.on) f->timer.begin(ph, st);   \
-        expr;                                      \
-        if (f->timer.on) f->timer.end(st);         \
+#define TL(ph, expr)                              \
+    do {                                          \
+        if (timer.on) timer.begin(ph, st);        \
+        expr;                                     \
+        if (timer.on) timer.end(st);              \
     } while (0)
 
 namespace kkt {
@@ -112,7 +113,7 @@ hipError_t LaunchTimer::read(double* ms, int* launches, int nph) {
 
 hipError_t DevPattern::build(const Symbolic& S) {
     hipError_t e;
-#define UP(buf, vec, field, type)                  \
+#define UP(buf, vec, field, type)                         \
     if ((e = upload(buf, S.vec)) != hipSuccess) return e; \
     desc.field = (const type*)buf.p;
     desc.n = S.n;
@@ -128,6 +129,7 @@ hipError_t DevPattern::build(const Symbolic& S) {
     UP(b_vofs, sn_vofs, sn_vofs, int64_t)
     UP(b_rows, rows, rows, int)
     UP(b_rel, rel, rel, int)
+    UP(b_relnp, rel_np, rel_np, int)
     UP(b_chptr, ch_ptr, ch_ptr, int)
     UP(b_chlist, ch_list, ch_list, int)
     UP(b_ksnptr, k_snptr, k_snptr, int64_t)
@@ -149,29 +151,378 @@ hipError_t DevPattern::build(const Symbolic& S) {
     UP(b_jte, jt_e, jt_e, int)
     UP(b_jtrow, jt_row, jt_row, int)
 #undef UP
-    // level lists and row-block work items (single instance 0)
-    std::vector<WorkItem> sn(S.ns), nb, mb, kb;
-    for (int q = 0; q < S.ns; q++) sn[q] = WorkItem{0, S.lvl_list[q]};
-    for (int i = 0; i < S.n; i += kBlock) nb.push_back(WorkItem{0, i});
-    for (int i = 0; i < S.m; i += kBlock) mb.push_back(WorkItem{0, i});
-    for (int64_t i = 0; i < S.nnzk; i += kBlock) kb.push_back(WorkItem{0, (int)i});
-    if ((e = upload(b_snitems, sn)) != hipSuccess) return e;
-    if ((e = upload(b_nitems, nb)) != hipSuccess) return e;
-    if ((e = upload(b_mitems, mb)) != hipSuccess) return e;
-    if ((e = upload(b_kitems, kb)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Engine
+// ---------------------------------------------------------------------------
+Engine::~Engine() {
+    if (hpin) (void)hipHostFree(hpin);
+}
+
+hipError_t Engine::ensure_pinned(size_t bytes) {
+    if (bytes <= hpin_bytes) return hipSuccess;
+    if (hpin) (void)hipHostFree(hpin);
+    hpin = nullptr;
+    hpin_bytes = 0;
+    bytes = std::max<size_t>(bytes, 4096);
+    hipError_t e = hipHostMalloc(&hpin, bytes, hipHostMallocDefault);
+    if (e == hipSuccess) hpin_bytes = bytes;
+    return e;
+}
+
+namespace {
+// bump allocator over an arena (256-byte aligned pieces); measures when base is NULL
+struct Carver {
+    char* base;
+    size_t off = 0, cap;
+    Carver(char* b, size_t c) : base(b), cap(c) {}
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += std::max<size_t>(count, 1) * sizeof(T);
+        return p;
+    }
+};
+}  // namespace
+
+kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vector<const DevPattern*>& p, char* mem,
+                         size_t cap, bool staging, hipStream_t st, size_t* used) {
+    syms = s;
+    pat_of = p;
+    ninst = (int)s.size();
+    n_ofs.assign(ninst + 1, 0);
+    m_ofs.assign(ninst + 1, 0);
+    w_ofs.assign(ninst + 1, 0);
+    j_ofs.assign(ninst + 1, 0);
+    std::vector<int64_t> lo(ninst + 1, 0), uo(ninst + 1, 0), vo(ninst + 1, 0), ko(ninst + 1, 0), ro(ninst + 1, 0);
+    lds_factor = lds_solve = 0;
+    int nlev = 0;
+    size_t nsn = 0, nnb = 0, nmb = 0, nkb = 0;
+    for (int q = 0; q < ninst; q++) {
+        const Symbolic& S = *s[q];
+        n_ofs[q + 1] = n_ofs[q] + S.n;
+        m_ofs[q + 1] = m_ofs[q] + S.m;
+        w_ofs[q + 1] = w_ofs[q] + S.nnz_w;
+        j_ofs[q + 1] = j_ofs[q] + S.nnz_j;
+        lo[q + 1] = lo[q] + S.lsize;
+        uo[q + 1] = uo[q] + S.usize;
+        vo[q + 1] = vo[q] + S.vsize;
+        ko[q + 1] = ko[q] + S.nnzk;
+        ro[q + 1] = ro[q] + (std::max(S.n, S.m) + kBlock - 1) / kBlock + 1;
+        for (int k = 0; k < S.ns; k++) {
+            lds_factor = std::max(lds_factor, (size_t)factor_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]));
+            lds_solve = std::max(lds_solve, (size_t)solve_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]));
+        }
+        nlev = std::max(nlev, S.nlevels);
+        nsn += S.ns;
+        nnb += (S.n + kBlock - 1) / kBlock;
+        nmb += (S.m + kBlock - 1) / kBlock;
+        nkb += (S.nnzk + kBlock - 1) / kBlock;
+    }
+    if (lds_factor > (size_t)kMaxDynLds || lds_solve > (size_t)kMaxDynLds)
+        return fail(KKT_ERR_PATTERN, "a front exceeds the per-workgroup LDS budget");
+    const size_t N = (size_t)n_ofs[ninst], M = (size_t)m_ofs[ninst];
+    Carver cv(mem, cap);
+    L = cv.take<double>(lo[ninst]);
+    U = cv.take<double>(uo[ninst]);
+    V = cv.take<double>(vo[ninst]);
+    kval = cv.take<double>(ko[ninst]);
+    dinv = cv.take<double>(N);
+    y = cv.take<double>(N);
+    r = cv.take<double>(N);
+    xprev = cv.take<double>(N);
+    tn = cv.take<double>(N);
+    fg = cv.take<double>(N);
+    cvec = cv.take<double>(M);
+    rvec = cv.take<double>(M);
+    pvec = cv.take<double>(M);
+    qvec = cv.take<double>(M);
+    red = cv.take<double>(ro[ninst]);
+    jcopy = cv.take<double>(j_ofs[ninst]);
+    status = cv.take<int>(2 * (size_t)ninst);
+    ndone = cv.take<int>(4);
+    rs = cv.take<RefineState>(ninst);
+    cg = cv.take<CgState>(ninst);
+    dinsts = cv.take<InstDev>(ninst);
+    snitems = cv.take<WorkItem>(nsn);
+    nitems = cv.take<WorkItem>(nnb);
+    mitems = cv.take<WorkItem>(nmb);
+    kitems = cv.take<WorkItem>(nkb);
+    stage = Staging{};
+    if (staging) {
+        stage.w = cv.take<double>(w_ofs[ninst]);
+        stage.j = cv.take<double>(j_ofs[ninst]);
+        stage.sx = cv.take<double>(N);
+        stage.ss = cv.take<double>(M);
+        stage.b = cv.take<double>(N);
+        stage.x = cv.take<double>(N);
+    }
+    const size_t total = (cv.off + 255) & ~(size_t)255;
+    if (used) *used = total;
+    if (!mem) return KKT_OK;
+    if (total > cap) return fail(KKT_ERR_BUDGET, "instances do not fit the arena");
+
+    hinst.assign(ninst, InstDev{});
+    for (int q = 0; q < ninst; q++) {
+        InstDev& I = hinst[q];
+        std::memset(&I, 0, sizeof(I));
+        I.P = p[q]->desc;
+        I.w_off = w_ofs[q];
+        I.j_off = j_ofs[q];
+        I.n_off = n_ofs[q];
+        I.m_off = m_ofs[q];
+        I.L = L + lo[q];
+        I.U = U + uo[q];
+        I.V = V + vo[q];
+        I.kval = kval + ko[q];
+        I.dinv = dinv + n_ofs[q];
+        I.y = y + n_ofs[q];
+        I.r = r + n_ofs[q];
+        I.xprev = xprev + n_ofs[q];
+        I.tn = tn + n_ofs[q];
+        I.fg = fg + n_ofs[q];
+        I.cvec = cvec + m_ofs[q];
+        I.rvec = rvec + m_ofs[q];
+        I.pvec = pvec + m_ofs[q];
+        I.qvec = qvec + m_ofs[q];
+        I.red = red + ro[q];
+        I.status = status + 2 * q;
+        I.rs = rs + q;
+        I.cg = cg + q;
+    }
+    // work lists: supernodes by tree level (leaves first) across instances,
+    // and row / entry blocks of each instance
+    std::vector<WorkItem> sn, nb, mb, kb;
+    sn.reserve(nsn);
+    lvl_ptr.assign(1, 0);
+    for (int l = 0; l < nlev; l++) {
+        for (int q = 0; q < ninst; q++) {
+            const Symbolic& S = *s[q];
+            if (l >= S.nlevels) continue;
+            for (int t = S.lvl_ptr[l]; t < S.lvl_ptr[l + 1]; t++) sn.push_back(WorkItem{q, S.lvl_list[t]});
+        }
+        lvl_ptr.push_back((int)sn.size());
+    }
+    for (int q = 0; q < ninst; q++) {
+        const Symbolic& S = *s[q];
+        for (int i = 0; i < S.n; i += kBlock) nb.push_back(WorkItem{q, i});
+        for (int i = 0; i < S.m; i += kBlock) mb.push_back(WorkItem{q, i});
+        for (int64_t i = 0; i < S.nnzk; i += kBlock) kb.push_back(WorkItem{q, (int)i});
+    }
     n_nitems = (int)nb.size();
     n_mitems = (int)mb.size();
     n_kitems = (int)kb.size();
-    lvl_ptr = S.lvl_ptr;
-    size_t lf = 0, ls = 0;
-    for (int s = 0; s < S.ns; s++) {
-        size_t r = S.sn_nrow[s], c = S.sn_ncol[s];
-        lf = std::max(lf, r * c * 8);
-        ls = std::max(ls, (r * c + r) * 8);
+    // one packed upload from pinned memory
+    const size_t b_inst = (size_t)ninst * sizeof(InstDev), b_sn = sn.size() * sizeof(WorkItem),
+                 b_nb = nb.size() * sizeof(WorkItem), b_mb = mb.size() * sizeof(WorkItem),
+                 b_kb = kb.size() * sizeof(WorkItem);
+    const size_t readback = (size_t)ninst * std::max(sizeof(RefineState), sizeof(CgState)) + 64;
+    hipError_t e = ensure_pinned(std::max(b_inst + b_sn + b_nb + b_mb + b_kb, readback));
+    if (e != hipSuccess) return hip_fail(e, "pinned host buffer");
+    char* h = (char*)hpin;
+    std::memcpy(h, hinst.data(), b_inst);
+    if (b_sn) std::memcpy(h + b_inst, sn.data(), b_sn);
+    if (b_nb) std::memcpy(h + b_inst + b_sn, nb.data(), b_nb);
+    if (b_mb) std::memcpy(h + b_inst + b_sn + b_nb, mb.data(), b_mb);
+    if (b_kb) std::memcpy(h + b_inst + b_sn + b_nb + b_mb, kb.data(), b_kb);
+    struct { void* dst; size_t off, bytes; } ups[] = {
+        {dinsts, 0, b_inst}, {snitems, b_inst, b_sn}, {nitems, b_inst + b_sn, b_nb},
+        {mitems, b_inst + b_sn + b_nb, b_mb}, {kitems, b_inst + b_sn + b_nb + b_mb, b_kb}};
+    for (auto& u : ups)
+        if (u.bytes && (e = hipMemcpyAsync(u.dst, h + u.off, u.bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return hip_fail(e, "descriptor upload");
+    if ((e = hipMemsetAsync(status, 0, 2 * (size_t)ninst * sizeof(int), st)) != hipSuccess ||
+        (e = hipMemsetAsync(rs, 0, (size_t)ninst * sizeof(RefineState), st)) != hipSuccess ||
+        (e = hipMemsetAsync(cg, 0, (size_t)ninst * sizeof(CgState), st)) != hipSuccess)
+        return hip_fail(e, "state init");
+    last_stream = st;
+    factored = false;
+    return KKT_OK;
+}
+
+size_t instance_bytes(const Symbolic& S) {
+    Engine probe;
+    std::vector<const Symbolic*> one{&S};
+    std::vector<const DevPattern*> none{nullptr};
+    size_t used = 0;
+    probe.place(one, none, nullptr, 0, true, nullptr, &used);
+    return used;
+}
+
+kkt_status Engine::init_owned(const std::vector<const Symbolic*>& s) {
+    kkt_status st = ensure_runtime();
+    if (st) return st;
+    hipError_t e;
+    std::map<const Symbolic*, const DevPattern*> up;
+    std::vector<const DevPattern*> p(s.size());
+    for (size_t q = 0; q < s.size(); q++) {
+        auto it = up.find(s[q]);
+        if (it == up.end()) {
+            pats.emplace_back(new DevPattern);
+            if ((e = pats.back()->build(*s[q])) != hipSuccess) return hip_fail(e, "pattern upload");
+            it = up.emplace(s[q], pats.back().get()).first;
+        }
+        p[q] = it->second;
     }
-    lds_factor = lf;
-    lds_solve = ls;
-    return hipSuccess;
+    size_t need = 0;
+    if ((st = place(s, p, nullptr, 0, false, nullptr, &need)) != KKT_OK) return st;
+    if ((e = own.alloc(need)) != hipSuccess) return hip_fail(e, "device allocation");
+    if ((st = place(s, p, (char*)own.p, need, false, nullptr, nullptr)) != KKT_OK) return st;
+    if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) return hip_fail(e, "init");
+    return KKT_OK;
+}
+
+kkt_status Engine::refactor(const Calls& C, hipStream_t st) {
+    last_stream = st;
+    mode = C.gamma == 0.0 ? 1 : 2;
+    gamma = C.gamma;
+    int* stat = status;
+    // per instance: status[0] = 0, status[1] = INT_MAX (first failing pivot)
+    for (int q = 0; q < ninst; q++) {
+        TL(KKT_PHASE_CONTROL, launch_fill_i32(stat + 2 * q, 0, 1, st));
+        TL(KKT_PHASE_CONTROL, launch_fill_i32(stat + 2 * q + 1, INT_MAX, 1, st));
+    }
+    TL(KKT_PHASE_ASSEMBLE, launch_assemble(di(), C, kitems, n_kitems, st));
+    const WorkItem* items = snitems;
+    for (size_t l = 0; l + 1 < lvl_ptr.size(); l++)
+        TL(KKT_PHASE_FACTOR, launch_factor(di(), items + lvl_ptr[l], lvl_ptr[l + 1] - lvl_ptr[l], lds_factor, st));
+    if (mode == 2 && j_ofs[ninst] > 0) {
+        hipError_t e = hipMemcpyAsync(jcopy, C.jv, (size_t)j_ofs[ninst] * 8, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "copy J values");
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "refactor launch");
+    factored = true;
+    return KKT_OK;
+}
+
+void Engine::sweeps(hipStream_t st, int skip_done) {
+    const WorkItem* items = snitems;
+    const int nl = (int)lvl_ptr.size() - 1;
+    for (int l = 0; l < nl; l++)
+        TL(KKT_PHASE_FWD, launch_fwd(di(), items + lvl_ptr[l], lvl_ptr[l + 1] - lvl_ptr[l], lds_solve, skip_done, st));
+    for (int l = nl - 1; l >= 0; l--)
+        TL(KKT_PHASE_BWD, launch_bwd(di(), items + lvl_ptr[l], lvl_ptr[l + 1] - lvl_ptr[l], lds_solve, skip_done, st));
+}
+
+kkt_status Engine::read_status(int* st_out, int* bad_out) {
+    hipError_t e = hipStreamSynchronize(last_stream);
+    if (e == hipSuccess) e = hipMemcpy(hpin, status, (size_t)ninst * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "status read");
+    const int* hs = (const int*)hpin;
+    kkt_status worst = KKT_OK;
+    for (int q = 0; q < ninst; q++) {
+        const int code = hs[2 * q];
+        int bad = -1;
+        if (code == KKT_ERR_NOT_SPD && hs[2 * q + 1] >= 0 && hs[2 * q + 1] < syms[q]->n) bad = syms[q]->perm[hs[2 * q + 1]];
+        if (st_out) st_out[q] = code;
+        if (bad_out) bad_out[q] = bad;
+        if (code != KKT_OK && worst == KKT_OK) worst = code;
+    }
+    return worst;
+}
+
+kkt_status Engine::solve(const Calls& C, int maxit, double tol, kkt_solve_info* infos, hipStream_t st) {
+    last_stream = st;
+    const WorkItem* nit = nitems;
+    int* nd = ndone;
+    TL(KKT_PHASE_CONTROL, launch_refine_reset(di(), ninst, tol, maxit, st));
+    TL(KKT_PHASE_CONTROL, launch_fill_i32(nd, 0, 1, st));
+    TL(KKT_PHASE_PERMUTE, launch_perm_in(di(), C, nit, n_nitems, PIN_B, st));
+    sweeps(st, 0);
+    TL(KKT_PHASE_PERMUTE, launch_perm_out(di(), C, nit, n_nitems, POUT_X, st));
+    int* hp = (int*)hpin;
+    for (int iter = 0; iter <= maxit + 1; iter++) {
+        TL(KKT_PHASE_RESIDUAL, launch_residual(di(), C, nit, n_nitems, st));
+        TL(KKT_PHASE_CONTROL, launch_refine_decide(di(), ninst, nd, st));
+        hipError_t e = hipMemcpyAsync(hp, nd, 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "refinement control");
+        if (hp[0] >= ninst) break;
+        TL(KKT_PHASE_PERMUTE, launch_perm_in(di(), C, nit, n_nitems, PIN_R, st));
+        sweeps(st, 1);
+        TL(KKT_PHASE_PERMUTE, launch_perm_out(di(), C, nit, n_nitems, POUT_X_UPDATE, st));
+    }
+    TL(KKT_PHASE_PERMUTE, launch_refine_revert(di(), C, nit, n_nitems, st));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "solve launch");
+    // a failed factor makes the solve meaningless: report it
+    kkt_status fst = read_status(nullptr, nullptr);
+    if (fst == KKT_ERR_DEVICE || fst == KKT_ERR_OOM) return fst;
+    if (fst != KKT_OK) return fail(fst, "factor failed; solve result invalid");
+    if (!infos) return KKT_OK;
+    e = hipMemcpy(hpin, rs, (size_t)ninst * sizeof(RefineState), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "solve info");
+    const RefineState* hr = (const RefineState*)hpin;
+    kkt_status worst = KKT_OK;
+    for (int q = 0; q < ninst; q++) {
+        const RefineState& S = hr[q];
+        const bool rev = S.revert != 0;
+        kkt_solve_info& inf = infos[q];
+        inf.iters = rev ? S.it - 1 : S.it;
+        inf.eta = rev ? S.eta_prev : S.eta;
+        inf.omega = rev ? S.omega_prev : S.omega;
+        inf.relres = rev ? S.relres_prev : S.relres;
+        inf.status = inf.omega <= tol ? KKT_OK : KKT_ERR_NOT_CONVERGED;
+        if (inf.status != KKT_OK) worst = inf.status;
+    }
+    return worst;
+}
+
+kkt_status Engine::cg_schur(const Calls& C, double tol, int maxit, kkt_cg_info* info, hipStream_t st) {
+    last_stream = st;
+    const WorkItem* nit = nitems;
+    const WorkItem* mit = mitems;
+    int* nd = ndone;
+    int* hp = (int*)hpin;
+    TL(KKT_PHASE_CONTROL, launch_fill_i32(nd, 0, 1, st));
+    TL(KKT_PHASE_CG, launch_cg_fgamma(di(), C, nit, n_nitems, st));
+    TL(KKT_PHASE_PERMUTE, launch_perm_in(di(), C, nit, n_nitems, PIN_FG, st));
+    sweeps(st, 0);
+    TL(KKT_PHASE_PERMUTE, launch_perm_out(di(), C, nit, n_nitems, POUT_TN, st));
+    TL(KKT_PHASE_CG, launch_cg_init(di(), C, mit, n_mitems, st));
+    TL(KKT_PHASE_CONTROL, launch_cg_start(di(), ninst, tol, maxit, nd, st));
+    hipError_t e = hipMemcpyAsync(hp, nd, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "cg control");
+    const int started_done = hp[0];
+    kkt_status fst = read_status(nullptr, nullptr);
+    if (fst != KKT_OK) return fail(fst, "factor failed; solve refused");
+    hp[0] = started_done;
+    for (int it = 0; hp[0] < ninst && it < maxit; it++) {
+        TL(KKT_PHASE_CG, launch_cg_jt(di(), C, nit, n_nitems, 0, st));
+        TL(KKT_PHASE_PERMUTE, launch_perm_in(di(), C, nit, n_nitems, PIN_TN, st));
+        sweeps(st, 0);
+        TL(KKT_PHASE_PERMUTE, launch_perm_out(di(), C, nit, n_nitems, POUT_TN, st));
+        TL(KKT_PHASE_CG, launch_cg_jq(di(), C, mit, n_mitems, st));
+        TL(KKT_PHASE_CONTROL, launch_cg_alpha(di(), ninst, nd, st));
+        TL(KKT_PHASE_CG, launch_cg_update(di(), C, mit, n_mitems, st));
+        TL(KKT_PHASE_CONTROL, launch_cg_beta(di(), ninst, nd, st));
+        TL(KKT_PHASE_CG, launch_cg_p(di(), mit, n_mitems, st));
+        e = hipMemcpyAsync(hp, nd, 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "cg control");
+    }
+    TL(KKT_PHASE_CG, launch_cg_jt(di(), C, nit, n_nitems, 1, st));
+    TL(KKT_PHASE_PERMUTE, launch_perm_in(di(), C, nit, n_nitems, PIN_TN, st));
+    sweeps(st, 0);
+    TL(KKT_PHASE_PERMUTE, launch_perm_out(di(), C, nit, n_nitems, POUT_DX, st));
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "cg launch");
+    if (!info) return KKT_OK;
+    e = hipMemcpyAsync(hpin, cg, sizeof(CgState), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "cg info");
+    CgState G;
+    std::memcpy(&G, hpin, sizeof(G));
+    info->iters = G.it;
+    const double rr = (G.it > 0 && G.status == 0 && G.done) ? G.rr_new : G.rr;
+    info->rel_res = G.cnorm > 0 ? std::sqrt(rr) / G.cnorm : 0.0;
+    info->status = G.status == 0 ? (G.done ? KKT_OK : KKT_ERR_NOT_CONVERGED) : G.status;
+    return info->status;
 }
 
 }  // namespace kkt
@@ -217,13 +568,15 @@ kkt_status kkt_symbolic_analyze(int32_t n, int32_t m, const int32_t* w_rowptr, c
     kkt_options o;
     kkt_options_default(&o);
     if (opt) o = *opt;
+    if (o.ordering < 0 || o.ordering > 2) return fail(KKT_ERR_INVALID_ARG, "unknown ordering");
     SymOptions so;
     so.ordering = o.ordering;
     so.nd_leaf = o.nd_leaf;
     so.max_super = o.max_super > 0 ? o.max_super : 96;
+    if (so.max_super > 128) return fail(KKT_ERR_INVALID_ARG, "max_super must be <= 128");
     so.relax_small = o.relax_small == 0 ? 16 : (o.relax_small < 0 ? 0 : o.relax_small);
     so.relax_frac = o.relax_frac < 0 ? 0.5 : o.relax_frac;
-    if (o.ordering < 0 || o.ordering > 2) return fail(KKT_ERR_INVALID_ARG, "unknown ordering");
+    so.lds_bytes = kMaxDynLds;
     kkt_symbolic* sym = new (std::nothrow) kkt_symbolic;
     if (!sym) return fail(KKT_ERR_OOM, "host allocation");
     std::string err;
@@ -286,174 +639,67 @@ void kkt_symbolic_destroy(kkt_symbolic* sym) { delete sym; }
 kkt_status kkt_factor_create(const kkt_symbolic* sym, kkt_factor** out) {
     if (!sym || !out) return fail(KKT_ERR_INVALID_ARG, "NULL argument");
     *out = nullptr;
-    kkt_status st = ensure_runtime();
-    if (st) return st;
     kkt_factor* f = new (std::nothrow) kkt_factor;
     if (!f) return fail(KKT_ERR_OOM, "host allocation");
     f->sym = sym;
-    const Symbolic& S = sym->S;
-    hipError_t e = f->pat.build(S);
-    if (e != hipSuccess) { delete f; return hip_fail(e, "pattern upload"); }
-    const size_t n = std::max(S.n, 1), m = std::max(S.m, 1);
-    const size_t nred = (std::max(S.n, S.m) + kBlock - 1) / kBlock + 1;
-    struct { DevBuf* b; size_t bytes; } al[] = {
-        {&f->L, (size_t)S.lsize * 8}, {&f->U, (size_t)S.usize * 8}, {&f->V, (size_t)S.vsize * 8},
-        {&f->kval, (size_t)S.nnzk * 8},
-        {&f->y, n * 8}, {&f->r, n * 8}, {&f->xprev, n * 8}, {&f->tn, n * 8}, {&f->fg, n * 8},
-        {&f->cvec, m * 8}, {&f->rvec, m * 8}, {&f->pvec, m * 8}, {&f->qvec, m * 8}, {&f->red, nred * 8},
-        {&f->status, 16}, {&f->rs, sizeof(RefineState)}, {&f->cg, sizeof(CgState)}, {&f->ndone, 16},
-        {&f->jcopy, std::max<size_t>((size_t)S.nnz_j, 1) * 8}, {&f->dinst, sizeof(InstDev)},
-    };
-    for (auto& a : al) {
-        e = a.b->alloc(a.bytes);
-        if (e != hipSuccess) { delete f; return hip_fail(e, "factor allocation"); }
+    kkt_status st = f->eng.init_owned({&sym->S});
+    if (st != KKT_OK) {
+        delete f;
+        return st;
     }
-    InstDev I;
-    std::memset(&I, 0, sizeof(I));
-    I.P = f->pat.desc;
-    I.L = (double*)f->L.p; I.U = (double*)f->U.p; I.V = (double*)f->V.p; I.kval = (double*)f->kval.p;
-    I.y = (double*)f->y.p; I.r = (double*)f->r.p; I.xprev = (double*)f->xprev.p; I.tn = (double*)f->tn.p;
-    I.fg = (double*)f->fg.p; I.cvec = (double*)f->cvec.p; I.rvec = (double*)f->rvec.p;
-    I.pvec = (double*)f->pvec.p; I.qvec = (double*)f->qvec.p; I.red = (double*)f->red.p;
-    I.status = (int*)f->status.p; I.rs = (RefineState*)f->rs.p; I.cg = (CgState*)f->cg.p;
-    f->hinst = I;
-    e = hipMemcpy(f->dinst.p, &I, sizeof(I), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&f->hpin, 4096, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipMemset(f->status.p, 0, 16);
-    if (e == hipSuccess) e = hipMemset(f->rs.p, 0, sizeof(RefineState));
-    if (e == hipSuccess) e = hipMemset(f->cg.p, 0, sizeof(CgState));
-    if (e != hipSuccess) { delete f; return hip_fail(e, "factor setup"); }
     *out = f;
     return KKT_OK;
 }
 
 void kkt_factor_destroy(kkt_factor* f) { delete f; }
 
+static kkt_status check_values(const Engine& E, const double* w_vals, const double* j_vals, const double* sigma_x,
+                               const double* sigma_s, double gamma) {
+    const int64_t nw = E.w_ofs[E.ninst], nj = E.j_ofs[E.ninst], n = E.n_ofs[E.ninst], m = E.m_ofs[E.ninst];
+    if ((nw > 0 && !w_vals) || (nj > 0 && !j_vals) || (n > 0 && !sigma_x))
+        return fail(KKT_ERR_INVALID_ARG, "NULL value array");
+    if (!(gamma >= 0.0) || !std::isfinite(gamma)) return fail(KKT_ERR_INVALID_ARG, "gamma must be finite and >= 0");
+    if (gamma == 0.0 && m > 0 && !sigma_s) return fail(KKT_ERR_INVALID_ARG, "Lifted-KKT (gamma == 0) needs sigma_s");
+    if (gamma > 0.0 && sigma_s) return fail(KKT_ERR_INVALID_ARG, "HyKKT (gamma > 0) takes sigma_s = NULL");
+    return KKT_OK;
+}
+
 kkt_status kkt_refactor(kkt_factor* f, const double* w_vals, const double* j_vals, const double* sigma_x,
                         const double* sigma_s, double gamma, void* stream) {
     if (!f) return fail(KKT_ERR_INVALID_ARG, "NULL factor");
-    const Symbolic& S = f->sym->S;
-    if ((S.nnz_w > 0 && !w_vals) || (S.nnz_j > 0 && !j_vals) || (S.n > 0 && !sigma_x))
-        return fail(KKT_ERR_INVALID_ARG, "NULL value array");
-    if (!(gamma >= 0.0) || !std::isfinite(gamma)) return fail(KKT_ERR_INVALID_ARG, "gamma must be finite and >= 0");
-    const bool lifted = gamma == 0.0;
-    if (lifted && S.m > 0 && !sigma_s) return fail(KKT_ERR_INVALID_ARG, "Lifted-KKT (gamma == 0) needs sigma_s");
-    if (!lifted && sigma_s) return fail(KKT_ERR_INVALID_ARG, "HyKKT (gamma > 0) takes sigma_s = NULL");
-    hipStream_t st = (hipStream_t)stream;
-    f->last_stream = st;
-    f->mode = lifted ? 1 : 2;
-    f->gamma = gamma;
+    kkt_status st = check_values(f->eng, w_vals, j_vals, sigma_x, sigma_s, gamma);
+    if (st) return st;
     Calls C;
     std::memset(&C, 0, sizeof(C));
-    C.one.w = w_vals; C.one.jv = j_vals; C.one.sx = sigma_x; C.one.ss = sigma_s; C.one.gamma = gamma;
-    const InstDev* di = (const InstDev*)f->dinst.p;
-    int* status = (int*)f->status.p;
-    TL(KKT_PHASE_CONTROL, launch_fill_i32(status, 0, 1, st));
-    TL(KKT_PHASE_CONTROL, launch_fill_i32(status + 1, INT_MAX, 1, st));
-    TL(KKT_PHASE_ASSEMBLE, launch_assemble(di, C, (const WorkItem*)f->pat.b_kitems.p, f->pat.n_kitems, st));
-    const WorkItem* items = (const WorkItem*)f->pat.b_snitems.p;
-    for (size_t l = 0; l + 1 < f->pat.lvl_ptr.size(); l++) {
-        int a = f->pat.lvl_ptr[l], b = f->pat.lvl_ptr[l + 1];
-        TL(KKT_PHASE_FACTOR, launch_factor(di, items + a, b - a, f->pat.lds_factor, st));
-    }
-    if (!lifted && S.nnz_j > 0) {
-        hipError_t e = hipMemcpyAsync(f->jcopy.p, j_vals, S.nnz_j * 8, hipMemcpyDeviceToDevice, st);
-        if (e != hipSuccess) return hip_fail(e, "copy J values");
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "refactor launch");
-    f->factored = true;
-    return KKT_OK;
+    C.w = w_vals; C.jv = j_vals; C.sx = sigma_x; C.ss = gamma == 0.0 ? sigma_s : nullptr; C.gamma = gamma;
+    return f->eng.refactor(C, (hipStream_t)stream);
 }
 
 kkt_status kkt_status_sync(kkt_factor* f, kkt_factor_info* info) {
     if (!f) return fail(KKT_ERR_INVALID_ARG, "NULL factor");
-    hipError_t e = hipStreamSynchronize(f->last_stream);
-    if (e != hipSuccess) return hip_fail(e, "stream sync");
-    int hs[2];
-    e = hipMemcpy(hs, f->status.p, 8, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "status read");
-    kkt_status st = hs[0] == 0 ? KKT_OK : hs[0];
-    int bad = -1;
-    if (hs[0] == KKT_ERR_NOT_SPD && hs[1] >= 0 && hs[1] < f->sym->S.n) bad = f->sym->S.perm[hs[1]];
-    if (info) { info->status = st; info->bad_col = bad; }
-    if (st != KKT_OK) g_last_error = std::string("factor status ") + kkt_status_string(st);
-    return st;
+    int code = 0, bad = -1;
+    kkt_status st = f->eng.read_status(&code, &bad);
+    if (st == KKT_ERR_DEVICE || st == KKT_ERR_OOM) return st;
+    if (info) { info->status = code; info->bad_col = bad; }
+    if (code != KKT_OK) g_last_error = std::string("factor status ") + kkt_status_string(code);
+    return code;
 }
-
-}  // extern "C"
-
-namespace kkt {
-
-// forward + backward sweeps over the level schedule; y holds the permuted vector
-void sweeps(kkt_factor* f, hipStream_t st) {
-    const InstDev* di = (const InstDev*)f->dinst.p;
-    const WorkItem* items = (const WorkItem*)f->pat.b_snitems.p;
-    const auto& lp = f->pat.lvl_ptr;
-    const int nl = (int)lp.size() - 1;
-    for (int l = 0; l < nl; l++) TL(KKT_PHASE_FWD, launch_fwd(di, items + lp[l], lp[l + 1] - lp[l], f->pat.lds_solve, st));
-    for (int l = nl - 1; l >= 0; l--) TL(KKT_PHASE_BWD, launch_bwd(di, items + lp[l], lp[l + 1] - lp[l], f->pat.lds_solve, st));
-}
-
-}  // namespace kkt
-
-extern "C" {
 
 kkt_status kkt_solve(kkt_factor* f, const double* b, double* x, const kkt_refine_opts* ro, kkt_solve_info* info,
                      void* stream) {
     if (!f) return fail(KKT_ERR_INVALID_ARG, "NULL factor");
-    const Symbolic& S = f->sym->S;
-    if (S.n > 0 && (!b || !x)) return fail(KKT_ERR_INVALID_ARG, "NULL vector");
-    if (b == x && S.n > 0) return fail(KKT_ERR_INVALID_ARG, "x aliases b");
-    if (!f->factored) return fail(KKT_ERR_STATE, "solve before refactor");
-    int maxit = ro ? ro->max_iter : 10;
-    double tol = ro ? ro->tol : 1e-14;
-    if (maxit < 0) return fail(KKT_ERR_INVALID_ARG, "negative max_iter");
-    hipStream_t st = (hipStream_t)stream;
-    f->last_stream = st;
-    const InstDev* di = (const InstDev*)f->dinst.p;
+    const int n = f->sym->S.n;
+    if (n > 0 && (!b || !x)) return fail(KKT_ERR_INVALID_ARG, "NULL vector");
+    if (b == x && n > 0) return fail(KKT_ERR_INVALID_ARG, "x aliases b");
+    if (!f->eng.factored) return fail(KKT_ERR_STATE, "solve before refactor");
+    const int maxit = ro ? ro->max_iter : 10;
+    const double tol = ro ? ro->tol : 1e-14;
+    if (maxit < 0 || !(tol >= 0.0)) return fail(KKT_ERR_INVALID_ARG, "bad refinement options");
     Calls C;
     std::memset(&C, 0, sizeof(C));
-    C.one.b = b;
-    C.one.x = x;
-    const WorkItem* nit = (const WorkItem*)f->pat.b_nitems.p;
-    const int nn = f->pat.n_nitems;
-    int* ndone = (int*)f->ndone.p;
-    TL(KKT_PHASE_CONTROL, launch_refine_reset(di, 1, tol, maxit, st));
-    TL(KKT_PHASE_CONTROL, launch_fill_i32(ndone, 0, 1, st));
-    TL(KKT_PHASE_PERMUTE, launch_perm_in(di, C, nit, nn, PIN_B, st));
-    sweeps(f, st);
-    TL(KKT_PHASE_PERMUTE, launch_perm_out(di, C, nit, nn, POUT_X, st));
-    int* hp = (int*)f->hpin;
-    for (int iter = 0; iter <= maxit + 1; iter++) {
-        TL(KKT_PHASE_RESIDUAL, launch_residual(di, C, nit, nn, st));
-        TL(KKT_PHASE_CONTROL, launch_refine_decide(di, 1, ndone, st));
-        hipError_t e = hipMemcpyAsync(hp, ndone, 4, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(hp + 1, f->status.p, 4, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_fail(e, "refinement control");
-        if (hp[1] != 0) return fail(hp[1], "factor failed; solve refused");
-        if (hp[0] >= 1) break;
-        TL(KKT_PHASE_PERMUTE, launch_perm_in(di, C, nit, nn, PIN_R, st));
-        sweeps(f, st);
-        TL(KKT_PHASE_PERMUTE, launch_perm_out(di, C, nit, nn, POUT_X_UPDATE, st));
-    }
-    TL(KKT_PHASE_PERMUTE, launch_refine_revert(di, C, nit, nn, st));
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "solve launch");
-    if (!info) return KKT_OK;
-    RefineState rs;
-    e = hipMemcpyAsync(f->hpin, f->rs.p, sizeof(RefineState), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail(e, "solve info");
-    std::memcpy(&rs, f->hpin, sizeof(rs));
-    const bool rev = rs.revert != 0;
-    info->iters = rev ? rs.it - 1 : rs.it;
-    info->eta = rev ? rs.eta_prev : rs.eta;
-    info->omega = rev ? rs.omega_prev : rs.omega;
-    info->relres = rev ? rs.relres_prev : rs.relres;
-    info->status = info->omega <= tol ? KKT_OK : KKT_ERR_NOT_CONVERGED;
-    return info->status;
+    C.b = b;
+    C.x = x;
+    return f->eng.solve(C, maxit, tol, info, (hipStream_t)stream);
 }
 
 kkt_status kkt_cg_schur(kkt_factor* f, const double* fv, const double* g, double tol, int32_t maxit, double* dx,
@@ -461,88 +707,123 @@ kkt_status kkt_cg_schur(kkt_factor* f, const double* fv, const double* g, double
     if (!f) return fail(KKT_ERR_INVALID_ARG, "NULL factor");
     const Symbolic& S = f->sym->S;
     if ((S.n > 0 && (!fv || !dx)) || (S.m > 0 && (!g || !dy))) return fail(KKT_ERR_INVALID_ARG, "NULL vector");
-    if (!f->factored || f->mode != 2) return fail(KKT_ERR_STATE, "cg_schur needs a K_gamma factor");
+    if (!f->eng.factored || f->eng.mode != 2) return fail(KKT_ERR_STATE, "cg_schur needs a K_gamma factor");
     if (maxit < 0 || !(tol >= 0.0)) return fail(KKT_ERR_INVALID_ARG, "bad tol/maxit");
-    hipStream_t st = (hipStream_t)stream;
-    f->last_stream = st;
-    const InstDev* di = (const InstDev*)f->dinst.p;
     Calls C;
     std::memset(&C, 0, sizeof(C));
-    C.one.jv = (const double*)f->jcopy.p;
-    C.one.gamma = f->gamma;
-    C.one.f = fv; C.one.g = g; C.one.dx = dx; C.one.dy = dy;
-    const WorkItem* nit = (const WorkItem*)f->pat.b_nitems.p;
-    const WorkItem* mit = (const WorkItem*)f->pat.b_mitems.p;
-    const int nn = f->pat.n_nitems, nm = f->pat.n_mitems;
-    int* ndone = (int*)f->ndone.p;
-    int* hp = (int*)f->hpin;
-    TL(KKT_PHASE_CONTROL, launch_fill_i32(ndone, 0, 1, st));
-    TL(KKT_PHASE_CG, launch_cg_fgamma(di, C, nit, nn, st));
-    TL(KKT_PHASE_PERMUTE, launch_perm_in(di, C, nit, nn, PIN_FG, st));
-    sweeps(f, st);
-    TL(KKT_PHASE_PERMUTE, launch_perm_out(di, C, nit, nn, POUT_TN, st));
-    TL(KKT_PHASE_CG, launch_cg_init(di, C, mit, nm, st));
-    TL(KKT_PHASE_CONTROL, launch_cg_start(di, 1, tol, maxit, ndone, st));
-    hipError_t e = hipMemcpyAsync(hp, ndone, 4, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(hp + 1, f->status.p, 4, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail(e, "cg control");
-    if (hp[1] != 0) return fail(hp[1], "factor failed; solve refused");
-    for (int it = 0; hp[0] == 0 && it < maxit; it++) {
-        TL(KKT_PHASE_CG, launch_cg_jt(di, C, nit, nn, 0, st));
-        TL(KKT_PHASE_PERMUTE, launch_perm_in(di, C, nit, nn, PIN_TN, st));
-        sweeps(f, st);
-        TL(KKT_PHASE_PERMUTE, launch_perm_out(di, C, nit, nn, POUT_TN, st));
-        TL(KKT_PHASE_CG, launch_cg_jq(di, C, mit, nm, st));
-        TL(KKT_PHASE_CONTROL, launch_cg_alpha(di, 1, ndone, st));
-        TL(KKT_PHASE_CG, launch_cg_update(di, C, mit, nm, st));
-        TL(KKT_PHASE_CONTROL, launch_cg_beta(di, 1, ndone, st));
-        TL(KKT_PHASE_CG, launch_cg_p(di, mit, nm, st));
-        e = hipMemcpyAsync(hp, ndone, 4, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_fail(e, "cg control");
-    }
-    TL(KKT_PHASE_CG, launch_cg_jt(di, C, nit, nn, 1, st));
-    TL(KKT_PHASE_PERMUTE, launch_perm_in(di, C, nit, nn, PIN_TN, st));
-    sweeps(f, st);
-    TL(KKT_PHASE_PERMUTE, launch_perm_out(di, C, nit, nn, POUT_DX, st));
-    e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "cg launch");
-    if (!info) return KKT_OK;
-    e = hipMemcpyAsync(f->hpin, f->cg.p, sizeof(CgState), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail(e, "cg info");
-    CgState G;
-    std::memcpy(&G, f->hpin, sizeof(G));
-    info->iters = G.it;
-    info->rel_res = G.cnorm > 0 ? std::sqrt(G.done && G.status == 0 && G.it > 0 ? G.rr_new : G.rr) / G.cnorm : 0.0;
-    info->status = G.status == 0 ? (G.done ? KKT_OK : KKT_ERR_NOT_CONVERGED) : G.status;
-    return info->status;
+    C.jv = f->eng.jcopy;
+    C.gamma = f->eng.gamma;
+    C.f = fv; C.g = g; C.dx = dx; C.dy = dy;
+    return f->eng.cg_schur(C, tol, maxit, info, (hipStream_t)stream);
 }
 
 kkt_status kkt_matvec(kkt_factor* f, const double* x, double* y, void* stream) {
     if (!f || (!x && f->sym->S.n > 0) || (!y && f->sym->S.n > 0)) return fail(KKT_ERR_INVALID_ARG, "NULL argument");
-    if (!f->factored) return fail(KKT_ERR_STATE, "matvec before refactor");
+    if (!f->eng.factored) return fail(KKT_ERR_STATE, "matvec before refactor");
+    Engine& E = f->eng;
+    LaunchTimer& timer = E.timer;
     hipStream_t st = (hipStream_t)stream;
-    TL(KKT_PHASE_RESIDUAL,
-       launch_matvec((const InstDev*)f->dinst.p, x, y, (const WorkItem*)f->pat.b_nitems.p, f->pat.n_nitems, st));
+    TL(KKT_PHASE_RESIDUAL, launch_matvec(E.di(), x, y, E.nitems, E.n_nitems, st));
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? KKT_OK : hip_fail(e, "matvec launch");
 }
 
+static kkt_status timing_read(Engine& E, kkt_timing* out) {
+    int launches[KKT_NPHASES];
+    hipError_t e = E.timer.read(out->ms, launches, KKT_NPHASES);
+    if (e != hipSuccess) return hip_fail(e, "timer read");
+    for (int q = 0; q < KKT_NPHASES; q++) out->launches[q] = launches[q];
+    return KKT_OK;
+}
+
 kkt_status kkt_factor_set_timing(kkt_factor* f, int32_t enable) {
     if (!f) return fail(KKT_ERR_INVALID_ARG, "NULL factor");
-    f->timer.on = enable != 0;
+    f->eng.timer.on = enable != 0;
     return KKT_OK;
 }
 
 kkt_status kkt_factor_read_timing(kkt_factor* f, kkt_timing* out) {
     if (!f || !out) return fail(KKT_ERR_INVALID_ARG, "NULL argument");
-    int launches[KKT_NPHASES];
-    hipError_t e = f->timer.read(out->ms, launches, KKT_NPHASES);
-    if (e != hipSuccess) return hip_fail(e, "timer read");
-    for (int q = 0; q < KKT_NPHASES; q++) out->launches[q] = launches[q];
+    return timing_read(f->eng, out);
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+kkt_status kkt_batch_create(int32_t count, const kkt_symbolic* const* syms, kkt_batch** out) {
+    if (!out || count < 1 || !syms) return fail(KKT_ERR_INVALID_ARG, "bad batch arguments");
+    *out = nullptr;
+    std::vector<const Symbolic*> v(count);
+    for (int q = 0; q < count; q++) {
+        if (!syms[q]) return fail(KKT_ERR_INVALID_ARG, "NULL symbolic in batch");
+        v[q] = &syms[q]->S;
+    }
+    kkt_batch* b = new (std::nothrow) kkt_batch;
+    if (!b) return fail(KKT_ERR_OOM, "host allocation");
+    b->syms.assign(syms, syms + count);
+    kkt_status st = b->eng.init_owned(v);
+    if (st != KKT_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
     return KKT_OK;
+}
+
+void kkt_batch_destroy(kkt_batch* b) { delete b; }
+
+kkt_status kkt_batch_offsets(const kkt_batch* b, int64_t* n_ofs, int64_t* m_ofs, int64_t* w_ofs, int64_t* j_ofs) {
+    if (!b) return fail(KKT_ERR_INVALID_ARG, "NULL batch");
+    const Engine& E = b->eng;
+    if (n_ofs) std::copy(E.n_ofs.begin(), E.n_ofs.end(), n_ofs);
+    if (m_ofs) std::copy(E.m_ofs.begin(), E.m_ofs.end(), m_ofs);
+    if (w_ofs) std::copy(E.w_ofs.begin(), E.w_ofs.end(), w_ofs);
+    if (j_ofs) std::copy(E.j_ofs.begin(), E.j_ofs.end(), j_ofs);
+    return KKT_OK;
+}
+
+kkt_status kkt_batch_refactor(kkt_batch* b, const double* w_vals, const double* j_vals, const double* sigma_x,
+                              const double* sigma_s, void* stream) {
+    if (!b) return fail(KKT_ERR_INVALID_ARG, "NULL batch");
+    kkt_status st = check_values(b->eng, w_vals, j_vals, sigma_x, sigma_s, 0.0);
+    if (st) return st;
+    Calls C;
+    std::memset(&C, 0, sizeof(C));
+    C.w = w_vals; C.jv = j_vals; C.sx = sigma_x; C.ss = sigma_s;
+    return b->eng.refactor(C, (hipStream_t)stream);
+}
+
+kkt_status kkt_batch_solve(kkt_batch* b, const double* rhs, double* x, const kkt_refine_opts* ro,
+                           kkt_solve_info* infos, void* stream) {
+    if (!b) return fail(KKT_ERR_INVALID_ARG, "NULL batch");
+    const int64_t n = b->eng.n_ofs[b->eng.ninst];
+    if (n > 0 && (!rhs || !x)) return fail(KKT_ERR_INVALID_ARG, "NULL vector");
+    if (rhs == x && n > 0) return fail(KKT_ERR_INVALID_ARG, "x aliases b");
+    if (!b->eng.factored) return fail(KKT_ERR_STATE, "solve before refactor");
+    const int maxit = ro ? ro->max_iter : 10;
+    const double tol = ro ? ro->tol : 1e-14;
+    if (maxit < 0 || !(tol >= 0.0)) return fail(KKT_ERR_INVALID_ARG, "bad refinement options");
+    Calls C;
+    std::memset(&C, 0, sizeof(C));
+    C.b = rhs;
+    C.x = x;
+    return b->eng.solve(C, maxit, tol, infos, (hipStream_t)stream);
+}
+
+kkt_status kkt_batch_status(kkt_batch* b, int32_t* status, int32_t* bad_col) {
+    if (!b) return fail(KKT_ERR_INVALID_ARG, "NULL batch");
+    return b->eng.read_status(status, bad_col);
+}
+
+kkt_status kkt_batch_set_timing(kkt_batch* b, int32_t enable) {
+    if (!b) return fail(KKT_ERR_INVALID_ARG, "NULL batch");
+    b->eng.timer.on = enable != 0;
+    return KKT_OK;
+}
+
+kkt_status kkt_batch_read_timing(kkt_batch* b, kkt_timing* out) {
+    if (!b || !out) return fail(KKT_ERR_INVALID_ARG, "NULL argument");
+    return timing_read(b->eng, out);
 }
 
 }  // extern "C"

@@ -1,13 +1,22 @@
 // Internal host-side objects behind the opaque C ABI handles.
+//
+// An Engine owns the device storage and work lists of a set of instances
+// (one instance for a kkt_factor, many for a kkt_batch). Every instance is a
+// symbolic pattern uploaded once (DevPattern, shared by instances with the
+// same analysis), a slice of the numeric storage, and the offsets of its
+// values inside the caller's concatenated arrays. Refactor, solve and CG run
+// the same kernels for one or many instances.
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "../../include/kkt.h"
 #include "device.hpp"
 #include "kernels.hpp"
+#include "lds_layout.hpp"
 #include "symbolic.hpp"
 
 namespace kkt {
@@ -29,17 +38,12 @@ struct DevBuf {
     hipError_t alloc(size_t nb);
 };
 
-// Symbolic arrays of one pattern uploaded to the device, plus the single
-// instance work lists.
+// Symbolic arrays of one pattern on the device.
 struct DevPattern {
     PatDev desc{};
-    DevBuf b_col0, b_ncol, b_nrow, b_rowofs, b_lofs, b_uofs, b_vofs, b_rows, b_rel, b_chptr, b_chlist,
+    DevBuf b_col0, b_ncol, b_nrow, b_rowofs, b_lofs, b_uofs, b_vofs, b_rows, b_rel, b_relnp, b_chptr, b_chlist,
         b_ksnptr, b_kloc, b_kw, b_kdiag, b_kpptr, b_pa, b_pb, b_jrow, b_perm, b_iperm, b_spptr, b_spe, b_spcol,
         b_jptr, b_jcol, b_jtptr, b_jte, b_jtrow;
-    DevBuf b_snitems, b_nitems, b_mitems, b_kitems;
-    int n_nitems = 0, n_mitems = 0, n_kitems = 0;
-    std::vector<int> lvl_ptr;
-    size_t lds_factor = 0, lds_solve = 0;
     hipError_t build(const Symbolic& S);
 };
 
@@ -50,12 +54,72 @@ struct LaunchTimer {
     std::vector<int> phase;     // phase of event pair q (events 2q, 2q+1)
     size_t used = 0;            // pairs recorded since the last read
     hipEvent_t cur = nullptr;
-    int cur_phase = 0;
     ~LaunchTimer();
     void begin(int ph, hipStream_t st);
     void end(hipStream_t st);
     hipError_t read(double* ms, int* launches, int nph);
 };
+
+// Value staging of a served wave: the requests' inputs gathered into
+// concatenated arrays so the batched kernels can address them by offset.
+struct Staging {
+    double *w = nullptr, *j = nullptr, *sx = nullptr, *ss = nullptr, *b = nullptr, *x = nullptr;
+};
+
+struct Engine {
+    int ninst = 0;
+    std::vector<const Symbolic*> syms;
+    std::vector<const DevPattern*> pat_of;
+    std::vector<std::unique_ptr<DevPattern>> pats;  // patterns uploaded by this engine itself
+    DevBuf own;                                     // arena owned by a factor / batch
+    // views into the arena
+    double *L = nullptr, *U = nullptr, *V = nullptr, *kval = nullptr, *dinv = nullptr, *y = nullptr, *r = nullptr,
+           *xprev = nullptr, *tn = nullptr, *fg = nullptr, *cvec = nullptr, *rvec = nullptr, *pvec = nullptr,
+           *qvec = nullptr, *red = nullptr, *jcopy = nullptr;
+    int *status = nullptr, *ndone = nullptr;
+    RefineState* rs = nullptr;
+    CgState* cg = nullptr;
+    InstDev* dinsts = nullptr;
+    WorkItem *snitems = nullptr, *nitems = nullptr, *mitems = nullptr, *kitems = nullptr;
+    Staging stage;                                  // used by served waves only
+    std::vector<InstDev> hinst;
+    std::vector<int> lvl_ptr;
+    int n_nitems = 0, n_mitems = 0, n_kitems = 0;
+    size_t lds_factor = 0, lds_solve = 0;
+    std::vector<int64_t> n_ofs, m_ofs, w_ofs, j_ofs;  // ninst + 1 prefix offsets
+    void* hpin = nullptr;                              // pinned host staging (uploads, readback)
+    size_t hpin_bytes = 0;
+    LaunchTimer timer;
+    hipStream_t last_stream = nullptr;
+    int mode = 0;                                      // 0 none, 1 Lifted-KKT, 2 HyKKT (K_gamma)
+    double gamma = 0.0;
+    bool factored = false;
+
+    Engine() = default;
+    Engine(const Engine&) = delete;
+    Engine& operator=(const Engine&) = delete;
+    ~Engine();
+
+    // Lays the instances out in `mem` (cap bytes; mem == NULL only measures)
+    // and uploads descriptors and work lists on `st`. Returns the bytes used
+    // through *used. With staging, also carves the served-wave value arrays.
+    kkt_status place(const std::vector<const Symbolic*>& s, const std::vector<const DevPattern*>& p, char* mem,
+                     size_t cap, bool staging, hipStream_t st, size_t* used);
+    // factor / batch: uploads the distinct patterns, allocates an own arena, places, waits
+    kkt_status init_owned(const std::vector<const Symbolic*>& s);
+    const InstDev* di() const { return dinsts; }
+    kkt_status refactor(const Calls& C, hipStream_t st);
+    void sweeps(hipStream_t st, int skip_done);
+    // Lifted-KKT solve with refinement; infos (ninst entries) filled when non-NULL.
+    kkt_status solve(const Calls& C, int maxit, double tol, kkt_solve_info* infos, hipStream_t st);
+    kkt_status cg_schur(const Calls& C, double tol, int maxit, kkt_cg_info* info, hipStream_t st);
+    // waits for st and returns each instance's latched status and failing column (original index)
+    kkt_status read_status(int* st_out, int* bad_out);
+    hipError_t ensure_pinned(size_t bytes);
+};
+
+// bytes of one instance of a pattern in an engine arena (with staging)
+size_t instance_bytes(const Symbolic& S);
 
 }  // namespace kkt
 
@@ -65,16 +129,10 @@ struct kkt_symbolic {
 
 struct kkt_factor {
     const kkt_symbolic* sym = nullptr;
-    kkt::DevPattern pat;
-    kkt::DevBuf L, U, V, kval, y, r, xprev, tn, fg, cvec, rvec, pvec, qvec, red, status, rs, cg, ndone, jcopy, dinst;
-    kkt::InstDev hinst{};
-    void* hpin = nullptr;          // pinned host staging (4 KB)
-    hipStream_t last_stream = nullptr;
-    int mode = 0;                  // 0 none, 1 Lifted-KKT, 2 HyKKT (K_gamma)
-    double gamma = 0.0;
-    bool factored = false;
-    kkt::LaunchTimer timer;
-    ~kkt_factor() {
-        if (hpin) (void)hipHostFree(hpin);
-    }
+    kkt::Engine eng;
+};
+
+struct kkt_batch {
+    std::vector<const kkt_symbolic*> syms;
+    kkt::Engine eng;
 };

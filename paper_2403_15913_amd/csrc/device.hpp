@@ -21,6 +21,7 @@ struct PatDev {
     const int64_t* sn_vofs;
     const int* rows;
     const int* rel;
+    const int* rel_np;
     const int* ch_ptr;
     const int* ch_list;
     const int64_t* k_snptr;
@@ -66,11 +67,14 @@ struct CgState {
 
 struct InstDev {
     PatDev P;
+    // offsets of this instance inside the caller's concatenated arrays
+    int64_t w_off, j_off, n_off, m_off;
     // numeric storage owned by the factor
     double* L;          // supernode panels, column-major, leading dimension = front rows
     double* U;          // update matrices, column-major u x u
     double* V;          // solve update vectors
     double* kval;       // assembled lower-triangle entries of K (grouped by supernode)
+    double* dinv;       // reciprocals of the pivots of L (pivot order)
     double* y;          // permuted work vector (n)
     double* r;          // residual (n)
     double* xprev;      // previous refinement iterate (n)

@@ -27,8 +27,6 @@ namespace kkt {
 #define KKT_ST_NOT_SPD 4
 #define KKT_ST_NONFINITE 5
 
-__device__ inline const CallPtrs& callp(const Calls& C, int inst) { return C.arr ? C.arr[inst] : C.one; }
-
 __device__ inline unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
 __device__ inline double bitsd(unsigned long long v) { return __longlong_as_double((long long)v); }
 
@@ -40,6 +38,15 @@ __global__ void k_fill_i32(int* __restrict__ p, int v, int64_t n) {
     if (i < n) p[i] = v;
 }
 
+// segment copies: blocks (segment, part) stride over one segment each
+constexpr int kCopyParts = 8;
+__global__ __launch_bounds__(256) void k_copy_segments(const CopySeg* __restrict__ segs) {
+    const CopySeg sg = segs[blockIdx.x / kCopyParts];
+    const int part = blockIdx.x % kCopyParts;
+    for (int64_t i = (int64_t)part * blockDim.x + threadIdx.x; i < sg.len; i += (int64_t)kCopyParts * blockDim.x)
+        sg.dst[i] = sg.src[i];
+}
+
 // ---------------------------------------------------------------------------
 // assembly: one thread per lower entry of K
 // ---------------------------------------------------------------------------
@@ -47,137 +54,247 @@ __global__ __launch_bounds__(256) void k_assemble(const InstDev* __restrict__ in
                                                   const WorkItem* __restrict__ items) {
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
-    const CallPtrs& cp = callp(C, it.inst);
     const int64_t nnzk = I.P.k_snptr[I.P.ns];
     const int64_t e = (int64_t)it.id + threadIdx.x;
     if (e >= nnzk) return;
     double v = 0.0;
     const int wi = I.P.k_w[e];
-    if (wi >= 0) v += cp.w[wi];
+    if (wi >= 0) v += C.w[I.w_off + wi];
     const int di = I.P.k_diag[e];
-    if (di >= 0) v += cp.sx[di];
+    if (di >= 0) v += C.sx[I.n_off + di];
     const int64_t p0 = I.P.k_pptr[e], p1 = I.P.k_pptr[e + 1];
-    const double* __restrict__ jv = cp.jv;
-    if (cp.ss) {
+    const double* __restrict__ jv = C.jv + I.j_off;
+    if (C.ss) {
+        const double* __restrict__ ss = C.ss + I.m_off;
         for (int64_t p = p0; p < p1; p++) {
             const int a = I.P.pair_a[p], b = I.P.pair_b[p];
-            v += jv[a] * cp.ss[I.P.jrow[a]] * jv[b];
+            v += jv[a] * ss[I.P.jrow[a]] * jv[b];
         }
     } else {
         double acc = 0.0;
         for (int64_t p = p0; p < p1; p++) acc += jv[I.P.pair_a[p]] * jv[I.P.pair_b[p]];
-        v += cp.gamma * acc;
+        v += C.gamma * acc;
     }
     I.kval[e] = v;
     if (!isfinite(v)) atomicMax(&I.status[0], KKT_ST_NONFINITE);
 }
 
 // ---------------------------------------------------------------------------
+// dense building blocks
+// ---------------------------------------------------------------------------
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64 on gfx950: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; element e of the result in lane l is D[4e + l/16][l%16].
+__device__ inline d4 mfma_f64_16x16x4(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ inline int rup16(int x) { return (x + 15) & ~15; }
+
+// value of a wave-uniform lane (scalar broadcast)
+__device__ inline double readlane_d(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// 16x16 tile of A B^T from a column-major LDS panel P (leading dimension ld):
+// A = rows i0..i0+15, B = rows j0..j0+15, both over columns k0..k0+K-1
+// (K a multiple of 4). Rows >= rlim read as zero.
+__device__ inline d4 tile_abt(const double* P, int ld, int i0, int j0, int k0, int K, int rlim, int lane) {
+    const int lr = lane & 15, lk = lane >> 4;
+    const int ia = i0 + lr, jb = j0 + lr;
+    const bool va = ia < rlim, vb = jb < rlim;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int kk = 0; kk < K; kk += 4) {
+        const int col = (k0 + kk + lk) * ld;
+        const double a = va ? P[col + ia] : 0.0;
+        const double b = vb ? P[col + jb] : 0.0;
+        acc = mfma_f64_16x16x4(a, b, acc);
+    }
+    return acc;
+}
+
+// lower-triangular tile enumeration: t -> (ti, tj) with tj0 <= tj <= ti < nb
+__device__ inline void tri_tile(int t, int tj0, int nb, int& ti, int& tj) {
+    tj = tj0;
+    int span = nb - tj;
+    while (t >= span) { t -= span; tj++; span = nb - tj; }
+    ti = tj + t;
+}
+
+// ---------------------------------------------------------------------------
 // multifrontal factorisation of one front per workgroup
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_factor(const InstDev* __restrict__ insts, const WorkItem* __restrict__ items) {
-    extern __shared__ double P[];  // front panel r x c, column-major, ld = r
+// The front panel (r rows x c columns) lives in LDS, column-major with an odd
+// leading dimension. It is assembled from the original entries of K and the
+// children's update matrices, factored in 16-column blocks (diagonal block by
+// one wave in registers, TRSM by all threads, trailing update on the matrix
+// cores), then the update matrix U = -L21 L21^T is formed on the matrix cores
+// and the children's pass-through entries are added to it.
+constexpr int kFactorThreads = 512;
+
+__global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __restrict__ insts,
+                                                          const WorkItem* __restrict__ items) {
+    extern __shared__ double P[];
+    __shared__ double invd[16];
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
     const PatDev& T = I.P;
     const int s = it.id;
     const int c = T.sn_ncol[s], r = T.sn_nrow[s], u = r - c, col0 = T.sn_col0[s];
-    const int ld = r;
+    const int rp = rup16(r), cp = rup16(c);
+    const int ld = rp + 1;
     const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
 
-    for (int q = tid; q < ld * c; q += nt) P[q] = 0.0;
+    for (int q = tid; q < ld * cp; q += nt) P[q] = 0.0;
     __syncthreads();
     for (int64_t e = T.k_snptr[s] + tid; e < T.k_snptr[s + 1]; e += nt) {
         const int loc = T.k_loc[e];
         P[(loc >> 16) * ld + (loc & 0xffff)] = I.kval[e];
     }
     __syncthreads();
-    // extend-add the children's update matrices into the panel columns
+    int* srel = (int*)(P + ld * cp);  // relative indices of the child being added
     for (int q = T.ch_ptr[s]; q < T.ch_ptr[s + 1]; q++) {
         const int ch = T.ch_list[q];
-        const int cc = T.sn_ncol[ch], uc = T.sn_nrow[ch] - cc;
+        const int cc = T.sn_ncol[ch], uc = T.sn_nrow[ch] - cc, nb = T.rel_np[ch];
         const double* __restrict__ Uc = I.U + T.sn_uofs[ch];
         const int* __restrict__ rl = T.rel + T.sn_rowofs[ch] + cc;
-        for (int b = 0; b < uc; b++) {
-            const int rb = rl[b];
-            if (rb >= c) break;  // relative indices increase
-            for (int a = b + tid; a < uc; a += nt) P[rb * ld + rl[a]] += Uc[(int64_t)b * uc + a];
+        for (int a = tid; a < uc; a += nt) srel[a] = rl[a];
+        __syncthreads();
+        // entries (a, b), a >= b, of the child's update matrix whose column b maps into the panel
+        int b = tid / uc, a = tid - b * uc;
+        for (int qq = tid; qq < nb * uc; qq += nt) {
+            if (a >= b) P[srel[b] * ld + srel[a]] += Uc[qq];
+            a += nt;
+            while (a >= uc) { a -= uc; b++; }
         }
         __syncthreads();
     }
-    // dense partial Cholesky of the panel (right-looking, column by column)
-    for (int j = 0; j < c; j++) {
-        double d = P[j * ld + j];
-        if (!(d > 0.0) || !isfinite(d)) {
-            if (tid == 0) {
-                atomicMin(&I.status[1], col0 + j);
-                atomicMax(&I.status[0], KKT_ST_NOT_SPD);
+
+    const int nbc = cp >> 4, nbr = rp >> 4;
+    for (int kb = 0; kb < nbc; kb++) {
+        const int j0 = kb << 4, w = min(16, c - j0);
+        if (wave == 0) {
+            // diagonal block: lane i < 16 holds row j0+i of the 16 block columns
+            const int i = lane;
+            double a[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) a[k] = (i < 16 && j0 + i < rp) ? P[(j0 + k) * ld + j0 + i] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 16; j++) {
+                if (j < w) {
+                    double d = readlane_d(a[j], j);
+                    if (!(d > 0.0) || !isfinite(d)) {
+                        if (lane == 0) {
+                            atomicMin(&I.status[1], col0 + j0 + j);
+                            atomicMax(&I.status[0], KKT_ST_NOT_SPD);
+                        }
+                        d = 1.0;
+                    }
+                    const double ljj = sqrt(d);
+                    const double inv = 1.0 / ljj;
+                    if (i == j) a[j] = ljj;
+                    else if (i > j) a[j] *= inv;
+                    if (lane == 0) {
+                        invd[j] = inv;
+                        I.dinv[col0 + j0 + j] = inv;
+                    }
+#pragma unroll
+                    for (int k = j + 1; k < 16; k++) {
+                        const double lkj = readlane_d(a[j], k);
+                        if (i >= k) a[k] -= a[j] * lkj;
+                    }
+                }
             }
-            d = 1.0;
-        }
-        const double ljj = sqrt(d);
-        const double inv = 1.0 / ljj;
-        __syncthreads();
-        if (tid == 0) P[j * ld + j] = ljj;
-        for (int i = j + 1 + tid; i < r; i += nt) P[j * ld + i] *= inv;
-        __syncthreads();
-        for (int i = j + 1 + tid; i < r; i += nt) {
-            const double lij = P[j * ld + i];
-            const int kmax = min(i, c - 1);
-            for (int k = j + 1; k <= kmax; k++) P[k * ld + i] -= lij * P[j * ld + k];
+            if (i < 16 && j0 + i < r) {
+#pragma unroll
+                for (int k = 0; k < 16; k++)
+                    if (k < w && k <= i) P[(j0 + k) * ld + j0 + i] = a[k];
+            }
         }
         __syncthreads();
+        // rows below the diagonal block: x = p L_kk^{-T}
+        for (int i = j0 + 16 + tid; i < r; i += nt) {
+            double x[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) x[k] = P[(j0 + k) * ld + i];
+#pragma unroll
+            for (int j = 0; j < 16; j++) {
+                if (j < w) {
+                    x[j] *= invd[j];
+#pragma unroll
+                    for (int k = j + 1; k < 16; k++) x[k] -= x[j] * P[(j0 + j) * ld + j0 + k];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 16; k++)
+                if (k < w) P[(j0 + k) * ld + i] = x[k];
+        }
+        __syncthreads();
+        // trailing update of the panel columns right of this block (matrix cores)
+        if (kb + 1 < nbc) {
+            int ntile = 0;
+            for (int jt = kb + 1; jt < nbc; jt++) ntile += nbr - jt;
+            for (int t = wave; t < ntile; t += nwave) {
+                int ti, tj;
+                tri_tile(t, kb + 1, nbr, ti, tj);
+                const d4 acc = tile_abt(P, ld, ti << 4, tj << 4, j0, 16, r, lane);
+                const int col = (tj << 4) + (lane & 15);
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int row = (ti << 4) + 4 * e + (lane >> 4);
+                    if (col < c && row >= col && row < r) P[col * ld + row] -= acc[e];
+                }
+            }
+            __syncthreads();
+        }
     }
+
     double* __restrict__ Ls = I.L + T.sn_lofs[s];
-    for (int q = tid; q < r * c; q += nt) Ls[q] = P[q];
-    if (u == 0) return;
-    // update matrix U = -L21 L21^T (lower part), 4x4 register blocks
-    double* __restrict__ Us = I.U + T.sn_uofs[s];
-    const int nb = (u + 3) >> 2;
-    const int nblk = nb * (nb + 1) / 2;
-    for (int q = tid; q < nblk; q += nt) {
-        int bi = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
-        while (bi * (bi + 1) / 2 > q) bi--;
-        while ((bi + 1) * (bi + 2) / 2 <= q) bi++;
-        const int bj = q - bi * (bi + 1) / 2;
-        double acc[4][4];
-#pragma unroll
-        for (int t = 0; t < 4; t++)
-#pragma unroll
-            for (int t2 = 0; t2 < 4; t2++) acc[t][t2] = 0.0;
-        for (int k = 0; k < c; k++) {
-            double av[4], bv[4];
-#pragma unroll
-            for (int t = 0; t < 4; t++) {
-                const int a = 4 * bi + t, b = 4 * bj + t;
-                av[t] = a < u ? P[k * ld + c + a] : 0.0;
-                bv[t] = b < u ? P[k * ld + c + b] : 0.0;
-            }
-#pragma unroll
-            for (int t = 0; t < 4; t++)
-#pragma unroll
-                for (int t2 = 0; t2 < 4; t2++) acc[t][t2] += av[t] * bv[t2];
+    {
+        int k = tid / r, i = tid - k * r;
+        for (int q = tid; q < r * c; q += nt) {
+            Ls[q] = P[k * ld + i];
+            i += nt;
+            while (i >= r) { i -= r; k++; }
         }
+    }
+    if (u == 0) return;
+    // update matrix U = -L21 L21^T (lower part) on the matrix cores
+    double* __restrict__ Us = I.U + T.sn_uofs[s];
+    const int nbu = (u + 15) >> 4;
+    const int ntu = nbu * (nbu + 1) / 2;
+    const int K4 = (c + 3) & ~3;
+    for (int t = wave; t < ntu; t += nwave) {
+        int ti, tj;
+        tri_tile(t, 0, nbu, ti, tj);
+        const d4 acc = tile_abt(P, ld, c + (ti << 4), c + (tj << 4), 0, K4, r, lane);
+        const int b = (tj << 4) + (lane & 15);
 #pragma unroll
-        for (int t = 0; t < 4; t++)
-#pragma unroll
-            for (int t2 = 0; t2 < 4; t2++) {
-                const int a = 4 * bi + t, b = 4 * bj + t2;
-                if (a < u && b <= a) Us[(int64_t)b * u + a] = -acc[t][t2];
-            }
+        for (int e = 0; e < 4; e++) {
+            const int a = (ti << 4) + 4 * e + (lane >> 4);
+            if (a < u && b <= a) Us[(int64_t)b * u + a] = -acc[e];
+        }
     }
     __syncthreads();
-    // extend-add the children's entries that pass through to the update matrix
+    // children's entries that pass through to the update matrix
     for (int q = T.ch_ptr[s]; q < T.ch_ptr[s + 1]; q++) {
         const int ch = T.ch_list[q];
-        const int cc = T.sn_ncol[ch], uc = T.sn_nrow[ch] - cc;
+        const int cc = T.sn_ncol[ch], uc = T.sn_nrow[ch] - cc, nb = T.rel_np[ch];
         const double* __restrict__ Uc = I.U + T.sn_uofs[ch];
         const int* __restrict__ rl = T.rel + T.sn_rowofs[ch] + cc;
-        for (int b = 0; b < uc; b++) {
-            const int rb = rl[b];
-            if (rb < c) continue;
-            for (int a = b + tid; a < uc; a += nt)
-                Us[(int64_t)(rb - c) * u + (rl[a] - c)] += Uc[(int64_t)b * uc + a];
+        for (int a = tid; a < uc; a += nt) srel[a] = rl[a] - c;
+        __syncthreads();
+        const int64_t base = (int64_t)nb * uc;
+        int b = nb + tid / uc, a = tid - (tid / uc) * uc;
+        for (int qq = tid; qq < (uc - nb) * uc; qq += nt) {
+            if (a >= b) Us[(int64_t)srel[b] * u + srel[a]] += Uc[base + qq];
+            a += nt;
+            while (a >= uc) { a -= uc; b++; }
         }
         __syncthreads();
     }
@@ -186,20 +303,40 @@ __global__ __launch_bounds__(256) void k_factor(const InstDev* __restrict__ inst
 // ---------------------------------------------------------------------------
 // triangular sweeps (y holds the permuted right-hand side, then the solution)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_fwd(const InstDev* __restrict__ insts, const WorkItem* __restrict__ items) {
+// The panel is staged in LDS (odd leading dimension); the c x c triangle is
+// solved by one wave with scalar broadcasts, the rectangular part by all
+// threads. Reciprocals of the pivots come from the factorisation.
+constexpr int kSolveThreads = 256;
+
+__device__ inline void stage_panel(double* P, int ld, const double* __restrict__ Ls, int r, int c, int tid, int nt) {
+    int k = tid / r, i = tid - k * r;
+    for (int q = tid; q < r * c; q += nt) {
+        P[k * ld + i] = Ls[q];
+        i += nt;
+        while (i >= r) { i -= r; k++; }
+    }
+}
+
+__global__ __launch_bounds__(kSolveThreads) void k_fwd(const InstDev* __restrict__ insts,
+                                                      const WorkItem* __restrict__ items, int skip_done) {
     extern __shared__ double sh[];
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
+    if (skip_done && I.rs->done) return;
     const PatDev& T = I.P;
     const int s = it.id;
     const int c = T.sn_ncol[s], r = T.sn_nrow[s], u = r - c, col0 = T.sn_col0[s];
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int ld = r | 1;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
     double* P = sh;
-    double* w = sh + (int64_t)r * c;
+    double* w = sh + (int64_t)ld * c;
     double* va = w + c;
-    const double* __restrict__ Ls = I.L + T.sn_lofs[s];
-    for (int q = tid; q < r * c; q += nt) P[q] = Ls[q];
-    for (int t = tid; t < c; t += nt) w[t] = I.y[col0 + t];
+    double* dv = va + u;
+    stage_panel(P, ld, I.L + T.sn_lofs[s], r, c, tid, nt);
+    for (int t = tid; t < c; t += nt) {
+        w[t] = I.y[col0 + t];
+        dv[t] = I.dinv[col0 + t];
+    }
     for (int t = tid; t < u; t += nt) va[t] = 0.0;
     __syncthreads();
     for (int q = T.ch_ptr[s]; q < T.ch_ptr[s + 1]; q++) {
@@ -214,52 +351,79 @@ __global__ __launch_bounds__(256) void k_fwd(const InstDev* __restrict__ insts, 
         }
         __syncthreads();
     }
-    for (int j = 0; j < c; j++) {
-        if (tid == 0) w[j] /= P[j * r + j];
-        __syncthreads();
-        const double wj = w[j];
-        for (int i = j + 1 + tid; i < c; i += nt) w[i] -= P[j * r + i] * wj;
-        __syncthreads();
+    if (tid < 64) {
+        // L11 y = w; lane holds entries lane and lane + 64 (c <= 128)
+        double w0 = lane < c ? w[lane] : 0.0;
+        double w1 = lane + 64 < c ? w[lane + 64] : 0.0;
+        for (int j = 0; j < c; j++) {
+            const double wj = j < 64 ? readlane_d(w0, j) : readlane_d(w1, j - 64);
+            const double yj = wj * dv[j];
+            const double* col = P + j * ld;
+            if (lane > j && lane < c) w0 -= col[lane] * yj;
+            if (lane + 64 > j && lane + 64 < c) w1 -= col[lane + 64] * yj;
+            if (lane == (j & 63)) {
+                if (j < 64) w0 = yj;
+                else w1 = yj;
+            }
+        }
+        if (lane < c) w[lane] = w0;
+        if (lane + 64 < c) w[lane + 64] = w1;
     }
+    __syncthreads();
     double* __restrict__ Vs = I.V + T.sn_vofs[s];
     for (int i = tid; i < u; i += nt) {
         double sum = va[i];
-        for (int k = 0; k < c; k++) sum -= P[k * r + c + i] * w[k];
+        const double* row = P + c + i;
+        for (int k = 0; k < c; k++) sum -= row[k * ld] * w[k];
         Vs[i] = sum;
     }
     for (int t = tid; t < c; t += nt) I.y[col0 + t] = w[t];
 }
 
-__global__ __launch_bounds__(256) void k_bwd(const InstDev* __restrict__ insts, const WorkItem* __restrict__ items) {
+__global__ __launch_bounds__(kSolveThreads) void k_bwd(const InstDev* __restrict__ insts,
+                                                      const WorkItem* __restrict__ items, int skip_done) {
     extern __shared__ double sh[];
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
+    if (skip_done && I.rs->done) return;
     const PatDev& T = I.P;
     const int s = it.id;
     const int c = T.sn_ncol[s], r = T.sn_nrow[s], u = r - c, col0 = T.sn_col0[s];
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int ld = r | 1;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
     double* P = sh;
-    double* t = sh + (int64_t)r * c;
+    double* t = sh + (int64_t)ld * c;
     double* zu = t + c;
-    const double* __restrict__ Ls = I.L + T.sn_lofs[s];
+    double* dv = zu + u;
     const int* __restrict__ rw = T.rows + T.sn_rowofs[s] + c;
-    for (int q = tid; q < r * c; q += nt) P[q] = Ls[q];
+    stage_panel(P, ld, I.L + T.sn_lofs[s], r, c, tid, nt);
     for (int i = tid; i < u; i += nt) zu[i] = I.y[rw[i]];
+    for (int k = tid; k < c; k += nt) dv[k] = I.dinv[col0 + k];
     __syncthreads();
     for (int k = tid; k < c; k += nt) {
         double sum = I.y[col0 + k];
-        for (int i = 0; i < u; i++) sum -= P[k * r + c + i] * zu[i];
+        const double* col = P + k * ld + c;
+        for (int i = 0; i < u; i++) sum -= col[i] * zu[i];
         t[k] = sum;
     }
     __syncthreads();
-    for (int j = c - 1; j >= 0; j--) {
-        if (tid == 0) t[j] /= P[j * r + j];
-        __syncthreads();
-        const double xj = t[j];
-        for (int i = tid; i < j; i += nt) t[i] -= P[i * r + j] * xj;
-        __syncthreads();
+    if (tid < 64) {
+        // L11^T x = t; lane holds entries lane and lane + 64 (c <= 128)
+        double t0 = lane < c ? t[lane] : 0.0;
+        double t1 = lane + 64 < c ? t[lane + 64] : 0.0;
+        for (int j = c - 1; j >= 0; j--) {
+            const double tj = j < 64 ? readlane_d(t0, j) : readlane_d(t1, j - 64);
+            const double xj = tj * dv[j];
+            if (lane < j) t0 -= P[lane * ld + j] * xj;
+            if (lane + 64 < j) t1 -= P[(lane + 64) * ld + j] * xj;
+            if (lane == (j & 63)) {
+                if (j < 64) t0 = xj;
+                else t1 = xj;
+            }
+        }
+        if (lane < c) I.y[col0 + lane] = t0;
+        if (lane + 64 < c) I.y[col0 + lane + 64] = t1;
     }
-    for (int k = tid; k < c; k += nt) I.y[col0 + k] = t[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -275,7 +439,7 @@ __global__ __launch_bounds__(256) void k_perm_in(const InstDev* __restrict__ ins
     if (mode == PIN_R && I.rs->done) return;
     const int k = it.id + threadIdx.x;
     if (k >= I.P.n) return;
-    const double* src = mode == PIN_B ? callp(C, it.inst).b : (mode == PIN_R ? I.r : (mode == PIN_TN ? I.tn : I.fg));
+    const double* src = mode == PIN_B ? C.b + I.n_off : (mode == PIN_R ? I.r : (mode == PIN_TN ? I.tn : I.fg));
     I.y[k] = src[I.P.perm[k]];
 }
 
@@ -291,16 +455,16 @@ __global__ __launch_bounds__(256) void k_perm_out(const InstDev* __restrict__ in
     const int i = I.P.perm[k];
     const double v = I.y[k];
     if (mode == POUT_X) {
-        callp(C, it.inst).x[i] = v;
+        C.x[I.n_off + i] = v;
     } else if (mode == POUT_X_UPDATE) {
-        double* x = callp(C, it.inst).x;
+        double* x = C.x + I.n_off;
         const double xo = x[i];
         I.xprev[i] = xo;
         x[i] = xo + v;
     } else if (mode == POUT_TN) {
         I.tn[i] = v;
     } else {
-        callp(C, it.inst).dx[i] = v;
+        C.dx[I.n_off + i] = v;
     }
 }
 
@@ -336,31 +500,44 @@ __device__ inline void block_max5(double v0, double v1, double v2, double v3, do
         for (int q = 0; q < 5; q++) atomicMax(&acc[q], dbits(red[q][0]));
 }
 
+// 16 lanes per row (coalesced reads of the row's entries), 256 rows per block.
 __global__ __launch_bounds__(256) void k_residual(const InstDev* __restrict__ insts, Calls C,
                                                   const WorkItem* __restrict__ items) {
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
     if (I.rs->done) return;  // uniform per block
-    const CallPtrs& cp = callp(C, it.inst);
-    const int i = it.id + threadIdx.x;
+    const double* __restrict__ x = C.x + I.n_off;
+    const double* __restrict__ b = C.b + I.n_off;
+    const int g = threadIdx.x >> 4, l = threadIdx.x & 15;
     double ra = 0.0, om = 0.0, rs = 0.0, xa = 0.0, ba = 0.0;
-    if (i < I.P.n) {
-        double sum = 0.0, den = 0.0;
-        for (int64_t p = I.P.sp_ptr[i]; p < I.P.sp_ptr[i + 1]; p++) {
+    const int iend = min(it.id + 256, I.P.n);
+    for (int i = it.id + g; i < iend; i += 16) {
+        double sum = 0.0, den = 0.0, ks = 0.0;
+        for (int64_t p = I.P.sp_ptr[i] + l; p < I.P.sp_ptr[i + 1]; p += 16) {
             const double kv = I.kval[I.P.sp_e[p]];
-            const double t = kv * cp.x[I.P.sp_col[p]];
+            const double t = kv * x[I.P.sp_col[p]];
             sum += t;
             den += fabs(t);
-            rs += fabs(kv);
+            ks += fabs(kv);
         }
-        const double bi = cp.b[i];
-        const double ri = bi - sum;
-        I.r[i] = ri;
-        ra = fabs(ri);
-        den += fabs(bi);
-        om = den > 0.0 ? ra / den : (ra > 0.0 ? INFINITY : 0.0);
-        xa = fabs(cp.x[i]);
-        ba = fabs(bi);
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+            sum += __shfl_xor(sum, o, 16);
+            den += __shfl_xor(den, o, 16);
+            ks += __shfl_xor(ks, o, 16);
+        }
+        if (l == 0) {
+            const double bi = b[i];
+            const double ri = bi - sum;
+            I.r[i] = ri;
+            const double ai = fabs(ri);
+            den += fabs(bi);
+            ra = fmax(ra, ai);
+            om = fmax(om, den > 0.0 ? ai / den : (ai > 0.0 ? INFINITY : 0.0));
+            rs = fmax(rs, ks);
+            xa = fmax(xa, fabs(x[i]));
+            ba = fmax(ba, fabs(bi));
+        }
     }
     block_max5(ra, om, rs, xa, ba, I.rs->acc);
 }
@@ -403,7 +580,7 @@ __global__ __launch_bounds__(256) void k_refine_revert(const InstDev* __restrict
     if (!I.rs->revert) return;
     const int i = it.id + threadIdx.x;
     if (i >= I.P.n) return;
-    callp(C, it.inst).x[i] = I.xprev[i];
+    C.x[I.n_off + i] = I.xprev[i];
 }
 
 __global__ __launch_bounds__(256) void k_matvec(const InstDev* __restrict__ insts, const double* __restrict__ x,
@@ -455,12 +632,13 @@ __global__ __launch_bounds__(256) void k_cg_fgamma(const InstDev* __restrict__ i
                                                    const WorkItem* __restrict__ items) {
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
-    const CallPtrs& cp = callp(C, it.inst);
     const int j = it.id + threadIdx.x;
     if (j >= I.P.n) return;
+    const double* __restrict__ jv = C.jv + I.j_off;
+    const double* __restrict__ g = C.g + I.m_off;
     double sum = 0.0;
-    for (int p = I.P.jt_ptr[j]; p < I.P.jt_ptr[j + 1]; p++) sum += cp.jv[I.P.jt_e[p]] * cp.g[I.P.jt_row[p]];
-    I.fg[j] = cp.f[j] + cp.gamma * sum;
+    for (int p = I.P.jt_ptr[j]; p < I.P.jt_ptr[j + 1]; p++) sum += jv[I.P.jt_e[p]] * g[I.P.jt_row[p]];
+    I.fg[j] = C.f[I.n_off + j] + C.gamma * sum;
 }
 
 // c = J w - g with w = K_gamma^{-1} f_gamma in tn; r = p = c; dy = 0; partial c.c
@@ -468,17 +646,17 @@ __global__ __launch_bounds__(256) void k_cg_init(const InstDev* __restrict__ ins
                                                  const WorkItem* __restrict__ items) {
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
-    const CallPtrs& cp = callp(C, it.inst);
     const int i = it.id + threadIdx.x;
     double v = 0.0;
     if (i < I.P.m) {
+        const double* __restrict__ jv = C.jv + I.j_off;
         double sum = 0.0;
-        for (int p = I.P.j_ptr[i]; p < I.P.j_ptr[i + 1]; p++) sum += cp.jv[p] * I.tn[I.P.j_col[p]];
-        const double ci = sum - cp.g[i];
+        for (int p = I.P.j_ptr[i]; p < I.P.j_ptr[i + 1]; p++) sum += jv[p] * I.tn[I.P.j_col[p]];
+        const double ci = sum - C.g[I.m_off + i];
         I.cvec[i] = ci;
         I.rvec[i] = ci;
         I.pvec[i] = ci;
-        cp.dy[i] = 0.0;
+        C.dy[I.m_off + i] = 0.0;
         v = ci * ci;
     }
     block_sum_to(v, &I.red[it.id / 256]);
@@ -508,12 +686,12 @@ __global__ __launch_bounds__(256) void k_cg_jt(const InstDev* __restrict__ insts
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
     if (!dx_rhs && I.cg->done) return;
-    const CallPtrs& cp = callp(C, it.inst);
     const int j = it.id + threadIdx.x;
     if (j >= I.P.n) return;
-    const double* v = dx_rhs ? cp.dy : I.pvec;
+    const double* __restrict__ jv = C.jv + I.j_off;
+    const double* v = dx_rhs ? C.dy + I.m_off : I.pvec;
     double sum = 0.0;
-    for (int p = I.P.jt_ptr[j]; p < I.P.jt_ptr[j + 1]; p++) sum += cp.jv[I.P.jt_e[p]] * v[I.P.jt_row[p]];
+    for (int p = I.P.jt_ptr[j]; p < I.P.jt_ptr[j + 1]; p++) sum += jv[I.P.jt_e[p]] * v[I.P.jt_row[p]];
     I.tn[j] = dx_rhs ? I.fg[j] - sum : sum;
 }
 
@@ -523,12 +701,12 @@ __global__ __launch_bounds__(256) void k_cg_jq(const InstDev* __restrict__ insts
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
     if (I.cg->done) return;
-    const CallPtrs& cp = callp(C, it.inst);
     const int i = it.id + threadIdx.x;
     double v = 0.0;
     if (i < I.P.m) {
+        const double* __restrict__ jv = C.jv + I.j_off;
         double sum = 0.0;
-        for (int p = I.P.j_ptr[i]; p < I.P.j_ptr[i + 1]; p++) sum += cp.jv[p] * I.tn[I.P.j_col[p]];
+        for (int p = I.P.j_ptr[i]; p < I.P.j_ptr[i + 1]; p++) sum += jv[p] * I.tn[I.P.j_col[p]];
         I.qvec[i] = sum;
         v = I.pvec[i] * sum;
     }
@@ -559,12 +737,11 @@ __global__ __launch_bounds__(256) void k_cg_update(const InstDev* __restrict__ i
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
     if (I.cg->done) return;
-    const CallPtrs& cp = callp(C, it.inst);
     const int i = it.id + threadIdx.x;
     const double a = I.cg->alpha;
     double v = 0.0;
     if (i < I.P.m) {
-        cp.dy[i] += a * I.pvec[i];
+        C.dy[I.m_off + i] += a * I.pvec[i];
         const double ri = I.rvec[i] - a * I.qvec[i];
         I.rvec[i] = ri;
         v = ri * ri;
@@ -607,7 +784,7 @@ __global__ __launch_bounds__(256) void k_cg_p(const InstDev* __restrict__ insts,
 // launch wrappers
 // ---------------------------------------------------------------------------
 hipError_t set_kernel_attributes() {
-    const int lds = 160 * 1024;
+    const int lds = kMaxDynLds;
     hipError_t e = hipFuncSetAttribute((const void*)k_factor, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void*)k_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -617,6 +794,9 @@ hipError_t set_kernel_attributes() {
 
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+void launch_copy_segments(const CopySeg* segs, int nseg, hipStream_t st) {
+    if (nseg > 0) k_copy_segments<<<nseg * kCopyParts, 256, 0, st>>>(segs);
+}
 void launch_fill_i32(int* p, int v, int64_t n, hipStream_t st) {
     if (n > 0) k_fill_i32<<<blocks_for(n, kBlock), kBlock, 0, st>>>(p, v, n);
 }
@@ -624,13 +804,13 @@ void launch_assemble(const InstDev* insts, const Calls& C, const WorkItem* items
     if (nitems > 0) k_assemble<<<nitems, kBlock, 0, st>>>(insts, C, items);
 }
 void launch_factor(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, hipStream_t st) {
-    if (nitems > 0) k_factor<<<nitems, kBlock, lds, st>>>(insts, items);
+    if (nitems > 0) k_factor<<<nitems, kFactorThreads, lds, st>>>(insts, items);
 }
-void launch_fwd(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, hipStream_t st) {
-    if (nitems > 0) k_fwd<<<nitems, kBlock, lds, st>>>(insts, items);
+void launch_fwd(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, int skip_done, hipStream_t st) {
+    if (nitems > 0) k_fwd<<<nitems, kSolveThreads, lds, st>>>(insts, items, skip_done);
 }
-void launch_bwd(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, hipStream_t st) {
-    if (nitems > 0) k_bwd<<<nitems, kBlock, lds, st>>>(insts, items);
+void launch_bwd(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, int skip_done, hipStream_t st) {
+    if (nitems > 0) k_bwd<<<nitems, kSolveThreads, lds, st>>>(insts, items, skip_done);
 }
 void launch_perm_in(const InstDev* insts, const Calls& C, const WorkItem* rows, int nitems, int mode, hipStream_t st) {
     if (nitems > 0) k_perm_in<<<nitems, kBlock, 0, st>>>(insts, C, rows, mode);

@@ -6,10 +6,10 @@
 
 namespace kkt {
 
-// Per-call caller pointers of one instance (values of a refactorisation and
-// the vectors of a solve). Passed by value for a single instance, or as a
-// device array for batches.
-struct CallPtrs {
+// Base pointers of one call (values of a refactorisation, vectors of a
+// solve), passed by value. Instance q uses base + its offsets (InstDev
+// w_off / j_off / n_off / m_off), so a batch reads concatenated arrays.
+struct Calls {
     const double* w;
     const double* jv;
     const double* sx;
@@ -23,20 +23,27 @@ struct CallPtrs {
     double* dy;
 };
 
-struct Calls {
-    const CallPtrs* arr;  // device array indexed by instance, or NULL
-    CallPtrs one;         // used when arr is NULL
-};
-
 constexpr int kBlock = 256;
 
+// Dynamic LDS a front may use (the kernels also hold a little static LDS;
+// gfx950 gives a workgroup 160 KiB in total).
+constexpr int kMaxDynLds = 158 * 1024;
+
 hipError_t set_kernel_attributes();
+
+// A device-to-device copy of `len` doubles (gathering a served wave's inputs).
+struct CopySeg {
+    const double* src;
+    double* dst;
+    int64_t len;
+};
+void launch_copy_segments(const CopySeg* segs, int nseg, hipStream_t st);
 
 void launch_fill_i32(int* p, int v, int64_t n, hipStream_t st);
 void launch_assemble(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st);
 void launch_factor(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, hipStream_t st);
-void launch_fwd(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, hipStream_t st);
-void launch_bwd(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, hipStream_t st);
+void launch_fwd(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, int skip_done, hipStream_t st);
+void launch_bwd(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, int skip_done, hipStream_t st);
 
 // permutation modes
 enum { PIN_B = 0, PIN_R = 1, PIN_TN = 2, PIN_FG = 3 };

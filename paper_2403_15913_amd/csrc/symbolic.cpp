@@ -11,6 +11,8 @@
 // residual K x; level schedules.
 #include "symbolic.hpp"
 
+#include "lds_layout.hpp"
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -27,12 +29,7 @@ struct Graph {  // symmetric adjacency of K without self loops, original numberi
     std::vector<int> a;
 };
 
-int round_up(int x, int q) { return (x + q - 1) / q * q; }
-
-// LDS bytes one r x c front needs in the factor and solve kernels: the panel
-// with rows and columns padded to the 16-wide matrix-core tile, plus two
-// vectors of r entries.
-int64_t panel_lds_bytes(int r, int c) { return (int64_t)round_up(r, 16) * (round_up(c, 16) + 2) * 8; }
+int64_t panel_lds_bytes(int r, int c) { return front_lds_bytes(r, c); }
 
 int validate(int n, int m, const int32_t* wp, const int32_t* wi, const int32_t* jp, const int32_t* ji,
              std::string& err) {
@@ -547,8 +544,10 @@ int analyze(int n, int m, const int32_t* wp, const int32_t* wi, const int32_t* j
         for (int s = 0; s < ns; s++) S.lvl_list[fill[S.sn_level[s]]++] = s;
     }
 
-    // relative indices of update rows in the parent's front
+    // relative indices of update rows in the parent's front; rel_np[s] counts
+    // the update rows of s that land in the parent's own columns
     S.rel.assign(S.rows.size(), -1);
+    S.rel_np.assign(ns, 0);
     for (int s = 0; s < ns; s++) {
         int p = spar[s];
         int c = S.sn_ncol[s];
@@ -562,6 +561,7 @@ int analyze(int n, int m, const int32_t* wp, const int32_t* wi, const int32_t* j
             const int* it = std::lower_bound(pr, pr + pn, S.rows[q]);
             if (it == pr + pn || *it != S.rows[q]) { err = "internal: update row missing from parent front"; return ST_INVALID; }
             S.rel[q] = (int)(it - pr);
+            if (S.rel[q] < S.sn_ncol[p]) S.rel_np[s]++;
         }
     }
 

@@ -36,6 +36,7 @@ struct Symbolic {
     std::vector<int64_t> sn_rowofs, sn_lofs, sn_uofs, sn_vofs;
     std::vector<int> rows;                 // row structure of every front
     std::vector<int> rel;                  // rel[rowofs[s]+ncol+a]: local row of update row a in the parent front
+    std::vector<int> rel_np;               // update rows of s that fall in the parent's own columns
     std::vector<int> ch_ptr, ch_list;      // children, ascending
     std::vector<int> lvl_ptr, lvl_list;    // supernodes grouped by tree level (leaves first)
     int nlevels = 0;

@@ -100,6 +100,22 @@ SIGNATURES = {
     "kkt_matvec": (I32, [P, P, P, P]),
     "kkt_factor_set_timing": (I32, [P, I32]),
     "kkt_factor_read_timing": (I32, [P, P]),
+    "kkt_batch_create": (I32, [I32, P, P]),
+    "kkt_batch_destroy": (None, [P]),
+    "kkt_batch_offsets": (I32, [P, P, P, P, P]),
+    "kkt_batch_refactor": (I32, [P, P, P, P, P, P]),
+    "kkt_batch_solve": (I32, [P, P, P, P, P, P]),
+    "kkt_batch_status": (I32, [P, P, P]),
+    "kkt_batch_set_timing": (I32, [P, I32]),
+    "kkt_batch_read_timing": (I32, [P, P]),
+    "kkt_server_opts_default": (None, [P]),
+    "kkt_server_create": (I32, [P, P]),
+    "kkt_server_register": (I32, [P, P, P]),
+    "kkt_server_submit": (I32, [P, I32, P, P, P, P, P, P, P]),
+    "kkt_server_wait": (I32, [P, I64, P, P]),
+    "kkt_server_get_stats": (I32, [P, P]),
+    "kkt_server_reset_stats": (I32, [P]),
+    "kkt_server_destroy": (None, [P]),
 }
 
 _lib = None
@@ -319,6 +335,154 @@ class Factor:
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
             kkt_factor_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# batches
+# ---------------------------------------------------------------------------
+
+def kkt_batch_create(sym_handles):
+    arr = (C.c_void_p * len(sym_handles))(*[h.value for h in sym_handles])
+    h = C.c_void_p()
+    _err(lib().kkt_batch_create(len(sym_handles), arr, C.byref(h)))
+    return h
+
+
+def kkt_batch_offsets(h, count: int):
+    outs = [np.empty(count + 1, dtype=np.int64) for _ in range(4)]
+    _err(lib().kkt_batch_offsets(h, *[_ptr_np(o) for o in outs]))
+    return dict(zip(("n", "m", "w", "j"), outs))
+
+
+def kkt_batch_refactor(h, w_vals, j_vals, sigma_x, sigma_s, stream=None):
+    _err(lib().kkt_batch_refactor(h, _dptr(w_vals), _dptr(j_vals), _dptr(sigma_x), _dptr(sigma_s), _stream(stream)))
+
+
+def kkt_batch_solve(h, count, b, x, max_iter=10, tol=1e-14, info=True, stream=None):
+    ro = RefineOpts(max_iter, tol)
+    infos = (SolveInfo * count)()
+    st = lib().kkt_batch_solve(h, _dptr(b), _dptr(x), C.byref(ro), infos if info else None, _stream(stream))
+    if st not in (KKT_OK, 6):
+        _err(st)
+    return [i.as_dict() for i in infos] if info else None
+
+
+def kkt_batch_status(h, count):
+    st = np.zeros(count, dtype=np.int32)
+    bad = np.zeros(count, dtype=np.int32)
+    lib().kkt_batch_status(h, _ptr_np(st), _ptr_np(bad))
+    return st, bad
+
+
+class Batch:
+    """Batched refactor + solve of many instances (concatenated device arrays)."""
+
+    def __init__(self, syms):
+        self.syms = list(syms)
+        self.count = len(self.syms)
+        self.h = kkt_batch_create([s.h for s in self.syms])
+        self.ofs = kkt_batch_offsets(self.h, self.count)
+
+    def refactor(self, w_vals, j_vals, sigma_x, sigma_s, stream=None):
+        kkt_batch_refactor(self.h, w_vals, j_vals, sigma_x, sigma_s, stream)
+
+    def solve(self, b, x, max_iter=10, tol=1e-14, info=True, stream=None):
+        return kkt_batch_solve(self.h, self.count, b, x, max_iter, tol, info, stream)
+
+    def status(self):
+        return kkt_batch_status(self.h, self.count)
+
+    def set_timing(self, enable=True):
+        _err(lib().kkt_batch_set_timing(self.h, 1 if enable else 0))
+
+    def read_timing(self) -> dict:
+        t = Timing()
+        _err(lib().kkt_batch_read_timing(self.h, C.byref(t)))
+        return t.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().kkt_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# served form
+# ---------------------------------------------------------------------------
+
+class ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_int64), ("max_wave", C.c_int32), ("workers", C.c_int32),
+                ("refine_max_iter", C.c_int32), ("refine_tol", C.c_double), ("linger_us", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64), ("waves", C.c_int64),
+                ("mean_wave", C.c_double), ("p50_s", C.c_double), ("p99_s", C.c_double),
+                ("mean_queue_s", C.c_double), ("mean_service_s", C.c_double), ("throughput", C.c_double),
+                ("window_s", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Server:
+    """Request loop over resident patterns (continuous batching)."""
+
+    def __init__(self, hbm_budget=8 << 30, max_wave=64, workers=2, refine_max_iter=10, refine_tol=1e-14,
+                 linger_us=0.0):
+        o = ServerOpts()
+        lib().kkt_server_opts_default(C.byref(o))
+        o.hbm_budget, o.max_wave, o.workers = int(hbm_budget), int(max_wave), int(workers)
+        o.refine_max_iter, o.refine_tol, o.linger_us = int(refine_max_iter), float(refine_tol), float(linger_us)
+        self.h = C.c_void_p()
+        _err(lib().kkt_server_create(C.byref(o), C.byref(self.h)))
+        self.keep = []
+
+    def register(self, sym: Symbolic) -> int:
+        pid = C.c_int32()
+        _err(lib().kkt_server_register(self.h, sym.h, C.byref(pid)))
+        self.keep.append(sym)
+        return pid.value
+
+    def submit(self, pid, w_vals, j_vals, sigma_x, sigma_s, b, x) -> int:
+        t = C.c_int64()
+        _err(lib().kkt_server_submit(self.h, int(pid), _dptr(w_vals), _dptr(j_vals), _dptr(sigma_x),
+                                     _dptr(sigma_s), _dptr(b), _dptr(x), C.byref(t)))
+        return t.value
+
+    def wait(self, ticket):
+        si = SolveInfo()
+        lat = C.c_double()
+        st = lib().kkt_server_wait(self.h, int(ticket), C.byref(si), C.byref(lat))
+        d = si.as_dict()
+        d["status"] = st
+        d["latency_s"] = lat.value
+        return d
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _err(lib().kkt_server_get_stats(self.h, C.byref(s)))
+        return s.as_dict()
+
+    def reset_stats(self):
+        _err(lib().kkt_server_reset_stats(self.h))
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().kkt_server_destroy(self.h)
             self.h = C.c_void_p()
 
     def __del__(self):

@@ -1,0 +1,106 @@
+"""GPU parity of the batched form (many NMPC instances per launch).
+
+Gates: every instance's backward error eta <= 1e-10; each instance's batched
+solution is bitwise identical to the same instance solved alone by a plain
+factor (identical per-instance operation order, no cross-instance
+reductions); a factor failure in one instance is reported for that instance
+only. Instance shapes follow the batched workload: N ~ U{20..200},
+nx ~ U{16..64}, nu ~ U{1..4}, Sigma ~ logU[1e-6, 1e6].
+"""
+import numpy as np
+import pytest
+
+import kktgen
+from oracle import dense as D
+from oracle import sparse as S
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def kkt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_15913_amd import kkt as K
+    K.lib()
+    return K
+
+
+def dev(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float64, device="cuda")
+
+
+def make_batch(count, shrink=1):
+    pats, vals = [], []
+    for q in range(count):
+        N, nx, nu = kktgen.batch_shapes()[q]
+        N = max(2, N // shrink)
+        pat = kktgen.nmpc_pattern(N, nx, nu)
+        pats.append(pat)
+        vals.append(kktgen.nmpc_values(pat, kktgen.rng_for(3, q, 1), 1e-6, 1e6))
+    return pats, vals
+
+
+def concat(vals, field):
+    return dev(np.concatenate([getattr(v, field) for v in vals]))
+
+
+@pytest.mark.parametrize("ordering", [1, 2])
+def test_batch_matches_oracle_and_plain(kkt, ordering):
+    count = 12
+    pats, vals = make_batch(count, shrink=4)
+    print(f"batch of {count}, ordering {ordering}", flush=True)
+    syms = [kkt.Symbolic.from_pattern(p, ordering=ordering) for p in pats]
+    B = kkt.Batch(syms)
+    n_ofs = B.ofs["n"]
+    B.refactor(concat(vals, "w_vals"), concat(vals, "j_vals"), concat(vals, "sigma_x"), concat(vals, "sigma_s"))
+    st, bad = B.status()
+    assert (st == 0).all()
+    x = torch.zeros(int(n_ofs[-1]), dtype=torch.float64, device="cuda")
+    infos = B.solve(concat(vals, "b"), x)
+    xb = x.cpu().numpy()
+    for q in range(count):
+        pat, v = pats[q], vals[q]
+        xq = xb[n_ofs[q]:n_ofs[q + 1]]
+        K = D.condensed(pat, v, v.sigma_s)
+        be = D.backward_errors(K, xq, v.b)
+        assert be["eta"] <= 1e-10 and infos[q]["eta"] <= 1e-10, (q, be, infos[q])
+        xo, oinfo = S.lifted_solve(pat, v, v.b)
+        assert oinfo["spd"]
+        # plain factor of the same instance: bitwise identical
+        f = kkt.Factor(syms[q])
+        f.refactor(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), dev(v.sigma_s))
+        xp = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
+        pinfo = f.solve(dev(v.b), xp)
+        assert np.array_equal(xp.cpu().numpy(), xq), q
+        assert pinfo["iters"] == infos[q]["iters"]
+
+
+def test_batch_failure_isolated(kkt):
+    count = 6
+    pats, vals = make_batch(count, shrink=8)
+    bad_q = 3
+    s = pats[bad_q].meta["stage"]
+    vals[bad_q].sigma_x[2 * s:3 * s] = -1e7
+    syms = [kkt.Symbolic.from_pattern(p) for p in pats]
+    B = kkt.Batch(syms)
+    B.refactor(concat(vals, "w_vals"), concat(vals, "j_vals"), concat(vals, "sigma_x"), concat(vals, "sigma_s"))
+    st, bad = B.status()
+    assert st[bad_q] == 4 and all(st[q] == 0 for q in range(count) if q != bad_q)
+    assert bad[bad_q] >= 0
+
+
+def test_batch_shared_symbolic(kkt):
+    """The same analysis reused for several instances (one upload)."""
+    pat = kktgen.nmpc_pattern(30, 20, 2)
+    vals = [kktgen.nmpc_values(pat, kktgen.rng_for(3, 900, vs), 1e-6, 1e6) for vs in range(5)]
+    sym = kkt.Symbolic.from_pattern(pat)
+    B = kkt.Batch([sym] * 5)
+    B.refactor(concat(vals, "w_vals"), concat(vals, "j_vals"), concat(vals, "sigma_x"), concat(vals, "sigma_s"))
+    x = torch.zeros(5 * pat.n, dtype=torch.float64, device="cuda")
+    infos = B.solve(concat(vals, "b"), x)
+    xb = x.cpu().numpy()
+    for q in range(5):
+        K = D.condensed(pat, vals[q], vals[q].sigma_s)
+        assert D.backward_errors(K, xb[q * pat.n:(q + 1) * pat.n], vals[q].b)["eta"] <= 1e-10
