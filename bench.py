@@ -41,7 +41,137 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ordering", type=int, default=0)
     ap.add_argument("--nd-leaf", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=256, help="instances of the batched workload (0: skip)")
+    ap.add_argument("--batch-ordering", type=int, default=0)
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests of the served workload (0: skip)")
+    ap.add_argument("--serve-rho", type=float, default=0.8, help="arrival rate / plain-solver capacity")
     return ap.parse_args()
+
+
+def bench_batched(args, kkt, kktgen, torch, dev):
+    """Batched NMPC instances: one batched refactor+solve vs one plain factor per instance."""
+    count = args.batch
+    shapes = kktgen.batch_shapes(count)
+    pats = [kktgen.nmpc_pattern(*sh) for sh in shapes]
+    vals = [kktgen.nmpc_values(p, kktgen.rng_for(3, q, 1), 1e-6, 1e6) for q, p in enumerate(pats)]
+
+    def T(a):
+        return torch.tensor(np.asarray(a), dtype=torch.float64, device=dev)
+
+    syms = [kkt.Symbolic.from_pattern(p, ordering=args.batch_ordering) for p in pats]
+    B = kkt.Batch(syms)
+    cat = {f: T(np.concatenate([getattr(v, f) for v in vals])) for f in ("w_vals", "j_vals", "sigma_x", "sigma_s", "b")}
+    x = torch.zeros(int(B.ofs["n"][-1]), dtype=torch.float64, device=dev)
+
+    def bstep():
+        B.refactor(cat["w_vals"], cat["j_vals"], cat["sigma_x"], cat["sigma_s"])
+        return B.solve(cat["b"], x)
+
+    bstep()
+    reps = 5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        infos = bstep()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    etas = np.array([i["eta"] for i in infos])
+    ok = int((etas <= ETA_GATE).sum())
+    # plain: one factor per instance, one instance per launch sequence
+    facs = [kkt.Factor(s) for s in syms]
+    dv = [dict(w=T(v.w_vals), j=T(v.j_vals), sx=T(v.sigma_x), ss=T(v.sigma_s), b=T(v.b)) for v in vals]
+    xs = [torch.zeros(p.n, dtype=torch.float64, device=dev) for p in pats]
+
+    def pstep():
+        res = []
+        for f, d, xq in zip(facs, dv, xs):
+            f.refactor(d["w"], d["j"], d["sx"], d["ss"])
+            res.append(f.solve(d["b"], xq))
+        return res
+
+    pstep()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pinfos = pstep()
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    pok = int(sum(i["eta"] <= ETA_GATE for i in pinfos))
+    # batched equals plain, bitwise
+    same = all(np.array_equal(x[B.ofs["n"][q]:B.ofs["n"][q + 1]].cpu().numpy(), xs[q].cpu().numpy())
+               for q in range(count))
+    st = [s.stats() for s in syms]
+    return dict(instances=count, sum_n=int(B.ofs["n"][-1]), sum_nnz_l=int(sum(s["nnz_l"] for s in st)),
+                flops_exact=float(sum(s["flops_exact"] for s in st)), ordering=args.batch_ordering,
+                batched_pairs_per_s=round(ok / tb, 2), batched_ms=round(1e3 * tb, 3),
+                plain_pairs_per_s=round(pok / tp, 2), plain_ms=round(1e3 * tp, 3),
+                speedup=round((ok / tb) / max(pok / tp, 1e-12), 2), eta_max=float(etas.max()),
+                passing=f"{ok}/{count}", batched_equals_plain_bitwise=bool(same))
+
+
+def bench_served(args, kkt, kktgen, torch, dev):
+    """Poisson stream over 16 resident patterns: continuous batching vs plain FIFO."""
+    shapes = kktgen.serving_shapes(16)
+    pats = [kktgen.nmpc_pattern(*sh) for sh in shapes]
+    syms = [kkt.Symbolic.from_pattern(p) for p in pats]
+    nvs = 3
+
+    def T(a):
+        return torch.tensor(np.asarray(a), dtype=torch.float64, device=dev)
+
+    pool = []
+    for p, pat in enumerate(pats):
+        vs = [kktgen.nmpc_values(pat, kktgen.rng_for(4, p, 1 + r), 1e-6, 1e6) for r in range(nvs)]
+        pool.append([[T(v.w_vals), T(v.j_vals), T(v.sigma_x), T(v.sigma_s), T(v.b)] for v in vs])
+    # plain capacity on this mix: mean service time of one request alone
+    plain = kkt.Server(hbm_budget=16 << 30, max_wave=1, workers=1)
+    pid = [plain.register(s) for s in syms]
+    xbuf = [torch.zeros(p.n, dtype=torch.float64, device=dev) for p in pats]
+    for p in range(16):
+        plain.wait(plain.submit(pid[p], *pool[p][0], xbuf[p]))
+    plain.reset_stats()
+    for rep in range(2):
+        for p in range(16):
+            plain.wait(plain.submit(pid[p], *pool[p][rep % nvs], xbuf[p]))
+    svc = plain.stats()["mean_service_s"]
+    capacity = 1.0 / svc
+    rate = args.serve_rho * capacity
+    nreq = args.serve_requests
+    times, which = kktgen.poisson_arrivals(rate, nreq, 16)
+    warm = nreq // 20
+
+    def run(server, pids):
+        outs = [[torch.zeros(p.n, dtype=torch.float64, device=dev) for _ in range(8)] for p in pats]
+        tickets = []
+        t0 = time.perf_counter()
+        for k in range(nreq):
+            delay = t0 + times[k] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            p = int(which[k])
+            if k == warm:
+                server.reset_stats()
+            tickets.append(server.submit(pids[p], *pool[p][k % nvs], outs[p][k % 8]))
+        res = [server.wait(t) for t in tickets]
+        st = server.stats()
+        bad = sum(r["status"] != 0 or r["eta"] > ETA_GATE for r in res)
+        return st, bad
+
+    plain.reset_stats()
+    pst, pbad = run(plain, pid)
+    plain.close()
+    cb = kkt.Server(hbm_budget=16 << 30, max_wave=64, workers=2)
+    cid = [cb.register(s) for s in syms]
+    cst, cbad = run(cb, cid)
+    cb.close()
+
+    def pick(st):
+        return {k: (round(st[k] * 1e3, 3) if k.endswith("_s") else round(st[k], 3)) for k in
+                ("p50_s", "p99_s", "mean_queue_s", "mean_service_s", "throughput", "mean_wave")}
+
+    return dict(patterns=16, n_range=[min(p.n for p in pats), max(p.n for p in pats)], requests=nreq,
+                warmup_discarded=warm, rho=args.serve_rho, rate_per_s=round(rate, 2),
+                plain_capacity_per_s=round(capacity, 2), units="latencies in ms, throughput in requests/s",
+                continuous_batching=pick(cst), plain_fifo=pick(pst), failed=int(cbad), plain_failed=int(pbad))
 
 
 def algorithmic_work(stats, pat, n_steps, sweeps_per_step, residuals_per_step, nnz_k_full):
@@ -152,6 +282,9 @@ def main():
                           f"scipy assembly + C up-looking sparse LDL^T in stage order + Richardson refinement, "
                           f"single thread", seconds=round(cs, 3))
 
+    batched = bench_batched(args, kkt, kktgen, torch, dev) if args.batch > 0 else None
+    served = bench_served(args, kkt, kktgen, torch, dev) if args.serve_requests > 0 else None
+
     out = {
         "metric": "KKT refactor+solves/sec at residual <=1e-10 (batched vs plain); served p50/p99",
         "value": round(value, 3),
@@ -179,6 +312,8 @@ def main():
             "phase_ms_per_step": {k: round(v, 4) for k, v in phase_ms.items()},
             "symbolic": {k: stats[k] for k in ("nsuper", "levels", "max_rows", "max_cols", "nnz_k", "nnz_l",
                                                "nnz_l_exact", "flops", "flops_exact")},
+            "batched": batched,
+            "served": served,
         },
     }
     print(json.dumps(out), flush=True)

@@ -117,6 +117,29 @@ __device__ inline d4 tile_abt(const double* P, int ld, int i0, int j0, int k0, i
     return acc;
 }
 
+// Copy n doubles (n even, both 16-byte aligned) with 8 independent 16-byte
+// loads in flight per thread.
+__device__ inline void copy_vec(double* __restrict__ dst, const double* __restrict__ src, int n, int tid, int nt) {
+    const double2* s2 = (const double2*)src;
+    double2* d2 = (double2*)dst;
+    const int n2 = n >> 1;
+    for (int base = tid; base < n2; base += nt * 8) {
+        double2 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int q = base + k * nt;
+            if (q < n2) v[k] = s2[q];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int q = base + k * nt;
+            if (q < n2) d2[q] = v[k];
+        }
+    }
+}
+
+__device__ inline int even_up(int x) { return (x + 1) & ~1; }
+
 // lower-triangular tile enumeration: t -> (ti, tj) with tj0 <= tj <= ti < nb
 __device__ inline void tri_tile(int t, int tj0, int nb, int& ti, int& tj) {
     tj = tj0;
@@ -138,7 +161,7 @@ constexpr int kFactorThreads = 512;
 
 __global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __restrict__ insts,
                                                           const WorkItem* __restrict__ items) {
-    extern __shared__ double P[];
+    extern __shared__ __align__(16) double P[];
     __shared__ double invd[16];
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
@@ -146,7 +169,7 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __rest
     const int s = it.id;
     const int c = T.sn_ncol[s], r = T.sn_nrow[s], u = r - c, col0 = T.sn_col0[s];
     const int rp = rup16(r), cp = rup16(c);
-    const int ld = rp + 1;
+    const int ld = r | 1;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
 
@@ -165,12 +188,24 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __rest
         const int* __restrict__ rl = T.rel + T.sn_rowofs[ch] + cc;
         for (int a = tid; a < uc; a += nt) srel[a] = rl[a];
         __syncthreads();
-        // entries (a, b), a >= b, of the child's update matrix whose column b maps into the panel
-        int b = tid / uc, a = tid - b * uc;
-        for (int qq = tid; qq < nb * uc; qq += nt) {
-            if (a >= b) P[srel[b] * ld + srel[a]] += Uc[qq];
-            a += nt;
-            while (a >= uc) { a -= uc; b++; }
+        // entries (a, b), a >= b, of the child's update matrix whose column b
+        // maps into the panel; 8 loads in flight per thread
+        const int tot = nb * uc;
+        for (int base = tid; base < tot; base += nt * 8) {
+            double v[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const int qq = base + k * nt;
+                v[k] = qq < tot ? Uc[qq] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const int qq = base + k * nt;
+                if (qq < tot) {
+                    const int b = qq / uc, a = qq - b * uc;
+                    if (a >= b) P[srel[b] * ld + srel[a]] += v[k];
+                }
+            }
         }
         __syncthreads();
     }
@@ -183,7 +218,7 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __rest
             const int i = lane;
             double a[16];
 #pragma unroll
-            for (int k = 0; k < 16; k++) a[k] = (i < 16 && j0 + i < rp) ? P[(j0 + k) * ld + j0 + i] : 0.0;
+            for (int k = 0; k < 16; k++) a[k] = (i < 16 && j0 + i < r) ? P[(j0 + k) * ld + j0 + i] : 0.0;
 #pragma unroll
             for (int j = 0; j < 16; j++) {
                 if (j < w) {
@@ -254,15 +289,8 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __rest
         }
     }
 
-    double* __restrict__ Ls = I.L + T.sn_lofs[s];
-    {
-        int k = tid / r, i = tid - k * r;
-        for (int q = tid; q < r * c; q += nt) {
-            Ls[q] = P[k * ld + i];
-            i += nt;
-            while (i >= r) { i -= r; k++; }
-        }
-    }
+    // panel -> HBM: same layout, contiguous 16-byte stores
+    copy_vec(I.L + T.sn_lofs[s], P, even_up(ld * c), tid, nt);
     if (u == 0) return;
     // update matrix U = -L21 L21^T (lower part) on the matrix cores
     double* __restrict__ Us = I.U + T.sn_uofs[s];
@@ -290,11 +318,28 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __rest
         for (int a = tid; a < uc; a += nt) srel[a] = rl[a] - c;
         __syncthreads();
         const int64_t base = (int64_t)nb * uc;
-        int b = nb + tid / uc, a = tid - (tid / uc) * uc;
-        for (int qq = tid; qq < (uc - nb) * uc; qq += nt) {
-            if (a >= b) Us[(int64_t)srel[b] * u + srel[a]] += Uc[base + qq];
-            a += nt;
-            while (a >= uc) { a -= uc; b++; }
+        const int tot = (uc - nb) * uc;
+        for (int b0 = tid; b0 < tot; b0 += nt * 8) {
+            double v[8], cur[8];
+            int64_t dst[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const int qq = b0 + k * nt;
+                dst[k] = -1;
+                v[k] = 0.0;
+                cur[k] = 0.0;
+                if (qq < tot) {
+                    const int b = nb + qq / uc, a = qq - (qq / uc) * uc;
+                    if (a >= b) {
+                        dst[k] = (int64_t)srel[b] * u + srel[a];
+                        v[k] = Uc[base + qq];
+                        cur[k] = Us[dst[k]];
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 8; k++)
+                if (dst[k] >= 0) Us[dst[k]] = cur[k] + v[k];
         }
         __syncthreads();
     }
@@ -308,18 +353,9 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __rest
 // threads. Reciprocals of the pivots come from the factorisation.
 constexpr int kSolveThreads = 256;
 
-__device__ inline void stage_panel(double* P, int ld, const double* __restrict__ Ls, int r, int c, int tid, int nt) {
-    int k = tid / r, i = tid - k * r;
-    for (int q = tid; q < r * c; q += nt) {
-        P[k * ld + i] = Ls[q];
-        i += nt;
-        while (i >= r) { i -= r; k++; }
-    }
-}
-
 __global__ __launch_bounds__(kSolveThreads) void k_fwd(const InstDev* __restrict__ insts,
                                                       const WorkItem* __restrict__ items, int skip_done) {
-    extern __shared__ double sh[];
+    extern __shared__ __align__(16) double sh[];
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
     if (skip_done && I.rs->done) return;
@@ -329,10 +365,10 @@ __global__ __launch_bounds__(kSolveThreads) void k_fwd(const InstDev* __restrict
     const int ld = r | 1;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
     double* P = sh;
-    double* w = sh + (int64_t)ld * c;
+    double* w = sh + even_up(ld * c);
     double* va = w + c;
     double* dv = va + u;
-    stage_panel(P, ld, I.L + T.sn_lofs[s], r, c, tid, nt);
+    copy_vec(P, I.L + T.sn_lofs[s], even_up(ld * c), tid, nt);
     for (int t = tid; t < c; t += nt) {
         w[t] = I.y[col0 + t];
         dv[t] = I.dinv[col0 + t];
@@ -382,7 +418,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_fwd(const InstDev* __restrict
 
 __global__ __launch_bounds__(kSolveThreads) void k_bwd(const InstDev* __restrict__ insts,
                                                       const WorkItem* __restrict__ items, int skip_done) {
-    extern __shared__ double sh[];
+    extern __shared__ __align__(16) double sh[];
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
     if (skip_done && I.rs->done) return;
@@ -392,11 +428,11 @@ __global__ __launch_bounds__(kSolveThreads) void k_bwd(const InstDev* __restrict
     const int ld = r | 1;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
     double* P = sh;
-    double* t = sh + (int64_t)ld * c;
+    double* t = sh + even_up(ld * c);
     double* zu = t + c;
     double* dv = zu + u;
     const int* __restrict__ rw = T.rows + T.sn_rowofs[s] + c;
-    stage_panel(P, ld, I.L + T.sn_lofs[s], r, c, tid, nt);
+    copy_vec(P, I.L + T.sn_lofs[s], even_up(ld * c), tid, nt);
     for (int i = tid; i < u; i += nt) zu[i] = I.y[rw[i]];
     for (int k = tid; k < c; k += nt) dv[k] = I.dinv[col0 + k];
     __syncthreads();

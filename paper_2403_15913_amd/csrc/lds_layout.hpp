@@ -7,14 +7,17 @@
 
 namespace kkt {
 
-// factor: (rup16(r)+1) x rup16(c) panel of doubles + r staged relative indices
+// Panels use an odd leading dimension r|1 in LDS and in HBM (conflict-free
+// strided LDS access; the HBM<->LDS copies are contiguous).
+// factor: (r|1) x rup16(c) panel of doubles (columns padded to the 16-wide
+// matrix-core tile) + r staged relative indices
 inline int64_t factor_lds_bytes(int r, int c) {
-    const int64_t rp = (r + 15) & ~15, cp = (c + 15) & ~15;
-    return (rp + 1) * cp * 8 + (int64_t)r * 4;
+    const int64_t cp = (c + 15) & ~15;
+    return (int64_t)(r | 1) * cp * 8 + (int64_t)r * 4 + 16;
 }
 
-// sweeps: (r|1) x c panel + r vector entries + c pivot reciprocals
-inline int64_t solve_lds_bytes(int r, int c) { return ((int64_t)(r | 1) * c + r + c) * 8; }
+// sweeps: (r|1) x c panel (padded to an even count) + r vector entries + c pivot reciprocals
+inline int64_t solve_lds_bytes(int r, int c) { return ((((int64_t)(r | 1) * c + 1) & ~(int64_t)1) + r + c) * 8; }
 
 inline int64_t front_lds_bytes(int r, int c) { return std::max(factor_lds_bytes(r, c), solve_lds_bytes(r, c)); }
 

@@ -572,7 +572,9 @@ int analyze(int n, int m, const int32_t* wp, const int32_t* wi, const int32_t* j
     S.flops = 0;
     for (int s = 0; s < ns; s++) {
         int r = S.sn_nrow[s], c = S.sn_ncol[s], u = r - c;
-        S.sn_lofs[s + 1] = S.sn_lofs[s] + (int64_t)r * c;
+        // panel stored column-major with leading dimension r|1 (odd, as in
+        // LDS), padded to an even count so every panel starts 16-byte aligned
+        S.sn_lofs[s + 1] = S.sn_lofs[s] + (((int64_t)(r | 1) * c + 1) & ~(int64_t)1);
         S.sn_uofs[s + 1] = S.sn_uofs[s] + (int64_t)u * u;
         S.sn_vofs[s + 1] = S.sn_vofs[s] + u;
         for (int k = 0; k < c; k++) S.flops += (double)(r - k - 1) * (r - k) + (r - k - 1);

@@ -33,7 +33,7 @@ struct Symbolic {
 
     int ns = 0;
     std::vector<int> sn_col0, sn_ncol, sn_nrow, sn_parent, sn_level;
-    std::vector<int64_t> sn_rowofs, sn_lofs, sn_uofs, sn_vofs;
+    std::vector<int64_t> sn_rowofs, sn_lofs, sn_uofs, sn_vofs;  // panels: ld = nrow|1, even length
     std::vector<int> rows;                 // row structure of every front
     std::vector<int> rel;                  // rel[rowofs[s]+ncol+a]: local row of update row a in the parent front
     std::vector<int> rel_np;               // update rows of s that fall in the parent's own columns

@@ -99,13 +99,21 @@ def test_small_budget_forces_small_waves(kkt):
     pats = patterns(2)
     syms = [kkt.Symbolic.from_pattern(p) for p in pats]
     from paper_2403_15913_amd import kkt as K
-    # room for about two requests per worker
-    need = max(pats[0].n, pats[1].n) * 8 * 400
-    srv = K.Server(hbm_budget=need, max_wave=64, workers=1)
-    try:
-        pid = [srv.register(s) for s in syms]
-    except K.KKTError:
-        pytest.skip("budget heuristic too small for these shapes")
+    # smallest budget that admits the larger pattern, then room for about two requests
+    budget = 1 << 20
+    while True:
+        probe = K.Server(hbm_budget=budget, max_wave=64, workers=1)
+        try:
+            for s in syms:
+                probe.register(s)
+            break
+        except K.KKTError as e:
+            assert e.status == 9
+            budget *= 2
+        finally:
+            probe.close()
+    srv = K.Server(hbm_budget=int(budget * 1.5), max_wave=64, workers=1)
+    pid = [srv.register(s) for s in syms]
     tickets, xs, vals, keep = [], [], [], []
     for q in range(10):
         p = q % 2
