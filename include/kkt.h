@@ -228,8 +228,8 @@ kkt_status kkt_matvec(kkt_factor* f, const double* x, double* y, void* stream);
 
 /* Kernel phases timed by the per-launch event timers. */
 #define KKT_PHASE_ASSEMBLE 0  /* K = W + Sigma_x + J^T d J */
-#define KKT_PHASE_FACTOR 1    /* supernodal Cholesky (one launch per tree level) */
-#define KKT_PHASE_FWD 2       /* forward sweep L y = P b */
+#define KKT_PHASE_FACTOR 1    /* supernodal Cholesky (one launch per tree level, or one queue launch) */
+#define KKT_PHASE_FWD 2       /* forward sweep L y = P b (with the queue schedule: both sweeps) */
 #define KKT_PHASE_BWD 3       /* backward sweep L^T z = y */
 #define KKT_PHASE_RESIDUAL 4  /* r = b - K x and backward-error reductions */
 #define KKT_PHASE_PERMUTE 5   /* gathers between original and pivot order */
@@ -250,10 +250,31 @@ kkt_status kkt_factor_set_timing(kkt_factor* f, int32_t enable);
 kkt_status kkt_factor_read_timing(kkt_factor* f, kkt_timing* out);
 
 /*
+ * Launch schedules of the supernode tree (factorization and both sweeps; the
+ * tree is the elimination tree of the supernodal Cholesky, section "Hybrid
+ * linear solver", and every front depends on its children only).
+ *   LEVELS: one launch per tree level (leaves first for the factor and the
+ *           forward sweep, roots first for the backward sweep).
+ *   QUEUE:  one persistent launch for the factor and one for both sweeps;
+ *           workgroups take fronts from a ticket counter in topological order
+ *           and wait on per-front dependency counters, so fronts of different
+ *           levels (and instances) overlap. A dependency wait that exceeds its
+ *           spin bound makes the next status read return KKT_ERR_DEVICE.
+ * Both schedules run the same per-front arithmetic in the same order, so
+ * results are bitwise identical. The default is LEVELS. Host only; applies
+ * to launches issued after the call.
+ */
+#define KKT_SCHEDULE_LEVELS 0
+#define KKT_SCHEDULE_QUEUE 1
+kkt_status kkt_factor_set_schedule(kkt_factor* f, int32_t schedule);
+
+/*
  * Batched form: many independent instances (each with its own pattern; the
  * same symbolic object may appear several times) refactored and solved by
- * the same launches. Every launch covers one tree level of all instances, so
- * small NMPC-sized fronts from different instances share the GPU.
+ * the same launches. With the LEVELS schedule every launch covers one tree
+ * level of all instances; with QUEUE one persistent launch walks the fronts
+ * of all instances; either way small NMPC-sized fronts from different
+ * instances share the GPU.
  *
  * Values and vectors are concatenated in instance order: instance q owns
  * w_vals[w_ofs[q] .. w_ofs[q+1]), j_vals[j_ofs[q] ..), sigma_x / b / x
@@ -282,6 +303,32 @@ kkt_status kkt_batch_solve(kkt_batch* b, const double* rhs, double* x, const kkt
 /* Waits and reports each instance's factor status and failing column (original
  * index, -1 if none); either array (count entries) may be NULL. */
 kkt_status kkt_batch_status(kkt_batch* b, int32_t* status, int32_t* bad_col);
+
+/* Launch schedule of the batch (see KKT_SCHEDULE_*). */
+kkt_status kkt_batch_set_schedule(kkt_batch* b, int32_t schedule);
+
+/*
+ * Graph form of kkt_batch_refactor + kkt_batch_solve. kkt_batch_capture
+ * records, as one HIP graph on a stream private to the batch, the status
+ * reset, assembly, factorization, first solve and `rounds` refinement rounds
+ * (each: residual, stop decision, and a correction for the instances still
+ * refining), bound to the given device arrays; it runs nothing. The graph
+ * holds kernel nodes only. kkt_batch_replay launches it on `stream`, then
+ * continues the refinement loop on the host from round `rounds` (for the
+ * instances not yet stopped), applies the better-of-last-two rule and fills
+ * `infos` (count entries, may be NULL); it synchronises the stream and
+ * returns as kkt_batch_solve does. Every instance goes through exactly the
+ * operations of the two separate calls, so the results are bitwise the same.
+ * The caller refreshes the arrays' contents between replays and keeps them
+ * allocated while the graph exists. A new capture replaces the old one;
+ * kkt_batch_destroy releases it.
+ * Errors: INVALID_ARG (NULL arrays, x aliasing rhs, bad refinement options,
+ * rounds outside 0..max_iter+1), STATE (replay without a capture), HIP.
+ */
+kkt_status kkt_batch_capture(kkt_batch* b, const double* w_vals, const double* j_vals, const double* sigma_x,
+                             const double* sigma_s, const double* rhs, double* x, const kkt_refine_opts* ro,
+                             int32_t rounds);
+kkt_status kkt_batch_replay(kkt_batch* b, kkt_solve_info* infos, void* stream);
 
 kkt_status kkt_batch_set_timing(kkt_batch* b, int32_t enable);
 kkt_status kkt_batch_read_timing(kkt_batch* b, kkt_timing* out);

@@ -1,0 +1,153 @@
+"""Autotuner for the symbolic options that shape the GPU work.
+
+For a pattern (or a batch of patterns) it measures refactor+solve on the
+device for a set of candidate options -- ordering (natural stage order or
+nested dissection), nested-dissection leaf size, widest supernode -- and
+keeps the fastest candidate whose solves all pass the backward-error gate.
+These options decide the supernode tree the kernels run on: the depth of
+the dependency chain, the front sizes (rows x columns of every LDS panel and
+of the matrix-core tiles), and the total flops.
+
+Results are cached in a JSON table keyed by a pattern signature, so a
+pattern is tuned once and later analyses reuse the choice:
+
+    from paper_2403_15913_amd import autotune
+    opts = autotune.tune_pattern(pat, vals)            # measure (GPU)
+    sym = kkt.Symbolic.from_pattern(pat, **opts)
+
+Timing uses the library's own calls; nothing here computes any part of the
+solve.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+
+import numpy as np
+
+from . import kkt
+
+DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_table.json")
+ETA_GATE = 1e-10
+
+
+def signature(pat) -> str:
+    """Stable key of a sparsity pattern (sizes + a hash of the index arrays)."""
+    h = hashlib.sha1()
+    for a in (pat.w_rowptr, pat.w_colind, pat.j_rowptr, pat.j_colind):
+        h.update(np.ascontiguousarray(a, dtype=np.int32).tobytes())
+    return f"n{pat.n}-m{pat.m}-w{pat.nnz_w}-j{pat.nnz_j}-{h.hexdigest()[:16]}"
+
+
+def candidates(n: int):
+    """Option sets to try for a pattern of n variables."""
+    out = [dict(ordering=kkt.ORDER_NATURAL, nd_leaf=0, max_super=96)]
+    for leaf in sorted({max(64, n // k) for k in (1024, 512, 256, 128, 64, 16)}):
+        if leaf < n:
+            for ms in (64, 96):
+                out.append(dict(ordering=kkt.ORDER_ND, nd_leaf=int(leaf), max_super=ms))
+    return out
+
+
+def load_table(path: str = DEFAULT_TABLE) -> dict:
+    if os.path.exists(path):
+        with open(path) as fh:
+            return json.load(fh)
+    return {}
+
+
+def save_table(table: dict, path: str = DEFAULT_TABLE):
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _dev(a):
+    import torch
+    return torch.tensor(np.asarray(a), dtype=torch.float64, device="cuda")
+
+
+def _time_plain(pat, vals, opts, reps: int):
+    import torch
+    sym = kkt.Symbolic.from_pattern(pat, **opts)
+    f = kkt.Factor(sym)
+    d = [_dev(vals.w_vals), _dev(vals.j_vals), _dev(vals.sigma_x), _dev(vals.sigma_s)]
+    b = _dev(vals.b)
+    x = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
+    f.refactor(*d)
+    f.solve(b, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    worst = 0.0
+    for _ in range(reps):
+        f.refactor(*d)
+        worst = max(worst, f.solve(b, x)["eta"])
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, worst, sym.stats()
+
+
+def _time_batch(pats, vals, opts, reps: int):
+    import torch
+    syms = [kkt.Symbolic.from_pattern(p, **opts) for p in pats]
+    B = kkt.Batch(syms)
+    cat = [_dev(np.concatenate([getattr(v, f) for v in vals])) for f in ("w_vals", "j_vals", "sigma_x", "sigma_s")]
+    b = _dev(np.concatenate([v.b for v in vals]))
+    x = torch.zeros(int(B.ofs["n"][-1]), dtype=torch.float64, device="cuda")
+    B.refactor(*cat)
+    B.solve(b, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    worst = 0.0
+    for _ in range(reps):
+        B.refactor(*cat)
+        worst = max(worst, max(i["eta"] for i in B.solve(b, x)))
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, worst, None
+
+
+def tune_pattern(pat, vals, reps: int = 3, table_path: str | None = DEFAULT_TABLE, force: bool = False,
+                 log=None) -> dict:
+    """Best options for one pattern (measured on the GPU, cached by signature)."""
+    key = signature(pat)
+    table = load_table(table_path) if table_path else {}
+    if not force and key in table:
+        return dict(table[key]["options"])
+    results = []
+    for opts in candidates(pat.n):
+        try:
+            t, eta, st = _time_plain(pat, vals, opts, reps)
+        except kkt.KKTError as e:
+            if log:
+                log(f"{opts}: {e}")
+            continue
+        results.append((t, eta, opts, st))
+        if log:
+            log(f"{opts}: {1e3 * t:.3f} ms, eta {eta:.1e}, levels {st['levels']}, flops {st['flops']:.3g}")
+    ok = [r for r in results if r[1] <= ETA_GATE]
+    if not ok:
+        raise RuntimeError("no candidate passed the backward-error gate")
+    t, eta, best, st = min(ok, key=lambda r: r[0])
+    if table_path:
+        table[key] = dict(options=best, ms=1e3 * t, eta=eta,
+                          tried=[dict(options=o, ms=1e3 * tt) for tt, _, o, _ in results])
+        save_table(table, table_path)
+    return dict(best)
+
+
+def tune_batch(pats, vals, reps: int = 3, log=None) -> dict:
+    """One option set for a whole batch (measured as a batched refactor + solve)."""
+    nmax = max(p.n for p in pats)
+    tried = []
+    for opts in [dict(ordering=kkt.ORDER_NATURAL, nd_leaf=0, max_super=96),
+                 dict(ordering=kkt.ORDER_NATURAL, nd_leaf=0, max_super=64)] + \
+            [dict(ordering=kkt.ORDER_ND, nd_leaf=leaf, max_super=96) for leaf in (128, 256, 512, 1024) if leaf < nmax]:
+        t, eta, _ = _time_batch(pats, vals, opts, reps)
+        tried.append((t, eta, opts))
+        if log:
+            log(f"{opts}: {1e3 * t:.3f} ms, eta {eta:.1e}")
+    ok = [r for r in tried if r[1] <= ETA_GATE]
+    t, eta, best = min(ok, key=lambda r: r[0])
+    return dict(best, ms=1e3 * t)

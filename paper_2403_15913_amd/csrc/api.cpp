@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -158,6 +159,8 @@ hipError_t DevPattern::build(const Symbolic& S) {
 // Engine
 // ---------------------------------------------------------------------------
 Engine::~Engine() {
+    drop_graph();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (hpin) (void)hipHostFree(hpin);
 }
 
@@ -251,6 +254,9 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     nitems = cv.take<WorkItem>(nnb);
     mitems = cv.take<WorkItem>(nmb);
     kitems = cv.take<WorkItem>(nkb);
+    dep_parent = cv.take<int>(nsn);
+    dep_nchild = cv.take<int>(nsn);
+    dep_ctr = cv.take<int>(3 * nsn + 2);
     stage = Staging{};
     if (staging) {
         stage.w = cv.take<double>(w_ofs[ninst]);
@@ -306,6 +312,21 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         }
         lvl_ptr.push_back((int)sn.size());
     }
+    // dependency lists in the same (topological) item order
+    std::vector<int> dpar(sn.size(), -1), dnch(sn.size(), 0);
+    {
+        std::vector<std::vector<int>> item_of(ninst);
+        for (int q = 0; q < ninst; q++) item_of[q].assign(s[q]->ns, -1);
+        for (size_t t = 0; t < sn.size(); t++) item_of[sn[t].inst][sn[t].id] = (int)t;
+        for (size_t t = 0; t < sn.size(); t++) {
+            const Symbolic& S = *s[sn[t].inst];
+            const int par = S.sn_parent[sn[t].id];
+            if (par >= 0) {
+                dpar[t] = item_of[sn[t].inst][par];
+                dnch[dpar[t]]++;
+            }
+        }
+    }
     for (int q = 0; q < ninst; q++) {
         const Symbolic& S = *s[q];
         for (int i = 0; i < S.n; i += kBlock) nb.push_back(WorkItem{q, i});
@@ -316,24 +337,31 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     n_mitems = (int)mb.size();
     n_kitems = (int)kb.size();
     // one packed upload from pinned memory
-    const size_t b_inst = (size_t)ninst * sizeof(InstDev), b_sn = sn.size() * sizeof(WorkItem),
-                 b_nb = nb.size() * sizeof(WorkItem), b_mb = mb.size() * sizeof(WorkItem),
-                 b_kb = kb.size() * sizeof(WorkItem);
+    struct Piece { void* dst; const void* src; size_t bytes; } pieces[] = {
+        {dinsts, hinst.data(), (size_t)ninst * sizeof(InstDev)},
+        {snitems, sn.data(), sn.size() * sizeof(WorkItem)},
+        {nitems, nb.data(), nb.size() * sizeof(WorkItem)},
+        {mitems, mb.data(), mb.size() * sizeof(WorkItem)},
+        {kitems, kb.data(), kb.size() * sizeof(WorkItem)},
+        {dep_parent, dpar.data(), dpar.size() * sizeof(int)},
+        {dep_nchild, dnch.data(), dnch.size() * sizeof(int)},
+    };
+    size_t up_bytes = 0;
+    for (auto& pc : pieces) up_bytes += pc.bytes;
     const size_t readback = (size_t)ninst * std::max(sizeof(RefineState), sizeof(CgState)) + 64;
-    hipError_t e = ensure_pinned(std::max(b_inst + b_sn + b_nb + b_mb + b_kb, readback));
+    hipError_t e = ensure_pinned(std::max(up_bytes, readback));
     if (e != hipSuccess) return hip_fail(e, "pinned host buffer");
+    // one packed staging buffer, one copy per piece
     char* h = (char*)hpin;
-    std::memcpy(h, hinst.data(), b_inst);
-    if (b_sn) std::memcpy(h + b_inst, sn.data(), b_sn);
-    if (b_nb) std::memcpy(h + b_inst + b_sn, nb.data(), b_nb);
-    if (b_mb) std::memcpy(h + b_inst + b_sn + b_nb, mb.data(), b_mb);
-    if (b_kb) std::memcpy(h + b_inst + b_sn + b_nb + b_mb, kb.data(), b_kb);
-    struct { void* dst; size_t off, bytes; } ups[] = {
-        {dinsts, 0, b_inst}, {snitems, b_inst, b_sn}, {nitems, b_inst + b_sn, b_nb},
-        {mitems, b_inst + b_sn + b_nb, b_mb}, {kitems, b_inst + b_sn + b_nb + b_mb, b_kb}};
-    for (auto& u : ups)
-        if (u.bytes && (e = hipMemcpyAsync(u.dst, h + u.off, u.bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
-            return hip_fail(e, "descriptor upload");
+    size_t off = 0;
+    for (auto& pc : pieces) {
+        if (pc.bytes) {
+            std::memcpy(h + off, pc.src, pc.bytes);
+            if ((e = hipMemcpyAsync(pc.dst, h + off, pc.bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
+                return hip_fail(e, "descriptor upload");
+        }
+        off += pc.bytes;
+    }
     if ((e = hipMemsetAsync(status, 0, 2 * (size_t)ninst * sizeof(int), st)) != hipSuccess ||
         (e = hipMemsetAsync(rs, 0, (size_t)ninst * sizeof(RefineState), st)) != hipSuccess ||
         (e = hipMemsetAsync(cg, 0, (size_t)ninst * sizeof(CgState), st)) != hipSuccess)
@@ -375,20 +403,37 @@ kkt_status Engine::init_owned(const std::vector<const Symbolic*>& s) {
     return KKT_OK;
 }
 
+DepLists Engine::deps() const {
+    DepLists D;
+    const int N = lvl_ptr.empty() ? 0 : lvl_ptr.back();
+    D.parent = dep_parent;
+    D.nchild = dep_nchild;
+    D.cnt = dep_ctr;
+    D.fdone = dep_ctr + N;
+    D.bdone = dep_ctr + 2 * N;
+    D.ticket = dep_ctr + 3 * N;
+    D.err = dep_ctr + 3 * N + 1;
+    D.nitems = N;
+    return D;
+}
+
 kkt_status Engine::refactor(const Calls& C, hipStream_t st) {
     last_stream = st;
     mode = C.gamma == 0.0 ? 1 : 2;
     gamma = C.gamma;
-    int* stat = status;
     // per instance: status[0] = 0, status[1] = INT_MAX (first failing pivot)
-    for (int q = 0; q < ninst; q++) {
-        TL(KKT_PHASE_CONTROL, launch_fill_i32(stat + 2 * q, 0, 1, st));
-        TL(KKT_PHASE_CONTROL, launch_fill_i32(stat + 2 * q + 1, INT_MAX, 1, st));
-    }
+    TL(KKT_PHASE_CONTROL, launch_status_init(status, ninst, st));
     TL(KKT_PHASE_ASSEMBLE, launch_assemble(di(), C, kitems, n_kitems, st));
     const WorkItem* items = snitems;
-    for (size_t l = 0; l + 1 < lvl_ptr.size(); l++)
-        TL(KKT_PHASE_FACTOR, launch_factor(di(), items + lvl_ptr[l], lvl_ptr[l + 1] - lvl_ptr[l], lds_factor, st));
+    if (queue_sched) {
+        const DepLists D = deps();
+        // counters, ticket and the error latch (the latch is cleared only here)
+        TL(KKT_PHASE_CONTROL, launch_fill_i32(dep_ctr, 0, 3 * (int64_t)D.nitems + 2, st));
+        TL(KKT_PHASE_FACTOR, launch_factor_queue(di(), items, D, std::min(D.nitems, 512), lds_factor, st));
+    } else {
+        for (size_t l = 0; l + 1 < lvl_ptr.size(); l++)
+            TL(KKT_PHASE_FACTOR, launch_factor(di(), items + lvl_ptr[l], lvl_ptr[l + 1] - lvl_ptr[l], lds_factor, st));
+    }
     if (mode == 2 && j_ofs[ninst] > 0) {
         hipError_t e = hipMemcpyAsync(jcopy, C.jv, (size_t)j_ofs[ninst] * 8, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return hip_fail(e, "copy J values");
@@ -401,6 +446,12 @@ kkt_status Engine::refactor(const Calls& C, hipStream_t st) {
 
 void Engine::sweeps(hipStream_t st, int skip_done) {
     const WorkItem* items = snitems;
+    if (queue_sched) {
+        const DepLists D = deps();
+        TL(KKT_PHASE_CONTROL, launch_fill_i32(dep_ctr, 0, 3 * (int64_t)D.nitems + 1, st));
+        TL(KKT_PHASE_FWD, launch_sweeps_queue(di(), items, D, std::min(2 * D.nitems, 1024), lds_solve, skip_done, st));
+        return;
+    }
     const int nl = (int)lvl_ptr.size() - 1;
     for (int l = 0; l < nl; l++)
         TL(KKT_PHASE_FWD, launch_fwd(di(), items + lvl_ptr[l], lvl_ptr[l + 1] - lvl_ptr[l], lds_solve, skip_done, st));
@@ -410,8 +461,11 @@ void Engine::sweeps(hipStream_t st, int skip_done) {
 
 kkt_status Engine::read_status(int* st_out, int* bad_out) {
     hipError_t e = hipStreamSynchronize(last_stream);
+    int derr = 0;
+    if (e == hipSuccess) e = hipMemcpy(&derr, deps().err, sizeof(int), hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(hpin, status, (size_t)ninst * 8, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "status read");
+    if (derr) return fail(KKT_ERR_DEVICE, "a dependency wait of the queue schedule timed out");
     const int* hs = (const int*)hpin;
     kkt_status worst = KKT_OK;
     for (int q = 0; q < ninst; q++) {
@@ -425,28 +479,49 @@ kkt_status Engine::read_status(int* st_out, int* bad_out) {
     return worst;
 }
 
+// first solve from the right-hand side (refinement state reset)
+void Engine::solve_start(const Calls& C, int maxit, double tol, hipStream_t st) {
+    TL(KKT_PHASE_CONTROL, launch_refine_reset(di(), ninst, tol, maxit, st));
+    TL(KKT_PHASE_CONTROL, launch_fill_i32(ndone, 0, 1, st));
+    TL(KKT_PHASE_PERMUTE, launch_perm_in(di(), C, nitems, n_nitems, PIN_B, st));
+    sweeps(st, 0);
+    TL(KKT_PHASE_PERMUTE, launch_perm_out(di(), C, nitems, n_nitems, POUT_X, st));
+}
+
+// residual + stop decision of every instance still refining
+void Engine::refine_check(const Calls& C, hipStream_t st) {
+    TL(KKT_PHASE_RESIDUAL, launch_residual(di(), C, nitems, n_nitems, st));
+    TL(KKT_PHASE_CONTROL, launch_refine_decide(di(), ninst, ndone, st));
+}
+
+// one correction x += K^{-1} r of every instance still refining
+void Engine::refine_correct(const Calls& C, hipStream_t st) {
+    TL(KKT_PHASE_PERMUTE, launch_perm_in(di(), C, nitems, n_nitems, PIN_R, st));
+    sweeps(st, 1);
+    TL(KKT_PHASE_PERMUTE, launch_perm_out(di(), C, nitems, n_nitems, POUT_X_UPDATE, st));
+}
+
 kkt_status Engine::solve(const Calls& C, int maxit, double tol, kkt_solve_info* infos, hipStream_t st) {
     last_stream = st;
-    const WorkItem* nit = nitems;
-    int* nd = ndone;
-    TL(KKT_PHASE_CONTROL, launch_refine_reset(di(), ninst, tol, maxit, st));
-    TL(KKT_PHASE_CONTROL, launch_fill_i32(nd, 0, 1, st));
-    TL(KKT_PHASE_PERMUTE, launch_perm_in(di(), C, nit, n_nitems, PIN_B, st));
-    sweeps(st, 0);
-    TL(KKT_PHASE_PERMUTE, launch_perm_out(di(), C, nit, n_nitems, POUT_X, st));
+    solve_start(C, maxit, tol, st);
+    return solve_finish(C, 0, maxit, tol, infos, st);
+}
+
+// Host-driven refinement from round `iter0` on: check, stop when every
+// instance is done, else correct. Then the better-of-last-two rule, the
+// factor status and the per-instance reports.
+kkt_status Engine::solve_finish(const Calls& C, int iter0, int maxit, double tol, kkt_solve_info* infos,
+                                hipStream_t st) {
     int* hp = (int*)hpin;
-    for (int iter = 0; iter <= maxit + 1; iter++) {
-        TL(KKT_PHASE_RESIDUAL, launch_residual(di(), C, nit, n_nitems, st));
-        TL(KKT_PHASE_CONTROL, launch_refine_decide(di(), ninst, nd, st));
-        hipError_t e = hipMemcpyAsync(hp, nd, 4, hipMemcpyDeviceToHost, st);
+    for (int iter = iter0; iter <= maxit + 1; iter++) {
+        refine_check(C, st);
+        hipError_t e = hipMemcpyAsync(hp, ndone, 4, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "refinement control");
         if (hp[0] >= ninst) break;
-        TL(KKT_PHASE_PERMUTE, launch_perm_in(di(), C, nit, n_nitems, PIN_R, st));
-        sweeps(st, 1);
-        TL(KKT_PHASE_PERMUTE, launch_perm_out(di(), C, nit, n_nitems, POUT_X_UPDATE, st));
+        refine_correct(C, st);
     }
-    TL(KKT_PHASE_PERMUTE, launch_refine_revert(di(), C, nit, n_nitems, st));
+    TL(KKT_PHASE_PERMUTE, launch_refine_revert(di(), C, nitems, n_nitems, st));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "solve launch");
     // a failed factor makes the solve meaningless: report it
@@ -470,6 +545,68 @@ kkt_status Engine::solve(const Calls& C, int maxit, double tol, kkt_solve_info* 
         if (inf.status != KKT_OK) worst = inf.status;
     }
     return worst;
+}
+
+void Engine::drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+}
+
+// Records refactor + first solve + `rounds` refinement rounds on a private
+// stream. Kernels only (no memset or copy nodes); the per-launch timers are
+// off while recording.
+kkt_status Engine::capture(const Calls& C, int maxit, double tol, int rounds) {
+    drop_graph();
+    hipError_t e = hipSuccess;
+    if (!cap_stream && (e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "capture stream");
+    const bool timing = timer.on;
+    timer.on = false;
+    hipStream_t st = cap_stream;
+    if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+        timer.on = timing;
+        return hip_fail(e, "begin capture");
+    }
+    kkt_status ks = refactor(C, st);
+    if (ks == KKT_OK) {
+        solve_start(C, maxit, tol, st);
+        for (int q = 0; q < rounds; q++) {
+            refine_check(C, st);
+            refine_correct(C, st);
+        }
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(st, &g);
+    timer.on = timing;
+    factored = false;  // nothing ran yet
+    if (ks != KKT_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return ks;
+    }
+    if (ee != hipSuccess) return hip_fail(ee, "end capture");
+    graph = g;
+    if ((e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0)) != hipSuccess) {
+        drop_graph();
+        return hip_fail(e, "graph instantiation");
+    }
+    g_calls = C;
+    g_rounds = rounds;
+    g_maxit = maxit;
+    g_tol = tol;
+    return KKT_OK;
+}
+
+kkt_status Engine::replay(kkt_solve_info* infos, hipStream_t st) {
+    if (!gexec) return fail(KKT_ERR_STATE, "no captured graph");
+    last_stream = st;
+    hipError_t e = hipGraphLaunch(gexec, st);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    mode = 1;
+    gamma = 0.0;
+    factored = true;
+    return solve_finish(g_calls, g_rounds, g_maxit, g_tol, infos, st);
 }
 
 kkt_status Engine::cg_schur(const Calls& C, double tol, int maxit, kkt_cg_info* info, hipStream_t st) {
@@ -742,6 +879,14 @@ kkt_status kkt_factor_set_timing(kkt_factor* f, int32_t enable) {
     return KKT_OK;
 }
 
+kkt_status kkt_factor_set_schedule(kkt_factor* f, int32_t schedule) {
+    if (!f) return fail(KKT_ERR_INVALID_ARG, "NULL factor");
+    if (schedule != KKT_SCHEDULE_LEVELS && schedule != KKT_SCHEDULE_QUEUE)
+        return fail(KKT_ERR_INVALID_ARG, "unknown schedule");
+    f->eng.queue_sched = schedule == KKT_SCHEDULE_QUEUE;
+    return KKT_OK;
+}
+
 kkt_status kkt_factor_read_timing(kkt_factor* f, kkt_timing* out) {
     if (!f || !out) return fail(KKT_ERR_INVALID_ARG, "NULL argument");
     return timing_read(f->eng, out);
@@ -808,6 +953,41 @@ kkt_status kkt_batch_solve(kkt_batch* b, const double* rhs, double* x, const kkt
     C.b = rhs;
     C.x = x;
     return b->eng.solve(C, maxit, tol, infos, (hipStream_t)stream);
+}
+
+kkt_status kkt_batch_capture(kkt_batch* b, const double* w_vals, const double* j_vals, const double* sigma_x,
+                             const double* sigma_s, const double* rhs, double* x, const kkt_refine_opts* ro,
+                             int32_t rounds) {
+    if (!b) return fail(KKT_ERR_INVALID_ARG, "NULL batch");
+    Engine& E = b->eng;
+    kkt_status st = check_values(E, w_vals, j_vals, sigma_x, sigma_s, 0.0);
+    if (st) return st;
+    const int64_t n = E.n_ofs[E.ninst];
+    if (n > 0 && (!rhs || !x)) return fail(KKT_ERR_INVALID_ARG, "NULL vector");
+    if (rhs == x && n > 0) return fail(KKT_ERR_INVALID_ARG, "x aliases b");
+    const int maxit = ro ? ro->max_iter : 10;
+    const double tol = ro ? ro->tol : 1e-14;
+    if (maxit < 0 || !(tol >= 0.0)) return fail(KKT_ERR_INVALID_ARG, "bad refinement options");
+    if (rounds < 0 || rounds > maxit + 1) return fail(KKT_ERR_INVALID_ARG, "rounds outside 0..max_iter+1");
+    Calls C;
+    std::memset(&C, 0, sizeof(C));
+    C.w = w_vals; C.jv = j_vals; C.sx = sigma_x; C.ss = sigma_s;
+    C.b = rhs;
+    C.x = x;
+    return E.capture(C, maxit, tol, rounds);
+}
+
+kkt_status kkt_batch_replay(kkt_batch* b, kkt_solve_info* infos, void* stream) {
+    if (!b) return fail(KKT_ERR_INVALID_ARG, "NULL batch");
+    return b->eng.replay(infos, (hipStream_t)stream);
+}
+
+kkt_status kkt_batch_set_schedule(kkt_batch* b, int32_t schedule) {
+    if (!b) return fail(KKT_ERR_INVALID_ARG, "NULL batch");
+    if (schedule != KKT_SCHEDULE_LEVELS && schedule != KKT_SCHEDULE_QUEUE)
+        return fail(KKT_ERR_INVALID_ARG, "unknown schedule");
+    b->eng.queue_sched = schedule == KKT_SCHEDULE_QUEUE;
+    return KKT_OK;
 }
 
 kkt_status kkt_batch_status(kkt_batch* b, int32_t* status, int32_t* bad_col) {

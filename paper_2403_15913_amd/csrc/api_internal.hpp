@@ -81,6 +81,15 @@ struct Engine {
     CgState* cg = nullptr;
     InstDev* dinsts = nullptr;
     WorkItem *snitems = nullptr, *nitems = nullptr, *mitems = nullptr, *kitems = nullptr;
+    int *dep_parent = nullptr, *dep_nchild = nullptr, *dep_ctr = nullptr;  // queue scheduling
+    bool queue_sched = false;                       // dependency-driven launches (else one launch per level)
+    // captured refactor + solve (batched form)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    Calls g_calls{};
+    int g_rounds = 0, g_maxit = 0;
+    double g_tol = 0.0;
     Staging stage;                                  // used by served waves only
     std::vector<InstDev> hinst;
     std::vector<int> lvl_ptr;
@@ -112,10 +121,20 @@ struct Engine {
     void sweeps(hipStream_t st, int skip_done);
     // Lifted-KKT solve with refinement; infos (ninst entries) filled when non-NULL.
     kkt_status solve(const Calls& C, int maxit, double tol, kkt_solve_info* infos, hipStream_t st);
+    void solve_start(const Calls& C, int maxit, double tol, hipStream_t st);
+    void refine_check(const Calls& C, hipStream_t st);
+    void refine_correct(const Calls& C, hipStream_t st);
+    kkt_status solve_finish(const Calls& C, int iter0, int maxit, double tol, kkt_solve_info* infos,
+                            hipStream_t st);
+    // hipGraph of refactor + first solve + `rounds` refinement rounds, and its replay
+    kkt_status capture(const Calls& C, int maxit, double tol, int rounds);
+    kkt_status replay(kkt_solve_info* infos, hipStream_t st);
+    void drop_graph();
     kkt_status cg_schur(const Calls& C, double tol, int maxit, kkt_cg_info* info, hipStream_t st);
     // waits for st and returns each instance's latched status and failing column (original index)
     kkt_status read_status(int* st_out, int* bad_out);
     hipError_t ensure_pinned(size_t bytes);
+    DepLists deps() const;
 };
 
 // bytes of one instance of a pattern in an engine arena (with staging)

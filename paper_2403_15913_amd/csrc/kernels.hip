@@ -17,6 +17,7 @@
 // All arithmetic is FP64.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdint>
 
 #include "device.hpp"
@@ -36,6 +37,15 @@ __device__ inline double bitsd(unsigned long long v) { return __longlong_as_doub
 __global__ void k_fill_i32(int* __restrict__ p, int v, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// per-instance factor status pairs: (0 = ok, INT_MAX = no failing column yet)
+__global__ void k_status_init(int* __restrict__ status, int ninst) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < ninst) {
+        status[2 * q] = 0;
+        status[2 * q + 1] = INT_MAX;
+    }
 }
 
 // segment copies: blocks (segment, part) stride over one segment each
@@ -117,21 +127,21 @@ __device__ inline d4 tile_abt(const double* P, int ld, int i0, int j0, int k0, i
     return acc;
 }
 
-// Copy n doubles (n even, both 16-byte aligned) with 8 independent 16-byte
+// Copy n doubles (n even, both 16-byte aligned) with 16 independent 16-byte
 // loads in flight per thread.
 __device__ inline void copy_vec(double* __restrict__ dst, const double* __restrict__ src, int n, int tid, int nt) {
     const double2* s2 = (const double2*)src;
     double2* d2 = (double2*)dst;
     const int n2 = n >> 1;
-    for (int base = tid; base < n2; base += nt * 8) {
-        double2 v[8];
+    for (int base = tid; base < n2; base += nt * 16) {
+        double2 v[16];
 #pragma unroll
-        for (int k = 0; k < 8; k++) {
+        for (int k = 0; k < 16; k++) {
             const int q = base + k * nt;
             if (q < n2) v[k] = s2[q];
         }
 #pragma unroll
-        for (int k = 0; k < 8; k++) {
+        for (int k = 0; k < 16; k++) {
             const int q = base + k * nt;
             if (q < n2) d2[q] = v[k];
         }
@@ -139,6 +149,26 @@ __device__ inline void copy_vec(double* __restrict__ dst, const double* __restri
 }
 
 __device__ inline int even_up(int x) { return (x + 1) & ~1; }
+
+// Loop over q in [0, tot) in batches: every thread first issues up to UNR
+// independent loads (load(q)), then consumes them (use(q, value)), so up to
+// UNR global loads per thread are in flight at once.
+template <int UNR, class LoadF, class UseF>
+__device__ inline void batched(int tot, int tid, int nt, LoadF load, UseF use) {
+    for (int base = tid; base < tot; base += nt * UNR) {
+        double v[UNR];
+#pragma unroll
+        for (int k = 0; k < UNR; k++) {
+            const int q = base + k * nt;
+            v[k] = q < tot ? load(q) : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < UNR; k++) {
+            const int q = base + k * nt;
+            if (q < tot) use(q, v[k]);
+        }
+    }
+}
 
 // lower-triangular tile enumeration: t -> (ti, tj) with tj0 <= tj <= ti < nb
 __device__ inline void tri_tile(int t, int tj0, int nb, int& ti, int& tj) {
@@ -159,14 +189,8 @@ __device__ inline void tri_tile(int t, int tj0, int nb, int& ti, int& tj) {
 // and the children's pass-through entries are added to it.
 constexpr int kFactorThreads = 512;
 
-__global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __restrict__ insts,
-                                                          const WorkItem* __restrict__ items) {
-    extern __shared__ __align__(16) double P[];
-    __shared__ double invd[16];
-    const WorkItem it = items[blockIdx.x];
-    const InstDev& I = insts[it.inst];
+__device__ void factor_front(const InstDev& I, const int s, double* __restrict__ P, double* invd) {
     const PatDev& T = I.P;
-    const int s = it.id;
     const int c = T.sn_ncol[s], r = T.sn_nrow[s], u = r - c, col0 = T.sn_col0[s];
     const int rp = rup16(r), cp = rup16(c);
     const int ld = r | 1;
@@ -175,9 +199,15 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __rest
 
     for (int q = tid; q < ld * cp; q += nt) P[q] = 0.0;
     __syncthreads();
-    for (int64_t e = T.k_snptr[s] + tid; e < T.k_snptr[s + 1]; e += nt) {
-        const int loc = T.k_loc[e];
-        P[(loc >> 16) * ld + (loc & 0xffff)] = I.kval[e];
+    {
+        const int64_t e0 = T.k_snptr[s];
+        const int* __restrict__ kl = T.k_loc + e0;
+        const double* __restrict__ kv = I.kval + e0;
+        batched<8>((int)(T.k_snptr[s + 1] - e0), tid, nt, [&](int q) { return kv[q]; },
+                   [&](int q, double v) {
+                       const int loc = kl[q];
+                       P[(loc >> 16) * ld + (loc & 0xffff)] = v;
+                   });
     }
     __syncthreads();
     int* srel = (int*)(P + ld * cp);  // relative indices of the child being added
@@ -189,24 +219,12 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __rest
         for (int a = tid; a < uc; a += nt) srel[a] = rl[a];
         __syncthreads();
         // entries (a, b), a >= b, of the child's update matrix whose column b
-        // maps into the panel; 8 loads in flight per thread
-        const int tot = nb * uc;
-        for (int base = tid; base < tot; base += nt * 8) {
-            double v[8];
-#pragma unroll
-            for (int k = 0; k < 8; k++) {
-                const int qq = base + k * nt;
-                v[k] = qq < tot ? Uc[qq] : 0.0;
-            }
-#pragma unroll
-            for (int k = 0; k < 8; k++) {
-                const int qq = base + k * nt;
-                if (qq < tot) {
-                    const int b = qq / uc, a = qq - b * uc;
-                    if (a >= b) P[srel[b] * ld + srel[a]] += v[k];
-                }
-            }
-        }
+        // maps into the panel
+        batched<24>(nb * uc, tid, nt, [&](int qq) { return Uc[qq]; },
+                    [&](int qq, double v) {
+                        const int b = qq / uc, a = qq - b * uc;
+                        if (a >= b) P[srel[b] * ld + srel[a]] += v;
+                    });
         __syncthreads();
     }
 
@@ -319,29 +337,115 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __rest
         __syncthreads();
         const int64_t base = (int64_t)nb * uc;
         const int tot = (uc - nb) * uc;
-        for (int b0 = tid; b0 < tot; b0 += nt * 8) {
-            double v[8], cur[8];
-            int64_t dst[8];
+        constexpr int UNR = 16;
+        for (int b0 = tid; b0 < tot; b0 += nt * UNR) {
+            double v[UNR], cur[UNR];
+            int dst[UNR];
 #pragma unroll
-            for (int k = 0; k < 8; k++) {
+            for (int k = 0; k < UNR; k++) {
                 const int qq = b0 + k * nt;
                 dst[k] = -1;
                 v[k] = 0.0;
                 cur[k] = 0.0;
                 if (qq < tot) {
-                    const int b = nb + qq / uc, a = qq - (qq / uc) * uc;
+                    const int bq = qq / uc;
+                    const int b = nb + bq, a = qq - bq * uc;
                     if (a >= b) {
-                        dst[k] = (int64_t)srel[b] * u + srel[a];
+                        dst[k] = srel[b] * u + srel[a];
                         v[k] = Uc[base + qq];
                         cur[k] = Us[dst[k]];
                     }
                 }
             }
 #pragma unroll
-            for (int k = 0; k < 8; k++)
+            for (int k = 0; k < UNR; k++)
                 if (dst[k] >= 0) Us[dst[k]] = cur[k] + v[k];
         }
         __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __restrict__ insts,
+                                                          const WorkItem* __restrict__ items) {
+    extern __shared__ __align__(16) double P[];
+    __shared__ double invd[16];
+    const WorkItem it = items[blockIdx.x];
+    factor_front(insts[it.inst], it.id, P, invd);
+}
+
+// ---------------------------------------------------------------------------
+// dependency-driven (persistent) scheduling
+// ---------------------------------------------------------------------------
+// Workgroups take tickets in a topological order of the fronts (children
+// before parents), wait until the children have published, process the
+// front, release their writes at agent scope and count themselves done in
+// the parent. A workgroup holding ticket t only waits for fronts with smaller
+// tickets, which are held by running workgroups, so the queue always drains.
+// Every wait is bounded: past the limit it latches an error and proceeds.
+//
+// All control flow of the persistent loops is wave-uniform. The scheduling
+// steps run on wave 0 with every lane active (the test is on an SGPR), and
+// only lane 0 adds to a counter, through the value it adds rather than a
+// branch. A lane-divergent test such as threadIdx.x == 0 at both ends of the
+// loop lets the optimizer thread the back-edge past the barriers; the loop
+// then exits lane by lane and the other lanes of wave 0 re-run the body with
+// the previous ticket.
+constexpr long kSpinLimit = 1L << 22;
+
+__device__ inline bool sched_wave() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0; }
+__device__ inline int lane0() { return (threadIdx.x & 63) == 0 ? 1 : 0; }
+
+// called by a whole wave; the counter is read into a scalar register
+__device__ inline void wait_at_least(const int* p, int v, int* err) {
+    for (long spins = 0;; ++spins) {
+        const int cur = __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (cur >= v) break;
+        if (spins > kSpinLimit) {
+            atomicMax(err, 1);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// called by a whole wave; adds exactly one
+__device__ inline void publish_add(int* p) {
+    __hip_atomic_fetch_add(p, lane0(), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The ticket is broadcast through LDS and then moved to a scalar register,
+// so everything derived from it (front index, sizes, loop bounds) is
+// wave-uniform and every barrier below sits in uniform control flow.
+__device__ inline int take_ticket(int* ticket, int* slot) {
+    if (sched_wave()) {
+        // lane 0 adds one; its return value is the ticket whatever the lane order
+        const int old = atomicAdd(ticket, lane0());
+        *slot = __builtin_amdgcn_readfirstlane(old);
+    }
+    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(*slot);
+    __syncthreads();
+    return t;
+}
+
+__global__ __launch_bounds__(kFactorThreads) void k_factor_queue(const InstDev* __restrict__ insts,
+                                                                const WorkItem* __restrict__ items, DepLists D) {
+    extern __shared__ __align__(16) double P[];
+    __shared__ double invd[16];
+    __shared__ int slot;
+    for (;;) {
+        const int t = take_ticket(D.ticket, &slot);
+        if (t >= D.nitems) break;
+        const int need = __builtin_amdgcn_readfirstlane(D.nchild[t]);
+        const int par = __builtin_amdgcn_readfirstlane(D.parent[t]);
+        if (sched_wave()) wait_at_least(D.cnt + t, need, D.err);
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const WorkItem it = items[t];
+        factor_front(insts[it.inst], it.id, P, invd);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (sched_wave() && par >= 0) publish_add(D.cnt + par);
     }
 }
 
@@ -353,14 +457,8 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __rest
 // threads. Reciprocals of the pivots come from the factorisation.
 constexpr int kSolveThreads = 256;
 
-__global__ __launch_bounds__(kSolveThreads) void k_fwd(const InstDev* __restrict__ insts,
-                                                      const WorkItem* __restrict__ items, int skip_done) {
-    extern __shared__ __align__(16) double sh[];
-    const WorkItem it = items[blockIdx.x];
-    const InstDev& I = insts[it.inst];
-    if (skip_done && I.rs->done) return;
+__device__ void fwd_front(const InstDev& I, const int s, double* __restrict__ sh) {
     const PatDev& T = I.P;
-    const int s = it.id;
     const int c = T.sn_ncol[s], r = T.sn_nrow[s], u = r - c, col0 = T.sn_col0[s];
     const int ld = r | 1;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
@@ -388,19 +486,22 @@ __global__ __launch_bounds__(kSolveThreads) void k_fwd(const InstDev* __restrict
         __syncthreads();
     }
     if (tid < 64) {
-        // L11 y = w; lane holds entries lane and lane + 64 (c <= 128)
+        // L11 y = w; lane holds entries lane and lane + 64 (c <= 128) and
+        // their pivot reciprocals; lane j finishes y_j before it is broadcast
         double w0 = lane < c ? w[lane] : 0.0;
         double w1 = lane + 64 < c ? w[lane + 64] : 0.0;
+        const double d0 = lane < c ? dv[lane] : 0.0;
+        const double d1 = lane + 64 < c ? dv[lane + 64] : 0.0;
+#pragma unroll 4
         for (int j = 0; j < c; j++) {
-            const double wj = j < 64 ? readlane_d(w0, j) : readlane_d(w1, j - 64);
-            const double yj = wj * dv[j];
+            if (lane == (j & 63)) {
+                if (j < 64) w0 *= d0;
+                else w1 *= d1;
+            }
+            const double yj = j < 64 ? readlane_d(w0, j) : readlane_d(w1, j - 64);
             const double* col = P + j * ld;
             if (lane > j && lane < c) w0 -= col[lane] * yj;
             if (lane + 64 > j && lane + 64 < c) w1 -= col[lane + 64] * yj;
-            if (lane == (j & 63)) {
-                if (j < 64) w0 = yj;
-                else w1 = yj;
-            }
         }
         if (lane < c) w[lane] = w0;
         if (lane + 64 < c) w[lane + 64] = w1;
@@ -410,20 +511,15 @@ __global__ __launch_bounds__(kSolveThreads) void k_fwd(const InstDev* __restrict
     for (int i = tid; i < u; i += nt) {
         double sum = va[i];
         const double* row = P + c + i;
+#pragma unroll 8
         for (int k = 0; k < c; k++) sum -= row[k * ld] * w[k];
         Vs[i] = sum;
     }
     for (int t = tid; t < c; t += nt) I.y[col0 + t] = w[t];
 }
 
-__global__ __launch_bounds__(kSolveThreads) void k_bwd(const InstDev* __restrict__ insts,
-                                                      const WorkItem* __restrict__ items, int skip_done) {
-    extern __shared__ __align__(16) double sh[];
-    const WorkItem it = items[blockIdx.x];
-    const InstDev& I = insts[it.inst];
-    if (skip_done && I.rs->done) return;
+__device__ void bwd_front(const InstDev& I, const int s, double* __restrict__ sh) {
     const PatDev& T = I.P;
-    const int s = it.id;
     const int c = T.sn_ncol[s], r = T.sn_nrow[s], u = r - c, col0 = T.sn_col0[s];
     const int ld = r | 1;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
@@ -439,26 +535,88 @@ __global__ __launch_bounds__(kSolveThreads) void k_bwd(const InstDev* __restrict
     for (int k = tid; k < c; k += nt) {
         double sum = I.y[col0 + k];
         const double* col = P + k * ld + c;
+#pragma unroll 8
         for (int i = 0; i < u; i++) sum -= col[i] * zu[i];
         t[k] = sum;
     }
     __syncthreads();
     if (tid < 64) {
-        // L11^T x = t; lane holds entries lane and lane + 64 (c <= 128)
+        // L11^T x = t; lane holds entries lane and lane + 64 (c <= 128) and
+        // their pivot reciprocals; lane j finishes x_j before it is broadcast
         double t0 = lane < c ? t[lane] : 0.0;
         double t1 = lane + 64 < c ? t[lane + 64] : 0.0;
+        const double d0 = lane < c ? dv[lane] : 0.0;
+        const double d1 = lane + 64 < c ? dv[lane + 64] : 0.0;
+#pragma unroll 4
         for (int j = c - 1; j >= 0; j--) {
-            const double tj = j < 64 ? readlane_d(t0, j) : readlane_d(t1, j - 64);
-            const double xj = tj * dv[j];
+            if (lane == (j & 63)) {
+                if (j < 64) t0 *= d0;
+                else t1 *= d1;
+            }
+            const double xj = j < 64 ? readlane_d(t0, j) : readlane_d(t1, j - 64);
             if (lane < j) t0 -= P[lane * ld + j] * xj;
             if (lane + 64 < j) t1 -= P[(lane + 64) * ld + j] * xj;
-            if (lane == (j & 63)) {
-                if (j < 64) t0 = xj;
-                else t1 = xj;
-            }
         }
         if (lane < c) I.y[col0 + lane] = t0;
         if (lane + 64 < c) I.y[col0 + lane + 64] = t1;
+    }
+}
+
+__global__ __launch_bounds__(kSolveThreads) void k_fwd(const InstDev* __restrict__ insts,
+                                                      const WorkItem* __restrict__ items, int skip_done) {
+    extern __shared__ __align__(16) double sh[];
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    if (skip_done && I.rs->done) return;
+    fwd_front(I, it.id, sh);
+}
+
+__global__ __launch_bounds__(kSolveThreads) void k_bwd(const InstDev* __restrict__ insts,
+                                                      const WorkItem* __restrict__ items, int skip_done) {
+    extern __shared__ __align__(16) double sh[];
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    if (skip_done && I.rs->done) return;
+    bwd_front(I, it.id, sh);
+}
+
+// Both sweeps in one launch: tickets 0..N-1 are the forward sweep in
+// topological order, tickets N..2N-1 the backward sweep in reverse order. A
+// front's backward step waits for its parent's (a root waits for its own
+// forward step, the last of its tree).
+__global__ __launch_bounds__(kSolveThreads) void k_sweeps_queue(const InstDev* __restrict__ insts,
+                                                               const WorkItem* __restrict__ items, DepLists D,
+                                                               int skip_done) {
+    extern __shared__ __align__(16) double sh[];
+    __shared__ int slot;
+    const int N = D.nitems;
+    for (;;) {
+        const int t = take_ticket(D.ticket, &slot);
+        if (t >= 2 * N) break;
+        const bool fwd = t < N;
+        const int k = fwd ? t : 2 * N - 1 - t;
+        const int par = __builtin_amdgcn_readfirstlane(D.parent[k]);
+        if (sched_wave()) {
+            if (fwd) wait_at_least(D.cnt + k, __builtin_amdgcn_readfirstlane(D.nchild[k]), D.err);
+            else if (par >= 0) wait_at_least(D.bdone + par, 1, D.err);
+            else wait_at_least(D.fdone + k, 1, D.err);
+        }
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const WorkItem it = items[k];
+        const InstDev& I = insts[it.inst];
+        const int idle = skip_done ? __builtin_amdgcn_readfirstlane(I.rs->done) : 0;
+        if (!idle) {
+            if (fwd) fwd_front(I, it.id, sh);
+            else bwd_front(I, it.id, sh);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (sched_wave()) {
+            if (!fwd) publish_add(D.bdone + k);
+            else if (par >= 0) publish_add(D.cnt + par);
+            else publish_add(D.fdone + k);
+        }
     }
 }
 
@@ -825,6 +983,10 @@ hipError_t set_kernel_attributes() {
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void*)k_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)k_factor_queue, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)k_sweeps_queue, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)k_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
@@ -836,11 +998,22 @@ void launch_copy_segments(const CopySeg* segs, int nseg, hipStream_t st) {
 void launch_fill_i32(int* p, int v, int64_t n, hipStream_t st) {
     if (n > 0) k_fill_i32<<<blocks_for(n, kBlock), kBlock, 0, st>>>(p, v, n);
 }
+void launch_status_init(int* status, int ninst, hipStream_t st) {
+    if (ninst > 0) k_status_init<<<blocks_for(ninst, kBlock), kBlock, 0, st>>>(status, ninst);
+}
 void launch_assemble(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st) {
     if (nitems > 0) k_assemble<<<nitems, kBlock, 0, st>>>(insts, C, items);
 }
 void launch_factor(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, hipStream_t st) {
     if (nitems > 0) k_factor<<<nitems, kFactorThreads, lds, st>>>(insts, items);
+}
+void launch_factor_queue(const InstDev* insts, const WorkItem* items, const DepLists& D, int grid, size_t lds,
+                         hipStream_t st) {
+    if (D.nitems > 0) k_factor_queue<<<grid, kFactorThreads, lds, st>>>(insts, items, D);
+}
+void launch_sweeps_queue(const InstDev* insts, const WorkItem* items, const DepLists& D, int grid, size_t lds,
+                         int skip_done, hipStream_t st) {
+    if (D.nitems > 0) k_sweeps_queue<<<grid, kSolveThreads, lds, st>>>(insts, items, D, skip_done);
 }
 void launch_fwd(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, int skip_done, hipStream_t st) {
     if (nitems > 0) k_fwd<<<nitems, kSolveThreads, lds, st>>>(insts, items, skip_done);

@@ -25,6 +25,20 @@ struct Calls {
 
 constexpr int kBlock = 256;
 
+// Dependency lists of a persistent (queue-scheduled) launch over the fronts
+// in topological order: parent item (-1 for roots), number of children, and
+// per-item counters reset before every launch.
+struct DepLists {
+    const int* parent;
+    const int* nchild;
+    int* cnt;     // children done (factor / forward sweep)
+    int* fdone;   // root forward step done
+    int* bdone;   // backward step done
+    int* ticket;
+    int* err;     // set when a bounded wait expired
+    int nitems;
+};
+
 // Dynamic LDS a front may use (the kernels also hold a little static LDS;
 // gfx950 gives a workgroup 160 KiB in total).
 constexpr int kMaxDynLds = 158 * 1024;
@@ -40,8 +54,13 @@ struct CopySeg {
 void launch_copy_segments(const CopySeg* segs, int nseg, hipStream_t st);
 
 void launch_fill_i32(int* p, int v, int64_t n, hipStream_t st);
+void launch_status_init(int* status, int ninst, hipStream_t st);
 void launch_assemble(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st);
 void launch_factor(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, hipStream_t st);
+void launch_factor_queue(const InstDev* insts, const WorkItem* items, const DepLists& D, int grid, size_t lds,
+                         hipStream_t st);
+void launch_sweeps_queue(const InstDev* insts, const WorkItem* items, const DepLists& D, int grid, size_t lds,
+                         int skip_done, hipStream_t st);
 void launch_fwd(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, int skip_done, hipStream_t st);
 void launch_bwd(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, int skip_done, hipStream_t st);
 

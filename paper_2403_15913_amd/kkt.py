@@ -23,6 +23,7 @@ KKT_OK = 0
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "PATTERN", 3: "STATE", 4: "NOT_SPD", 5: "NONFINITE",
                 6: "NOT_CONVERGED", 7: "BREAKDOWN", 8: "OOM", 9: "BUDGET", 10: "DEVICE"}
 ORDER_AUTO, ORDER_NATURAL, ORDER_ND = 0, 1, 2
+SCHEDULE_LEVELS, SCHEDULE_QUEUE = 0, 1
 
 
 class KKTError(RuntimeError):
@@ -100,6 +101,7 @@ SIGNATURES = {
     "kkt_matvec": (I32, [P, P, P, P]),
     "kkt_factor_set_timing": (I32, [P, I32]),
     "kkt_factor_read_timing": (I32, [P, P]),
+    "kkt_factor_set_schedule": (I32, [P, I32]),
     "kkt_batch_create": (I32, [I32, P, P]),
     "kkt_batch_destroy": (None, [P]),
     "kkt_batch_offsets": (I32, [P, P, P, P, P]),
@@ -108,6 +110,9 @@ SIGNATURES = {
     "kkt_batch_status": (I32, [P, P, P]),
     "kkt_batch_set_timing": (I32, [P, I32]),
     "kkt_batch_read_timing": (I32, [P, P]),
+    "kkt_batch_set_schedule": (I32, [P, I32]),
+    "kkt_batch_capture": (I32, [P, P, P, P, P, P, P, P, I32]),
+    "kkt_batch_replay": (I32, [P, P, P]),
     "kkt_server_opts_default": (None, [P]),
     "kkt_server_create": (I32, [P, P]),
     "kkt_server_register": (I32, [P, P, P]),
@@ -266,6 +271,10 @@ def kkt_factor_read_timing(h) -> dict:
     return t.as_dict()
 
 
+def kkt_factor_set_schedule(h, schedule: int):
+    _err(lib().kkt_factor_set_schedule(h, int(schedule)))
+
+
 # ---------------------------------------------------------------------------
 # handle wrappers
 # ---------------------------------------------------------------------------
@@ -332,6 +341,9 @@ class Factor:
     def read_timing(self) -> dict:
         return kkt_factor_read_timing(self.h)
 
+    def set_schedule(self, schedule: int):
+        kkt_factor_set_schedule(self.h, schedule)
+
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
             kkt_factor_destroy(self.h)
@@ -381,6 +393,24 @@ def kkt_batch_status(h, count):
     return st, bad
 
 
+def kkt_batch_set_schedule(h, schedule: int):
+    _err(lib().kkt_batch_set_schedule(h, int(schedule)))
+
+
+def kkt_batch_capture(h, w_vals, j_vals, sigma_x, sigma_s, b, x, max_iter=10, tol=1e-14, rounds=2):
+    ro = RefineOpts(max_iter, tol)
+    _err(lib().kkt_batch_capture(h, _dptr(w_vals), _dptr(j_vals), _dptr(sigma_x), _dptr(sigma_s), _dptr(b),
+                                 _dptr(x), C.byref(ro), int(rounds)))
+
+
+def kkt_batch_replay(h, count, info=True, stream=None):
+    infos = (SolveInfo * count)()
+    st = lib().kkt_batch_replay(h, infos if info else None, _stream(stream))
+    if st not in (KKT_OK, 6):
+        _err(st)
+    return [i.as_dict() for i in infos] if info else None
+
+
 class Batch:
     """Batched refactor + solve of many instances (concatenated device arrays)."""
 
@@ -398,6 +428,17 @@ class Batch:
 
     def status(self):
         return kkt_batch_status(self.h, self.count)
+
+    def set_schedule(self, schedule: int):
+        kkt_batch_set_schedule(self.h, schedule)
+
+    def capture(self, w_vals, j_vals, sigma_x, sigma_s, b, x, max_iter=10, tol=1e-14, rounds=2):
+        """Record refactor + solve as a graph bound to these arrays (kept alive here)."""
+        kkt_batch_capture(self.h, w_vals, j_vals, sigma_x, sigma_s, b, x, max_iter, tol, rounds)
+        self._graph_args = (w_vals, j_vals, sigma_x, sigma_s, b, x)
+
+    def replay(self, info=True, stream=None):
+        return kkt_batch_replay(self.h, self.count, info, stream)
 
     def set_timing(self, enable=True):
         _err(lib().kkt_batch_set_timing(self.h, 1 if enable else 0))
