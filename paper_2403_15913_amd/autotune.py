@@ -1,12 +1,13 @@
-"""Autotuner for the symbolic options that shape the GPU work.
+"""Autotuner for the symbolic options and launch schedule that shape the GPU work.
 
 For a pattern (or a batch of patterns) it measures refactor+solve on the
 device for a set of candidate options -- ordering (natural stage order or
-nested dissection), nested-dissection leaf size, widest supernode -- and
-keeps the fastest candidate whose solves all pass the backward-error gate.
-These options decide the supernode tree the kernels run on: the depth of
-the dependency chain, the front sizes (rows x columns of every LDS panel and
-of the matrix-core tiles), and the total flops.
+nested dissection), nested-dissection leaf size, widest supernode, and for
+batches the launch schedule (one launch per tree level, or the persistent
+work queue) -- and keeps the fastest candidate whose solves all pass the
+backward-error gate. These options decide the supernode tree the kernels run
+on: the depth of the dependency chain, the front sizes (rows x columns of
+every LDS panel and of the matrix-core tiles), and the total flops.
 
 Results are cached in a JSON table keyed by a pattern signature, so a
 pattern is tuned once and later analyses reuse the choice:
@@ -24,6 +25,7 @@ import hashlib
 import json
 import os
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -89,13 +91,14 @@ def _time_plain(pat, vals, opts, reps: int):
     return (time.perf_counter() - t0) / reps, worst, sym.stats()
 
 
-def _time_batch(pats, vals, opts, reps: int):
+def analyze_many(pats, threads: int = 16, **opts):
+    """Symbolic analyses of many patterns on host threads (the C call drops the GIL)."""
+    with ThreadPoolExecutor(max_workers=max(1, min(threads, len(pats)))) as ex:
+        return list(ex.map(lambda p: kkt.Symbolic.from_pattern(p, **opts), pats))
+
+
+def _time_batch(B, cat, b, x, reps: int):
     import torch
-    syms = [kkt.Symbolic.from_pattern(p, **opts) for p in pats]
-    B = kkt.Batch(syms)
-    cat = [_dev(np.concatenate([getattr(v, f) for v in vals])) for f in ("w_vals", "j_vals", "sigma_x", "sigma_s")]
-    b = _dev(np.concatenate([v.b for v in vals]))
-    x = torch.zeros(int(B.ofs["n"][-1]), dtype=torch.float64, device="cuda")
     B.refactor(*cat)
     B.solve(b, x)
     torch.cuda.synchronize()
@@ -105,7 +108,7 @@ def _time_batch(pats, vals, opts, reps: int):
         B.refactor(*cat)
         worst = max(worst, max(i["eta"] for i in B.solve(b, x)))
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / reps, worst, None
+    return (time.perf_counter() - t0) / reps, worst
 
 
 def tune_pattern(pat, vals, reps: int = 3, table_path: str | None = DEFAULT_TABLE, force: bool = False,
@@ -137,17 +140,33 @@ def tune_pattern(pat, vals, reps: int = 3, table_path: str | None = DEFAULT_TABL
     return dict(best)
 
 
-def tune_batch(pats, vals, reps: int = 3, log=None) -> dict:
-    """One option set for a whole batch (measured as a batched refactor + solve)."""
+def batch_candidates(nmax: int):
+    out = [dict(ordering=kkt.ORDER_NATURAL, nd_leaf=0, max_super=96),
+           dict(ordering=kkt.ORDER_NATURAL, nd_leaf=0, max_super=64)]
+    out += [dict(ordering=kkt.ORDER_ND, nd_leaf=leaf, max_super=96) for leaf in (256, 1024) if leaf < nmax]
+    return out
+
+
+def tune_batch(pats, vals, reps: int = 2, log=None, threads: int = 16) -> dict:
+    """One option set and schedule for a whole batch (measured as batched refactor + solve)."""
+    import torch
     nmax = max(p.n for p in pats)
+    cat = [_dev(np.concatenate([getattr(v, f) for v in vals])) for f in ("w_vals", "j_vals", "sigma_x", "sigma_s")]
+    b = _dev(np.concatenate([v.b for v in vals]))
+    x = torch.zeros(sum(p.n for p in pats), dtype=torch.float64, device="cuda")
     tried = []
-    for opts in [dict(ordering=kkt.ORDER_NATURAL, nd_leaf=0, max_super=96),
-                 dict(ordering=kkt.ORDER_NATURAL, nd_leaf=0, max_super=64)] + \
-            [dict(ordering=kkt.ORDER_ND, nd_leaf=leaf, max_super=96) for leaf in (128, 256, 512, 1024) if leaf < nmax]:
-        t, eta, _ = _time_batch(pats, vals, opts, reps)
-        tried.append((t, eta, opts))
-        if log:
-            log(f"{opts}: {1e3 * t:.3f} ms, eta {eta:.1e}")
+    for opts in batch_candidates(nmax):
+        syms = analyze_many(pats, threads, **opts)
+        B = kkt.Batch(syms)
+        for sched in (kkt.SCHEDULE_LEVELS, kkt.SCHEDULE_QUEUE):
+            B.set_schedule(sched)
+            t, eta = _time_batch(B, cat, b, x, reps)
+            tried.append((t, eta, dict(opts, schedule=sched)))
+            if log:
+                log(f"{opts} schedule {sched}: {1e3 * t:.3f} ms, eta {eta:.1e}")
+        B.close()
     ok = [r for r in tried if r[1] <= ETA_GATE]
+    if not ok:
+        raise RuntimeError("no candidate passed the backward-error gate")
     t, eta, best = min(ok, key=lambda r: r[0])
-    return dict(best, ms=1e3 * t)
+    return dict(best=best, ms=1e3 * t, tried=[dict(options=o, ms=round(1e3 * tt, 3)) for tt, _, o in tried])

@@ -364,7 +364,8 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     }
     if ((e = hipMemsetAsync(status, 0, 2 * (size_t)ninst * sizeof(int), st)) != hipSuccess ||
         (e = hipMemsetAsync(rs, 0, (size_t)ninst * sizeof(RefineState), st)) != hipSuccess ||
-        (e = hipMemsetAsync(cg, 0, (size_t)ninst * sizeof(CgState), st)) != hipSuccess)
+        (e = hipMemsetAsync(cg, 0, (size_t)ninst * sizeof(CgState), st)) != hipSuccess ||
+        (e = hipMemsetAsync(dep_ctr, 0, (3 * sn.size() + 2) * sizeof(int), st)) != hipSuccess)
         return hip_fail(e, "state init");
     last_stream = st;
     factored = false;

@@ -230,11 +230,6 @@ int analyze(int n, int m, const int32_t* wp, const int32_t* wi, const int32_t* j
     }
     const int64_t nnzk = Kp[n];
     S.nnzk = nnzk;
-    auto kfind = [&](int i, int j) -> int64_t {  // entry id of (i, j), j <= i
-        auto b = Kj.begin() + Kp[i], e = Kj.begin() + Kp[i + 1];
-        auto it = std::lower_bound(b, e, j);
-        return (it != e && *it == j) ? (int64_t)(it - Kj.begin()) : -1;
-    };
 
     // ---- symmetric graph (no self loops) -------------------------------------
     Graph G;
@@ -587,29 +582,46 @@ int analyze(int n, int m, const int32_t* wp, const int32_t* wi, const int32_t* j
     S.vsize = S.sn_vofs[ns];
 
     // ---- assembly map: contributions of every entry of K's lower triangle -------
+    // K is walked row by row with a dense position map (pos[j] = id of entry
+    // (i, j)), so every lookup is O(1). The J^T d J pairs (a, b) of entry
+    // (i, j) come in ascending J-row order: the rows r holding column i, and
+    // in row r the position a of column j (rows are sorted, so a <= b).
     std::vector<int> kw(nnzk, -1), kd(nnzk, -1);
     std::vector<int64_t> kpp(nnzk + 1, 0);
-    for (int i = 0; i < n; i++) {
-        for (int p = wp[i]; p < wp[i + 1]; p++) kw[kfind(i, wi[p])] = p;
-        kd[kfind(i, i)] = i;
-    }
-    for (int r = 0; r < m; r++)
-        for (int a = jp[r]; a < jp[r + 1]; a++)
-            for (int b = a; b < jp[r + 1]; b++) kpp[kfind(ji[b], ji[a]) + 1]++;
-    for (int64_t e = 0; e < nnzk; e++) kpp[e + 1] += kpp[e];
-    std::vector<int> pa(kpp[nnzk]), pb(kpp[nnzk]);
+    std::vector<int> pa, pb;
     {
-        std::vector<int64_t> fill(kpp.begin(), kpp.end() - 1);
-        for (int r = 0; r < m; r++)
-            for (int a = jp[r]; a < jp[r + 1]; a++)
-                for (int b = a; b < jp[r + 1]; b++) {
-                    int64_t q = fill[kfind(ji[b], ji[a])]++;
-                    pa[q] = a;
-                    pb[q] = b;
+        std::vector<int64_t> pos(n, -1), fill;
+        for (int pass = 0; pass < 2; pass++) {  // 0: count pairs per entry, 1: place them
+            if (pass == 1) {
+                for (int64_t e = 0; e < nnzk; e++) kpp[e + 1] += kpp[e];
+                pa.resize(kpp[nnzk]);
+                pb.resize(kpp[nnzk]);
+                fill.assign(kpp.begin(), kpp.end() - 1);
+            }
+            for (int i = 0; i < n; i++) {
+                for (int64_t e = Kp[i]; e < Kp[i + 1]; e++) pos[Kj[e]] = e;
+                if (pass == 0) {
+                    for (int p = wp[i]; p < wp[i + 1]; p++) kw[pos[wi[p]]] = p;
+                    kd[pos[i]] = i;
                 }
+                for (int q = S.jt_ptr[i]; q < S.jt_ptr[i + 1]; q++) {
+                    const int r = S.jt_row[q], b = S.jt_e[q];
+                    for (int a = jp[r]; a <= b; a++) {
+                        const int64_t e = pos[ji[a]];
+                        if (pass == 0) {
+                            kpp[e + 1]++;
+                        } else {
+                            const int64_t t = fill[e]++;
+                            pa[t] = a;
+                            pb[t] = b;
+                        }
+                    }
+                }
+            }
+        }
     }
     // destination of each entry, then regroup entries by supernode
-    std::vector<int> krow_o(nnzk), kcol_o(nnzk), ksn(nnzk), kloc(nnzk);
+    std::vector<int> krow_o(nnzk), kcol_o(nnzk), ksn(nnzk), kloc(nnzk), kpr(nnzk), kpc(nnzk);
     for (int i = 0; i < n; i++)
         for (int64_t e = Kp[i]; e < Kp[i + 1]; e++) {
             int j = Kj[e];
@@ -623,12 +635,27 @@ int analyze(int n, int m, const int32_t* wp, const int32_t* wi, const int32_t* j
             if (it == rb + S.sn_nrow[s] || *it != pr) { err = "internal: K entry outside the front"; return ST_INVALID; }
             ksn[e] = s;
             kloc[e] = ((pc - S.sn_col0[s]) << 16) | (int)(it - rb);
+            kpr[e] = pr;
+            kpc[e] = pc;
         }
+    // Supernodes are contiguous column ranges in order and front rows are
+    // sorted, so (supernode, kloc) order is (permuted column, permuted row)
+    // order: two stable counting passes, by row and then by column.
     std::vector<int64_t> eord(nnzk);
-    std::iota(eord.begin(), eord.end(), 0);
-    std::sort(eord.begin(), eord.end(), [&](int64_t a, int64_t b) {
-        return ksn[a] != ksn[b] ? ksn[a] < ksn[b] : kloc[a] < kloc[b];
-    });
+    {
+        std::vector<int64_t> cnt(n + 1), tmp(nnzk);
+        auto pass = [&](const std::vector<int>& key, const int64_t* src, int64_t* dst) {
+            std::fill(cnt.begin(), cnt.end(), 0);
+            for (int64_t q = 0; q < nnzk; q++) cnt[key[src ? src[q] : q] + 1]++;
+            for (int t = 0; t < n; t++) cnt[t + 1] += cnt[t];
+            for (int64_t q = 0; q < nnzk; q++) {
+                const int64_t e = src ? src[q] : q;
+                dst[cnt[key[e]]++] = e;
+            }
+        };
+        pass(kpr, nullptr, tmp.data());
+        pass(kpc, tmp.data(), eord.data());
+    }
     std::vector<int64_t> newid(nnzk);
     for (int64_t q = 0; q < nnzk; q++) newid[eord[q]] = q;
     S.k_snptr.assign(ns + 1, 0);
