@@ -43,13 +43,19 @@ def parse():
     ap.add_argument("--nd-leaf", type=int, default=0)
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched workload (0: skip)")
     ap.add_argument("--batch-ordering", type=int, default=0)
+    ap.add_argument("--batch-autotune", type=int, default=1, help="pick batch options and schedule by measurement")
+    ap.add_argument("--graph-rounds", type=int, default=1, help="refinement rounds recorded in the batch graph")
+    ap.add_argument("--schedule", default="levels", choices=["levels", "queue"], help="plain-solver launch schedule")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run one plain device copy of this many MiB (HBM counter calibration) and exit")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests of the served workload (0: skip)")
     ap.add_argument("--serve-rho", type=float, default=0.8, help="arrival rate / plain-solver capacity")
     return ap.parse_args()
 
 
 def bench_batched(args, kkt, kktgen, torch, dev):
-    """Batched NMPC instances: one batched refactor+solve vs one plain factor per instance."""
+    """Batched NMPC instances: graph-replayed and eager batched refactor+solve vs one plain factor per instance."""
+    from paper_2403_15913_amd import autotune
     count = args.batch
     shapes = kktgen.batch_shapes(count)
     pats = [kktgen.nmpc_pattern(*sh) for sh in shapes]
@@ -58,26 +64,49 @@ def bench_batched(args, kkt, kktgen, torch, dev):
     def T(a):
         return torch.tensor(np.asarray(a), dtype=torch.float64, device=dev)
 
-    syms = [kkt.Symbolic.from_pattern(p, ordering=args.batch_ordering) for p in pats]
+    # options and schedule from the autotuner (measured on this batch), or fixed ones
+    t0 = time.perf_counter()
+    if args.batch_autotune:
+        tuned = autotune.tune_batch(pats, vals, reps=2)
+        best = tuned["best"]
+    else:
+        tuned = None
+        best = dict(ordering=args.batch_ordering, nd_leaf=0, max_super=96, schedule=kkt.SCHEDULE_QUEUE)
+    tune_s = time.perf_counter() - t0
+    opts = {k: best[k] for k in ("ordering", "nd_leaf", "max_super")}
+    t0 = time.perf_counter()
+    syms = autotune.analyze_many(pats, **opts)
+    analyze_s = time.perf_counter() - t0
     B = kkt.Batch(syms)
+    B.set_schedule(best["schedule"])
     cat = {f: T(np.concatenate([getattr(v, f) for v in vals])) for f in ("w_vals", "j_vals", "sigma_x", "sigma_s", "b")}
     x = torch.zeros(int(B.ofs["n"][-1]), dtype=torch.float64, device=dev)
+    reps = 5
 
-    def bstep():
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps, out
+
+    def eager():
         B.refactor(cat["w_vals"], cat["j_vals"], cat["sigma_x"], cat["sigma_s"])
         return B.solve(cat["b"], x)
 
-    bstep()
-    reps = 5
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        infos = bstep()
-    torch.cuda.synchronize()
-    tb = (time.perf_counter() - t0) / reps
+    eager_s = {}
+    for name, sched in (("levels", kkt.SCHEDULE_LEVELS), ("queue", kkt.SCHEDULE_QUEUE)):
+        B.set_schedule(sched)
+        eager_s[name], _ = timed(eager)
+    B.set_schedule(best["schedule"])
+    xg = torch.zeros_like(x)
+    B.capture(cat["w_vals"], cat["j_vals"], cat["sigma_x"], cat["sigma_s"], cat["b"], xg, rounds=args.graph_rounds)
+    tg, infos = timed(B.replay)
     etas = np.array([i["eta"] for i in infos])
     ok = int((etas <= ETA_GATE).sum())
-    # plain: one factor per instance, one instance per launch sequence
+    # plain: one factor per instance, one instance per launch sequence (level schedule)
     facs = [kkt.Factor(s) for s in syms]
     dv = [dict(w=T(v.w_vals), j=T(v.j_vals), sx=T(v.sigma_x), ss=T(v.sigma_s), b=T(v.b)) for v in vals]
     xs = [torch.zeros(p.n, dtype=torch.float64, device=dev) for p in pats]
@@ -96,15 +125,20 @@ def bench_batched(args, kkt, kktgen, torch, dev):
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
     pok = int(sum(i["eta"] <= ETA_GATE for i in pinfos))
-    # batched equals plain, bitwise
-    same = all(np.array_equal(x[B.ofs["n"][q]:B.ofs["n"][q + 1]].cpu().numpy(), xs[q].cpu().numpy())
-               for q in range(count))
+    # the graph's solutions equal the plain ones, bitwise
+    n_ofs = B.ofs["n"]
+    xgh = xg.cpu().numpy()
+    same = all(np.array_equal(xgh[n_ofs[q]:n_ofs[q + 1]], xs[q].cpu().numpy()) for q in range(count))
     st = [s.stats() for s in syms]
-    return dict(instances=count, sum_n=int(B.ofs["n"][-1]), sum_nnz_l=int(sum(s["nnz_l"] for s in st)),
-                flops_exact=float(sum(s["flops_exact"] for s in st)), ordering=args.batch_ordering,
-                batched_pairs_per_s=round(ok / tb, 2), batched_ms=round(1e3 * tb, 3),
+    sched_name = {kkt.SCHEDULE_LEVELS: "levels", kkt.SCHEDULE_QUEUE: "queue"}[best["schedule"]]
+    return dict(instances=count, sum_n=int(n_ofs[-1]), sum_nnz_l=int(sum(s["nnz_l"] for s in st)),
+                flops_exact=float(sum(s["flops_exact"] for s in st)), options=opts, schedule=sched_name,
+                autotuned=bool(args.batch_autotune), tune_s=round(tune_s, 2), analyze_s=round(analyze_s, 2),
+                tried=tuned["tried"] if tuned else None, graph_rounds=args.graph_rounds,
+                batched_pairs_per_s=round(ok / tg, 2), batched_ms=round(1e3 * tg, 3),
+                eager_levels_ms=round(1e3 * eager_s["levels"], 3), eager_queue_ms=round(1e3 * eager_s["queue"], 3),
                 plain_pairs_per_s=round(pok / tp, 2), plain_ms=round(1e3 * tp, 3),
-                speedup=round((ok / tb) / max(pok / tp, 1e-12), 2), eta_max=float(etas.max()),
+                speedup=round((ok / tg) / max(pok / tp, 1e-12), 2), eta_max=float(etas.max()),
                 passing=f"{ok}/{count}", batched_equals_plain_bitwise=bool(same))
 
 
@@ -200,6 +234,16 @@ def main():
     from paper_2403_15913_amd import kkt
 
     dev = torch.device("cuda:0")
+    if args.copy_probe_mib > 0:
+        # reads and writes exactly copy_probe_mib MiB each: the scale of FETCH_SIZE / WRITE_SIZE
+        n = args.copy_probe_mib << 17
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_mib": args.copy_probe_mib, "bytes_each_way": 8 * n}), flush=True)
+        return
     kkt.lib()
     gen = {"paper": (1, kktgen.paper_config, kktgen.distillation_values),
            "small": (0, kktgen.small_config, kktgen.nmpc_values)}[args.workload]
@@ -218,6 +262,7 @@ def main():
     analyze_s = time.perf_counter() - t0
     stats = sym.stats()
     fac = kkt.Factor(sym)
+    fac.set_schedule(kkt.SCHEDULE_QUEUE if args.schedule == "queue" else kkt.SCHEDULE_LEVELS)
 
     def step(i):
         d = dvals[i % len(dvals)]
@@ -305,7 +350,8 @@ def main():
         "config": {"workload": ("lifted-kkt plain, distillation-shaped N=2000 (n=142000, m=140000), "
                                 "Sigma~logU[1e-8,1e8], 10 value sets") if args.workload == "paper"
                    else "lifted-kkt plain, NMPC N=50 nx=8 nu=1 (n=450, m=400)",
-                   "mode": "plain", "ordering": args.ordering, "nd_leaf": args.nd_leaf},
+                   "mode": "plain", "ordering": args.ordering, "nd_leaf": args.nd_leaf,
+                   "schedule": args.schedule},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail": {

@@ -129,17 +129,25 @@ __device__ inline d4 tile_abt(const double* P, int ld, int i0, int j0, int k0, i
 
 // Copy n doubles (n even, both 16-byte aligned) with 16 independent 16-byte
 // loads in flight per thread.
+// Empty asm that takes a value in a vector register: emits nothing, but
+// keeps the optimizer from sinking a batch of loads into the predicated
+// blocks that consume them (which would serialise the loads).
+__device__ inline void pin(double& x) { asm volatile("" : "+v"(x)); }
+__device__ inline void pin(double2& x) { asm volatile("" : "+v"(x.x), "+v"(x.y)); }
+__device__ inline void pin(int& x) { asm volatile("" : "+v"(x)); }
+
 __device__ inline void copy_vec(double* __restrict__ dst, const double* __restrict__ src, int n, int tid, int nt) {
     const double2* s2 = (const double2*)src;
     double2* d2 = (double2*)dst;
     const int n2 = n >> 1;
+    // loads use a clamped (always valid) index so all 16 are issued
+    // unconditionally and stay in registers; only the stores are predicated
     for (int base = tid; base < n2; base += nt * 16) {
         double2 v[16];
 #pragma unroll
-        for (int k = 0; k < 16; k++) {
-            const int q = base + k * nt;
-            if (q < n2) v[k] = s2[q];
-        }
+        for (int k = 0; k < 16; k++) v[k] = s2[min(base + k * nt, n2 - 1)];
+#pragma unroll
+        for (int k = 0; k < 16; k++) pin(v[k]);
 #pragma unroll
         for (int k = 0; k < 16; k++) {
             const int q = base + k * nt;
@@ -157,11 +165,11 @@ template <int UNR, class LoadF, class UseF>
 __device__ inline void batched(int tot, int tid, int nt, LoadF load, UseF use) {
     for (int base = tid; base < tot; base += nt * UNR) {
         double v[UNR];
+        // clamped indices: every load is valid, so none is predicated
 #pragma unroll
-        for (int k = 0; k < UNR; k++) {
-            const int q = base + k * nt;
-            v[k] = q < tot ? load(q) : 0.0;
-        }
+        for (int k = 0; k < UNR; k++) v[k] = load(min(base + k * nt, tot - 1));
+#pragma unroll
+        for (int k = 0; k < UNR; k++) pin(v[k]);
 #pragma unroll
         for (int k = 0; k < UNR; k++) {
             const int q = base + k * nt;
@@ -338,28 +346,32 @@ __device__ void factor_front(const InstDev& I, const int s, double* __restrict__
         const int64_t base = (int64_t)nb * uc;
         const int tot = (uc - nb) * uc;
         constexpr int UNR = 16;
+        // Every index is clamped into [0, tot) and every (a, b) maps inside
+        // U_s (upper-part entries too), so all loads are unpredicated; only
+        // the stores of lower-part entries a >= b within range happen.
         for (int b0 = tid; b0 < tot; b0 += nt * UNR) {
             double v[UNR], cur[UNR];
             int dst[UNR];
+            bool keep[UNR];
 #pragma unroll
             for (int k = 0; k < UNR; k++) {
-                const int qq = b0 + k * nt;
-                dst[k] = -1;
-                v[k] = 0.0;
-                cur[k] = 0.0;
-                if (qq < tot) {
-                    const int bq = qq / uc;
-                    const int b = nb + bq, a = qq - bq * uc;
-                    if (a >= b) {
-                        dst[k] = srel[b] * u + srel[a];
-                        v[k] = Uc[base + qq];
-                        cur[k] = Us[dst[k]];
-                    }
-                }
+                const int q0 = b0 + k * nt;
+                const int qq = min(q0, tot - 1);
+                const int bq = qq / uc;
+                const int b = nb + bq, a = qq - bq * uc;
+                keep[k] = q0 < tot && a >= b;
+                dst[k] = srel[b] * u + srel[a];
+                v[k] = Uc[base + qq];
+                cur[k] = Us[dst[k]];
+            }
+#pragma unroll
+            for (int k = 0; k < UNR; k++) {
+                pin(v[k]);
+                pin(cur[k]);
             }
 #pragma unroll
             for (int k = 0; k < UNR; k++)
-                if (dst[k] >= 0) Us[dst[k]] = cur[k] + v[k];
+                if (keep[k]) Us[dst[k]] = cur[k] + v[k];
         }
         __syncthreads();
     }
