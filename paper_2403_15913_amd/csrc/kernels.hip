@@ -197,9 +197,22 @@ __device__ inline void tri_tile(int t, int tj0, int nb, int& ti, int& tj) {
 // and the children's pass-through entries are added to it.
 constexpr int kFactorThreads = 512;
 
-__device__ void factor_front(const InstDev& I, const int s, double* __restrict__ P, double* invd) {
+__device__ __forceinline__ void factor_front(const InstDev& I, const int s, double* __restrict__ P, double* invd) {
     const PatDev& T = I.P;
-    const int c = T.sn_ncol[s], r = T.sn_nrow[s], u = r - c, col0 = T.sn_col0[s];
+    const int c = __builtin_amdgcn_readfirstlane(T.sn_ncol[s]), r = __builtin_amdgcn_readfirstlane(T.sn_nrow[s]);
+    const int u = r - c, col0 = __builtin_amdgcn_readfirstlane(T.sn_col0[s]);
+    // descriptor fields used inside the loops below, read once
+    int* const status = I.status;
+    double* const dinv = I.dinv + col0;
+    const double* const Ubase = I.U;
+    const int* const chl = T.ch_list;
+    const int* const sn_ncol = T.sn_ncol;
+    const int* const sn_nrow = T.sn_nrow;
+    const int* const rel_np = T.rel_np;
+    const int64_t* const sn_uofs = T.sn_uofs;
+    const int* const rel = T.rel;
+    const int64_t* const sn_rowofs = T.sn_rowofs;
+    const int ch0 = __builtin_amdgcn_readfirstlane(T.ch_ptr[s]), ch1 = __builtin_amdgcn_readfirstlane(T.ch_ptr[s + 1]);
     const int rp = rup16(r), cp = rup16(c);
     const int ld = r | 1;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -219,11 +232,12 @@ __device__ void factor_front(const InstDev& I, const int s, double* __restrict__
     }
     __syncthreads();
     int* srel = (int*)(P + ld * cp);  // relative indices of the child being added
-    for (int q = T.ch_ptr[s]; q < T.ch_ptr[s + 1]; q++) {
-        const int ch = T.ch_list[q];
-        const int cc = T.sn_ncol[ch], uc = T.sn_nrow[ch] - cc, nb = T.rel_np[ch];
-        const double* __restrict__ Uc = I.U + T.sn_uofs[ch];
-        const int* __restrict__ rl = T.rel + T.sn_rowofs[ch] + cc;
+    for (int q = ch0; q < ch1; q++) {
+        const int ch = __builtin_amdgcn_readfirstlane(chl[q]);
+        const int cc = __builtin_amdgcn_readfirstlane(sn_ncol[ch]);
+        const int uc = __builtin_amdgcn_readfirstlane(sn_nrow[ch]) - cc, nb = __builtin_amdgcn_readfirstlane(rel_np[ch]);
+        const double* __restrict__ Uc = Ubase + sn_uofs[ch];
+        const int* __restrict__ rl = rel + sn_rowofs[ch] + cc;
         for (int a = tid; a < uc; a += nt) srel[a] = rl[a];
         __syncthreads();
         // entries (a, b), a >= b, of the child's update matrix whose column b
@@ -251,8 +265,8 @@ __device__ void factor_front(const InstDev& I, const int s, double* __restrict__
                     double d = readlane_d(a[j], j);
                     if (!(d > 0.0) || !isfinite(d)) {
                         if (lane == 0) {
-                            atomicMin(&I.status[1], col0 + j0 + j);
-                            atomicMax(&I.status[0], KKT_ST_NOT_SPD);
+                            atomicMin(&status[1], col0 + j0 + j);
+                            atomicMax(&status[0], KKT_ST_NOT_SPD);
                         }
                         d = 1.0;
                     }
@@ -260,10 +274,7 @@ __device__ void factor_front(const InstDev& I, const int s, double* __restrict__
                     const double inv = 1.0 / ljj;
                     if (i == j) a[j] = ljj;
                     else if (i > j) a[j] *= inv;
-                    if (lane == 0) {
-                        invd[j] = inv;
-                        I.dinv[col0 + j0 + j] = inv;
-                    }
+                    if (lane == 0) invd[j] = inv;
 #pragma unroll
                     for (int k = j + 1; k < 16; k++) {
                         const double lkj = readlane_d(a[j], k);
@@ -278,6 +289,7 @@ __device__ void factor_front(const InstDev& I, const int s, double* __restrict__
             }
         }
         __syncthreads();
+        if (tid < w) dinv[j0 + tid] = invd[tid];
         // rows below the diagonal block: x = p L_kk^{-T}
         for (int i = j0 + 16 + tid; i < r; i += nt) {
             double x[16];
@@ -336,11 +348,12 @@ __device__ void factor_front(const InstDev& I, const int s, double* __restrict__
     }
     __syncthreads();
     // children's entries that pass through to the update matrix
-    for (int q = T.ch_ptr[s]; q < T.ch_ptr[s + 1]; q++) {
-        const int ch = T.ch_list[q];
-        const int cc = T.sn_ncol[ch], uc = T.sn_nrow[ch] - cc, nb = T.rel_np[ch];
-        const double* __restrict__ Uc = I.U + T.sn_uofs[ch];
-        const int* __restrict__ rl = T.rel + T.sn_rowofs[ch] + cc;
+    for (int q = ch0; q < ch1; q++) {
+        const int ch = __builtin_amdgcn_readfirstlane(chl[q]);
+        const int cc = __builtin_amdgcn_readfirstlane(sn_ncol[ch]);
+        const int uc = __builtin_amdgcn_readfirstlane(sn_nrow[ch]) - cc, nb = __builtin_amdgcn_readfirstlane(rel_np[ch]);
+        const double* __restrict__ Uc = Ubase + sn_uofs[ch];
+        const int* __restrict__ rl = rel + sn_rowofs[ch] + cc;
         for (int a = tid; a < uc; a += nt) srel[a] = rl[a] - c;
         __syncthreads();
         const int64_t base = (int64_t)nb * uc;
@@ -462,6 +475,112 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor_queue(const InstDev* 
 }
 
 // ---------------------------------------------------------------------------
+// triangular solves with the c x c diagonal triangle of a staged panel, by
+// one wave (c <= 128): lane l carries rows l and l + 64 in x0 and x1, dv
+// holds the pivot reciprocals. Blocks of 16 columns: the block's own
+// triangle is read into registers first, so its 16 dependent steps are
+// register FMAs with scalar broadcasts; the rows outside the block then
+// take the block's contribution with all their LDS loads issued together.
+// Each row's terms are subtracted in the same order as plain substitution.
+// ---------------------------------------------------------------------------
+// L11 y = w (forward)
+__device__ inline void tri_fwd_wave(const double* __restrict__ P, int ld, int c, const double* __restrict__ dv,
+                                    double& x0, double& x1, int lane) {
+    for (int j0 = 0; j0 < c; j0 += 16) {
+        const int nb = min(16, c - j0);
+        const bool hi = j0 >= 64;
+        const int rb = lane - (j0 & 63);
+        const bool inblk = rb >= 0 && rb < nb;
+        const int rbc = min(max(rb, 0), nb - 1);
+        double Lr[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++) Lr[k] = P[min(j0 + k, c - 1) * ld + j0 + rbc];
+#pragma unroll
+        for (int k = 0; k < 16; k++) Lr[k] = (inblk && k < rb) ? Lr[k] : 0.0;
+        const double d = dv[j0 + rbc];
+        double wb = hi ? x1 : x0;
+        double y[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            y[k] = k < nb ? readlane_d(wb * d, (j0 & 63) + k) : 0.0;
+            wb = fma(-Lr[k], y[k], wb);
+        }
+        if (inblk) {
+            if (hi) x1 = wb * d;
+            else x0 = wb * d;
+        }
+        const int e = j0 + nb;  // rows e .. c-1 lie below the block
+        if (e < c) {
+            const int i0 = min(lane, c - 1), i1 = min(lane + 64, c - 1);
+            double a0[16], a1[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                const double* col = P + min(j0 + k, c - 1) * ld;
+                a0[k] = col[i0];
+                a1[k] = col[i1];
+            }
+            double s0 = x0, s1 = x1;
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                s0 = fma(-a0[k], y[k], s0);
+                s1 = fma(-a1[k], y[k], s1);
+            }
+            if (lane >= e && lane < c) x0 = s0;
+            if (lane + 64 >= e && lane + 64 < c) x1 = s1;
+        }
+    }
+}
+
+// L11^T x = t (backward), blocks from the last one down
+__device__ inline void tri_bwd_wave(const double* __restrict__ P, int ld, int c, const double* __restrict__ dv,
+                                    double& x0, double& x1, int lane) {
+    for (int j0 = (c - 1) & ~15; j0 >= 0; j0 -= 16) {
+        const int nb = min(16, c - j0);
+        const bool hi = j0 >= 64;
+        const int rb = lane - (j0 & 63);
+        const bool inblk = rb >= 0 && rb < nb;
+        const int rbc = min(max(rb, 0), nb - 1);
+        // Lc[k] = L[j0 + k][j0 + rb] for k > rb (row k of the block, this lane's column)
+        double Lc[16];
+        const double* colr = P + (j0 + rbc) * ld + j0;
+#pragma unroll
+        for (int k = 0; k < 16; k++) Lc[k] = colr[min(k, nb - 1)];
+#pragma unroll
+        for (int k = 0; k < 16; k++) Lc[k] = (inblk && k > rb && k < nb) ? Lc[k] : 0.0;
+        const double d = dv[j0 + rbc];
+        double tb = hi ? x1 : x0;
+        double x[16];
+#pragma unroll
+        for (int k = 15; k >= 0; k--) {
+            x[k] = k < nb ? readlane_d(tb * d, (j0 & 63) + k) : 0.0;
+            tb = fma(-Lc[k], x[k], tb);
+        }
+        if (inblk) {
+            if (hi) x1 = tb * d;
+            else x0 = tb * d;
+        }
+        if (j0 > 0) {  // rows 0 .. j0-1 lie above the block
+            const int i0 = min(lane, j0 - 1), i1 = min(lane + 64, j0 - 1);
+            double a0[16], a1[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                const int kr = j0 + min(k, nb - 1);
+                a0[k] = P[i0 * ld + kr];
+                a1[k] = P[i1 * ld + kr];
+            }
+            double s0 = x0, s1 = x1;
+#pragma unroll
+            for (int k = 15; k >= 0; k--) {
+                s0 = fma(-a0[k], x[k], s0);
+                s1 = fma(-a1[k], x[k], s1);
+            }
+            if (lane < j0) x0 = s0;
+            if (lane + 64 < j0) x1 = s1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // triangular sweeps (y holds the permuted right-hand side, then the solution)
 // ---------------------------------------------------------------------------
 // The panel is staged in LDS (odd leading dimension); the c x c triangle is
@@ -469,9 +588,10 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor_queue(const InstDev* 
 // threads. Reciprocals of the pivots come from the factorisation.
 constexpr int kSolveThreads = 256;
 
-__device__ void fwd_front(const InstDev& I, const int s, double* __restrict__ sh) {
+__device__ __forceinline__ void fwd_front(const InstDev& I, const int s, double* __restrict__ sh) {
     const PatDev& T = I.P;
-    const int c = T.sn_ncol[s], r = T.sn_nrow[s], u = r - c, col0 = T.sn_col0[s];
+    const int c = __builtin_amdgcn_readfirstlane(T.sn_ncol[s]), r = __builtin_amdgcn_readfirstlane(T.sn_nrow[s]);
+    const int u = r - c, col0 = __builtin_amdgcn_readfirstlane(T.sn_col0[s]);
     const int ld = r | 1;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
     double* P = sh;
@@ -498,25 +618,11 @@ __device__ void fwd_front(const InstDev& I, const int s, double* __restrict__ sh
         __syncthreads();
     }
     if (tid < 64) {
-        // L11 y = w; lane holds entries lane and lane + 64 (c <= 128) and
-        // their pivot reciprocals; lane j finishes y_j before it is broadcast
-        double w0 = lane < c ? w[lane] : 0.0;
-        double w1 = lane + 64 < c ? w[lane + 64] : 0.0;
-        const double d0 = lane < c ? dv[lane] : 0.0;
-        const double d1 = lane + 64 < c ? dv[lane + 64] : 0.0;
-#pragma unroll 4
-        for (int j = 0; j < c; j++) {
-            if (lane == (j & 63)) {
-                if (j < 64) w0 *= d0;
-                else w1 *= d1;
-            }
-            const double yj = j < 64 ? readlane_d(w0, j) : readlane_d(w1, j - 64);
-            const double* col = P + j * ld;
-            if (lane > j && lane < c) w0 -= col[lane] * yj;
-            if (lane + 64 > j && lane + 64 < c) w1 -= col[lane + 64] * yj;
-        }
-        if (lane < c) w[lane] = w0;
-        if (lane + 64 < c) w[lane + 64] = w1;
+        double x0 = lane < c ? w[lane] : 0.0;
+        double x1 = lane + 64 < c ? w[lane + 64] : 0.0;
+        tri_fwd_wave(P, ld, c, dv, x0, x1, lane);
+        if (lane < c) w[lane] = x0;
+        if (lane + 64 < c) w[lane + 64] = x1;
     }
     __syncthreads();
     double* __restrict__ Vs = I.V + T.sn_vofs[s];
@@ -530,9 +636,10 @@ __device__ void fwd_front(const InstDev& I, const int s, double* __restrict__ sh
     for (int t = tid; t < c; t += nt) I.y[col0 + t] = w[t];
 }
 
-__device__ void bwd_front(const InstDev& I, const int s, double* __restrict__ sh) {
+__device__ __forceinline__ void bwd_front(const InstDev& I, const int s, double* __restrict__ sh) {
     const PatDev& T = I.P;
-    const int c = T.sn_ncol[s], r = T.sn_nrow[s], u = r - c, col0 = T.sn_col0[s];
+    const int c = __builtin_amdgcn_readfirstlane(T.sn_ncol[s]), r = __builtin_amdgcn_readfirstlane(T.sn_nrow[s]);
+    const int u = r - c, col0 = __builtin_amdgcn_readfirstlane(T.sn_col0[s]);
     const int ld = r | 1;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
     double* P = sh;
@@ -553,24 +660,11 @@ __device__ void bwd_front(const InstDev& I, const int s, double* __restrict__ sh
     }
     __syncthreads();
     if (tid < 64) {
-        // L11^T x = t; lane holds entries lane and lane + 64 (c <= 128) and
-        // their pivot reciprocals; lane j finishes x_j before it is broadcast
-        double t0 = lane < c ? t[lane] : 0.0;
-        double t1 = lane + 64 < c ? t[lane + 64] : 0.0;
-        const double d0 = lane < c ? dv[lane] : 0.0;
-        const double d1 = lane + 64 < c ? dv[lane + 64] : 0.0;
-#pragma unroll 4
-        for (int j = c - 1; j >= 0; j--) {
-            if (lane == (j & 63)) {
-                if (j < 64) t0 *= d0;
-                else t1 *= d1;
-            }
-            const double xj = j < 64 ? readlane_d(t0, j) : readlane_d(t1, j - 64);
-            if (lane < j) t0 -= P[lane * ld + j] * xj;
-            if (lane + 64 < j) t1 -= P[(lane + 64) * ld + j] * xj;
-        }
-        if (lane < c) I.y[col0 + lane] = t0;
-        if (lane + 64 < c) I.y[col0 + lane + 64] = t1;
+        double x0 = lane < c ? t[lane] : 0.0;
+        double x1 = lane + 64 < c ? t[lane + 64] : 0.0;
+        tri_bwd_wave(P, ld, c, dv, x0, x1, lane);
+        if (lane < c) I.y[col0 + lane] = x0;
+        if (lane + 64 < c) I.y[col0 + lane + 64] = x1;
     }
 }
 
