@@ -15,6 +15,7 @@ region) and the FP64 oracle timed on the host cores as ``cpu_baseline``.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -208,6 +209,35 @@ def bench_served(args, kkt, kktgen, torch, dev):
                 continuous_batching=pick(cst), plain_fifo=pick(pst), failed=int(cbad), plain_failed=int(pbad))
 
 
+# kernels launched under each timed phase
+PHASE_KERNELS = {"factor": "k_factor+k_update", "fwd": "k_fwd", "bwd": "k_bwd", "assemble": "k_assemble",
+                 "residual": "k_residual"}
+
+
+def measured_traffic(phase, args):
+    """HBM bytes per launch of a phase from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes scaled by a plain copy's reading), or
+    None when the kernels changed since the counters were taken or another
+    configuration is benchmarked."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    src = os.path.join(ROOT, "paper_2403_15913_amd", "csrc", "kernels.hip")
+    if args.workload != "paper" or args.schedule != "levels" or args.ordering or args.nd_leaf:
+        return None
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+        with open(src, "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("kernels_sha256") != sha:
+        return None
+    if phase in rec.get("phases", {}):
+        return round(rec["phases"][phase]["bytes_per_launch"])
+    k = rec.get("per_launch", {}).get(PHASE_KERNELS.get(phase, ""))
+    return round(k["fetch_bytes"] + k["write_bytes"]) if k else None
+
+
 def algorithmic_work(stats, pat, n_steps, sweeps_per_step, residuals_per_step, nnz_k_full):
     """Minimal bytes / flops of each phase over the timed steps."""
     n, m = pat.n, pat.m
@@ -309,9 +339,10 @@ def main():
         achieved, peak = wd["work"] / secs / 1e12, PEAK_FP64_TFLOPS
     else:
         achieved, peak = wd["work"] / secs / 1e9, PEAK_HBM_GBS
+    kernel = PHASE_KERNELS.get(dom, f"k_{dom}")
     roofline = dict(bound=wd["bound"], achieved=round(achieved, 4), peak=peak, unit=wd["unit"],
-                    frac=round(achieved / peak, 5), traffic=None, kernel=f"k_{dom}",
-                    launches_per_step=tm[dom]["launches"] / args.steps,
+                    frac=round(achieved / peak, 5), traffic=measured_traffic(dom, args), traffic_unit="bytes/launch",
+                    kernel=kernel, launches_per_step=tm[dom]["launches"] / args.steps,
                     avg_launch_us=1e3 * tm[dom]["ms"] / max(1, tm[dom]["launches"]))
 
     cpu = None

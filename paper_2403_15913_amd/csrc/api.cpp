@@ -160,6 +160,8 @@ hipError_t DevPattern::build(const Symbolic& S) {
 // ---------------------------------------------------------------------------
 Engine::~Engine() {
     drop_graph();
+    if (ctl_event) (void)hipEventDestroy(ctl_event);
+    if (ctl_event2) (void)hipEventDestroy(ctl_event2);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (hpin) (void)hipHostFree(hpin);
 }
@@ -203,7 +205,8 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     std::vector<int64_t> lo(ninst + 1, 0), uo(ninst + 1, 0), vo(ninst + 1, 0), ko(ninst + 1, 0), ro(ninst + 1, 0);
     lds_factor = lds_solve = 0;
     int nlev = 0;
-    size_t nsn = 0, nnb = 0, nmb = 0, nkb = 0;
+    size_t nsn = 0, nnb = 0, nmb = 0, nkb = 0, nup = 0;
+    int max_rows = 0;
     for (int q = 0; q < ninst; q++) {
         const Symbolic& S = *s[q];
         n_ofs[q + 1] = n_ofs[q] + S.n;
@@ -218,6 +221,8 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         for (int k = 0; k < S.ns; k++) {
             lds_factor = std::max(lds_factor, (size_t)factor_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]));
             lds_solve = std::max(lds_solve, (size_t)solve_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]));
+            max_rows = std::max(max_rows, S.sn_nrow[k]);
+            nup += (size_t)(S.sn_nrow[k] - S.sn_ncol[k] + 15) / 16;
         }
         nlev = std::max(nlev, S.nlevels);
         nsn += S.ns;
@@ -257,6 +262,8 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     dep_parent = cv.take<int>(nsn);
     dep_nchild = cv.take<int>(nsn);
     dep_ctr = cv.take<int>(3 * nsn + 2);
+    upitems = cv.take<StripItem>(nup);
+    split_update = max_rows <= kUpdMaxRows;
     stage = Staging{};
     if (staging) {
         stage.w = cv.take<double>(w_ofs[ninst]);
@@ -312,6 +319,18 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         }
         lvl_ptr.push_back((int)sn.size());
     }
+    // update-matrix strips of the same fronts, level by level
+    std::vector<StripItem> up;
+    up.reserve(nup);
+    up_ptr.assign(1, 0);
+    for (size_t l = 0; l + 1 < lvl_ptr.size(); l++) {
+        for (int t = lvl_ptr[l]; t < lvl_ptr[l + 1]; t++) {
+            const Symbolic& S = *s[sn[t].inst];
+            const int u = S.sn_nrow[sn[t].id] - S.sn_ncol[sn[t].id];
+            for (int k = 0; k < (u + 15) / 16; k++) up.push_back(StripItem{sn[t].inst, sn[t].id, k, 0});
+        }
+        up_ptr.push_back((int)up.size());
+    }
     // dependency lists in the same (topological) item order
     std::vector<int> dpar(sn.size(), -1), dnch(sn.size(), 0);
     {
@@ -345,6 +364,7 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         {kitems, kb.data(), kb.size() * sizeof(WorkItem)},
         {dep_parent, dpar.data(), dpar.size() * sizeof(int)},
         {dep_nchild, dnch.data(), dnch.size() * sizeof(int)},
+        {upitems, up.data(), up.size() * sizeof(StripItem)},
     };
     size_t up_bytes = 0;
     for (auto& pc : pieces) up_bytes += pc.bytes;
@@ -432,8 +452,15 @@ kkt_status Engine::refactor(const Calls& C, hipStream_t st) {
         TL(KKT_PHASE_CONTROL, launch_fill_i32(dep_ctr, 0, 3 * (int64_t)D.nitems + 2, st));
         TL(KKT_PHASE_FACTOR, launch_factor_queue(di(), items, D, std::min(D.nitems, 512), lds_factor, st));
     } else {
-        for (size_t l = 0; l + 1 < lvl_ptr.size(); l++)
-            TL(KKT_PHASE_FACTOR, launch_factor(di(), items + lvl_ptr[l], lvl_ptr[l + 1] - lvl_ptr[l], lds_factor, st));
+        // A level with few fronts leaves most compute units idle: its update
+        // matrices then go to a launch of their own with one workgroup per
+        // 16-column strip. Wide levels keep them in the factor kernel.
+        for (size_t l = 0; l + 1 < lvl_ptr.size(); l++) {
+            const int nf = lvl_ptr[l + 1] - lvl_ptr[l];
+            const bool split = split_update && nf < kSplitMaxFronts;
+            TL(KKT_PHASE_FACTOR, launch_factor(di(), items + lvl_ptr[l], nf, lds_factor, split ? 0 : 1, st));
+            if (split) TL(KKT_PHASE_FACTOR, launch_update(di(), upitems + up_ptr[l], up_ptr[l + 1] - up_ptr[l], st));
+        }
     }
     if (mode == 2 && j_ofs[ninst] > 0) {
         hipError_t e = hipMemcpyAsync(jcopy, C.jv, (size_t)j_ofs[ninst] * 8, hipMemcpyDeviceToDevice, st);
@@ -513,17 +540,27 @@ kkt_status Engine::solve(const Calls& C, int maxit, double tol, kkt_solve_info* 
 // factor status and the per-instance reports.
 kkt_status Engine::solve_finish(const Calls& C, int iter0, int maxit, double tol, kkt_solve_info* infos,
                                 hipStream_t st) {
-    int* hp = (int*)hpin;
+    // One round of lookahead: the next correction and check are queued
+    // before the host reads the current count of stopped instances, so the
+    // GPU never idles on the round trip. Every refinement kernel skips
+    // stopped instances, so the extra queued round changes no result.
+    volatile int* hp = (volatile int*)hpin;
+    hipError_t e = hipSuccess;
+    if (!ctl_event && (e = hipEventCreateWithFlags(&ctl_event, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "refinement control event");
+    refine_check(C, st);
     for (int iter = iter0; iter <= maxit + 1; iter++) {
-        refine_check(C, st);
-        hipError_t e = hipMemcpyAsync(hp, ndone, 4, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_fail(e, "refinement control");
-        if (hp[0] >= ninst) break;
+        // ndone after the check of round iter
+        if ((e = hipMemcpyAsync((void*)hp, ndone, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipEventRecord(ctl_event, st)) != hipSuccess)
+            return hip_fail(e, "refinement control");
         refine_correct(C, st);
+        refine_check(C, st);
+        if ((e = hipEventSynchronize(ctl_event)) != hipSuccess) return hip_fail(e, "refinement control");
+        if (hp[0] >= ninst) break;
     }
     TL(KKT_PHASE_PERMUTE, launch_refine_revert(di(), C, nitems, n_nitems, st));
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "solve launch");
     // a failed factor makes the solve meaningless: report it
     kkt_status fst = read_status(nullptr, nullptr);
@@ -629,8 +666,18 @@ kkt_status Engine::cg_schur(const Calls& C, double tol, int maxit, kkt_cg_info* 
     const int started_done = hp[0];
     kkt_status fst = read_status(nullptr, nullptr);
     if (fst != KKT_OK) return fail(fst, "factor failed; solve refused");
-    hp[0] = started_done;
-    for (int it = 0; hp[0] < ninst && it < maxit; it++) {
+    // CG iterations with one iteration of lookahead: iteration k+1 is queued
+    // before the host reads the count of stopped instances after iteration
+    // k. The CG kernels skip stopped instances, the work vector t is rebuilt
+    // from scratch for dx below, and no instance gets more than maxit
+    // iterations, so the lookahead changes no result.
+    if (!ctl_event && (e = hipEventCreateWithFlags(&ctl_event, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "cg control event");
+    if (!ctl_event2 && (e = hipEventCreateWithFlags(&ctl_event2, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "cg control event");
+    volatile int* slot[2] = {(volatile int*)hpin, (volatile int*)hpin + 16};
+    hipEvent_t ev[2] = {ctl_event, ctl_event2};
+    auto issue = [&](int k) -> hipError_t {
         TL(KKT_PHASE_CG, launch_cg_jt(di(), C, nit, n_nitems, 0, st));
         TL(KKT_PHASE_PERMUTE, launch_perm_in(di(), C, nit, n_nitems, PIN_TN, st));
         sweeps(st, 0);
@@ -640,9 +687,19 @@ kkt_status Engine::cg_schur(const Calls& C, double tol, int maxit, kkt_cg_info* 
         TL(KKT_PHASE_CG, launch_cg_update(di(), C, mit, n_mitems, st));
         TL(KKT_PHASE_CONTROL, launch_cg_beta(di(), ninst, nd, st));
         TL(KKT_PHASE_CG, launch_cg_p(di(), mit, n_mitems, st));
-        e = hipMemcpyAsync(hp, nd, 4, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_fail(e, "cg control");
+        hipError_t r = hipMemcpyAsync((void*)slot[k & 1], nd, 4, hipMemcpyDeviceToHost, st);
+        if (r == hipSuccess) r = hipEventRecord(ev[k & 1], st);
+        return r;
+    };
+    int issued = 0;
+    if (started_done < ninst) {
+        while (issued < maxit && issued < 2)
+            if ((e = issue(issued++)) != hipSuccess) return hip_fail(e, "cg control");
+        for (int k = 0; k < issued; k++) {
+            if ((e = hipEventSynchronize(ev[k & 1])) != hipSuccess) return hip_fail(e, "cg control");
+            if (*slot[k & 1] >= ninst) break;
+            if (issued < maxit && (e = issue(issued++)) != hipSuccess) return hip_fail(e, "cg control");
+        }
     }
     TL(KKT_PHASE_CG, launch_cg_jt(di(), C, nit, n_nitems, 1, st));
     TL(KKT_PHASE_PERMUTE, launch_perm_in(di(), C, nit, n_nitems, PIN_TN, st));

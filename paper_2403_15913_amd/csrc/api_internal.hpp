@@ -82,11 +82,15 @@ struct Engine {
     InstDev* dinsts = nullptr;
     WorkItem *snitems = nullptr, *nitems = nullptr, *mitems = nullptr, *kitems = nullptr;
     int *dep_parent = nullptr, *dep_nchild = nullptr, *dep_ctr = nullptr;  // queue scheduling
+    StripItem* upitems = nullptr;                   // update-matrix strips by level (level schedule)
+    std::vector<int> up_ptr;
+    bool split_update = true;                       // level schedule: update matrices in their own launch
     bool queue_sched = false;                       // dependency-driven launches (else one launch per level)
     // captured refactor + solve (batched form)
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_stream = nullptr;
+    hipEvent_t ctl_event = nullptr, ctl_event2 = nullptr;  // refinement / CG control readback
     Calls g_calls{};
     int g_rounds = 0, g_maxit = 0;
     double g_tol = 0.0;

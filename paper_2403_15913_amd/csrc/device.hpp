@@ -95,4 +95,12 @@ struct WorkItem {
     int id;   // supernode, or first row of a block
 };
 
+// one 16-column strip of a front's update matrix
+struct StripItem {
+    int inst;
+    int id;     // supernode
+    int strip;  // first column / 16
+    int pad;
+};
+
 }  // namespace kkt

@@ -117,18 +117,29 @@ __device__ inline d4 tile_abt(const double* P, int ld, int i0, int j0, int k0, i
     const int lr = lane & 15, lk = lane >> 4;
     const int ia = i0 + lr, jb = j0 + lr;
     const bool va = ia < rlim, vb = jb < rlim;
+    // rows clamped into the panel so every load is valid and unpredicated
+    const int iac = min(ia, rlim - 1), jbc = min(jb, rlim - 1);
     d4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int kk = 0; kk < K; kk += 4) {
+    int kk = 0;
+    for (; kk + 16 <= K; kk += 16) {
+        double a[4], b[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int col = (k0 + kk + 4 * q + lk) * ld;
+            a[q] = P[col + iac];
+            b[q] = P[col + jbc];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) acc = mfma_f64_16x16x4(va ? a[q] : 0.0, vb ? b[q] : 0.0, acc);
+    }
+    for (; kk < K; kk += 4) {
         const int col = (k0 + kk + lk) * ld;
-        const double a = va ? P[col + ia] : 0.0;
-        const double b = vb ? P[col + jb] : 0.0;
-        acc = mfma_f64_16x16x4(a, b, acc);
+        const double a = P[col + iac], b = P[col + jbc];
+        acc = mfma_f64_16x16x4(va ? a : 0.0, vb ? b : 0.0, acc);
     }
     return acc;
 }
 
-// Copy n doubles (n even, both 16-byte aligned) with 16 independent 16-byte
-// loads in flight per thread.
 // Empty asm that takes a value in a vector register: emits nothing, but
 // keeps the optimizer from sinking a batch of loads into the predicated
 // blocks that consume them (which would serialise the loads).
@@ -136,6 +147,8 @@ __device__ inline void pin(double& x) { asm volatile("" : "+v"(x)); }
 __device__ inline void pin(double2& x) { asm volatile("" : "+v"(x.x), "+v"(x.y)); }
 __device__ inline void pin(int& x) { asm volatile("" : "+v"(x)); }
 
+// Copy n doubles (n even, both 16-byte aligned) with 16 independent 16-byte
+// loads in flight per thread.
 __device__ inline void copy_vec(double* __restrict__ dst, const double* __restrict__ src, int n, int tid, int nt) {
     const double2* s2 = (const double2*)src;
     double2* d2 = (double2*)dst;
@@ -197,7 +210,8 @@ __device__ inline void tri_tile(int t, int tj0, int nb, int& ti, int& tj) {
 // and the children's pass-through entries are added to it.
 constexpr int kFactorThreads = 512;
 
-__device__ __forceinline__ void factor_front(const InstDev& I, const int s, double* __restrict__ P, double* invd) {
+__device__ __forceinline__ void factor_front(const InstDev& I, const int s, double* __restrict__ P, double* invd,
+                                             const bool fused_update) {
     const PatDev& T = I.P;
     const int c = __builtin_amdgcn_readfirstlane(T.sn_ncol[s]), r = __builtin_amdgcn_readfirstlane(T.sn_nrow[s]);
     const int u = r - c, col0 = __builtin_amdgcn_readfirstlane(T.sn_col0[s]);
@@ -254,11 +268,21 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
     for (int kb = 0; kb < nbc; kb++) {
         const int j0 = kb << 4, w = min(16, c - j0);
         if (wave == 0) {
-            // diagonal block: lane i < 16 holds row j0+i of the 16 block columns
+            // diagonal block: lane i < 16 holds row j0+i of the 16 block
+            // columns (entries right of the diagonal are never read back).
+            // Step j: the pivot is broadcast from lane j, its reciprocal
+            // square root comes from rsq and two Newton steps, column j is
+            // scaled and shared through LDS (one wave: LDS operations
+            // complete in order), and every lane updates its later entries.
             const int i = lane;
+            double* const colb = invd + 16;
             double a[16];
 #pragma unroll
-            for (int k = 0; k < 16; k++) a[k] = (i < 16 && j0 + i < r) ? P[(j0 + k) * ld + j0 + i] : 0.0;
+            for (int k = 0; k < 16; k++) a[k] = P[(j0 + k) * ld + j0 + min(i, 15)];
+            if (!(i < 16 && j0 + i < r)) {
+#pragma unroll
+                for (int k = 0; k < 16; k++) a[k] = 0.0;
+            }
 #pragma unroll
             for (int j = 0; j < 16; j++) {
                 if (j < w) {
@@ -270,16 +294,24 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
                         }
                         d = 1.0;
                     }
-                    const double ljj = sqrt(d);
-                    const double inv = 1.0 / ljj;
-                    if (i == j) a[j] = ljj;
-                    else if (i > j) a[j] *= inv;
-                    if (lane == 0) invd[j] = inv;
-#pragma unroll
-                    for (int k = j + 1; k < 16; k++) {
-                        const double lkj = readlane_d(a[j], k);
-                        if (i >= k) a[k] -= a[j] * lkj;
+                    double inv, ljj;
+                    if (d > 1e-290 && d < 1e290) {
+                        inv = __builtin_amdgcn_rsq(d);
+                        inv = fma(0.5 * inv, fma(-d * inv, inv, 1.0), inv);
+                        inv = fma(0.5 * inv, fma(-d * inv, inv, 1.0), inv);
+                        ljj = d * inv;
+                    } else {
+                        ljj = sqrt(d);
+                        inv = 1.0 / ljj;
                     }
+                    a[j] = i == j ? ljj : a[j] * inv;
+                    if (i < 16) colb[i] = a[j];
+                    if (lane == 0) invd[j] = inv;
+                    double lk[16];
+#pragma unroll
+                    for (int k = j + 1; k < 16; k++) lk[k] = colb[k];
+#pragma unroll
+                    for (int k = j + 1; k < 16; k++) a[k] = fma(-a[j], lk[k], a[k]);
                 }
             }
             if (i < 16 && j0 + i < r) {
@@ -290,18 +322,28 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
         }
         __syncthreads();
         if (tid < w) dinv[j0 + tid] = invd[tid];
-        // rows below the diagonal block: x = p L_kk^{-T}
+        // rows below the diagonal block: x = p L_kk^{-T}; column j of L_kk
+        // is fetched (contiguous, broadcast to all lanes) while step j-1
+        // computes
         for (int i = j0 + 16 + tid; i < r; i += nt) {
-            double x[16];
+            double x[16], lc[16], ln[16];
 #pragma unroll
             for (int k = 0; k < 16; k++) x[k] = P[(j0 + k) * ld + i];
 #pragma unroll
+            for (int k = 0; k < 16; k++) lc[k] = P[j0 * ld + j0 + k];
+#pragma unroll
             for (int j = 0; j < 16; j++) {
+                if (j + 1 < 16) {
+#pragma unroll
+                    for (int k = 0; k < 16; k++) ln[k] = P[(j0 + j + 1) * ld + j0 + k];
+                }
                 if (j < w) {
                     x[j] *= invd[j];
 #pragma unroll
-                    for (int k = j + 1; k < 16; k++) x[k] -= x[j] * P[(j0 + j) * ld + j0 + k];
+                    for (int k = j + 1; k < 16; k++) x[k] = fma(-x[j], lc[k], x[k]);
                 }
+#pragma unroll
+                for (int k = 0; k < 16; k++) lc[k] = ln[k];
             }
 #pragma unroll
             for (int k = 0; k < 16; k++)
@@ -329,7 +371,7 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
 
     // panel -> HBM: same layout, contiguous 16-byte stores
     copy_vec(I.L + T.sn_lofs[s], P, even_up(ld * c), tid, nt);
-    if (u == 0) return;
+    if (u == 0 || !fused_update) return;
     // update matrix U = -L21 L21^T (lower part) on the matrix cores
     double* __restrict__ Us = I.U + T.sn_uofs[s];
     const int nbu = (u + 15) >> 4;
@@ -391,11 +433,142 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
 }
 
 __global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __restrict__ insts,
-                                                          const WorkItem* __restrict__ items) {
+                                                          const WorkItem* __restrict__ items, int fused_update) {
     extern __shared__ __align__(16) double P[];
-    __shared__ double invd[16];
+    __shared__ double invd[32];
     const WorkItem it = items[blockIdx.x];
-    factor_front(insts[it.inst], it.id, P, invd);
+    factor_front(insts[it.inst], it.id, P, invd, fused_update != 0);
+}
+
+// ---------------------------------------------------------------------------
+// update matrix of a front by 16-column strips (level schedule)
+// ---------------------------------------------------------------------------
+// 16x16 tile of L21 L21^T read from a stored panel (column-major, leading
+// dimension ld, kmax columns): the same k steps as tile_abt over the
+// zero-padded LDS panel, with columns >= kmax contributing zeros.
+__device__ inline d4 tile_abt_g(const double* __restrict__ Lp, int ld, int i0, int j0, int kmax, int rlim,
+                                int lane) {
+    const int lr = lane & 15, lk = lane >> 4;
+    const int ia = i0 + lr, jb = j0 + lr;
+    const bool va = ia < rlim, vb = jb < rlim;
+    const int iac = min(ia, rlim - 1), jbc = min(jb, rlim - 1);
+    const int K4 = (kmax + 3) & ~3;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    int kk = 0;
+    for (; kk + 16 <= K4; kk += 16) {
+        double a[4], b[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int col = min(kk + 4 * q + lk, kmax - 1) * ld;
+            a[q] = Lp[col + iac];
+            b[q] = Lp[col + jbc];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const bool vk = kk + 4 * q + lk < kmax;
+            acc = mfma_f64_16x16x4(va && vk ? a[q] : 0.0, vb && vk ? b[q] : 0.0, acc);
+        }
+    }
+    for (; kk < K4; kk += 4) {
+        const int col = min(kk + lk, kmax - 1) * ld;
+        const double a = Lp[col + iac], b = Lp[col + jbc];
+        const bool vk = kk + lk < kmax;
+        acc = mfma_f64_16x16x4(va && vk ? a : 0.0, vb && vk ? b : 0.0, acc);
+    }
+    return acc;
+}
+
+// One workgroup per 16-column strip of U = -L21 L21^T: the strip's tiles
+// on the matrix cores from the stored panel, then, child by child, the
+// children's update entries that pass through to the strip's columns. Each
+// entry of U receives the same operations, in the same order, as in the
+// factor kernel's fused path, so the two paths agree bitwise.
+constexpr int kUpdThreads = 256;
+__global__ __launch_bounds__(kUpdThreads) void k_update(const InstDev* __restrict__ insts,
+                                                       const StripItem* __restrict__ items) {
+    __shared__ int srel[kUpdMaxRows];
+    const StripItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    const PatDev& T = I.P;
+    const int s = it.id;
+    const int c = __builtin_amdgcn_readfirstlane(T.sn_ncol[s]), r = __builtin_amdgcn_readfirstlane(T.sn_nrow[s]);
+    const int u = r - c, ld = r | 1;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
+    const double* __restrict__ Lp = I.L + T.sn_lofs[s];
+    double* __restrict__ Us = I.U + T.sn_uofs[s];
+    const int tj = it.strip, nbu = (u + 15) >> 4;
+    for (int t = wave; t < nbu - tj; t += nwave) {
+        const int ti = tj + t;
+        const d4 acc = tile_abt_g(Lp, ld, c + (ti << 4), c + (tj << 4), c, r, lane);
+        const int b = (tj << 4) + (lane & 15);
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int a = (ti << 4) + 4 * e + (lane >> 4);
+            if (a < u && b <= a) Us[(int64_t)b * u + a] = -acc[e];
+        }
+    }
+    __syncthreads();
+    const int b0 = tj << 4, b1 = min(b0 + 16, u);
+    const int ch0 = __builtin_amdgcn_readfirstlane(T.ch_ptr[s]), ch1 = __builtin_amdgcn_readfirstlane(T.ch_ptr[s + 1]);
+    for (int q = ch0; q < ch1; q++) {
+        const int ch = __builtin_amdgcn_readfirstlane(T.ch_list[q]);
+        const int cc = __builtin_amdgcn_readfirstlane(T.sn_ncol[ch]);
+        const int uc = __builtin_amdgcn_readfirstlane(T.sn_nrow[ch]) - cc;
+        const int nb = __builtin_amdgcn_readfirstlane(T.rel_np[ch]);
+        const double* __restrict__ Uc = I.U + T.sn_uofs[ch];
+        const int* __restrict__ rl = T.rel + T.sn_rowofs[ch] + cc;
+        for (int a = tid; a < uc; a += nt) srel[a] = rl[a] - c;
+        __syncthreads();
+        // child columns nb <= b < uc whose target column lies in [b0, b1):
+        // a contiguous range, since the relative indices increase
+        int blo = nb, bhi;
+        {
+            int lo = nb, hi = uc;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (srel[mid] < b0) lo = mid + 1;
+                else hi = mid;
+            }
+            blo = lo;
+            hi = uc;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (srel[mid] < b1) lo = mid + 1;
+                else hi = mid;
+            }
+            bhi = lo;
+        }
+        blo = __builtin_amdgcn_readfirstlane(blo);
+        bhi = __builtin_amdgcn_readfirstlane(bhi);
+        const int tot = (bhi - blo) * uc;
+        const int64_t base = (int64_t)blo * uc;
+        constexpr int UNR = 16;
+        for (int q0 = tid; q0 < tot; q0 += nt * UNR) {
+            double v[UNR], cur[UNR];
+            int dst[UNR];
+            bool keep[UNR];
+#pragma unroll
+            for (int k = 0; k < UNR; k++) {
+                const int qa = q0 + k * nt;
+                const int qq = min(qa, tot - 1);
+                const int bq = qq / uc;
+                const int b = blo + bq, a = qq - bq * uc;
+                keep[k] = qa < tot && a >= b;
+                dst[k] = srel[b] * u + srel[a];
+                v[k] = Uc[base + qq];
+                cur[k] = Us[dst[k]];
+            }
+#pragma unroll
+            for (int k = 0; k < UNR; k++) {
+                pin(v[k]);
+                pin(cur[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < UNR; k++)
+                if (keep[k]) Us[dst[k]] = cur[k] + v[k];
+        }
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -456,7 +629,7 @@ __device__ inline int take_ticket(int* ticket, int* slot) {
 __global__ __launch_bounds__(kFactorThreads) void k_factor_queue(const InstDev* __restrict__ insts,
                                                                 const WorkItem* __restrict__ items, DepLists D) {
     extern __shared__ __align__(16) double P[];
-    __shared__ double invd[16];
+    __shared__ double invd[32];
     __shared__ int slot;
     for (;;) {
         const int t = take_ticket(D.ticket, &slot);
@@ -467,7 +640,7 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor_queue(const InstDev* 
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const WorkItem it = items[t];
-        factor_front(insts[it.inst], it.id, P, invd);
+        factor_front(insts[it.inst], it.id, P, invd, true);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
         if (sched_wave() && par >= 0) publish_add(D.cnt + par);
@@ -1110,8 +1283,12 @@ void launch_status_init(int* status, int ninst, hipStream_t st) {
 void launch_assemble(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st) {
     if (nitems > 0) k_assemble<<<nitems, kBlock, 0, st>>>(insts, C, items);
 }
-void launch_factor(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, hipStream_t st) {
-    if (nitems > 0) k_factor<<<nitems, kFactorThreads, lds, st>>>(insts, items);
+void launch_factor(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, int fused_update,
+                   hipStream_t st) {
+    if (nitems > 0) k_factor<<<nitems, kFactorThreads, lds, st>>>(insts, items, fused_update);
+}
+void launch_update(const InstDev* insts, const StripItem* items, int nitems, hipStream_t st) {
+    if (nitems > 0) k_update<<<nitems, kUpdThreads, 0, st>>>(insts, items);
 }
 void launch_factor_queue(const InstDev* insts, const WorkItem* items, const DepLists& D, int grid, size_t lds,
                          hipStream_t st) {

@@ -24,6 +24,8 @@ struct Calls {
 };
 
 constexpr int kBlock = 256;
+constexpr int kUpdMaxRows = 4096;  // strip update kernel: largest child update (rows) it stages
+constexpr int kSplitMaxFronts = 48;  // levels with fewer fronts launch their update matrices by strips
 
 // Dependency lists of a persistent (queue-scheduled) launch over the fronts
 // in topological order: parent item (-1 for roots), number of children, and
@@ -56,7 +58,10 @@ void launch_copy_segments(const CopySeg* segs, int nseg, hipStream_t st);
 void launch_fill_i32(int* p, int v, int64_t n, hipStream_t st);
 void launch_status_init(int* status, int ninst, hipStream_t st);
 void launch_assemble(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st);
-void launch_factor(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, hipStream_t st);
+void launch_factor(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, int fused_update,
+                   hipStream_t st);
+// update matrices by 16-column strips (after the factor launch of the same level)
+void launch_update(const InstDev* insts, const StripItem* items, int nitems, hipStream_t st);
 void launch_factor_queue(const InstDev* insts, const WorkItem* items, const DepLists& D, int grid, size_t lds,
                          hipStream_t st);
 void launch_sweeps_queue(const InstDev* insts, const WorkItem* items, const DepLists& D, int grid, size_t lds,
