@@ -144,7 +144,7 @@ hipError_t DevPattern::build(const Symbolic& S) {
     UP(b_perm, perm, perm, int)
     UP(b_iperm, iperm, iperm, int)
     UP(b_spptr, sp_ptr, sp_ptr, int64_t)
-    UP(b_spe, sp_e, sp_e, int)
+    UP(b_kcsr, k_csr, k_csr, int)
     UP(b_spcol, sp_col, sp_col, int)
     UP(b_jptr, j_ptr, j_ptr, int)
     UP(b_jcol, j_col, j_col, int)
@@ -202,7 +202,8 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     m_ofs.assign(ninst + 1, 0);
     w_ofs.assign(ninst + 1, 0);
     j_ofs.assign(ninst + 1, 0);
-    std::vector<int64_t> lo(ninst + 1, 0), uo(ninst + 1, 0), vo(ninst + 1, 0), ko(ninst + 1, 0), ro(ninst + 1, 0);
+    std::vector<int64_t> lo(ninst + 1, 0), uo(ninst + 1, 0), vo(ninst + 1, 0), ko(ninst + 1, 0), ro(ninst + 1, 0),
+        co(ninst + 1, 0), po(ninst + 1, 0);
     lds_factor = lds_solve = 0;
     int nlev = 0;
     size_t nsn = 0, nnb = 0, nmb = 0, nkb = 0, nup = 0;
@@ -217,6 +218,8 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         uo[q + 1] = uo[q] + S.usize;
         vo[q + 1] = vo[q] + S.vsize;
         ko[q + 1] = ko[q] + S.nnzk;
+        co[q + 1] = co[q] + S.sp_ptr[S.n];
+        po[q + 1] = po[q] + 5 * (int64_t)((S.n + kBlock - 1) / kBlock) * kResidualSplit;
         ro[q + 1] = ro[q] + (std::max(S.n, S.m) + kBlock - 1) / kBlock + 1;
         for (int k = 0; k < S.ns; k++) {
             lds_factor = std::max(lds_factor, (size_t)factor_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]));
@@ -238,6 +241,8 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     U = cv.take<double>(uo[ninst]);
     V = cv.take<double>(vo[ninst]);
     kval = cv.take<double>(ko[ninst]);
+    kcsr = cv.take<double>(co[ninst]);
+    rpart = cv.take<double>(po[ninst]);
     dinv = cv.take<double>(N);
     y = cv.take<double>(N);
     r = cv.take<double>(N);
@@ -291,6 +296,8 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         I.U = U + uo[q];
         I.V = V + vo[q];
         I.kval = kval + ko[q];
+        I.kcsr = kcsr + co[q];
+        I.rpart = rpart + po[q];
         I.dinv = dinv + n_ofs[q];
         I.y = y + n_ofs[q];
         I.r = r + n_ofs[q];
@@ -540,16 +547,26 @@ kkt_status Engine::solve(const Calls& C, int maxit, double tol, kkt_solve_info* 
 // factor status and the per-instance reports.
 kkt_status Engine::solve_finish(const Calls& C, int iter0, int maxit, double tol, kkt_solve_info* infos,
                                 hipStream_t st) {
-    // One round of lookahead: the next correction and check are queued
-    // before the host reads the current count of stopped instances, so the
-    // GPU never idles on the round trip. Every refinement kernel skips
-    // stopped instances, so the extra queued round changes no result.
+    // With several instances, one round of lookahead: the next correction
+    // and check are queued before the host reads the current count of
+    // stopped instances, so the GPU does not idle on the round trip. Every
+    // refinement kernel skips stopped instances, so the extra queued round
+    // changes no result. A single instance reads its decision first (after
+    // its last correction a queued round would only delay the return).
     volatile int* hp = (volatile int*)hpin;
     hipError_t e = hipSuccess;
     if (!ctl_event && (e = hipEventCreateWithFlags(&ctl_event, hipEventDisableTiming)) != hipSuccess)
         return hip_fail(e, "refinement control event");
     refine_check(C, st);
-    for (int iter = iter0; iter <= maxit + 1; iter++) {
+    for (int iter = iter0; iter <= maxit + 1 && ninst == 1; iter++) {
+        if ((e = hipMemcpyAsync((void*)hp, ndone, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess)
+            return hip_fail(e, "refinement control");
+        if (hp[0] >= ninst) break;
+        refine_correct(C, st);
+        refine_check(C, st);
+    }
+    for (int iter = iter0; iter <= maxit + 1 && ninst > 1; iter++) {
         // ndone after the check of round iter
         if ((e = hipMemcpyAsync((void*)hp, ndone, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
             (e = hipEventRecord(ctl_event, st)) != hipSuccess)

@@ -42,7 +42,7 @@ struct DevBuf {
 struct DevPattern {
     PatDev desc{};
     DevBuf b_col0, b_ncol, b_nrow, b_rowofs, b_lofs, b_uofs, b_vofs, b_rows, b_rel, b_relnp, b_chptr, b_chlist,
-        b_ksnptr, b_kloc, b_kw, b_kdiag, b_kpptr, b_pa, b_pb, b_jrow, b_perm, b_iperm, b_spptr, b_spe, b_spcol,
+        b_ksnptr, b_kloc, b_kw, b_kdiag, b_kpptr, b_pa, b_pb, b_jrow, b_perm, b_iperm, b_spptr, b_kcsr, b_spcol,
         b_jptr, b_jcol, b_jtptr, b_jte, b_jtrow;
     hipError_t build(const Symbolic& S);
 };
@@ -73,7 +73,7 @@ struct Engine {
     std::vector<std::unique_ptr<DevPattern>> pats;  // patterns uploaded by this engine itself
     DevBuf own;                                     // arena owned by a factor / batch
     // views into the arena
-    double *L = nullptr, *U = nullptr, *V = nullptr, *kval = nullptr, *dinv = nullptr, *y = nullptr, *r = nullptr,
+    double *L = nullptr, *U = nullptr, *V = nullptr, *kval = nullptr, *kcsr = nullptr, *rpart = nullptr, *dinv = nullptr, *y = nullptr, *r = nullptr,
            *xprev = nullptr, *tn = nullptr, *fg = nullptr, *cvec = nullptr, *rvec = nullptr, *pvec = nullptr,
            *qvec = nullptr, *red = nullptr, *jcopy = nullptr;
     int *status = nullptr, *ndone = nullptr;

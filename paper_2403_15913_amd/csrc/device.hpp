@@ -35,7 +35,7 @@ struct PatDev {
     const int* perm;
     const int* iperm;
     const int64_t* sp_ptr;
-    const int* sp_e;
+    const int* k_csr;
     const int* sp_col;
     const int* j_ptr;
     const int* j_col;
@@ -44,13 +44,7 @@ struct PatDev {
     const int* jt_row;
 };
 
-// Ordered-bits accumulators: a non-negative double compares like its bit
-// pattern read as an unsigned integer, so max-reductions use integer atomics
-// and are independent of the order in which blocks arrive.
-enum { ACC_RMAX = 0, ACC_OMEGA, ACC_KNORM, ACC_XMAX, ACC_BMAX, ACC_N };
-
 struct RefineState {
-    unsigned long long acc[ACC_N];
     double omega, omega_prev, eta, eta_prev, relres, relres_prev;
     double tol;
     int maxit;
@@ -74,6 +68,8 @@ struct InstDev {
     double* U;          // update matrices, column-major u x u
     double* V;          // solve update vectors
     double* kval;       // assembled lower-triangle entries of K (grouped by supernode)
+    double* kcsr;       // the same values in the symmetric row lists (both triangles, original rows)
+    double* rpart;      // residual block maxima: 5 per residual block
     double* dinv;       // reciprocals of the pivots of L (pivot order)
     double* y;          // permuted work vector (n)
     double* r;          // residual (n)

@@ -28,8 +28,6 @@ namespace kkt {
 #define KKT_ST_NOT_SPD 4
 #define KKT_ST_NONFINITE 5
 
-__device__ inline unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
-__device__ inline double bitsd(unsigned long long v) { return __longlong_as_double((long long)v); }
 
 // ---------------------------------------------------------------------------
 // fills (used instead of hipMemsetAsync so the sequences stay graph-safe)
@@ -86,6 +84,10 @@ __global__ __launch_bounds__(256) void k_assemble(const InstDev* __restrict__ in
         v += C.gamma * acc;
     }
     I.kval[e] = v;
+    // row-ordered copy (both triangles) for the residual and K x
+    const int c0 = I.P.k_csr[2 * e], c1 = I.P.k_csr[2 * e + 1];
+    I.kcsr[c0] = v;
+    if (c1 >= 0) I.kcsr[c1] = v;
     if (!isfinite(v)) atomicMax(&I.status[0], KKT_ST_NONFINITE);
 }
 
@@ -948,7 +950,6 @@ __global__ void k_refine_reset(const InstDev* __restrict__ insts, int ninst, dou
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= ninst) return;
     RefineState* S = insts[q].rs;
-    for (int k = 0; k < ACC_N; k++) S->acc[k] = 0ull;
     S->omega = S->omega_prev = INFINITY;
     S->eta = S->eta_prev = INFINITY;
     S->relres = S->relres_prev = INFINITY;
@@ -959,7 +960,9 @@ __global__ void k_refine_reset(const InstDev* __restrict__ insts, int ninst, dou
     S->revert = 0;
 }
 
-__device__ inline void block_max5(double v0, double v1, double v2, double v3, double v4, unsigned long long* acc) {
+// block maxima of five values, written to this block's slot (no atomics:
+// the decision kernel takes the maximum over the slots)
+__device__ inline void block_max5(double v0, double v1, double v2, double v3, double v4, double* out) {
     __shared__ double red[5][256];
     const int tid = threadIdx.x;
     red[0][tid] = v0; red[1][tid] = v1; red[2][tid] = v2; red[3][tid] = v3; red[4][tid] = v4;
@@ -969,25 +972,28 @@ __device__ inline void block_max5(double v0, double v1, double v2, double v3, do
             for (int q = 0; q < 5; q++) red[q][tid] = fmax(red[q][tid], red[q][tid + h]);
         __syncthreads();
     }
-    if (tid == 0)
-        for (int q = 0; q < 5; q++) atomicMax(&acc[q], dbits(red[q][0]));
+    if (tid < 5) out[tid] = red[tid][0];
 }
 
 // 16 lanes per row (coalesced reads of the row's entries), 256 rows per block.
+// 16 lanes per row (coalesced reads of the row's entries). Sixteen blocks
+// per 256-row item, one row per 16-lane group: many short independent rows
+// in flight hide the dependent loads (row bounds, then columns, then x).
 __global__ __launch_bounds__(256) void k_residual(const InstDev* __restrict__ insts, Calls C,
                                                   const WorkItem* __restrict__ items) {
-    const WorkItem it = items[blockIdx.x];
+    const WorkItem it = items[blockIdx.x / kResidualSplit];
     const InstDev& I = insts[it.inst];
     if (I.rs->done) return;  // uniform per block
     const double* __restrict__ x = C.x + I.n_off;
     const double* __restrict__ b = C.b + I.n_off;
     const int g = threadIdx.x >> 4, l = threadIdx.x & 15;
     double ra = 0.0, om = 0.0, rs = 0.0, xa = 0.0, ba = 0.0;
-    const int iend = min(it.id + 256, I.P.n);
-    for (int i = it.id + g; i < iend; i += 16) {
+    const int row = it.id + (blockIdx.x % kResidualSplit) * 16 + g;
+    const int iend = min(row + 1, I.P.n);
+    for (int i = row; i < iend; i++) {
         double sum = 0.0, den = 0.0, ks = 0.0;
         for (int64_t p = I.P.sp_ptr[i] + l; p < I.P.sp_ptr[i + 1]; p += 16) {
-            const double kv = I.kval[I.P.sp_e[p]];
+            const double kv = I.kcsr[p];
             const double t = kv * x[I.P.sp_col[p]];
             sum += t;
             den += fabs(t);
@@ -1012,21 +1018,34 @@ __global__ __launch_bounds__(256) void k_residual(const InstDev* __restrict__ in
             ba = fmax(ba, fabs(bi));
         }
     }
-    block_max5(ra, om, rs, xa, ba, I.rs->acc);
+    const int slot = (it.id >> 8) * kResidualSplit + (int)(blockIdx.x % kResidualSplit);
+    block_max5(ra, om, rs, xa, ba, I.rpart + 5 * slot);
 }
 
-// One thread per instance: turn the accumulated maxima into eta / omega and
-// apply the refinement stop rule (omega <= tol, maxit corrections, or omega
-// not halving; in the last case the previous iterate wins if omega grew).
-__global__ void k_refine_decide(const InstDev* __restrict__ insts, int ninst, int* ndone) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= ninst) return;
-    RefineState* S = insts[q].rs;
-    if (S->done) return;
-    const double rmax = bitsd(S->acc[ACC_RMAX]), om = bitsd(S->acc[ACC_OMEGA]);
-    const double kn = bitsd(S->acc[ACC_KNORM]), xm = bitsd(S->acc[ACC_XMAX]), bm = bitsd(S->acc[ACC_BMAX]);
+// One workgroup per instance: the maxima over the residual blocks' slots
+// (order-independent), then eta / omega and the refinement stop rule
+// (omega <= tol, maxit corrections, or omega not halving; in the last case
+// the previous iterate wins if omega grew).
+__global__ __launch_bounds__(256) void k_refine_decide(const InstDev* __restrict__ insts, int* ndone) {
+    const InstDev& I = insts[blockIdx.x];
+    RefineState* S = I.rs;
+    if (S->done) return;  // uniform per block
+    const int nslots = ((I.P.n + 255) >> 8) * kResidualSplit;
+    double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int t = threadIdx.x; t < nslots; t += blockDim.x)
+#pragma unroll
+        for (int q = 0; q < 5; q++) m[q] = fmax(m[q], I.rpart[5 * t + q]);
+    __shared__ double red[5][256];
+    for (int q = 0; q < 5; q++) red[q][threadIdx.x] = m[q];
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+            for (int q = 0; q < 5; q++) red[q][threadIdx.x] = fmax(red[q][threadIdx.x], red[q][threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double rmax = red[0][0], om = red[1][0], kn = red[2][0], xm = red[3][0], bm = red[4][0];
     const double den = kn * xm + bm;
-    for (int k = 0; k < ACC_N; k++) S->acc[k] = 0ull;
     S->eta_prev = S->eta;
     S->relres_prev = S->relres;
     S->omega_prev = S->omega;
@@ -1063,7 +1082,7 @@ __global__ __launch_bounds__(256) void k_matvec(const InstDev* __restrict__ inst
     const int i = it.id + threadIdx.x;
     if (i >= I.P.n) return;
     double sum = 0.0;
-    for (int64_t p = I.P.sp_ptr[i]; p < I.P.sp_ptr[i + 1]; p++) sum += I.kval[I.P.sp_e[p]] * x[I.P.sp_col[p]];
+    for (int64_t p = I.P.sp_ptr[i]; p < I.P.sp_ptr[i + 1]; p++) sum += I.kcsr[p] * x[I.P.sp_col[p]];
     y[i] = sum;
 }
 
@@ -1314,10 +1333,10 @@ void launch_refine_reset(const InstDev* insts, int ninst, double tol, int maxit,
     k_refine_reset<<<blocks_for(ninst, 64), 64, 0, st>>>(insts, ninst, tol, maxit);
 }
 void launch_residual(const InstDev* insts, const Calls& C, const WorkItem* rows, int nitems, hipStream_t st) {
-    if (nitems > 0) k_residual<<<nitems, kBlock, 0, st>>>(insts, C, rows);
+    if (nitems > 0) k_residual<<<nitems * kResidualSplit, kBlock, 0, st>>>(insts, C, rows);
 }
 void launch_refine_decide(const InstDev* insts, int ninst, int* ndone, hipStream_t st) {
-    k_refine_decide<<<blocks_for(ninst, 64), 64, 0, st>>>(insts, ninst, ndone);
+    if (ninst > 0) k_refine_decide<<<ninst, 256, 0, st>>>(insts, ndone);
 }
 void launch_refine_revert(const InstDev* insts, const Calls& C, const WorkItem* rows, int nitems, hipStream_t st) {
     if (nitems > 0) k_refine_revert<<<nitems, kBlock, 0, st>>>(insts, C, rows);

@@ -704,7 +704,15 @@ int analyze(int n, int m, const int32_t* wp, const int32_t* wi, const int32_t* j
                 }
             }
     }
-    if (nnzk >= INT32_MAX || (int64_t)S.pair_a.size() >= INT32_MAX * 2LL) {
+    // positions of every K entry in the symmetric row lists: assembly writes
+    // the row-ordered copy of K that the residual reads sequentially
+    S.k_csr.assign(2 * (size_t)nnzk, -1);
+    for (int64_t q = 0; q < S.sp_ptr[n]; q++) {
+        const int e = S.sp_e[q];
+        if (S.k_csr[2 * (size_t)e] < 0) S.k_csr[2 * (size_t)e] = (int)q;
+        else S.k_csr[2 * (size_t)e + 1] = (int)q;
+    }
+    if (nnzk >= INT32_MAX || S.sp_ptr[n] >= INT32_MAX || (int64_t)S.pair_a.size() >= INT32_MAX * 2LL) {
         err = "pattern too large for 32-bit entry ids";
         return ST_PATTERN;
     }

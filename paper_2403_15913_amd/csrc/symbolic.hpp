@@ -54,6 +54,7 @@ struct Symbolic {
     std::vector<int> jrow;                 // row of every J entry
     std::vector<int64_t> sp_ptr;           // n + 1: symmetric K x by original rows
     std::vector<int> sp_e, sp_col;         // entry id and column for each stored product
+    std::vector<int> k_csr;                // 2 per K entry: its positions in the row lists (-1: diagonal)
     std::vector<int> j_ptr, j_col;         // J as CSR (copy)
     std::vector<int> jt_ptr, jt_e, jt_row; // J^T as CSR (i.e. J by columns)
 
