@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ordering", type=int, default=0)
     ap.add_argument("--nd-leaf", type=int, default=0)
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="pick ordering / leaf size by measurement (ignored when --ordering or --nd-leaf is set)")
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched workload (0: skip)")
     ap.add_argument("--batch-ordering", type=int, default=0)
     ap.add_argument("--batch-autotune", type=int, default=1, help="pick batch options and schedule by measurement")
@@ -214,14 +216,14 @@ PHASE_KERNELS = {"factor": "k_factor+k_update", "fwd": "k_fwd", "bwd": "k_bwd", 
                  "residual": "k_residual"}
 
 
-def measured_traffic(phase, args):
+def measured_traffic(phase, args, opts):
     """HBM bytes per launch of a phase from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE passes scaled by a plain copy's reading), or
     None when the kernels changed since the counters were taken or another
-    configuration is benchmarked."""
+    configuration (workload, schedule, symbolic options) is benchmarked."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     src = os.path.join(ROOT, "paper_2403_15913_amd", "csrc", "kernels.hip")
-    if args.workload != "paper" or args.schedule != "levels" or args.ordering or args.nd_leaf:
+    if args.workload != "paper" or args.schedule != "levels":
         return None
     try:
         with open(path) as fh:
@@ -230,7 +232,7 @@ def measured_traffic(phase, args):
             sha = hashlib.sha256(fh.read()).hexdigest()
     except OSError:
         return None
-    if rec.get("kernels_sha256") != sha:
+    if rec.get("kernels_sha256") != sha or rec.get("options") != {k: int(v) for k, v in opts.items()}:
         return None
     if phase in rec.get("phases", {}):
         return round(rec["phases"][phase]["bytes_per_launch"])
@@ -287,8 +289,16 @@ def main():
     dvals = [dict(w=T(v.w_vals), j=T(v.j_vals), sx=T(v.sigma_x), ss=T(v.sigma_s), b=T(v.b)) for v in vals]
     x = torch.zeros(pat.n, dtype=torch.float64, device=dev)
 
+    tuned = None
+    opts = dict(ordering=args.ordering, nd_leaf=args.nd_leaf)
+    if args.autotune and not args.ordering and not args.nd_leaf:
+        from paper_2403_15913_amd import autotune
+        t0 = time.perf_counter()
+        tried = []
+        opts = autotune.tune_pattern(pat, vals[0], reps=3, table_path=None, log=tried.append)
+        tuned = dict(seconds=round(time.perf_counter() - t0, 2), tried=tried)
     t0 = time.perf_counter()
-    sym = kkt.Symbolic.from_pattern(pat, ordering=args.ordering, nd_leaf=args.nd_leaf)
+    sym = kkt.Symbolic.from_pattern(pat, **opts)
     analyze_s = time.perf_counter() - t0
     stats = sym.stats()
     fac = kkt.Factor(sym)
@@ -341,7 +351,7 @@ def main():
         achieved, peak = wd["work"] / secs / 1e9, PEAK_HBM_GBS
     kernel = PHASE_KERNELS.get(dom, f"k_{dom}")
     roofline = dict(bound=wd["bound"], achieved=round(achieved, 4), peak=peak, unit=wd["unit"],
-                    frac=round(achieved / peak, 5), traffic=measured_traffic(dom, args), traffic_unit="bytes/launch",
+                    frac=round(achieved / peak, 5), traffic=measured_traffic(dom, args, opts), traffic_unit="bytes/launch",
                     kernel=kernel, launches_per_step=tm[dom]["launches"] / args.steps,
                     avg_launch_us=1e3 * tm[dom]["ms"] / max(1, tm[dom]["launches"]))
 
@@ -381,7 +391,7 @@ def main():
         "config": {"workload": ("lifted-kkt plain, distillation-shaped N=2000 (n=142000, m=140000), "
                                 "Sigma~logU[1e-8,1e8], 10 value sets") if args.workload == "paper"
                    else "lifted-kkt plain, NMPC N=50 nx=8 nu=1 (n=450, m=400)",
-                   "mode": "plain", "ordering": args.ordering, "nd_leaf": args.nd_leaf,
+                   "mode": "plain", "options": opts, "autotuned": tuned is not None,
                    "schedule": args.schedule},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -390,6 +400,7 @@ def main():
             "eta_max": float(etas.max()),
             "refine_iters_mean": float(iters.mean()),
             "analyze_s": round(analyze_s, 4),
+            "autotune": tuned,
             "phase_ms_per_step": {k: round(v, 4) for k, v in phase_ms.items()},
             "symbolic": {k: stats[k] for k in ("nsuper", "levels", "max_rows", "max_cols", "nnz_k", "nnz_l",
                                                "nnz_l_exact", "flops", "flops_exact")},

@@ -44,12 +44,14 @@ def signature(pat) -> str:
 
 
 def candidates(n: int):
-    """Option sets to try for a pattern of n variables."""
+    """Option sets to try for a pattern of n variables: natural order, and
+    nested dissection with leaf parts from n/1024 to n/128 vertices (the
+    leaf size trades the depth of the chains inside the leaves against the
+    number of separator levels)."""
     out = [dict(ordering=kkt.ORDER_NATURAL, nd_leaf=0, max_super=96)]
-    for leaf in sorted({max(64, n // k) for k in (1024, 512, 256, 128, 64, 16)}):
+    for leaf in sorted({max(64, n // k) for k in (1024, 512, 340, 256, 128)}):
         if leaf < n:
-            for ms in (64, 96):
-                out.append(dict(ordering=kkt.ORDER_ND, nd_leaf=int(leaf), max_super=ms))
+            out.append(dict(ordering=kkt.ORDER_ND, nd_leaf=int(leaf), max_super=96))
     return out
 
 

@@ -149,22 +149,23 @@ __device__ inline void pin(double& x) { asm volatile("" : "+v"(x)); }
 __device__ inline void pin(double2& x) { asm volatile("" : "+v"(x.x), "+v"(x.y)); }
 __device__ inline void pin(int& x) { asm volatile("" : "+v"(x)); }
 
-// Copy n doubles (n even, both 16-byte aligned) with 16 independent 16-byte
+// Copy n doubles (n even, both 16-byte aligned) with UNR independent 16-byte
 // loads in flight per thread.
+template <int UNR = 16>
 __device__ inline void copy_vec(double* __restrict__ dst, const double* __restrict__ src, int n, int tid, int nt) {
     const double2* s2 = (const double2*)src;
     double2* d2 = (double2*)dst;
     const int n2 = n >> 1;
-    // loads use a clamped (always valid) index so all 16 are issued
+    // loads use a clamped (always valid) index so all UNR are issued
     // unconditionally and stay in registers; only the stores are predicated
-    for (int base = tid; base < n2; base += nt * 16) {
-        double2 v[16];
+    for (int base = tid; base < n2; base += nt * UNR) {
+        double2 v[UNR];
 #pragma unroll
-        for (int k = 0; k < 16; k++) v[k] = s2[min(base + k * nt, n2 - 1)];
+        for (int k = 0; k < UNR; k++) v[k] = s2[min(base + k * nt, n2 - 1)];
 #pragma unroll
-        for (int k = 0; k < 16; k++) pin(v[k]);
+        for (int k = 0; k < UNR; k++) pin(v[k]);
 #pragma unroll
-        for (int k = 0; k < 16; k++) {
+        for (int k = 0; k < UNR; k++) {
             const int q = base + k * nt;
             if (q < n2) d2[q] = v[k];
         }
@@ -267,62 +268,67 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
     }
 
     const int nbc = cp >> 4, nbr = rp >> 4;
-    for (int kb = 0; kb < nbc; kb++) {
+    // diagonal block kb by one wave (the pivot chain)
+    auto diag_block = [&](const int kb) {
         const int j0 = kb << 4, w = min(16, c - j0);
-        if (wave == 0) {
-            // diagonal block: lane i < 16 holds row j0+i of the 16 block
-            // columns (entries right of the diagonal are never read back).
-            // Step j: the pivot is broadcast from lane j, its reciprocal
-            // square root comes from rsq and two Newton steps, column j is
-            // scaled and shared through LDS (one wave: LDS operations
-            // complete in order), and every lane updates its later entries.
-            const int i = lane;
-            double* const colb = invd + 16;
-            double a[16];
+        // diagonal block: lane i < 16 holds row j0+i of the 16 block
+        // columns (entries right of the diagonal are never read back).
+        // Step j: the pivot is broadcast from lane j, its reciprocal
+        // square root comes from rsq and two Newton steps, column j is
+        // scaled and shared through LDS (one wave: LDS operations
+        // complete in order), and every lane updates its later entries.
+        const int i = lane;
+        double a[16];
 #pragma unroll
-            for (int k = 0; k < 16; k++) a[k] = P[(j0 + k) * ld + j0 + min(i, 15)];
-            if (!(i < 16 && j0 + i < r)) {
+        for (int k = 0; k < 16; k++) a[k] = P[(j0 + k) * ld + j0 + min(i, 15)];
+        if (!(i < 16 && j0 + i < r)) {
 #pragma unroll
-                for (int k = 0; k < 16; k++) a[k] = 0.0;
-            }
+            for (int k = 0; k < 16; k++) a[k] = 0.0;
+        }
 #pragma unroll
-            for (int j = 0; j < 16; j++) {
-                if (j < w) {
-                    double d = readlane_d(a[j], j);
-                    if (!(d > 0.0) || !isfinite(d)) {
-                        if (lane == 0) {
-                            atomicMin(&status[1], col0 + j0 + j);
-                            atomicMax(&status[0], KKT_ST_NOT_SPD);
-                        }
-                        d = 1.0;
+        for (int j = 0; j < 16; j++) {
+            if (j < w) {
+                double d = readlane_d(a[j], j);
+                if (!(d > 0.0) || !isfinite(d)) {
+                    if (lane == 0) {
+                        atomicMin(&status[1], col0 + j0 + j);
+                        atomicMax(&status[0], KKT_ST_NOT_SPD);
                     }
-                    double inv, ljj;
-                    if (d > 1e-290 && d < 1e290) {
-                        inv = __builtin_amdgcn_rsq(d);
-                        inv = fma(0.5 * inv, fma(-d * inv, inv, 1.0), inv);
-                        inv = fma(0.5 * inv, fma(-d * inv, inv, 1.0), inv);
-                        ljj = d * inv;
-                    } else {
-                        ljj = sqrt(d);
-                        inv = 1.0 / ljj;
-                    }
-                    a[j] = i == j ? ljj : a[j] * inv;
-                    if (i < 16) colb[i] = a[j];
-                    if (lane == 0) invd[j] = inv;
-                    double lk[16];
-#pragma unroll
-                    for (int k = j + 1; k < 16; k++) lk[k] = colb[k];
-#pragma unroll
-                    for (int k = j + 1; k < 16; k++) a[k] = fma(-a[j], lk[k], a[k]);
+                    d = 1.0;
                 }
-            }
-            if (i < 16 && j0 + i < r) {
+                double inv, ljj;
+                if (d > 1e-290 && d < 1e290) {
+                    inv = __builtin_amdgcn_rsq(d);
+                    inv = fma(0.5 * inv, fma(-d * inv, inv, 1.0), inv);
+                    inv = fma(0.5 * inv, fma(-d * inv, inv, 1.0), inv);
+                    ljj = d * inv;
+                } else {
+                    ljj = sqrt(d);
+                    inv = 1.0 / ljj;
+                }
+                a[j] = i == j ? ljj : a[j] * inv;
+                // two alternating broadcast buffers: step j+1's write
+                // does not wait for step j's reads
+                double* const colb = invd + 16 + 16 * (j & 1);
+                if (i < 16) colb[i] = a[j];
+                if (lane == 0) invd[j] = inv;
+                double lk[16];
 #pragma unroll
-                for (int k = 0; k < 16; k++)
-                    if (k < w && k <= i) P[(j0 + k) * ld + j0 + i] = a[k];
+                for (int k = j + 1; k < 16; k++) lk[k] = colb[k];
+                // the next pivot's column first
+#pragma unroll
+                for (int k = j + 1; k < 16; k++) a[k] = fma(-a[j], lk[k], a[k]);
             }
         }
-        __syncthreads();
+        if (i < 16 && j0 + i < r) {
+#pragma unroll
+            for (int k = 0; k < 16; k++)
+                if (k < w && k <= i) P[(j0 + k) * ld + j0 + i] = a[k];
+        }
+    };
+    // rows below diagonal block kb, by all threads (after diag_block(kb))
+    auto trsm_block = [&](const int kb) {
+        const int j0 = kb << 4, w = min(16, c - j0);
         if (tid < w) dinv[j0 + tid] = invd[tid];
         // rows below the diagonal block: x = p L_kk^{-T}; column j of L_kk
         // is fetched (contiguous, broadcast to all lanes) while step j-1
@@ -351,24 +357,41 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
             for (int k = 0; k < 16; k++)
                 if (k < w) P[(j0 + k) * ld + i] = x[k];
         }
-        __syncthreads();
-        // trailing update of the panel columns right of this block (matrix cores)
-        if (kb + 1 < nbc) {
-            int ntile = 0;
-            for (int jt = kb + 1; jt < nbc; jt++) ntile += nbr - jt;
-            for (int t = wave; t < ntile; t += nwave) {
-                int ti, tj;
-                tri_tile(t, kb + 1, nbr, ti, tj);
-                const d4 acc = tile_abt(P, ld, ti << 4, tj << 4, j0, 16, r, lane);
-                const int col = (tj << 4) + (lane & 15);
+    };
+    // update by block kb of the column blocks [tj0, tj1) (matrix cores);
+    // tiles t0, t0 + ts, ... of that range
+    auto update_tiles = [&](const int kb, const int tj0, const int tj1, const int t0, const int ts) {
+        const int j0 = kb << 4;
+        int ntile = 0;
+        for (int jt = tj0; jt < tj1; jt++) ntile += nbr - jt;
+        for (int t = t0; t < ntile; t += ts) {
+            int ti, tj;
+            tri_tile(t, tj0, nbr, ti, tj);
+            const d4 acc = tile_abt(P, ld, ti << 4, tj << 4, j0, 16, r, lane);
+            const int col = (tj << 4) + (lane & 15);
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const int row = (ti << 4) + 4 * e + (lane >> 4);
-                    if (col < c && row >= col && row < r) P[col * ld + row] -= acc[e];
-                }
+            for (int e = 0; e < 4; e++) {
+                const int row = (ti << 4) + 4 * e + (lane >> 4);
+                if (col < c && row >= col && row < r) P[col * ld + row] -= acc[e];
             }
-            __syncthreads();
         }
+    };
+    // Right-looking blocked Cholesky with one block of look-ahead: column
+    // block kb+1 takes block kb's update first; then wave 0 factors diagonal
+    // block kb+1 while the other waves apply block kb's update to the columns
+    // beyond it. Every entry still receives the block updates in block order.
+    if (wave == 0) diag_block(0);
+    __syncthreads();
+    trsm_block(0);
+    __syncthreads();
+    for (int kb = 0; kb + 1 < nbc; kb++) {
+        update_tiles(kb, kb + 1, kb + 2, wave, nwave);
+        __syncthreads();
+        if (wave == 0) diag_block(kb + 1);
+        else update_tiles(kb, kb + 2, nbc, wave - 1, nwave - 1);
+        __syncthreads();
+        trsm_block(kb + 1);
+        __syncthreads();
     }
 
     // panel -> HBM: same layout, contiguous 16-byte stores
@@ -437,7 +460,7 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
 __global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __restrict__ insts,
                                                           const WorkItem* __restrict__ items, int fused_update) {
     extern __shared__ __align__(16) double P[];
-    __shared__ double invd[32];
+    __shared__ double invd[48];
     const WorkItem it = items[blockIdx.x];
     factor_front(insts[it.inst], it.id, P, invd, fused_update != 0);
 }
@@ -631,7 +654,7 @@ __device__ inline int take_ticket(int* ticket, int* slot) {
 __global__ __launch_bounds__(kFactorThreads) void k_factor_queue(const InstDev* __restrict__ insts,
                                                                 const WorkItem* __restrict__ items, DepLists D) {
     extern __shared__ __align__(16) double P[];
-    __shared__ double invd[32];
+    __shared__ double invd[48];
     __shared__ int slot;
     for (;;) {
         const int t = take_ticket(D.ticket, &slot);
@@ -773,7 +796,7 @@ __device__ __forceinline__ void fwd_front(const InstDev& I, const int s, double*
     double* w = sh + even_up(ld * c);
     double* va = w + c;
     double* dv = va + u;
-    copy_vec(P, I.L + T.sn_lofs[s], even_up(ld * c), tid, nt);
+    copy_vec<32>(P, I.L + T.sn_lofs[s], even_up(ld * c), tid, nt);
     for (int t = tid; t < c; t += nt) {
         w[t] = I.y[col0 + t];
         dv[t] = I.dinv[col0 + t];
@@ -822,7 +845,7 @@ __device__ __forceinline__ void bwd_front(const InstDev& I, const int s, double*
     double* zu = t + c;
     double* dv = zu + u;
     const int* __restrict__ rw = T.rows + T.sn_rowofs[s] + c;
-    copy_vec(P, I.L + T.sn_lofs[s], even_up(ld * c), tid, nt);
+    copy_vec<32>(P, I.L + T.sn_lofs[s], even_up(ld * c), tid, nt);
     for (int i = tid; i < u; i += nt) zu[i] = I.y[rw[i]];
     for (int k = tid; k < c; k += nt) dv[k] = I.dinv[col0 + k];
     __syncthreads();
