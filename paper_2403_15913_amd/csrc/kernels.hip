@@ -235,36 +235,130 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
 
-    for (int q = tid; q < ld * cp; q += nt) P[q] = 0.0;
-    __syncthreads();
-    {
-        const int64_t e0 = T.k_snptr[s];
-        const int* __restrict__ kl = T.k_loc + e0;
-        const double* __restrict__ kv = I.kval + e0;
-        batched<8>((int)(T.k_snptr[s + 1] - e0), tid, nt, [&](int q) { return kv[q]; },
-                   [&](int q, double v) {
-                       const int loc = kl[q];
-                       P[(loc >> 16) * ld + (loc & 0xffff)] = v;
-                   });
-    }
-    __syncthreads();
-    int* srel = (int*)(P + ld * cp);  // relative indices of the child being added
-    for (int q = ch0; q < ch1; q++) {
+    // Assembly of the front: the original entries of K, then the children's
+    // update matrices (entries (a, b), a >= b, whose column b maps into the
+    // panel), child by child in a fixed order (two children can add into the
+    // same entry). The loads of the K entries and of the first batch of the
+    // first two children are all issued before the first wait, so their
+    // memory round trips overlap; later batches are loaded and added in turn.
+    // Loads use clamped indices, nothing is predicated.
+    constexpr int EU = 18;  // extend-add entries per thread and batch
+    struct Child {
+        const double* Uc;
+        const int* rl;
+        int uc, nb, tot;
+    };
+    struct ExtBatch {
+        double v[EU];
+        int ra[EU], rb[EU];  // relative row / column; row < 0 (as ~row): not kept
+    };
+    auto child_at = [&](const int q) {
+        Child C;
         const int ch = __builtin_amdgcn_readfirstlane(chl[q]);
         const int cc = __builtin_amdgcn_readfirstlane(sn_ncol[ch]);
-        const int uc = __builtin_amdgcn_readfirstlane(sn_nrow[ch]) - cc, nb = __builtin_amdgcn_readfirstlane(rel_np[ch]);
-        const double* __restrict__ Uc = Ubase + sn_uofs[ch];
-        const int* __restrict__ rl = rel + sn_rowofs[ch] + cc;
-        for (int a = tid; a < uc; a += nt) srel[a] = rl[a];
+        C.uc = __builtin_amdgcn_readfirstlane(sn_nrow[ch]) - cc;
+        C.nb = __builtin_amdgcn_readfirstlane(rel_np[ch]);
+        C.tot = C.nb * C.uc;
+        C.Uc = Ubase + sn_uofs[ch];
+        C.rl = rel + sn_rowofs[ch] + cc;
+        return C;
+    };
+    // (column, row) of the flat index q0 + k*nt by stepping, not dividing
+    auto ext_load = [&](ExtBatch& B, const Child& C, const int q0) {
+        const int uc = C.uc, tot = C.tot;
+        const int db = nt / uc, da = nt - db * uc;
+        int bq = q0 / uc, aq = q0 - bq * uc;
+#pragma unroll
+        for (int k = 0; k < EU; k++) {
+            const int qa = q0 + k * nt;
+            const bool keep = qa < tot && aq >= bq;
+            B.v[k] = C.Uc[min(qa, tot - 1)];
+            const int ri = C.rl[qa < tot ? aq : uc - 1];
+            B.ra[k] = keep ? ri : ~ri;
+            B.rb[k] = C.rl[min(bq, C.nb - 1)];
+            aq += da;
+            bq += db;
+            if (aq >= uc) {
+                aq -= uc;
+                bq++;
+            }
+        }
+    };
+    auto ext_pin = [&](ExtBatch& B) {
+#pragma unroll
+        for (int k = 0; k < EU; k++) {
+            pin(B.v[k]);
+            pin(B.ra[k]);
+            pin(B.rb[k]);
+        }
+    };
+    // the destinations of one child are distinct: read all, then write
+    auto ext_add = [&](const ExtBatch& B) {
+        double cur[EU];
+        int dst[EU];
+#pragma unroll
+        for (int k = 0; k < EU; k++) {
+            dst[k] = B.rb[k] * ld + (B.ra[k] >= 0 ? B.ra[k] : ~B.ra[k]);
+            cur[k] = P[dst[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < EU; k++)
+            if (B.ra[k] >= 0) P[dst[k]] = cur[k] + B.v[k];
+    };
+    // all batches of child C; the first one is already loaded when pre
+    auto ext_child = [&](const Child& C, ExtBatch& B, const bool pre) {
+        for (int q0 = tid; q0 < C.tot; q0 += nt * EU) {
+            if (!(pre && q0 == tid)) {
+                ext_load(B, C, q0);
+                ext_pin(B);
+            }
+            ext_add(B);
+        }
         __syncthreads();
-        // entries (a, b), a >= b, of the child's update matrix whose column b
-        // maps into the panel
-        batched<24>(nb * uc, tid, nt, [&](int qq) { return Uc[qq]; },
-                    [&](int qq, double v) {
-                        const int b = qq / uc, a = qq - b * uc;
-                        if (a >= b) P[srel[b] * ld + srel[a]] += v;
-                    });
-        __syncthreads();
+    };
+    const int nch = ch1 - ch0;
+    Child C0 = {}, C1 = {};
+    ExtBatch B0, B1;
+    if (nch > 0) C0 = child_at(ch0);
+    if (nch > 1) C1 = child_at(ch0 + 1);
+    const bool pre0 = nch > 0 && C0.tot > 0, pre1 = nch > 1 && C1.tot > 0;
+    const int64_t e0 = T.k_snptr[s];
+    const int nk = (int)(T.k_snptr[s + 1] - e0);
+    const int* __restrict__ kl = T.k_loc + e0;
+    const double* __restrict__ kv = I.kval + e0;
+    constexpr int KU = 8;
+    double kvv[KU];
+    int klv[KU];
+#pragma unroll
+    for (int k = 0; k < KU; k++) {
+        const int q = min(tid + k * nt, nk - 1);
+        kvv[k] = kv[max(q, 0)];
+        klv[k] = kl[max(q, 0)];
+    }
+    if (pre0) ext_load(B0, C0, tid);
+    if (pre1) ext_load(B1, C1, tid);
+#pragma unroll
+    for (int k = 0; k < KU; k++) {
+        pin(kvv[k]);
+        pin(klv[k]);
+    }
+    if (pre0) ext_pin(B0);
+    if (pre1) ext_pin(B1);
+    for (int q = tid; q < ld * cp; q += nt) P[q] = 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KU; k++)
+        if (tid + k * nt < nk) P[(klv[k] >> 16) * ld + (klv[k] & 0xffff)] = kvv[k];
+    for (int q = tid + KU * nt; q < nk; q += nt) {
+        const int loc = kl[q];
+        P[(loc >> 16) * ld + (loc & 0xffff)] = kv[q];
+    }
+    __syncthreads();
+    if (nch > 0) ext_child(C0, B0, pre0);
+    if (nch > 1) ext_child(C1, B1, pre1);
+    for (int q = 2; q < nch; q++) {
+        const Child C = child_at(ch0 + q);
+        ext_child(C, B0, false);
     }
 
     const int nbc = cp >> 4, nbr = rp >> 4;
@@ -421,27 +515,48 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
         const int uc = __builtin_amdgcn_readfirstlane(sn_nrow[ch]) - cc, nb = __builtin_amdgcn_readfirstlane(rel_np[ch]);
         const double* __restrict__ Uc = Ubase + sn_uofs[ch];
         const int* __restrict__ rl = rel + sn_rowofs[ch] + cc;
-        for (int a = tid; a < uc; a += nt) srel[a] = rl[a] - c;
-        __syncthreads();
         const int64_t base = (int64_t)nb * uc;
         const int tot = (uc - nb) * uc;
         constexpr int UNR = 16;
-        // Every index is clamped into [0, tot) and every (a, b) maps inside
-        // U_s (upper-part entries too), so all loads are unpredicated; only
-        // the stores of lower-part entries a >= b within range happen.
+        // Every index is clamped into [0, tot) and entries that are not kept
+        // address a valid place of U_s, so all loads are unpredicated: the
+        // values and relative indices in one round, the current entries of
+        // U_s in the next; only the stores of lower-part entries a >= b
+        // within range happen.
+        const int db = nt / uc, da = nt - db * uc;
         for (int b0 = tid; b0 < tot; b0 += nt * UNR) {
             double v[UNR], cur[UNR];
-            int dst[UNR];
+            int ra[UNR], rb[UNR], dst[UNR];
             bool keep[UNR];
+            int bq = b0 / uc, aq = b0 - bq * uc;
 #pragma unroll
             for (int k = 0; k < UNR; k++) {
                 const int q0 = b0 + k * nt;
                 const int qq = min(q0, tot - 1);
-                const int bq = qq / uc;
-                const int b = nb + bq, a = qq - bq * uc;
-                keep[k] = q0 < tot && a >= b;
-                dst[k] = srel[b] * u + srel[a];
+                const int b = min(nb + bq, uc - 1);
+                keep[k] = q0 < tot && aq >= nb + bq;
+                // entries not kept (upper part, past the end) address the
+                // column's diagonal: rows below nb map into the front's own
+                // columns and have no place in U_s
+                const int a = keep[k] ? aq : b;
                 v[k] = Uc[base + qq];
+                ra[k] = rl[a];
+                rb[k] = rl[b];
+                aq += da;
+                bq += db;
+                if (aq >= uc) {
+                    aq -= uc;
+                    bq++;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < UNR; k++) {
+                pin(ra[k]);
+                pin(rb[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < UNR; k++) {
+                dst[k] = (rb[k] - c) * u + (ra[k] - c);
                 cur[k] = Us[dst[k]];
             }
 #pragma unroll
@@ -577,8 +692,11 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(const InstDev* __restric
                 const int qa = q0 + k * nt;
                 const int qq = min(qa, tot - 1);
                 const int bq = qq / uc;
-                const int b = blo + bq, a = qq - bq * uc;
-                keep[k] = qa < tot && a >= b;
+                const int b = blo + bq, aq = qq - bq * uc;
+                keep[k] = qa < tot && aq >= b;
+                // not kept: the column's diagonal (rows below nb map into the
+                // front's own columns and have no place in U)
+                const int a = keep[k] ? aq : b;
                 dst[k] = srel[b] * u + srel[a];
                 v[k] = Uc[base + qq];
                 cur[k] = Us[dst[k]];
@@ -796,25 +914,83 @@ __device__ __forceinline__ void fwd_front(const InstDev& I, const int s, double*
     double* w = sh + even_up(ld * c);
     double* va = w + c;
     double* dv = va + u;
-    copy_vec<32>(P, I.L + T.sn_lofs[s], even_up(ld * c), tid, nt);
-    for (int t = tid; t < c; t += nt) {
-        w[t] = I.y[col0 + t];
-        dv[t] = I.dinv[col0 + t];
+    // Every load of the prologue is issued before the first wait: the first
+    // batch of the panel, the right-hand side and pivot reciprocals of the
+    // front's columns (c <= 128 < threads), and the first entries of the
+    // first two children's update vectors with their relative indices.
+    constexpr int PU = 32;
+    const double2* __restrict__ s2 = (const double2*)(I.L + T.sn_lofs[s]);
+    double2* d2 = (double2*)P;
+    const int n2 = even_up(ld * c) >> 1;
+    double2 pv[PU];
+#pragma unroll
+    for (int k = 0; k < PU; k++) pv[k] = s2[min(tid + k * nt, n2 - 1)];
+    const int tc = min(tid, c - 1);
+    double wy = I.y[col0 + tc], wd = I.dinv[col0 + tc];
+    const int ch0 = __builtin_amdgcn_readfirstlane(T.ch_ptr[s]), ch1 = __builtin_amdgcn_readfirstlane(T.ch_ptr[s + 1]);
+    const int nch = ch1 - ch0;
+    struct VChild {
+        const double* Vc;
+        const int* rl;
+        int uc;
+    };
+    auto vchild = [&](const int q) {
+        VChild C;
+        const int ch = __builtin_amdgcn_readfirstlane(T.ch_list[q]);
+        const int cc = __builtin_amdgcn_readfirstlane(T.sn_ncol[ch]);
+        C.uc = __builtin_amdgcn_readfirstlane(T.sn_nrow[ch]) - cc;
+        C.Vc = I.V + T.sn_vofs[ch];
+        C.rl = T.rel + T.sn_rowofs[ch] + cc;
+        return C;
+    };
+    VChild V0 = {}, V1 = {};
+    double v0 = 0.0, v1 = 0.0;
+    int r0 = 0, r1 = 0;
+    if (nch > 0) {
+        V0 = vchild(ch0);
+        const int a = min(tid, V0.uc - 1);
+        v0 = V0.Vc[a];
+        r0 = V0.rl[a];
+    }
+    if (nch > 1) {
+        V1 = vchild(ch0 + 1);
+        const int a = min(tid, V1.uc - 1);
+        v1 = V1.Vc[a];
+        r1 = V1.rl[a];
+    }
+#pragma unroll
+    for (int k = 0; k < PU; k++) pin(pv[k]);
+    pin(wy);
+    pin(wd);
+    pin(v0);
+    pin(v1);
+    pin(r0);
+    pin(r1);
+#pragma unroll
+    for (int k = 0; k < PU; k++)
+        if (tid + k * nt < n2) d2[tid + k * nt] = pv[k];
+    for (int q = tid + PU * nt; q < n2; q += nt) d2[q] = s2[q];
+    if (tid < c) {
+        w[tid] = wy;
+        dv[tid] = wd;
     }
     for (int t = tid; t < u; t += nt) va[t] = 0.0;
     __syncthreads();
-    for (int q = T.ch_ptr[s]; q < T.ch_ptr[s + 1]; q++) {
-        const int ch = T.ch_list[q];
-        const int cc = T.sn_ncol[ch], uc = T.sn_nrow[ch] - cc;
-        const double* __restrict__ Vc = I.V + T.sn_vofs[ch];
-        const int* __restrict__ rl = T.rel + T.sn_rowofs[ch] + cc;
-        for (int a = tid; a < uc; a += nt) {
-            const int ra = rl[a];
-            if (ra < c) w[ra] += Vc[a];
-            else va[ra - c] += Vc[a];
+    // children's update vectors, child by child (entries of one child are
+    // distinct; two children can add into the same entry)
+    auto add_child = [&](const VChild& C, const bool pre, const double vp, const int rp) {
+        for (int a = tid; a < C.uc; a += nt) {
+            const bool first = pre && a == tid;
+            const int ra = first ? rp : C.rl[a];
+            const double v = first ? vp : C.Vc[a];
+            if (ra < c) w[ra] += v;
+            else va[ra - c] += v;
         }
         __syncthreads();
-    }
+    };
+    if (nch > 0) add_child(V0, true, v0, r0);
+    if (nch > 1) add_child(V1, true, v1, r1);
+    for (int q = ch0 + 2; q < ch1; q++) add_child(vchild(q), false, 0.0, 0);
     if (tid < 64) {
         double x0 = lane < c ? w[lane] : 0.0;
         double x1 = lane + 64 < c ? w[lane + 64] : 0.0;
@@ -845,9 +1021,30 @@ __device__ __forceinline__ void bwd_front(const InstDev& I, const int s, double*
     double* zu = t + c;
     double* dv = zu + u;
     const int* __restrict__ rw = T.rows + T.sn_rowofs[s] + c;
-    copy_vec<32>(P, I.L + T.sn_lofs[s], even_up(ld * c), tid, nt);
-    for (int i = tid; i < u; i += nt) zu[i] = I.y[rw[i]];
-    for (int k = tid; k < c; k += nt) dv[k] = I.dinv[col0 + k];
+    // The update rows' indices are loaded first, so the gather of their
+    // values waits only for them while the panel loads stay in flight.
+    constexpr int PU = 32;
+    int ri = u > 0 ? rw[min(tid, u - 1)] : 0;
+    const double2* __restrict__ s2 = (const double2*)(I.L + T.sn_lofs[s]);
+    double2* d2 = (double2*)P;
+    const int n2 = even_up(ld * c) >> 1;
+    double2 pv[PU];
+#pragma unroll
+    for (int k = 0; k < PU; k++) pv[k] = s2[min(tid + k * nt, n2 - 1)];
+    double wd = I.dinv[col0 + min(tid, c - 1)];
+    pin(ri);
+    double zy = u > 0 ? I.y[ri] : 0.0;
+#pragma unroll
+    for (int k = 0; k < PU; k++) pin(pv[k]);
+    pin(wd);
+    pin(zy);
+#pragma unroll
+    for (int k = 0; k < PU; k++)
+        if (tid + k * nt < n2) d2[tid + k * nt] = pv[k];
+    for (int q = tid + PU * nt; q < n2; q += nt) d2[q] = s2[q];
+    if (tid < u) zu[tid] = zy;
+    for (int i = tid + nt; i < u; i += nt) zu[i] = I.y[rw[i]];
+    if (tid < c) dv[tid] = wd;
     __syncthreads();
     for (int k = tid; k < c; k += nt) {
         double sum = I.y[col0 + k];
