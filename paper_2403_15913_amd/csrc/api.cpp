@@ -206,7 +206,7 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         co(ninst + 1, 0), po(ninst + 1, 0);
     lds_factor = lds_solve = 0;
     int nlev = 0;
-    size_t nsn = 0, nnb = 0, nmb = 0, nkb = 0, nup = 0;
+    size_t nsn = 0, nnb = 0, nmb = 0, nkb = 0, nup = 0, njb = 0;
     int max_rows = 0;
     for (int q = 0; q < ninst; q++) {
         const Symbolic& S = *s[q];
@@ -232,6 +232,7 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         nnb += (S.n + kBlock - 1) / kBlock;
         nmb += (S.m + kBlock - 1) / kBlock;
         nkb += (S.nnzk + kBlock - 1) / kBlock;
+        njb += (S.nnz_j + kBlock - 1) / kBlock;
     }
     if (lds_factor > (size_t)kMaxDynLds || lds_solve > (size_t)kMaxDynLds)
         return fail(KKT_ERR_PATTERN, "a front exceeds the per-workgroup LDS budget");
@@ -264,6 +265,7 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     nitems = cv.take<WorkItem>(nnb);
     mitems = cv.take<WorkItem>(nmb);
     kitems = cv.take<WorkItem>(nkb);
+    jitems = cv.take<WorkItem>(njb);
     dep_parent = cv.take<int>(nsn);
     dep_nchild = cv.take<int>(nsn);
     dep_ctr = cv.take<int>(3 * nsn + 2);
@@ -298,6 +300,7 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         I.kval = kval + ko[q];
         I.kcsr = kcsr + co[q];
         I.rpart = rpart + po[q];
+        I.js = jcopy + j_ofs[q];
         I.dinv = dinv + n_ofs[q];
         I.y = y + n_ofs[q];
         I.r = r + n_ofs[q];
@@ -315,7 +318,7 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     }
     // work lists: supernodes by tree level (leaves first) across instances,
     // and row / entry blocks of each instance
-    std::vector<WorkItem> sn, nb, mb, kb;
+    std::vector<WorkItem> sn, nb, mb, kb, jb;
     sn.reserve(nsn);
     lvl_ptr.assign(1, 0);
     for (int l = 0; l < nlev; l++) {
@@ -358,10 +361,12 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         for (int i = 0; i < S.n; i += kBlock) nb.push_back(WorkItem{q, i});
         for (int i = 0; i < S.m; i += kBlock) mb.push_back(WorkItem{q, i});
         for (int64_t i = 0; i < S.nnzk; i += kBlock) kb.push_back(WorkItem{q, (int)i});
+        for (int64_t i = 0; i < S.nnz_j; i += kBlock) jb.push_back(WorkItem{q, (int)i});
     }
     n_nitems = (int)nb.size();
     n_mitems = (int)mb.size();
     n_kitems = (int)kb.size();
+    n_jitems = (int)jb.size();
     // one packed upload from pinned memory
     struct Piece { void* dst; const void* src; size_t bytes; } pieces[] = {
         {dinsts, hinst.data(), (size_t)ninst * sizeof(InstDev)},
@@ -369,6 +374,7 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         {nitems, nb.data(), nb.size() * sizeof(WorkItem)},
         {mitems, mb.data(), mb.size() * sizeof(WorkItem)},
         {kitems, kb.data(), kb.size() * sizeof(WorkItem)},
+        {jitems, jb.data(), jb.size() * sizeof(WorkItem)},
         {dep_parent, dpar.data(), dpar.size() * sizeof(int)},
         {dep_nchild, dnch.data(), dnch.size() * sizeof(int)},
         {upitems, up.data(), up.size() * sizeof(StripItem)},
@@ -451,6 +457,7 @@ kkt_status Engine::refactor(const Calls& C, hipStream_t st) {
     gamma = C.gamma;
     // per instance: status[0] = 0, status[1] = INT_MAX (first failing pivot)
     TL(KKT_PHASE_CONTROL, launch_status_init(status, ninst, st));
+    if (C.ss) TL(KKT_PHASE_ASSEMBLE, launch_jscale(di(), C, jitems, n_jitems, st));
     TL(KKT_PHASE_ASSEMBLE, launch_assemble(di(), C, kitems, n_kitems, st));
     const WorkItem* items = snitems;
     if (queue_sched) {

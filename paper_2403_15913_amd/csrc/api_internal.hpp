@@ -80,7 +80,7 @@ struct Engine {
     RefineState* rs = nullptr;
     CgState* cg = nullptr;
     InstDev* dinsts = nullptr;
-    WorkItem *snitems = nullptr, *nitems = nullptr, *mitems = nullptr, *kitems = nullptr;
+    WorkItem *snitems = nullptr, *nitems = nullptr, *mitems = nullptr, *kitems = nullptr, *jitems = nullptr;
     int *dep_parent = nullptr, *dep_nchild = nullptr, *dep_ctr = nullptr;  // queue scheduling
     StripItem* upitems = nullptr;                   // update-matrix strips by level (level schedule)
     std::vector<int> up_ptr;
@@ -97,7 +97,7 @@ struct Engine {
     Staging stage;                                  // used by served waves only
     std::vector<InstDev> hinst;
     std::vector<int> lvl_ptr;
-    int n_nitems = 0, n_mitems = 0, n_kitems = 0;
+    int n_nitems = 0, n_mitems = 0, n_kitems = 0, n_jitems = 0;
     size_t lds_factor = 0, lds_solve = 0;
     std::vector<int64_t> n_ofs, m_ofs, w_ofs, j_ofs;  // ninst + 1 prefix offsets
     void* hpin = nullptr;                              // pinned host staging (uploads, readback)

@@ -70,6 +70,7 @@ struct InstDev {
     double* kval;       // assembled lower-triangle entries of K (grouped by supernode)
     double* kcsr;       // the same values in the symmetric row lists (both triangles, original rows)
     double* rpart;      // residual block maxima: 5 per residual block
+    double* js;         // Lifted-KKT: J values scaled by their row's Sigma_s (HyKKT: copy of J)
     double* dinv;       // reciprocals of the pivots of L (pivot order)
     double* y;          // permuted work vector (n)
     double* r;          // residual (n)

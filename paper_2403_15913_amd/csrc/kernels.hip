@@ -73,10 +73,12 @@ __global__ __launch_bounds__(256) void k_assemble(const InstDev* __restrict__ in
     const int64_t p0 = I.P.k_pptr[e], p1 = I.P.k_pptr[e + 1];
     const double* __restrict__ jv = C.jv + I.j_off;
     if (C.ss) {
-        const double* __restrict__ ss = C.ss + I.m_off;
+        // js[a] = J_a * Sigma_s[row of a] (k_jscale), so each product is
+        // (J_a Sigma_s) J_b with two gathers
+        const double* __restrict__ js = I.js;
         for (int64_t p = p0; p < p1; p++) {
             const int a = I.P.pair_a[p], b = I.P.pair_b[p];
-            v += jv[a] * ss[I.P.jrow[a]] * jv[b];
+            v += js[a] * jv[b];
         }
     } else {
         double acc = 0.0;
@@ -89,6 +91,16 @@ __global__ __launch_bounds__(256) void k_assemble(const InstDev* __restrict__ in
     I.kcsr[c0] = v;
     if (c1 >= 0) I.kcsr[c1] = v;
     if (!isfinite(v)) atomicMax(&I.status[0], KKT_ST_NONFINITE);
+}
+
+// Lifted-KKT: J values scaled by their row's Sigma_s, one thread per entry
+__global__ __launch_bounds__(256) void k_jscale(const InstDev* __restrict__ insts, Calls C,
+                                                const WorkItem* __restrict__ items) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    const int p = it.id + threadIdx.x;
+    if (p >= I.P.j_ptr[I.P.m]) return;
+    I.js[p] = C.jv[I.j_off + p] * C.ss[I.m_off + I.P.jrow[p]];
 }
 
 // ---------------------------------------------------------------------------
@@ -1518,6 +1530,9 @@ void launch_fill_i32(int* p, int v, int64_t n, hipStream_t st) {
 }
 void launch_status_init(int* status, int ninst, hipStream_t st) {
     if (ninst > 0) k_status_init<<<blocks_for(ninst, kBlock), kBlock, 0, st>>>(status, ninst);
+}
+void launch_jscale(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st) {
+    if (nitems > 0) k_jscale<<<nitems, kBlock, 0, st>>>(insts, C, items);
 }
 void launch_assemble(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st) {
     if (nitems > 0) k_assemble<<<nitems, kBlock, 0, st>>>(insts, C, items);

@@ -58,6 +58,7 @@ void launch_copy_segments(const CopySeg* segs, int nseg, hipStream_t st);
 
 void launch_fill_i32(int* p, int v, int64_t n, hipStream_t st);
 void launch_status_init(int* status, int ninst, hipStream_t st);
+void launch_jscale(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st);
 void launch_assemble(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st);
 void launch_factor(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, int fused_update,
                    hipStream_t st);
