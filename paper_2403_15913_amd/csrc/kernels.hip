@@ -404,8 +404,9 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
                 }
                 double inv, ljj;
                 if (d > 1e-290 && d < 1e290) {
+                    // hardware estimate (about half of double precision)
+                    // and one Newton step, which doubles the correct bits
                     inv = __builtin_amdgcn_rsq(d);
-                    inv = fma(0.5 * inv, fma(-d * inv, inv, 1.0), inv);
                     inv = fma(0.5 * inv, fma(-d * inv, inv, 1.0), inv);
                     ljj = d * inv;
                 } else {
@@ -486,6 +487,10 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
     // block kb+1 takes block kb's update first; then wave 0 factors diagonal
     // block kb+1 while the other waves apply block kb's update to the columns
     // beyond it. Every entry still receives the block updates in block order.
+    // Waves are spread over the four SIMDs round-robin; the wave that shares
+    // wave 0's SIMD stays out of the look-ahead update, so the pivot chain
+    // has its SIMD to itself.
+    const int upd_w = wave - 1 - (wave > 4 ? 1 : 0), upd_n = nwave - 2;
     if (wave == 0) diag_block(0);
     __syncthreads();
     trsm_block(0);
@@ -494,7 +499,7 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
         update_tiles(kb, kb + 1, kb + 2, wave, nwave);
         __syncthreads();
         if (wave == 0) diag_block(kb + 1);
-        else update_tiles(kb, kb + 2, nbc, wave - 1, nwave - 1);
+        else if (wave != 4) update_tiles(kb, kb + 2, nbc, upd_w, upd_n);
         __syncthreads();
         trsm_block(kb + 1);
         __syncthreads();
