@@ -808,7 +808,7 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor_queue(const InstDev* 
 }
 
 // ---------------------------------------------------------------------------
-// triangular solves with the c x c diagonal triangle of a staged panel, by
+// triangular solve with the c x c diagonal triangle of a staged panel, by
 // one wave (c <= 128): lane l carries rows l and l + 64 in x0 and x1, dv
 // holds the pivot reciprocals. Blocks of 16 columns: the block's own
 // triangle is read into registers first, so its 16 dependent steps are
@@ -816,54 +816,6 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor_queue(const InstDev* 
 // take the block's contribution with all their LDS loads issued together.
 // Each row's terms are subtracted in the same order as plain substitution.
 // ---------------------------------------------------------------------------
-// L11 y = w (forward)
-__device__ inline void tri_fwd_wave(const double* __restrict__ P, int ld, int c, const double* __restrict__ dv,
-                                    double& x0, double& x1, int lane) {
-    for (int j0 = 0; j0 < c; j0 += 16) {
-        const int nb = min(16, c - j0);
-        const bool hi = j0 >= 64;
-        const int rb = lane - (j0 & 63);
-        const bool inblk = rb >= 0 && rb < nb;
-        const int rbc = min(max(rb, 0), nb - 1);
-        double Lr[16];
-#pragma unroll
-        for (int k = 0; k < 16; k++) Lr[k] = P[min(j0 + k, c - 1) * ld + j0 + rbc];
-#pragma unroll
-        for (int k = 0; k < 16; k++) Lr[k] = (inblk && k < rb) ? Lr[k] : 0.0;
-        const double d = dv[j0 + rbc];
-        double wb = hi ? x1 : x0;
-        double y[16];
-#pragma unroll
-        for (int k = 0; k < 16; k++) {
-            y[k] = k < nb ? readlane_d(wb * d, (j0 & 63) + k) : 0.0;
-            wb = fma(-Lr[k], y[k], wb);
-        }
-        if (inblk) {
-            if (hi) x1 = wb * d;
-            else x0 = wb * d;
-        }
-        const int e = j0 + nb;  // rows e .. c-1 lie below the block
-        if (e < c) {
-            const int i0 = min(lane, c - 1), i1 = min(lane + 64, c - 1);
-            double a0[16], a1[16];
-#pragma unroll
-            for (int k = 0; k < 16; k++) {
-                const double* col = P + min(j0 + k, c - 1) * ld;
-                a0[k] = col[i0];
-                a1[k] = col[i1];
-            }
-            double s0 = x0, s1 = x1;
-#pragma unroll
-            for (int k = 0; k < 16; k++) {
-                s0 = fma(-a0[k], y[k], s0);
-                s1 = fma(-a1[k], y[k], s1);
-            }
-            if (lane >= e && lane < c) x0 = s0;
-            if (lane + 64 >= e && lane + 64 < c) x1 = s1;
-        }
-    }
-}
-
 // L11^T x = t (backward), blocks from the last one down
 __device__ inline void tri_bwd_wave(const double* __restrict__ P, int ld, int c, const double* __restrict__ dv,
                                     double& x0, double& x1, int lane) {
@@ -1008,22 +960,66 @@ __device__ __forceinline__ void fwd_front(const InstDev& I, const int s, double*
     if (nch > 0) add_child(V0, true, v0, r0);
     if (nch > 1) add_child(V1, true, v1, r1);
     for (int q = ch0 + 2; q < ch1; q++) add_child(vchild(q), false, 0.0, 0);
-    if (tid < 64) {
-        double x0 = lane < c ? w[lane] : 0.0;
-        double x1 = lane + 64 < c ? w[lane + 64] : 0.0;
-        tri_fwd_wave(P, ld, c, dv, x0, x1, lane);
-        if (lane < c) w[lane] = x0;
-        if (lane + 64 < c) w[lane + 64] = x1;
+    // L11 y = w and the update rows' GEMV, pipelined by 16-column blocks.
+    // Phase kb: wave 0 takes block kb-1's contribution into block kb's
+    // rows, then solves block kb (its triangle in registers, scalar
+    // broadcasts); meanwhile the other waves take block kb-1's contribution
+    // into every later row (triangle rows past block kb and the update
+    // rows). Every row subtracts its terms in ascending column order.
+    const int nblk = (c + 15) >> 4;
+    const int wave = tid >> 6;
+    for (int kb = 0; kb <= nblk; kb++) {
+        const int p0 = (kb - 1) << 4, nprev = min(16, c - p0);
+        if (wave == 0 && kb < nblk) {
+            const int j0 = kb << 4, nbk = min(16, c - j0);
+            const bool inb = lane < nbk;
+            const int row = j0 + min(lane, nbk - 1);
+            double wb = w[row];
+            if (kb > 0) {
+                double a[16], yv[16];
+#pragma unroll
+                for (int j = 0; j < 16; j++) {
+                    a[j] = P[(p0 + j) * ld + row];
+                    yv[j] = w[p0 + j];
+                }
+#pragma unroll
+                for (int j = 0; j < 16; j++) wb = fma(-a[j], yv[j], wb);
+            }
+            double Lr[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) Lr[k] = P[min(j0 + k, c - 1) * ld + row];
+#pragma unroll
+            for (int k = 0; k < 16; k++) Lr[k] = (inb && k < lane) ? Lr[k] : 0.0;
+            const double d = dv[row];
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                const double yk = k < nbk ? readlane_d(wb * d, k) : 0.0;
+                wb = fma(-Lr[k], yk, wb);
+            }
+            if (inb) w[j0 + lane] = wb * d;
+        } else if (kb > 0) {
+            // rows after block kb: triangle rows, then the update rows
+            const int r1 = min(c, (kb + 1) << 4), ntr = c - r1;
+            const int t0 = kb < nblk ? tid - 64 : tid, ts = kb < nblk ? nt - 64 : nt;
+            double yv[16];
+#pragma unroll
+            for (int j = 0; j < 16; j++) yv[j] = j < nprev ? w[p0 + j] : 0.0;
+            for (int q = t0; q < ntr + u; q += ts) {
+                const int prow = q < ntr ? r1 + q : c + (q - ntr);
+                double a[16];
+#pragma unroll
+                for (int j = 0; j < 16; j++) a[j] = P[(p0 + min(j, nprev - 1)) * ld + prow];
+                double acc = q < ntr ? w[prow] : va[q - ntr];
+#pragma unroll
+                for (int j = 0; j < 16; j++) acc = fma(-a[j], yv[j], acc);
+                if (q < ntr) w[prow] = acc;
+                else va[q - ntr] = acc;
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
     double* __restrict__ Vs = I.V + T.sn_vofs[s];
-    for (int i = tid; i < u; i += nt) {
-        double sum = va[i];
-        const double* row = P + c + i;
-#pragma unroll 8
-        for (int k = 0; k < c; k++) sum -= row[k * ld] * w[k];
-        Vs[i] = sum;
-    }
+    for (int i = tid; i < u; i += nt) Vs[i] = va[i];
     for (int t = tid; t < c; t += nt) I.y[col0 + t] = w[t];
 }
 
