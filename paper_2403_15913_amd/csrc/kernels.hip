@@ -76,9 +76,25 @@ __global__ __launch_bounds__(256) void k_assemble(const InstDev* __restrict__ in
         // js[a] = J_a * Sigma_s[row of a] (k_jscale), so each product is
         // (J_a Sigma_s) J_b with two gathers
         const double* __restrict__ js = I.js;
-        for (int64_t p = p0; p < p1; p++) {
-            const int a = I.P.pair_a[p], b = I.P.pair_b[p];
-            v += js[a] * jv[b];
+        // four pairs per round: indices, then values, all loads issued before
+        // the products are added in pair order
+        for (int64_t p = p0; p < p1; p += 4) {
+            int a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int64_t pc = min(p + q, p1 - 1);
+                a[q] = I.P.pair_a[pc];
+                b[q] = I.P.pair_b[pc];
+            }
+            double x[4], y[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                x[q] = js[a[q]];
+                y[q] = jv[b[q]];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                if (p + q < p1) v += x[q] * y[q];
         }
     } else {
         double acc = 0.0;
