@@ -321,12 +321,41 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     std::vector<WorkItem> sn, nb, mb, kb, jb;
     sn.reserve(nsn);
     lvl_ptr.assign(1, 0);
+    sw_part.clear();
+    sw_lvl.assign(1, 0);
     for (int l = 0; l < nlev; l++) {
         for (int q = 0; q < ninst; q++) {
             const Symbolic& S = *s[q];
             if (l >= S.nlevels) continue;
             for (int t = S.lvl_ptr[l]; t < S.lvl_ptr[l + 1]; t++) sn.push_back(WorkItem{q, S.lvl_list[t]});
         }
+        // Each sweep launch takes the LDS of its own largest front, so a level
+        // of small fronts runs two workgroups per compute unit. Fronts of one
+        // level are independent and their order in the launch is free: where
+        // the small fronts alone fill two workgroups on every compute unit,
+        // they go first and get a launch of their own (launches on one stream
+        // run one after the other, so a split pays only for wide levels).
+        const int b0 = lvl_ptr.back();
+        auto slds = [&](const WorkItem& w) {
+            const Symbolic& S = *s[w.inst];
+            return (size_t)solve_lds_bytes(S.sn_nrow[w.id], S.sn_ncol[w.id]);
+        };
+        int nsmall = 0;
+        for (size_t t = b0; t < sn.size(); t++) nsmall += slds(sn[t]) <= kSweepHalfLds;
+        int b1 = b0;
+        if (nsmall >= kSweepSplitMin && nsmall < (int)sn.size() - b0)
+            b1 = (int)(std::stable_partition(sn.begin() + b0, sn.end(),
+                                             [&](const WorkItem& w) { return slds(w) <= kSweepHalfLds; }) -
+                       sn.begin());
+        const int b2 = (int)sn.size();
+        for (int c = 0; c < 2; c++) {
+            const int lo_i = c ? b1 : b0, hi_i = c ? b2 : b1;
+            if (hi_i == lo_i) continue;
+            size_t mx = 0;
+            for (int t = lo_i; t < hi_i; t++) mx = std::max(mx, slds(sn[t]));
+            sw_part.push_back(SweepPart{lo_i, hi_i - lo_i, mx});
+        }
+        sw_lvl.push_back((int)sw_part.size());
         lvl_ptr.push_back((int)sn.size());
     }
     // update-matrix strips of the same fronts, level by level
@@ -496,9 +525,15 @@ void Engine::sweeps(hipStream_t st, int skip_done) {
     }
     const int nl = (int)lvl_ptr.size() - 1;
     for (int l = 0; l < nl; l++)
-        TL(KKT_PHASE_FWD, launch_fwd(di(), items + lvl_ptr[l], lvl_ptr[l + 1] - lvl_ptr[l], lds_solve, skip_done, st));
+        for (int k = sw_lvl[l]; k < sw_lvl[l + 1]; k++) {
+            const SweepPart& P = sw_part[k];
+            TL(KKT_PHASE_FWD, launch_fwd(di(), items + P.begin, P.count, P.lds, skip_done, st));
+        }
     for (int l = nl - 1; l >= 0; l--)
-        TL(KKT_PHASE_BWD, launch_bwd(di(), items + lvl_ptr[l], lvl_ptr[l + 1] - lvl_ptr[l], lds_solve, skip_done, st));
+        for (int k = sw_lvl[l]; k < sw_lvl[l + 1]; k++) {
+            const SweepPart& P = sw_part[k];
+            TL(KKT_PHASE_BWD, launch_bwd(di(), items + P.begin, P.count, P.lds, skip_done, st));
+        }
 }
 
 kkt_status Engine::read_status(int* st_out, int* bad_out) {

@@ -97,6 +97,11 @@ struct Engine {
     Staging stage;                                  // used by served waves only
     std::vector<InstDev> hinst;
     std::vector<int> lvl_ptr;
+    // sweep launches: each level split into LDS size classes (small fronts
+    // first), parts sw_lvl[l] .. sw_lvl[l + 1] of sw_part
+    struct SweepPart { int begin, count; size_t lds; };
+    std::vector<SweepPart> sw_part;
+    std::vector<int> sw_lvl;
     int n_nitems = 0, n_mitems = 0, n_kitems = 0, n_jitems = 0;
     size_t lds_factor = 0, lds_solve = 0;
     std::vector<int64_t> n_ofs, m_ofs, w_ofs, j_ofs;  // ninst + 1 prefix offsets

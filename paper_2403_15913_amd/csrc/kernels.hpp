@@ -45,6 +45,12 @@ struct DepLists {
 // Dynamic LDS a front may use (the kernels also hold a little static LDS;
 // gfx950 gives a workgroup 160 KiB in total).
 constexpr int kMaxDynLds = 158 * 1024;
+// sweep fronts at or below this LDS size run two workgroups per compute unit
+// (160 KiB of LDS per CU; the sweep kernels' registers allow two)
+constexpr size_t kSweepHalfLds = 79 * 1024;
+// a level's small fronts get a sweep launch of their own from this many on
+// (two workgroups on each of the 256 compute units)
+constexpr int kSweepSplitMin = 512;
 
 hipError_t set_kernel_attributes();
 
