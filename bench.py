@@ -38,14 +38,16 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper", choices=["paper", "small"])
     ap.add_argument("--value-sets", type=int, default=10)
-    ap.add_argument("--cpu-sample", type=int, default=4, help="oracle refactor+solve pairs timed for cpu_baseline")
+    ap.add_argument("--cpu-sample", type=int, default=32, help="oracle refactor+solve pairs timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ordering", type=int, default=0)
     ap.add_argument("--nd-leaf", type=int, default=0)
+    ap.add_argument("--max-super", type=int, default=96, help="widest supernode (columns)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="pick ordering / leaf size by measurement (ignored when --ordering or --nd-leaf is set)")
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched workload (0: skip)")
-    ap.add_argument("--batch-ordering", type=int, default=0)
+    ap.add_argument("--batch-ordering", type=int, default=2, help="batch ordering when not autotuned")
+    ap.add_argument("--batch-nd-leaf", type=int, default=256, help="batch nested-dissection leaf when not autotuned")
     ap.add_argument("--batch-autotune", type=int, default=1, help="pick batch options and schedule by measurement")
     ap.add_argument("--graph-rounds", type=int, default=1, help="refinement rounds recorded in the batch graph")
     ap.add_argument("--schedule", default="levels", choices=["levels", "queue"], help="plain-solver launch schedule")
@@ -74,7 +76,8 @@ def bench_batched(args, kkt, kktgen, torch, dev):
         best = tuned["best"]
     else:
         tuned = None
-        best = dict(ordering=args.batch_ordering, nd_leaf=0, max_super=96, schedule=kkt.SCHEDULE_QUEUE)
+        best = dict(ordering=args.batch_ordering, nd_leaf=args.batch_nd_leaf, max_super=96,
+                    schedule=kkt.SCHEDULE_LEVELS)
     tune_s = time.perf_counter() - t0
     opts = {k: best[k] for k in ("ordering", "nd_leaf", "max_super")}
     t0 = time.perf_counter()
@@ -290,7 +293,7 @@ def main():
     x = torch.zeros(pat.n, dtype=torch.float64, device=dev)
 
     tuned = None
-    opts = dict(ordering=args.ordering, nd_leaf=args.nd_leaf)
+    opts = dict(ordering=args.ordering, nd_leaf=args.nd_leaf, max_super=args.max_super)
     if args.autotune and not args.ordering and not args.nd_leaf:
         from paper_2403_15913_amd import autotune
         t0 = time.perf_counter()
@@ -360,15 +363,16 @@ def main():
         from oracle import sparse as S
         from oracle.build import build_oracle
         build_oracle(force=False)
-        ns = min(args.cpu_sample, len(vals))
+        ns = args.cpu_sample
         t0 = time.perf_counter()
         ok = 0
-        for v in vals[:ns]:
+        for i in range(ns):
+            v = vals[i % len(vals)]
             xo, oinfo = S.lifted_solve(pat, v, v.b)
             ok += int(oinfo["spd"] and oinfo["eta"] <= ETA_GATE)
         cs = time.perf_counter() - t0
         cpu = dict(value=round(ok / cs, 4), unit="refactor+solves/s", cores=1, kind="oracle",
-                   sample=f"{ns} refactor+solve pairs (value sets 0..{ns - 1}) of the same workload: "
+                   sample=f"{ns} refactor+solve pairs (value sets 0..{min(ns, len(vals)) - 1} in turn) of the same workload: "
                           f"scipy assembly + C up-looking sparse LDL^T in stage order + Richardson refinement, "
                           f"single thread", seconds=round(cs, 3))
 

@@ -19,6 +19,7 @@
 
 #include <climits>
 #include <cstdint>
+#include <utility>
 
 #include "device.hpp"
 #include "kernels.hpp"
@@ -140,6 +141,45 @@ __device__ inline double readlane_d(double v, int l) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// value of lane K of this lane's 16-lane row (DPP row broadcast: a
+// cross-lane move inside the vector unit, no LDS round trip)
+template <int K>
+__device__ __forceinline__ double row_bcast(double v) {
+    return __longlong_as_double(__builtin_amdgcn_mov_dpp(__double_as_longlong(v), 0x150 + K, 0xF, 0xF, false));
+}
+
+// value of the wave's first active lane, as a wave-uniform (scalar) value
+__device__ inline double readfirstlane_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)b);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Square root and its reciprocal of a Cholesky pivot d > 0 (finite). d is
+// first scaled by an even power of two into [0.5, 2) (exact), so the
+// hardware estimate and the Newton step meet no overflow, underflow or
+// subnormal for any positive d; the estimate carries about half of double
+// precision and one Newton step doubles the correct bits.
+__device__ __forceinline__ void pivot_roots(const double d, double& inv, double& ljj) {
+    const int h = __builtin_amdgcn_frexp_exp(d) >> 1;
+    const double ds = __builtin_amdgcn_ldexp(d, -2 * h);
+    double t = __builtin_amdgcn_rsq(ds);
+    t = fma(0.5 * t, fma(-ds * t, t, 1.0), t);
+    inv = __builtin_amdgcn_ldexp(t, -h);
+    ljj = d * inv;
+}
+
+// f(integral_constant<int, I>) for I = 0 .. N-1, unrolled at compile time
+template <int... I, class F>
+__device__ __forceinline__ void static_for_impl(std::integer_sequence<int, I...>, F&& f) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(std::make_integer_sequence<int, N>{}, f);
+}
+
 // 16x16 tile of A B^T from a column-major LDS panel P (leading dimension ld):
 // A = rows i0..i0+15, B = rows j0..j0+15, both over columns k0..k0+K-1
 // (K a multiple of 4). Rows >= rlim read as zero.
@@ -240,9 +280,10 @@ __device__ inline void tri_tile(int t, int tj0, int nb, int& ti, int& tj) {
 // cores), then the update matrix U = -L21 L21^T is formed on the matrix cores
 // and the children's pass-through entries are added to it.
 constexpr int kFactorThreads = 512;
+static_assert(kFactorThreads == 512, "the panel schedule assumes eight waves");
 
 __device__ __forceinline__ void factor_front(const InstDev& I, const int s, double* __restrict__ P, double* invd,
-                                             const bool fused_update) {
+                                             const bool fused_update, const bool fused_panel) {
     const PatDev& T = I.P;
     const int c = __builtin_amdgcn_readfirstlane(T.sn_ncol[s]), r = __builtin_amdgcn_readfirstlane(T.sn_nrow[s]);
     const int u = r - c, col0 = __builtin_amdgcn_readfirstlane(T.sn_col0[s]);
@@ -393,24 +434,26 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
     // diagonal block kb by one wave (the pivot chain)
     auto diag_block = [&](const int kb) {
         const int j0 = kb << 4, w = min(16, c - j0);
-        // diagonal block: lane i < 16 holds row j0+i of the 16 block
-        // columns (entries right of the diagonal are never read back).
-        // Step j: the pivot is broadcast from lane j, its reciprocal
-        // square root comes from rsq and two Newton steps, column j is
-        // scaled and shared through LDS (one wave: LDS operations
-        // complete in order), and every lane updates its later entries.
-        const int i = lane;
+        // Diagonal block: each 16-lane row of the wave holds the block, lane
+        // i of a row holding row j0+i (entries right of the diagonal are
+        // never read back; rows past r are zero). Step j: the pivot comes
+        // from lane j, column j is scaled, and every lane takes column j's
+        // entries of the later rows by row broadcasts for its rank-one
+        // update.
+        const int i = lane & 15;
+        const bool live = j0 + i < r;
+        const int row = min(j0 + i, r - 1);
         double a[16];
 #pragma unroll
-        for (int k = 0; k < 16; k++) a[k] = P[(j0 + k) * ld + j0 + min(i, 15)];
-        if (!(i < 16 && j0 + i < r)) {
+        for (int k = 0; k < 16; k++) a[k] = P[(j0 + k) * ld + row];
+        if (!live) {
 #pragma unroll
             for (int k = 0; k < 16; k++) a[k] = 0.0;
         }
-#pragma unroll
-        for (int j = 0; j < 16; j++) {
+        static_for<16>([&](auto J) {
+            constexpr int j = J;
             if (j < w) {
-                double d = readlane_d(a[j], j);
+                double d = readfirstlane_d(row_bcast<j>(a[j]));
                 if (!(d > 0.0) || !isfinite(d)) {
                     if (lane == 0) {
                         atomicMin(&status[1], col0 + j0 + j);
@@ -419,31 +462,17 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
                     d = 1.0;
                 }
                 double inv, ljj;
-                if (d > 1e-290 && d < 1e290) {
-                    // hardware estimate (about half of double precision)
-                    // and one Newton step, which doubles the correct bits
-                    inv = __builtin_amdgcn_rsq(d);
-                    inv = fma(0.5 * inv, fma(-d * inv, inv, 1.0), inv);
-                    ljj = d * inv;
-                } else {
-                    ljj = sqrt(d);
-                    inv = 1.0 / ljj;
-                }
+                pivot_roots(d, inv, ljj);
                 a[j] = i == j ? ljj : a[j] * inv;
-                // two alternating broadcast buffers: step j+1's write
-                // does not wait for step j's reads
-                double* const colb = invd + 16 + 16 * (j & 1);
-                if (i < 16) colb[i] = a[j];
                 if (lane == 0) invd[j] = inv;
-                double lk[16];
-#pragma unroll
-                for (int k = j + 1; k < 16; k++) lk[k] = colb[k];
                 // the next pivot's column first
-#pragma unroll
-                for (int k = j + 1; k < 16; k++) a[k] = fma(-a[j], lk[k], a[k]);
+                static_for<16>([&](auto K) {
+                    constexpr int k = K;
+                    if constexpr (k > j) a[k] = fma(-a[j], row_bcast<k>(a[j]), a[k]);
+                });
             }
-        }
-        if (i < 16 && j0 + i < r) {
+        });
+        if (lane < 16 && live) {
 #pragma unroll
             for (int k = 0; k < 16; k++)
                 if (k < w && k <= i) P[(j0 + k) * ld + j0 + i] = a[k];
@@ -499,26 +528,122 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
             }
         }
     };
+    // Column block kb of the panel in one pass by each of waves 0-3: every
+    // 16-lane row of a wave holds the diagonal block (lane i: row j0+i) and
+    // runs the pivot chain on it, and each lane also carries one row below
+    // the block (wave w, lane l: row j0+16+64w+l). Step j scales column j
+    // and broadcasts its entries of the diagonal rows across the 16-lane
+    // rows; the same broadcast values serve the rank-one update of the
+    // diagonal rows and the substitution step of the rows below. Each entry
+    // sees the same operations in the same order as a pivot chain followed
+    // by a row-by-row triangular solve.
+    auto panel_block = [&](const int kb) {
+        const int j0 = kb << 4, w = min(16, c - j0);
+        const int i = lane & 15;
+        const bool live = j0 + i < r;
+        const int row = min(j0 + i, r - 1);
+        const int prow = j0 + 16 + (wave << 6) + lane;
+        const bool plive = prow < r;
+        const int prc = min(prow, r - 1);
+        double a[16], x[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            a[k] = P[(j0 + k) * ld + row];
+            x[k] = P[(j0 + k) * ld + prc];
+        }
+        if (!live) {
+#pragma unroll
+            for (int k = 0; k < 16; k++) a[k] = 0.0;
+        }
+        // Without branches inside the steps (a failing pivot is recorded and
+        // replaced by one, every step of a full block is unconditional), so
+        // the updates of step j can be scheduled alongside the pivot of step
+        // j+1.
+        double myinv = 0.0;
+        unsigned bad = 0;
+        auto steps = [&](auto full) {
+            static_for<16>([&](auto J) {
+                constexpr int j = J;
+                if (decltype(full)::value || j < w) {
+                    const double dp = readfirstlane_d(row_bcast<j>(a[j]));
+                    const bool ok = dp > 0.0 && isfinite(dp);
+                    bad |= ok ? 0u : 1u << j;
+                    double inv, ljj;
+                    pivot_roots(ok ? dp : 1.0, inv, ljj);
+                    a[j] = i == j ? ljj : a[j] * inv;
+                    myinv = i == j ? inv : myinv;
+                    x[j] *= inv;
+                    double lk[16];
+                    static_for<16>([&](auto K) {
+                        constexpr int k = K;
+                        if constexpr (k > j) lk[k] = row_bcast<k>(a[j]);
+                    });
+                    static_for<16>([&](auto K) {
+                        constexpr int k = K;
+                        if constexpr (k > j) {
+                            a[k] = fma(-a[j], lk[k], a[k]);
+                            x[k] = fma(-x[j], lk[k], x[k]);
+                        }
+                    });
+                }
+            });
+        };
+        if (w == 16)
+            steps(std::true_type{});
+        else
+            steps(std::false_type{});
+        if (bad && tid == 0) {
+            atomicMin(&status[1], col0 + j0 + __builtin_ctz(bad));
+            atomicMax(&status[0], KKT_ST_NOT_SPD);
+        }
+        if (wave == 0 && lane < 16) {
+            if (live) {
+#pragma unroll
+                for (int k = 0; k < 16; k++)
+                    if (k < w && k <= i) P[(j0 + k) * ld + j0 + i] = a[k];
+            }
+            if (lane < w) dinv[j0 + lane] = myinv;
+        }
+        if (plive) {
+#pragma unroll
+            for (int k = 0; k < 16; k++)
+                if (k < w) P[(j0 + k) * ld + prow] = x[k];
+        }
+    };
     // Right-looking blocked Cholesky with one block of look-ahead: column
-    // block kb+1 takes block kb's update first; then wave 0 factors diagonal
-    // block kb+1 while the other waves apply block kb's update to the columns
-    // beyond it. Every entry still receives the block updates in block order.
-    // Waves are spread over the four SIMDs round-robin; the wave that shares
-    // wave 0's SIMD stays out of the look-ahead update, so the pivot chain
-    // has its SIMD to itself.
-    const int upd_w = wave - 1 - (wave > 4 ? 1 : 0), upd_n = nwave - 2;
-    if (wave == 0) diag_block(0);
-    __syncthreads();
-    trsm_block(0);
-    __syncthreads();
-    for (int kb = 0; kb + 1 < nbc; kb++) {
-        update_tiles(kb, kb + 1, kb + 2, wave, nwave);
+    // block kb+1 takes block kb's update first; then waves 0-3 factor
+    // column block kb+1 while waves 4-7 apply block kb's update to the
+    // columns beyond it. Every entry still receives the block updates in
+    // block order. Fronts taller than waves 0-3 can cover, and the
+    // persistent queue kernel, take the pivot chain by wave 0 and a
+    // separate triangular solve of the rows below (same arithmetic).
+    if (fused_panel && r <= 16 + 4 * 64) {
+        if (wave < 4) panel_block(0);
         __syncthreads();
-        if (wave == 0) diag_block(kb + 1);
-        else if (wave != 4) update_tiles(kb, kb + 2, nbc, upd_w, upd_n);
+        for (int kb = 0; kb + 1 < nbc; kb++) {
+            update_tiles(kb, kb + 1, kb + 2, wave, nwave);
+            __syncthreads();
+            if (wave < 4) panel_block(kb + 1);
+            else update_tiles(kb, kb + 2, nbc, wave - 4, nwave - 4);
+            __syncthreads();
+        }
+    } else {
+        // the wave that shares wave 0's SIMD stays out of the look-ahead
+        // update, so the pivot chain has its SIMD to itself
+        const int upd_w = wave - 1 - (wave > 4 ? 1 : 0), upd_n = nwave - 2;
+        if (wave == 0) diag_block(0);
         __syncthreads();
-        trsm_block(kb + 1);
+        trsm_block(0);
         __syncthreads();
+        for (int kb = 0; kb + 1 < nbc; kb++) {
+            update_tiles(kb, kb + 1, kb + 2, wave, nwave);
+            __syncthreads();
+            if (wave == 0) diag_block(kb + 1);
+            else if (wave != 4) update_tiles(kb, kb + 2, nbc, upd_w, upd_n);
+            __syncthreads();
+            trsm_block(kb + 1);
+            __syncthreads();
+        }
     }
 
     // panel -> HBM: same layout, contiguous 16-byte stores
@@ -608,9 +733,9 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
 __global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __restrict__ insts,
                                                           const WorkItem* __restrict__ items, int fused_update) {
     extern __shared__ __align__(16) double P[];
-    __shared__ double invd[48];
+    __shared__ double invd[16];
     const WorkItem it = items[blockIdx.x];
-    factor_front(insts[it.inst], it.id, P, invd, fused_update != 0);
+    factor_front(insts[it.inst], it.id, P, invd, fused_update != 0, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -805,7 +930,7 @@ __device__ inline int take_ticket(int* ticket, int* slot) {
 __global__ __launch_bounds__(kFactorThreads) void k_factor_queue(const InstDev* __restrict__ insts,
                                                                 const WorkItem* __restrict__ items, DepLists D) {
     extern __shared__ __align__(16) double P[];
-    __shared__ double invd[48];
+    __shared__ double invd[16];
     __shared__ int slot;
     for (;;) {
         const int t = take_ticket(D.ticket, &slot);
@@ -816,7 +941,7 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor_queue(const InstDev* 
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const WorkItem it = items[t];
-        factor_front(insts[it.inst], it.id, P, invd, true);
+        factor_front(insts[it.inst], it.id, P, invd, true, false);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
         if (sched_wave() && par >= 0) publish_add(D.cnt + par);

@@ -570,8 +570,11 @@ int analyze(int n, int m, const int32_t* wp, const int32_t* wi, const int32_t* j
         // panel stored column-major with leading dimension r|1 (odd, as in
         // LDS), padded to an even count so every panel starts 16-byte aligned
         S.sn_lofs[s + 1] = S.sn_lofs[s] + (((int64_t)(r | 1) * c + 1) & ~(int64_t)1);
-        S.sn_uofs[s + 1] = S.sn_uofs[s] + (int64_t)u * u;
-        S.sn_vofs[s + 1] = S.sn_vofs[s] + u;
+        // update matrices and vectors start on 256-byte boundaries: no cache
+        // line holds entries of two fronts, which matters where fronts of
+        // one launch hand their results to each other on other compute units
+        S.sn_uofs[s + 1] = S.sn_uofs[s] + (((int64_t)u * u + 31) & ~(int64_t)31);
+        S.sn_vofs[s + 1] = S.sn_vofs[s] + ((u + 31) & ~31);
         for (int k = 0; k < c; k++) S.flops += (double)(r - k - 1) * (r - k) + (r - k - 1);
         S.max_nrow = std::max(S.max_nrow, r);
         S.max_ncol = std::max(S.max_ncol, c);

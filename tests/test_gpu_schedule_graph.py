@@ -152,3 +152,22 @@ def test_graph_replays_match_eager(kkt, schedule, rounds):
     # the eager calls still work on the batch after the graph replays
     xe2, _ = batch_eager(B, vals_b, schedule)
     assert np.array_equal(xe2, xb)
+
+
+def test_queue_full_batch_repeated(kkt):
+    """Full-size instances under the queue schedule, refactored several times:
+    every instance factors (no spurious NOT_SPD) and every solution equals the
+    level schedule's bitwise."""
+    count = 128
+    shapes = kktgen.batch_shapes(count)
+    pats = [kktgen.nmpc_pattern(*sh) for sh in shapes]
+    vals = [kktgen.nmpc_values(p, kktgen.rng_for(3, q, 1), 1e-6, 1e6) for q, p in enumerate(pats)]
+    print(f"queue: {count} full-size instances", flush=True)
+    syms = [kkt.Symbolic.from_pattern(p, ordering=kkt.ORDER_ND, nd_leaf=256, max_super=96) for p in pats]
+    B = kkt.Batch(syms)
+    xl, il = batch_eager(B, vals, kkt.SCHEDULE_LEVELS)
+    for rep in range(4):
+        xq, iq = batch_eager(B, vals, kkt.SCHEDULE_QUEUE)
+        st, bad = B.status()
+        assert not st.any(), (rep, np.nonzero(st)[0].tolist())
+        assert np.array_equal(xl, xq), rep
