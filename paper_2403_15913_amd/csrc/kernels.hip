@@ -156,17 +156,13 @@ __device__ inline double readfirstlane_d(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Square root and its reciprocal of a Cholesky pivot d > 0 (finite). d is
-// first scaled by an even power of two into [0.5, 2) (exact), so the
-// hardware estimate and the Newton step meet no overflow, underflow or
-// subnormal for any positive d; the estimate carries about half of double
-// precision and one Newton step doubles the correct bits.
+// Square root and its reciprocal of a Cholesky pivot d > 0 (finite): the
+// hardware estimate of 1/sqrt(d) (relative error about 3e-8, subnormal d
+// included) and one Newton step, which leaves a relative error of about
+// 1.5e-15 over the whole positive range; no scaling or range test needed.
 __device__ __forceinline__ void pivot_roots(const double d, double& inv, double& ljj) {
-    const int h = __builtin_amdgcn_frexp_exp(d) >> 1;
-    const double ds = __builtin_amdgcn_ldexp(d, -2 * h);
-    double t = __builtin_amdgcn_rsq(ds);
-    t = fma(0.5 * t, fma(-ds * t, t, 1.0), t);
-    inv = __builtin_amdgcn_ldexp(t, -h);
+    const double t = __builtin_amdgcn_rsq(d);
+    inv = fma(0.5 * t, fma(-d * t, t, 1.0), t);
     ljj = d * inv;
 }
 
@@ -560,14 +556,14 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
         // the updates of step j can be scheduled alongside the pivot of step
         // j+1.
         double myinv = 0.0;
-        unsigned bad = 0;
+        unsigned badv = 0;  // the same in every lane
         auto steps = [&](auto full) {
             static_for<16>([&](auto J) {
                 constexpr int j = J;
                 if (decltype(full)::value || j < w) {
-                    const double dp = readfirstlane_d(row_bcast<j>(a[j]));
+                    const double dp = row_bcast<j>(a[j]);
                     const bool ok = dp > 0.0 && isfinite(dp);
-                    bad |= ok ? 0u : 1u << j;
+                    badv |= ok ? 0u : 1u << j;
                     double inv, ljj;
                     pivot_roots(ok ? dp : 1.0, inv, ljj);
                     a[j] = i == j ? ljj : a[j] * inv;
@@ -592,6 +588,7 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
             steps(std::true_type{});
         else
             steps(std::false_type{});
+        const unsigned bad = __builtin_amdgcn_readfirstlane(badv);
         if (bad && tid == 0) {
             atomicMin(&status[1], col0 + j0 + __builtin_ctz(bad));
             atomicMax(&status[0], KKT_ST_NOT_SPD);
