@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstddef>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -262,6 +263,7 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     cg = cv.take<CgState>(ninst);
     dinsts = cv.take<InstDev>(ninst);
     snitems = cv.take<WorkItem>(nsn);
+    fdesc = cv.take<FrontDesc>(nsn);
     nitems = cv.take<WorkItem>(nnb);
     mitems = cv.take<WorkItem>(nmb);
     kitems = cv.take<WorkItem>(nkb);
@@ -385,6 +387,41 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
             }
         }
     }
+    // front descriptors in item order (absolute device addresses)
+    std::vector<FrontDesc> fd(sn.size());
+    for (size_t t = 0; t < sn.size(); t++) {
+        const int q = sn[t].inst, k = sn[t].id;
+        const Symbolic& S = *s[q];
+        const PatDev& PD = p[q]->desc;
+        const InstDev& I = hinst[q];
+        FrontDesc& F = fd[t];
+        std::memset(&F, 0, sizeof(F));
+        F.r = S.sn_nrow[k];
+        F.c = S.sn_ncol[k];
+        F.col0 = S.sn_col0[k];
+        F.nk = (int)(S.k_snptr[k + 1] - S.k_snptr[k]);
+        F.kv = I.kval + S.k_snptr[k];
+        F.kl = PD.k_loc + S.k_snptr[k];
+        F.L = I.L + S.sn_lofs[k];
+        F.U = I.U + S.sn_uofs[k];
+        F.V = I.V + S.sn_vofs[k];
+        F.y = I.y + F.col0;
+        F.dinv = I.dinv + F.col0;
+        F.rw = PD.rows + S.sn_rowofs[k] + F.c;
+        F.done = (const int*)((const char*)I.rs + offsetof(RefineState, done));
+        F.ch0 = S.ch_ptr[k];
+        F.nch = S.ch_ptr[k + 1] - S.ch_ptr[k];
+        for (int j = 0; j < 2 && j < F.nch; j++) {
+            const int ch = S.ch_list[F.ch0 + j], cc = S.sn_ncol[ch];
+            F.cuc[j] = S.sn_nrow[ch] - cc;
+            F.cnb[j] = S.rel_np[ch];
+            F.cU[j] = I.U + S.sn_uofs[ch];
+            F.cV[j] = I.V + S.sn_vofs[ch];
+            F.crl[j] = PD.rel + S.sn_rowofs[ch] + cc;
+        }
+        F.inst = q;
+        F.id = k;
+    }
     for (int q = 0; q < ninst; q++) {
         const Symbolic& S = *s[q];
         for (int i = 0; i < S.n; i += kBlock) nb.push_back(WorkItem{q, i});
@@ -400,6 +437,7 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     struct Piece { void* dst; const void* src; size_t bytes; } pieces[] = {
         {dinsts, hinst.data(), (size_t)ninst * sizeof(InstDev)},
         {snitems, sn.data(), sn.size() * sizeof(WorkItem)},
+        {fdesc, fd.data(), fd.size() * sizeof(FrontDesc)},
         {nitems, nb.data(), nb.size() * sizeof(WorkItem)},
         {mitems, mb.data(), mb.size() * sizeof(WorkItem)},
         {kitems, kb.data(), kb.size() * sizeof(WorkItem)},
@@ -488,12 +526,11 @@ kkt_status Engine::refactor(const Calls& C, hipStream_t st) {
     TL(KKT_PHASE_CONTROL, launch_status_init(status, ninst, st));
     if (C.ss) TL(KKT_PHASE_ASSEMBLE, launch_jscale(di(), C, jitems, n_jitems, st));
     TL(KKT_PHASE_ASSEMBLE, launch_assemble(di(), C, kitems, n_kitems, st));
-    const WorkItem* items = snitems;
     if (queue_sched) {
         const DepLists D = deps();
         // counters, ticket and the error latch (the latch is cleared only here)
         TL(KKT_PHASE_CONTROL, launch_fill_i32(dep_ctr, 0, 3 * (int64_t)D.nitems + 2, st));
-        TL(KKT_PHASE_FACTOR, launch_factor_queue(di(), items, D, std::min(D.nitems, 512), lds_factor, st));
+        TL(KKT_PHASE_FACTOR, launch_factor_queue(di(), fdesc, D, std::min(D.nitems, 512), lds_factor, st));
     } else {
         // A level with few fronts leaves most compute units idle: its update
         // matrices then go to a launch of their own with one workgroup per
@@ -501,7 +538,7 @@ kkt_status Engine::refactor(const Calls& C, hipStream_t st) {
         for (size_t l = 0; l + 1 < lvl_ptr.size(); l++) {
             const int nf = lvl_ptr[l + 1] - lvl_ptr[l];
             const bool split = split_update && nf < kSplitMaxFronts;
-            TL(KKT_PHASE_FACTOR, launch_factor(di(), items + lvl_ptr[l], nf, lds_factor, split ? 0 : 1, st));
+            TL(KKT_PHASE_FACTOR, launch_factor(di(), fdesc + lvl_ptr[l], nf, lds_factor, split ? 0 : 1, st));
             if (split) TL(KKT_PHASE_FACTOR, launch_update(di(), upitems + up_ptr[l], up_ptr[l + 1] - up_ptr[l], st));
         }
     }
@@ -516,23 +553,22 @@ kkt_status Engine::refactor(const Calls& C, hipStream_t st) {
 }
 
 void Engine::sweeps(hipStream_t st, int skip_done) {
-    const WorkItem* items = snitems;
     if (queue_sched) {
         const DepLists D = deps();
         TL(KKT_PHASE_CONTROL, launch_fill_i32(dep_ctr, 0, 3 * (int64_t)D.nitems + 1, st));
-        TL(KKT_PHASE_FWD, launch_sweeps_queue(di(), items, D, std::min(2 * D.nitems, 1024), lds_solve, skip_done, st));
+        TL(KKT_PHASE_FWD, launch_sweeps_queue(di(), fdesc, D, std::min(2 * D.nitems, 1024), lds_solve, skip_done, st));
         return;
     }
     const int nl = (int)lvl_ptr.size() - 1;
     for (int l = 0; l < nl; l++)
         for (int k = sw_lvl[l]; k < sw_lvl[l + 1]; k++) {
             const SweepPart& P = sw_part[k];
-            TL(KKT_PHASE_FWD, launch_fwd(di(), items + P.begin, P.count, P.lds, skip_done, st));
+            TL(KKT_PHASE_FWD, launch_fwd(di(), fdesc + P.begin, P.count, P.lds, skip_done, st));
         }
     for (int l = nl - 1; l >= 0; l--)
         for (int k = sw_lvl[l]; k < sw_lvl[l + 1]; k++) {
             const SweepPart& P = sw_part[k];
-            TL(KKT_PHASE_BWD, launch_bwd(di(), items + P.begin, P.count, P.lds, skip_done, st));
+            TL(KKT_PHASE_BWD, launch_bwd(fdesc + P.begin, P.count, P.lds, skip_done, st));
         }
 }
 

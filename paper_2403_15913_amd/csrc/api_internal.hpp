@@ -81,6 +81,7 @@ struct Engine {
     CgState* cg = nullptr;
     InstDev* dinsts = nullptr;
     WorkItem *snitems = nullptr, *nitems = nullptr, *mitems = nullptr, *kitems = nullptr, *jitems = nullptr;
+    FrontDesc* fdesc = nullptr;                     // one per front work item (same order as snitems)
     int *dep_parent = nullptr, *dep_nchild = nullptr, *dep_ctr = nullptr;  // queue scheduling
     StripItem* upitems = nullptr;                   // update-matrix strips by level (level schedule)
     std::vector<int> up_ptr;

@@ -87,6 +87,28 @@ struct InstDev {
     CgState* cg;
 };
 
+// One per front work item, in launch order: what a front's kernels read
+// first, as absolute addresses, so its first data loads wait for this record
+// alone instead of a chain of descriptor lookups. The first two children are
+// inline; later children are read from the pattern arrays.
+struct FrontDesc {
+    const double* kv;       // original entries of K in the front
+    const int* kl;          // their panel places (column << 16 | row)
+    double* L;              // stored panel
+    double* U;              // update matrix (u x u)
+    double* V;              // update vector (u)
+    double* y;              // work vector at the front's first column
+    double* dinv;           // pivot reciprocals at the front's first column
+    const int* rw;          // rows of the update part (instance numbering)
+    const int* done;        // the instance's refinement stop flag
+    const double* cU[2];    // first two children: update matrices,
+    const double* cV[2];    //   update vectors,
+    const int* crl[2];      //   relative rows of their update parts,
+    int cuc[2], cnb[2];     //   update sizes, and rows mapping into this front's columns
+    int r, c, col0, nk;     // rows, columns, first column, entries of K
+    int nch, ch0, inst, id; // children, first child in ch_list, instance, supernode
+};
+
 struct WorkItem {
     int inst;
     int id;   // supernode, or first row of a block

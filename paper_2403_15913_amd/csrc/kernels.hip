@@ -278,14 +278,15 @@ __device__ inline void tri_tile(int t, int tj0, int nb, int& ti, int& tj) {
 constexpr int kFactorThreads = 512;
 static_assert(kFactorThreads == 512, "the panel schedule assumes eight waves");
 
-__device__ __forceinline__ void factor_front(const InstDev& I, const int s, double* __restrict__ P, double* invd,
-                                             const bool fused_update, const bool fused_panel) {
+__device__ __forceinline__ void factor_front(const InstDev& I, const FrontDesc& F, double* __restrict__ P,
+                                             double* invd, const bool fused_update, const bool fused_panel) {
     const PatDev& T = I.P;
-    const int c = __builtin_amdgcn_readfirstlane(T.sn_ncol[s]), r = __builtin_amdgcn_readfirstlane(T.sn_nrow[s]);
-    const int u = r - c, col0 = __builtin_amdgcn_readfirstlane(T.sn_col0[s]);
+    const int s = F.id;
+    const int c = F.c, r = F.r;
+    const int u = r - c, col0 = F.col0;
     // descriptor fields used inside the loops below, read once
     int* const status = I.status;
-    double* const dinv = I.dinv + col0;
+    double* const dinv = F.dinv;
     const double* const Ubase = I.U;
     const int* const chl = T.ch_list;
     const int* const sn_ncol = T.sn_ncol;
@@ -294,7 +295,7 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
     const int64_t* const sn_uofs = T.sn_uofs;
     const int* const rel = T.rel;
     const int64_t* const sn_rowofs = T.sn_rowofs;
-    const int ch0 = __builtin_amdgcn_readfirstlane(T.ch_ptr[s]), ch1 = __builtin_amdgcn_readfirstlane(T.ch_ptr[s + 1]);
+    const int ch0 = F.ch0, ch1 = F.ch0 + F.nch;
     const int rp = rup16(r), cp = rup16(c);
     const int ld = r | 1;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -317,15 +318,23 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
         double v[EU];
         int ra[EU], rb[EU];  // relative row / column; row < 0 (as ~row): not kept
     };
-    auto child_at = [&](const int q) {
+    // child k (0-based): the first two from the front descriptor
+    auto child_at = [&](const int k) {
         Child C;
-        const int ch = __builtin_amdgcn_readfirstlane(chl[q]);
-        const int cc = __builtin_amdgcn_readfirstlane(sn_ncol[ch]);
-        C.uc = __builtin_amdgcn_readfirstlane(sn_nrow[ch]) - cc;
-        C.nb = __builtin_amdgcn_readfirstlane(rel_np[ch]);
+        if (k < 2) {
+            C.uc = k ? F.cuc[1] : F.cuc[0];
+            C.nb = k ? F.cnb[1] : F.cnb[0];
+            C.Uc = k ? F.cU[1] : F.cU[0];
+            C.rl = k ? F.crl[1] : F.crl[0];
+        } else {
+            const int ch = __builtin_amdgcn_readfirstlane(chl[ch0 + k]);
+            const int cc = __builtin_amdgcn_readfirstlane(sn_ncol[ch]);
+            C.uc = __builtin_amdgcn_readfirstlane(sn_nrow[ch]) - cc;
+            C.nb = __builtin_amdgcn_readfirstlane(rel_np[ch]);
+            C.Uc = Ubase + sn_uofs[ch];
+            C.rl = rel + sn_rowofs[ch] + cc;
+        }
         C.tot = C.nb * C.uc;
-        C.Uc = Ubase + sn_uofs[ch];
-        C.rl = rel + sn_rowofs[ch] + cc;
         return C;
     };
     // (column, row) of the flat index q0 + k*nt by stepping, not dividing
@@ -384,13 +393,12 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
     const int nch = ch1 - ch0;
     Child C0 = {}, C1 = {};
     ExtBatch B0, B1;
-    if (nch > 0) C0 = child_at(ch0);
-    if (nch > 1) C1 = child_at(ch0 + 1);
+    if (nch > 0) C0 = child_at(0);
+    if (nch > 1) C1 = child_at(1);
     const bool pre0 = nch > 0 && C0.tot > 0, pre1 = nch > 1 && C1.tot > 0;
-    const int64_t e0 = T.k_snptr[s];
-    const int nk = (int)(T.k_snptr[s + 1] - e0);
-    const int* __restrict__ kl = T.k_loc + e0;
-    const double* __restrict__ kv = I.kval + e0;
+    const int nk = F.nk;
+    const int* __restrict__ kl = F.kl;
+    const double* __restrict__ kv = F.kv;
     constexpr int KU = 8;
     double kvv[KU];
     int klv[KU];
@@ -422,7 +430,7 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
     if (nch > 0) ext_child(C0, B0, pre0);
     if (nch > 1) ext_child(C1, B1, pre1);
     for (int q = 2; q < nch; q++) {
-        const Child C = child_at(ch0 + q);
+        const Child C = child_at(q);
         ext_child(C, B0, false);
     }
 
@@ -644,10 +652,10 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
     }
 
     // panel -> HBM: same layout, contiguous 16-byte stores
-    copy_vec(I.L + T.sn_lofs[s], P, even_up(ld * c), tid, nt);
+    copy_vec(F.L, P, even_up(ld * c), tid, nt);
     if (u == 0 || !fused_update) return;
     // update matrix U = -L21 L21^T (lower part) on the matrix cores
-    double* __restrict__ Us = I.U + T.sn_uofs[s];
+    double* __restrict__ Us = F.U;
     const int nbu = (u + 15) >> 4;
     const int ntu = nbu * (nbu + 1) / 2;
     const int K4 = (c + 3) & ~3;
@@ -664,12 +672,11 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
     }
     __syncthreads();
     // children's entries that pass through to the update matrix
-    for (int q = ch0; q < ch1; q++) {
-        const int ch = __builtin_amdgcn_readfirstlane(chl[q]);
-        const int cc = __builtin_amdgcn_readfirstlane(sn_ncol[ch]);
-        const int uc = __builtin_amdgcn_readfirstlane(sn_nrow[ch]) - cc, nb = __builtin_amdgcn_readfirstlane(rel_np[ch]);
-        const double* __restrict__ Uc = Ubase + sn_uofs[ch];
-        const int* __restrict__ rl = rel + sn_rowofs[ch] + cc;
+    for (int q = 0; q < nch; q++) {
+        const Child C = child_at(q);
+        const int uc = C.uc, nb = C.nb;
+        const double* __restrict__ Uc = C.Uc;
+        const int* __restrict__ rl = C.rl;
         const int64_t base = (int64_t)nb * uc;
         const int tot = (uc - nb) * uc;
         constexpr int UNR = 16;
@@ -728,11 +735,11 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const int s, doub
 }
 
 __global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __restrict__ insts,
-                                                          const WorkItem* __restrict__ items, int fused_update) {
+                                                          const FrontDesc* __restrict__ fds, int fused_update) {
     extern __shared__ __align__(16) double P[];
     __shared__ double invd[16];
-    const WorkItem it = items[blockIdx.x];
-    factor_front(insts[it.inst], it.id, P, invd, fused_update != 0, true);
+    const FrontDesc& F = fds[blockIdx.x];
+    factor_front(insts[F.inst], F, P, invd, fused_update != 0, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -925,7 +932,7 @@ __device__ inline int take_ticket(int* ticket, int* slot) {
 }
 
 __global__ __launch_bounds__(kFactorThreads) void k_factor_queue(const InstDev* __restrict__ insts,
-                                                                const WorkItem* __restrict__ items, DepLists D) {
+                                                                const FrontDesc* __restrict__ fds, DepLists D) {
     extern __shared__ __align__(16) double P[];
     __shared__ double invd[16];
     __shared__ int slot;
@@ -937,8 +944,8 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor_queue(const InstDev* 
         if (sched_wave()) wait_at_least(D.cnt + t, need, D.err);
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const WorkItem it = items[t];
-        factor_front(insts[it.inst], it.id, P, invd, true, false);
+        const FrontDesc& F = fds[t];
+        factor_front(insts[F.inst], F, P, invd, true, false);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
         if (sched_wave() && par >= 0) publish_add(D.cnt + par);
@@ -1011,10 +1018,11 @@ __device__ inline void tri_bwd_wave(const double* __restrict__ P, int ld, int c,
 // threads. Reciprocals of the pivots come from the factorisation.
 constexpr int kSolveThreads = 256;
 
-__device__ __forceinline__ void fwd_front(const InstDev& I, const int s, double* __restrict__ sh) {
+__device__ __forceinline__ void fwd_front(const InstDev& I, const FrontDesc& F, double* __restrict__ sh) {
     const PatDev& T = I.P;
-    const int c = __builtin_amdgcn_readfirstlane(T.sn_ncol[s]), r = __builtin_amdgcn_readfirstlane(T.sn_nrow[s]);
-    const int u = r - c, col0 = __builtin_amdgcn_readfirstlane(T.sn_col0[s]);
+    const int s = F.id;
+    const int c = F.c, r = F.r;
+    const int u = r - c;
     const int ld = r | 1;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
     double* P = sh;
@@ -1026,28 +1034,35 @@ __device__ __forceinline__ void fwd_front(const InstDev& I, const int s, double*
     // front's columns (c <= 128 < threads), and the first entries of the
     // first two children's update vectors with their relative indices.
     constexpr int PU = 32;
-    const double2* __restrict__ s2 = (const double2*)(I.L + T.sn_lofs[s]);
+    const double2* __restrict__ s2 = (const double2*)F.L;
     double2* d2 = (double2*)P;
     const int n2 = even_up(ld * c) >> 1;
     double2 pv[PU];
 #pragma unroll
     for (int k = 0; k < PU; k++) pv[k] = s2[min(tid + k * nt, n2 - 1)];
     const int tc = min(tid, c - 1);
-    double wy = I.y[col0 + tc], wd = I.dinv[col0 + tc];
-    const int ch0 = __builtin_amdgcn_readfirstlane(T.ch_ptr[s]), ch1 = __builtin_amdgcn_readfirstlane(T.ch_ptr[s + 1]);
-    const int nch = ch1 - ch0;
+    double wy = F.y[tc], wd = F.dinv[tc];
+    const int ch0 = F.ch0, nch = F.nch, ch1 = ch0 + nch;
     struct VChild {
         const double* Vc;
         const int* rl;
         int uc;
     };
+    // child at ch_list position q; the first two from the front descriptor
     auto vchild = [&](const int q) {
         VChild C;
-        const int ch = __builtin_amdgcn_readfirstlane(T.ch_list[q]);
-        const int cc = __builtin_amdgcn_readfirstlane(T.sn_ncol[ch]);
-        C.uc = __builtin_amdgcn_readfirstlane(T.sn_nrow[ch]) - cc;
-        C.Vc = I.V + T.sn_vofs[ch];
-        C.rl = T.rel + T.sn_rowofs[ch] + cc;
+        const int k = q - ch0;
+        if (k < 2) {
+            C.uc = k ? F.cuc[1] : F.cuc[0];
+            C.Vc = k ? F.cV[1] : F.cV[0];
+            C.rl = k ? F.crl[1] : F.crl[0];
+        } else {
+            const int ch = __builtin_amdgcn_readfirstlane(T.ch_list[q]);
+            const int cc = __builtin_amdgcn_readfirstlane(T.sn_ncol[ch]);
+            C.uc = __builtin_amdgcn_readfirstlane(T.sn_nrow[ch]) - cc;
+            C.Vc = I.V + T.sn_vofs[ch];
+            C.rl = T.rel + T.sn_rowofs[ch] + cc;
+        }
         return C;
     };
     VChild V0 = {}, V1 = {};
@@ -1156,35 +1171,36 @@ __device__ __forceinline__ void fwd_front(const InstDev& I, const int s, double*
         }
         __syncthreads();
     }
-    double* __restrict__ Vs = I.V + T.sn_vofs[s];
+    double* __restrict__ Vs = F.V;
     for (int i = tid; i < u; i += nt) Vs[i] = va[i];
-    for (int t = tid; t < c; t += nt) I.y[col0 + t] = w[t];
+    for (int t = tid; t < c; t += nt) F.y[t] = w[t];
 }
 
-__device__ __forceinline__ void bwd_front(const InstDev& I, const int s, double* __restrict__ sh) {
-    const PatDev& T = I.P;
-    const int c = __builtin_amdgcn_readfirstlane(T.sn_ncol[s]), r = __builtin_amdgcn_readfirstlane(T.sn_nrow[s]);
-    const int u = r - c, col0 = __builtin_amdgcn_readfirstlane(T.sn_col0[s]);
+__device__ __forceinline__ void bwd_front(const FrontDesc& F, double* __restrict__ sh) {
+    const int s = F.id;
+    const int c = F.c, r = F.r;
+    const int u = r - c;
+    double* const yb = F.y - F.col0;  // the instance's work vector
     const int ld = r | 1;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
     double* P = sh;
     double* t = sh + even_up(ld * c);
     double* zu = t + c;
     double* dv = zu + u;
-    const int* __restrict__ rw = T.rows + T.sn_rowofs[s] + c;
+    const int* __restrict__ rw = F.rw;
     // The update rows' indices are loaded first, so the gather of their
     // values waits only for them while the panel loads stay in flight.
     constexpr int PU = 32;
     int ri = u > 0 ? rw[min(tid, u - 1)] : 0;
-    const double2* __restrict__ s2 = (const double2*)(I.L + T.sn_lofs[s]);
+    const double2* __restrict__ s2 = (const double2*)F.L;
     double2* d2 = (double2*)P;
     const int n2 = even_up(ld * c) >> 1;
     double2 pv[PU];
 #pragma unroll
     for (int k = 0; k < PU; k++) pv[k] = s2[min(tid + k * nt, n2 - 1)];
-    double wd = I.dinv[col0 + min(tid, c - 1)];
+    double wd = F.dinv[min(tid, c - 1)];
     pin(ri);
-    double zy = u > 0 ? I.y[ri] : 0.0;
+    double zy = u > 0 ? yb[ri] : 0.0;
 #pragma unroll
     for (int k = 0; k < PU; k++) pin(pv[k]);
     pin(wd);
@@ -1194,11 +1210,11 @@ __device__ __forceinline__ void bwd_front(const InstDev& I, const int s, double*
         if (tid + k * nt < n2) d2[tid + k * nt] = pv[k];
     for (int q = tid + PU * nt; q < n2; q += nt) d2[q] = s2[q];
     if (tid < u) zu[tid] = zy;
-    for (int i = tid + nt; i < u; i += nt) zu[i] = I.y[rw[i]];
+    for (int i = tid + nt; i < u; i += nt) zu[i] = yb[rw[i]];
     if (tid < c) dv[tid] = wd;
     __syncthreads();
     for (int k = tid; k < c; k += nt) {
-        double sum = I.y[col0 + k];
+        double sum = F.y[k];
         const double* col = P + k * ld + c;
 #pragma unroll 8
         for (int i = 0; i < u; i++) sum -= col[i] * zu[i];
@@ -1209,27 +1225,24 @@ __device__ __forceinline__ void bwd_front(const InstDev& I, const int s, double*
         double x0 = lane < c ? t[lane] : 0.0;
         double x1 = lane + 64 < c ? t[lane + 64] : 0.0;
         tri_bwd_wave(P, ld, c, dv, x0, x1, lane);
-        if (lane < c) I.y[col0 + lane] = x0;
-        if (lane + 64 < c) I.y[col0 + lane + 64] = x1;
+        if (lane < c) F.y[lane] = x0;
+        if (lane + 64 < c) F.y[lane + 64] = x1;
     }
 }
 
 __global__ __launch_bounds__(kSolveThreads) void k_fwd(const InstDev* __restrict__ insts,
-                                                      const WorkItem* __restrict__ items, int skip_done) {
+                                                      const FrontDesc* __restrict__ fds, int skip_done) {
     extern __shared__ __align__(16) double sh[];
-    const WorkItem it = items[blockIdx.x];
-    const InstDev& I = insts[it.inst];
-    if (skip_done && I.rs->done) return;
-    fwd_front(I, it.id, sh);
+    const FrontDesc& F = fds[blockIdx.x];
+    if (skip_done && *F.done) return;
+    fwd_front(insts[F.inst], F, sh);
 }
 
-__global__ __launch_bounds__(kSolveThreads) void k_bwd(const InstDev* __restrict__ insts,
-                                                      const WorkItem* __restrict__ items, int skip_done) {
+__global__ __launch_bounds__(kSolveThreads) void k_bwd(const FrontDesc* __restrict__ fds, int skip_done) {
     extern __shared__ __align__(16) double sh[];
-    const WorkItem it = items[blockIdx.x];
-    const InstDev& I = insts[it.inst];
-    if (skip_done && I.rs->done) return;
-    bwd_front(I, it.id, sh);
+    const FrontDesc& F = fds[blockIdx.x];
+    if (skip_done && *F.done) return;
+    bwd_front(F, sh);
 }
 
 // Both sweeps in one launch: tickets 0..N-1 are the forward sweep in
@@ -1237,7 +1250,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_bwd(const InstDev* __restrict
 // front's backward step waits for its parent's (a root waits for its own
 // forward step, the last of its tree).
 __global__ __launch_bounds__(kSolveThreads) void k_sweeps_queue(const InstDev* __restrict__ insts,
-                                                               const WorkItem* __restrict__ items, DepLists D,
+                                                               const FrontDesc* __restrict__ fds, DepLists D,
                                                                int skip_done) {
     extern __shared__ __align__(16) double sh[];
     __shared__ int slot;
@@ -1255,12 +1268,11 @@ __global__ __launch_bounds__(kSolveThreads) void k_sweeps_queue(const InstDev* _
         }
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const WorkItem it = items[k];
-        const InstDev& I = insts[it.inst];
-        const int idle = skip_done ? __builtin_amdgcn_readfirstlane(I.rs->done) : 0;
+        const FrontDesc& F = fds[k];
+        const int idle = skip_done ? __builtin_amdgcn_readfirstlane(*F.done) : 0;
         if (!idle) {
-            if (fwd) fwd_front(I, it.id, sh);
-            else bwd_front(I, it.id, sh);
+            if (fwd) fwd_front(insts[F.inst], F, sh);
+            else bwd_front(F, sh);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
@@ -1676,26 +1688,26 @@ void launch_jscale(const InstDev* insts, const Calls& C, const WorkItem* items, 
 void launch_assemble(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st) {
     if (nitems > 0) k_assemble<<<nitems, kBlock, 0, st>>>(insts, C, items);
 }
-void launch_factor(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, int fused_update,
+void launch_factor(const InstDev* insts, const FrontDesc* fds, int nitems, size_t lds, int fused_update,
                    hipStream_t st) {
-    if (nitems > 0) k_factor<<<nitems, kFactorThreads, lds, st>>>(insts, items, fused_update);
+    if (nitems > 0) k_factor<<<nitems, kFactorThreads, lds, st>>>(insts, fds, fused_update);
 }
 void launch_update(const InstDev* insts, const StripItem* items, int nitems, hipStream_t st) {
     if (nitems > 0) k_update<<<nitems, kUpdThreads, 0, st>>>(insts, items);
 }
-void launch_factor_queue(const InstDev* insts, const WorkItem* items, const DepLists& D, int grid, size_t lds,
+void launch_factor_queue(const InstDev* insts, const FrontDesc* fds, const DepLists& D, int grid, size_t lds,
                          hipStream_t st) {
-    if (D.nitems > 0) k_factor_queue<<<grid, kFactorThreads, lds, st>>>(insts, items, D);
+    if (D.nitems > 0) k_factor_queue<<<grid, kFactorThreads, lds, st>>>(insts, fds, D);
 }
-void launch_sweeps_queue(const InstDev* insts, const WorkItem* items, const DepLists& D, int grid, size_t lds,
+void launch_sweeps_queue(const InstDev* insts, const FrontDesc* fds, const DepLists& D, int grid, size_t lds,
                          int skip_done, hipStream_t st) {
-    if (D.nitems > 0) k_sweeps_queue<<<grid, kSolveThreads, lds, st>>>(insts, items, D, skip_done);
+    if (D.nitems > 0) k_sweeps_queue<<<grid, kSolveThreads, lds, st>>>(insts, fds, D, skip_done);
 }
-void launch_fwd(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, int skip_done, hipStream_t st) {
-    if (nitems > 0) k_fwd<<<nitems, kSolveThreads, lds, st>>>(insts, items, skip_done);
+void launch_fwd(const InstDev* insts, const FrontDesc* fds, int nitems, size_t lds, int skip_done, hipStream_t st) {
+    if (nitems > 0) k_fwd<<<nitems, kSolveThreads, lds, st>>>(insts, fds, skip_done);
 }
-void launch_bwd(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, int skip_done, hipStream_t st) {
-    if (nitems > 0) k_bwd<<<nitems, kSolveThreads, lds, st>>>(insts, items, skip_done);
+void launch_bwd(const FrontDesc* fds, int nitems, size_t lds, int skip_done, hipStream_t st) {
+    if (nitems > 0) k_bwd<<<nitems, kSolveThreads, lds, st>>>(fds, skip_done);
 }
 void launch_perm_in(const InstDev* insts, const Calls& C, const WorkItem* rows, int nitems, int mode, hipStream_t st) {
     if (nitems > 0) k_perm_in<<<nitems, kBlock, 0, st>>>(insts, C, rows, mode);

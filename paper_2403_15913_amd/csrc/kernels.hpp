@@ -66,16 +66,16 @@ void launch_fill_i32(int* p, int v, int64_t n, hipStream_t st);
 void launch_status_init(int* status, int ninst, hipStream_t st);
 void launch_jscale(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st);
 void launch_assemble(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st);
-void launch_factor(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, int fused_update,
+void launch_factor(const InstDev* insts, const FrontDesc* fds, int nitems, size_t lds, int fused_update,
                    hipStream_t st);
 // update matrices by 16-column strips (after the factor launch of the same level)
 void launch_update(const InstDev* insts, const StripItem* items, int nitems, hipStream_t st);
-void launch_factor_queue(const InstDev* insts, const WorkItem* items, const DepLists& D, int grid, size_t lds,
+void launch_factor_queue(const InstDev* insts, const FrontDesc* fds, const DepLists& D, int grid, size_t lds,
                          hipStream_t st);
-void launch_sweeps_queue(const InstDev* insts, const WorkItem* items, const DepLists& D, int grid, size_t lds,
+void launch_sweeps_queue(const InstDev* insts, const FrontDesc* fds, const DepLists& D, int grid, size_t lds,
                          int skip_done, hipStream_t st);
-void launch_fwd(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, int skip_done, hipStream_t st);
-void launch_bwd(const InstDev* insts, const WorkItem* items, int nitems, size_t lds, int skip_done, hipStream_t st);
+void launch_fwd(const InstDev* insts, const FrontDesc* fds, int nitems, size_t lds, int skip_done, hipStream_t st);
+void launch_bwd(const FrontDesc* fds, int nitems, size_t lds, int skip_done, hipStream_t st);
 
 // permutation modes
 enum { PIN_B = 0, PIN_R = 1, PIN_TN = 2, PIN_FG = 3 };
