@@ -316,7 +316,8 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const FrontDesc& 
     };
     struct ExtBatch {
         double v[EU];
-        int ra[EU], rb[EU];  // relative row / column; row < 0 (as ~row): not kept
+        int ra[EU], rb[EU];  // relative row / column
+        unsigned keep;       // bit k: entry k is in range and in the lower part
     };
     // child k (0-based): the first two from the front descriptor
     auto child_at = [&](const int k) {
@@ -342,13 +343,15 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const FrontDesc& 
         const int uc = C.uc, tot = C.tot;
         const int db = nt / uc, da = nt - db * uc;
         int bq = q0 / uc, aq = q0 - bq * uc;
+        // the keep flags come from the indices alone, so no load waits for
+        // another before all of them are issued
+        B.keep = 0;
 #pragma unroll
         for (int k = 0; k < EU; k++) {
             const int qa = q0 + k * nt;
-            const bool keep = qa < tot && aq >= bq;
+            B.keep |= (qa < tot && aq >= bq) ? 1u << k : 0u;
             B.v[k] = C.Uc[min(qa, tot - 1)];
-            const int ri = C.rl[qa < tot ? aq : uc - 1];
-            B.ra[k] = keep ? ri : ~ri;
+            B.ra[k] = C.rl[qa < tot ? aq : uc - 1];
             B.rb[k] = C.rl[min(bq, C.nb - 1)];
             aq += da;
             bq += db;
@@ -372,12 +375,12 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const FrontDesc& 
         int dst[EU];
 #pragma unroll
         for (int k = 0; k < EU; k++) {
-            dst[k] = B.rb[k] * ld + (B.ra[k] >= 0 ? B.ra[k] : ~B.ra[k]);
+            dst[k] = B.rb[k] * ld + B.ra[k];
             cur[k] = P[dst[k]];
         }
 #pragma unroll
         for (int k = 0; k < EU; k++)
-            if (B.ra[k] >= 0) P[dst[k]] = cur[k] + B.v[k];
+            if ((B.keep >> k) & 1u) P[dst[k]] = cur[k] + B.v[k];
     };
     // all batches of child C; the first one is already loaded when pre
     auto ext_child = [&](const Child& C, ExtBatch& B, const bool pre) {
