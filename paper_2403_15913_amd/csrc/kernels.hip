@@ -535,7 +535,7 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const FrontDesc& 
             }
         }
     };
-    // Column block kb of the panel in one pass by each of waves 0-3: every
+    // Column block kb of the panel in one pass by each panel wave (0-3): every
     // 16-lane row of a wave holds the diagonal block (lane i: row j0+i) and
     // runs the pivot chain on it, and each lane also carries one row below
     // the block (wave w, lane l: row j0+16+64w+l). Step j scales column j
@@ -619,20 +619,24 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const FrontDesc& 
         }
     };
     // Right-looking blocked Cholesky with one block of look-ahead: column
-    // block kb+1 takes block kb's update first; then waves 0-3 factor
-    // column block kb+1 while waves 4-7 apply block kb's update to the
-    // columns beyond it. Every entry still receives the block updates in
+    // block kb+1 takes block kb's update first; then the first waves (up to
+    // four) factor column block kb+1 while the others apply block kb's
+    // update to the columns beyond it. Every entry still receives the block updates in
     // block order. Fronts taller than waves 0-3 can cover, and the
     // persistent queue kernel, take the pivot chain by wave 0 and a
     // separate triangular solve of the rows below (same arithmetic).
     if (fused_panel && r <= 16 + 4 * 64) {
-        if (wave < 4) panel_block(0);
+        // panel waves: one per 64 rows below the diagonal block (at least
+        // one), the rest take the look-ahead update
+        auto npanel = [&](const int kb) { return min(4, max(1, (r - (kb << 4) - 16 + 63) >> 6)); };
+        if (wave < npanel(0)) panel_block(0);
         __syncthreads();
         for (int kb = 0; kb + 1 < nbc; kb++) {
             update_tiles(kb, kb + 1, kb + 2, wave, nwave);
             __syncthreads();
-            if (wave < 4) panel_block(kb + 1);
-            else update_tiles(kb, kb + 2, nbc, wave - 4, nwave - 4);
+            const int np = npanel(kb + 1);
+            if (wave < np) panel_block(kb + 1);
+            else update_tiles(kb, kb + 2, nbc, wave - np, nwave - np);
             __syncthreads();
         }
     } else {
