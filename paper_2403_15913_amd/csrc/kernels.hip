@@ -1036,17 +1036,36 @@ __device__ __forceinline__ void fwd_front(const InstDev& I, const FrontDesc& F, 
     double* w = sh + even_up(ld * c);
     double* va = w + c;
     double* dv = va + u;
-    // Every load of the prologue is issued before the first wait: the first
-    // batch of the panel, the right-hand side and pivot reciprocals of the
-    // front's columns (c <= 128 < threads), and the first entries of the
-    // first two children's update vectors with their relative indices.
-    constexpr int PU = 32;
+    // The panel is staged one 16-column block at a time: block b is one
+    // contiguous range of 8 ld double2 in HBM and in LDS. Block 0 comes
+    // with the prologue; block kb+1 is loaded into registers while phase
+    // kb computes and stored before the phase's barrier. Every load of the
+    // prologue is issued before the first wait: panel block 0, the
+    // right-hand side and pivot reciprocals of the front's columns
+    // (c <= 128 < threads), and the first entries of the first two
+    // children's update vectors with their relative indices.
+    constexpr int BU = 8;  // double2 per thread and block in registers (ld < 256)
     const double2* __restrict__ s2 = (const double2*)F.L;
     double2* d2 = (double2*)P;
     const int n2 = even_up(ld * c) >> 1;
-    double2 pv[PU];
+    const int bw2 = 8 * ld;
+    double2 pb[BU];
+    auto blk_load = [&](const int bk) {
+        const int q0 = bk * bw2, q1 = min(q0 + bw2, n2);
 #pragma unroll
-    for (int k = 0; k < PU; k++) pv[k] = s2[min(tid + k * nt, n2 - 1)];
+        for (int k = 0; k < BU; k++) pb[k] = s2[min(q0 + tid + k * nt, q1 - 1)];
+    };
+    auto blk_store = [&](const int bk) {
+        const int q0 = bk * bw2, q1 = min(q0 + bw2, n2);
+#pragma unroll
+        for (int k = 0; k < BU; k++) pin(pb[k]);
+#pragma unroll
+        for (int k = 0; k < BU; k++)
+            if (q0 + tid + k * nt < q1) d2[q0 + tid + k * nt] = pb[k];
+        for (int q = q0 + tid + BU * nt; q < q1; q += nt) d2[q] = s2[q];
+    };
+    const int nblk = (c + 15) >> 4;
+    blk_load(0);
     const int tc = min(tid, c - 1);
     double wy = F.y[tc], wd = F.dinv[tc];
     const int ch0 = F.ch0, nch = F.nch, ch1 = ch0 + nch;
@@ -1087,24 +1106,20 @@ __device__ __forceinline__ void fwd_front(const InstDev& I, const FrontDesc& F, 
         v1 = V1.Vc[a];
         r1 = V1.rl[a];
     }
-#pragma unroll
-    for (int k = 0; k < PU; k++) pin(pv[k]);
     pin(wy);
     pin(wd);
     pin(v0);
     pin(v1);
     pin(r0);
     pin(r1);
-#pragma unroll
-    for (int k = 0; k < PU; k++)
-        if (tid + k * nt < n2) d2[tid + k * nt] = pv[k];
-    for (int q = tid + PU * nt; q < n2; q += nt) d2[q] = s2[q];
+    blk_store(0);
     if (tid < c) {
         w[tid] = wy;
         dv[tid] = wd;
     }
     for (int t = tid; t < u; t += nt) va[t] = 0.0;
     __syncthreads();
+    if (nblk > 1) blk_load(1);
     // children's update vectors, child by child (entries of one child are
     // distinct; two children can add into the same entry)
     auto add_child = [&](const VChild& C, const bool pre, const double vp, const int rp) {
@@ -1126,7 +1141,6 @@ __device__ __forceinline__ void fwd_front(const InstDev& I, const FrontDesc& F, 
     // broadcasts); meanwhile the other waves take block kb-1's contribution
     // into every later row (triangle rows past block kb and the update
     // rows). Every row subtracts its terms in ascending column order.
-    const int nblk = (c + 15) >> 4;
     const int wave = tid >> 6;
     for (int kb = 0; kb <= nblk; kb++) {
         const int p0 = (kb - 1) << 4, nprev = min(16, c - p0);
@@ -1176,7 +1190,9 @@ __device__ __forceinline__ void fwd_front(const InstDev& I, const FrontDesc& F, 
                 else va[q - ntr] = acc;
             }
         }
+        if (kb + 1 < nblk) blk_store(kb + 1);
         __syncthreads();
+        if (kb + 2 < nblk) blk_load(kb + 2);
     }
     double* __restrict__ Vs = F.V;
     for (int i = tid; i < u; i += nt) Vs[i] = va[i];
