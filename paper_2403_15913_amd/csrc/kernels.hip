@@ -1024,6 +1024,7 @@ __device__ inline void tri_bwd_wave(const double* __restrict__ P, int ld, int c,
 // solved by one wave with scalar broadcasts, the rectangular part by all
 // threads. Reciprocals of the pivots come from the factorisation.
 constexpr int kSolveThreads = 256;
+static_assert(kSolveThreads == 256, "the sweep work splits assume 256 threads");
 
 __device__ __forceinline__ void fwd_front(const InstDev& I, const FrontDesc& F, double* __restrict__ sh) {
     const PatDev& T = I.P;
@@ -1236,12 +1237,27 @@ __device__ __forceinline__ void bwd_front(const FrontDesc& F, double* __restrict
     for (int i = tid + nt; i < u; i += nt) zu[i] = yb[rw[i]];
     if (tid < c) dv[tid] = wd;
     __syncthreads();
-    for (int k = tid; k < c; k += nt) {
-        double sum = F.y[k];
-        const double* col = P + k * ld + c;
-#pragma unroll 8
-        for (int i = 0; i < u; i++) sum -= col[i] * zu[i];
-        t[k] = sum;
+    // t = y1 - L21^T z: G consecutive lanes per column (G c <= 256 for
+    // c <= 128), each with four running sums over rows g, g + G, ...; a
+    // group's sums are combined in a fixed order
+    {
+        const int lg = c <= 16 ? 4 : c <= 32 ? 3 : c <= 64 ? 2 : 1, G = 1 << lg;
+        const int k = tid >> lg, g = tid & (G - 1);
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        if (k < c) {
+            const double* col = P + k * ld + c;
+            int i = g;
+            for (; i + 3 * G < u; i += 4 * G) {
+                a0 = fma(col[i], zu[i], a0);
+                a1 = fma(col[i + G], zu[i + G], a1);
+                a2 = fma(col[i + 2 * G], zu[i + 2 * G], a2);
+                a3 = fma(col[i + 3 * G], zu[i + 3 * G], a3);
+            }
+            for (; i < u; i += G) a0 = fma(col[i], zu[i], a0);
+        }
+        double part = (a0 + a1) + (a2 + a3);
+        for (int off = G >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off);
+        if (k < c && g == 0) t[k] = F.y[k] - part;
     }
     __syncthreads();
     if (tid < 64) {
