@@ -368,7 +368,7 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         for (int t = lvl_ptr[l]; t < lvl_ptr[l + 1]; t++) {
             const Symbolic& S = *s[sn[t].inst];
             const int u = S.sn_nrow[sn[t].id] - S.sn_ncol[sn[t].id];
-            for (int k = 0; k < (u + 15) / 16; k++) up.push_back(StripItem{sn[t].inst, sn[t].id, k, 0});
+            for (int k = 0; k < (u + 15) / 16; k++) up.push_back(StripItem{sn[t].inst, sn[t].id, k, t});
         }
         up_ptr.push_back((int)up.size());
     }
@@ -539,7 +539,7 @@ kkt_status Engine::refactor(const Calls& C, hipStream_t st) {
             const int nf = lvl_ptr[l + 1] - lvl_ptr[l];
             const bool split = split_update && nf < kSplitMaxFronts;
             TL(KKT_PHASE_FACTOR, launch_factor(di(), fdesc + lvl_ptr[l], nf, lds_factor, split ? 0 : 1, st));
-            if (split) TL(KKT_PHASE_FACTOR, launch_update(di(), upitems + up_ptr[l], up_ptr[l + 1] - up_ptr[l], st));
+            if (split) TL(KKT_PHASE_FACTOR, launch_update(di(), fdesc, upitems + up_ptr[l], up_ptr[l + 1] - up_ptr[l], st));
         }
     }
     if (mode == 2 && j_ofs[ninst] > 0) {

@@ -119,7 +119,7 @@ struct StripItem {
     int inst;
     int id;     // supernode
     int strip;  // first column / 16
-    int pad;
+    int item;   // the front's work item (index into the front descriptors)
 };
 
 }  // namespace kkt

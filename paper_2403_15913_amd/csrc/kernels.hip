@@ -761,28 +761,24 @@ __device__ inline d4 tile_abt_g(const double* __restrict__ Lp, int ld, int i0, i
     const int ia = i0 + lr, jb = j0 + lr;
     const bool va = ia < rlim, vb = jb < rlim;
     const int iac = min(ia, rlim - 1), jbc = min(jb, rlim - 1);
-    const int K4 = (kmax + 3) & ~3;
+    // every column's loads are issued before the first step (kmax <= 128:
+    // at most 32 steps of 4); indices past the last step repeat it, so no
+    // load is predicated, and only the steps below nq run
+    const int nq = (kmax + 3) >> 2;
+    double a[32], b[32];
+#pragma unroll
+    for (int q = 0; q < 32; q++) {
+        const int col = min(4 * min(q, nq - 1) + lk, kmax - 1) * ld;
+        a[q] = Lp[col + iac];
+        b[q] = Lp[col + jbc];
+    }
     d4 acc = {0.0, 0.0, 0.0, 0.0};
-    int kk = 0;
-    for (; kk + 16 <= K4; kk += 16) {
-        double a[4], b[4];
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const int col = min(kk + 4 * q + lk, kmax - 1) * ld;
-            a[q] = Lp[col + iac];
-            b[q] = Lp[col + jbc];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const bool vk = kk + 4 * q + lk < kmax;
+    for (int q = 0; q < 32; q++) {
+        if (q < nq) {
+            const bool vk = 4 * q + lk < kmax;
             acc = mfma_f64_16x16x4(va && vk ? a[q] : 0.0, vb && vk ? b[q] : 0.0, acc);
         }
-    }
-    for (; kk < K4; kk += 4) {
-        const int col = min(kk + lk, kmax - 1) * ld;
-        const double a = Lp[col + iac], b = Lp[col + jbc];
-        const bool vk = kk + lk < kmax;
-        acc = mfma_f64_16x16x4(va && vk ? a : 0.0, vb && vk ? b : 0.0, acc);
     }
     return acc;
 }
@@ -794,17 +790,18 @@ __device__ inline d4 tile_abt_g(const double* __restrict__ Lp, int ld, int i0, i
 // factor kernel's fused path, so the two paths agree bitwise.
 constexpr int kUpdThreads = 256;
 __global__ __launch_bounds__(kUpdThreads) void k_update(const InstDev* __restrict__ insts,
+                                                       const FrontDesc* __restrict__ fds,
                                                        const StripItem* __restrict__ items) {
     __shared__ int srel[kUpdMaxRows];
     const StripItem it = items[blockIdx.x];
-    const InstDev& I = insts[it.inst];
+    const FrontDesc& F = fds[it.item];
+    const InstDev& I = insts[F.inst];
     const PatDev& T = I.P;
-    const int s = it.id;
-    const int c = __builtin_amdgcn_readfirstlane(T.sn_ncol[s]), r = __builtin_amdgcn_readfirstlane(T.sn_nrow[s]);
+    const int c = F.c, r = F.r;
     const int u = r - c, ld = r | 1;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
-    const double* __restrict__ Lp = I.L + T.sn_lofs[s];
-    double* __restrict__ Us = I.U + T.sn_uofs[s];
+    const double* __restrict__ Lp = F.L;
+    double* __restrict__ Us = F.U;
     const int tj = it.strip, nbu = (u + 15) >> 4;
     for (int t = wave; t < nbu - tj; t += nwave) {
         const int ti = tj + t;
@@ -818,14 +815,24 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(const InstDev* __restric
     }
     __syncthreads();
     const int b0 = tj << 4, b1 = min(b0 + 16, u);
-    const int ch0 = __builtin_amdgcn_readfirstlane(T.ch_ptr[s]), ch1 = __builtin_amdgcn_readfirstlane(T.ch_ptr[s + 1]);
-    for (int q = ch0; q < ch1; q++) {
-        const int ch = __builtin_amdgcn_readfirstlane(T.ch_list[q]);
-        const int cc = __builtin_amdgcn_readfirstlane(T.sn_ncol[ch]);
-        const int uc = __builtin_amdgcn_readfirstlane(T.sn_nrow[ch]) - cc;
-        const int nb = __builtin_amdgcn_readfirstlane(T.rel_np[ch]);
-        const double* __restrict__ Uc = I.U + T.sn_uofs[ch];
-        const int* __restrict__ rl = T.rel + T.sn_rowofs[ch] + cc;
+    for (int q = 0; q < F.nch; q++) {
+        // the first two children from the front descriptor
+        int uc, nb;
+        const double* __restrict__ Uc;
+        const int* __restrict__ rl;
+        if (q < 2) {
+            uc = q ? F.cuc[1] : F.cuc[0];
+            nb = q ? F.cnb[1] : F.cnb[0];
+            Uc = q ? F.cU[1] : F.cU[0];
+            rl = q ? F.crl[1] : F.crl[0];
+        } else {
+            const int ch = __builtin_amdgcn_readfirstlane(T.ch_list[F.ch0 + q]);
+            const int cc = __builtin_amdgcn_readfirstlane(T.sn_ncol[ch]);
+            uc = __builtin_amdgcn_readfirstlane(T.sn_nrow[ch]) - cc;
+            nb = __builtin_amdgcn_readfirstlane(T.rel_np[ch]);
+            Uc = I.U + T.sn_uofs[ch];
+            rl = T.rel + T.sn_rowofs[ch] + cc;
+        }
         for (int a = tid; a < uc; a += nt) srel[a] = rl[a] - c;
         __syncthreads();
         // child columns nb <= b < uc whose target column lies in [b0, b1):
@@ -1731,8 +1738,8 @@ void launch_factor(const InstDev* insts, const FrontDesc* fds, int nitems, size_
                    hipStream_t st) {
     if (nitems > 0) k_factor<<<nitems, kFactorThreads, lds, st>>>(insts, fds, fused_update);
 }
-void launch_update(const InstDev* insts, const StripItem* items, int nitems, hipStream_t st) {
-    if (nitems > 0) k_update<<<nitems, kUpdThreads, 0, st>>>(insts, items);
+void launch_update(const InstDev* insts, const FrontDesc* fds, const StripItem* items, int nitems, hipStream_t st) {
+    if (nitems > 0) k_update<<<nitems, kUpdThreads, 0, st>>>(insts, fds, items);
 }
 void launch_factor_queue(const InstDev* insts, const FrontDesc* fds, const DepLists& D, int grid, size_t lds,
                          hipStream_t st) {

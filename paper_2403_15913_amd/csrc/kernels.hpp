@@ -69,7 +69,7 @@ void launch_assemble(const InstDev* insts, const Calls& C, const WorkItem* items
 void launch_factor(const InstDev* insts, const FrontDesc* fds, int nitems, size_t lds, int fused_update,
                    hipStream_t st);
 // update matrices by 16-column strips (after the factor launch of the same level)
-void launch_update(const InstDev* insts, const StripItem* items, int nitems, hipStream_t st);
+void launch_update(const InstDev* insts, const FrontDesc* fds, const StripItem* items, int nitems, hipStream_t st);
 void launch_factor_queue(const InstDev* insts, const FrontDesc* fds, const DepLists& D, int grid, size_t lds,
                          hipStream_t st);
 void launch_sweeps_queue(const InstDev* insts, const FrontDesc* fds, const DepLists& D, int grid, size_t lds,
