@@ -971,8 +971,8 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor_queue(const InstDev* 
 // one wave (c <= 128): lane l carries rows l and l + 64 in x0 and x1, dv
 // holds the pivot reciprocals. Blocks of 16 columns: the block's own
 // triangle is read into registers first, so its 16 dependent steps are
-// register FMAs with scalar broadcasts; the rows outside the block then
-// take the block's contribution with all their LDS loads issued together.
+// register FMAs with row broadcasts; the rows outside the block then take
+// the block's contribution with all their LDS loads issued together.
 // Each row's terms are subtracted in the same order as plain substitution.
 // ---------------------------------------------------------------------------
 // L11^T x = t (backward), blocks from the last one down
@@ -993,16 +993,23 @@ __device__ inline void tri_bwd_wave(const double* __restrict__ P, int ld, int c,
         for (int k = 0; k < 16; k++) Lc[k] = (inblk && k > rb && k < nb) ? Lc[k] : 0.0;
         const double d = dv[j0 + rbc];
         double tb = hi ? x1 : x0;
+        // the chain runs inside the block's 16-lane row: step k takes lane
+        // k's value by a row broadcast (lanes of the row past the block
+        // hold zeros and have zero coefficients; other rows' results are
+        // discarded)
+        static_for<16>([&](auto K) {
+            constexpr int k = 15 - decltype(K)::value;
+            tb = fma(-Lc[k], row_bcast<k>(tb * d), tb);
+        });
+        const double xv = tb * d;
+        if (inblk) {
+            if (hi) x1 = xv;
+            else x0 = xv;
+        }
+        // the block's values for the rows above it, from every lane
         double x[16];
 #pragma unroll
-        for (int k = 15; k >= 0; k--) {
-            x[k] = k < nb ? readlane_d(tb * d, (j0 & 63) + k) : 0.0;
-            tb = fma(-Lc[k], x[k], tb);
-        }
-        if (inblk) {
-            if (hi) x1 = tb * d;
-            else x0 = tb * d;
-        }
+        for (int k = 0; k < 16; k++) x[k] = j0 > 0 ? readlane_d(xv, (j0 & 63) + k) : 0.0;
         if (j0 > 0) {  // rows 0 .. j0-1 lie above the block
             const int i0 = min(lane, j0 - 1), i1 = min(lane + 64, j0 - 1);
             double a0[16], a1[16];
@@ -1173,11 +1180,12 @@ __device__ __forceinline__ void fwd_front(const InstDev& I, const FrontDesc& F, 
 #pragma unroll
             for (int k = 0; k < 16; k++) Lr[k] = (inb && k < lane) ? Lr[k] : 0.0;
             const double d = dv[row];
-#pragma unroll
-            for (int k = 0; k < 16; k++) {
-                const double yk = k < nbk ? readlane_d(wb * d, k) : 0.0;
-                wb = fma(-Lr[k], yk, wb);
-            }
+            // lanes 0-15 hold the block's rows; step k takes lane k's value
+            // by a row broadcast (coefficients past the block are zero)
+            static_for<16>([&](auto K) {
+                constexpr int k = K;
+                wb = fma(-Lr[k], row_bcast<k>(wb * d), wb);
+            });
             if (inb) w[j0 + lane] = wb * d;
         } else if (kb > 0) {
             // rows after block kb: triangle rows, then the update rows
