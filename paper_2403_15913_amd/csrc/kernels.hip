@@ -1429,12 +1429,36 @@ __global__ __launch_bounds__(256) void k_residual(const InstDev* __restrict__ in
     const int iend = min(row + 1, I.P.n);
     for (int i = row; i < iend; i++) {
         double sum = 0.0, den = 0.0, ks = 0.0;
-        for (int64_t p = I.P.sp_ptr[i] + l; p < I.P.sp_ptr[i + 1]; p += 16) {
-            const double kv = I.kcsr[p];
-            const double t = kv * x[I.P.sp_col[p]];
+        const int64_t pb = I.P.sp_ptr[i], pe = I.P.sp_ptr[i + 1];
+        // the first three entries of each lane in one round (values, columns,
+        // then the gathered x), clamped so no load is predicated; the terms
+        // are then summed in the lane's order, as in the loop for the rest
+        constexpr int RU = 3;
+        double kv[RU], xv[RU];
+        int cl[RU];
+#pragma unroll
+        for (int q = 0; q < RU; q++) {
+            const int64_t p = min(pb + l + 16 * q, pe - 1);
+            kv[q] = I.kcsr[p];
+            cl[q] = I.P.sp_col[p];
+        }
+#pragma unroll
+        for (int q = 0; q < RU; q++) xv[q] = x[cl[q]];
+#pragma unroll
+        for (int q = 0; q < RU; q++) {
+            if (pb + l + 16 * q < pe) {
+                const double t = kv[q] * xv[q];
+                sum += t;
+                den += fabs(t);
+                ks += fabs(kv[q]);
+            }
+        }
+        for (int64_t p = pb + l + 16 * RU; p < pe; p += 16) {
+            const double kp = I.kcsr[p];
+            const double t = kp * x[I.P.sp_col[p]];
             sum += t;
             den += fabs(t);
-            ks += fabs(kv);
+            ks += fabs(kp);
         }
 #pragma unroll
         for (int o = 8; o > 0; o >>= 1) {
@@ -1469,9 +1493,23 @@ __global__ __launch_bounds__(256) void k_refine_decide(const InstDev* __restrict
     if (S->done) return;  // uniform per block
     const int nslots = ((I.P.n + 255) >> 8) * kResidualSplit;
     double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int t = threadIdx.x; t < nslots; t += blockDim.x)
+    // eight slots per thread in flight at once; a maximum is unchanged by
+    // repeats, so indices past the end repeat the last slot
+    constexpr int UNR = 8;
+    const double* __restrict__ rp = I.rpart;
+    for (int t0 = threadIdx.x; t0 < nslots; t0 += blockDim.x * UNR) {
+        double v[UNR][5];
 #pragma unroll
-        for (int q = 0; q < 5; q++) m[q] = fmax(m[q], I.rpart[5 * t + q]);
+        for (int k = 0; k < UNR; k++) {
+            const int t = min(t0 + k * (int)blockDim.x, nslots - 1);
+#pragma unroll
+            for (int q = 0; q < 5; q++) v[k][q] = rp[5 * t + q];
+        }
+#pragma unroll
+        for (int k = 0; k < UNR; k++)
+#pragma unroll
+            for (int q = 0; q < 5; q++) m[q] = fmax(m[q], v[k][q]);
+    }
     __shared__ double red[5][256];
     for (int q = 0; q < 5; q++) red[q][threadIdx.x] = m[q];
     __syncthreads();
