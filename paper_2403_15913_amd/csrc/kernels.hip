@@ -678,64 +678,101 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const FrontDesc& 
         }
     }
     __syncthreads();
-    // children's entries that pass through to the update matrix
-    for (int q = 0; q < nch; q++) {
-        const Child C = child_at(q);
-        const int uc = C.uc, nb = C.nb;
-        const double* __restrict__ Uc = C.Uc;
-        const int* __restrict__ rl = C.rl;
+    // Children's entries that pass through to the update matrix, child by
+    // child (two children can add into the same entry), in batches of PT
+    // entries per thread. Every index is clamped into [0, tot) and entries
+    // that are not kept address a valid place of U_s (the column's
+    // diagonal: rows below nb map into the front's own columns and have no
+    // place in U_s), so all loads are unpredicated. The next batch's child
+    // values and relative indices are loaded before the current batch's
+    // read-modify-write of U_s, so only that one round trip is exposed.
+    constexpr int PT = 8;
+    struct PBatch {
+        double v[PT];
+        int ra[PT], rb[PT];
+        unsigned keep;
+    };
+    auto pt_count = [&](const Child& C) { return ((C.uc - C.nb) * C.uc + PT * nt - 1) / (PT * nt); };
+    auto pt_load = [&](const Child& C, const int bi, PBatch& B) {
+        const int uc = C.uc, nb = C.nb, tot = (uc - nb) * uc;
         const int64_t base = (int64_t)nb * uc;
-        const int tot = (uc - nb) * uc;
-        constexpr int UNR = 16;
-        // Every index is clamped into [0, tot) and entries that are not kept
-        // address a valid place of U_s, so all loads are unpredicated: the
-        // values and relative indices in one round, the current entries of
-        // U_s in the next; only the stores of lower-part entries a >= b
-        // within range happen.
+        const int b0 = tid + bi * PT * nt;
         const int db = nt / uc, da = nt - db * uc;
-        for (int b0 = tid; b0 < tot; b0 += nt * UNR) {
-            double v[UNR], cur[UNR];
-            int ra[UNR], rb[UNR], dst[UNR];
-            bool keep[UNR];
-            int bq = b0 / uc, aq = b0 - bq * uc;
+        int bq = b0 / uc, aq = b0 - bq * uc;
+        B.keep = 0;
 #pragma unroll
-            for (int k = 0; k < UNR; k++) {
-                const int q0 = b0 + k * nt;
-                const int qq = min(q0, tot - 1);
-                const int b = min(nb + bq, uc - 1);
-                keep[k] = q0 < tot && aq >= nb + bq;
-                // entries not kept (upper part, past the end) address the
-                // column's diagonal: rows below nb map into the front's own
-                // columns and have no place in U_s
-                const int a = keep[k] ? aq : b;
-                v[k] = Uc[base + qq];
-                ra[k] = rl[a];
-                rb[k] = rl[b];
-                aq += da;
-                bq += db;
-                if (aq >= uc) {
-                    aq -= uc;
-                    bq++;
+        for (int k = 0; k < PT; k++) {
+            const int q0 = b0 + k * nt;
+            const int qq = min(q0, tot - 1);
+            const int bcol = min(nb + bq, uc - 1);
+            const bool kp = q0 < tot && aq >= nb + bq;
+            B.keep |= kp ? 1u << k : 0u;
+            const int arow = kp ? aq : bcol;
+            B.v[k] = C.Uc[base + qq];
+            B.ra[k] = C.rl[arow];
+            B.rb[k] = C.rl[bcol];
+            aq += da;
+            bq += db;
+            if (aq >= uc) {
+                aq -= uc;
+                bq++;
+            }
+        }
+    };
+    auto pt_apply = [&](PBatch& B) {
+        double cur[PT];
+        int dst[PT];
+#pragma unroll
+        for (int k = 0; k < PT; k++) {
+            pin(B.ra[k]);
+            pin(B.rb[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < PT; k++) {
+            dst[k] = (B.rb[k] - c) * u + (B.ra[k] - c);
+            cur[k] = Us[dst[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < PT; k++) {
+            pin(B.v[k]);
+            pin(cur[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < PT; k++)
+            if ((B.keep >> k) & 1u) Us[dst[k]] = cur[k] + B.v[k];
+    };
+    {
+        int q = 0, bi = 0, nbq = 0;
+        Child Cq = {};
+        for (; q < nch; q++) {
+            Cq = child_at(q);
+            if ((nbq = pt_count(Cq)) > 0) break;
+        }
+        if (q < nch) {
+            PBatch B0, B1;
+            pt_load(Cq, 0, B0);
+            for (;;) {
+                // the next batch: this child's, else the next child's first
+                int q2 = q, bi2 = bi + 1, nb2 = nbq;
+                Child C2 = Cq;
+                if (bi2 >= nbq) {
+                    bi2 = 0;
+                    for (q2 = q + 1; q2 < nch; q2++) {
+                        C2 = child_at(q2);
+                        if ((nb2 = pt_count(C2)) > 0) break;
+                    }
                 }
+                const bool more = q2 < nch;
+                if (more) pt_load(C2, bi2, B1);
+                pt_apply(B0);
+                if (!more) break;
+                if (q2 != q) __syncthreads();  // the previous child's updates first
+                B0 = B1;
+                q = q2;
+                bi = bi2;
+                nbq = nb2;
+                Cq = C2;
             }
-#pragma unroll
-            for (int k = 0; k < UNR; k++) {
-                pin(ra[k]);
-                pin(rb[k]);
-            }
-#pragma unroll
-            for (int k = 0; k < UNR; k++) {
-                dst[k] = (rb[k] - c) * u + (ra[k] - c);
-                cur[k] = Us[dst[k]];
-            }
-#pragma unroll
-            for (int k = 0; k < UNR; k++) {
-                pin(v[k]);
-                pin(cur[k]);
-            }
-#pragma unroll
-            for (int k = 0; k < UNR; k++)
-                if (keep[k]) Us[dst[k]] = cur[k] + v[k];
         }
         __syncthreads();
     }
