@@ -364,10 +364,12 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     std::vector<StripItem> up;
     up.reserve(nup);
     up_ptr.assign(1, 0);
+    lvl_maxu.assign(lvl_ptr.size() - 1, 0);
     for (size_t l = 0; l + 1 < lvl_ptr.size(); l++) {
         for (int t = lvl_ptr[l]; t < lvl_ptr[l + 1]; t++) {
             const Symbolic& S = *s[sn[t].inst];
             const int u = S.sn_nrow[sn[t].id] - S.sn_ncol[sn[t].id];
+            lvl_maxu[l] = std::max(lvl_maxu[l], u);
             for (int k = 0; k < (u + 15) / 16; k++) up.push_back(StripItem{sn[t].inst, sn[t].id, k, t});
         }
         up_ptr.push_back((int)up.size());
@@ -534,10 +536,11 @@ kkt_status Engine::refactor(const Calls& C, hipStream_t st) {
     } else {
         // A level with few fronts leaves most compute units idle: its update
         // matrices then go to a launch of their own with one workgroup per
-        // 16-column strip. Wide levels keep them in the factor kernel.
+        // 16-column strip, where they are large enough to repay the launch.
+        // Wide levels keep them in the factor kernel.
         for (size_t l = 0; l + 1 < lvl_ptr.size(); l++) {
             const int nf = lvl_ptr[l + 1] - lvl_ptr[l];
-            const bool split = split_update && nf < kSplitMaxFronts;
+            const bool split = split_update && nf < kSplitMaxFronts && lvl_maxu[l] >= kSplitMinRows;
             TL(KKT_PHASE_FACTOR, launch_factor(di(), fdesc + lvl_ptr[l], nf, lds_factor, split ? 0 : 1, st));
             if (split) TL(KKT_PHASE_FACTOR, launch_update(di(), fdesc, upitems + up_ptr[l], up_ptr[l + 1] - up_ptr[l], st));
         }

@@ -85,6 +85,7 @@ struct Engine {
     int *dep_parent = nullptr, *dep_nchild = nullptr, *dep_ctr = nullptr;  // queue scheduling
     StripItem* upitems = nullptr;                   // update-matrix strips by level (level schedule)
     std::vector<int> up_ptr;
+    std::vector<int> lvl_maxu;                      // widest update part of each level
     bool split_update = true;                       // level schedule: update matrices in their own launch
     bool queue_sched = false;                       // dependency-driven launches (else one launch per level)
     // captured refactor + solve (batched form)

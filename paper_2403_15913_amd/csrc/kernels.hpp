@@ -25,8 +25,9 @@ struct Calls {
 
 constexpr int kBlock = 256;
 constexpr int kUpdMaxRows = 4096;  // strip update kernel: largest child update (rows) it stages
-constexpr int kSplitMaxFronts = 48;
-constexpr int kResidualSplit = 16;   // residual blocks per 256-row item (one row per 16-lane group)  // levels with fewer fronts launch their update matrices by strips
+constexpr int kSplitMaxFronts = 48;  // levels with fewer fronts launch their update matrices by strips
+constexpr int kSplitMinRows = 96;    // ... when the level's widest update part has at least this many rows
+constexpr int kResidualSplit = 16;   // residual blocks per 256-row item (one row per 16-lane group)
 
 // Dependency lists of a persistent (queue-scheduled) launch over the fronts
 // in topological order: parent item (-1 for roots), number of children, and
