@@ -1072,8 +1072,9 @@ __device__ inline void tri_bwd_wave(const double* __restrict__ P, int ld, int c,
 // triangular sweeps (y holds the permuted right-hand side, then the solution)
 // ---------------------------------------------------------------------------
 // The panel is staged in LDS (odd leading dimension); the c x c triangle is
-// solved by one wave with scalar broadcasts, the rectangular part by all
-// threads. Reciprocals of the pivots come from the factorisation.
+// solved by one wave in 16-column blocks (each block's 16-step chain by
+// DPP row broadcasts), the rectangular part by all threads. Reciprocals of
+// the pivots come from the factorisation.
 constexpr int kSolveThreads = 256;
 static_assert(kSolveThreads == 256, "the sweep work splits assume 256 threads");
 
@@ -1189,7 +1190,7 @@ __device__ __forceinline__ void fwd_front(const InstDev& I, const FrontDesc& F, 
     for (int q = ch0 + 2; q < ch1; q++) add_child(vchild(q), false, 0.0, 0);
     // L11 y = w and the update rows' GEMV, pipelined by 16-column blocks.
     // Phase kb: wave 0 takes block kb-1's contribution into block kb's
-    // rows, then solves block kb (its triangle in registers, scalar
+    // rows, then solves block kb (its triangle in registers, row
     // broadcasts); meanwhile the other waves take block kb-1's contribution
     // into every later row (triangle rows past block kb and the update
     // rows). Every row subtracts its terms in ascending column order.
