@@ -182,11 +182,14 @@ def test_cg_on_lifted_factor_refused(kkt):
         f.cg_schur(z, zm, z.clone(), zm.clone())
 
 
-def test_paper_scale_lifted(kkt):
-    """Distillation shape, N=2000 (n=142,000): eta <= 1e-10 for two value sets."""
+@pytest.mark.parametrize("opts", [{}, dict(ordering=2, nd_leaf=417, max_super=96)], ids=["default", "bench"])
+def test_paper_scale_lifted(kkt, opts):
+    """Distillation shape, N=2000 (n=142,000): eta <= 1e-10 for two value sets,
+    with the default symbolic options and with the options bench.py's
+    autotuner picks for this pattern (the timed configuration)."""
     pat, v = kktgen.workload("paper")
-    print("paper-scale lifted", flush=True)
-    sym = kkt.Symbolic.from_pattern(pat)
+    print(f"paper-scale lifted {opts}", flush=True)
+    sym = kkt.Symbolic.from_pattern(pat, **opts)
     f = kkt.Factor(sym)
     for vs in (0, 1):
         if vs:
@@ -205,3 +208,33 @@ def test_paper_scale_lifted(kkt):
         # both solutions are backward stable; their difference is bounded by
         # the conditioning (forward error is reported, gated loosely)
         assert D.forward_error(xh, xo) <= 1e-3
+
+
+@pytest.mark.parametrize("shape,opts", [((4, 300, 4), dict(ordering=1)), ((8, 120, 6), dict(ordering=2, nd_leaf=64))],
+                         ids=["natural-353rows", "nd-313rows"])
+def test_tall_fronts(kkt, shape, opts):
+    """Fronts taller than the fused panel path covers (more than 272 rows:
+    the pivot chain by one wave and a separate triangular solve): eta <=
+    1e-10, forward error <= 1e-8 against the oracle (Sigma in [1e-2, 1e2]),
+    and the queue schedule bitwise equal to the level schedule."""
+    pat = kktgen.nmpc_pattern(*shape)
+    v = kktgen.nmpc_values(pat, kktgen.rng_for(95, 0, 0), 1e-2, 1e2)
+    sym = kkt.Symbolic.from_pattern(pat, **opts)
+    cp, _, nr = sym.supernodes()
+    print(f"tall fronts {shape} {opts}: max rows {max(nr)}", flush=True)
+    assert max(nr) > 272
+    xs = []
+    for sched in (kkt.SCHEDULE_LEVELS, kkt.SCHEDULE_QUEUE):
+        f = kkt.Factor(sym)
+        f.set_schedule(sched)
+        f.refactor(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), dev(v.sigma_s))
+        assert f.status()[0] == 0
+        x = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
+        info = f.solve(dev(v.b), x)
+        xs.append(host(x))
+        assert info["eta"] <= 1e-10
+    K = D.condensed(pat, v, v.sigma_s)
+    assert D.backward_errors(K, xs[0], v.b)["eta"] <= 1e-10
+    xo, oinfo = S.lifted_solve(pat, v, v.b)
+    assert oinfo["spd"] and D.forward_error(xs[0], xo) <= 1e-8
+    assert np.array_equal(xs[0], xs[1])
