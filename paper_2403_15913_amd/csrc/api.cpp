@@ -450,7 +450,8 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     };
     size_t up_bytes = 0;
     for (auto& pc : pieces) up_bytes += pc.bytes;
-    const size_t readback = (size_t)ninst * std::max(sizeof(RefineState), sizeof(CgState)) + 64;
+    // read-back area: error latch, status words, refinement or CG records
+    const size_t readback = 128 + (size_t)ninst * (8 + std::max(sizeof(RefineState), sizeof(CgState))) + 64;
     hipError_t e = ensure_pinned(std::max(up_bytes, readback));
     if (e != hipSuccess) return hip_fail(e, "pinned host buffer");
     // one packed staging buffer, one copy per piece
@@ -581,8 +582,12 @@ kkt_status Engine::read_status(int* st_out, int* bad_out) {
     if (e == hipSuccess) e = hipMemcpy(&derr, deps().err, sizeof(int), hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(hpin, status, (size_t)ninst * 8, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "status read");
+    return parse_status(derr, (const int*)hpin, st_out, bad_out);
+}
+
+// status words (2 per instance) and the queue schedule's error latch
+kkt_status Engine::parse_status(int derr, const int* hs, int* st_out, int* bad_out) {
     if (derr) return fail(KKT_ERR_DEVICE, "a dependency wait of the queue schedule timed out");
-    const int* hs = (const int*)hpin;
     kkt_status worst = KKT_OK;
     for (int q = 0; q < ninst; q++) {
         const int code = hs[2 * q];
@@ -660,14 +665,23 @@ kkt_status Engine::solve_finish(const Calls& C, int iter0, int maxit, double tol
     TL(KKT_PHASE_PERMUTE, launch_refine_revert(di(), C, nitems, n_nitems, st));
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "solve launch");
+    // One synchronisation: the error latch, the status words and the
+    // refinement records are copied behind the queued work, then read.
+    char* hb = (char*)hpin;
+    int* hderr = (int*)hb;
+    const int* hs = (const int*)(hb + 64);
+    const RefineState* hr = (const RefineState*)(hb + 64 + (((size_t)ninst * 8 + 63) & ~(size_t)63));
+    if ((e = hipMemcpyAsync(hderr, deps().err, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipMemcpyAsync((void*)hs, status, (size_t)ninst * 8, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (infos && (e = hipMemcpyAsync((void*)hr, rs, (size_t)ninst * sizeof(RefineState), hipMemcpyDeviceToHost,
+                                      st)) != hipSuccess) ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(e, "solve read-back");
     // a failed factor makes the solve meaningless: report it
-    kkt_status fst = read_status(nullptr, nullptr);
+    kkt_status fst = parse_status(*hderr, hs, nullptr, nullptr);
     if (fst == KKT_ERR_DEVICE || fst == KKT_ERR_OOM) return fst;
     if (fst != KKT_OK) return fail(fst, "factor failed; solve result invalid");
     if (!infos) return KKT_OK;
-    e = hipMemcpy(hpin, rs, (size_t)ninst * sizeof(RefineState), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "solve info");
-    const RefineState* hr = (const RefineState*)hpin;
     kkt_status worst = KKT_OK;
     for (int q = 0; q < ninst; q++) {
         const RefineState& S = hr[q];

@@ -144,6 +144,7 @@ struct Engine {
     kkt_status cg_schur(const Calls& C, double tol, int maxit, kkt_cg_info* info, hipStream_t st);
     // waits for st and returns each instance's latched status and failing column (original index)
     kkt_status read_status(int* st_out, int* bad_out);
+    kkt_status parse_status(int derr, const int* hs, int* st_out, int* bad_out);
     hipError_t ensure_pinned(size_t bytes);
     DepLists deps() const;
 };
