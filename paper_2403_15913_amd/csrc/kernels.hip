@@ -281,7 +281,6 @@ static_assert(kFactorThreads == 512, "the panel schedule assumes eight waves");
 __device__ __forceinline__ void factor_front(const InstDev& I, const FrontDesc& F, double* __restrict__ P,
                                              double* invd, const bool fused_update, const bool fused_panel) {
     const PatDev& T = I.P;
-    const int s = F.id;
     const int c = F.c, r = F.r;
     const int u = r - c, col0 = F.col0;
     // descriptor fields used inside the loops below, read once
@@ -1080,7 +1079,6 @@ static_assert(kSolveThreads == 256, "the sweep work splits assume 256 threads");
 
 __device__ __forceinline__ void fwd_front(const InstDev& I, const FrontDesc& F, double* __restrict__ sh) {
     const PatDev& T = I.P;
-    const int s = F.id;
     const int c = F.c, r = F.r;
     const int u = r - c;
     const int ld = r | 1;
@@ -1254,7 +1252,6 @@ __device__ __forceinline__ void fwd_front(const InstDev& I, const FrontDesc& F, 
 }
 
 __device__ __forceinline__ void bwd_front(const FrontDesc& F, double* __restrict__ sh) {
-    const int s = F.id;
     const int c = F.c, r = F.r;
     const int u = r - c;
     double* const yb = F.y - F.col0;  // the instance's work vector
@@ -1552,7 +1549,7 @@ __global__ __launch_bounds__(256) void k_refine_decide(const InstDev* __restrict
     for (int q = 0; q < 5; q++) red[q][threadIdx.x] = m[q];
     __syncthreads();
     for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h)
+        if ((int)threadIdx.x < h)
             for (int q = 0; q < 5; q++) red[q][threadIdx.x] = fmax(red[q][threadIdx.x], red[q][threadIdx.x + h]);
         __syncthreads();
     }
