@@ -1447,7 +1447,6 @@ __device__ inline void block_max5(double v0, double v1, double v2, double v3, do
     if (tid < 5) out[tid] = red[tid][0];
 }
 
-// 16 lanes per row (coalesced reads of the row's entries), 256 rows per block.
 // 16 lanes per row (coalesced reads of the row's entries). Sixteen blocks
 // per 256-row item, one row per 16-lane group: many short independent rows
 // in flight hide the dependent loads (row bounds, then columns, then x).
