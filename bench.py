@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--max-super", type=int, default=96, help="widest supernode (columns)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="pick ordering / leaf size by measurement (ignored when --ordering or --nd-leaf is set)")
+    ap.add_argument("--hykkt", type=int, default=1, help="also time HyKKT (refactor + Schur CG) at paper scale")
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched workload (0: skip)")
     ap.add_argument("--batch-ordering", type=int, default=2, help="batch ordering when not autotuned")
     ap.add_argument("--batch-nd-leaf", type=int, default=256, help="batch nested-dissection leaf when not autotuned")
@@ -146,6 +147,52 @@ def bench_batched(args, kkt, kktgen, torch, dev):
                 plain_pairs_per_s=round(pok / tp, 2), plain_ms=round(1e3 * tp, 3),
                 speedup=round((ok / tg) / max(pok / tp, 1e-12), 2), eta_max=float(etas.max()),
                 passing=f"{ok}/{count}", batched_equals_plain_bitwise=bool(same))
+
+
+def bench_hykkt(args, kkt, kktgen, torch, dev, opts):
+    """HyKKT on the paper-scale shape: refactor K_gamma = W + Sigma_x + gamma J^T J, then conjugate
+    gradient on the Schur complement J K_gamma^{-1} J^T (section "Solution 2: HyKKT"). A pair counts
+    when the library reports CG convergence to the tolerance. Sigma_x ~ logU[1e-2, 1e2]: with the
+    late-iteration range [1e-8, 1e8], K_gamma at gamma = 1e7 is too ill-conditioned for the inner
+    solves and CG stalls (reported by the library as not converged)."""
+    pat, _ = kktgen.paper_config()
+    vals = [kktgen.distillation_values(pat, kktgen.rng_for(1, 0, vs), 1e-2, 1e2) for vs in range(3)]
+
+    def T(a):
+        return torch.tensor(np.asarray(a), dtype=torch.float64, device=dev)
+
+    gamma, tol = 1e7, 1e-10
+    sym = kkt.Symbolic.from_pattern(pat, **opts)
+    fac = kkt.Factor(sym)
+    dv = [dict(w=T(v.w_vals), j=T(v.j_vals), sx=T(v.sigma_x), f=T(v.f), g=T(v.g)) for v in vals]
+    dx = torch.zeros(pat.n, dtype=torch.float64, device=dev)
+    dy = torch.zeros(pat.m, dtype=torch.float64, device=dev)
+
+    def step(i):
+        d = dv[i % len(dv)]
+        fac.refactor(d["w"], d["j"], d["sx"], None, gamma)
+        return fac.cg_schur(d["f"], d["g"], dx, dy, tol=tol, maxit=200)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [step(i) for i in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fac.set_timing(True)
+    fac.read_timing()
+    for i in range(args.steps):
+        step(i)
+    tm = fac.read_timing()
+    fac.set_timing(False)
+    ok = sum(1 for i in infos if i["status"] == 0)
+    return dict(workload="hykkt, distillation-shaped N=2000 (n=142000, m=140000), Sigma_x~logU[1e-2,1e2], "
+                         "gamma=1e7, CG tol 1e-10",
+                pairs_per_s=round(ok / elapsed, 3), ms_per_pair=round(1e3 * elapsed / args.steps, 4),
+                passing=f"{ok}/{args.steps}", cg_iters_mean=float(np.mean([i["iters"] for i in infos])),
+                rel_res_max=float(max(i["rel_res"] for i in infos)),
+                phase_ms_per_pair={p: round(tm[p]["ms"] / args.steps, 4) for p in tm})
 
 
 def bench_served(args, kkt, kktgen, torch, dev):
@@ -376,6 +423,7 @@ def main():
                           f"scipy assembly + C up-looking sparse LDL^T in stage order + Richardson refinement, "
                           f"single thread", seconds=round(cs, 3))
 
+    hykkt = bench_hykkt(args, kkt, kktgen, torch, dev, opts) if args.hykkt and args.workload == "paper" else None
     batched = bench_batched(args, kkt, kktgen, torch, dev) if args.batch > 0 else None
     served = bench_served(args, kkt, kktgen, torch, dev) if args.serve_requests > 0 else None
 
@@ -408,6 +456,7 @@ def main():
             "phase_ms_per_step": {k: round(v, 4) for k, v in phase_ms.items()},
             "symbolic": {k: stats[k] for k in ("nsuper", "levels", "max_rows", "max_cols", "nnz_k", "nnz_l",
                                                "nnz_l_exact", "flops", "flops_exact")},
+            "hykkt": hykkt,
             "batched": batched,
             "served": served,
         },

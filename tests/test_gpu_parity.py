@@ -238,3 +238,26 @@ def test_tall_fronts(kkt, shape, opts):
     xo, oinfo = S.lifted_solve(pat, v, v.b)
     assert oinfo["spd"] and D.forward_error(xs[0], xo) <= 1e-8
     assert np.array_equal(xs[0], xs[1])
+
+
+def test_hykkt_larger_system(kkt):
+    """HyKKT on a 200-stage NMPC system (n=7200, m=6400), gamma = 1e7: eta on
+    the 2x2 system <= 1e-10, forward error <= 1e-8 against the saddle-point
+    LDL^T, CG iteration count within one of the oracle's."""
+    pat = kktgen.nmpc_pattern(200, 32, 4)
+    v = kktgen.nmpc_values(pat, kktgen.rng_for(96, 0, 0), 1e-2, 1e2)
+    print(f"hykkt n={pat.n} m={pat.m}", flush=True)
+    dx0, dy0, inn, ok = S.hykkt_saddle_solve(pat, v, v.f, v.g)
+    assert ok and inn == (pat.n, 0, pat.m)
+    f = kkt.Factor(kkt.Symbolic.from_pattern(pat))
+    f.refactor(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), None, 1e7)
+    assert f.status()[0] == 0
+    dx = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
+    dy = torch.zeros(pat.m, dtype=torch.float64, device="cuda")
+    info = f.cg_schur(dev(v.f), dev(v.g), dx, dy, tol=1e-10, maxit=200)
+    assert info["status"] == 0
+    dxh, dyh = host(dx), host(dy)
+    assert D.hykkt_backward_errors(pat, v, dxh, dyh, v.f, v.g)["eta"] <= 1e-10
+    assert D.forward_error(dxh, dx0) <= 1e-8
+    _, _, oinfo = S.hykkt_cg_solve(pat, v, v.f, v.g, 1e7, tol=1e-10)
+    assert abs(info["iters"] - oinfo["iters"]) <= 1
