@@ -56,12 +56,24 @@ __global__ __launch_bounds__(256) void k_copy_segments(const CopySeg* __restrict
         sg.dst[i] = sg.src[i];
 }
 
+// Workgroups go to the 8 XCDs in turn (workgroup b runs on XCD b mod 8) and
+// every XCD has an L2 of its own. This renumbering hands each XCD one
+// contiguous share of the launch's items, so neighbouring items, which read
+// the same data (rows of J, a front's stored panel), meet in one L2 instead
+// of being fetched into all eight.
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_block() {
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int x = b % kNumXcd, q = nb / kNumXcd, rem = nb % kNumXcd;
+    return x * q + min(x, rem) + b / kNumXcd;
+}
+
 // ---------------------------------------------------------------------------
 // assembly: one thread per lower entry of K
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_assemble(const InstDev* __restrict__ insts, Calls C,
                                                   const WorkItem* __restrict__ items) {
-    const WorkItem it = items[blockIdx.x];
+    const WorkItem it = items[xcd_block()];
     const InstDev& I = insts[it.inst];
     const int64_t nnzk = I.P.k_snptr[I.P.ns];
     const int64_t e = (int64_t)it.id + threadIdx.x;
@@ -829,7 +841,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(const InstDev* __restric
                                                        const FrontDesc* __restrict__ fds,
                                                        const StripItem* __restrict__ items) {
     __shared__ int srel[kUpdMaxRows];
-    const StripItem it = items[blockIdx.x];
+    const StripItem it = items[xcd_block()];
     const FrontDesc& F = fds[it.item];
     const InstDev& I = insts[F.inst];
     const PatDev& T = I.P;
