@@ -1459,47 +1459,62 @@ __device__ inline void block_max5(double v0, double v1, double v2, double v3, do
     if (tid < 5) out[tid] = red[tid][0];
 }
 
-// 16 lanes per row (coalesced reads of the row's entries). Sixteen blocks
-// per 256-row item, one row per 16-lane group: many short independent rows
-// in flight hide the dependent loads (row bounds, then columns, then x).
+// 16 lanes per row (coalesced reads of the row's entries); each 16-lane
+// group takes NR rows, 16 apart, and issues the loads of all of them before
+// the first wait: many short independent rows in flight hide the dependent
+// loads (row bounds, then columns, then x), and each block's reduction is
+// shared by 16 NR rows.
 __global__ __launch_bounds__(256) void k_residual(const InstDev* __restrict__ insts, Calls C,
                                                   const WorkItem* __restrict__ items) {
+    constexpr int NR = 16 / kResidualSplit;  // rows per 16-lane group
     const WorkItem it = items[blockIdx.x / kResidualSplit];
     const InstDev& I = insts[it.inst];
     if (I.rs->done) return;  // uniform per block
     const double* __restrict__ x = C.x + I.n_off;
     const double* __restrict__ b = C.b + I.n_off;
+    const int n = I.P.n;
     const int g = threadIdx.x >> 4, l = threadIdx.x & 15;
     double ra = 0.0, om = 0.0, rs = 0.0, xa = 0.0, ba = 0.0;
-    const int row = it.id + (blockIdx.x % kResidualSplit) * 16 + g;
-    const int iend = min(row + 1, I.P.n);
-    for (int i = row; i < iend; i++) {
-        double sum = 0.0, den = 0.0, ks = 0.0;
-        const int64_t pb = I.P.sp_ptr[i], pe = I.P.sp_ptr[i + 1];
-        // the first three entries of each lane in one round (values, columns,
-        // then the gathered x), clamped so no load is predicated; the terms
-        // are then summed in the lane's order, as in the loop for the rest
-        constexpr int RU = 3;
-        double kv[RU], xv[RU];
-        int cl[RU];
+    const int row0 = it.id + (blockIdx.x % kResidualSplit) * 16 * NR + g;
+    // rows past the end load the last row (valid addresses) and are discarded
+    int64_t pb[NR], pe[NR];
+#pragma unroll
+    for (int j = 0; j < NR; j++) {
+        const int i = min(row0 + 16 * j, n - 1);
+        pb[j] = I.P.sp_ptr[i];
+        pe[j] = I.P.sp_ptr[i + 1];
+    }
+    // the first three entries of each lane and row in one round (values,
+    // columns, then the gathered x), clamped so no load is predicated; the
+    // terms are then summed in the lane's order, as in the loop for the rest
+    constexpr int RU = 3;
+    double kv[NR][RU], xv[NR][RU];
+    int cl[NR][RU];
+#pragma unroll
+    for (int j = 0; j < NR; j++)
 #pragma unroll
         for (int q = 0; q < RU; q++) {
-            const int64_t p = min(pb + l + 16 * q, pe - 1);
-            kv[q] = I.kcsr[p];
-            cl[q] = I.P.sp_col[p];
+            const int64_t p = min(pb[j] + l + 16 * q, pe[j] - 1);
+            kv[j][q] = I.kcsr[p];
+            cl[j][q] = I.P.sp_col[p];
         }
 #pragma unroll
-        for (int q = 0; q < RU; q++) xv[q] = x[cl[q]];
+    for (int j = 0; j < NR; j++)
+#pragma unroll
+        for (int q = 0; q < RU; q++) xv[j][q] = x[cl[j][q]];
+#pragma unroll
+    for (int j = 0; j < NR; j++) {
+        double sum = 0.0, den = 0.0, ks = 0.0;
 #pragma unroll
         for (int q = 0; q < RU; q++) {
-            if (pb + l + 16 * q < pe) {
-                const double t = kv[q] * xv[q];
+            if (pb[j] + l + 16 * q < pe[j]) {
+                const double t = kv[j][q] * xv[j][q];
                 sum += t;
                 den += fabs(t);
-                ks += fabs(kv[q]);
+                ks += fabs(kv[j][q]);
             }
         }
-        for (int64_t p = pb + l + 16 * RU; p < pe; p += 16) {
+        for (int64_t p = pb[j] + l + 16 * RU; p < pe[j]; p += 16) {
             const double kp = I.kcsr[p];
             const double t = kp * x[I.P.sp_col[p]];
             sum += t;
@@ -1512,7 +1527,8 @@ __global__ __launch_bounds__(256) void k_residual(const InstDev* __restrict__ in
             den += __shfl_xor(den, o, 16);
             ks += __shfl_xor(ks, o, 16);
         }
-        if (l == 0) {
+        const int i = row0 + 16 * j;
+        if (l == 0 && i < n) {
             const double bi = b[i];
             const double ri = bi - sum;
             I.r[i] = ri;

@@ -27,7 +27,8 @@ constexpr int kBlock = 256;
 constexpr int kUpdMaxRows = 4096;  // strip update kernel: largest child update (rows) it stages
 constexpr int kSplitMaxFronts = 48;  // levels with fewer fronts launch their update matrices by strips
 constexpr int kSplitMinRows = 96;    // ... when the level's widest update part has at least this many rows
-constexpr int kResidualSplit = 16;   // residual blocks per 256-row item (one row per 16-lane group)
+constexpr int kResidualSplit = 8;    // residual blocks per 256-row item (two rows per 16-lane group)
+static_assert(16 % kResidualSplit == 0, "a 256-row item splits into whole rows per 16-lane group");
 
 // Dependency lists of a persistent (queue-scheduled) launch over the fronts
 // in topological order: parent item (-1 for roots), number of children, and
