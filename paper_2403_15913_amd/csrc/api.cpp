@@ -209,8 +209,12 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     int nlev = 0;
     size_t nsn = 0, nnb = 0, nmb = 0, nkb = 0, nup = 0, njb = 0;
     int max_rows = 0;
+    // entries of K with long product lists, assembled 16 lanes per entry
+    std::vector<WorkItem> hv;
     for (int q = 0; q < ninst; q++) {
         const Symbolic& S = *s[q];
+        for (int64_t e = 0; e < S.nnzk; e++)
+            if (S.k_pptr[e + 1] - S.k_pptr[e] > kHeavyPairs) hv.push_back(WorkItem{q, (int)e});
         n_ofs[q + 1] = n_ofs[q] + S.n;
         m_ofs[q + 1] = m_ofs[q] + S.m;
         w_ofs[q + 1] = w_ofs[q] + S.nnz_w;
@@ -268,6 +272,7 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     mitems = cv.take<WorkItem>(nmb);
     kitems = cv.take<WorkItem>(nkb);
     jitems = cv.take<WorkItem>(njb);
+    hitems = cv.take<WorkItem>(hv.size());
     dep_parent = cv.take<int>(nsn);
     dep_nchild = cv.take<int>(nsn);
     dep_ctr = cv.take<int>(3 * nsn + 2);
@@ -435,6 +440,7 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     n_mitems = (int)mb.size();
     n_kitems = (int)kb.size();
     n_jitems = (int)jb.size();
+    n_hitems = (int)hv.size();
     // one packed upload from pinned memory
     struct Piece { void* dst; const void* src; size_t bytes; } pieces[] = {
         {dinsts, hinst.data(), (size_t)ninst * sizeof(InstDev)},
@@ -444,6 +450,7 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         {mitems, mb.data(), mb.size() * sizeof(WorkItem)},
         {kitems, kb.data(), kb.size() * sizeof(WorkItem)},
         {jitems, jb.data(), jb.size() * sizeof(WorkItem)},
+        {hitems, hv.data(), hv.size() * sizeof(WorkItem)},
         {dep_parent, dpar.data(), dpar.size() * sizeof(int)},
         {dep_nchild, dnch.data(), dnch.size() * sizeof(int)},
         {upitems, up.data(), up.size() * sizeof(StripItem)},
@@ -529,6 +536,7 @@ kkt_status Engine::refactor(const Calls& C, hipStream_t st) {
     TL(KKT_PHASE_CONTROL, launch_status_init(status, ninst, st));
     if (C.ss) TL(KKT_PHASE_ASSEMBLE, launch_jscale(di(), C, jitems, n_jitems, st));
     TL(KKT_PHASE_ASSEMBLE, launch_assemble(di(), C, kitems, n_kitems, st));
+    TL(KKT_PHASE_ASSEMBLE, launch_assemble_heavy(di(), C, hitems, n_hitems, st));
     if (queue_sched) {
         const DepLists D = deps();
         // counters, ticket and the error latch (the latch is cleared only here)

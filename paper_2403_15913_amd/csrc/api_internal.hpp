@@ -80,7 +80,8 @@ struct Engine {
     RefineState* rs = nullptr;
     CgState* cg = nullptr;
     InstDev* dinsts = nullptr;
-    WorkItem *snitems = nullptr, *nitems = nullptr, *mitems = nullptr, *kitems = nullptr, *jitems = nullptr;
+    WorkItem *snitems = nullptr, *nitems = nullptr, *mitems = nullptr, *kitems = nullptr, *jitems = nullptr,
+             *hitems = nullptr;
     FrontDesc* fdesc = nullptr;                     // one per front work item (same order as snitems)
     int *dep_parent = nullptr, *dep_nchild = nullptr, *dep_ctr = nullptr;  // queue scheduling
     StripItem* upitems = nullptr;                   // update-matrix strips by level (level schedule)
@@ -104,7 +105,7 @@ struct Engine {
     struct SweepPart { int begin, count; size_t lds; };
     std::vector<SweepPart> sw_part;
     std::vector<int> sw_lvl;
-    int n_nitems = 0, n_mitems = 0, n_kitems = 0, n_jitems = 0;
+    int n_nitems = 0, n_mitems = 0, n_kitems = 0, n_jitems = 0, n_hitems = 0;
     size_t lds_factor = 0, lds_solve = 0;
     std::vector<int64_t> n_ofs, m_ofs, w_ofs, j_ofs;  // ninst + 1 prefix offsets
     void* hpin = nullptr;                              // pinned host staging (uploads, readback)

@@ -78,12 +78,13 @@ __global__ __launch_bounds__(256) void k_assemble(const InstDev* __restrict__ in
     const int64_t nnzk = I.P.k_snptr[I.P.ns];
     const int64_t e = (int64_t)it.id + threadIdx.x;
     if (e >= nnzk) return;
+    const int64_t p0 = I.P.k_pptr[e], p1 = I.P.k_pptr[e + 1];
+    if (p1 - p0 > kHeavyPairs) return;  // k_assemble_heavy's entry
     double v = 0.0;
     const int wi = I.P.k_w[e];
     if (wi >= 0) v += C.w[I.w_off + wi];
     const int di = I.P.k_diag[e];
     if (di >= 0) v += C.sx[I.n_off + di];
-    const int64_t p0 = I.P.k_pptr[e], p1 = I.P.k_pptr[e + 1];
     const double* __restrict__ jv = C.jv + I.j_off;
     if (C.ss) {
         // js[a] = J_a * Sigma_s[row of a] (k_jscale), so each product is
@@ -116,6 +117,41 @@ __global__ __launch_bounds__(256) void k_assemble(const InstDev* __restrict__ in
     }
     I.kval[e] = v;
     // row-ordered copy (both triangles) for the residual and K x
+    const int c0 = I.P.k_csr[2 * e], c1 = I.P.k_csr[2 * e + 1];
+    I.kcsr[c0] = v;
+    if (c1 >= 0) I.kcsr[c1] = v;
+    if (!isfinite(v)) atomicMax(&I.status[0], KKT_ST_NONFINITE);
+}
+
+// Entries of K with more than kHeavyPairs products: columns of J that many
+// rows share (a stage's coupling variables) give a few entries long product
+// lists, which would keep a whole wave of the one-thread-per-entry kernel
+// looping for one lane. Here 16 lanes take one entry: lane l sums products
+// l, l + 16, ... in order, then a fixed butterfly over the 16 lanes, so every
+// run gives the same value.
+__global__ __launch_bounds__(256) void k_assemble_heavy(const InstDev* __restrict__ insts, Calls C,
+                                                        const WorkItem* __restrict__ items, int nitems) {
+    const int h = blockIdx.x * 16 + (threadIdx.x >> 4), l = threadIdx.x & 15;
+    if (h >= nitems) return;  // whole 16-lane groups leave together
+    const WorkItem it = items[h];
+    const InstDev& I = insts[it.inst];
+    const int64_t e = it.id;
+    const int64_t p0 = I.P.k_pptr[e], p1 = I.P.k_pptr[e + 1];
+    const double* __restrict__ jv = C.jv + I.j_off;
+    // Lifted-KKT: (J_a Sigma_s) J_b from k_jscale's scaled copy; K_gamma: J_a J_b
+    const double* __restrict__ ja = C.ss ? I.js : jv;
+    double acc = 0.0;
+    for (int64_t p = p0 + l; p < p1; p += 16) acc += ja[I.P.pair_a[p]] * jv[I.P.pair_b[p]];
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+    if (l != 0) return;
+    double v = 0.0;
+    const int wi = I.P.k_w[e];
+    if (wi >= 0) v += C.w[I.w_off + wi];
+    const int di = I.P.k_diag[e];
+    if (di >= 0) v += C.sx[I.n_off + di];
+    v += C.ss ? acc : C.gamma * acc;
+    I.kval[e] = v;
     const int c0 = I.P.k_csr[2 * e], c1 = I.P.k_csr[2 * e + 1];
     I.kcsr[c0] = v;
     if (c1 >= 0) I.kcsr[c1] = v;
@@ -1838,6 +1874,9 @@ void launch_status_init(int* status, int ninst, hipStream_t st) {
 }
 void launch_jscale(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st) {
     if (nitems > 0) k_jscale<<<nitems, kBlock, 0, st>>>(insts, C, items);
+}
+void launch_assemble_heavy(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st) {
+    if (nitems > 0) k_assemble_heavy<<<(nitems + 15) / 16, kBlock, 0, st>>>(insts, C, items, nitems);
 }
 void launch_assemble(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st) {
     if (nitems > 0) k_assemble<<<nitems, kBlock, 0, st>>>(insts, C, items);
