@@ -213,8 +213,7 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     std::vector<WorkItem> hv;
     for (int q = 0; q < ninst; q++) {
         const Symbolic& S = *s[q];
-        for (int64_t e = 0; e < S.nnzk; e++)
-            if (S.k_pptr[e + 1] - S.k_pptr[e] > kHeavyPairs) hv.push_back(WorkItem{q, (int)e});
+        for (const int e : S.k_heavy) hv.push_back(WorkItem{q, e});
         n_ofs[q + 1] = n_ofs[q] + S.n;
         m_ofs[q + 1] = m_ofs[q] + S.m;
         w_ofs[q + 1] = w_ofs[q] + S.nnz_w;

@@ -9,6 +9,11 @@
 
 namespace kkt {
 
+// Entries of K with more than this many products of J entries are assembled
+// by a 16-lane group each instead of one thread (the symbolic analysis lists
+// them once per pattern).
+constexpr int kHeavyPairs = 8;
+
 struct PatDev {
     int n, m, ns;
     int nlevels;

@@ -140,8 +140,28 @@ __global__ __launch_bounds__(256) void k_assemble_heavy(const InstDev* __restric
     const double* __restrict__ jv = C.jv + I.j_off;
     // Lifted-KKT: (J_a Sigma_s) J_b from k_jscale's scaled copy; K_gamma: J_a J_b
     const double* __restrict__ ja = C.ss ? I.js : jv;
+    // HU products per lane and round: indices, then values, all loads issued
+    // before the products are added in the lane's order
+    constexpr int HU = 5;
     double acc = 0.0;
-    for (int64_t p = p0 + l; p < p1; p += 16) acc += ja[I.P.pair_a[p]] * jv[I.P.pair_b[p]];
+    for (int64_t p = p0 + l; p < p1; p += 16 * HU) {
+        int a[HU], b[HU];
+#pragma unroll
+        for (int q = 0; q < HU; q++) {
+            const int64_t pc = min(p + 16 * q, p1 - 1);
+            a[q] = I.P.pair_a[pc];
+            b[q] = I.P.pair_b[pc];
+        }
+        double x[HU], y[HU];
+#pragma unroll
+        for (int q = 0; q < HU; q++) {
+            x[q] = ja[a[q]];
+            y[q] = jv[b[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < HU; q++)
+            if (p + 16 * q < p1) acc += x[q] * y[q];
+    }
 #pragma unroll
     for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
     if (l != 0) return;

@@ -70,7 +70,6 @@ void launch_jscale(const InstDev* insts, const Calls& C, const WorkItem* items, 
 void launch_assemble(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st);
 // entries of K with more than kHeavyPairs products of J entries are left to
 // launch_assemble_heavy (one item per entry, 16 lanes each)
-constexpr int kHeavyPairs = 8;
 void launch_assemble_heavy(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st);
 void launch_factor(const InstDev* insts, const FrontDesc* fds, int nitems, size_t lds, int fused_update,
                    hipStream_t st);

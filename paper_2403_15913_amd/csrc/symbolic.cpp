@@ -11,6 +11,7 @@
 // residual K x; level schedules.
 #include "symbolic.hpp"
 
+#include "device.hpp"
 #include "lds_layout.hpp"
 
 #include <algorithm>
@@ -682,6 +683,9 @@ int analyze(int n, int m, const int32_t* wp, const int32_t* wi, const int32_t* j
         std::copy(pa.begin() + kpp[e], pa.begin() + kpp[e + 1], S.pair_a.begin() + S.k_pptr[q]);
         std::copy(pb.begin() + kpp[e], pb.begin() + kpp[e + 1], S.pair_b.begin() + S.k_pptr[q]);
     }
+    S.k_heavy.clear();
+    for (int64_t q = 0; q < nnzk; q++)
+        if (S.k_pptr[q + 1] - S.k_pptr[q] > kHeavyPairs) S.k_heavy.push_back((int)q);
 
     // ---- symmetric row lists for K x (original numbering) -----------------------
     S.sp_ptr.assign(n + 1, 0);

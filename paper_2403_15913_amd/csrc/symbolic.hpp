@@ -51,6 +51,7 @@ struct Symbolic {
     std::vector<int> k_diag;               // original index i for Sigma_x[i], or -1
     std::vector<int64_t> k_pptr;           // nnzk + 1: range of J-entry pairs
     std::vector<int> pair_a, pair_b;       // J entry indices (same row of J)
+    std::vector<int> k_heavy;              // entries with more than kHeavyPairs pairs
     std::vector<int> jrow;                 // row of every J entry
     std::vector<int64_t> sp_ptr;           // n + 1: symmetric K x by original rows
     std::vector<int> sp_e, sp_col;         // entry id and column for each stored product
