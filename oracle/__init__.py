@@ -8,7 +8,7 @@ library itself never does, and nothing here imports the library.
 Contents:
   dense   -- explicit systems (condensed, 2x2 saddle-point, 3x3 augmented),
              Bunch-Kaufman LDL^T with inertia, residual evaluators,
-             Schur-complement closed forms and a plain conjugate gradient.
+             Schur-complement closed forms.
   sparse  -- ctypes front end to ``sparse_ldl.c``: up-looking sparse LDL^T
              with static pivots (condensed Cholesky, saddle-point LDL^T),
              Richardson refinement and the Cholesky + CG HyKKT solve.

@@ -281,7 +281,26 @@ def backward_errors(A, x, b) -> dict:
 
 
 def forward_error(x, xstar) -> float:
+    """Normwise relative forward error ||x - x*||_inf / ||x*||_inf."""
     return float(np.linalg.norm(x - xstar, np.inf) / np.linalg.norm(xstar, np.inf))
+
+
+def componentwise_error(x, xstar, floor: float = 1e-12) -> float:
+    """max_i |x_i - x*_i| / (|x*_i| + floor ||x*||_inf).
+
+    The relative error of every entry, with entries far below the largest
+    one measured against floor * ||x*||_inf instead of themselves; a value
+    <= tol means |x - x*| <= tol |x*| + tol * floor ||x*||_inf entrywise.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    xstar = np.asarray(xstar, dtype=np.float64)
+    if len(xstar) == 0:
+        return 0.0
+    den = np.abs(xstar) + floor * np.abs(xstar).max()
+    d = np.abs(x - xstar)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        q = np.where(den > 0, d / np.where(den > 0, den, 1.0), np.where(d > 0, np.inf, 0.0))
+    return float(q.max())
 
 
 def hykkt_backward_errors(pat, vals, dx, dy, f, g) -> dict:
@@ -317,32 +336,3 @@ def schur_eigs_closed_form(eig_s0: np.ndarray, gamma: float) -> np.ndarray:
 def cg_iteration_bound(kappa: float, tol: float) -> int:
     """Classical CG bound: iterations <= ceil(0.5 sqrt(kappa) ln(2/tol))."""
     return int(np.ceil(0.5 * np.sqrt(kappa) * np.log(2.0 / tol)))
-
-
-def conjugate_gradient(apply_S, c: np.ndarray, tol: float, maxit: int):
-    """Plain CG from y0 = 0 on S y = c, stopped when ||r_k||_2 <= tol ||c||_2.
-
-    Returns (y, iterations, status) with status 'ok', 'maxit' or 'breakdown'
-    (p^T S p <= 0).
-    """
-    y = np.zeros_like(c)
-    r = c.copy()
-    p = r.copy()
-    rr = float(r @ r)
-    cn = float(np.sqrt(c @ c))
-    if np.sqrt(rr) <= tol * cn:
-        return y, 0, "ok"
-    for it in range(1, maxit + 1):
-        q = apply_S(p)
-        pq = float(p @ q)
-        if not pq > 0.0:
-            return y, it, "breakdown"
-        a = rr / pq
-        y += a * p
-        r -= a * q
-        rr_new = float(r @ r)
-        if np.sqrt(rr_new) <= tol * cn:
-            return y, it, "ok"
-        p = r + (rr_new / rr) * p
-        rr = rr_new
-    return y, maxit, "maxit"

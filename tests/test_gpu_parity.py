@@ -2,17 +2,27 @@
 
 Tolerances (stated per test):
   * backward error eta_inf <= 1e-10 in every case (the library's gate);
-  * relative forward error <= 1e-8 where Sigma is well conditioned
-    (Sigma in [1e-2, 1e2]); at the paper-scale shape Sigma spans
-    [1e-8, 1e8] and K's condition number reaches ~1e9, so there the forward
-    difference to the oracle is bounded by cond(K) * 1e-15 instead;
-  * HyKKT: forward error <= 1e-8 against the saddle-point LDL^T for
-    gamma in {1e4, 1e6, 1e7, 1e8}, eta on the 2x2 system <= 1e-10, CG
-    iteration count within one of the oracle's.
+  * Lifted-KKT, Sigma in [1e-2, 1e2]: relative forward error <= 1e-8 and,
+    entry by entry, |x - x*| <= 1e-8 |x*| + 1e-12 ||x*||_inf (tests/checks.py);
+    wider Sigma ranges: forward error <= 1e-13 cond_2(K);
+  * HyKKT: dx and dy each within a relative forward error of 1e-8 of the
+    saddle-point LDL^T for gamma in {1e4, 1e6, 1e7, 1e8} (normwise: the
+    error HyKKT adds grows with gamma and is not small entry by entry; the
+    oracle's own CG and its LDL^T differ by up to 6e-7 componentwise at
+    gamma = 1e8), eta on the 2x2 system <= 1e-10, CG iteration count within
+    one of the oracle's;
+  * HyKKT with Sigma_x ~ logU[1e-8, 1e8] on the small system (saddle condition
+    number ~1e15): eta <= 1e-10, forward error <= 1e-7 against Bunch-Kaufman,
+    CG count within two of the oracle's;
+  * HyKKT at paper scale: CG count within one of the oracle's for each value
+    set, eta <= 1e-10, dx and dy within 1e-6 of the saddle-point LDL^T (the
+    oracle's CG and LDL^T themselves differ by 8e-8 there: J is nearly
+    singular, sigma_min ~ 1e-4).
 """
 import numpy as np
 import pytest
 
+import checks
 import kktgen
 from oracle import dense as D
 from oracle import sparse as S
@@ -66,7 +76,7 @@ def test_small_lifted(kkt, kw, seed):
     assert info["eta"] <= 1e-10 and be["eta"] <= 1e-10
     # at eta ~ 1e-17 both values are rounding noise of the residual itself
     assert abs(info["eta"] - be["eta"]) <= max(0.5 * be["eta"], 1e-15)
-    assert D.forward_error(x, xs) <= 1e-8
+    checks.assert_well_conditioned(x, xs)
 
 
 def test_small_ill_conditioned(kkt):
@@ -78,8 +88,7 @@ def test_small_ill_conditioned(kkt):
     be = D.backward_errors(K, x, v.b)
     assert be["eta"] <= 1e-10 and info["eta"] <= 1e-10
     xo, _ = S.lifted_solve(pat, v, v.b)
-    cond = np.linalg.cond(K.toarray())
-    assert D.forward_error(x, xo) <= 1e-15 * cond * 100
+    checks.assert_cond_bounded(x, xo, K)
 
 
 def test_not_spd_detected(kkt):
@@ -121,7 +130,8 @@ def test_refactor_new_values_same_factor(kkt):
         x = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
         info = f.solve(dev(v.b), x)
         xs, _ = D.lifted_solution(pat, v, v.b)
-        assert info["eta"] <= 1e-10 and D.forward_error(host(x), xs) <= 1e-8
+        assert info["eta"] <= 1e-10
+        checks.assert_well_conditioned(host(x), xs, vs)
 
 
 def test_matvec(kkt):
@@ -192,7 +202,7 @@ def test_hykkt_gamma(kkt, gamma):
     info = f.cg_schur(dev(v.f), dev(v.g), dx, dy, tol=1e-10, maxit=200)
     assert info["status"] == 0
     dxh, dyh = host(dx), host(dy)
-    assert D.forward_error(dxh, dx0) <= 1e-8
+    assert D.forward_error(dxh, dx0) <= 1e-8 and D.forward_error(dyh, dy0) <= 1e-8
     assert D.hykkt_backward_errors(pat, v, dxh, dyh, v.f, v.g)["eta"] <= 1e-10
     _, _, oinfo = S.hykkt_cg_solve(pat, v, v.f, v.g, gamma, tol=1e-10)
     assert abs(info["iters"] - oinfo["iters"]) <= 1
@@ -261,7 +271,8 @@ def test_tall_fronts(kkt, shape, opts):
     K = D.condensed(pat, v, v.sigma_s)
     assert D.backward_errors(K, xs[0], v.b)["eta"] <= 1e-10
     xo, oinfo = S.lifted_solve(pat, v, v.b)
-    assert oinfo["spd"] and D.forward_error(xs[0], xo) <= 1e-8
+    assert oinfo["spd"]
+    checks.assert_well_conditioned(xs[0], xo)
     assert np.array_equal(xs[0], xs[1])
 
 
@@ -283,6 +294,59 @@ def test_hykkt_larger_system(kkt):
     assert info["status"] == 0
     dxh, dyh = host(dx), host(dy)
     assert D.hykkt_backward_errors(pat, v, dxh, dyh, v.f, v.g)["eta"] <= 1e-10
-    assert D.forward_error(dxh, dx0) <= 1e-8
+    assert D.forward_error(dxh, dx0) <= 1e-8 and D.forward_error(dyh, dy0) <= 1e-8
     _, _, oinfo = S.hykkt_cg_solve(pat, v, v.f, v.g, 1e7, tol=1e-10)
     assert abs(info["iters"] - oinfo["iters"]) <= 1
+
+
+@pytest.mark.parametrize("inst", [0, 1, 2])
+def test_hykkt_wide_sigma(kkt, inst):
+    """HyKKT on the small NMPC pattern with the late-iteration range
+    Sigma_x ~ logU[1e-8, 1e8], gamma = 1e7 (section "Solution 2: HyKKT"):
+    the saddle system's condition number is ~1e15, yet CG converges (the
+    Schur spectrum 1/(gamma + 1/lambda(S_0)) stays clustered) and (dx, dy)
+    match Bunch-Kaufman on the saddle system to 1e-7, eta <= 1e-10 on it, CG
+    count within two of the oracle's."""
+    pat, _ = kktgen.small_config()
+    v = kktgen.nmpc_values(pat, kktgen.rng_for(2, inst, 9), 1e-8, 1e8)
+    print(f"hykkt wide sigma inst={inst}", flush=True)
+    dxb, dyb, inn = D.hykkt_solution(pat, v, v.f, v.g, 0.0)
+    assert inn == (pat.n, 0, pat.m)
+    f = kkt.Factor(kkt.Symbolic.from_pattern(pat, ordering=2, nd_leaf=64))
+    f.refactor(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), None, 1e7)
+    assert f.status()[0] == 0
+    dx = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
+    dy = torch.zeros(pat.m, dtype=torch.float64, device="cuda")
+    info = f.cg_schur(dev(v.f), dev(v.g), dx, dy, tol=1e-10, maxit=1000)
+    assert info["status"] == 0, info
+    dxh, dyh = host(dx), host(dy)
+    assert D.hykkt_backward_errors(pat, v, dxh, dyh, v.f, v.g)["eta"] <= 1e-10
+    assert D.forward_error(dxh, dxb) <= 1e-7 and D.forward_error(dyh, dyb) <= 1e-7
+    _, _, oinfo = S.hykkt_cg_solve(pat, v, v.f, v.g, 1e7, tol=1e-10, maxit=1000)
+    assert oinfo["status"] == "ok" and abs(info["iters"] - oinfo["iters"]) <= 2, (info, oinfo)
+
+
+def test_hykkt_paper_scale_cg_count(kkt):
+    """HyKKT on the distillation-shaped system at paper scale (n=142,000,
+    Sigma_x ~ logU[1e-2, 1e2], gamma = 1e7, tol 1e-10) with the benchmark's
+    symbolic options: for three value sets the CG iteration count is within
+    one of the oracle's (Cholesky of K_gamma in stage order + the same CG),
+    eta on the 2x2 system <= 1e-10, and dx, dy within 1e-6 of the saddle-point
+    LDL^T (the two oracle routes differ by 8e-8 there)."""
+    pat, _ = kktgen.paper_config()
+    f = kkt.Factor(kkt.Symbolic.from_pattern(pat, ordering=2, nd_leaf=417, max_super=96))
+    dx = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
+    dy = torch.zeros(pat.m, dtype=torch.float64, device="cuda")
+    for vs in range(3):
+        v = kktgen.distillation_values(pat, kktgen.rng_for(1, 0, vs), 1e-2, 1e2)
+        print(f"paper-scale hykkt value set {vs}", flush=True)
+        f.refactor(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), None, 1e7)
+        info = f.cg_schur(dev(v.f), dev(v.g), dx, dy, tol=1e-10, maxit=200)
+        assert info["status"] == 0, info
+        dxh, dyh = host(dx), host(dy)
+        _, _, oinfo = S.hykkt_cg_solve(pat, v, v.f, v.g, 1e7, tol=1e-10, maxit=200)
+        print(vs, info, oinfo, flush=True)
+        assert oinfo["status"] == "ok" and abs(info["iters"] - oinfo["iters"]) <= 1
+        assert D.hykkt_backward_errors(pat, v, dxh, dyh, v.f, v.g)["eta"] <= 1e-10
+        dx0, dy0, _, ok = S.hykkt_saddle_solve(pat, v, v.f, v.g)
+        assert ok and D.forward_error(dxh, dx0) <= 1e-6 and D.forward_error(dyh, dy0) <= 1e-6

@@ -16,6 +16,7 @@ arrays between them.
 import numpy as np
 import pytest
 
+import checks
 import kktgen
 from oracle import dense as D
 from oracle import sparse as S
@@ -65,6 +66,10 @@ def test_queue_matches_levels_plain(kkt, case):
     assert D.backward_errors(K, xq, v.b)["eta"] <= 1e-10
     xo, oinfo = S.lifted_solve(pat, v, v.b)
     assert oinfo["spd"]
+    if case.startswith("nmpc"):
+        checks.assert_well_conditioned(xq, xo)
+    else:
+        checks.assert_cond_bounded(xq, xo, K)
 
 
 def make_batch(count, shrink, value_set=1):
@@ -79,6 +84,18 @@ def make_batch(count, shrink, value_set=1):
 
 def concat(vals, field):
     return np.concatenate([getattr(v, field) for v in vals])
+
+
+def check_against_oracle(pats, vals, x, n_ofs, which):
+    """eta <= 1e-10 and the cond-bounded forward error against the oracle's x*
+    for the instances in `which` (Sigma ~ logU[1e-6, 1e6])."""
+    for q in which:
+        xq = x[n_ofs[q]:n_ofs[q + 1]]
+        K = D.condensed(pats[q], vals[q], vals[q].sigma_s)
+        assert D.backward_errors(K, xq, vals[q].b)["eta"] <= 1e-10, q
+        xo, oinfo = S.lifted_solve(pats[q], vals[q], vals[q].b)
+        assert oinfo["spd"], q
+        checks.assert_cond_bounded(xq, xo, K, q)
 
 
 def batch_eager(B, vals, schedule):
@@ -101,8 +118,7 @@ def test_queue_matches_levels_batch(kkt):
     n_ofs = B.ofs["n"]
     for q in range(count):
         assert il[q]["iters"] == iq[q]["iters"]
-        K = D.condensed(pats[q], vals[q], vals[q].sigma_s)
-        assert D.backward_errors(K, xq[n_ofs[q]:n_ofs[q + 1]], vals[q].b)["eta"] <= 1e-10
+    check_against_oracle(pats, vals, xq, n_ofs, range(count))
 
 
 def test_queue_failure_isolated(kkt):
@@ -129,6 +145,7 @@ def test_graph_replays_match_eager(kkt, schedule, rounds):
     B = kkt.Batch(syms)
     xa, ia = batch_eager(B, vals_a, schedule)
     xb, ib = batch_eager(B, vals_b, schedule)
+    check_against_oracle(pats, vals_a, xa, B.ofs["n"], range(count))
     # arrays bound to the graph
     bufs = {f: dev(concat(vals_a, f)) for f in ("w_vals", "j_vals", "sigma_x", "sigma_s", "b")}
     x = torch.full((int(B.ofs["n"][-1]),), np.nan, dtype=torch.float64, device="cuda")
@@ -166,6 +183,7 @@ def test_queue_full_batch_repeated(kkt):
     syms = [kkt.Symbolic.from_pattern(p, ordering=kkt.ORDER_ND, nd_leaf=256, max_super=96) for p in pats]
     B = kkt.Batch(syms)
     xl, il = batch_eager(B, vals, kkt.SCHEDULE_LEVELS)
+    check_against_oracle(pats, vals, xl, B.ofs["n"], range(0, count, 16))
     for rep in range(4):
         xq, iq = batch_eager(B, vals, kkt.SCHEDULE_QUEUE)
         st, bad = B.status()

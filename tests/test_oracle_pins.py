@@ -398,3 +398,113 @@ def test_planted_mistakes_are_caught(monkeypatch, oracle_lib):
     monkeypatch.setattr(D, "lifted_saddle", bad_saddle)
     assert fails(lambda: test_exact_lifted((2, 2, 1), None))
     monkeypatch.undo()
+
+
+# --------------------------------------------------------------------------
+# the evaluators: backward errors by hand and by their defining perturbations
+# --------------------------------------------------------------------------
+
+def test_backward_errors_hand_computed():
+    """eta, omega and relres of a 3x3 system, worked out by hand.
+
+    A = [[4,-1,0],[-1,4,-1],[0,-1,4]], x = [1,-2,1/2], b = [13/2,-19/2,3]:
+    A x = [6, -19/2, 4], so r = b - A x = [1/2, 0, -1].
+    ||A||_inf = 6 (middle row), ||x||_inf = 2, ||b||_inf = 19/2:
+      eta = 1 / (6*2 + 19/2) = 2/43.
+    |A||x| = [6, 19/2, 4], |A||x| + |b| = [25/2, 19, 7]:
+      omega = max(1/25, 0, 1/7) = 1/7;   relres = 1 / (19/2) = 2/19.
+    """
+    A = np.array([[4.0, -1.0, 0.0], [-1.0, 4.0, -1.0], [0.0, -1.0, 4.0]])
+    x = np.array([1.0, -2.0, 0.5])
+    b = np.array([6.5, -9.5, 3.0])
+    for M in (A, sp.csr_matrix(A)):
+        be = D.backward_errors(M, x, b)
+        assert be["eta"] == pytest.approx(2.0 / 43.0, rel=1e-15)
+        assert be["omega"] == pytest.approx(1.0 / 7.0, rel=1e-15)
+        assert be["relres"] == pytest.approx(2.0 / 19.0, rel=1e-15)
+    # an exact solution has zero backward error; 0/0 rows count as zero
+    be = D.backward_errors(A, np.zeros(3), np.zeros(3))
+    assert be == dict(eta=0.0, omega=0.0, relres=0.0)
+
+
+def test_backward_errors_attained_by_perturbations():
+    """The two backward errors are the sizes of perturbations that make x exact.
+
+    Rigal-Gaches: with z = sign(x_k) e_k (k the largest |x_k|) and
+    t = 1 / (||A|| ||x|| + ||b||), the system (A + ||A|| t r z^T) x = b - ||b|| t r
+    holds exactly, with ||dA|| = eta ||A|| and ||db|| = eta ||b||.
+    Oettli-Prager: with s_i = r_i / (|A||x| + |b|)_i, the rows
+    dA = diag(s) |A| diag(sign x), db = -diag(s) |b| make x exact, with
+    |dA| <= omega |A| and |db| <= omega |b|. Any smaller perturbation leaves a
+    residual, since ||r|| <= eps (||A|| ||x|| + ||b||) (normwise) and
+    |r| <= eps (|A||x| + |b|) (componentwise) for a perturbation of size eps.
+    """
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((7, 7))
+    x = rng.standard_normal(7)
+    b = A @ x + 1e-3 * rng.standard_normal(7)
+    be = D.backward_errors(A, x, b)
+    r = b - A @ x
+    nA = np.abs(A).sum(axis=1).max()
+    k = int(np.argmax(np.abs(x)))
+    z = np.zeros(7)
+    z[k] = np.sign(x[k])
+    t = 1.0 / (nA * np.abs(x).max() + np.abs(b).max())
+    dA = nA * t * np.outer(r, z)
+    db = -np.abs(b).max() * t * r
+    assert np.abs((A + dA) @ x - (b + db)).max() <= 1e-14 * np.abs(b).max()
+    assert np.abs(dA).sum(axis=1).max() == pytest.approx(be["eta"] * nA, rel=1e-12)
+    assert np.abs(db).max() == pytest.approx(be["eta"] * np.abs(b).max(), rel=1e-12)
+    s = r / (np.abs(A) @ np.abs(x) + np.abs(b))
+    dA = s[:, None] * np.abs(A) * np.sign(x)[None, :]
+    db = -s * np.abs(b)
+    assert np.abs((A + dA) @ x - (b + db)).max() <= 1e-14 * np.abs(b).max()
+    assert np.abs(s).max() == pytest.approx(be["omega"], rel=1e-12)
+    assert (np.abs(dA) <= be["omega"] * np.abs(A) * (1 + 1e-12)).all()
+
+
+def test_componentwise_error_hand_computed():
+    """x* = [1000, -2, 1e-9], x = [1000.001, -2, 2e-9], floor 1e-12:
+    entry errors 1e-3 / (1000 + 1e-9), 0, 1e-9 / (1e-9 + 1e-9) = 1/2."""
+    xs = np.array([1000.0, -2.0, 1e-9])
+    x = np.array([1000.001, -2.0, 2e-9])
+    assert D.componentwise_error(x, xs) == pytest.approx(0.5, rel=1e-9)
+    assert D.componentwise_error(x[:2], xs[:2]) == pytest.approx(1e-6, rel=1e-6)
+    assert D.componentwise_error(xs, xs) == 0.0
+
+
+def test_oracle_routes_agree_componentwise(oracle_lib):
+    """Three independent routes to the Lifted-KKT x* (Bunch-Kaufman on the 2x2
+    form, the C sparse LDL^T with refinement, numpy's LU of K) and two to the
+    HyKKT (dx*, dy*) agree entry by entry, not only in norm, on the
+    well-conditioned small workload."""
+    pat, v = kktgen.workload("small")
+    xb, _ = D.lifted_solution(pat, v, v.b)
+    xc, info = S.lifted_solve(pat, v, v.b)
+    xn = np.linalg.solve(D.condensed(pat, v, v.sigma_s).toarray(), v.b)
+    assert D.componentwise_error(xb, xn) <= 1e-11 and D.componentwise_error(xc, xn) <= 1e-11
+    pat, v = kktgen.workload("hykkt")
+    dxb, dyb, _ = D.hykkt_solution(pat, v, v.f, v.g, 0.0)
+    dxs, dys, _, ok = S.hykkt_saddle_solve(pat, v, v.f, v.g)
+    assert ok
+    assert D.componentwise_error(dxs, dxb) <= 1e-10 and D.componentwise_error(dys, dyb) <= 1e-10
+
+
+def test_hykkt_wide_sigma_small_system(oracle_lib):
+    """The small NMPC system with Sigma_x ~ logU[1e-8, 1e8] (late-iteration
+    range) at gamma = 1e7: the Schur CG converges within the closed-form bound,
+    and its (dx, dy) agrees with Bunch-Kaufman on the saddle system although
+    that system's condition number is ~1e15, because the perturbations the
+    wide Sigma_x causes are diagonal scalings the two methods both absorb."""
+    pat, _ = kktgen.small_config()
+    v = kktgen.nmpc_values(pat, kktgen.rng_for(2, 0, 9), 1e-8, 1e8)
+    K0 = D.condensed(pat, v, 0.0).toarray()
+    J = D.jacobian(pat, v).toarray()
+    s0 = np.linalg.eigvalsh(J @ np.linalg.solve(K0, J.T))
+    e = D.schur_eigs_closed_form(s0, 1e7)
+    dxb, dyb, inn = D.hykkt_solution(pat, v, v.f, v.g, 0.0)
+    assert inn == (pat.n, 0, pat.m)
+    dx, dy, info = S.hykkt_cg_solve(pat, v, v.f, v.g, 1e7, tol=1e-10, maxit=1000)
+    assert info["status"] == "ok" and info["iters"] <= D.cg_iteration_bound(e.max() / e.min(), 1e-10)
+    assert D.hykkt_backward_errors(pat, v, dx, dy, v.f, v.g)["eta"] <= 1e-10
+    assert D.forward_error(dx, dxb) <= 1e-7 and D.forward_error(dy, dyb) <= 1e-7
