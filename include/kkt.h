@@ -37,9 +37,12 @@
  *     must keep inputs alive until the stream has passed the call.
  *   - The library owns the symbolic objects, factors and all workspaces.
  *   - Calls that take a `stream` (a hipStream_t; NULL = the default stream)
- *     enqueue their work on it and return without waiting, except that an
- *     entry point given a non-NULL info pointer synchronises the stream and
- *     fills the info.
+ *     enqueue their work on it. kkt_refactor, kkt_matvec, and kkt_solve /
+ *     kkt_cg_schur with info == NULL return without waiting for the device
+ *     (their loop decisions are taken on the device; see each entry point).
+ *     kkt_solve / kkt_cg_schur with a non-NULL info, kkt_status_sync and the
+ *     batched solve synchronise the stream. Inputs must be complete on the
+ *     device, in stream order, when the work enqueued on `stream` reads them.
  *   - No exception crosses the ABI. Host-side validation errors return at
  *     once; errors found on the device (a non-positive pivot, non-finite
  *     values) are latched in the factor and returned by the next
@@ -111,10 +114,20 @@ typedef struct kkt_solve_info {
     double relres;         /* ||b-Kx||_inf / ||b||_inf */
 } kkt_solve_info;
 
+typedef struct kkt_cg_opts {
+    double tol;            /* stop when the recurrence residual ||r||_2 <= tol ||c||_2 (default 1e-10) */
+    int32_t maxit;         /* iteration limit (default 200) */
+    double eta_tol;        /* > 0: also stop once a bound on the saddle system's normwise backward
+                              error is <= eta_tol (default 0: off); see kkt_cg_schur */
+} kkt_cg_opts;
+
 typedef struct kkt_cg_info {
     int32_t status;        /* KKT_OK, KKT_ERR_NOT_CONVERGED, KKT_ERR_BREAKDOWN, KKT_ERR_NOT_SPD */
     int32_t iters;         /* CG iterations */
     double rel_res;        /* recurrence residual ||r||_2 / ||c||_2 at exit */
+    double eta;            /* normwise backward error of (dx, dy) on [[W + Sx, J^T], [J, 0]]:
+                              ||res||_inf / (||A||_inf ||(dx, dy)||_inf + ||(f, g)||_inf) */
+    int32_t eta_stop;      /* 1: stopped by the eta bound (eta_tol), 0: by tol, maxit or a breakdown */
 } kkt_cg_info;
 
 typedef struct kkt_factor_info {
@@ -199,27 +212,53 @@ kkt_status kkt_status_sync(kkt_factor* f, kkt_factor_info* info);
  * factor: a forward and backward sweep, then Richardson refinement
  * r = b - K x, x += K^{-1} r, stopping when omega <= ro->tol, after
  * ro->max_iter corrections, or when omega fails to halve; the iterate with the
- * smaller omega of the last two is returned. b and x are device arrays of n
- * (x may not alias b). ro may be NULL (defaults). With info == NULL the call
- * is asynchronous; otherwise it synchronises and returns KKT_ERR_NOT_SPD if
- * the factor failed or KKT_ERR_NOT_CONVERGED if omega > tol at exit (x still
- * holds the best iterate).
+ * smaller omega of the last two is returned (section "Hybrid linear solver":
+ * the Cholesky solve followed by iterative refinement). b and x are device
+ * arrays of n (x may not alias b). ro may be NULL (defaults).
+ *   info != NULL: the host reads each stop decision (one synchronisation per
+ *     round), then synchronises once more and returns KKT_ERR_NOT_SPD if the
+ *     factor failed or KKT_ERR_NOT_CONVERGED if omega > tol at exit (x still
+ *     holds the best iterate).
+ *   info == NULL: asynchronous. The first solve and ro->max_iter refinement
+ *     rounds are enqueued; the stop rule is evaluated on the device and the
+ *     kernels of the rounds after it fired return at once, so x is the same
+ *     bit for bit as with info. Nothing is read back: a failed factor is
+ *     reported by kkt_status_sync (x is then meaningless).
  */
 kkt_status kkt_solve(kkt_factor* f, const double* b, double* x, const kkt_refine_opts* ro,
                      kkt_solve_info* info, void* stream);
 
+/* Fills *o with the CG defaults (tol 1e-10, maxit 200, eta_tol 0). */
+void kkt_cg_opts_default(kkt_cg_opts* o);
+
 /*
- * HyKKT (eqs. (hykkt), (schurcomp)): with f factored as K_gamma (sigma_s NULL,
- * gamma > 0), solves [[W + Sx, J^T], [J, 0]] [dx; dy] = [fv; g]:
+ * HyKKT (section "Solution 2: HyKKT", eqs. (hykkt), (schurcomp)): with f
+ * factored as K_gamma (sigma_s NULL, gamma > 0), solves
+ * [[W + Sx, J^T], [J, 0]] [dx; dy] = [fv; g]:
  *   f_gamma = fv + gamma J^T g;  c = J K_gamma^{-1} f_gamma - g;
- *   CG from dy = 0 on S_gamma dy = c, S_gamma = J K_gamma^{-1} J^T (matrix-free),
- *   until ||r||_2 <= tol ||c||_2 or maxit iterations;
- *   dx = K_gamma^{-1}(f_gamma - J^T dy).
- * fv (n), g (m), dx (n), dy (m) are device arrays. Returns STATE on a
- * Lifted-KKT factor. With info == NULL the call is asynchronous; otherwise it
- * synchronises and reports NOT_SPD / NOT_CONVERGED / BREAKDOWN.
+ *   CG from dy = 0 on S_gamma dy = c, S_gamma = J K_gamma^{-1} J^T (matrix-free,
+ *   one sweep pair per iteration), stopping when ||r||_2 <= tol ||c||_2, or
+ *   (eta_tol > 0) when max(gamma ||J^T r||_inf, ||r||_inf) / (||A||_inf
+ *   ||dy||_inf + ||(fv, g)||_inf) <= eta_tol -- an upper bound on the saddle
+ *   system's normwise backward error, since with dx below its residual is
+ *   (gamma J^T r, r) -- or after maxit iterations;
+ *   dx = K_gamma^{-1}(f_gamma - J^T dy);
+ *   then the saddle-system residual of (dx, dy) and its normwise backward
+ *   error eta (kkt_cg_info.eta).
+ * fv (n), g (m), dx (n), dy (m) are device arrays; opts may be NULL
+ * (defaults). Needs m <= n (J of full row rank). Errors: INVALID_ARG, STATE
+ * (no K_gamma factor, e.g. a Lifted-KKT factor).
+ *   info != NULL: synchronises once before the iterations (a failed factor
+ *     returns NOT_SPD / NONFINITE) and once per iteration (one iteration of
+ *     lookahead), and returns NOT_CONVERGED or BREAKDOWN as they occur.
+ *   info == NULL: asynchronous; all maxit iterations are enqueued and the
+ *     stop decisions are taken on the device (the kernels of the iterations
+ *     after the stop return at once), so dx, dy are the same bit for bit as
+ *     with info. Each queued iteration costs launches even when it does
+ *     nothing: choose maxit near the expected count. A failed factor is
+ *     reported by kkt_status_sync.
  */
-kkt_status kkt_cg_schur(kkt_factor* f, const double* fv, const double* g, double tol, int32_t maxit,
+kkt_status kkt_cg_schur(kkt_factor* f, const double* fv, const double* g, const kkt_cg_opts* opts,
                         double* dx, double* dy, kkt_cg_info* info, void* stream);
 
 /* Matrix-vector product y = K x with the assembled K of the current factor

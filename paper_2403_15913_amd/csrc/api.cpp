@@ -153,6 +153,25 @@ hipError_t DevPattern::build(const Symbolic& S) {
     UP(b_jte, jt_e, jt_e, int)
     UP(b_jtrow, jt_row, jt_row, int)
 #undef UP
+    // J by columns in pivot order, and the pivot position of every J entry's
+    // column (the CG reads and writes the sweep vector directly)
+    std::vector<int> tp(S.n + 1, 0), trow(S.jt_row.size()), te(S.jt_e.size()), colp(S.j_col.size());
+    for (int k = 0; k < S.n; k++) {
+        const int j = S.perm[k];
+        tp[k + 1] = tp[k] + (S.jt_ptr[j + 1] - S.jt_ptr[j]);
+        for (int q = S.jt_ptr[j], o = tp[k]; q < S.jt_ptr[j + 1]; q++, o++) {
+            trow[o] = S.jt_row[q];
+            te[o] = S.jt_e[q];
+        }
+    }
+    for (size_t p = 0; p < S.j_col.size(); p++) colp[p] = S.iperm[S.j_col[p]];
+    if ((e = upload(b_jtpptr, tp)) != hipSuccess || (e = upload(b_jtprow, trow)) != hipSuccess ||
+        (e = upload(b_jtpe, te)) != hipSuccess || (e = upload(b_jcolp, colp)) != hipSuccess)
+        return e;
+    desc.jtp_ptr = (const int*)b_jtpptr.p;
+    desc.jtp_row = (const int*)b_jtprow.p;
+    desc.jtp_e = (const int*)b_jtpe.p;
+    desc.j_colp = (const int*)b_jcolp.p;
     return hipSuccess;
 }
 
@@ -224,7 +243,8 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         ko[q + 1] = ko[q] + S.nnzk;
         co[q + 1] = co[q] + S.sp_ptr[S.n];
         po[q + 1] = po[q] + 5 * (int64_t)((S.n + kBlock - 1) / kBlock) * kResidualSplit;
-        ro[q + 1] = ro[q] + (std::max(S.n, S.m) + kBlock - 1) / kBlock + 1;
+        // CG reduction slots: 4 per 256-row block of n, then 4 per block of m
+        ro[q + 1] = ro[q] + 4 * (int64_t)((S.n + kBlock - 1) / kBlock + (S.m + kBlock - 1) / kBlock + 1);
         for (int k = 0; k < S.ns; k++) {
             lds_factor = std::max(lds_factor, (size_t)factor_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]));
             lds_solve = std::max(lds_solve, (size_t)solve_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]));
@@ -252,14 +272,16 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     y = cv.take<double>(N);
     r = cv.take<double>(N);
     xprev = cv.take<double>(N);
-    tn = cv.take<double>(N);
     fg = cv.take<double>(N);
     cvec = cv.take<double>(M);
     rvec = cv.take<double>(M);
     pvec = cv.take<double>(M);
+    pvec2 = cv.take<double>(M);
     qvec = cv.take<double>(M);
     red = cv.take<double>(ro[ninst]);
     jcopy = cv.take<double>(j_ofs[ninst]);
+    jtv = hykkt_storage ? cv.take<double>(j_ofs[ninst]) : nullptr;
+    k0csr = hykkt_storage ? cv.take<double>(co[ninst]) : nullptr;
     status = cv.take<int>(2 * (size_t)ninst);
     ndone = cv.take<int>(4);
     rs = cv.take<RefineState>(ninst);
@@ -311,12 +333,14 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         I.y = y + n_ofs[q];
         I.r = r + n_ofs[q];
         I.xprev = xprev + n_ofs[q];
-        I.tn = tn + n_ofs[q];
         I.fg = fg + n_ofs[q];
         I.cvec = cvec + m_ofs[q];
         I.rvec = rvec + m_ofs[q];
         I.pvec = pvec + m_ofs[q];
+        I.pvec2 = pvec2 + m_ofs[q];
         I.qvec = qvec + m_ofs[q];
+        I.jtv = jtv ? jtv + j_ofs[q] : nullptr;
+        I.k0csr = k0csr ? k0csr + co[q] : nullptr;
         I.red = red + ro[q];
         I.status = status + 2 * q;
         I.rs = rs + q;
@@ -415,6 +439,7 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         F.dinv = I.dinv + F.col0;
         F.rw = PD.rows + S.sn_rowofs[k] + F.c;
         F.done = (const int*)((const char*)I.rs + offsetof(RefineState, done));
+        F.cgdone = (const int*)((const char*)I.cg + offsetof(CgState, done));
         F.ch0 = S.ch_ptr[k];
         F.nch = S.ch_ptr[k + 1] - S.ch_ptr[k];
         for (int j = 0; j < 2 && j < F.nch; j++) {
@@ -508,6 +533,11 @@ kkt_status Engine::init_owned(const std::vector<const Symbolic*>& s) {
     size_t need = 0;
     if ((st = place(s, p, nullptr, 0, false, nullptr, &need)) != KKT_OK) return st;
     if ((e = own.alloc(need)) != hipSuccess) return hip_fail(e, "device allocation");
+    // control events of the refinement and CG loops (created here, so that
+    // no solve call allocates)
+    if ((e = hipEventCreateWithFlags(&ctl_event, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&ctl_event2, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "control events");
     if ((st = place(s, p, (char*)own.p, need, false, nullptr, nullptr)) != KKT_OK) return st;
     if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) return hip_fail(e, "init");
     return KKT_OK;
@@ -553,10 +583,7 @@ kkt_status Engine::refactor(const Calls& C, hipStream_t st) {
             if (split) TL(KKT_PHASE_FACTOR, launch_update(di(), fdesc, upitems + up_ptr[l], up_ptr[l + 1] - up_ptr[l], st));
         }
     }
-    if (mode == 2 && j_ofs[ninst] > 0) {
-        hipError_t e = hipMemcpyAsync(jcopy, C.jv, (size_t)j_ofs[ninst] * 8, hipMemcpyDeviceToDevice, st);
-        if (e != hipSuccess) return hip_fail(e, "copy J values");
-    }
+    if (mode == 2) TL(KKT_PHASE_ASSEMBLE, launch_jcopy(di(), C, jitems, n_jitems, st));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "refactor launch");
     factored = true;
@@ -612,7 +639,7 @@ void Engine::solve_start(const Calls& C, int maxit, double tol, hipStream_t st) 
     TL(KKT_PHASE_CONTROL, launch_refine_reset(di(), ninst, tol, maxit, st));
     TL(KKT_PHASE_CONTROL, launch_fill_i32(ndone, 0, 1, st));
     TL(KKT_PHASE_PERMUTE, launch_perm_in(di(), C, nitems, n_nitems, PIN_B, st));
-    sweeps(st, 0);
+    sweeps(st, SKIP_NONE);
     TL(KKT_PHASE_PERMUTE, launch_perm_out(di(), C, nitems, n_nitems, POUT_X, st));
 }
 
@@ -625,7 +652,7 @@ void Engine::refine_check(const Calls& C, hipStream_t st) {
 // one correction x += K^{-1} r of every instance still refining
 void Engine::refine_correct(const Calls& C, hipStream_t st) {
     TL(KKT_PHASE_PERMUTE, launch_perm_in(di(), C, nitems, n_nitems, PIN_R, st));
-    sweeps(st, 1);
+    sweeps(st, SKIP_REFINE);
     TL(KKT_PHASE_PERMUTE, launch_perm_out(di(), C, nitems, n_nitems, POUT_X_UPDATE, st));
 }
 
@@ -633,6 +660,19 @@ kkt_status Engine::solve(const Calls& C, int maxit, double tol, kkt_solve_info* 
     last_stream = st;
     solve_start(C, maxit, tol, st);
     return solve_finish(C, 0, maxit, tol, infos, st);
+}
+
+// The same operations as the host-driven loop of solve_finish in its longest
+// case (maxit + 1 checks, maxit corrections); the refinement kernels and the
+// sweeps of an instance that has stopped return at once, so the result is
+// the same bit for bit and nothing is read back.
+void Engine::solve_rounds(const Calls& C, int maxit, hipStream_t st) {
+    refine_check(C, st);
+    for (int q = 0; q < maxit; q++) {
+        refine_correct(C, st);
+        refine_check(C, st);
+    }
+    TL(KKT_PHASE_PERMUTE, launch_refine_revert(di(), C, nitems, n_nitems, st));
 }
 
 // Host-driven refinement from round `iter0` on: check, stop when every
@@ -766,64 +806,64 @@ kkt_status Engine::replay(kkt_solve_info* infos, hipStream_t st) {
     return solve_finish(g_calls, g_rounds, g_maxit, g_tol, infos, st);
 }
 
-kkt_status Engine::cg_schur(const Calls& C, double tol, int maxit, kkt_cg_info* info, hipStream_t st) {
+// One CG iteration (three launches around the sweep pair; see the CG kernels).
+// `parity` alternates the two direction buffers.
+void Engine::cg_iteration(int parity, hipStream_t st) {
+    TL(KKT_PHASE_CG, launch_cg_dir(di(), cg_calls, nitems, n_nitems, parity, ndone, st));
+    sweeps(st, SKIP_CG);
+    TL(KKT_PHASE_CG, launch_cg_q(di(), mitems, n_mitems, parity, ndone, st));
+    TL(KKT_PHASE_CG, launch_cg_upd(di(), cg_calls, mitems, n_mitems, parity, ndone, st));
+}
+
+kkt_status Engine::cg_schur(const Calls& C, double tol, int maxit, double eta_tol, kkt_cg_info* info,
+                            hipStream_t st) {
     last_stream = st;
-    const WorkItem* nit = nitems;
-    const WorkItem* mit = mitems;
+    cg_calls = C;
     int* nd = ndone;
-    int* hp = (int*)hpin;
     TL(KKT_PHASE_CONTROL, launch_fill_i32(nd, 0, 1, st));
-    TL(KKT_PHASE_CG, launch_cg_fgamma(di(), C, nit, n_nitems, st));
-    TL(KKT_PHASE_PERMUTE, launch_perm_in(di(), C, nit, n_nitems, PIN_FG, st));
-    sweeps(st, 0);
-    TL(KKT_PHASE_PERMUTE, launch_perm_out(di(), C, nit, n_nitems, POUT_TN, st));
-    TL(KKT_PHASE_CG, launch_cg_init(di(), C, mit, n_mitems, st));
-    TL(KKT_PHASE_CONTROL, launch_cg_start(di(), ninst, tol, maxit, nd, st));
-    hipError_t e = hipMemcpyAsync(hp, nd, 4, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail(e, "cg control");
-    const int started_done = hp[0];
-    kkt_status fst = read_status(nullptr, nullptr);
-    if (fst != KKT_OK) return fail(fst, "factor failed; solve refused");
-    // CG iterations with one iteration of lookahead: iteration k+1 is queued
-    // before the host reads the count of stopped instances after iteration
-    // k. The CG kernels skip stopped instances, the work vector t is rebuilt
-    // from scratch for dx below, and no instance gets more than maxit
-    // iterations, so the lookahead changes no result.
-    if (!ctl_event && (e = hipEventCreateWithFlags(&ctl_event, hipEventDisableTiming)) != hipSuccess)
-        return hip_fail(e, "cg control event");
-    if (!ctl_event2 && (e = hipEventCreateWithFlags(&ctl_event2, hipEventDisableTiming)) != hipSuccess)
-        return hip_fail(e, "cg control event");
-    volatile int* slot[2] = {(volatile int*)hpin, (volatile int*)hpin + 16};
-    hipEvent_t ev[2] = {ctl_event, ctl_event2};
-    auto issue = [&](int k) -> hipError_t {
-        TL(KKT_PHASE_CG, launch_cg_jt(di(), C, nit, n_nitems, 0, st));
-        TL(KKT_PHASE_PERMUTE, launch_perm_in(di(), C, nit, n_nitems, PIN_TN, st));
-        sweeps(st, 0);
-        TL(KKT_PHASE_PERMUTE, launch_perm_out(di(), C, nit, n_nitems, POUT_TN, st));
-        TL(KKT_PHASE_CG, launch_cg_jq(di(), C, mit, n_mitems, st));
-        TL(KKT_PHASE_CONTROL, launch_cg_alpha(di(), ninst, nd, st));
-        TL(KKT_PHASE_CG, launch_cg_update(di(), C, mit, n_mitems, st));
-        TL(KKT_PHASE_CONTROL, launch_cg_beta(di(), ninst, nd, st));
-        TL(KKT_PHASE_CG, launch_cg_p(di(), mit, n_mitems, st));
-        hipError_t r = hipMemcpyAsync((void*)slot[k & 1], nd, 4, hipMemcpyDeviceToHost, st);
-        if (r == hipSuccess) r = hipEventRecord(ev[k & 1], st);
-        return r;
-    };
-    int issued = 0;
-    if (started_done < ninst) {
-        while (issued < maxit && issued < 2)
-            if ((e = issue(issued++)) != hipSuccess) return hip_fail(e, "cg control");
-        for (int k = 0; k < issued; k++) {
-            if ((e = hipEventSynchronize(ev[k & 1])) != hipSuccess) return hip_fail(e, "cg control");
-            if (*slot[k & 1] >= ninst) break;
-            if (issued < maxit && (e = issue(issued++)) != hipSuccess) return hip_fail(e, "cg control");
+    // f_gamma = f + gamma J^T g (pivot order), c = J K_gamma^{-1} f_gamma - g
+    TL(KKT_PHASE_CG, launch_cg_fg(di(), C, nitems, n_nitems, st));
+    sweeps(st, SKIP_NONE);
+    TL(KKT_PHASE_CG, launch_cg_c(di(), C, mitems, n_mitems, tol, maxit, eta_tol, nd, st));
+    hipError_t e = hipSuccess;
+    if (!info) {
+        // asynchronous: all maxit iterations are queued; once an instance's
+        // CG has stopped, its kernels of the later iterations return at once
+        for (int k = 0; k < maxit; k++) cg_iteration(k & 1, st);
+    } else {
+        // With one iteration of lookahead: iteration k+1 is queued before
+        // the host reads the count of stopped instances after iteration k.
+        // The kernels of a stopped instance return at once, so the queued
+        // iteration changes nothing.
+        volatile int* slot[2] = {(volatile int*)hpin, (volatile int*)hpin + 16};
+        hipEvent_t ev[2] = {ctl_event, ctl_event2};
+        auto issue = [&](int k) -> hipError_t {
+            cg_iteration(k & 1, st);
+            hipError_t r = hipMemcpyAsync((void*)slot[k & 1], nd, 4, hipMemcpyDeviceToHost, st);
+            if (r == hipSuccess) r = hipEventRecord(ev[k & 1], st);
+            return r;
+        };
+        if ((e = hipMemcpyAsync((void*)slot[1], nd, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess)
+            return hip_fail(e, "cg control");
+        kkt_status fst = read_status(nullptr, nullptr);
+        if (fst != KKT_OK) return fail(fst, "factor failed; solve refused");
+        int issued = 0;
+        if (*slot[1] < ninst) {
+            while (issued < maxit && issued < 2)
+                if ((e = issue(issued++)) != hipSuccess) return hip_fail(e, "cg control");
+            for (int k = 0; k < issued; k++) {
+                if ((e = hipEventSynchronize(ev[k & 1])) != hipSuccess) return hip_fail(e, "cg control");
+                if (*slot[k & 1] >= ninst) break;
+                if (issued < maxit && (e = issue(issued++)) != hipSuccess) return hip_fail(e, "cg control");
+            }
         }
     }
-    TL(KKT_PHASE_CG, launch_cg_jt(di(), C, nit, n_nitems, 1, st));
-    TL(KKT_PHASE_PERMUTE, launch_perm_in(di(), C, nit, n_nitems, PIN_TN, st));
-    sweeps(st, 0);
-    TL(KKT_PHASE_PERMUTE, launch_perm_out(di(), C, nit, n_nitems, POUT_DX, st));
+    // dx = K_gamma^{-1}(f_gamma - J^T dy), then the saddle-system residual and eta
+    TL(KKT_PHASE_CG, launch_cg_dxrhs(di(), C, nitems, n_nitems, st));
+    sweeps(st, SKIP_NONE);
+    TL(KKT_PHASE_PERMUTE, launch_perm_out(di(), C, nitems, n_nitems, POUT_DX, st));
+    TL(KKT_PHASE_RESIDUAL, launch_cg_residual(di(), C, nitems, n_nitems, mitems, n_mitems, st));
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "cg launch");
     if (!info) return KKT_OK;
@@ -833,8 +873,9 @@ kkt_status Engine::cg_schur(const Calls& C, double tol, int maxit, kkt_cg_info* 
     CgState G;
     std::memcpy(&G, hpin, sizeof(G));
     info->iters = G.it;
-    const double rr = (G.it > 0 && G.status == 0 && G.done) ? G.rr_new : G.rr;
-    info->rel_res = G.cnorm > 0 ? std::sqrt(rr) / G.cnorm : 0.0;
+    info->rel_res = G.cnorm > 0 ? std::sqrt(G.rr_new) / G.cnorm : 0.0;
+    info->eta = G.eta;
+    info->eta_stop = G.eta_stop;
     info->status = G.status == 0 ? (G.done ? KKT_OK : KKT_ERR_NOT_CONVERGED) : G.status;
     return info->status;
 }
@@ -956,6 +997,7 @@ kkt_status kkt_factor_create(const kkt_symbolic* sym, kkt_factor** out) {
     kkt_factor* f = new (std::nothrow) kkt_factor;
     if (!f) return fail(KKT_ERR_OOM, "host allocation");
     f->sym = sym;
+    f->eng.hykkt_storage = true;
     kkt_status st = f->eng.init_owned({&sym->S});
     if (st != KKT_OK) {
         delete f;
@@ -1013,22 +1055,39 @@ kkt_status kkt_solve(kkt_factor* f, const double* b, double* x, const kkt_refine
     std::memset(&C, 0, sizeof(C));
     C.b = b;
     C.x = x;
-    return f->eng.solve(C, maxit, tol, info, (hipStream_t)stream);
+    Engine& E = f->eng;
+    const hipStream_t st = (hipStream_t)stream;
+    if (info) return E.solve(C, maxit, tol, info, st);
+    E.last_stream = st;
+    E.solve_start(C, maxit, tol, st);
+    E.solve_rounds(C, maxit, st);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? KKT_OK : hip_fail(e, "solve launch");
 }
 
-kkt_status kkt_cg_schur(kkt_factor* f, const double* fv, const double* g, double tol, int32_t maxit, double* dx,
+void kkt_cg_opts_default(kkt_cg_opts* o) {
+    if (!o) return;
+    o->tol = 1e-10;
+    o->maxit = 200;
+    o->eta_tol = 0.0;
+}
+
+kkt_status kkt_cg_schur(kkt_factor* f, const double* fv, const double* g, const kkt_cg_opts* opts, double* dx,
                         double* dy, kkt_cg_info* info, void* stream) {
     if (!f) return fail(KKT_ERR_INVALID_ARG, "NULL factor");
     const Symbolic& S = f->sym->S;
     if ((S.n > 0 && (!fv || !dx)) || (S.m > 0 && (!g || !dy))) return fail(KKT_ERR_INVALID_ARG, "NULL vector");
+    if (S.m > S.n) return fail(KKT_ERR_INVALID_ARG, "the Schur system needs m <= n (J of full row rank)");
     if (!f->eng.factored || f->eng.mode != 2) return fail(KKT_ERR_STATE, "cg_schur needs a K_gamma factor");
-    if (maxit < 0 || !(tol >= 0.0)) return fail(KKT_ERR_INVALID_ARG, "bad tol/maxit");
+    kkt_cg_opts o;
+    kkt_cg_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.maxit < 0 || !(o.tol >= 0.0) || !(o.eta_tol >= 0.0)) return fail(KKT_ERR_INVALID_ARG, "bad CG options");
     Calls C;
     std::memset(&C, 0, sizeof(C));
-    C.jv = f->eng.jcopy;
     C.gamma = f->eng.gamma;
     C.f = fv; C.g = g; C.dx = dx; C.dy = dy;
-    return f->eng.cg_schur(C, tol, maxit, info, (hipStream_t)stream);
+    return f->eng.cg_schur(C, o.tol, o.maxit, o.eta_tol, info, (hipStream_t)stream);
 }
 
 kkt_status kkt_matvec(kkt_factor* f, const double* x, double* y, void* stream) {

@@ -43,7 +43,7 @@ struct DevPattern {
     PatDev desc{};
     DevBuf b_col0, b_ncol, b_nrow, b_rowofs, b_lofs, b_uofs, b_vofs, b_rows, b_rel, b_relnp, b_chptr, b_chlist,
         b_ksnptr, b_kloc, b_kw, b_kdiag, b_kpptr, b_pa, b_pb, b_jrow, b_perm, b_iperm, b_spptr, b_kcsr, b_spcol,
-        b_jptr, b_jcol, b_jtptr, b_jte, b_jtrow;
+        b_jptr, b_jcol, b_jtptr, b_jte, b_jtrow, b_jtpptr, b_jtprow, b_jtpe, b_jcolp;
     hipError_t build(const Symbolic& S);
 };
 
@@ -74,8 +74,8 @@ struct Engine {
     DevBuf own;                                     // arena owned by a factor / batch
     // views into the arena
     double *L = nullptr, *U = nullptr, *V = nullptr, *kval = nullptr, *kcsr = nullptr, *rpart = nullptr, *dinv = nullptr, *y = nullptr, *r = nullptr,
-           *xprev = nullptr, *tn = nullptr, *fg = nullptr, *cvec = nullptr, *rvec = nullptr, *pvec = nullptr,
-           *qvec = nullptr, *red = nullptr, *jcopy = nullptr;
+           *xprev = nullptr, *fg = nullptr, *cvec = nullptr, *rvec = nullptr, *pvec = nullptr,
+           *pvec2 = nullptr, *qvec = nullptr, *red = nullptr, *jcopy = nullptr, *jtv = nullptr, *k0csr = nullptr;
     int *status = nullptr, *ndone = nullptr;
     RefineState* rs = nullptr;
     CgState* cg = nullptr;
@@ -89,6 +89,7 @@ struct Engine {
     std::vector<int> lvl_maxu;                      // widest update part of each level
     bool split_update = true;                       // level schedule: update matrices in their own launch
     bool queue_sched = false;                       // dependency-driven launches (else one launch per level)
+    bool hykkt_storage = false;                     // single factors: K0 and J by columns, for the HyKKT CG
     // captured refactor + solve (batched form)
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -142,7 +143,12 @@ struct Engine {
     kkt_status capture(const Calls& C, int maxit, double tol, int rounds);
     kkt_status replay(kkt_solve_info* infos, hipStream_t st);
     void drop_graph();
-    kkt_status cg_schur(const Calls& C, double tol, int maxit, kkt_cg_info* info, hipStream_t st);
+    kkt_status cg_schur(const Calls& C, double tol, int maxit, double eta_tol, kkt_cg_info* info, hipStream_t st);
+    void cg_iteration(int parity, hipStream_t st);
+    Calls cg_calls{};
+    // asynchronous solve: the first solve and max_iter refinement rounds,
+    // every kernel gated by the instance's stop flag, no read-back
+    void solve_rounds(const Calls& C, int maxit, hipStream_t st);
     // waits for st and returns each instance's latched status and failing column (original index)
     kkt_status read_status(int* st_out, int* bad_out);
     kkt_status parse_status(int derr, const int* hs, int* st_out, int* bad_out);

@@ -47,6 +47,12 @@ struct PatDev {
     const int* jt_ptr;
     const int* jt_e;
     const int* jt_row;
+    // J by columns in pivot order: the entries of column perm[k] are
+    // jtp_ptr[k] .. jtp_ptr[k+1], with their rows and CSR entry indices
+    const int* jtp_ptr;
+    const int* jtp_row;
+    const int* jtp_e;
+    const int* j_colp;      // pivot position of the column of every CSR entry of J
 };
 
 struct RefineState {
@@ -58,10 +64,18 @@ struct RefineState {
     int revert;    // 1: the previous iterate is the better one
 };
 
-// Conjugate-gradient scalars of one instance (eq. (schurcomp)).
+// Conjugate-gradient scalars of one instance (eq. (schurcomp)), written by
+// the last workgroup of each reduction (see cg_last_block).
 struct CgState {
     double rr, rr_new, pq, cnorm, alpha, beta, tol;
+    double eta_tol;          // > 0: also stop once the saddle system's eta bound is below it
+    double norm_a;           // ||[[K0, J^T], [J, 0]]||_inf
+    double norm_rhs;         // max(||f||_inf, ||g||_inf)
+    double rmax, dymax;      // ||r||_inf (last eta test) and ||dy||_inf (last update)
+    double eta;              // normwise backward error of (dx, dy) on the saddle system
     int it, maxit, done, status;
+    int eta_stop;            // 1: stopped by the eta bound
+    int arrive;              // workgroups arrived at the current reduction
 };
 
 struct InstDev {
@@ -81,11 +95,14 @@ struct InstDev {
     double* r;          // residual (n)
     double* xprev;      // previous refinement iterate (n)
     double* tn;         // scratch (n)
-    double* fg;         // HyKKT f_gamma (n)
+    double* fg;         // HyKKT f_gamma in pivot order (n)
     double* cvec;       // HyKKT Schur right-hand side c (m)
     double* rvec;       // CG residual (m)
     double* pvec;       // CG direction (m)
     double* qvec;       // S_gamma p (m)
+    double* pvec2;      // CG direction, second buffer (m): iterations alternate
+    double* jtv;        // HyKKT: J values by columns in pivot order (jtp_ptr layout)
+    double* k0csr;      // HyKKT: W + Sigma_x in the symmetric row lists (kcsr layout)
     double* red;        // per-block partial sums (deterministic reductions)
     int* status;        // [0] latched status, [1] first failing pivot (permuted index)
     RefineState* rs;
@@ -106,6 +123,7 @@ struct FrontDesc {
     double* dinv;           // pivot reciprocals at the front's first column
     const int* rw;          // rows of the update part (instance numbering)
     const int* done;        // the instance's refinement stop flag
+    const int* cgdone;      // the instance's CG stop flag
     const double* cU[2];    // first two children: update matrices,
     const double* cV[2];    //   update vectors,
     const int* crl[2];      //   relative rows of their update parts,

@@ -111,6 +111,13 @@ __global__ __launch_bounds__(256) void k_assemble(const InstDev* __restrict__ in
                 if (p + q < p1) v += x[q] * y[q];
         }
     } else {
+        // K_gamma: W + Sigma_x is also kept (single factors), for the
+        // saddle-system residual
+        if (I.k0csr) {
+            const int c0 = I.P.k_csr[2 * e], c1 = I.P.k_csr[2 * e + 1];
+            I.k0csr[c0] = v;
+            if (c1 >= 0) I.k0csr[c1] = v;
+        }
         double acc = 0.0;
         for (int64_t p = p0; p < p1; p++) acc += jv[I.P.pair_a[p]] * jv[I.P.pair_b[p]];
         v += C.gamma * acc;
@@ -170,9 +177,13 @@ __global__ __launch_bounds__(256) void k_assemble_heavy(const InstDev* __restric
     if (wi >= 0) v += C.w[I.w_off + wi];
     const int di = I.P.k_diag[e];
     if (di >= 0) v += C.sx[I.n_off + di];
+    const int c0 = I.P.k_csr[2 * e], c1 = I.P.k_csr[2 * e + 1];
+    if (!C.ss && I.k0csr) {
+        I.k0csr[c0] = v;
+        if (c1 >= 0) I.k0csr[c1] = v;
+    }
     v += C.ss ? acc : C.gamma * acc;
     I.kval[e] = v;
-    const int c0 = I.P.k_csr[2 * e], c1 = I.P.k_csr[2 * e + 1];
     I.kcsr[c0] = v;
     if (c1 >= 0) I.kcsr[c1] = v;
     if (!isfinite(v)) atomicMax(&I.status[0], KKT_ST_NONFINITE);
@@ -186,6 +197,19 @@ __global__ __launch_bounds__(256) void k_jscale(const InstDev* __restrict__ inst
     const int p = it.id + threadIdx.x;
     if (p >= I.P.j_ptr[I.P.m]) return;
     I.js[p] = C.jv[I.j_off + p] * C.ss[I.m_off + I.P.jrow[p]];
+}
+
+// K_gamma: the factor keeps J's values, by rows (js) and by columns in pivot
+// order (jtv), for the Schur-complement CG; one thread per entry
+__global__ __launch_bounds__(256) void k_jcopy(const InstDev* __restrict__ insts, Calls C,
+                                               const WorkItem* __restrict__ items) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    const int p = it.id + threadIdx.x;
+    if (p >= I.P.j_ptr[I.P.m]) return;
+    const double* __restrict__ jv = C.jv + I.j_off;
+    I.js[p] = jv[p];
+    I.jtv[p] = jv[I.P.jtp_e[p]];
 }
 
 // ---------------------------------------------------------------------------
@@ -1387,18 +1411,25 @@ __device__ __forceinline__ void bwd_front(const FrontDesc& F, double* __restrict
     }
 }
 
+// skip modes of the sweeps: SKIP_NONE runs every front; SKIP_REFINE skips
+// the fronts of instances whose refinement has stopped, SKIP_CG those whose
+// CG has stopped (the queued rounds after a stop decision do nothing)
+__device__ __forceinline__ bool front_idle(const FrontDesc& F, int skip) {
+    return skip == SKIP_REFINE ? *F.done != 0 : (skip == SKIP_CG ? *F.cgdone != 0 : false);
+}
+
 __global__ __launch_bounds__(kSolveThreads) void k_fwd(const InstDev* __restrict__ insts,
                                                       const FrontDesc* __restrict__ fds, int skip_done) {
     extern __shared__ __align__(16) double sh[];
     const FrontDesc& F = fds[blockIdx.x];
-    if (skip_done && *F.done) return;
+    if (front_idle(F, skip_done)) return;
     fwd_front(insts[F.inst], F, sh);
 }
 
 __global__ __launch_bounds__(kSolveThreads) void k_bwd(const FrontDesc* __restrict__ fds, int skip_done) {
     extern __shared__ __align__(16) double sh[];
     const FrontDesc& F = fds[blockIdx.x];
-    if (skip_done && *F.done) return;
+    if (front_idle(F, skip_done)) return;
     bwd_front(F, sh);
 }
 
@@ -1426,7 +1457,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_sweeps_queue(const InstDev* _
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const FrontDesc& F = fds[k];
-        const int idle = skip_done ? __builtin_amdgcn_readfirstlane(*F.done) : 0;
+        const int idle = __builtin_amdgcn_readfirstlane((int)front_idle(F, skip_done));
         if (!idle) {
             if (fwd) fwd_front(insts[F.inst], F, sh);
             else bwd_front(F, sh);
@@ -1444,9 +1475,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_sweeps_queue(const InstDev* _
 // ---------------------------------------------------------------------------
 // permutations between original and pivot order (row blocks of 256)
 // ---------------------------------------------------------------------------
-__device__ inline bool inst_idle(const InstDev& I, int use_cg) { return use_cg ? I.cg->done : I.rs->done; }
-
-// y[k] = src[perm[k]] with src = b (PIN_B), r (PIN_R), tn (PIN_TN) or f_gamma (PIN_FG)
+// y[k] = src[perm[k]] with src = b (PIN_B) or r (PIN_R)
 __global__ __launch_bounds__(256) void k_perm_in(const InstDev* __restrict__ insts, Calls C,
                                                  const WorkItem* __restrict__ items, int mode) {
     const WorkItem it = items[blockIdx.x];
@@ -1454,11 +1483,11 @@ __global__ __launch_bounds__(256) void k_perm_in(const InstDev* __restrict__ ins
     if (mode == PIN_R && I.rs->done) return;
     const int k = it.id + threadIdx.x;
     if (k >= I.P.n) return;
-    const double* src = mode == PIN_B ? C.b + I.n_off : (mode == PIN_R ? I.r : (mode == PIN_TN ? I.tn : I.fg));
+    const double* src = mode == PIN_B ? C.b + I.n_off : I.r;
     I.y[k] = src[I.P.perm[k]];
 }
 
-// POUT_X: x[perm[k]] = y[k]; POUT_X_UPDATE: xprev = x, x += y[iperm]; POUT_TN: tn[perm[k]] = y[k];
+// POUT_X: x[perm[k]] = y[k]; POUT_X_UPDATE: xprev = x, x += y[iperm];
 // POUT_DX: dx[perm[k]] = y[k]
 __global__ __launch_bounds__(256) void k_perm_out(const InstDev* __restrict__ insts, Calls C,
                                                   const WorkItem* __restrict__ items, int mode) {
@@ -1476,8 +1505,6 @@ __global__ __launch_bounds__(256) void k_perm_out(const InstDev* __restrict__ in
         const double xo = x[i];
         I.xprev[i] = xo;
         x[i] = xo + v;
-    } else if (mode == POUT_TN) {
-        I.tn[i] = v;
     } else {
         C.dx[I.n_off + i] = v;
     }
@@ -1680,27 +1707,26 @@ __global__ __launch_bounds__(256) void k_matvec(const InstDev* __restrict__ inst
 }
 
 // ---------------------------------------------------------------------------
-// Schur-complement CG (eq. (schurcomp)); vectors in original numbering
+// Schur-complement CG (eq. (schurcomp)). The m-vectors (c, r, p, q, dy) are in
+// the numbering of J's rows; the n-vectors handed to the sweeps are in pivot
+// order, so J^T v is written straight into the sweep vector (pivot position k
+// holds column perm[k]) and J t reads the sweep output through j_colp.
+//
+// One iteration is three launches around the sweep pair:
+//   k_cg_dir  p = r + beta p_old (row owners) and y = J^T p for the sweeps,
+//             with p's entries formed on the fly, so no launch separates them;
+//   k_cg_q    q = J K_gamma^{-1} J^T p and the partial sums of p.q; the last
+//             workgroup forms alpha = r.r / p.q (or flags a breakdown);
+//   k_cg_upd  dy += alpha p, r -= alpha q, the partial sums of r.r and the
+//             maximum of |dy|; the last workgroup takes the stop decision
+//             and beta.
+// Every kernel returns at once when the instance's CG has stopped, so a
+// sequence of iterations can be queued without reading the decisions back.
 // ---------------------------------------------------------------------------
-// deterministic block sum of v into red[blockslot]
-__device__ inline void block_sum_to(double v, double* out) {
+// deterministic block sum of v (every thread gets the sum)
+__device__ inline double block_sum(double v) {
     __shared__ double sred[256];
     const int tid = threadIdx.x;
-    sred[tid] = v;
-    __syncthreads();
-    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-        if (tid < h) sred[tid] += sred[tid + h];
-        __syncthreads();
-    }
-    if (tid == 0) *out = sred[0];
-}
-
-// one block per instance: fixed-order sum of nb partials
-__device__ inline double block_sum_partials(const double* red, int nb) {
-    __shared__ double sred[256];
-    const int tid = threadIdx.x;
-    double v = 0.0;
-    for (int q = tid; q < nb; q += blockDim.x) v += red[q];
     sred[tid] = v;
     __syncthreads();
     for (int h = blockDim.x / 2; h > 0; h >>= 1) {
@@ -1712,99 +1738,248 @@ __device__ inline double block_sum_partials(const double* red, int nb) {
     return t;
 }
 
-// f_gamma = f + gamma J^T g (one thread per column of J)
-__global__ __launch_bounds__(256) void k_cg_fgamma(const InstDev* __restrict__ insts, Calls C,
-                                                   const WorkItem* __restrict__ items) {
-    const WorkItem it = items[blockIdx.x];
-    const InstDev& I = insts[it.inst];
-    const int j = it.id + threadIdx.x;
-    if (j >= I.P.n) return;
-    const double* __restrict__ jv = C.jv + I.j_off;
-    const double* __restrict__ g = C.g + I.m_off;
-    double sum = 0.0;
-    for (int p = I.P.jt_ptr[j]; p < I.P.jt_ptr[j + 1]; p++) sum += jv[I.P.jt_e[p]] * g[I.P.jt_row[p]];
-    I.fg[j] = C.f[I.n_off + j] + C.gamma * sum;
+__device__ inline double block_max(double v) {
+    __shared__ double smax[256];
+    const int tid = threadIdx.x;
+    smax[tid] = v;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if (tid < h) smax[tid] = fmax(smax[tid], smax[tid + h]);
+        __syncthreads();
+    }
+    const double t = smax[0];
+    __syncthreads();
+    return t;
 }
 
-// c = J w - g with w = K_gamma^{-1} f_gamma in tn; r = p = c; dy = 0; partial c.c
-__global__ __launch_bounds__(256) void k_cg_init(const InstDev* __restrict__ insts, Calls C,
-                                                 const WorkItem* __restrict__ items) {
+// Reduction slots of one instance: the n-side kernels write 4 values per
+// 256-row block at red[4 b + k]; the m-side kernels at red[mslot0 + 4 b + k].
+__device__ __forceinline__ int cg_mslot0(const InstDev& I) { return 4 * ((I.P.n + 255) >> 8); }
+
+// Every thread of the workgroup returns true in the instance's last
+// workgroup to arrive at this reduction (the arrival counter is reset there
+// for the next one). Thread 0 published this workgroup's slots before the
+// release; the last workgroup reads every slot after the acquire.
+__device__ inline bool cg_last_block(CgState* G, int nblocks) {
+    __shared__ int last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const int prev = __hip_atomic_fetch_add(&G->arrive, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        last = prev == nblocks - 1;
+        if (last) __hip_atomic_store(&G->arrive, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const int l = __builtin_amdgcn_readfirstlane(last);
+    if (l) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return l != 0;
+}
+
+// slot values of other workgroups: atomic loads, so nothing is served from a
+// stale cache line or hoisted above the acquire
+__device__ __forceinline__ double slot_load(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// fixed-order sum / maximum over slots k of nb blocks (stride 4)
+__device__ inline double slots_sum(const double* red, int nb, int k) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) v += slot_load(red + 4 * b + k);
+    return block_sum(v);
+}
+__device__ inline double slots_max(const double* red, int nb, int k) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) v = fmax(v, slot_load(red + 4 * b + k));
+    return block_max(v);
+}
+
+// f_gamma = f + gamma J^T g in pivot order (sweep vector and a copy for dx),
+// and the n-side norms: per row i of the saddle matrix, sum_j |K0_ij| +
+// sum_r |J_ri|; |f_i|.
+__global__ __launch_bounds__(256) void k_cg_fg(const InstDev* __restrict__ insts, Calls C,
+                                               const WorkItem* __restrict__ items) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    if (it.id == 0 && threadIdx.x == 0) I.cg->arrive = 0;
+    const int k = it.id + threadIdx.x;
+    double arow = 0.0, fa = 0.0;
+    if (k < I.P.n) {
+        const int j = I.P.perm[k];
+        const double* __restrict__ g = C.g + I.m_off;
+        double s = 0.0, csum = 0.0;
+        for (int q = I.P.jtp_ptr[k]; q < I.P.jtp_ptr[k + 1]; q++) {
+            const double a = I.jtv[q];
+            s += a * g[I.P.jtp_row[q]];
+            csum += fabs(a);
+        }
+        const double fj = C.f[I.n_off + j];
+        const double v = fj + C.gamma * s;
+        I.fg[k] = v;
+        I.y[k] = v;
+        double ka = 0.0;
+        for (int64_t p = I.P.sp_ptr[j]; p < I.P.sp_ptr[j + 1]; p++) ka += fabs(I.k0csr[p]);
+        arow = ka + csum;
+        fa = fabs(fj);
+    }
+    arow = block_max(arow);
+    fa = block_max(fa);
+    if (threadIdx.x == 0) {
+        double* s = I.red + 4 * (it.id >> 8);
+        s[0] = arow;
+        s[1] = fa;
+    }
+}
+
+// After the sweeps: c = J K_gamma^{-1} f_gamma - g; r = c; p_old = 0; dy = 0;
+// the m-side norms; the last workgroup sets up the CG state.
+__global__ __launch_bounds__(256) void k_cg_c(const InstDev* __restrict__ insts, Calls C,
+                                              const WorkItem* __restrict__ items, double tol, int maxit,
+                                              double eta_tol, int* ndone) {
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
     const int i = it.id + threadIdx.x;
-    double v = 0.0;
+    double cc = 0.0, ga = 0.0, jrow = 0.0;
     if (i < I.P.m) {
-        const double* __restrict__ jv = C.jv + I.j_off;
-        double sum = 0.0;
-        for (int p = I.P.j_ptr[i]; p < I.P.j_ptr[i + 1]; p++) sum += jv[p] * I.tn[I.P.j_col[p]];
-        const double ci = sum - C.g[I.m_off + i];
+        const double* __restrict__ jv = I.js;
+        double s = 0.0;
+        for (int p = I.P.j_ptr[i]; p < I.P.j_ptr[i + 1]; p++) {
+            s += jv[p] * I.y[I.P.j_colp[p]];
+            jrow += fabs(jv[p]);
+        }
+        const double gi = C.g[I.m_off + i];
+        const double ci = s - gi;
         I.cvec[i] = ci;
         I.rvec[i] = ci;
-        I.pvec[i] = ci;
+        I.pvec2[i] = 0.0;
         C.dy[I.m_off + i] = 0.0;
-        v = ci * ci;
+        cc = ci * ci;
+        ga = fabs(gi);
     }
-    block_sum_to(v, &I.red[it.id / 256]);
-}
-
-__global__ __launch_bounds__(256) void k_cg_start(const InstDev* __restrict__ insts, double tol, int maxit, int* ndone) {
-    const InstDev& I = insts[blockIdx.x];
-    const int nb = (I.P.m + 255) / 256;
-    const double rr = block_sum_partials(I.red, nb);
+    cc = block_sum(cc);
+    ga = block_max(ga);
+    jrow = block_max(jrow);
+    const int m0 = cg_mslot0(I);
     if (threadIdx.x == 0) {
-        CgState* G = I.cg;
+        double* s = I.red + m0 + 4 * (it.id >> 8);
+        s[0] = cc;
+        s[1] = ga;
+        s[2] = jrow;
+    }
+    CgState* G = I.cg;
+    const int nbm = (I.P.m + 255) >> 8, nbn = (I.P.n + 255) >> 8;
+    if (!cg_last_block(G, nbm)) return;
+    const double rr = slots_sum(I.red + m0, nbm, 0);
+    const double gmax = slots_max(I.red + m0, nbm, 1);
+    const double jr = slots_max(I.red + m0, nbm, 2);
+    const double an = slots_max(I.red, nbn, 0);
+    const double fmx = slots_max(I.red, nbn, 1);
+    if (threadIdx.x == 0) {
         G->rr = rr;
+        G->rr_new = rr;
         G->cnorm = sqrt(rr);
         G->tol = tol;
+        G->eta_tol = eta_tol;
         G->maxit = maxit;
+        G->norm_a = fmax(an, jr);
+        G->norm_rhs = fmax(fmx, gmax);
+        G->rmax = 0.0;
+        G->dymax = 0.0;
+        G->eta = 0.0;
         G->it = 0;
         G->status = 0;
-        G->done = (sqrt(rr) <= tol * G->cnorm) ? 1 : 0;  // c == 0
+        G->eta_stop = 0;
         G->alpha = G->beta = 0.0;
+        G->pq = 0.0;
+        G->done = rr == 0.0 ? 1 : 0;  // c == 0: dy = 0 solves the Schur system
         if (G->done) atomicAdd(ndone, 1);
     }
 }
 
-// tn = J^T p (dx_rhs = 0), or tn = f_gamma - J^T dy (dx_rhs = 1)
-__global__ __launch_bounds__(256) void k_cg_jt(const InstDev* __restrict__ insts, Calls C,
-                                               const WorkItem* __restrict__ items, int dx_rhs) {
+// p = r + beta p_old for the instance's rows (row i by thread i of the
+// n-side blocks; the Schur system needs m <= n) and y[k] = (J^T p)_{perm[k]},
+// each entry of p formed by the same fma as its stored value.
+// With eta_tol > 0 the kernel also takes the eta test of the current iterate
+// dy (its residual r is final here): for dx = K_gamma^{-1}(f_gamma - J^T dy)
+// the saddle system's residual is (gamma J^T r, r), so
+//   max(gamma ||J^T r||_inf, ||r||_inf) / (||A||_inf ||dy||_inf + ||(f, g)||_inf)
+// bounds its normwise backward error from above (the denominator leaves out
+// ||dx||); the last workgroup stops the CG when the bound is <= eta_tol.
+__global__ __launch_bounds__(256) void k_cg_dir(const InstDev* __restrict__ insts, Calls C,
+                                                const WorkItem* __restrict__ items, int parity, int* ndone) {
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
-    if (!dx_rhs && I.cg->done) return;
-    const int j = it.id + threadIdx.x;
-    if (j >= I.P.n) return;
-    const double* __restrict__ jv = C.jv + I.j_off;
-    const double* v = dx_rhs ? C.dy + I.m_off : I.pvec;
-    double sum = 0.0;
-    for (int p = I.P.jt_ptr[j]; p < I.P.jt_ptr[j + 1]; p++) sum += jv[I.P.jt_e[p]] * v[I.P.jt_row[p]];
-    I.tn[j] = dx_rhs ? I.fg[j] - sum : sum;
+    CgState* G = I.cg;
+    if (G->done) return;  // uniform per block
+    const double beta = G->beta;
+    const bool eta_test = G->eta_tol > 0.0;
+    double* __restrict__ pn = parity ? I.pvec2 : I.pvec;
+    const double* __restrict__ po = parity ? I.pvec : I.pvec2;
+    const double* __restrict__ r = I.rvec;
+    const int k = it.id + threadIdx.x;
+    double ra = 0.0, ja = 0.0;
+    if (k < I.P.m) {
+        pn[k] = fma(beta, po[k], r[k]);
+        ra = fabs(r[k]);
+    }
+    if (k < I.P.n) {
+        double s = 0.0, t = 0.0;
+        for (int q = I.P.jtp_ptr[k]; q < I.P.jtp_ptr[k + 1]; q++) {
+            const int row = I.P.jtp_row[q];
+            const double a = I.jtv[q], rv = r[row];
+            s += a * fma(beta, po[row], rv);
+            t += a * rv;
+        }
+        I.y[k] = s;
+        ja = fabs(t);
+    }
+    if (!eta_test) return;  // uniform per launch
+    ra = block_max(ra);
+    ja = block_max(ja);
+    if (threadIdx.x == 0) {
+        double* sl = I.red + 4 * (it.id >> 8);
+        sl[0] = ra;
+        sl[1] = ja;
+    }
+    const int nbn = (I.P.n + 255) >> 8;
+    if (!cg_last_block(G, nbn)) return;
+    const double rmax = slots_max(I.red, nbn, 0);
+    const double jrmax = slots_max(I.red, nbn, 1);
+    if (threadIdx.x == 0) {
+        G->rmax = rmax;
+        const double bound = fmax(C.gamma * jrmax, rmax);
+        if (bound <= G->eta_tol * (G->norm_a * G->dymax + G->norm_rhs)) {
+            G->done = 1;
+            G->eta_stop = 1;
+            atomicAdd(ndone, 1);
+        }
+    }
 }
 
-// q = J t (t in tn), partial p.q
-__global__ __launch_bounds__(256) void k_cg_jq(const InstDev* __restrict__ insts, Calls C,
-                                               const WorkItem* __restrict__ items) {
+// q = J t with t = K_gamma^{-1} J^T p (the sweep output, pivot order) and
+// p.q; the last workgroup forms alpha or flags a breakdown (p^T S p <= 0).
+__global__ __launch_bounds__(256) void k_cg_q(const InstDev* __restrict__ insts,
+                                              const WorkItem* __restrict__ items, int parity, int* ndone) {
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
-    if (I.cg->done) return;
+    CgState* G = I.cg;
+    if (G->done) return;  // uniform per block
+    const double* __restrict__ pn = parity ? I.pvec2 : I.pvec;
     const int i = it.id + threadIdx.x;
     double v = 0.0;
     if (i < I.P.m) {
-        const double* __restrict__ jv = C.jv + I.j_off;
-        double sum = 0.0;
-        for (int p = I.P.j_ptr[i]; p < I.P.j_ptr[i + 1]; p++) sum += jv[p] * I.tn[I.P.j_col[p]];
-        I.qvec[i] = sum;
-        v = I.pvec[i] * sum;
+        const double* __restrict__ jv = I.js;
+        double s = 0.0;
+        for (int p = I.P.j_ptr[i]; p < I.P.j_ptr[i + 1]; p++) s += jv[p] * I.y[I.P.j_colp[p]];
+        I.qvec[i] = s;
+        v = pn[i] * s;
     }
-    block_sum_to(v, &I.red[it.id / 256]);
-}
-
-__global__ __launch_bounds__(256) void k_cg_alpha(const InstDev* __restrict__ insts, int* ndone) {
-    const InstDev& I = insts[blockIdx.x];
-    if (I.cg->done) return;
-    const int nb = (I.P.m + 255) / 256;
-    const double pq = block_sum_partials(I.red, nb);
+    v = block_sum(v);
+    const int m0 = cg_mslot0(I);
+    if (threadIdx.x == 0) I.red[m0 + 4 * (it.id >> 8)] = v;
+    const int nbm = (I.P.m + 255) >> 8;
+    if (!cg_last_block(G, nbm)) return;
+    const double pq = slots_sum(I.red + m0, nbm, 0);
     if (threadIdx.x == 0) {
-        CgState* G = I.cg;
         G->pq = pq;
         if (!(pq > 0.0)) {
             G->status = 7;  // breakdown
@@ -1816,33 +1991,43 @@ __global__ __launch_bounds__(256) void k_cg_alpha(const InstDev* __restrict__ in
     }
 }
 
-// dy += alpha p; r -= alpha q; partial r.r
-__global__ __launch_bounds__(256) void k_cg_update(const InstDev* __restrict__ insts, Calls C,
-                                                   const WorkItem* __restrict__ items) {
+// dy += alpha p; r -= alpha q; the last workgroup: r.r, ||dy||_inf, the stop
+// rule ||r||_2 <= tol ||c||_2 or maxit iterations (NOT_CONVERGED), and beta.
+__global__ __launch_bounds__(256) void k_cg_upd(const InstDev* __restrict__ insts, Calls C,
+                                                const WorkItem* __restrict__ items, int parity, int* ndone) {
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
-    if (I.cg->done) return;
+    CgState* G = I.cg;
+    if (G->done) return;  // uniform per block
+    const double a = G->alpha;
+    const double* __restrict__ pn = parity ? I.pvec2 : I.pvec;
     const int i = it.id + threadIdx.x;
-    const double a = I.cg->alpha;
-    double v = 0.0;
+    double rr = 0.0, da = 0.0;
     if (i < I.P.m) {
-        C.dy[I.m_off + i] += a * I.pvec[i];
-        const double ri = I.rvec[i] - a * I.qvec[i];
+        double* dy = C.dy + I.m_off;
+        const double d = fma(a, pn[i], dy[i]);
+        dy[i] = d;
+        const double ri = fma(-a, I.qvec[i], I.rvec[i]);
         I.rvec[i] = ri;
-        v = ri * ri;
+        rr = ri * ri;
+        da = fabs(d);
     }
-    block_sum_to(v, &I.red[it.id / 256]);
-}
-
-__global__ __launch_bounds__(256) void k_cg_beta(const InstDev* __restrict__ insts, int* ndone) {
-    const InstDev& I = insts[blockIdx.x];
-    if (I.cg->done) return;
-    const int nb = (I.P.m + 255) / 256;
-    const double rr2 = block_sum_partials(I.red, nb);
+    rr = block_sum(rr);
+    da = block_max(da);
+    const int m0 = cg_mslot0(I);
     if (threadIdx.x == 0) {
-        CgState* G = I.cg;
+        double* s = I.red + m0 + 4 * (it.id >> 8);
+        s[0] = rr;
+        s[1] = da;
+    }
+    const int nbm = (I.P.m + 255) >> 8;
+    if (!cg_last_block(G, nbm)) return;
+    const double rr2 = slots_sum(I.red + m0, nbm, 0);
+    const double dymax = slots_max(I.red + m0, nbm, 1);
+    if (threadIdx.x == 0) {
         G->it += 1;
         G->rr_new = rr2;
+        G->dymax = dymax;
         if (sqrt(rr2) <= G->tol * G->cnorm) {
             G->done = 1;
         } else if (G->it >= G->maxit) {
@@ -1856,13 +2041,80 @@ __global__ __launch_bounds__(256) void k_cg_beta(const InstDev* __restrict__ ins
     }
 }
 
-__global__ __launch_bounds__(256) void k_cg_p(const InstDev* __restrict__ insts, const WorkItem* __restrict__ items) {
+// right-hand side of the last solve: y[k] = f_gamma[k] - (J^T dy)_{perm[k]}
+__global__ __launch_bounds__(256) void k_cg_dxrhs(const InstDev* __restrict__ insts, Calls C,
+                                                  const WorkItem* __restrict__ items) {
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
-    if (I.cg->done) return;
+    const int k = it.id + threadIdx.x;
+    if (k >= I.P.n) return;
+    const double* __restrict__ dy = C.dy + I.m_off;
+    double s = 0.0;
+    for (int q = I.P.jtp_ptr[k]; q < I.P.jtp_ptr[k + 1]; q++) s += I.jtv[q] * dy[I.P.jtp_row[q]];
+    I.y[k] = I.fg[k] - s;
+}
+
+// Saddle-system residual of (dx, dy): rows of the primal block,
+// f - K0 dx - J^T dy (original numbering), with the maxima of |res| and |dx|.
+__global__ __launch_bounds__(256) void k_cg_res_n(const InstDev* __restrict__ insts, Calls C,
+                                                  const WorkItem* __restrict__ items) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    const int j = it.id + threadIdx.x;
+    double ra = 0.0, xa = 0.0;
+    if (j < I.P.n) {
+        const double* __restrict__ dx = C.dx + I.n_off;
+        const double* __restrict__ dy = C.dy + I.m_off;
+        double s = 0.0;
+        for (int64_t p = I.P.sp_ptr[j]; p < I.P.sp_ptr[j + 1]; p++) s += I.k0csr[p] * dx[I.P.sp_col[p]];
+        for (int q = I.P.jt_ptr[j]; q < I.P.jt_ptr[j + 1]; q++) s += I.js[I.P.jt_e[q]] * dy[I.P.jt_row[q]];
+        ra = fabs(C.f[I.n_off + j] - s);
+        xa = fabs(dx[j]);
+    }
+    ra = block_max(ra);
+    xa = block_max(xa);
+    if (threadIdx.x == 0) {
+        double* s = I.red + 4 * (it.id >> 8);
+        s[0] = ra;
+        s[1] = xa;
+    }
+}
+
+// constraint rows, g - J dx, with |dy|; the last workgroup forms
+// eta = ||res||_inf / (||A||_inf ||(dx, dy)||_inf + ||(f, g)||_inf).
+__global__ __launch_bounds__(256) void k_cg_res_m(const InstDev* __restrict__ insts, Calls C,
+                                                  const WorkItem* __restrict__ items) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
     const int i = it.id + threadIdx.x;
-    if (i >= I.P.m) return;
-    I.pvec[i] = I.rvec[i] + I.cg->beta * I.pvec[i];
+    double ra = 0.0, ya = 0.0;
+    if (i < I.P.m) {
+        const double* __restrict__ dx = C.dx + I.n_off;
+        double s = 0.0;
+        for (int p = I.P.j_ptr[i]; p < I.P.j_ptr[i + 1]; p++) s += I.js[p] * dx[I.P.j_col[p]];
+        ra = fabs(C.g[I.m_off + i] - s);
+        ya = fabs(C.dy[I.m_off + i]);
+    }
+    ra = block_max(ra);
+    ya = block_max(ya);
+    const int m0 = cg_mslot0(I);
+    if (threadIdx.x == 0) {
+        double* s = I.red + m0 + 4 * (it.id >> 8);
+        s[0] = ra;
+        s[1] = ya;
+    }
+    CgState* G = I.cg;
+    const int nbm = (I.P.m + 255) >> 8, nbn = (I.P.n + 255) >> 8;
+    if (!cg_last_block(G, nbm)) return;
+    const double r2 = slots_max(I.red + m0, nbm, 0);
+    const double y2 = slots_max(I.red + m0, nbm, 1);
+    const double r1 = slots_max(I.red, nbn, 0);
+    const double x1 = slots_max(I.red, nbn, 1);
+    if (threadIdx.x == 0) {
+        const double den = G->norm_a * fmax(x1, y2) + G->norm_rhs;
+        const double res = fmax(r1, r2);
+        G->eta = den > 0.0 ? res / den : (res > 0.0 ? INFINITY : 0.0);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1894,6 +2146,9 @@ void launch_status_init(int* status, int ninst, hipStream_t st) {
 }
 void launch_jscale(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st) {
     if (nitems > 0) k_jscale<<<nitems, kBlock, 0, st>>>(insts, C, items);
+}
+void launch_jcopy(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st) {
+    if (nitems > 0) k_jcopy<<<nitems, kBlock, 0, st>>>(insts, C, items);
 }
 void launch_assemble_heavy(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st) {
     if (nitems > 0) k_assemble_heavy<<<(nitems + 15) / 16, kBlock, 0, st>>>(insts, C, items, nitems);
@@ -1943,32 +2198,31 @@ void launch_refine_revert(const InstDev* insts, const Calls& C, const WorkItem* 
 void launch_matvec(const InstDev* insts, const double* x, double* y, const WorkItem* rows, int nitems, hipStream_t st) {
     if (nitems > 0) k_matvec<<<nitems, kBlock, 0, st>>>(insts, x, y, rows);
 }
-void launch_cg_fgamma(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, hipStream_t st) {
-    if (nitems > 0) k_cg_fgamma<<<nitems, kBlock, 0, st>>>(insts, C, ncols);
+void launch_cg_fg(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, hipStream_t st) {
+    if (nitems > 0) k_cg_fg<<<nitems, kBlock, 0, st>>>(insts, C, ncols);
 }
-void launch_cg_init(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, hipStream_t st) {
-    if (nitems > 0) k_cg_init<<<nitems, kBlock, 0, st>>>(insts, C, mrows);
+void launch_cg_c(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, double tol, int maxit,
+                 double eta_tol, int* ndone, hipStream_t st) {
+    if (nitems > 0) k_cg_c<<<nitems, kBlock, 0, st>>>(insts, C, mrows, tol, maxit, eta_tol, ndone);
 }
-void launch_cg_start(const InstDev* insts, int ninst, double tol, int maxit, int* ndone, hipStream_t st) {
-    k_cg_start<<<ninst, kBlock, 0, st>>>(insts, tol, maxit, ndone);
+void launch_cg_dir(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, int parity, int* ndone,
+                   hipStream_t st) {
+    if (nitems > 0) k_cg_dir<<<nitems, kBlock, 0, st>>>(insts, C, ncols, parity, ndone);
 }
-void launch_cg_jt(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, int dx_rhs, hipStream_t st) {
-    if (nitems > 0) k_cg_jt<<<nitems, kBlock, 0, st>>>(insts, C, ncols, dx_rhs);
+void launch_cg_q(const InstDev* insts, const WorkItem* mrows, int nitems, int parity, int* ndone, hipStream_t st) {
+    if (nitems > 0) k_cg_q<<<nitems, kBlock, 0, st>>>(insts, mrows, parity, ndone);
 }
-void launch_cg_jq(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, hipStream_t st) {
-    if (nitems > 0) k_cg_jq<<<nitems, kBlock, 0, st>>>(insts, C, mrows);
+void launch_cg_upd(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, int parity, int* ndone,
+                   hipStream_t st) {
+    if (nitems > 0) k_cg_upd<<<nitems, kBlock, 0, st>>>(insts, C, mrows, parity, ndone);
 }
-void launch_cg_alpha(const InstDev* insts, int ninst, int* ndone, hipStream_t st) {
-    k_cg_alpha<<<ninst, kBlock, 0, st>>>(insts, ndone);
+void launch_cg_dxrhs(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, hipStream_t st) {
+    if (nitems > 0) k_cg_dxrhs<<<nitems, kBlock, 0, st>>>(insts, C, ncols);
 }
-void launch_cg_update(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, hipStream_t st) {
-    if (nitems > 0) k_cg_update<<<nitems, kBlock, 0, st>>>(insts, C, mrows);
-}
-void launch_cg_beta(const InstDev* insts, int ninst, int* ndone, hipStream_t st) {
-    k_cg_beta<<<ninst, kBlock, 0, st>>>(insts, ndone);
-}
-void launch_cg_p(const InstDev* insts, const WorkItem* mrows, int nitems, hipStream_t st) {
-    if (nitems > 0) k_cg_p<<<nitems, kBlock, 0, st>>>(insts, mrows);
+void launch_cg_residual(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nn, const WorkItem* mrows,
+                        int nm, hipStream_t st) {
+    if (nn > 0) k_cg_res_n<<<nn, kBlock, 0, st>>>(insts, C, ncols);
+    if (nm > 0) k_cg_res_m<<<nm, kBlock, 0, st>>>(insts, C, mrows);
 }
 
 }  // namespace kkt

@@ -56,6 +56,7 @@ constexpr int kSweepSplitMin = 512;
 
 hipError_t set_kernel_attributes();
 
+
 // A device-to-device copy of `len` doubles (gathering a served wave's inputs).
 struct CopySeg {
     const double* src;
@@ -67,6 +68,8 @@ void launch_copy_segments(const CopySeg* segs, int nseg, hipStream_t st);
 void launch_fill_i32(int* p, int v, int64_t n, hipStream_t st);
 void launch_status_init(int* status, int ninst, hipStream_t st);
 void launch_jscale(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st);
+// K_gamma: J's values by rows and by columns in pivot order, kept for the CG
+void launch_jcopy(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st);
 void launch_assemble(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st);
 // entries of K with more than kHeavyPairs products of J entries are left to
 // launch_assemble_heavy (one item per entry, 16 lanes each)
@@ -83,8 +86,10 @@ void launch_fwd(const InstDev* insts, const FrontDesc* fds, int nitems, size_t l
 void launch_bwd(const FrontDesc* fds, int nitems, size_t lds, int skip_done, hipStream_t st);
 
 // permutation modes
-enum { PIN_B = 0, PIN_R = 1, PIN_TN = 2, PIN_FG = 3 };
-enum { POUT_X = 0, POUT_X_UPDATE = 1, POUT_TN = 2, POUT_DX = 3 };
+enum { PIN_B = 0, PIN_R = 1 };
+enum { POUT_X = 0, POUT_X_UPDATE = 1, POUT_DX = 3 };
+// sweep skip modes (see front_idle)
+enum { SKIP_NONE = 0, SKIP_REFINE = 1, SKIP_CG = 2 };
 void launch_perm_in(const InstDev* insts, const Calls& C, const WorkItem* rows, int nitems, int mode, hipStream_t st);
 void launch_perm_out(const InstDev* insts, const Calls& C, const WorkItem* rows, int nitems, int mode, hipStream_t st);
 
@@ -94,15 +99,18 @@ void launch_refine_decide(const InstDev* insts, int ninst, int* ndone, hipStream
 void launch_refine_revert(const InstDev* insts, const Calls& C, const WorkItem* rows, int nitems, hipStream_t st);
 void launch_matvec(const InstDev* insts, const double* x, double* y, const WorkItem* rows, int nitems, hipStream_t st);
 
-// Schur-complement CG (one instance per CgState)
-void launch_cg_fgamma(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, hipStream_t st);
-void launch_cg_init(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, hipStream_t st);
-void launch_cg_start(const InstDev* insts, int ninst, double tol, int maxit, int* ndone, hipStream_t st);
-void launch_cg_jt(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, int dx_rhs, hipStream_t st);
-void launch_cg_jq(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, hipStream_t st);
-void launch_cg_alpha(const InstDev* insts, int ninst, int* ndone, hipStream_t st);
-void launch_cg_update(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, hipStream_t st);
-void launch_cg_beta(const InstDev* insts, int ninst, int* ndone, hipStream_t st);
-void launch_cg_p(const InstDev* insts, const WorkItem* mrows, int nitems, hipStream_t st);
+// Schur-complement CG (one CgState per instance)
+void launch_cg_fg(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, hipStream_t st);
+void launch_cg_c(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, double tol, int maxit,
+                 double eta_tol, int* ndone, hipStream_t st);
+void launch_cg_dir(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, int parity, int* ndone,
+                   hipStream_t st);
+void launch_cg_q(const InstDev* insts, const WorkItem* mrows, int nitems, int parity, int* ndone, hipStream_t st);
+void launch_cg_upd(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, int parity, int* ndone,
+                   hipStream_t st);
+void launch_cg_dxrhs(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, hipStream_t st);
+// saddle-system residual of (dx, dy) and its normwise backward error (CgState::eta)
+void launch_cg_residual(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nn, const WorkItem* mrows,
+                        int nm, hipStream_t st);
 
 }  // namespace kkt

@@ -59,8 +59,13 @@ class SolveInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class CgOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("eta_tol", C.c_double)]
+
+
 class CgInfo(C.Structure):
-    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("rel_res", C.c_double)]
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("rel_res", C.c_double), ("eta", C.c_double),
+                ("eta_stop", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -97,7 +102,8 @@ SIGNATURES = {
     "kkt_refactor": (I32, [P, P, P, P, P, D, P]),
     "kkt_status_sync": (I32, [P, P]),
     "kkt_solve": (I32, [P, P, P, P, P, P]),
-    "kkt_cg_schur": (I32, [P, P, P, D, I32, P, P, P, P]),
+    "kkt_cg_opts_default": (None, [P]),
+    "kkt_cg_schur": (I32, [P, P, P, P, P, P, P, P]),
     "kkt_matvec": (I32, [P, P, P, P]),
     "kkt_factor_set_timing": (I32, [P, I32]),
     "kkt_factor_read_timing": (I32, [P, P]),
@@ -248,9 +254,17 @@ def kkt_solve(h, b, x, max_iter: int = 10, tol: float = 1e-14, info: bool = True
     return si.as_dict() if info else None
 
 
-def kkt_cg_schur(h, f, g, dx, dy, tol: float = 1e-10, maxit: int = 200, info: bool = True, stream=None):
+def kkt_cg_opts_default() -> CgOpts:
+    o = CgOpts()
+    lib().kkt_cg_opts_default(C.byref(o))
+    return o
+
+
+def kkt_cg_schur(h, f, g, dx, dy, tol: float = 1e-10, maxit: int = 200, eta_tol: float = 0.0, info: bool = True,
+                 stream=None):
+    o = CgOpts(float(tol), int(maxit), float(eta_tol))
     ci = CgInfo()
-    st = lib().kkt_cg_schur(h, _dptr(f), _dptr(g), float(tol), int(maxit), _dptr(dx), _dptr(dy),
+    st = lib().kkt_cg_schur(h, _dptr(f), _dptr(g), C.byref(o), _dptr(dx), _dptr(dy),
                             C.byref(ci) if info else None, _stream(stream))
     if st not in (KKT_OK, 6, 7):
         _err(st)
@@ -329,8 +343,9 @@ class Factor:
     def solve(self, b, x, max_iter=10, tol=1e-14, info=True, stream=None):
         return kkt_solve(self.h, b, x, max_iter, tol, info, stream)
 
-    def cg_schur(self, f, g, dx, dy, tol=1e-10, maxit=200, info=True, stream=None):
-        return kkt_cg_schur(self.h, f, g, dx, dy, tol, maxit, info, stream)
+
+    def cg_schur(self, f, g, dx, dy, tol=1e-10, maxit=200, eta_tol=0.0, info=True, stream=None):
+        return kkt_cg_schur(self.h, f, g, dx, dy, tol, maxit, eta_tol, info, stream)
 
     def matvec(self, x, y, stream=None):
         kkt_matvec(self.h, x, y, stream)

@@ -203,9 +203,60 @@ def test_hykkt_gamma(kkt, gamma):
     assert info["status"] == 0
     dxh, dyh = host(dx), host(dy)
     assert D.forward_error(dxh, dx0) <= 1e-8 and D.forward_error(dyh, dy0) <= 1e-8
-    assert D.hykkt_backward_errors(pat, v, dxh, dyh, v.f, v.g)["eta"] <= 1e-10
+    be = D.hykkt_backward_errors(pat, v, dxh, dyh, v.f, v.g)
+    assert be["eta"] <= 1e-10
+    check_device_eta(info, be)
     _, _, oinfo = S.hykkt_cg_solve(pat, v, v.f, v.g, gamma, tol=1e-10)
     assert abs(info["iters"] - oinfo["iters"]) <= 1
+
+
+def check_device_eta(info, be):
+    """The library's eta of the saddle system (its own residual kernels)
+    against the oracle's evaluation of the same (dx, dy): both are rounding
+    noise of the same residual, so they agree within a factor of 2 or 1e-15."""
+    assert info["eta"] <= 1e-10
+    assert abs(info["eta"] - be["eta"]) <= max(0.5 * be["eta"], 1e-15), (info, be)
+
+
+def test_solve_async_matches_sync(kkt):
+    """kkt_solve without an info record is asynchronous (stop decisions on
+    the device, the rounds after the stop do nothing): the same x bit for bit
+    as the host-driven solve, for a solve that refines and one that stops at
+    once (max_iter = 0)."""
+    pat, v = kktgen.workload("small", instance=5)
+    v = kktgen.nmpc_values(pat, kktgen.rng_for(0, 5, 3), 1e-8, 1e8)
+    print("solve async vs sync", flush=True)
+    st, bad, x_sync, info, f = lifted_run(kkt, pat, v, ordering=2, nd_leaf=64)
+    assert st == 0
+    # tol = 0: refinement runs until omega stops halving or max_iter
+    for max_iter, tol in ((10, 0.0), (10, 1e-14), (0, 0.0)):
+        xs = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
+        si = f.solve(dev(v.b), xs, max_iter=max_iter, tol=tol)
+        assert si["iters"] >= (1 if max_iter and tol == 0.0 else 0), si
+        xa = torch.full((pat.n,), float("nan"), dtype=torch.float64, device="cuda")
+        assert f.solve(dev(v.b), xa, max_iter=max_iter, tol=tol, info=False) is None
+        assert f.status()[0] == 0
+        assert np.array_equal(host(xa), host(xs)), (max_iter, tol)
+
+
+def test_cg_async_matches_sync(kkt):
+    """kkt_cg_schur without an info record queues maxit iterations whose
+    stop decisions are taken on the device: dx and dy equal the synchronous
+    call's bit for bit (recurrence stop and eta stop)."""
+    pat, v = kktgen.workload("hykkt")
+    print("cg async vs sync", flush=True)
+    f = kkt.Factor(kkt.Symbolic.from_pattern(pat, ordering=2, nd_leaf=64))
+    f.refactor(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), None, 1e4)
+    for eta_tol in (0.0, 1e-12):
+        out = []
+        for info in (True, False):
+            dx = torch.full((pat.n,), float("nan"), dtype=torch.float64, device="cuda")
+            dy = torch.full((pat.m,), float("nan"), dtype=torch.float64, device="cuda")
+            ci = f.cg_schur(dev(v.f), dev(v.g), dx, dy, tol=1e-10, maxit=40, eta_tol=eta_tol, info=info)
+            if info:
+                assert ci["status"] == 0 and ci["iters"] < 40, ci
+            out.append((host(dx), host(dy)))
+        assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1]), eta_tol
 
 
 def test_cg_on_lifted_factor_refused(kkt):
@@ -293,7 +344,7 @@ def test_hykkt_larger_system(kkt):
     info = f.cg_schur(dev(v.f), dev(v.g), dx, dy, tol=1e-10, maxit=200)
     assert info["status"] == 0
     dxh, dyh = host(dx), host(dy)
-    assert D.hykkt_backward_errors(pat, v, dxh, dyh, v.f, v.g)["eta"] <= 1e-10
+    check_device_eta(info, D.hykkt_backward_errors(pat, v, dxh, dyh, v.f, v.g))
     assert D.forward_error(dxh, dx0) <= 1e-8 and D.forward_error(dyh, dy0) <= 1e-8
     _, _, oinfo = S.hykkt_cg_solve(pat, v, v.f, v.g, 1e7, tol=1e-10)
     assert abs(info["iters"] - oinfo["iters"]) <= 1
@@ -320,7 +371,9 @@ def test_hykkt_wide_sigma(kkt, inst):
     info = f.cg_schur(dev(v.f), dev(v.g), dx, dy, tol=1e-10, maxit=1000)
     assert info["status"] == 0, info
     dxh, dyh = host(dx), host(dy)
-    assert D.hykkt_backward_errors(pat, v, dxh, dyh, v.f, v.g)["eta"] <= 1e-10
+    be = D.hykkt_backward_errors(pat, v, dxh, dyh, v.f, v.g)
+    assert be["eta"] <= 1e-10
+    check_device_eta(info, be)
     assert D.forward_error(dxh, dxb) <= 1e-7 and D.forward_error(dyh, dyb) <= 1e-7
     _, _, oinfo = S.hykkt_cg_solve(pat, v, v.f, v.g, 1e7, tol=1e-10, maxit=1000)
     assert oinfo["status"] == "ok" and abs(info["iters"] - oinfo["iters"]) <= 2, (info, oinfo)
@@ -347,6 +400,31 @@ def test_hykkt_paper_scale_cg_count(kkt):
         _, _, oinfo = S.hykkt_cg_solve(pat, v, v.f, v.g, 1e7, tol=1e-10, maxit=200)
         print(vs, info, oinfo, flush=True)
         assert oinfo["status"] == "ok" and abs(info["iters"] - oinfo["iters"]) <= 1
-        assert D.hykkt_backward_errors(pat, v, dxh, dyh, v.f, v.g)["eta"] <= 1e-10
+        check_device_eta(info, D.hykkt_backward_errors(pat, v, dxh, dyh, v.f, v.g))
         dx0, dy0, _, ok = S.hykkt_saddle_solve(pat, v, v.f, v.g)
         assert ok and D.forward_error(dxh, dx0) <= 1e-6 and D.forward_error(dyh, dy0) <= 1e-6
+
+
+def test_hykkt_paper_scale_wide_sigma_eta_stop(kkt):
+    """HyKKT at paper scale (n=142,000) in the late-iteration range
+    Sigma_x ~ logU[1e-8, 1e8], gamma = 1e7 (section "Solution 2: HyKKT").
+    There lambda_min(J K0^{-1} J^T) is ~1e-11, so kappa(S_gamma) is in the
+    thousands and CG cannot bring ||r|| below 1e-10 ||c|| (the oracle's CG
+    stalls too); the saddle system's normwise backward error, the gate, falls
+    below 1e-10 within tens of iterations. With eta_tol = 1e-10 the CG stops
+    on its bound: the library's eta and the oracle's evaluation of the same
+    (dx, dy) are both <= 1e-10 for two value sets."""
+    pat, _ = kktgen.paper_config()
+    f = kkt.Factor(kkt.Symbolic.from_pattern(pat, ordering=2, nd_leaf=417, max_super=96))
+    dx = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
+    dy = torch.zeros(pat.m, dtype=torch.float64, device="cuda")
+    for vs in range(2):
+        v = kktgen.distillation_values(pat, kktgen.rng_for(1, 0, vs), 1e-8, 1e8)
+        print(f"paper-scale hykkt wide sigma value set {vs}", flush=True)
+        f.refactor(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), None, 1e7)
+        assert f.status()[0] == 0
+        info = f.cg_schur(dev(v.f), dev(v.g), dx, dy, tol=1e-10, maxit=300, eta_tol=1e-10)
+        print(vs, info, flush=True)
+        assert info["status"] == 0 and info["eta_stop"] == 1, info
+        be = D.hykkt_backward_errors(pat, v, host(dx), host(dy), v.f, v.g)
+        check_device_eta(info, be)
