@@ -261,6 +261,22 @@ void kkt_cg_opts_default(kkt_cg_opts* o);
 kkt_status kkt_cg_schur(kkt_factor* f, const double* fv, const double* g, const kkt_cg_opts* opts,
                         double* dx, double* dy, kkt_cg_info* info, void* stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): kkt_solve
+ * with the same arguments, results (bit for bit) and synchronisation rules,
+ * whose per-solve workspace lives in a static device array of the library
+ * (32 MiB per GPU, held until the process ends) instead of the factor's
+ * storage. The call allocates nothing: no hipMalloc, no host allocation of
+ * the runtime, no event (per-launch timers are suspended during the call).
+ * Errors: those of kkt_solve, and BUDGET when the workspace (about 24 n +
+ * 8 * update rows + 176 * supernodes bytes) exceeds the array. Every call on
+ * a GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, other host threads) race and must be serialised by the caller.
+ */
+kkt_status kkt_solve_noalloc(kkt_factor* f, const double* b, double* x, const kkt_refine_opts* ro,
+                             kkt_solve_info* info, void* stream);
+
 /* Matrix-vector product y = K x with the assembled K of the current factor
  * (device arrays of n). Asynchronous. Used to evaluate residuals. */
 kkt_status kkt_matvec(kkt_factor* f, const double* x, double* y, void* stream);

@@ -19,7 +19,8 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall"]
 
-SOURCES = [("kernels.hip", "hip"), ("api.cpp", "hip"), ("server.cpp", "hip"), ("symbolic.cpp", "host")]
+SOURCES = [("kernels.hip", "hip"), ("api.cpp", "hip"), ("server.cpp", "hip"), ("noalloc.cpp", "hip"),
+           ("symbolic.cpp", "host")]
 
 
 def _run(cmd):

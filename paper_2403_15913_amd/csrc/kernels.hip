@@ -2118,6 +2118,35 @@ __global__ __launch_bounds__(256) void k_cg_res_m(const InstDev* __restrict__ in
 }
 
 // ---------------------------------------------------------------------------
+// workspace redirection (allocation-free solve): copies of a factor's instance
+// descriptor and front descriptors whose per-solve vectors point into a
+// caller-provided workspace
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ws_redirect(const InstDev* __restrict__ src_inst,
+                                                     const FrontDesc* __restrict__ src_fd, int nf, SolveWs w) {
+    const InstDev& S = src_inst[0];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        InstDev D = S;
+        D.y = w.y;
+        D.V = w.V;
+        D.r = w.r;
+        D.xprev = w.xprev;
+        D.rpart = w.rpart;
+        D.rs = w.rs;
+        w.inst[0] = D;
+    }
+    if (t >= nf) return;
+    FrontDesc F = src_fd[t];
+    F.y = w.y + F.col0;
+    F.V = w.V + (F.V - S.V);
+    for (int j = 0; j < 2; j++)
+        if (j < F.nch) F.cV[j] = w.V + (F.cV[j] - S.V);
+    F.done = &w.rs->done;
+    w.fd[t] = F;
+}
+
+// ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
 hipError_t set_kernel_attributes() {
@@ -2135,6 +2164,9 @@ hipError_t set_kernel_attributes() {
 
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+void launch_ws_redirect(const InstDev* src_inst, const FrontDesc* src_fd, int nf, const SolveWs& w, hipStream_t st) {
+    k_ws_redirect<<<blocks_for(nf > 0 ? nf : 1, 256), 256, 0, st>>>(src_inst, src_fd, nf, w);
+}
 void launch_copy_segments(const CopySeg* segs, int nseg, hipStream_t st) {
     if (nseg > 0) k_copy_segments<<<nseg * kCopyParts, 256, 0, st>>>(segs);
 }

@@ -56,6 +56,22 @@ constexpr int kSweepSplitMin = 512;
 
 hipError_t set_kernel_attributes();
 
+// Per-solve workspace of one instance held outside the factor (the
+// allocation-free solve): redirected copies of the instance and front
+// descriptors and the vectors a refined solve writes.
+struct SolveWs {
+    InstDev* inst;       // 1
+    FrontDesc* fd;       // one per front, in the factor's launch order
+    double* y;           // n: permuted work vector
+    double* V;           // forward-sweep update vectors (the factor's V layout)
+    double* r;           // n: residual
+    double* xprev;       // n: previous iterate
+    double* rpart;       // residual block maxima
+    RefineState* rs;     // 1
+};
+// Writes ws.inst and ws.fd from the factor's descriptors (src_inst[0],
+// src_fd[0 .. nf)) with every per-solve pointer moved into ws.
+void launch_ws_redirect(const InstDev* src_inst, const FrontDesc* src_fd, int nf, const SolveWs& ws, hipStream_t st);
 
 // A device-to-device copy of `len` doubles (gathering a served wave's inputs).
 struct CopySeg {

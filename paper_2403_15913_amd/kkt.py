@@ -102,6 +102,7 @@ SIGNATURES = {
     "kkt_refactor": (I32, [P, P, P, P, P, D, P]),
     "kkt_status_sync": (I32, [P, P]),
     "kkt_solve": (I32, [P, P, P, P, P, P]),
+    "kkt_solve_noalloc": (I32, [P, P, P, P, P, P]),
     "kkt_cg_opts_default": (None, [P]),
     "kkt_cg_schur": (I32, [P, P, P, P, P, P, P, P]),
     "kkt_matvec": (I32, [P, P, P, P]),
@@ -254,6 +255,16 @@ def kkt_solve(h, b, x, max_iter: int = 10, tol: float = 1e-14, info: bool = True
     return si.as_dict() if info else None
 
 
+def kkt_solve_noalloc(h, b, x, max_iter: int = 10, tol: float = 1e-14, info: bool = True, stream=None):
+    ro = RefineOpts(max_iter, tol)
+    si = SolveInfo()
+    st = lib().kkt_solve_noalloc(h, _dptr(b), _dptr(x), C.byref(ro), C.byref(si) if info else None,
+                                 _stream(stream))
+    if st not in (KKT_OK, 6):
+        _err(st)
+    return si.as_dict() if info else None
+
+
 def kkt_cg_opts_default() -> CgOpts:
     o = CgOpts()
     lib().kkt_cg_opts_default(C.byref(o))
@@ -343,6 +354,8 @@ class Factor:
     def solve(self, b, x, max_iter=10, tol=1e-14, info=True, stream=None):
         return kkt_solve(self.h, b, x, max_iter, tol, info, stream)
 
+    def solve_noalloc(self, b, x, max_iter=10, tol=1e-14, info=True, stream=None):
+        return kkt_solve_noalloc(self.h, b, x, max_iter, tol, info, stream)
 
     def cg_schur(self, f, g, dx, dy, tol=1e-10, maxit=200, eta_tol=0.0, info=True, stream=None):
         return kkt_cg_schur(self.h, f, g, dx, dy, tol, maxit, eta_tol, info, stream)
