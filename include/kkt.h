@@ -431,16 +431,19 @@ kkt_status kkt_server_create(const kkt_server_opts* opt, kkt_server** out);
 kkt_status kkt_server_register(kkt_server* s, const kkt_symbolic* sym, int32_t* pattern_id);
 
 /* Queues one Lifted-KKT refactor+solve: device arrays in the pattern's entry
- * order (w_vals, j_vals, sigma_x, sigma_s, b) and the output x (n). They must
- * stay valid (inputs unchanged) until kkt_server_wait returns for *ticket.
- * Returns at once. */
+ * order (w_vals, j_vals, sigma_x, sigma_s, b) and the output x (n). The
+ * request is ordered after the work enqueued on `stream` (a hipStream_t,
+ * NULL = the default stream) before this call: an event recorded there at
+ * submission is waited for by the worker's stream before it reads the inputs
+ * or writes x. The arrays must stay valid (inputs unchanged) until
+ * kkt_server_wait returns for *ticket. Returns at once. */
 kkt_status kkt_server_submit(kkt_server* s, int32_t pattern_id, const double* w_vals, const double* j_vals,
                              const double* sigma_x, const double* sigma_s, const double* b, double* x,
-                             int64_t* ticket);
+                             void* stream, int64_t* ticket);
 
-/* Blocks until the request is done; returns its status (NOT_SPD, NONFINITE,
- * NOT_CONVERGED or OK) and fills its solve info and latency (may be NULL).
- * A ticket can be waited for once. */
+/* Blocks until the request is done (its x complete on the device); returns
+ * its status (NOT_SPD, NONFINITE, NOT_CONVERGED or OK) and fills its solve
+ * info and latency (may be NULL). A ticket can be waited for once. */
 kkt_status kkt_server_wait(kkt_server* s, int64_t ticket, kkt_solve_info* info, double* latency_s);
 
 kkt_status kkt_server_get_stats(kkt_server* s, kkt_server_stats* out);

@@ -243,8 +243,8 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         ko[q + 1] = ko[q] + S.nnzk;
         co[q + 1] = co[q] + S.sp_ptr[S.n];
         po[q + 1] = po[q] + 5 * (int64_t)((S.n + kBlock - 1) / kBlock) * kResidualSplit;
-        // CG reduction slots: 4 per 256-row block of n, then 4 per block of m
-        ro[q + 1] = ro[q] + 4 * (int64_t)((S.n + kBlock - 1) / kBlock + (S.m + kBlock - 1) / kBlock + 1);
+        // CG reduction slots: 4 per 256-row block of n, 4 then 2 per block of m
+        ro[q + 1] = ro[q] + 4 * (int64_t)((S.n + kBlock - 1) / kBlock) + 6 * (int64_t)((S.m + kBlock - 1) / kBlock) + 4;
         for (int k = 0; k < S.ns; k++) {
             lds_factor = std::max(lds_factor, (size_t)factor_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]));
             lds_solve = std::max(lds_solve, (size_t)solve_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]));
@@ -806,13 +806,16 @@ kkt_status Engine::replay(kkt_solve_info* infos, hipStream_t st) {
     return solve_finish(g_calls, g_rounds, g_maxit, g_tol, infos, st);
 }
 
-// One CG iteration (three launches around the sweep pair; see the CG kernels).
-// `parity` alternates the two direction buffers.
-void Engine::cg_iteration(int parity, hipStream_t st) {
-    TL(KKT_PHASE_CG, launch_cg_dir(di(), cg_calls, nitems, n_nitems, parity, ndone, st));
+// CG iteration k: the stop tests of dy_k and the direction (k_cg_dir), the
+// eta test when asked for, then S_gamma p_k and the update; iteration maxit
+// is the last test only.
+void Engine::cg_iteration(int k, int maxit, bool eta_test, hipStream_t st) {
+    TL(KKT_PHASE_CG, launch_cg_dir(di(), nitems, n_nitems, k, ndone, st));
+    if (k >= maxit) return;
+    if (eta_test) TL(KKT_PHASE_CONTROL, launch_cg_eta_test(di(), cg_calls, ninst, k, ndone, st));
     sweeps(st, SKIP_CG);
-    TL(KKT_PHASE_CG, launch_cg_q(di(), mitems, n_mitems, parity, ndone, st));
-    TL(KKT_PHASE_CG, launch_cg_upd(di(), cg_calls, mitems, n_mitems, parity, ndone, st));
+    TL(KKT_PHASE_CG, launch_cg_q(di(), mitems, n_mitems, k, st));
+    TL(KKT_PHASE_CG, launch_cg_upd(di(), cg_calls, mitems, n_mitems, k, ndone, st));
 }
 
 kkt_status Engine::cg_schur(const Calls& C, double tol, int maxit, double eta_tol, kkt_cg_info* info,
@@ -820,16 +823,17 @@ kkt_status Engine::cg_schur(const Calls& C, double tol, int maxit, double eta_to
     last_stream = st;
     cg_calls = C;
     int* nd = ndone;
+    const bool eta_test = eta_tol > 0.0;
     TL(KKT_PHASE_CONTROL, launch_fill_i32(nd, 0, 1, st));
     // f_gamma = f + gamma J^T g (pivot order), c = J K_gamma^{-1} f_gamma - g
-    TL(KKT_PHASE_CG, launch_cg_fg(di(), C, nitems, n_nitems, st));
+    TL(KKT_PHASE_CG, launch_cg_fg(di(), C, nitems, n_nitems, tol, maxit, eta_tol, st));
     sweeps(st, SKIP_NONE);
-    TL(KKT_PHASE_CG, launch_cg_c(di(), C, mitems, n_mitems, tol, maxit, eta_tol, nd, st));
+    TL(KKT_PHASE_CG, launch_cg_c(di(), C, mitems, n_mitems, ninst, st));
     hipError_t e = hipSuccess;
     if (!info) {
-        // asynchronous: all maxit iterations are queued; once an instance's
-        // CG has stopped, its kernels of the later iterations return at once
-        for (int k = 0; k < maxit; k++) cg_iteration(k & 1, st);
+        // asynchronous: every iteration is queued; once an instance's CG has
+        // stopped, its kernels of the later iterations return at once
+        for (int k = 0; k <= maxit; k++) cg_iteration(k, maxit, eta_test, st);
     } else {
         // With one iteration of lookahead: iteration k+1 is queued before
         // the host reads the count of stopped instances after iteration k.
@@ -838,32 +842,27 @@ kkt_status Engine::cg_schur(const Calls& C, double tol, int maxit, double eta_to
         volatile int* slot[2] = {(volatile int*)hpin, (volatile int*)hpin + 16};
         hipEvent_t ev[2] = {ctl_event, ctl_event2};
         auto issue = [&](int k) -> hipError_t {
-            cg_iteration(k & 1, st);
+            cg_iteration(k, maxit, eta_test, st);
             hipError_t r = hipMemcpyAsync((void*)slot[k & 1], nd, 4, hipMemcpyDeviceToHost, st);
             if (r == hipSuccess) r = hipEventRecord(ev[k & 1], st);
             return r;
         };
-        if ((e = hipMemcpyAsync((void*)slot[1], nd, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-            (e = hipStreamSynchronize(st)) != hipSuccess)
-            return hip_fail(e, "cg control");
         kkt_status fst = read_status(nullptr, nullptr);
         if (fst != KKT_OK) return fail(fst, "factor failed; solve refused");
         int issued = 0;
-        if (*slot[1] < ninst) {
-            while (issued < maxit && issued < 2)
-                if ((e = issue(issued++)) != hipSuccess) return hip_fail(e, "cg control");
-            for (int k = 0; k < issued; k++) {
-                if ((e = hipEventSynchronize(ev[k & 1])) != hipSuccess) return hip_fail(e, "cg control");
-                if (*slot[k & 1] >= ninst) break;
-                if (issued < maxit && (e = issue(issued++)) != hipSuccess) return hip_fail(e, "cg control");
-            }
+        while (issued <= maxit && issued < 2)
+            if ((e = issue(issued++)) != hipSuccess) return hip_fail(e, "cg control");
+        for (int k = 0; k < issued; k++) {
+            if ((e = hipEventSynchronize(ev[k & 1])) != hipSuccess) return hip_fail(e, "cg control");
+            if (*slot[k & 1] >= ninst) break;
+            if (issued <= maxit && (e = issue(issued++)) != hipSuccess) return hip_fail(e, "cg control");
         }
     }
     // dx = K_gamma^{-1}(f_gamma - J^T dy), then the saddle-system residual and eta
     TL(KKT_PHASE_CG, launch_cg_dxrhs(di(), C, nitems, n_nitems, st));
     sweeps(st, SKIP_NONE);
     TL(KKT_PHASE_PERMUTE, launch_perm_out(di(), C, nitems, n_nitems, POUT_DX, st));
-    TL(KKT_PHASE_RESIDUAL, launch_cg_residual(di(), C, nitems, n_nitems, mitems, n_mitems, st));
+    TL(KKT_PHASE_RESIDUAL, launch_cg_residual(di(), C, nitems, n_nitems, mitems, n_mitems, ninst, st));
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "cg launch");
     if (!info) return KKT_OK;
@@ -877,7 +876,10 @@ kkt_status Engine::cg_schur(const Calls& C, double tol, int maxit, double eta_to
     info->eta = G.eta;
     info->eta_stop = G.eta_stop;
     info->status = G.status == 0 ? (G.done ? KKT_OK : KKT_ERR_NOT_CONVERGED) : G.status;
-    return info->status;
+    if (info->status != KKT_OK)
+        return fail(info->status, info->status == KKT_ERR_BREAKDOWN ? "CG breakdown (p^T S p <= 0)"
+                                                                    : "CG reached its iteration limit");
+    return KKT_OK;
 }
 
 }  // namespace kkt

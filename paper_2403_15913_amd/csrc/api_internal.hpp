@@ -144,7 +144,7 @@ struct Engine {
     kkt_status replay(kkt_solve_info* infos, hipStream_t st);
     void drop_graph();
     kkt_status cg_schur(const Calls& C, double tol, int maxit, double eta_tol, kkt_cg_info* info, hipStream_t st);
-    void cg_iteration(int parity, hipStream_t st);
+    void cg_iteration(int k, int maxit, bool eta_test, hipStream_t st);
     Calls cg_calls{};
     // asynchronous solve: the first solve and max_iter refinement rounds,
     // every kernel gated by the instance's stop flag, no read-back

@@ -64,18 +64,18 @@ struct RefineState {
     int revert;    // 1: the previous iterate is the better one
 };
 
-// Conjugate-gradient scalars of one instance (eq. (schurcomp)), written by
-// the last workgroup of each reduction (see cg_last_block).
+// Conjugate-gradient record of one instance (eq. (schurcomp)), written by the
+// instance's workgroup 0 of the kernel that takes each decision.
 struct CgState {
-    double rr, rr_new, pq, cnorm, alpha, beta, tol;
+    double rrs[2];           // r_k . r_k of iteration k in rrs[k & 1]
+    double rr_new, pq, cnorm, tol;
     double eta_tol;          // > 0: also stop once the saddle system's eta bound is below it
     double norm_a;           // ||[[K0, J^T], [J, 0]]||_inf
     double norm_rhs;         // max(||f||_inf, ||g||_inf)
-    double rmax, dymax;      // ||r||_inf (last eta test) and ||dy||_inf (last update)
+    double rmax, dymax;      // ||r||_inf and ||dy||_inf of the last eta test
     double eta;              // normwise backward error of (dx, dy) on the saddle system
     int it, maxit, done, status;
     int eta_stop;            // 1: stopped by the eta bound
-    int arrive;              // workgroups arrived at the current reduction
 };
 
 struct InstDev {

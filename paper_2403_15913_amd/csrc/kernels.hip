@@ -1712,16 +1712,30 @@ __global__ __launch_bounds__(256) void k_matvec(const InstDev* __restrict__ inst
 // order, so J^T v is written straight into the sweep vector (pivot position k
 // holds column perm[k]) and J t reads the sweep output through j_colp.
 //
-// One iteration is three launches around the sweep pair:
-//   k_cg_dir  p = r + beta p_old (row owners) and y = J^T p for the sweeps,
-//             with p's entries formed on the fly, so no launch separates them;
-//   k_cg_q    q = J K_gamma^{-1} J^T p and the partial sums of p.q; the last
-//             workgroup forms alpha = r.r / p.q (or flags a breakdown);
-//   k_cg_upd  dy += alpha p, r -= alpha q, the partial sums of r.r and the
-//             maximum of |dy|; the last workgroup takes the stop decision
-//             and beta.
-// Every kernel returns at once when the instance's CG has stopped, so a
-// sequence of iterations can be queued without reading the decisions back.
+// Iteration k is three launches around the sweep pair:
+//   k_cg_dir  the stop tests of the iterate dy_k, then p_k = r_k + beta_k p_{k-1}
+//             (row owners) and y = J^T p_k for the sweeps, each entry of p_k
+//             formed on the fly by the same fma as its stored value;
+//   k_cg_q    q = J K_gamma^{-1} J^T p_k and the partial sums of p.q;
+//   k_cg_upd  alpha = r.r / p.q, dy += alpha p, r -= alpha q, and the partial
+//             sums of r.r and maxima of |dy|.
+// Each scalar (r.r, p.q, the norms) is reduced from the previous launch's
+// per-workgroup partial sums by every workgroup that needs it, in one fixed
+// order, so every workgroup takes the same decision without any
+// synchronisation inside a launch; workgroup 0 of the instance records it.
+// Every kernel returns at once when the instance's CG has stopped, so the
+// iterations can be queued without reading decisions back.
+//
+// Reduction slots of one instance (4 per 256-row block):
+//   N-region red[4 b + k], n-side blocks:  0 max row sum of |A|, 1 max |f|
+//                                          (k_cg_fg); 2 max |r|, 3 max
+//                                          |J^T r| (k_cg_dir, eta test);
+//                                          0, 1 again for the final residual
+//   M-region red[mslot0 + 4 b + k]:        0 r.r, 1 max |dy| (k_cg_c with
+//                                          dy = 0, then k_cg_upd); 2 max |g|,
+//                                          3 max row sum of |J| (k_cg_c)
+//   Q-region red[qslot0 + 2 b + k]:        p.q (k_cg_q, stride 1); the final
+//                                          residual's max |g - J dx|, |dy|
 // ---------------------------------------------------------------------------
 // deterministic block sum of v (every thread gets the sum)
 __device__ inline double block_sum(double v) {
@@ -1752,55 +1766,65 @@ __device__ inline double block_max(double v) {
     return t;
 }
 
-// Reduction slots of one instance: the n-side kernels write 4 values per
-// 256-row block at red[4 b + k]; the m-side kernels at red[mslot0 + 4 b + k].
-__device__ __forceinline__ int cg_mslot0(const InstDev& I) { return 4 * ((I.P.n + 255) >> 8); }
+__device__ __forceinline__ int cg_nb(int len) { return (len + 255) >> 8; }
+__device__ __forceinline__ int cg_mslot0(const InstDev& I) { return 4 * cg_nb(I.P.n); }
+__device__ __forceinline__ int cg_qslot0(const InstDev& I) { return 4 * (cg_nb(I.P.n) + cg_nb(I.P.m)); }
 
-// Every thread of the workgroup returns true in the instance's last
-// workgroup to arrive at this reduction (the arrival counter is reset there
-// for the next one). Thread 0 published this workgroup's slots before the
-// release; the last workgroup reads every slot after the acquire.
-__device__ inline bool cg_last_block(CgState* G, int nblocks) {
-    __shared__ int last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const int prev = __hip_atomic_fetch_add(&G->arrive, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        last = prev == nblocks - 1;
-        if (last) __hip_atomic_store(&G->arrive, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    const int l = __builtin_amdgcn_readfirstlane(last);
-    if (l) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return l != 0;
-}
-
-// slot values of other workgroups: atomic loads, so nothing is served from a
-// stale cache line or hoisted above the acquire
-__device__ __forceinline__ double slot_load(const double* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// fixed-order sum / maximum over slots k of nb blocks (stride 4)
-__device__ inline double slots_sum(const double* red, int nb, int k) {
+// fixed-order sum / maximum over slot k of nb blocks (stride `stride`)
+__device__ inline double slots_sum(const double* red, int nb, int stride, int k) {
     double v = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) v += slot_load(red + 4 * b + k);
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) v += red[stride * b + k];
     return block_sum(v);
 }
-__device__ inline double slots_max(const double* red, int nb, int k) {
+__device__ inline double slots_max(const double* red, int nb, int stride, int k) {
     double v = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) v = fmax(v, slot_load(red + 4 * b + k));
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) v = fmax(v, red[stride * b + k]);
     return block_max(v);
 }
 
+// sum_q a[q] * v[idx[q]] over q in [q0, q1), four loads in flight per round,
+// terms added in q order
+template <class F>
+__device__ __forceinline__ double gather_dot(int q0, int q1, const double* __restrict__ a,
+                                             const int* __restrict__ idx, F&& v) {
+    double s = 0.0;
+    for (int q = q0; q < q1; q += 4) {
+        int id[4];
+        double av[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int qc = min(q + u, q1 - 1);
+            id[u] = idx[qc];
+            av[u] = a[qc];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) xv[u] = v(id[u]);
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (q + u < q1) s += av[u] * xv[u];
+    }
+    return s;
+}
+
 // f_gamma = f + gamma J^T g in pivot order (sweep vector and a copy for dx),
-// and the n-side norms: per row i of the saddle matrix, sum_j |K0_ij| +
-// sum_r |J_ri|; |f_i|.
+// the n-side norms (per row i of the saddle matrix, sum_j |K0_ij| +
+// sum_r |J_ri|; |f_i|), and the CG record's set-up (workgroup 0).
 __global__ __launch_bounds__(256) void k_cg_fg(const InstDev* __restrict__ insts, Calls C,
-                                               const WorkItem* __restrict__ items) {
+                                               const WorkItem* __restrict__ items, double tol, int maxit,
+                                               double eta_tol) {
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
-    if (it.id == 0 && threadIdx.x == 0) I.cg->arrive = 0;
+    if (it.id == 0 && threadIdx.x == 0) {
+        CgState* G = I.cg;
+        G->tol = tol;
+        G->maxit = maxit;
+        G->eta_tol = eta_tol;
+        G->it = 0;
+        G->status = 0;
+        G->done = 0;
+        G->eta_stop = 0;
+        G->eta = 0.0;
+    }
     const int k = it.id + threadIdx.x;
     double arow = 0.0, fa = 0.0;
     if (k < I.P.n) {
@@ -1831,21 +1855,18 @@ __global__ __launch_bounds__(256) void k_cg_fg(const InstDev* __restrict__ insts
 }
 
 // After the sweeps: c = J K_gamma^{-1} f_gamma - g; r = c; p_old = 0; dy = 0;
-// the m-side norms; the last workgroup sets up the CG state.
+// partial sums of c.c and the m-side norms.
 __global__ __launch_bounds__(256) void k_cg_c(const InstDev* __restrict__ insts, Calls C,
-                                              const WorkItem* __restrict__ items, double tol, int maxit,
-                                              double eta_tol, int* ndone) {
+                                              const WorkItem* __restrict__ items) {
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
     const int i = it.id + threadIdx.x;
     double cc = 0.0, ga = 0.0, jrow = 0.0;
     if (i < I.P.m) {
-        const double* __restrict__ jv = I.js;
-        double s = 0.0;
-        for (int p = I.P.j_ptr[i]; p < I.P.j_ptr[i + 1]; p++) {
-            s += jv[p] * I.y[I.P.j_colp[p]];
-            jrow += fabs(jv[p]);
-        }
+        const int p0 = I.P.j_ptr[i], p1 = I.P.j_ptr[i + 1];
+        const double* __restrict__ y = I.y;
+        const double s = gather_dot(p0, p1, I.js, I.P.j_colp, [&](int c) { return y[c]; });
+        for (int p = p0; p < p1; p++) jrow += fabs(I.js[p]);
         const double gi = C.g[I.m_off + i];
         const double ci = s - gi;
         I.cvec[i] = ci;
@@ -1858,78 +1879,86 @@ __global__ __launch_bounds__(256) void k_cg_c(const InstDev* __restrict__ insts,
     cc = block_sum(cc);
     ga = block_max(ga);
     jrow = block_max(jrow);
-    const int m0 = cg_mslot0(I);
     if (threadIdx.x == 0) {
-        double* s = I.red + m0 + 4 * (it.id >> 8);
+        double* s = I.red + cg_mslot0(I) + 4 * (it.id >> 8);
         s[0] = cc;
-        s[1] = ga;
-        s[2] = jrow;
-    }
-    CgState* G = I.cg;
-    const int nbm = (I.P.m + 255) >> 8, nbn = (I.P.n + 255) >> 8;
-    if (!cg_last_block(G, nbm)) return;
-    const double rr = slots_sum(I.red + m0, nbm, 0);
-    const double gmax = slots_max(I.red + m0, nbm, 1);
-    const double jr = slots_max(I.red + m0, nbm, 2);
-    const double an = slots_max(I.red, nbn, 0);
-    const double fmx = slots_max(I.red, nbn, 1);
-    if (threadIdx.x == 0) {
-        G->rr = rr;
-        G->rr_new = rr;
-        G->cnorm = sqrt(rr);
-        G->tol = tol;
-        G->eta_tol = eta_tol;
-        G->maxit = maxit;
-        G->norm_a = fmax(an, jr);
-        G->norm_rhs = fmax(fmx, gmax);
-        G->rmax = 0.0;
-        G->dymax = 0.0;
-        G->eta = 0.0;
-        G->it = 0;
-        G->status = 0;
-        G->eta_stop = 0;
-        G->alpha = G->beta = 0.0;
-        G->pq = 0.0;
-        G->done = rr == 0.0 ? 1 : 0;  // c == 0: dy = 0 solves the Schur system
-        if (G->done) atomicAdd(ndone, 1);
+        s[1] = 0.0;  // ||dy_0||_inf
+        s[2] = ga;
+        s[3] = jrow;
     }
 }
 
-// p = r + beta p_old for the instance's rows (row i by thread i of the
-// n-side blocks; the Schur system needs m <= n) and y[k] = (J^T p)_{perm[k]},
-// each entry of p formed by the same fma as its stored value.
-// With eta_tol > 0 the kernel also takes the eta test of the current iterate
-// dy (its residual r is final here): for dx = K_gamma^{-1}(f_gamma - J^T dy)
-// the saddle system's residual is (gamma J^T r, r), so
-//   max(gamma ||J^T r||_inf, ||r||_inf) / (||A||_inf ||dy||_inf + ||(f, g)||_inf)
-// bounds its normwise backward error from above (the denominator leaves out
-// ||dx||); the last workgroup stops the CG when the bound is <= eta_tol.
-__global__ __launch_bounds__(256) void k_cg_dir(const InstDev* __restrict__ insts, Calls C,
-                                                const WorkItem* __restrict__ items, int parity, int* ndone) {
+// Iteration k: stop tests of dy_k (r_k . r_k from the M-region partials),
+// p_k = r_k + beta_k p_{k-1} for the instance's rows (row i by thread i of the
+// n-side blocks; the Schur system needs m <= n) and y[k'] = (J^T p_k)_{perm[k']}.
+// Stops: ||r_k||_2 <= tol ||c||_2 (converged) or k == maxit (NOT_CONVERGED).
+// With eta_tol > 0 the maxima of |r_k| and |J^T r_k| go to the N-region for
+// k_cg_eta_test.
+__global__ __launch_bounds__(256) void k_cg_dir(const InstDev* __restrict__ insts,
+                                                const WorkItem* __restrict__ items, int k, int* ndone) {
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
     CgState* G = I.cg;
     if (G->done) return;  // uniform per block
-    const double beta = G->beta;
-    const bool eta_test = G->eta_tol > 0.0;
+    const int nbm = cg_nb(I.P.m);
+    const double rr = slots_sum(I.red + cg_mslot0(I), nbm, 4, 0);
+    const double cnorm = k == 0 ? sqrt(rr) : G->cnorm;
+    const bool conv = k == 0 ? rr == 0.0 : sqrt(rr) <= G->tol * cnorm;
+    const bool lead = it.id == 0 && threadIdx.x == 0;
+    if (conv || k >= G->maxit) {
+        if (lead) {
+            G->rr_new = rr;
+            if (k == 0) G->cnorm = cnorm;
+            G->it = k;
+            G->status = conv ? 0 : 6;  // not converged after maxit iterations
+            G->done = 1;
+            atomicAdd(ndone, 1);
+        }
+        return;
+    }
+    const double beta = k == 0 ? 0.0 : rr / G->rrs[(k - 1) & 1];
+    if (lead) {
+        G->rrs[k & 1] = rr;
+        G->rr_new = rr;
+        G->it = k;
+        if (k == 0) G->cnorm = cnorm;
+    }
+    const int parity = k & 1;
     double* __restrict__ pn = parity ? I.pvec2 : I.pvec;
     const double* __restrict__ po = parity ? I.pvec : I.pvec2;
     const double* __restrict__ r = I.rvec;
-    const int k = it.id + threadIdx.x;
+    const int kk = it.id + threadIdx.x;
     double ra = 0.0, ja = 0.0;
-    if (k < I.P.m) {
-        pn[k] = fma(beta, po[k], r[k]);
-        ra = fabs(r[k]);
+    if (kk < I.P.m) {
+        pn[kk] = fma(beta, po[kk], r[kk]);
+        ra = fabs(r[kk]);
     }
-    if (k < I.P.n) {
+    const bool eta_test = G->eta_tol > 0.0;
+    if (kk < I.P.n) {
+        const int q0 = I.P.jtp_ptr[kk], q1 = I.P.jtp_ptr[kk + 1];
         double s = 0.0, t = 0.0;
-        for (int q = I.P.jtp_ptr[k]; q < I.P.jtp_ptr[k + 1]; q++) {
-            const int row = I.P.jtp_row[q];
-            const double a = I.jtv[q], rv = r[row];
-            s += a * fma(beta, po[row], rv);
-            t += a * rv;
+        for (int q = q0; q < q1; q += 4) {
+            int row[4];
+            double a[4], rv[4], pv[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int qc = min(q + u, q1 - 1);
+                row[u] = I.P.jtp_row[qc];
+                a[u] = I.jtv[qc];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                rv[u] = r[row[u]];
+                pv[u] = po[row[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (q + u < q1) {
+                    s += a[u] * fma(beta, pv[u], rv[u]);
+                    t += a[u] * rv[u];
+                }
         }
-        I.y[k] = s;
+        I.y[kk] = s;
         ja = fabs(t);
     }
     if (!eta_test) return;  // uniform per launch
@@ -1937,17 +1966,37 @@ __global__ __launch_bounds__(256) void k_cg_dir(const InstDev* __restrict__ inst
     ja = block_max(ja);
     if (threadIdx.x == 0) {
         double* sl = I.red + 4 * (it.id >> 8);
-        sl[0] = ra;
-        sl[1] = ja;
+        sl[2] = ra;
+        sl[3] = ja;
     }
-    const int nbn = (I.P.n + 255) >> 8;
-    if (!cg_last_block(G, nbn)) return;
-    const double rmax = slots_max(I.red, nbn, 0);
-    const double jrmax = slots_max(I.red, nbn, 1);
+}
+
+// eta_tol > 0, one workgroup per instance, between k_cg_dir and the sweeps:
+// for dx = K_gamma^{-1}(f_gamma - J^T dy) the saddle system's residual is
+// (gamma J^T r, r), so
+//   max(gamma ||J^T r||_inf, ||r||_inf) / (||A||_inf ||dy||_inf + ||(f, g)||_inf)
+// bounds its normwise backward error from above (the denominator leaves out
+// ||dx||); the CG stops at dy_k when the bound is <= eta_tol.
+__global__ __launch_bounds__(256) void k_cg_eta_test(const InstDev* __restrict__ insts, Calls C, int k,
+                                                     int* ndone) {
+    const InstDev& I = insts[blockIdx.x];
+    CgState* G = I.cg;
+    if (G->done || !(G->eta_tol > 0.0)) return;  // uniform
+    const int nbn = cg_nb(I.P.n), nbm = cg_nb(I.P.m);
+    const double* Nr = I.red;
+    const double* Mr = I.red + cg_mslot0(I);
+    const double norm_a = fmax(slots_max(Nr, nbn, 4, 0), slots_max(Mr, nbm, 4, 3));
+    const double norm_rhs = fmax(slots_max(Nr, nbn, 4, 1), slots_max(Mr, nbm, 4, 2));
+    const double rmax = slots_max(Nr, nbn, 4, 2);
+    const double jrmax = slots_max(Nr, nbn, 4, 3);
+    const double dymax = slots_max(Mr, nbm, 4, 1);
     if (threadIdx.x == 0) {
+        G->norm_a = norm_a;
+        G->norm_rhs = norm_rhs;
         G->rmax = rmax;
-        const double bound = fmax(C.gamma * jrmax, rmax);
-        if (bound <= G->eta_tol * (G->norm_a * G->dymax + G->norm_rhs)) {
+        G->dymax = dymax;
+        if (fmax(C.gamma * jrmax, rmax) <= G->eta_tol * (norm_a * dymax + norm_rhs)) {
+            G->it = k;
             G->done = 1;
             G->eta_stop = 1;
             atomicAdd(ndone, 1);
@@ -1955,52 +2004,48 @@ __global__ __launch_bounds__(256) void k_cg_dir(const InstDev* __restrict__ inst
     }
 }
 
-// q = J t with t = K_gamma^{-1} J^T p (the sweep output, pivot order) and
-// p.q; the last workgroup forms alpha or flags a breakdown (p^T S p <= 0).
+// q = J t with t = K_gamma^{-1} J^T p_k (the sweep output, pivot order) and the
+// partial sums of p_k . q
 __global__ __launch_bounds__(256) void k_cg_q(const InstDev* __restrict__ insts,
-                                              const WorkItem* __restrict__ items, int parity, int* ndone) {
+                                              const WorkItem* __restrict__ items, int k) {
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
-    CgState* G = I.cg;
-    if (G->done) return;  // uniform per block
-    const double* __restrict__ pn = parity ? I.pvec2 : I.pvec;
+    if (I.cg->done) return;  // uniform per block
+    const double* __restrict__ pn = (k & 1) ? I.pvec2 : I.pvec;
     const int i = it.id + threadIdx.x;
     double v = 0.0;
     if (i < I.P.m) {
-        const double* __restrict__ jv = I.js;
-        double s = 0.0;
-        for (int p = I.P.j_ptr[i]; p < I.P.j_ptr[i + 1]; p++) s += jv[p] * I.y[I.P.j_colp[p]];
+        const double* __restrict__ y = I.y;
+        const double s = gather_dot(I.P.j_ptr[i], I.P.j_ptr[i + 1], I.js, I.P.j_colp, [&](int c) { return y[c]; });
         I.qvec[i] = s;
         v = pn[i] * s;
     }
     v = block_sum(v);
-    const int m0 = cg_mslot0(I);
-    if (threadIdx.x == 0) I.red[m0 + 4 * (it.id >> 8)] = v;
-    const int nbm = (I.P.m + 255) >> 8;
-    if (!cg_last_block(G, nbm)) return;
-    const double pq = slots_sum(I.red + m0, nbm, 0);
-    if (threadIdx.x == 0) {
-        G->pq = pq;
-        if (!(pq > 0.0)) {
-            G->status = 7;  // breakdown
-            G->done = 1;
-            atomicAdd(ndone, 1);
-        } else {
-            G->alpha = G->rr / pq;
-        }
-    }
+    if (threadIdx.x == 0) I.red[cg_qslot0(I) + (it.id >> 8)] = v;
 }
 
-// dy += alpha p; r -= alpha q; the last workgroup: r.r, ||dy||_inf, the stop
-// rule ||r||_2 <= tol ||c||_2 or maxit iterations (NOT_CONVERGED), and beta.
+// alpha = r_k . r_k / p_k . q (p_k^T S p_k <= 0: BREAKDOWN), dy += alpha p_k,
+// r -= alpha q, and the partial sums of r.r and maxima of |dy|.
 __global__ __launch_bounds__(256) void k_cg_upd(const InstDev* __restrict__ insts, Calls C,
-                                                const WorkItem* __restrict__ items, int parity, int* ndone) {
+                                                const WorkItem* __restrict__ items, int k, int* ndone) {
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
     CgState* G = I.cg;
     if (G->done) return;  // uniform per block
-    const double a = G->alpha;
-    const double* __restrict__ pn = parity ? I.pvec2 : I.pvec;
+    const int nbm = cg_nb(I.P.m);
+    const double pq = slots_sum(I.red + cg_qslot0(I), nbm, 1, 0);
+    if (!(pq > 0.0)) {
+        if (it.id == 0 && threadIdx.x == 0) {
+            G->pq = pq;
+            G->it = k;
+            G->status = 7;  // breakdown
+            G->done = 1;
+            atomicAdd(ndone, 1);
+        }
+        return;
+    }
+    const double a = G->rrs[k & 1] / pq;
+    const double* __restrict__ pn = (k & 1) ? I.pvec2 : I.pvec;
     const int i = it.id + threadIdx.x;
     double rr = 0.0, da = 0.0;
     if (i < I.P.m) {
@@ -2014,30 +2059,10 @@ __global__ __launch_bounds__(256) void k_cg_upd(const InstDev* __restrict__ inst
     }
     rr = block_sum(rr);
     da = block_max(da);
-    const int m0 = cg_mslot0(I);
     if (threadIdx.x == 0) {
-        double* s = I.red + m0 + 4 * (it.id >> 8);
+        double* s = I.red + cg_mslot0(I) + 4 * (it.id >> 8);
         s[0] = rr;
         s[1] = da;
-    }
-    const int nbm = (I.P.m + 255) >> 8;
-    if (!cg_last_block(G, nbm)) return;
-    const double rr2 = slots_sum(I.red + m0, nbm, 0);
-    const double dymax = slots_max(I.red + m0, nbm, 1);
-    if (threadIdx.x == 0) {
-        G->it += 1;
-        G->rr_new = rr2;
-        G->dymax = dymax;
-        if (sqrt(rr2) <= G->tol * G->cnorm) {
-            G->done = 1;
-        } else if (G->it >= G->maxit) {
-            G->status = 6;  // not converged
-            G->done = 1;
-        } else {
-            G->beta = rr2 / G->rr;
-            G->rr = rr2;
-        }
-        if (G->done) atomicAdd(ndone, 1);
     }
 }
 
@@ -2049,8 +2074,7 @@ __global__ __launch_bounds__(256) void k_cg_dxrhs(const InstDev* __restrict__ in
     const int k = it.id + threadIdx.x;
     if (k >= I.P.n) return;
     const double* __restrict__ dy = C.dy + I.m_off;
-    double s = 0.0;
-    for (int q = I.P.jtp_ptr[k]; q < I.P.jtp_ptr[k + 1]; q++) s += I.jtv[q] * dy[I.P.jtp_row[q]];
+    const double s = gather_dot(I.P.jtp_ptr[k], I.P.jtp_ptr[k + 1], I.jtv, I.P.jtp_row, [&](int r) { return dy[r]; });
     I.y[k] = I.fg[k] - s;
 }
 
@@ -2080,8 +2104,7 @@ __global__ __launch_bounds__(256) void k_cg_res_n(const InstDev* __restrict__ in
     }
 }
 
-// constraint rows, g - J dx, with |dy|; the last workgroup forms
-// eta = ||res||_inf / (||A||_inf ||(dx, dy)||_inf + ||(f, g)||_inf).
+// constraint rows, g - J dx, with |dy|
 __global__ __launch_bounds__(256) void k_cg_res_m(const InstDev* __restrict__ insts, Calls C,
                                                   const WorkItem* __restrict__ items) {
     const WorkItem it = items[blockIdx.x];
@@ -2097,23 +2120,44 @@ __global__ __launch_bounds__(256) void k_cg_res_m(const InstDev* __restrict__ in
     }
     ra = block_max(ra);
     ya = block_max(ya);
-    const int m0 = cg_mslot0(I);
     if (threadIdx.x == 0) {
-        double* s = I.red + m0 + 4 * (it.id >> 8);
+        double* s = I.red + cg_qslot0(I) + 2 * (it.id >> 8);
         s[0] = ra;
         s[1] = ya;
     }
+}
+
+// one workgroup per instance: eta = ||res||_inf / (||A||_inf ||(dx, dy)||_inf
+// + ||(f, g)||_inf) from the residual kernels' maxima and the norms kept in
+// the record by k_cg_norms
+__global__ __launch_bounds__(256) void k_cg_eta(const InstDev* __restrict__ insts) {
+    const InstDev& I = insts[blockIdx.x];
     CgState* G = I.cg;
-    const int nbm = (I.P.m + 255) >> 8, nbn = (I.P.n + 255) >> 8;
-    if (!cg_last_block(G, nbm)) return;
-    const double r2 = slots_max(I.red + m0, nbm, 0);
-    const double y2 = slots_max(I.red + m0, nbm, 1);
-    const double r1 = slots_max(I.red, nbn, 0);
-    const double x1 = slots_max(I.red, nbn, 1);
+    const int nbn = cg_nb(I.P.n), nbm = cg_nb(I.P.m);
+    const double* Nr = I.red;
+    const double* Qr = I.red + cg_qslot0(I);
+    const double r1 = slots_max(Nr, nbn, 4, 0), x1 = slots_max(Nr, nbn, 4, 1);
+    const double r2 = slots_max(Qr, nbm, 2, 0), y2 = slots_max(Qr, nbm, 2, 1);
     if (threadIdx.x == 0) {
         const double den = G->norm_a * fmax(x1, y2) + G->norm_rhs;
         const double res = fmax(r1, r2);
         G->eta = den > 0.0 ? res / den : (res > 0.0 ? INFINITY : 0.0);
+    }
+}
+
+// one workgroup per instance, before the iterations: ||A||_inf (the n-side
+// part) and ||f||_inf from k_cg_fg's partials, kept in the record (the eta
+// test and the final residual overwrite the N-region)
+__global__ __launch_bounds__(256) void k_cg_norms(const InstDev* __restrict__ insts) {
+    const InstDev& I = insts[blockIdx.x];
+    CgState* G = I.cg;
+    const int nbn = cg_nb(I.P.n), nbm = cg_nb(I.P.m);
+    const double* Mr = I.red + cg_mslot0(I);
+    const double an = fmax(slots_max(I.red, nbn, 4, 0), slots_max(Mr, nbm, 4, 3));
+    const double fm = fmax(slots_max(I.red, nbn, 4, 1), slots_max(Mr, nbm, 4, 2));
+    if (threadIdx.x == 0) {
+        G->norm_a = an;
+        G->norm_rhs = fm;
     }
 }
 
@@ -2230,31 +2274,35 @@ void launch_refine_revert(const InstDev* insts, const Calls& C, const WorkItem* 
 void launch_matvec(const InstDev* insts, const double* x, double* y, const WorkItem* rows, int nitems, hipStream_t st) {
     if (nitems > 0) k_matvec<<<nitems, kBlock, 0, st>>>(insts, x, y, rows);
 }
-void launch_cg_fg(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, hipStream_t st) {
-    if (nitems > 0) k_cg_fg<<<nitems, kBlock, 0, st>>>(insts, C, ncols);
+void launch_cg_fg(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, double tol, int maxit,
+                  double eta_tol, hipStream_t st) {
+    if (nitems > 0) k_cg_fg<<<nitems, kBlock, 0, st>>>(insts, C, ncols, tol, maxit, eta_tol);
 }
-void launch_cg_c(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, double tol, int maxit,
-                 double eta_tol, int* ndone, hipStream_t st) {
-    if (nitems > 0) k_cg_c<<<nitems, kBlock, 0, st>>>(insts, C, mrows, tol, maxit, eta_tol, ndone);
+void launch_cg_c(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, int ninst, hipStream_t st) {
+    if (nitems > 0) k_cg_c<<<nitems, kBlock, 0, st>>>(insts, C, mrows);
+    if (ninst > 0) k_cg_norms<<<ninst, kBlock, 0, st>>>(insts);
 }
-void launch_cg_dir(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, int parity, int* ndone,
+void launch_cg_dir(const InstDev* insts, const WorkItem* ncols, int nitems, int k, int* ndone, hipStream_t st) {
+    if (nitems > 0) k_cg_dir<<<nitems, kBlock, 0, st>>>(insts, ncols, k, ndone);
+}
+void launch_cg_eta_test(const InstDev* insts, const Calls& C, int ninst, int k, int* ndone, hipStream_t st) {
+    if (ninst > 0) k_cg_eta_test<<<ninst, kBlock, 0, st>>>(insts, C, k, ndone);
+}
+void launch_cg_q(const InstDev* insts, const WorkItem* mrows, int nitems, int k, hipStream_t st) {
+    if (nitems > 0) k_cg_q<<<nitems, kBlock, 0, st>>>(insts, mrows, k);
+}
+void launch_cg_upd(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, int k, int* ndone,
                    hipStream_t st) {
-    if (nitems > 0) k_cg_dir<<<nitems, kBlock, 0, st>>>(insts, C, ncols, parity, ndone);
-}
-void launch_cg_q(const InstDev* insts, const WorkItem* mrows, int nitems, int parity, int* ndone, hipStream_t st) {
-    if (nitems > 0) k_cg_q<<<nitems, kBlock, 0, st>>>(insts, mrows, parity, ndone);
-}
-void launch_cg_upd(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, int parity, int* ndone,
-                   hipStream_t st) {
-    if (nitems > 0) k_cg_upd<<<nitems, kBlock, 0, st>>>(insts, C, mrows, parity, ndone);
+    if (nitems > 0) k_cg_upd<<<nitems, kBlock, 0, st>>>(insts, C, mrows, k, ndone);
 }
 void launch_cg_dxrhs(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, hipStream_t st) {
     if (nitems > 0) k_cg_dxrhs<<<nitems, kBlock, 0, st>>>(insts, C, ncols);
 }
 void launch_cg_residual(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nn, const WorkItem* mrows,
-                        int nm, hipStream_t st) {
+                        int nm, int ninst, hipStream_t st) {
     if (nn > 0) k_cg_res_n<<<nn, kBlock, 0, st>>>(insts, C, ncols);
     if (nm > 0) k_cg_res_m<<<nm, kBlock, 0, st>>>(insts, C, mrows);
+    if (ninst > 0) k_cg_eta<<<ninst, kBlock, 0, st>>>(insts);
 }
 
 }  // namespace kkt

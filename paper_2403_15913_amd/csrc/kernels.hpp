@@ -115,18 +115,18 @@ void launch_refine_decide(const InstDev* insts, int ninst, int* ndone, hipStream
 void launch_refine_revert(const InstDev* insts, const Calls& C, const WorkItem* rows, int nitems, hipStream_t st);
 void launch_matvec(const InstDev* insts, const double* x, double* y, const WorkItem* rows, int nitems, hipStream_t st);
 
-// Schur-complement CG (one CgState per instance)
-void launch_cg_fg(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, hipStream_t st);
-void launch_cg_c(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, double tol, int maxit,
-                 double eta_tol, int* ndone, hipStream_t st);
-void launch_cg_dir(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, int parity, int* ndone,
-                   hipStream_t st);
-void launch_cg_q(const InstDev* insts, const WorkItem* mrows, int nitems, int parity, int* ndone, hipStream_t st);
-void launch_cg_upd(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, int parity, int* ndone,
+// Schur-complement CG (one CgState per instance); k is the iteration index
+void launch_cg_fg(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, double tol, int maxit,
+                  double eta_tol, hipStream_t st);
+void launch_cg_c(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, int ninst, hipStream_t st);
+void launch_cg_dir(const InstDev* insts, const WorkItem* ncols, int nitems, int k, int* ndone, hipStream_t st);
+void launch_cg_eta_test(const InstDev* insts, const Calls& C, int ninst, int k, int* ndone, hipStream_t st);
+void launch_cg_q(const InstDev* insts, const WorkItem* mrows, int nitems, int k, hipStream_t st);
+void launch_cg_upd(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, int k, int* ndone,
                    hipStream_t st);
 void launch_cg_dxrhs(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, hipStream_t st);
 // saddle-system residual of (dx, dy) and its normwise backward error (CgState::eta)
 void launch_cg_residual(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nn, const WorkItem* mrows,
-                        int nm, hipStream_t st);
+                        int nm, int ninst, hipStream_t st);
 
 }  // namespace kkt

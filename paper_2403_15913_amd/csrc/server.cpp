@@ -45,6 +45,7 @@ struct SrvRequest {
     size_t bytes = 0;
     const double *w = nullptr, *j = nullptr, *sx = nullptr, *ss = nullptr, *b = nullptr;
     double* x = nullptr;
+    hipEvent_t ready = nullptr;  // recorded on the submitter's stream: the inputs and x are ready after it
     double t_submit = 0, t_start = 0, t_done = 0;
     kkt_status status = KKT_OK;
     kkt_solve_info info{};
@@ -80,6 +81,7 @@ struct kkt_server {
     int64_t next_ticket = 1;
     bool stop = false;
     std::vector<std::unique_ptr<SrvWorker>> workers;
+    std::vector<hipEvent_t> ev_free;  // events for the requests' readiness, reused
     // statistics since the last reset
     std::vector<double> lat, qdel, svc;
     int64_t submitted = 0, completed = 0, rejected = 0, waves = 0, wave_reqs = 0;
@@ -112,7 +114,12 @@ static void run_wave(kkt_server* S, SrvWorker* W, std::vector<SrvRequest*>& wave
             seg(r->ss, E.stage.ss + E.m_ofs[q], Y.m);
             seg(r->b, E.stage.b + E.n_ofs[q], Y.n);
         }
-        hipError_t e = hipMemcpyAsync(W->segs.p, W->hsegs, ns * sizeof(CopySeg), hipMemcpyHostToDevice, W->st);
+        // the gather reads the requests' arrays only after the work their
+        // submitters had queued before submitting
+        hipError_t e = hipSuccess;
+        for (int q = 0; q < nq && e == hipSuccess; q++) e = hipStreamWaitEvent(W->st, wave[q]->ready, 0);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(W->segs.p, W->hsegs, ns * sizeof(CopySeg), hipMemcpyHostToDevice, W->st);
         if (e != hipSuccess) st = hip_fail(e, "segment upload");
         if (st == KKT_OK) {
             launch_copy_segments((const CopySeg*)W->segs.p, ns, W->st);
@@ -156,6 +163,8 @@ static void run_wave(kkt_server* S, SrvWorker* W, std::vector<SrvRequest*>& wave
         else r->status = infos[q].status;
         r->info.status = r->status;
         r->done = true;
+        S->ev_free.push_back(r->ready);  // the worker's stream has passed the wait on it
+        r->ready = nullptr;
         S->lat.push_back(r->t_done - r->t_submit);
         S->qdel.push_back(r->t_start - r->t_submit);
         S->svc.push_back(r->t_done - r->t_start);
@@ -261,16 +270,40 @@ kkt_status kkt_server_register(kkt_server* S, const kkt_symbolic* sym, int32_t* 
 
 kkt_status kkt_server_submit(kkt_server* S, int32_t pattern_id, const double* w_vals, const double* j_vals,
                              const double* sigma_x, const double* sigma_s, const double* b, double* x,
-                             int64_t* ticket) {
+                             void* stream, int64_t* ticket) {
     if (!S || !ticket) return fail(KKT_ERR_INVALID_ARG, "NULL argument");
     std::unique_ptr<SrvRequest> r(new (std::nothrow) SrvRequest);
     if (!r) return fail(KKT_ERR_OOM, "host allocation");
+    hipEvent_t ev = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (!S->ev_free.empty()) {
+            ev = S->ev_free.back();
+            S->ev_free.pop_back();
+        }
+    }
+    hipError_t e = ev ? hipSuccess : hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        if (ev) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->ev_free.push_back(ev);
+        }
+        return hip_fail(e, "request event");
+    }
+    r->ready = ev;
     std::lock_guard<std::mutex> lk(S->mu);
-    if (pattern_id < 0 || pattern_id >= (int)S->psym.size()) return fail(KKT_ERR_INVALID_ARG, "unknown pattern id");
+    auto give_back = [&] { S->ev_free.push_back(ev); };
+    if (pattern_id < 0 || pattern_id >= (int)S->psym.size()) {
+        give_back();
+        return fail(KKT_ERR_INVALID_ARG, "unknown pattern id");
+    }
     const Symbolic& Y = *S->psym[pattern_id];
     if ((Y.nnz_w > 0 && !w_vals) || (Y.nnz_j > 0 && !j_vals) || (Y.n > 0 && (!sigma_x || !b || !x)) ||
-        (Y.m > 0 && !sigma_s))
+        (Y.m > 0 && !sigma_s)) {
+        give_back();
         return fail(KKT_ERR_INVALID_ARG, "NULL request array");
+    }
     r->ticket = S->next_ticket++;
     r->pat = pattern_id;
     r->sym = &Y;
@@ -349,6 +382,9 @@ void kkt_server_destroy(kkt_server* S) {
     S->cv_work.notify_all();
     for (auto& W : S->workers)
         if (W->th.joinable()) W->th.join();
+    for (hipEvent_t ev : S->ev_free) (void)hipEventDestroy(ev);
+    for (auto& kv : S->reqs)
+        if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
     delete S;
 }
 

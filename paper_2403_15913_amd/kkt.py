@@ -123,7 +123,7 @@ SIGNATURES = {
     "kkt_server_opts_default": (None, [P]),
     "kkt_server_create": (I32, [P, P]),
     "kkt_server_register": (I32, [P, P, P]),
-    "kkt_server_submit": (I32, [P, I32, P, P, P, P, P, P, P]),
+    "kkt_server_submit": (I32, [P, I32, P, P, P, P, P, P, P, P]),
     "kkt_server_wait": (I32, [P, I64, P, P]),
     "kkt_server_get_stats": (I32, [P, P]),
     "kkt_server_reset_stats": (I32, [P]),
@@ -526,10 +526,12 @@ class Server:
         self.keep.append(sym)
         return pid.value
 
-    def submit(self, pid, w_vals, j_vals, sigma_x, sigma_s, b, x) -> int:
+    def submit(self, pid, w_vals, j_vals, sigma_x, sigma_s, b, x, stream=None) -> int:
+        """Queues a request ordered after the work already enqueued on `stream` (default: torch's
+        current stream), so inputs and x written there just before are seen complete."""
         t = C.c_int64()
         _err(lib().kkt_server_submit(self.h, int(pid), _dptr(w_vals), _dptr(j_vals), _dptr(sigma_x),
-                                     _dptr(sigma_s), _dptr(b), _dptr(x), C.byref(t)))
+                                     _dptr(sigma_s), _dptr(b), _dptr(x), _stream(stream), C.byref(t)))
         return t.value
 
     def wait(self, ticket):
