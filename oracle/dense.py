@@ -92,6 +92,48 @@ def recover_slack_steps(pat, vals, dx, r2, r4):
     return ds, dz
 
 
+def lifted_augmented_regularized(pat, vals, delta: float) -> np.ndarray:
+    """The augmented system of eq. (kkt:augmented) (no equality rows) with the
+    primal regularisation delta added to the Hessian block only, the form whose
+    condensation is the condensed matrix K = W + delta_x I + H^T D_s H as the
+    paper writes it after eq. (kkt:condensed)."""
+    A = lifted_augmented(pat, vals)
+    A[:pat.n, :pat.n] += delta * np.eye(pat.n)
+    return A
+
+
+# Inertia correction: the regularisation (delta_x) is raised until the
+# augmented system has the inertia of eq. (inertia), (n + m, 0, m) with no
+# equality rows. The paper fixes no update rule; this is the rule of the
+# filter line-search interior-point method (Waechter & Biegler 2006, its
+# inertia-correction algorithm): try delta = 0; on failure start from
+# delta_first (no earlier success) or from max(delta_min, kappa_minus *
+# delta_last); multiply by kappa_plus_first (no earlier success) or
+# kappa_plus until the inertia is right or delta exceeds delta_max.
+INERTIA_DEFAULTS = dict(delta_first=1e-4, delta_min=1e-20, delta_max=1e40, kappa_minus=1.0 / 3.0,
+                        kappa_plus=8.0, kappa_plus_first=100.0)
+
+
+def augmented_inertia_ok(pat, vals, delta: float) -> bool:
+    """Inertia of the regularised augmented system by Bunch-Kaufman equals (n + m, 0, m)."""
+    return bunch_kaufman(lifted_augmented_regularized(pat, vals, delta)).inertia() == (pat.n + pat.m, 0, pat.m)
+
+
+def inertia_correction(pat, vals, delta_last: float = 0.0, **opts):
+    """Returns (delta, trials, delta_last_after); delta is None when delta_max is exceeded."""
+    o = dict(INERTIA_DEFAULTS, **opts)
+    trials = [0.0]
+    if augmented_inertia_ok(pat, vals, 0.0):
+        return 0.0, trials, delta_last
+    delta = o["delta_first"] if delta_last == 0.0 else max(o["delta_min"], o["kappa_minus"] * delta_last)
+    while delta <= o["delta_max"]:
+        trials.append(delta)
+        if augmented_inertia_ok(pat, vals, delta):
+            return delta, trials, delta
+        delta *= o["kappa_plus_first"] if delta_last == 0.0 else o["kappa_plus"]
+    return None, trials, delta_last
+
+
 def hykkt_saddle(pat, vals, gamma: float = 0.0) -> np.ndarray:
     """[[K0 + gamma J^T J, J^T], [J, 0]] with K0 = W + Sigma_x (eq. (hykkt); gamma=0 is eq. (kkt:condensed))."""
     K0 = w_full(pat, vals).toarray() + np.diag(vals.sigma_x)

@@ -508,3 +508,42 @@ def test_hykkt_wide_sigma_small_system(oracle_lib):
     assert info["status"] == "ok" and info["iters"] <= D.cg_iteration_bound(e.max() / e.min(), 1e-10)
     assert D.hykkt_backward_errors(pat, v, dx, dy, v.f, v.g)["eta"] <= 1e-10
     assert D.forward_error(dx, dxb) <= 1e-7 and D.forward_error(dy, dyb) <= 1e-7
+
+
+def test_inertia_correction_rule():
+    """The oracle's inertia correction (delta raised until the regularised
+    augmented system has the inertia of eq. (inertia)) against the spectrum of
+    the condensed matrix: by Haynsworth's formula (stated after eq.
+    (kkt:condensed)) the augmented inertia is right exactly when K + delta I
+    is positive definite, so the accepted delta is the first trial with
+    lambda_min(K + delta I) > 0 and every earlier trial has lambda_min <= 0.
+    The trials follow the update rule: delta_first, then factors of
+    kappa_plus_first; with an earlier success, kappa_minus * delta_last, then
+    factors of kappa_plus."""
+    pat = kktgen.nmpc_pattern(10, 4, 1)
+    v = kktgen.nmpc_values(pat, kktgen.rng_for(95, 0, 0), 1e-2, 1e2)
+    K = D.condensed(pat, v, v.sigma_s).toarray()
+    assert D.inertia_correction(pat, v) == (0.0, [0.0], 0.0)   # already positive definite
+    s = pat.meta["stage"]
+    v.sigma_x[3 * s:4 * s] -= 30.0 + np.linalg.eigvalsh(K).max()
+    K = D.condensed(pat, v, v.sigma_s).toarray()
+    lmin = np.linalg.eigvalsh(K).min()
+    assert lmin < -30.0
+    delta, trials, last = D.inertia_correction(pat, v)
+    assert trials[:2] == [0.0, 1e-4] and len(trials) >= 5   # lambda_min < -30 needs delta > 30
+    for a, b in zip(trials[1:], trials[2:]):
+        assert b == pytest.approx(100.0 * a, rel=1e-15)
+    assert delta == trials[-1] == last
+    assert np.linalg.eigvalsh(K + delta * np.eye(pat.n)).min() > 0
+    for t in trials[:-1]:
+        assert np.linalg.eigvalsh(K + t * np.eye(pat.n)).min() <= 0
+    # an earlier success: start from kappa_minus * delta_last, grow by kappa_plus
+    delta2, trials2, last2 = D.inertia_correction(pat, v, delta_last=delta)
+    assert trials2[1] == pytest.approx(delta / 3.0, rel=1e-15)
+    for a, b in zip(trials2[1:], trials2[2:]):
+        assert b == pytest.approx(8.0 * a, rel=1e-15)
+    assert np.linalg.eigvalsh(K + delta2 * np.eye(pat.n)).min() > 0
+    for t in trials2[:-1]:
+        assert np.linalg.eigvalsh(K + t * np.eye(pat.n)).min() <= 0
+    # beyond delta_max: no delta
+    assert D.inertia_correction(pat, v, delta_max=1.0)[0] is None
