@@ -130,6 +130,29 @@ typedef struct kkt_cg_info {
     int32_t eta_stop;      /* 1: stopped by the eta bound (eta_tol), 0: by tol, maxit or a breakdown */
 } kkt_cg_info;
 
+typedef struct kkt_inertia_opts {
+    double delta_first;      /* first trial delta when none succeeded before (default 1e-4) */
+    double delta_min;        /* smallest starting delta after a success (default 1e-20) */
+    double delta_max;        /* give up above this delta (default 1e40) */
+    double kappa_minus;      /* after a success the next call starts at kappa_minus * delta_last (default 1/3) */
+    double kappa_plus;       /* growth factor after a failed trial (default 8) */
+    double kappa_plus_first; /* growth factor while no delta has succeeded yet (default 100) */
+} kkt_inertia_opts;
+
+typedef struct kkt_inertia_info {
+    int32_t status;          /* KKT_OK, KKT_ERR_NOT_SPD (delta_max exceeded), KKT_ERR_NONFINITE */
+    int32_t trials;          /* factorizations run (the first with delta = 0) */
+    double delta;            /* the accepted delta (0 when K was definite as given) */
+} kkt_inertia_info;
+
+typedef struct kkt_aug_info {
+    int32_t status;          /* KKT_OK or KKT_ERR_NOT_CONVERGED (omega > tol at exit) */
+    int32_t iters;           /* corrections on the full system */
+    double eta;              /* normwise backward error on the augmented system */
+    double omega;            /* componentwise backward error on the augmented system */
+    int32_t inner_iters;     /* refinement corrections of the first condensed solve */
+} kkt_aug_info;
+
 typedef struct kkt_factor_info {
     int32_t status;        /* KKT_OK, KKT_ERR_NOT_SPD, KKT_ERR_NONFINITE */
     int32_t bad_col;       /* original index of the first failing pivot in elimination order, else -1 */
@@ -200,6 +223,32 @@ void kkt_factor_destroy(kkt_factor* f);
 kkt_status kkt_refactor(kkt_factor* f, const double* w_vals, const double* j_vals,
                         const double* sigma_x, const double* sigma_s, double gamma, void* stream);
 
+/* Fills *o with the inertia-correction defaults. */
+void kkt_inertia_opts_default(kkt_inertia_opts* o);
+
+/*
+ * Refactorisation with inertia correction (section "Augmented KKT system":
+ * when the inertia of the augmented system differs from eq. (inertia), the
+ * solver adds a primal regularisation delta_x; section "Solution 1:
+ * Lifted-KKT": delta_x is raised until the condensed matrix is positive
+ * definite). By Haynsworth's formula (after eq. (kkt:condensed)) the inertia
+ * condition holds exactly when K = W + Sx + delta I + J^T d J is positive
+ * definite, i.e. when the Cholesky factorization succeeds, so each trial is a
+ * refactorisation with the same analysis: delta = 0 first; on NOT_SPD
+ * delta_first (no earlier success on this factor) or max(delta_min,
+ * kappa_minus * delta_last); then delta grows by kappa_plus_first (no earlier
+ * success) or kappa_plus until the factorization succeeds or delta exceeds
+ * delta_max (the update rule of the filter line-search interior-point method
+ * the paper builds on; the paper itself fixes none). The factor remembers the
+ * last accepted delta. Arguments as kkt_refactor; o may be NULL (defaults),
+ * info may be NULL. Synchronises after every trial. Returns KKT_OK with K + delta I
+ * factored, KKT_ERR_NOT_SPD when delta_max is exceeded, or another failure
+ * (NONFINITE stops the trials at once).
+ */
+kkt_status kkt_refactor_inertia(kkt_factor* f, const double* w_vals, const double* j_vals, const double* sigma_x,
+                                const double* sigma_s, double gamma, const kkt_inertia_opts* o,
+                                kkt_inertia_info* info, void* stream);
+
 /*
  * Waits for the stream work of the factor and reports the latched status:
  * KKT_OK, KKT_ERR_NOT_SPD (info->bad_col = original index of the first
@@ -260,6 +309,27 @@ void kkt_cg_opts_default(kkt_cg_opts* o);
  */
 kkt_status kkt_cg_schur(kkt_factor* f, const double* fv, const double* g, const kkt_cg_opts* opts,
                         double* dx, double* dy, kkt_cg_info* info, void* stream);
+
+/*
+ * The augmented system of eq. (kkt:augmented) for Lifted-KKT (every
+ * constraint an inequality: H = J, D_s = Sigma_s, no equality rows), with the
+ * factor's primal regularisation (Sigma_x + delta I on the Hessian block):
+ *   [[W + Sx + delta I, 0, J^T], [0, Sigma_s, I], [J, I, 0]] [dx; ds; dz] = -[r1; r2; r4].
+ * Condensation (eq. (kkt:condensed)): K dx = -(r1 + J^T (Sigma_s r4 - r2)),
+ * solved with refinement as kkt_solve does; the slack and multiplier steps
+ * are recovered as ds = -r4 - J dx and dz = -r2 - Sigma_s ds (stated after
+ * eq. (kkt:condensed)). Then Richardson refinement on the full system
+ * (section "Hybrid linear solver"): residual e of the augmented system,
+ * correction by the same condensation with the factor, stop when its
+ * componentwise backward error omega <= ro->tol, after ro->max_iter
+ * corrections, or when omega fails to halve (the better of the last two
+ * iterates is kept). r1 (n), r2 (m), r4 (m), dx (n), ds (m), dz (m) are device
+ * arrays; ro may be NULL (defaults), info may be NULL. Needs a Lifted-KKT
+ * factor (STATE otherwise). Synchronises once per round.
+ */
+kkt_status kkt_solve_augmented(kkt_factor* f, const double* r1, const double* r2, const double* r4, double* dx,
+                               double* ds, double* dz, const kkt_refine_opts* ro, kkt_aug_info* info,
+                               void* stream);
 
 /*
  * For callers that cannot allocate device memory (code under HIP graph

@@ -243,8 +243,9 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         ko[q + 1] = ko[q] + S.nnzk;
         co[q + 1] = co[q] + S.sp_ptr[S.n];
         po[q + 1] = po[q] + 5 * (int64_t)((S.n + kBlock - 1) / kBlock) * kResidualSplit;
-        // CG reduction slots: 4 per 256-row block of n, 4 then 2 per block of m
-        ro[q + 1] = ro[q] + 4 * (int64_t)((S.n + kBlock - 1) / kBlock) + 6 * (int64_t)((S.m + kBlock - 1) / kBlock) + 4;
+        // reduction slots of the CG and the augmented solve: up to 8 per
+        // 256-row block of n and of m
+        ro[q + 1] = ro[q] + 8 * (int64_t)((S.n + kBlock - 1) / kBlock + (S.m + kBlock - 1) / kBlock) + 4;
         for (int k = 0; k < S.ns; k++) {
             lds_factor = std::max(lds_factor, (size_t)factor_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]));
             lds_solve = std::max(lds_solve, (size_t)solve_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]));
@@ -280,8 +281,15 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     qvec = cv.take<double>(M);
     red = cv.take<double>(ro[ninst]);
     jcopy = cv.take<double>(j_ofs[ninst]);
-    jtv = hykkt_storage ? cv.take<double>(j_ofs[ninst]) : nullptr;
-    k0csr = hykkt_storage ? cv.take<double>(co[ninst]) : nullptr;
+    jtv = single_storage ? cv.take<double>(j_ofs[ninst]) : nullptr;
+    k0csr = single_storage ? cv.take<double>(co[ninst]) : nullptr;
+    jraw = single_storage ? cv.take<double>(j_ofs[ninst]) : nullptr;
+    ssv = single_storage ? cv.take<double>(M) : nullptr;
+    aug_b = single_storage ? cv.take<double>(N) : nullptr;
+    aug_t = single_storage ? cv.take<double>(N) : nullptr;
+    aug_e = single_storage ? cv.take<double>(N + 2 * M) : nullptr;
+    aug_prev = single_storage ? cv.take<double>(N + 2 * M) : nullptr;
+    aug = single_storage ? cv.take<AugState>(ninst) : nullptr;
     status = cv.take<int>(2 * (size_t)ninst);
     ndone = cv.take<int>(4);
     rs = cv.take<RefineState>(ninst);
@@ -341,6 +349,14 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         I.qvec = qvec + m_ofs[q];
         I.jtv = jtv ? jtv + j_ofs[q] : nullptr;
         I.k0csr = k0csr ? k0csr + co[q] : nullptr;
+        I.jraw = jraw ? jraw + j_ofs[q] : nullptr;
+        I.ssv = ssv ? ssv + m_ofs[q] : nullptr;
+        // the augmented solve is offered for single factors (one instance)
+        I.aug_b = aug_b;
+        I.aug_t = aug_t;
+        I.aug_e = aug_e;
+        I.aug_prev = aug_prev;
+        I.aug = aug ? aug + q : nullptr;
         I.red = red + ro[q];
         I.status = status + 2 * q;
         I.rs = rs + q;
@@ -584,6 +600,8 @@ kkt_status Engine::refactor(const Calls& C, hipStream_t st) {
         }
     }
     if (mode == 2) TL(KKT_PHASE_ASSEMBLE, launch_jcopy(di(), C, jitems, n_jitems, st));
+    if (mode == 1 && single_storage)
+        TL(KKT_PHASE_ASSEMBLE, launch_keep_lifted(di(), C, jitems, n_jitems, mitems, n_mitems, st));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "refactor launch");
     factored = true;
@@ -882,6 +900,57 @@ kkt_status Engine::cg_schur(const Calls& C, double tol, int maxit, double eta_to
     return KKT_OK;
 }
 
+// Augmented system (Lifted-KKT): condensed solve with refinement, recovery of
+// ds and dz, then refinement on the full system with the host reading each
+// stop decision.
+kkt_status Engine::solve_augmented(const AugCall& A, int maxit, double tol, kkt_aug_info* info, hipStream_t st) {
+    last_stream = st;
+    const int ni = 10;  // refinement of the first condensed solve: kkt_solve's defaults
+    const double itol = 1e-14;
+    TL(KKT_PHASE_RESIDUAL, launch_aug_rhs(di(), A, nitems, n_nitems, 0, st));
+    Calls C;
+    std::memset(&C, 0, sizeof(C));
+    C.b = aug_b;
+    C.x = A.dx;
+    kkt_solve_info inner{};
+    kkt_status ks = solve(C, ni, itol, &inner, st);
+    if (ks != KKT_OK && ks != KKT_ERR_NOT_CONVERGED) return ks;
+    TL(KKT_PHASE_RESIDUAL, launch_aug_recover(di(), A, nitems, n_nitems, mitems, n_mitems, 0, st));
+    TL(KKT_PHASE_CONTROL, launch_aug_reset(di(), ninst, tol, maxit, st));
+    Calls Ct;
+    std::memset(&Ct, 0, sizeof(Ct));
+    Ct.b = aug_b;
+    Ct.x = aug_t;
+    AugState S{};
+    hipError_t e = hipSuccess;
+    for (int round = 0; round <= maxit + 1; round++) {
+        TL(KKT_PHASE_RESIDUAL, launch_aug_check(di(), A, nitems, n_nitems, mitems, n_mitems, ninst, st));
+        if ((e = hipMemcpyAsync(hpin, aug, sizeof(AugState), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess)
+            return hip_fail(e, "augmented refinement control");
+        std::memcpy(&S, hpin, sizeof(S));
+        if (S.done) break;
+        // correction: condensed right-hand side of e, one solve with the
+        // factor, recovery of the slack and multiplier parts, update
+        TL(KKT_PHASE_RESIDUAL, launch_aug_rhs(di(), A, nitems, n_nitems, 1, st));
+        solve_start(Ct, 0, 0.0, st);
+        TL(KKT_PHASE_RESIDUAL, launch_aug_recover(di(), A, nitems, n_nitems, mitems, n_mitems, 1, st));
+    }
+    TL(KKT_PHASE_PERMUTE, launch_aug_revert(di(), A, nitems, n_nitems, mitems, n_mitems, st));
+    if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(e, "augmented solve");
+    const bool rev = S.revert != 0;
+    const double om = rev ? S.omega_prev : S.omega;
+    if (info) {
+        info->iters = rev ? S.it - 1 : S.it;
+        info->eta = rev ? S.eta_prev : S.eta;
+        info->omega = om;
+        info->inner_iters = inner.iters;
+        info->status = om <= tol ? KKT_OK : KKT_ERR_NOT_CONVERGED;
+    }
+    return om <= tol ? KKT_OK : fail(KKT_ERR_NOT_CONVERGED, "augmented refinement stopped above tol");
+}
+
 }  // namespace kkt
 
 // ===========================================================================
@@ -999,7 +1068,7 @@ kkt_status kkt_factor_create(const kkt_symbolic* sym, kkt_factor** out) {
     kkt_factor* f = new (std::nothrow) kkt_factor;
     if (!f) return fail(KKT_ERR_OOM, "host allocation");
     f->sym = sym;
-    f->eng.hykkt_storage = true;
+    f->eng.single_storage = true;
     kkt_status st = f->eng.init_owned({&sym->S});
     if (st != KKT_OK) {
         delete f;
@@ -1031,6 +1100,85 @@ kkt_status kkt_refactor(kkt_factor* f, const double* w_vals, const double* j_val
     std::memset(&C, 0, sizeof(C));
     C.w = w_vals; C.jv = j_vals; C.sx = sigma_x; C.ss = gamma == 0.0 ? sigma_s : nullptr; C.gamma = gamma;
     return f->eng.refactor(C, (hipStream_t)stream);
+}
+
+void kkt_inertia_opts_default(kkt_inertia_opts* o) {
+    if (!o) return;
+    o->delta_first = 1e-4;
+    o->delta_min = 1e-20;
+    o->delta_max = 1e40;
+    o->kappa_minus = 1.0 / 3.0;
+    o->kappa_plus = 8.0;
+    o->kappa_plus_first = 100.0;
+}
+
+kkt_status kkt_refactor_inertia(kkt_factor* f, const double* w_vals, const double* j_vals, const double* sigma_x,
+                                const double* sigma_s, double gamma, const kkt_inertia_opts* opts,
+                                kkt_inertia_info* info, void* stream) {
+    if (!f) return fail(KKT_ERR_INVALID_ARG, "NULL factor");
+    kkt_status st = check_values(f->eng, w_vals, j_vals, sigma_x, sigma_s, gamma);
+    if (st) return st;
+    kkt_inertia_opts o;
+    kkt_inertia_opts_default(&o);
+    if (opts) o = *opts;
+    if (!(o.delta_first > 0.0) || !(o.delta_min >= 0.0) || !(o.delta_max >= o.delta_first) ||
+        !(o.kappa_minus > 0.0) || !(o.kappa_plus > 1.0) || !(o.kappa_plus_first > 1.0))
+        return fail(KKT_ERR_INVALID_ARG, "bad inertia-correction options");
+    Engine& E = f->eng;
+    Calls C;
+    std::memset(&C, 0, sizeof(C));
+    C.w = w_vals; C.jv = j_vals; C.sx = sigma_x; C.ss = gamma == 0.0 ? sigma_s : nullptr; C.gamma = gamma;
+    const hipStream_t s = (hipStream_t)stream;
+    int trials = 0;
+    auto attempt = [&](double delta, int* code) -> kkt_status {
+        C.delta = delta;
+        kkt_status r = E.refactor(C, s);
+        if (r != KKT_OK) return r;
+        trials++;
+        int bad = -1;
+        r = E.read_status(code, &bad);
+        return (r == KKT_ERR_DEVICE || r == KKT_ERR_OOM) ? r : KKT_OK;
+    };
+    int code = 0;
+    double delta = 0.0;
+    if ((st = attempt(0.0, &code)) != KKT_OK) return st;
+    if (code == KKT_ERR_NOT_SPD) {
+        const bool first = E.delta_last == 0.0;
+        delta = first ? o.delta_first : std::max(o.delta_min, o.kappa_minus * E.delta_last);
+        for (;;) {
+            if ((st = attempt(delta, &code)) != KKT_OK) return st;
+            if (code != KKT_ERR_NOT_SPD) break;
+            delta *= first ? o.kappa_plus_first : o.kappa_plus;
+            if (delta > o.delta_max) break;
+        }
+        if (code == KKT_OK) E.delta_last = delta;
+    }
+    if (info) {
+        info->status = code;
+        info->trials = trials;
+        info->delta = code == KKT_OK ? delta : -1.0;
+    }
+    if (code != KKT_OK)
+        return fail(code, code == KKT_ERR_NOT_SPD ? "no delta up to delta_max makes K positive definite"
+                                                  : "factor status " + std::string(kkt_status_string(code)));
+    return KKT_OK;
+}
+
+kkt_status kkt_solve_augmented(kkt_factor* f, const double* r1, const double* r2, const double* r4, double* dx,
+                               double* ds, double* dz, const kkt_refine_opts* ro, kkt_aug_info* info,
+                               void* stream) {
+    if (!f) return fail(KKT_ERR_INVALID_ARG, "NULL factor");
+    const Symbolic& S = f->sym->S;
+    if ((S.n > 0 && (!r1 || !dx)) || (S.m > 0 && (!r2 || !r4 || !ds || !dz)))
+        return fail(KKT_ERR_INVALID_ARG, "NULL vector");
+    if (!f->eng.factored || f->eng.mode != 1) return fail(KKT_ERR_STATE, "the augmented solve needs a Lifted-KKT factor");
+    const int maxit = ro ? ro->max_iter : 10;
+    const double tol = ro ? ro->tol : 1e-14;
+    if (maxit < 0 || !(tol >= 0.0)) return fail(KKT_ERR_INVALID_ARG, "bad refinement options");
+    kkt_status fst = f->eng.read_status(nullptr, nullptr);
+    if (fst != KKT_OK) return fail(fst, "factor failed; solve refused");
+    AugCall A{r1, r2, r4, dx, ds, dz};
+    return f->eng.solve_augmented(A, maxit, tol, info, (hipStream_t)stream);
 }
 
 kkt_status kkt_status_sync(kkt_factor* f, kkt_factor_info* info) {

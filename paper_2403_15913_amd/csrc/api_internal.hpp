@@ -75,7 +75,9 @@ struct Engine {
     // views into the arena
     double *L = nullptr, *U = nullptr, *V = nullptr, *kval = nullptr, *kcsr = nullptr, *rpart = nullptr, *dinv = nullptr, *y = nullptr, *r = nullptr,
            *xprev = nullptr, *fg = nullptr, *cvec = nullptr, *rvec = nullptr, *pvec = nullptr,
-           *pvec2 = nullptr, *qvec = nullptr, *red = nullptr, *jcopy = nullptr, *jtv = nullptr, *k0csr = nullptr;
+           *pvec2 = nullptr, *qvec = nullptr, *red = nullptr, *jcopy = nullptr, *jtv = nullptr, *k0csr = nullptr,
+           *jraw = nullptr, *ssv = nullptr, *aug_b = nullptr, *aug_t = nullptr, *aug_e = nullptr, *aug_prev = nullptr;
+    AugState* aug = nullptr;
     int *status = nullptr, *ndone = nullptr;
     RefineState* rs = nullptr;
     CgState* cg = nullptr;
@@ -89,7 +91,9 @@ struct Engine {
     std::vector<int> lvl_maxu;                      // widest update part of each level
     bool split_update = true;                       // level schedule: update matrices in their own launch
     bool queue_sched = false;                       // dependency-driven launches (else one launch per level)
-    bool hykkt_storage = false;                     // single factors: K0 and J by columns, for the HyKKT CG
+    bool single_storage = false;                    // single factors: K0, J and Sigma_s kept for the HyKKT CG
+                                                    // and the augmented-system solve
+    double delta_last = 0.0;                        // inertia correction: last delta that made K definite
     // captured refactor + solve (batched form)
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -149,6 +153,9 @@ struct Engine {
     // asynchronous solve: the first solve and max_iter refinement rounds,
     // every kernel gated by the instance's stop flag, no read-back
     void solve_rounds(const Calls& C, int maxit, hipStream_t st);
+    // augmented system (Lifted-KKT): condensed solve, slack and multiplier
+    // recovery, refinement on the full system
+    kkt_status solve_augmented(const AugCall& A, int maxit, double tol, kkt_aug_info* info, hipStream_t st);
     // waits for st and returns each instance's latched status and failing column (original index)
     kkt_status read_status(int* st_out, int* bad_out);
     kkt_status parse_status(int derr, const int* hs, int* st_out, int* bad_out);

@@ -78,6 +78,13 @@ struct CgState {
     int eta_stop;            // 1: stopped by the eta bound
 };
 
+// Full-system (augmented) refinement record of one instance: the backward
+// errors of the current and previous iterates and the stop rule's state.
+struct AugState {
+    double eta, eta_prev, omega, omega_prev, tol;
+    int it, maxit, done, revert;
+};
+
 struct InstDev {
     PatDev P;
     // offsets of this instance inside the caller's concatenated arrays
@@ -102,7 +109,14 @@ struct InstDev {
     double* qvec;       // S_gamma p (m)
     double* pvec2;      // CG direction, second buffer (m): iterations alternate
     double* jtv;        // HyKKT: J values by columns in pivot order (jtp_ptr layout)
-    double* k0csr;      // HyKKT: W + Sigma_x in the symmetric row lists (kcsr layout)
+    double* k0csr;      // single factors: W + Sigma_x + delta I in the symmetric row lists (kcsr layout)
+    double* jraw;       // Lifted-KKT, single factors: J values by rows (js holds them scaled)
+    double* ssv;        // Lifted-KKT, single factors: Sigma_s (m)
+    double* aug_b;      // augmented solve: condensed right-hand side (n, original numbering)
+    double* aug_t;      // augmented solve: correction K^{-1} b (n)
+    double* aug_e;      // augmented solve: residual (e1 n, e2 m, e4 m)
+    double* aug_prev;   // augmented solve: previous iterate (dx n, ds m, dz m)
+    AugState* aug;
     double* red;        // per-block partial sums (deterministic reductions)
     int* status;        // [0] latched status, [1] first failing pivot (permuted index)
     RefineState* rs;

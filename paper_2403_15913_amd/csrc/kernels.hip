@@ -84,8 +84,15 @@ __global__ __launch_bounds__(256) void k_assemble(const InstDev* __restrict__ in
     const int wi = I.P.k_w[e];
     if (wi >= 0) v += C.w[I.w_off + wi];
     const int di = I.P.k_diag[e];
-    if (di >= 0) v += C.sx[I.n_off + di];
+    if (di >= 0) v += C.sx[I.n_off + di] + C.delta;
     const double* __restrict__ jv = C.jv + I.j_off;
+    // single factors keep W + Sigma_x + delta I, for the saddle-system and
+    // augmented-system residuals
+    if (I.k0csr) {
+        const int c0 = I.P.k_csr[2 * e], c1 = I.P.k_csr[2 * e + 1];
+        I.k0csr[c0] = v;
+        if (c1 >= 0) I.k0csr[c1] = v;
+    }
     if (C.ss) {
         // js[a] = J_a * Sigma_s[row of a] (k_jscale), so each product is
         // (J_a Sigma_s) J_b with two gathers
@@ -111,13 +118,6 @@ __global__ __launch_bounds__(256) void k_assemble(const InstDev* __restrict__ in
                 if (p + q < p1) v += x[q] * y[q];
         }
     } else {
-        // K_gamma: W + Sigma_x is also kept (single factors), for the
-        // saddle-system residual
-        if (I.k0csr) {
-            const int c0 = I.P.k_csr[2 * e], c1 = I.P.k_csr[2 * e + 1];
-            I.k0csr[c0] = v;
-            if (c1 >= 0) I.k0csr[c1] = v;
-        }
         double acc = 0.0;
         for (int64_t p = p0; p < p1; p++) acc += jv[I.P.pair_a[p]] * jv[I.P.pair_b[p]];
         v += C.gamma * acc;
@@ -176,9 +176,9 @@ __global__ __launch_bounds__(256) void k_assemble_heavy(const InstDev* __restric
     const int wi = I.P.k_w[e];
     if (wi >= 0) v += C.w[I.w_off + wi];
     const int di = I.P.k_diag[e];
-    if (di >= 0) v += C.sx[I.n_off + di];
+    if (di >= 0) v += C.sx[I.n_off + di] + C.delta;
     const int c0 = I.P.k_csr[2 * e], c1 = I.P.k_csr[2 * e + 1];
-    if (!C.ss && I.k0csr) {
+    if (I.k0csr) {
         I.k0csr[c0] = v;
         if (c1 >= 0) I.k0csr[c1] = v;
     }
@@ -197,6 +197,24 @@ __global__ __launch_bounds__(256) void k_jscale(const InstDev* __restrict__ inst
     const int p = it.id + threadIdx.x;
     if (p >= I.P.j_ptr[I.P.m]) return;
     I.js[p] = C.jv[I.j_off + p] * C.ss[I.m_off + I.P.jrow[p]];
+}
+
+// Lifted-KKT, single factors: J's values by rows (jraw) and by columns in
+// pivot order (jtv) over the entry blocks of J, or Sigma_s (rows = 1) over the
+// row blocks, kept for the augmented-system solve
+__global__ __launch_bounds__(256) void k_keep_lifted(const InstDev* __restrict__ insts, Calls C,
+                                                     const WorkItem* __restrict__ items, int rows) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    const int p = it.id + threadIdx.x;
+    if (rows) {
+        if (p < I.P.m) I.ssv[p] = C.ss[I.m_off + p];
+        return;
+    }
+    if (p >= I.P.j_ptr[I.P.m]) return;
+    const double* __restrict__ jv = C.jv + I.j_off;
+    I.jraw[p] = jv[p];
+    I.jtv[p] = jv[I.P.jtp_e[p]];
 }
 
 // K_gamma: the factor keeps J's values, by rows (js) and by columns in pivot
@@ -2162,6 +2180,242 @@ __global__ __launch_bounds__(256) void k_cg_norms(const InstDev* __restrict__ in
 }
 
 // ---------------------------------------------------------------------------
+// Augmented system of eq. (kkt:augmented) with no equality rows (the Lifted-KKT
+// form, H = J, D_s = Sigma_s), regularised on the Hessian block as the
+// condensed matrix K = W + Sigma_x + delta I + J^T Sigma_s J is:
+//   [[K0, 0, J^T], [0, Sigma_s, I], [J, I, 0]] [dx; ds; dz] = -[r1; r2; r4],
+// K0 = W + Sigma_x + delta I. Condensation (eq. (kkt:condensed)) gives
+// K dx = -(r1 + J^T (Sigma_s r4 - r2)), and the slack and multiplier steps
+// follow as ds = -r4 - J dx, dz = -r2 - Sigma_s ds. The refinement on the
+// full system (section "Hybrid linear solver") takes the residual e of the
+// augmented system and solves for the correction the same way.
+// Slots: N-region 8 per block (k_aug_res_n), M-region 8 per block after it.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int aug_mslot0(const InstDev& I) { return 8 * cg_nb(I.P.n); }
+
+// b_j = p1_j - sum_q J_qj (p2_q - Sigma_s,q p4_q) with p = -r (mode 0) or
+// p = e (mode 1); pivot-ordered threads, b in original numbering
+__global__ __launch_bounds__(256) void k_aug_rhs(const InstDev* __restrict__ insts, AugCall A,
+                                                 const WorkItem* __restrict__ items, int mode) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    if (mode == 1 && I.aug->done) return;  // uniform per block
+    const int k = it.id + threadIdx.x;
+    if (k >= I.P.n) return;
+    const int n = I.P.n, m = I.P.m;
+    const int j = I.P.perm[k];
+    const double* __restrict__ p2 = mode ? I.aug_e + n : A.r2;
+    const double* __restrict__ p4 = mode ? I.aug_e + n + m : A.r4;
+    const double sgn = mode ? 1.0 : -1.0;
+    double s = 0.0;
+    for (int q = I.P.jtp_ptr[k]; q < I.P.jtp_ptr[k + 1]; q++) {
+        const int row = I.P.jtp_row[q];
+        s += I.jtv[q] * (sgn * p2[row] - I.ssv[row] * (sgn * p4[row]));
+    }
+    const double p1 = mode ? I.aug_e[j] : -A.r1[j];
+    I.aug_b[j] = p1 - s;
+}
+
+// mode 0: ds = p4 - J dx, dz = p2 - Sigma_s ds with p = -r.
+// mode 1: t = K^{-1} b is in aug_t; the iterate moves to aug_prev and
+// dx += t, ds += e4 - J t, dz += e2 - Sigma_s (e4 - J t).
+__global__ __launch_bounds__(256) void k_aug_recover_m(const InstDev* __restrict__ insts, AugCall A,
+                                                       const WorkItem* __restrict__ items, int mode) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    if (mode == 1 && I.aug->done) return;
+    const int i = it.id + threadIdx.x;
+    if (i >= I.P.m) return;
+    const int n = I.P.n, m = I.P.m;
+    const double* __restrict__ v = mode ? I.aug_t : A.dx;
+    double s = 0.0;
+    for (int p = I.P.j_ptr[i]; p < I.P.j_ptr[i + 1]; p++) s += I.jraw[p] * v[I.P.j_col[p]];
+    const double p2 = mode ? I.aug_e[n + i] : -A.r2[i];
+    const double p4 = mode ? I.aug_e[n + m + i] : -A.r4[i];
+    const double ds = p4 - s;
+    const double dz = p2 - I.ssv[i] * ds;
+    if (mode == 0) {
+        A.ds[i] = ds;
+        A.dz[i] = dz;
+    } else {
+        const double so = A.ds[i], zo = A.dz[i];
+        I.aug_prev[n + i] = so;
+        I.aug_prev[n + m + i] = zo;
+        A.ds[i] = so + ds;
+        A.dz[i] = zo + dz;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_aug_update_x(const InstDev* __restrict__ insts, AugCall A,
+                                                      const WorkItem* __restrict__ items) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    if (I.aug->done) return;
+    const int j = it.id + threadIdx.x;
+    if (j >= I.P.n) return;
+    const double xo = A.dx[j];
+    I.aug_prev[j] = xo;
+    A.dx[j] = xo + I.aug_t[j];
+}
+
+__global__ void k_aug_reset(const InstDev* __restrict__ insts, int ninst, double tol, int maxit) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= ninst) return;
+    AugState* S = insts[q].aug;
+    S->eta = S->eta_prev = S->omega = S->omega_prev = INFINITY;
+    S->tol = tol;
+    S->maxit = maxit;
+    S->it = 0;
+    S->done = 0;
+    S->revert = 0;
+}
+
+// ratio for the componentwise backward error (0/0 taken as 0)
+__device__ __forceinline__ double aug_ratio(double r, double den) {
+    return den > 0.0 ? r / den : (r > 0.0 ? INFINITY : 0.0);
+}
+
+// primal rows: e1 = -r1 - K0 dx - J^T dz, with |K0||dx| + |J|^T|dz| + |r1|,
+// the row sums of |A| and the maxima of |dx| and |r1|
+__global__ __launch_bounds__(256) void k_aug_res_n(const InstDev* __restrict__ insts, AugCall A,
+                                                   const WorkItem* __restrict__ items) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    if (I.aug->done) return;
+    const int j = it.id + threadIdx.x;
+    double ea = 0.0, om = 0.0, ar = 0.0, xa = 0.0, ba = 0.0;
+    if (j < I.P.n) {
+        double s = 0.0, den = 0.0, rs = 0.0;
+        for (int64_t p = I.P.sp_ptr[j]; p < I.P.sp_ptr[j + 1]; p++) {
+            const double a = I.k0csr[p], t = a * A.dx[I.P.sp_col[p]];
+            s += t;
+            den += fabs(t);
+            rs += fabs(a);
+        }
+        for (int q = I.P.jt_ptr[j]; q < I.P.jt_ptr[j + 1]; q++) {
+            const double a = I.jraw[I.P.jt_e[q]], t = a * A.dz[I.P.jt_row[q]];
+            s += t;
+            den += fabs(t);
+            rs += fabs(a);
+        }
+        const double p1 = -A.r1[j];
+        const double e1 = p1 - s;
+        I.aug_e[j] = e1;
+        ea = fabs(e1);
+        om = aug_ratio(ea, den + fabs(p1));
+        ar = rs;
+        xa = fabs(A.dx[j]);
+        ba = fabs(p1);
+    }
+    ea = block_max(ea);
+    om = block_max(om);
+    ar = block_max(ar);
+    xa = block_max(xa);
+    ba = block_max(ba);
+    if (threadIdx.x == 0) {
+        double* sl = I.red + 8 * (it.id >> 8);
+        sl[0] = ea;
+        sl[1] = om;
+        sl[2] = ar;
+        sl[3] = xa;
+        sl[4] = ba;
+    }
+}
+
+// slack rows e2 = -r2 - Sigma_s ds - dz and constraint rows e4 = -r4 - J dx - ds
+__global__ __launch_bounds__(256) void k_aug_res_m(const InstDev* __restrict__ insts, AugCall A,
+                                                   const WorkItem* __restrict__ items) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    if (I.aug->done) return;
+    const int i = it.id + threadIdx.x;
+    const int n = I.P.n, m = I.P.m;
+    double ea = 0.0, om = 0.0, ar = 0.0, xa = 0.0, ba = 0.0;
+    if (i < m) {
+        const double sg = I.ssv[i], ds = A.ds[i], dz = A.dz[i];
+        const double p2 = -A.r2[i], p4 = -A.r4[i];
+        const double t2 = sg * ds;
+        const double e2 = p2 - t2 - dz;
+        double s = 0.0, den4 = 0.0, rs4 = 0.0;
+        for (int p = I.P.j_ptr[i]; p < I.P.j_ptr[i + 1]; p++) {
+            const double a = I.jraw[p], t = a * A.dx[I.P.j_col[p]];
+            s += t;
+            den4 += fabs(t);
+            rs4 += fabs(a);
+        }
+        const double e4 = p4 - s - ds;
+        I.aug_e[n + i] = e2;
+        I.aug_e[n + m + i] = e4;
+        ea = fmax(fabs(e2), fabs(e4));
+        om = fmax(aug_ratio(fabs(e2), fabs(t2) + fabs(dz) + fabs(p2)),
+                  aug_ratio(fabs(e4), den4 + fabs(ds) + fabs(p4)));
+        ar = fmax(sg + 1.0, rs4 + 1.0);
+        xa = fmax(fabs(ds), fabs(dz));
+        ba = fmax(fabs(p2), fabs(p4));
+    }
+    ea = block_max(ea);
+    om = block_max(om);
+    ar = block_max(ar);
+    xa = block_max(xa);
+    ba = block_max(ba);
+    if (threadIdx.x == 0) {
+        double* sl = I.red + aug_mslot0(I) + 8 * (it.id >> 8);
+        sl[0] = ea;
+        sl[1] = om;
+        sl[2] = ar;
+        sl[3] = xa;
+        sl[4] = ba;
+    }
+}
+
+// one workgroup per instance: eta and omega of the augmented system, and the
+// stop rule of the refinement (omega <= tol, maxit corrections, or omega not
+// halving; the previous iterate wins if omega grew)
+__global__ __launch_bounds__(256) void k_aug_decide(const InstDev* __restrict__ insts) {
+    const InstDev& I = insts[blockIdx.x];
+    AugState* S = I.aug;
+    if (S->done) return;
+    const int nbn = cg_nb(I.P.n), nbm = cg_nb(I.P.m);
+    const double* Nr = I.red;
+    const double* Mr = I.red + aug_mslot0(I);
+    double v[5];
+    for (int k = 0; k < 5; k++) v[k] = fmax(slots_max(Nr, nbn, 8, k), slots_max(Mr, nbm, 8, k));
+    if (threadIdx.x != 0) return;
+    const double den = v[2] * v[3] + v[4];
+    S->eta_prev = S->eta;
+    S->omega_prev = S->omega;
+    S->eta = den > 0.0 ? v[0] / den : (v[0] > 0.0 ? INFINITY : 0.0);
+    S->omega = v[1];
+    bool stop = S->omega <= S->tol || S->it >= S->maxit;
+    if (S->it > 0 && S->omega > 0.5 * S->omega_prev) {
+        stop = true;
+        if (S->omega > S->omega_prev) S->revert = 1;
+    }
+    if (stop) S->done = 1;
+    else S->it += 1;
+}
+
+__global__ __launch_bounds__(256) void k_aug_revert_n(const InstDev* __restrict__ insts, AugCall A,
+                                                      const WorkItem* __restrict__ items) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    if (!I.aug->revert) return;
+    const int j = it.id + threadIdx.x;
+    if (j < I.P.n) A.dx[j] = I.aug_prev[j];
+}
+
+__global__ __launch_bounds__(256) void k_aug_revert_m(const InstDev* __restrict__ insts, AugCall A,
+                                                      const WorkItem* __restrict__ items) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    if (!I.aug->revert) return;
+    const int i = it.id + threadIdx.x;
+    if (i >= I.P.m) return;
+    A.ds[i] = I.aug_prev[I.P.n + i];
+    A.dz[i] = I.aug_prev[I.P.n + I.P.m + i];
+}
+
+// ---------------------------------------------------------------------------
 // workspace redirection (allocation-free solve): copies of a factor's instance
 // descriptor and front descriptors whose per-solve vectors point into a
 // caller-provided workspace
@@ -2208,6 +2462,29 @@ hipError_t set_kernel_attributes() {
 
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+void launch_aug_rhs(const InstDev* insts, const AugCall& A, const WorkItem* ncols, int nitems, int mode,
+                    hipStream_t st) {
+    if (nitems > 0) k_aug_rhs<<<nitems, kBlock, 0, st>>>(insts, A, ncols, mode);
+}
+void launch_aug_recover(const InstDev* insts, const AugCall& A, const WorkItem* ncols, int nn, const WorkItem* mrows,
+                        int nm, int mode, hipStream_t st) {
+    if (mode == 1 && nn > 0) k_aug_update_x<<<nn, kBlock, 0, st>>>(insts, A, ncols);
+    if (nm > 0) k_aug_recover_m<<<nm, kBlock, 0, st>>>(insts, A, mrows, mode);
+}
+void launch_aug_reset(const InstDev* insts, int ninst, double tol, int maxit, hipStream_t st) {
+    if (ninst > 0) k_aug_reset<<<blocks_for(ninst, 64), 64, 0, st>>>(insts, ninst, tol, maxit);
+}
+void launch_aug_check(const InstDev* insts, const AugCall& A, const WorkItem* ncols, int nn, const WorkItem* mrows,
+                      int nm, int ninst, hipStream_t st) {
+    if (nn > 0) k_aug_res_n<<<nn, kBlock, 0, st>>>(insts, A, ncols);
+    if (nm > 0) k_aug_res_m<<<nm, kBlock, 0, st>>>(insts, A, mrows);
+    if (ninst > 0) k_aug_decide<<<ninst, kBlock, 0, st>>>(insts);
+}
+void launch_aug_revert(const InstDev* insts, const AugCall& A, const WorkItem* ncols, int nn, const WorkItem* mrows,
+                       int nm, hipStream_t st) {
+    if (nn > 0) k_aug_revert_n<<<nn, kBlock, 0, st>>>(insts, A, ncols);
+    if (nm > 0) k_aug_revert_m<<<nm, kBlock, 0, st>>>(insts, A, mrows);
+}
 void launch_ws_redirect(const InstDev* src_inst, const FrontDesc* src_fd, int nf, const SolveWs& w, hipStream_t st) {
     k_ws_redirect<<<blocks_for(nf > 0 ? nf : 1, 256), 256, 0, st>>>(src_inst, src_fd, nf, w);
 }
@@ -2222,6 +2499,11 @@ void launch_status_init(int* status, int ninst, hipStream_t st) {
 }
 void launch_jscale(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st) {
     if (nitems > 0) k_jscale<<<nitems, kBlock, 0, st>>>(insts, C, items);
+}
+void launch_keep_lifted(const InstDev* insts, const Calls& C, const WorkItem* jentries, int nj, const WorkItem* mrows,
+                        int nm, hipStream_t st) {
+    if (nj > 0) k_keep_lifted<<<nj, kBlock, 0, st>>>(insts, C, jentries, 0);
+    if (nm > 0) k_keep_lifted<<<nm, kBlock, 0, st>>>(insts, C, mrows, 1);
 }
 void launch_jcopy(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st) {
     if (nitems > 0) k_jcopy<<<nitems, kBlock, 0, st>>>(insts, C, items);

@@ -15,6 +15,7 @@ struct Calls {
     const double* sx;
     const double* ss;   // NULL -> K_gamma with row weight gamma
     double gamma;
+    double delta;       // primal regularisation added to the diagonal of K (inertia correction)
     const double* b;    // Lifted-KKT solve
     double* x;
     const double* f;    // HyKKT solve
@@ -84,6 +85,10 @@ void launch_copy_segments(const CopySeg* segs, int nseg, hipStream_t st);
 void launch_fill_i32(int* p, int v, int64_t n, hipStream_t st);
 void launch_status_init(int* status, int ninst, hipStream_t st);
 void launch_jscale(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st);
+// Lifted-KKT, single factors: J's values by rows and by columns in pivot
+// order and Sigma_s, kept for the augmented-system solve
+void launch_keep_lifted(const InstDev* insts, const Calls& C, const WorkItem* jentries, int nj, const WorkItem* mrows,
+                        int nm, hipStream_t st);
 // K_gamma: J's values by rows and by columns in pivot order, kept for the CG
 void launch_jcopy(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st);
 void launch_assemble(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st);
@@ -128,5 +133,31 @@ void launch_cg_dxrhs(const InstDev* insts, const Calls& C, const WorkItem* ncols
 // saddle-system residual of (dx, dy) and its normwise backward error (CgState::eta)
 void launch_cg_residual(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nn, const WorkItem* mrows,
                         int nm, int ninst, hipStream_t st);
+
+// Augmented system of eq. (kkt:augmented) without equality rows (see the
+// kernels): the caller's right-hand sides r1, r2, r4 and unknowns dx, ds, dz
+struct AugCall {
+    const double* r1;   // n
+    const double* r2;   // m
+    const double* r4;   // m
+    double* dx;         // n
+    double* ds;         // m
+    double* dz;         // m
+};
+// mode 0: b = -(r1 + J^T (Sigma_s r4 - r2)); mode 1: the same with -r = e,
+// the current residual (correction right-hand side)
+void launch_aug_rhs(const InstDev* insts, const AugCall& A, const WorkItem* ncols, int nitems, int mode,
+                    hipStream_t st);
+// mode 0: ds = -r4 - J dx, dz = -r2 - Sigma_s ds; mode 1: the correction from
+// t = K^{-1} b (in aug_t): the previous iterate is kept, then dx += t,
+// ds += e4 - J t, dz += e2 - Sigma_s (e4 - J t)
+void launch_aug_recover(const InstDev* insts, const AugCall& A, const WorkItem* ncols, int nn, const WorkItem* mrows,
+                        int nm, int mode, hipStream_t st);
+void launch_aug_reset(const InstDev* insts, int ninst, double tol, int maxit, hipStream_t st);
+// residual of the augmented system, its backward errors and the stop rule
+void launch_aug_check(const InstDev* insts, const AugCall& A, const WorkItem* ncols, int nn, const WorkItem* mrows,
+                      int nm, int ninst, hipStream_t st);
+void launch_aug_revert(const InstDev* insts, const AugCall& A, const WorkItem* ncols, int nn, const WorkItem* mrows,
+                       int nm, hipStream_t st);
 
 }  // namespace kkt

@@ -71,6 +71,26 @@ class CgInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class InertiaOpts(C.Structure):
+    _fields_ = [("delta_first", C.c_double), ("delta_min", C.c_double), ("delta_max", C.c_double),
+                ("kappa_minus", C.c_double), ("kappa_plus", C.c_double), ("kappa_plus_first", C.c_double)]
+
+
+class InertiaInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("trials", C.c_int32), ("delta", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class AugInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("eta", C.c_double), ("omega", C.c_double),
+                ("inner_iters", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class FactorInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("bad_col", C.c_int32)]
 
@@ -101,6 +121,9 @@ SIGNATURES = {
     "kkt_factor_destroy": (None, [P]),
     "kkt_refactor": (I32, [P, P, P, P, P, D, P]),
     "kkt_status_sync": (I32, [P, P]),
+    "kkt_inertia_opts_default": (None, [P]),
+    "kkt_refactor_inertia": (I32, [P, P, P, P, P, D, P, P, P]),
+    "kkt_solve_augmented": (I32, [P, P, P, P, P, P, P, P, P, P]),
     "kkt_solve": (I32, [P, P, P, P, P, P]),
     "kkt_solve_noalloc": (I32, [P, P, P, P, P, P]),
     "kkt_cg_opts_default": (None, [P]),
@@ -240,6 +263,32 @@ def kkt_refactor(h, w_vals, j_vals, sigma_x, sigma_s=None, gamma: float = 0.0, s
                             _stream(stream)))
 
 
+def kkt_inertia_opts_default() -> InertiaOpts:
+    o = InertiaOpts()
+    lib().kkt_inertia_opts_default(C.byref(o))
+    return o
+
+
+def kkt_refactor_inertia(h, w_vals, j_vals, sigma_x, sigma_s=None, gamma: float = 0.0, opts: InertiaOpts | None = None,
+                         stream=None) -> dict:
+    ii = InertiaInfo()
+    st = lib().kkt_refactor_inertia(h, _dptr(w_vals), _dptr(j_vals), _dptr(sigma_x), _dptr(sigma_s), float(gamma),
+                                    C.byref(opts) if opts is not None else None, C.byref(ii), _stream(stream))
+    if st not in (KKT_OK, 4):
+        _err(st)
+    return ii.as_dict()
+
+
+def kkt_solve_augmented(h, r1, r2, r4, dx, ds, dz, max_iter: int = 10, tol: float = 1e-14, stream=None) -> dict:
+    ro = RefineOpts(max_iter, tol)
+    ai = AugInfo()
+    st = lib().kkt_solve_augmented(h, _dptr(r1), _dptr(r2), _dptr(r4), _dptr(dx), _dptr(ds), _dptr(dz),
+                                   C.byref(ro), C.byref(ai), _stream(stream))
+    if st not in (KKT_OK, 6):
+        _err(st)
+    return ai.as_dict()
+
+
 def kkt_status_sync(h):
     fi = FactorInfo()
     st = lib().kkt_status_sync(h, C.byref(fi))
@@ -347,6 +396,12 @@ class Factor:
 
     def refactor(self, w_vals, j_vals, sigma_x, sigma_s=None, gamma=0.0, stream=None):
         kkt_refactor(self.h, w_vals, j_vals, sigma_x, sigma_s, gamma, stream)
+
+    def refactor_inertia(self, w_vals, j_vals, sigma_x, sigma_s=None, gamma=0.0, opts=None, stream=None):
+        return kkt_refactor_inertia(self.h, w_vals, j_vals, sigma_x, sigma_s, gamma, opts, stream)
+
+    def solve_augmented(self, r1, r2, r4, dx, ds, dz, max_iter=10, tol=1e-14, stream=None):
+        return kkt_solve_augmented(self.h, r1, r2, r4, dx, ds, dz, max_iter, tol, stream)
 
     def status(self):
         return kkt_status_sync(self.h)
