@@ -141,6 +141,39 @@ def hykkt_saddle(pat, vals, gamma: float = 0.0) -> np.ndarray:
     return np.block([[K0 + gamma * (J.T @ J), J.T], [J, np.zeros((pat.m, pat.m))]])
 
 
+def split_rows(pat, vals, eq_rows):
+    """(G, H, D_s): the equality rows of J (in the order given), the remaining
+    (inequality) rows in ascending order, and their slack weights."""
+    J = jacobian(pat, vals)
+    eq = np.asarray(eq_rows, dtype=np.int64)
+    mask = np.zeros(pat.m, dtype=bool)
+    mask[eq] = True
+    ineq = np.nonzero(~mask)[0]
+    return J[eq].toarray(), J[ineq].toarray(), vals.sigma_s[ineq], eq, ineq
+
+
+def general_hykkt_saddle(pat, vals, eq_rows, gamma: float = 0.0) -> np.ndarray:
+    """[[K_k + gamma G^T G, G^T], [G, 0]] of eq. (hykkt) with the condensed
+    matrix K_k = W + Sigma_x + H^T D_s H of eq. (kkt:condensed): G the equality
+    rows of J, H the inequality rows with D_s their Sigma_s."""
+    G, H, ds, _, _ = split_rows(pat, vals, eq_rows)
+    Kk = w_full(pat, vals).toarray() + np.diag(vals.sigma_x) + H.T @ (ds[:, None] * H)
+    return np.block([[Kk + gamma * (G.T @ G), G.T], [G, np.zeros((len(G), len(G)))]])
+
+
+def general_augmented(pat, vals, eq_rows) -> np.ndarray:
+    """The augmented system of eq. (kkt:augmented) with equality rows G and
+    inequality rows H: unknowns (d_x, d_s, d_y, d_z)."""
+    G, H, ds, _, _ = split_rows(pat, vals, eq_rows)
+    n, me, mi = pat.n, len(G), len(H)
+    W = w_full(pat, vals).toarray() + np.diag(vals.sigma_x)
+    Z = np.zeros
+    return np.block([[W, Z((n, mi)), G.T, H.T],
+                     [Z((mi, n)), np.diag(ds), Z((mi, me)), np.eye(mi)],
+                     [G, Z((me, mi)), Z((me, me)), Z((me, mi))],
+                     [H, np.eye(mi), Z((mi, me)), Z((mi, mi))]])
+
+
 def hykkt_rhs(pat, vals, f, g, gamma: float) -> np.ndarray:
     """[f + gamma J^T g; g]: the r_gamma shift of eq. (hykkt) in the positive-sign convention."""
     J = jacobian(pat, vals)

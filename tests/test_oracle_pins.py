@@ -547,3 +547,33 @@ def test_inertia_correction_rule():
         assert np.linalg.eigvalsh(K + t * np.eye(pat.n)).min() <= 0
     # beyond delta_max: no delta
     assert D.inertia_correction(pat, v, delta_max=1.0)[0] is None
+
+
+def test_general_hykkt_condensation_and_gamma_independence():
+    """Equality rows G and inequality rows H: the augmented system of eq.
+    (kkt:augmented) with both, condensed as in eq. (kkt:condensed), gives the
+    saddle system [[K_k, G^T], [G, 0]] with K_k = W + Sigma_x + H^T D_s H and
+    right-hand side -[r1 + H^T (D_s r4 - r2); r3]; adding gamma G^T G with the
+    shifted right-hand side (eq. (hykkt), r_gamma) leaves (d_x, d_y) unchanged.
+    Checked with numpy's solver on the explicit matrices; the inertia of the
+    augmented system is (n + m_i, 0, m_i + m_e) (eq. (inertia))."""
+    pat, v = kktgen.workload("small", instance=3)
+    eq = np.arange(0, pat.m, 2)          # every other row an equality
+    G, H, ds, eqi, ineq = D.split_rows(pat, v, eq)
+    n, me, mi = pat.n, len(eqi), len(ineq)
+    rng = kktgen.rng_for(97, 0, 0)
+    r1, r2, r3, r4 = (rng.standard_normal(k) for k in (n, mi, me, mi))
+    A = D.general_augmented(pat, v, eq)
+    z = np.linalg.solve(A, -np.concatenate([r1, r2, r3, r4]))
+    dx, dsv, dy, dz = z[:n], z[n:n + mi], z[n + mi:n + mi + me], z[n + mi + me:]
+    ev = np.linalg.eigvalsh(A)
+    assert ((ev > 0).sum(), (ev == 0).sum(), (ev < 0).sum()) == (n + mi, 0, mi + me)
+    f = -(r1 + H.T @ (ds * r4 - r2))
+    g = -r3
+    for gamma in (0.0, 1e2, 1e4):
+        S = D.general_hykkt_saddle(pat, v, eq, gamma)
+        sol = np.linalg.solve(S, np.concatenate([f + gamma * (G.T @ g), g]))
+        assert D.forward_error(sol[:n], dx) < 1e-9 and D.forward_error(sol[n:], dy) < 1e-9, gamma
+    # slack and multiplier recovery with the inequality rows
+    assert D.forward_error(dsv, -r4 - H @ dx) < 1e-10
+    assert D.forward_error(dz, -r2 - ds * dsv) < 1e-10
