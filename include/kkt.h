@@ -209,6 +209,23 @@ kkt_status kkt_factor_create(const kkt_symbolic* sym, kkt_factor** out);
 void kkt_factor_destroy(kkt_factor* f);
 
 /*
+ * General HyKKT (section "Solution 2: HyKKT" with the condensed matrix of eq.
+ * (kkt:condensed)): marks rows of J as equality constraints G; the other rows
+ * are inequality constraints H with slack weights D_s = sigma_s. With rows set
+ * (count > 0), kkt_refactor takes gamma > 0 AND sigma_s and factors
+ *     K_gamma = W + Sx + H^T D_s H + gamma G^T G
+ * (per-row weight sigma_s on H rows, gamma on G rows), and kkt_cg_schur runs
+ * the Schur-complement CG over the equality rows only: it solves
+ *     [[W + Sx + H^T D_s H, G^T], [G, 0]] [dx; dy] = [fv; g]
+ * where fv is the condensed right-hand side -(r1 + H^T (D_s r4 - r2)) and g
+ * (length m, read on the G rows) is -r3; dy is 0 on the H rows. rows: host
+ * array of `count` distinct row indices; count = 0 returns the factor to the
+ * Lifted-KKT / HyKKT rules. The next refactor applies the setting.
+ * Errors: INVALID_ARG (out of range or repeated rows), OOM, DEVICE.
+ */
+kkt_status kkt_factor_set_equality_rows(kkt_factor* f, const int32_t* rows, int32_t count);
+
+/*
  * Numeric refactorisation with new values (same pattern).
  *   w_vals  (nnz_W)  lower-triangle values of W, CSR entry order
  *   j_vals  (nnz_J)  values of J, CSR entry order
@@ -216,6 +233,8 @@ void kkt_factor_destroy(kkt_factor* f);
  *   gamma == 0, sigma_s (m) slack diagonal -> Lifted-KKT: K = W + Sx + J^T diag(sigma_s) J
  *                           (sigma_s may be NULL only when m == 0)
  *   gamma > 0, sigma_s NULL                -> HyKKT:      K_gamma = W + Sx + gamma J^T J
+ *   equality rows set (kkt_factor_set_equality_rows), gamma > 0, sigma_s (m)
+ *                                          -> general HyKKT: K_gamma = W + Sx + H^T D_s H + gamma G^T G
  * Device pointers; asynchronous on `stream`. A non-positive or non-finite pivot
  * is latched (see kkt_status_sync). Errors returned at once: INVALID_ARG
  * (NULL pointers, negative or non-finite gamma, sigma_s given with gamma > 0), DEVICE.

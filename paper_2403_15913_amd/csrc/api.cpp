@@ -575,7 +575,7 @@ DepLists Engine::deps() const {
 
 kkt_status Engine::refactor(const Calls& C, hipStream_t st) {
     last_stream = st;
-    mode = C.gamma == 0.0 ? 1 : 2;
+    mode = C.eqm ? 3 : (C.gamma == 0.0 ? 1 : 2);
     gamma = C.gamma;
     // per instance: status[0] = 0, status[1] = INT_MAX (first failing pivot)
     TL(KKT_PHASE_CONTROL, launch_status_init(status, ninst, st));
@@ -600,7 +600,7 @@ kkt_status Engine::refactor(const Calls& C, hipStream_t st) {
         }
     }
     if (mode == 2) TL(KKT_PHASE_ASSEMBLE, launch_jcopy(di(), C, jitems, n_jitems, st));
-    if (mode == 1 && single_storage)
+    if (mode != 2 && single_storage)
         TL(KKT_PHASE_ASSEMBLE, launch_keep_lifted(di(), C, jitems, n_jitems, mitems, n_mitems, st));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "refactor launch");
@@ -832,7 +832,7 @@ void Engine::cg_iteration(int k, int maxit, bool eta_test, hipStream_t st) {
     if (k >= maxit) return;
     if (eta_test) TL(KKT_PHASE_CONTROL, launch_cg_eta_test(di(), cg_calls, ninst, k, ndone, st));
     sweeps(st, SKIP_CG);
-    TL(KKT_PHASE_CG, launch_cg_q(di(), mitems, n_mitems, k, st));
+    TL(KKT_PHASE_CG, launch_cg_q(di(), cg_calls, mitems, n_mitems, k, st));
     TL(KKT_PHASE_CG, launch_cg_upd(di(), cg_calls, mitems, n_mitems, k, ndone, st));
 }
 
@@ -1086,9 +1086,25 @@ static kkt_status check_values(const Engine& E, const double* w_vals, const doub
     if ((nw > 0 && !w_vals) || (nj > 0 && !j_vals) || (n > 0 && !sigma_x))
         return fail(KKT_ERR_INVALID_ARG, "NULL value array");
     if (!(gamma >= 0.0) || !std::isfinite(gamma)) return fail(KKT_ERR_INVALID_ARG, "gamma must be finite and >= 0");
+    if (E.n_eq > 0) {
+        if (!(gamma > 0.0) || (m > 0 && !sigma_s))
+            return fail(KKT_ERR_INVALID_ARG, "with equality rows set, refactor needs gamma > 0 and sigma_s");
+        return KKT_OK;
+    }
     if (gamma == 0.0 && m > 0 && !sigma_s) return fail(KKT_ERR_INVALID_ARG, "Lifted-KKT (gamma == 0) needs sigma_s");
     if (gamma > 0.0 && sigma_s) return fail(KKT_ERR_INVALID_ARG, "HyKKT (gamma > 0) takes sigma_s = NULL");
     return KKT_OK;
+}
+
+// values of one refactor call (general HyKKT when equality rows are set)
+static Calls refactor_calls(const Engine& E, const double* w_vals, const double* j_vals, const double* sigma_x,
+                            const double* sigma_s, double gamma) {
+    Calls C;
+    std::memset(&C, 0, sizeof(C));
+    C.w = w_vals; C.jv = j_vals; C.sx = sigma_x; C.gamma = gamma;
+    C.ss = (gamma == 0.0 || E.n_eq > 0) ? sigma_s : nullptr;
+    C.eqm = E.n_eq > 0 ? (const int*)E.eqmask.p : nullptr;
+    return C;
 }
 
 kkt_status kkt_refactor(kkt_factor* f, const double* w_vals, const double* j_vals, const double* sigma_x,
@@ -1096,10 +1112,7 @@ kkt_status kkt_refactor(kkt_factor* f, const double* w_vals, const double* j_val
     if (!f) return fail(KKT_ERR_INVALID_ARG, "NULL factor");
     kkt_status st = check_values(f->eng, w_vals, j_vals, sigma_x, sigma_s, gamma);
     if (st) return st;
-    Calls C;
-    std::memset(&C, 0, sizeof(C));
-    C.w = w_vals; C.jv = j_vals; C.sx = sigma_x; C.ss = gamma == 0.0 ? sigma_s : nullptr; C.gamma = gamma;
-    return f->eng.refactor(C, (hipStream_t)stream);
+    return f->eng.refactor(refactor_calls(f->eng, w_vals, j_vals, sigma_x, sigma_s, gamma), (hipStream_t)stream);
 }
 
 void kkt_inertia_opts_default(kkt_inertia_opts* o) {
@@ -1125,9 +1138,7 @@ kkt_status kkt_refactor_inertia(kkt_factor* f, const double* w_vals, const doubl
         !(o.kappa_minus > 0.0) || !(o.kappa_plus > 1.0) || !(o.kappa_plus_first > 1.0))
         return fail(KKT_ERR_INVALID_ARG, "bad inertia-correction options");
     Engine& E = f->eng;
-    Calls C;
-    std::memset(&C, 0, sizeof(C));
-    C.w = w_vals; C.jv = j_vals; C.sx = sigma_x; C.ss = gamma == 0.0 ? sigma_s : nullptr; C.gamma = gamma;
+    Calls C = refactor_calls(E, w_vals, j_vals, sigma_x, sigma_s, gamma);
     const hipStream_t s = (hipStream_t)stream;
     int trials = 0;
     auto attempt = [&](double delta, int* code) -> kkt_status {
@@ -1228,7 +1239,7 @@ kkt_status kkt_cg_schur(kkt_factor* f, const double* fv, const double* g, const 
     const Symbolic& S = f->sym->S;
     if ((S.n > 0 && (!fv || !dx)) || (S.m > 0 && (!g || !dy))) return fail(KKT_ERR_INVALID_ARG, "NULL vector");
     if (S.m > S.n) return fail(KKT_ERR_INVALID_ARG, "the Schur system needs m <= n (J of full row rank)");
-    if (!f->eng.factored || f->eng.mode != 2) return fail(KKT_ERR_STATE, "cg_schur needs a K_gamma factor");
+    if (!f->eng.factored || f->eng.mode < 2) return fail(KKT_ERR_STATE, "cg_schur needs a K_gamma factor");
     kkt_cg_opts o;
     kkt_cg_opts_default(&o);
     if (opts) o = *opts;
@@ -1236,8 +1247,30 @@ kkt_status kkt_cg_schur(kkt_factor* f, const double* fv, const double* g, const 
     Calls C;
     std::memset(&C, 0, sizeof(C));
     C.gamma = f->eng.gamma;
+    C.eqm = f->eng.mode == 3 ? (const int*)f->eng.eqmask.p : nullptr;
     C.f = fv; C.g = g; C.dx = dx; C.dy = dy;
     return f->eng.cg_schur(C, o.tol, o.maxit, o.eta_tol, info, (hipStream_t)stream);
+}
+
+kkt_status kkt_factor_set_equality_rows(kkt_factor* f, const int32_t* rows, int32_t count) {
+    if (!f) return fail(KKT_ERR_INVALID_ARG, "NULL factor");
+    const int m = f->sym->S.m;
+    if (count < 0 || count > m || (count > 0 && !rows)) return fail(KKT_ERR_INVALID_ARG, "bad equality-row list");
+    std::vector<int> mask(std::max(m, 1), 0);
+    for (int k = 0; k < count; k++) {
+        const int r = rows[k];
+        if (r < 0 || r >= m || mask[r]) return fail(KKT_ERR_INVALID_ARG, "equality row out of range or repeated");
+        mask[r] = 1;
+    }
+    Engine& E = f->eng;
+    hipError_t e = hipSuccess;
+    if (!E.eqmask.p && (e = E.eqmask.alloc(mask.size() * sizeof(int))) != hipSuccess)
+        return hip_fail(e, "equality-row mask");
+    if ((e = hipMemcpy(E.eqmask.p, mask.data(), mask.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "equality-row mask upload");
+    E.n_eq = count;
+    E.factored = false;  // the next refactor defines the mode
+    return KKT_OK;
 }
 
 kkt_status kkt_matvec(kkt_factor* f, const double* x, double* y, void* stream) {

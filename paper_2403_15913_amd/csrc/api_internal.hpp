@@ -94,6 +94,8 @@ struct Engine {
     bool single_storage = false;                    // single factors: K0, J and Sigma_s kept for the HyKKT CG
                                                     // and the augmented-system solve
     double delta_last = 0.0;                        // inertia correction: last delta that made K definite
+    DevBuf eqmask;                                  // general HyKKT: 1 on the equality rows of J (m ints)
+    int n_eq = 0;                                   // equality rows set (0: none)
     // captured refactor + solve (batched form)
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -117,7 +119,8 @@ struct Engine {
     size_t hpin_bytes = 0;
     LaunchTimer timer;
     hipStream_t last_stream = nullptr;
-    int mode = 0;                                      // 0 none, 1 Lifted-KKT, 2 HyKKT (K_gamma)
+    int mode = 0;                                      // 0 none, 1 Lifted-KKT, 2 HyKKT (K_gamma),
+                                                       // 3 general HyKKT (equality and inequality rows)
     double gamma = 0.0;
     bool factored = false;
 

@@ -86,12 +86,23 @@ __global__ __launch_bounds__(256) void k_assemble(const InstDev* __restrict__ in
     const int di = I.P.k_diag[e];
     if (di >= 0) v += C.sx[I.n_off + di] + C.delta;
     const double* __restrict__ jv = C.jv + I.j_off;
-    // single factors keep W + Sigma_x + delta I, for the saddle-system and
-    // augmented-system residuals
+    // single factors keep W + Sigma_x + delta I (general HyKKT: plus the
+    // inequality rows' J^T Sigma_s J, the condensed matrix K_k), for the
+    // saddle-system and augmented-system residuals
     if (I.k0csr) {
+        double v0 = v;
+        if (C.eqm) {
+            // (J_a w) J_b with w = Sigma_s on inequality rows, 0 on equality rows
+            const double* __restrict__ ss = C.ss + I.m_off;
+            for (int64_t p = p0; p < p1; p++) {
+                const int a = I.P.pair_a[p], r = I.P.jrow[a];
+                const double w = C.eqm[r] ? 0.0 : ss[r];
+                v0 += (jv[a] * w) * jv[I.P.pair_b[p]];
+            }
+        }
         const int c0 = I.P.k_csr[2 * e], c1 = I.P.k_csr[2 * e + 1];
-        I.k0csr[c0] = v;
-        if (c1 >= 0) I.k0csr[c1] = v;
+        I.k0csr[c0] = v0;
+        if (c1 >= 0) I.k0csr[c1] = v0;
     }
     if (C.ss) {
         // js[a] = J_a * Sigma_s[row of a] (k_jscale), so each product is
@@ -169,8 +180,21 @@ __global__ __launch_bounds__(256) void k_assemble_heavy(const InstDev* __restric
         for (int q = 0; q < HU; q++)
             if (p + 16 * q < p1) acc += x[q] * y[q];
     }
+    // general HyKKT, single factors: the inequality rows' part alone, for K_k
+    double accH = 0.0;
+    if (C.eqm && I.k0csr) {
+        const double* __restrict__ ss = C.ss + I.m_off;
+        for (int64_t p = p0 + l; p < p1; p += 16) {
+            const int a = I.P.pair_a[p], r = I.P.jrow[a];
+            const double w = C.eqm[r] ? 0.0 : ss[r];
+            accH += (jv[a] * w) * jv[I.P.pair_b[p]];
+        }
+    }
 #pragma unroll
-    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+    for (int o = 8; o > 0; o >>= 1) {
+        acc += __shfl_xor(acc, o, 16);
+        accH += __shfl_xor(accH, o, 16);
+    }
     if (l != 0) return;
     double v = 0.0;
     const int wi = I.P.k_w[e];
@@ -179,8 +203,8 @@ __global__ __launch_bounds__(256) void k_assemble_heavy(const InstDev* __restric
     if (di >= 0) v += C.sx[I.n_off + di] + C.delta;
     const int c0 = I.P.k_csr[2 * e], c1 = I.P.k_csr[2 * e + 1];
     if (I.k0csr) {
-        I.k0csr[c0] = v;
-        if (c1 >= 0) I.k0csr[c1] = v;
+        I.k0csr[c0] = v + accH;
+        if (c1 >= 0) I.k0csr[c1] = v + accH;
     }
     v += C.ss ? acc : C.gamma * acc;
     I.kval[e] = v;
@@ -189,14 +213,17 @@ __global__ __launch_bounds__(256) void k_assemble_heavy(const InstDev* __restric
     if (!isfinite(v)) atomicMax(&I.status[0], KKT_ST_NONFINITE);
 }
 
-// Lifted-KKT: J values scaled by their row's Sigma_s, one thread per entry
+// Lifted-KKT: J values scaled by their row's Sigma_s (general HyKKT: by gamma
+// on the equality rows), one thread per entry
 __global__ __launch_bounds__(256) void k_jscale(const InstDev* __restrict__ insts, Calls C,
                                                 const WorkItem* __restrict__ items) {
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
     const int p = it.id + threadIdx.x;
     if (p >= I.P.j_ptr[I.P.m]) return;
-    I.js[p] = C.jv[I.j_off + p] * C.ss[I.m_off + I.P.jrow[p]];
+    const int row = I.P.jrow[p];
+    const double d = (C.eqm && C.eqm[row]) ? C.gamma : C.ss[I.m_off + row];
+    I.js[p] = C.jv[I.j_off + p] * d;
 }
 
 // Lifted-KKT, single factors: J's values by rows (jraw) and by columns in
@@ -217,7 +244,7 @@ __global__ __launch_bounds__(256) void k_keep_lifted(const InstDev* __restrict__
     I.jtv[p] = jv[I.P.jtp_e[p]];
 }
 
-// K_gamma: the factor keeps J's values, by rows (js) and by columns in pivot
+// K_gamma: the factor keeps J's values, by rows (jraw) and by columns in pivot
 // order (jtv), for the Schur-complement CG; one thread per entry
 __global__ __launch_bounds__(256) void k_jcopy(const InstDev* __restrict__ insts, Calls C,
                                                const WorkItem* __restrict__ items) {
@@ -226,7 +253,7 @@ __global__ __launch_bounds__(256) void k_jcopy(const InstDev* __restrict__ insts
     const int p = it.id + threadIdx.x;
     if (p >= I.P.j_ptr[I.P.m]) return;
     const double* __restrict__ jv = C.jv + I.j_off;
-    I.js[p] = jv[p];
+    I.jraw[p] = jv[p];
     I.jtv[p] = jv[I.P.jtp_e[p]];
 }
 
@@ -1850,8 +1877,10 @@ __global__ __launch_bounds__(256) void k_cg_fg(const InstDev* __restrict__ insts
         const double* __restrict__ g = C.g + I.m_off;
         double s = 0.0, csum = 0.0;
         for (int q = I.P.jtp_ptr[k]; q < I.P.jtp_ptr[k + 1]; q++) {
+            const int row = I.P.jtp_row[q];
+            if (C.eqm && !C.eqm[row]) continue;  // general HyKKT: equality rows only
             const double a = I.jtv[q];
-            s += a * g[I.P.jtp_row[q]];
+            s += a * g[row];
             csum += fabs(a);
         }
         const double fj = C.f[I.n_off + j];
@@ -1883,10 +1912,14 @@ __global__ __launch_bounds__(256) void k_cg_c(const InstDev* __restrict__ insts,
     if (i < I.P.m) {
         const int p0 = I.P.j_ptr[i], p1 = I.P.j_ptr[i + 1];
         const double* __restrict__ y = I.y;
-        const double s = gather_dot(p0, p1, I.js, I.P.j_colp, [&](int c) { return y[c]; });
-        for (int p = p0; p < p1; p++) jrow += fabs(I.js[p]);
-        const double gi = C.g[I.m_off + i];
-        const double ci = s - gi;
+        // general HyKKT: the inequality rows are not in the Schur system; their
+        // entries of c, r, p and dy stay 0
+        const bool eq = !C.eqm || C.eqm[i];
+        const double s = gather_dot(p0, p1, I.jraw, I.P.j_colp, [&](int c) { return y[c]; });
+        if (eq)
+            for (int p = p0; p < p1; p++) jrow += fabs(I.jraw[p]);
+        const double gi = eq ? C.g[I.m_off + i] : 0.0;
+        const double ci = eq ? s - gi : 0.0;
         I.cvec[i] = ci;
         I.rvec[i] = ci;
         I.pvec2[i] = 0.0;
@@ -2024,7 +2057,7 @@ __global__ __launch_bounds__(256) void k_cg_eta_test(const InstDev* __restrict__
 
 // q = J t with t = K_gamma^{-1} J^T p_k (the sweep output, pivot order) and the
 // partial sums of p_k . q
-__global__ __launch_bounds__(256) void k_cg_q(const InstDev* __restrict__ insts,
+__global__ __launch_bounds__(256) void k_cg_q(const InstDev* __restrict__ insts, Calls C,
                                               const WorkItem* __restrict__ items, int k) {
     const WorkItem it = items[blockIdx.x];
     const InstDev& I = insts[it.inst];
@@ -2034,7 +2067,8 @@ __global__ __launch_bounds__(256) void k_cg_q(const InstDev* __restrict__ insts,
     double v = 0.0;
     if (i < I.P.m) {
         const double* __restrict__ y = I.y;
-        const double s = gather_dot(I.P.j_ptr[i], I.P.j_ptr[i + 1], I.js, I.P.j_colp, [&](int c) { return y[c]; });
+        double s = gather_dot(I.P.j_ptr[i], I.P.j_ptr[i + 1], I.jraw, I.P.j_colp, [&](int c) { return y[c]; });
+        if (C.eqm && !C.eqm[i]) s = 0.0;  // general HyKKT: equality rows only
         I.qvec[i] = s;
         v = pn[i] * s;
     }
@@ -2109,7 +2143,7 @@ __global__ __launch_bounds__(256) void k_cg_res_n(const InstDev* __restrict__ in
         const double* __restrict__ dy = C.dy + I.m_off;
         double s = 0.0;
         for (int64_t p = I.P.sp_ptr[j]; p < I.P.sp_ptr[j + 1]; p++) s += I.k0csr[p] * dx[I.P.sp_col[p]];
-        for (int q = I.P.jt_ptr[j]; q < I.P.jt_ptr[j + 1]; q++) s += I.js[I.P.jt_e[q]] * dy[I.P.jt_row[q]];
+        for (int q = I.P.jt_ptr[j]; q < I.P.jt_ptr[j + 1]; q++) s += I.jraw[I.P.jt_e[q]] * dy[I.P.jt_row[q]];
         ra = fabs(C.f[I.n_off + j] - s);
         xa = fabs(dx[j]);
     }
@@ -2129,10 +2163,10 @@ __global__ __launch_bounds__(256) void k_cg_res_m(const InstDev* __restrict__ in
     const InstDev& I = insts[it.inst];
     const int i = it.id + threadIdx.x;
     double ra = 0.0, ya = 0.0;
-    if (i < I.P.m) {
+    if (i < I.P.m && (!C.eqm || C.eqm[i])) {  // general HyKKT: equality rows only
         const double* __restrict__ dx = C.dx + I.n_off;
         double s = 0.0;
-        for (int p = I.P.j_ptr[i]; p < I.P.j_ptr[i + 1]; p++) s += I.js[p] * dx[I.P.j_col[p]];
+        for (int p = I.P.j_ptr[i]; p < I.P.j_ptr[i + 1]; p++) s += I.jraw[p] * dx[I.P.j_col[p]];
         ra = fabs(C.g[I.m_off + i] - s);
         ya = fabs(C.dy[I.m_off + i]);
     }
@@ -2570,8 +2604,8 @@ void launch_cg_dir(const InstDev* insts, const WorkItem* ncols, int nitems, int 
 void launch_cg_eta_test(const InstDev* insts, const Calls& C, int ninst, int k, int* ndone, hipStream_t st) {
     if (ninst > 0) k_cg_eta_test<<<ninst, kBlock, 0, st>>>(insts, C, k, ndone);
 }
-void launch_cg_q(const InstDev* insts, const WorkItem* mrows, int nitems, int k, hipStream_t st) {
-    if (nitems > 0) k_cg_q<<<nitems, kBlock, 0, st>>>(insts, mrows, k);
+void launch_cg_q(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, int k, hipStream_t st) {
+    if (nitems > 0) k_cg_q<<<nitems, kBlock, 0, st>>>(insts, C, mrows, k);
 }
 void launch_cg_upd(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, int k, int* ndone,
                    hipStream_t st) {

@@ -16,6 +16,8 @@ struct Calls {
     const double* ss;   // NULL -> K_gamma with row weight gamma
     double gamma;
     double delta;       // primal regularisation added to the diagonal of K (inertia correction)
+    const int* eqm;     // general HyKKT: 1 for the equality rows of J (weight gamma), 0 for the
+                        // inequality rows (weight sigma_s); NULL otherwise
     const double* b;    // Lifted-KKT solve
     double* x;
     const double* f;    // HyKKT solve
@@ -126,7 +128,7 @@ void launch_cg_fg(const InstDev* insts, const Calls& C, const WorkItem* ncols, i
 void launch_cg_c(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, int ninst, hipStream_t st);
 void launch_cg_dir(const InstDev* insts, const WorkItem* ncols, int nitems, int k, int* ndone, hipStream_t st);
 void launch_cg_eta_test(const InstDev* insts, const Calls& C, int ninst, int k, int* ndone, hipStream_t st);
-void launch_cg_q(const InstDev* insts, const WorkItem* mrows, int nitems, int k, hipStream_t st);
+void launch_cg_q(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, int k, hipStream_t st);
 void launch_cg_upd(const InstDev* insts, const Calls& C, const WorkItem* mrows, int nitems, int k, int* ndone,
                    hipStream_t st);
 void launch_cg_dxrhs(const InstDev* insts, const Calls& C, const WorkItem* ncols, int nitems, hipStream_t st);
