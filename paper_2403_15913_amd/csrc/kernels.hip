@@ -415,6 +415,8 @@ __device__ inline void tri_tile(int t, int tj0, int nb, int& ti, int& tj) {
 constexpr int kFactorThreads = 512;
 static_assert(kFactorThreads == 512, "the panel schedule assumes eight waves");
 
+// EU: extend-add entries per thread and batch (register budget of the caller)
+template <int EU>
 __device__ __forceinline__ void factor_front(const InstDev& I, const FrontDesc& F, double* __restrict__ P,
                                              double* invd, const bool fused_update, const bool fused_panel) {
     const PatDev& T = I.P;
@@ -444,7 +446,6 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const FrontDesc& 
     // first two children are all issued before the first wait, so their
     // memory round trips overlap; later batches are loaded and added in turn.
     // Loads use clamped indices, nothing is predicated.
-    constexpr int EU = 18;  // extend-add entries per thread and batch
     struct Child {
         const double* Uc;
         const int* rl;
@@ -680,6 +681,7 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const FrontDesc& 
     // diagonal rows and the substitution step of the rows below. Each entry
     // sees the same operations in the same order as a pivot chain followed
     // by a row-by-row triangular solve.
+    double dsave[16];  // wave 0: the last factored diagonal block (see flush_diag)
     auto panel_block = [&](const int kb) {
         const int j0 = kb << 4, w = min(16, c - j0);
         const int i = lane & 15;
@@ -740,12 +742,12 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const FrontDesc& 
             atomicMin(&status[1], col0 + j0 + __builtin_ctz(bad));
             atomicMax(&status[0], KKT_ST_NOT_SPD);
         }
-        if (wave == 0 && lane < 16) {
-            if (live) {
+        // The other panel waves load this diagonal block at their start, in
+        // the same phase: wave 0 keeps the factored block in registers and
+        // writes it back after the phase's barrier (flush_diag).
+        if (wave == 0) {
 #pragma unroll
-                for (int k = 0; k < 16; k++)
-                    if (k < w && k <= i) P[(j0 + k) * ld + j0 + i] = a[k];
-            }
+            for (int k = 0; k < 16; k++) dsave[k] = a[k];
             if (lane < w) dinv[j0 + lane] = myinv;
         }
         if (plive) {
@@ -765,9 +767,23 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const FrontDesc& 
         // panel waves: one per 64 rows below the diagonal block (at least
         // one), the rest take the look-ahead update
         auto npanel = [&](const int kb) { return min(4, max(1, (r - (kb << 4) - 16 + 63) >> 6)); };
+        // wave 0, after the barrier that ends panel_block(kb): the factored
+        // diagonal block kb into the panel. Nothing reads or writes that block
+        // until the panel is copied out (the updates touch the rows below it
+        // and later column blocks).
+        auto flush_diag = [&](const int kb) {
+            const int j0 = kb << 4, w = min(16, c - j0);
+            const int i = lane & 15;
+            if (lane < 16 && j0 + i < r) {
+#pragma unroll
+                for (int k = 0; k < 16; k++)
+                    if (k < w && k <= i) P[(j0 + k) * ld + j0 + i] = dsave[k];
+            }
+        };
         if (wave < npanel(0)) panel_block(0);
         __syncthreads();
         for (int kb = 0; kb + 1 < nbc; kb++) {
+            if (wave == 0) flush_diag(kb);
             update_tiles(kb, kb + 1, kb + 2, wave, nwave);
             __syncthreads();
             const int np = npanel(kb + 1);
@@ -775,6 +791,8 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const FrontDesc& 
             else update_tiles(kb, kb + 2, nbc, wave - np, nwave - np);
             __syncthreads();
         }
+        if (wave == 0) flush_diag(nbc - 1);
+        __syncthreads();
     } else {
         // the wave that shares wave 0's SIMD stays out of the look-ahead
         // update, so the pivot chain has its SIMD to itself
@@ -919,7 +937,7 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __rest
     extern __shared__ __align__(16) double P[];
     __shared__ double invd[16];
     const FrontDesc& F = fds[blockIdx.x];
-    factor_front(insts[F.inst], F, P, invd, fused_update != 0, true);
+    factor_front<18>(insts[F.inst], F, P, invd, fused_update != 0, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -1118,6 +1136,10 @@ __device__ inline int take_ticket(int* ticket, int* slot) {
     return t;
 }
 
+// the persistent loop keeps its scheduling state live across the front, so
+// its extend-add batches are smaller (no register spills)
+constexpr int kQueueExtBatch = 12;
+
 __global__ __launch_bounds__(kFactorThreads) void k_factor_queue(const InstDev* __restrict__ insts,
                                                                 const FrontDesc* __restrict__ fds, DepLists D) {
     extern __shared__ __align__(16) double P[];
@@ -1132,7 +1154,7 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor_queue(const InstDev* 
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const FrontDesc& F = fds[t];
-        factor_front(insts[F.inst], F, P, invd, true, false);
+        factor_front<kQueueExtBatch>(insts[F.inst], F, P, invd, true, true);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
         if (sched_wave() && par >= 0) publish_add(D.cnt + par);
