@@ -51,14 +51,17 @@ def parse():
     ap.add_argument("--batch-nd-leaf", type=int, default=256, help="batch nested-dissection leaf when not autotuned")
     ap.add_argument("--batch-autotune", type=int, default=1, help="pick batch options and schedule by measurement")
     ap.add_argument("--graph-rounds", type=int, default=1, help="refinement rounds recorded in the batch graph")
-    ap.add_argument("--schedule", default="levels", choices=["levels", "queue"], help="plain-solver launch schedule")
+    ap.add_argument("--schedule", dest="schedule_given", default=None, choices=["levels", "queue"],
+                    help="plain-solver launch schedule (default: the autotuner's pick, else levels)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run one plain device copy of this many MiB (HBM counter calibration) and exit")
     ap.add_argument("--serve-requests", type=int, default=10000, help="requests per arrival rate of the served "
                                                                         "workload (0: skip)")
     ap.add_argument("--serve-rho", default="0.5,0.8,1.2", help="arrival rates as fractions of the plain solver's "
                                                                  "capacity (comma-separated)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    args.schedule = args.schedule_given or "levels"
+    return args
 
 
 def bench_batched(args, kkt, kktgen, torch, dev):
@@ -425,7 +428,11 @@ def main():
         from paper_2403_15913_amd import autotune
         t0 = time.perf_counter()
         tried = []
-        opts = autotune.tune_pattern(pat, vals[0], reps=3, table_path=None, log=tried.append)
+        best = autotune.tune_pattern(pat, vals[0], reps=3, table_path=None, log=tried.append,
+                                     schedules=(kkt.SCHEDULE_LEVELS, kkt.SCHEDULE_QUEUE))
+        opts = {k: best[k] for k in ("ordering", "nd_leaf", "max_super")}
+        if args.schedule_given is None:
+            args.schedule = "queue" if best["schedule"] == kkt.SCHEDULE_QUEUE else "levels"
         tuned = dict(seconds=round(time.perf_counter() - t0, 2), tried=tried)
     t0 = time.perf_counter()
     sym = kkt.Symbolic.from_pattern(pat, **opts)
@@ -480,6 +487,8 @@ def main():
     else:
         achieved, peak = wd["work"] / secs / 1e9, PEAK_HBM_GBS
     kernel = PHASE_KERNELS.get(dom, f"k_{dom}")
+    if args.schedule == "queue":
+        kernel = {"factor": "k_factor_queue", "fwd": "k_sweeps_queue"}.get(dom, kernel)
     roofline = dict(bound=wd["bound"], achieved=round(achieved, 4), peak=peak, unit=wd["unit"],
                     frac=round(achieved / peak, 5), traffic=measured_traffic(dom, args, opts), traffic_unit="bytes/launch",
                     kernel=kernel, launches_per_step=tm[dom]["launches"] / args.steps,

@@ -330,6 +330,16 @@ kkt_status kkt_cg_schur(kkt_factor* f, const double* fv, const double* g, const 
                         double* dx, double* dy, kkt_cg_info* info, void* stream);
 
 /*
+ * Lifted-KKT refactorisations of this factor (enable = 1) also keep
+ * W + Sx + delta I, J (by rows and by columns) and Sigma_s on the device, which
+ * kkt_solve_augmented needs for the full system's residual; they cost about
+ * 12 nnz(K) + 16 nnz(J) + 8 m bytes of extra writes per refactor, so they are
+ * off by default. HyKKT factors always keep what their CG needs. Host only;
+ * applies from the next refactor.
+ */
+kkt_status kkt_factor_keep_augmented(kkt_factor* f, int32_t enable);
+
+/*
  * The augmented system of eq. (kkt:augmented) for Lifted-KKT (every
  * constraint an inequality: H = J, D_s = Sigma_s, no equality rows), with the
  * factor's primal regularisation (Sigma_x + delta I on the Hessian block):
@@ -344,7 +354,8 @@ kkt_status kkt_cg_schur(kkt_factor* f, const double* fv, const double* g, const 
  * corrections, or when omega fails to halve (the better of the last two
  * iterates is kept). r1 (n), r2 (m), r4 (m), dx (n), ds (m), dz (m) are device
  * arrays; ro may be NULL (defaults), info may be NULL. Needs a Lifted-KKT
- * factor (STATE otherwise). Synchronises once per round.
+ * factor refactored with kkt_factor_keep_augmented(f, 1) (STATE otherwise).
+ * Synchronises once per round.
  */
 kkt_status kkt_solve_augmented(kkt_factor* f, const double* r1, const double* r2, const double* r4, double* dx,
                                double* ds, double* dz, const kkt_refine_opts* ro, kkt_aug_info* info,

@@ -52,6 +52,10 @@ def candidates(n: int):
     for leaf in sorted({max(64, n // k) for k in (1024, 512, 340, 256, 128)}):
         if leaf < n:
             out.append(dict(ordering=kkt.ORDER_ND, nd_leaf=int(leaf), max_super=96))
+    # narrower supernodes at the middle leaf size: smaller fronts and panels
+    leaf = max(64, n // 340)
+    if leaf < n:
+        out += [dict(ordering=kkt.ORDER_ND, nd_leaf=int(leaf), max_super=ms) for ms in (64, 48)]
     return out
 
 
@@ -74,10 +78,11 @@ def _dev(a):
     return torch.tensor(np.asarray(a), dtype=torch.float64, device="cuda")
 
 
-def _time_plain(pat, vals, opts, reps: int):
+def _time_plain(pat, vals, opts, reps: int, schedule: int = kkt.SCHEDULE_LEVELS):
     import torch
     sym = kkt.Symbolic.from_pattern(pat, **opts)
     f = kkt.Factor(sym)
+    f.set_schedule(schedule)
     d = [_dev(vals.w_vals), _dev(vals.j_vals), _dev(vals.sigma_x), _dev(vals.sigma_s)]
     b = _dev(vals.b)
     x = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
@@ -114,8 +119,12 @@ def _time_batch(B, cat, b, x, reps: int):
 
 
 def tune_pattern(pat, vals, reps: int = 3, table_path: str | None = DEFAULT_TABLE, force: bool = False,
-                 log=None) -> dict:
-    """Best options for one pattern (measured on the GPU, cached by signature)."""
+                 log=None, schedules=(kkt.SCHEDULE_LEVELS,)) -> dict:
+    """Best options for one pattern (measured on the GPU, cached by signature).
+
+    The symbolic candidates are timed under the level schedule; then the best
+    few are timed again under every schedule in `schedules`. The result holds
+    the symbolic options and a "schedule" entry."""
     key = signature(pat)
     table = load_table(table_path) if table_path else {}
     if not force and key in table:
@@ -128,9 +137,20 @@ def tune_pattern(pat, vals, reps: int = 3, table_path: str | None = DEFAULT_TABL
             if log:
                 log(f"{opts}: {e}")
             continue
-        results.append((t, eta, opts, st))
+        results.append((t, eta, dict(opts, schedule=kkt.SCHEDULE_LEVELS), st))
         if log:
             log(f"{opts}: {1e3 * t:.3f} ms, eta {eta:.1e}, levels {st['levels']}, flops {st['flops']:.3g}")
+    # other schedules for the three fastest option sets
+    top = sorted((r for r in results if r[1] <= ETA_GATE), key=lambda r: r[0])[:3]
+    for sched in schedules:
+        if sched == kkt.SCHEDULE_LEVELS:
+            continue
+        for _, _, o, _ in top:
+            opts = {k: o[k] for k in ("ordering", "nd_leaf", "max_super")}
+            t, eta, st = _time_plain(pat, vals, opts, reps, sched)
+            results.append((t, eta, dict(opts, schedule=sched), st))
+            if log:
+                log(f"{opts} schedule {sched}: {1e3 * t:.3f} ms, eta {eta:.1e}")
     ok = [r for r in results if r[1] <= ETA_GATE]
     if not ok:
         raise RuntimeError("no candidate passed the backward-error gate")

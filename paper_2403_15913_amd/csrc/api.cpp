@@ -573,10 +573,15 @@ DepLists Engine::deps() const {
     return D;
 }
 
-kkt_status Engine::refactor(const Calls& C, hipStream_t st) {
+kkt_status Engine::refactor(const Calls& Cin, hipStream_t st) {
     last_stream = st;
-    mode = C.eqm ? 3 : (C.gamma == 0.0 ? 1 : 2);
-    gamma = C.gamma;
+    mode = Cin.eqm ? 3 : (Cin.gamma == 0.0 ? 1 : 2);
+    gamma = Cin.gamma;
+    // K0 (K_k) and the J / Sigma_s copies: always for the CG modes, on request
+    // for Lifted-KKT (the augmented solve)
+    aug_ready = single_storage && (mode != 1 || keep_aug);
+    Calls C = Cin;
+    C.keep_k0 = aug_ready ? 1 : 0;
     // per instance: status[0] = 0, status[1] = INT_MAX (first failing pivot)
     TL(KKT_PHASE_CONTROL, launch_status_init(status, ninst, st));
     if (C.ss) TL(KKT_PHASE_ASSEMBLE, launch_jscale(di(), C, jitems, n_jitems, st));
@@ -600,7 +605,7 @@ kkt_status Engine::refactor(const Calls& C, hipStream_t st) {
         }
     }
     if (mode == 2) TL(KKT_PHASE_ASSEMBLE, launch_jcopy(di(), C, jitems, n_jitems, st));
-    if (mode != 2 && single_storage)
+    if (mode != 2 && aug_ready)
         TL(KKT_PHASE_ASSEMBLE, launch_keep_lifted(di(), C, jitems, n_jitems, mitems, n_mitems, st));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "refactor launch");
@@ -1183,6 +1188,8 @@ kkt_status kkt_solve_augmented(kkt_factor* f, const double* r1, const double* r2
     if ((S.n > 0 && (!r1 || !dx)) || (S.m > 0 && (!r2 || !r4 || !ds || !dz)))
         return fail(KKT_ERR_INVALID_ARG, "NULL vector");
     if (!f->eng.factored || f->eng.mode != 1) return fail(KKT_ERR_STATE, "the augmented solve needs a Lifted-KKT factor");
+    if (!f->eng.aug_ready)
+        return fail(KKT_ERR_STATE, "the factor was refactored without kkt_factor_keep_augmented(f, 1)");
     const int maxit = ro ? ro->max_iter : 10;
     const double tol = ro ? ro->tol : 1e-14;
     if (maxit < 0 || !(tol >= 0.0)) return fail(KKT_ERR_INVALID_ARG, "bad refinement options");
@@ -1250,6 +1257,12 @@ kkt_status kkt_cg_schur(kkt_factor* f, const double* fv, const double* g, const 
     C.eqm = f->eng.mode == 3 ? (const int*)f->eng.eqmask.p : nullptr;
     C.f = fv; C.g = g; C.dx = dx; C.dy = dy;
     return f->eng.cg_schur(C, o.tol, o.maxit, o.eta_tol, info, (hipStream_t)stream);
+}
+
+kkt_status kkt_factor_keep_augmented(kkt_factor* f, int32_t enable) {
+    if (!f) return fail(KKT_ERR_INVALID_ARG, "NULL factor");
+    f->eng.keep_aug = enable != 0;
+    return KKT_OK;
 }
 
 kkt_status kkt_factor_set_equality_rows(kkt_factor* f, const int32_t* rows, int32_t count) {

@@ -94,6 +94,8 @@ struct Engine {
     bool single_storage = false;                    // single factors: K0, J and Sigma_s kept for the HyKKT CG
                                                     // and the augmented-system solve
     double delta_last = 0.0;                        // inertia correction: last delta that made K definite
+    bool keep_aug = false;                          // Lifted-KKT refactors keep K0, J and Sigma_s (augmented solve)
+    bool aug_ready = false;                         // the current factorization kept them
     DevBuf eqmask;                                  // general HyKKT: 1 on the equality rows of J (m ints)
     int n_eq = 0;                                   // equality rows set (0: none)
     // captured refactor + solve (batched form)

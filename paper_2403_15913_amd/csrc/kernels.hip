@@ -86,10 +86,10 @@ __global__ __launch_bounds__(256) void k_assemble(const InstDev* __restrict__ in
     const int di = I.P.k_diag[e];
     if (di >= 0) v += C.sx[I.n_off + di] + C.delta;
     const double* __restrict__ jv = C.jv + I.j_off;
-    // single factors keep W + Sigma_x + delta I (general HyKKT: plus the
-    // inequality rows' J^T Sigma_s J, the condensed matrix K_k), for the
-    // saddle-system and augmented-system residuals
-    if (I.k0csr) {
+    // single factors that need it keep W + Sigma_x + delta I (general HyKKT:
+    // plus the inequality rows' J^T Sigma_s J, the condensed matrix K_k), for
+    // the saddle-system and augmented-system residuals
+    if (C.keep_k0) {
         double v0 = v;
         if (C.eqm) {
             // (J_a w) J_b with w = Sigma_s on inequality rows, 0 on equality rows
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_assemble_heavy(const InstDev* __restric
     }
     // general HyKKT, single factors: the inequality rows' part alone, for K_k
     double accH = 0.0;
-    if (C.eqm && I.k0csr) {
+    if (C.eqm && C.keep_k0) {
         const double* __restrict__ ss = C.ss + I.m_off;
         for (int64_t p = p0 + l; p < p1; p += 16) {
             const int a = I.P.pair_a[p], r = I.P.jrow[a];
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void k_assemble_heavy(const InstDev* __restric
     const int di = I.P.k_diag[e];
     if (di >= 0) v += C.sx[I.n_off + di] + C.delta;
     const int c0 = I.P.k_csr[2 * e], c1 = I.P.k_csr[2 * e + 1];
-    if (I.k0csr) {
+    if (C.keep_k0) {
         I.k0csr[c0] = v + accH;
         if (c1 >= 0) I.k0csr[c1] = v + accH;
     }

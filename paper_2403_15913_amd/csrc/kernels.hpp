@@ -18,6 +18,7 @@ struct Calls {
     double delta;       // primal regularisation added to the diagonal of K (inertia correction)
     const int* eqm;     // general HyKKT: 1 for the equality rows of J (weight gamma), 0 for the
                         // inequality rows (weight sigma_s); NULL otherwise
+    int keep_k0;        // assembly also writes K0 (or K_k) into k0csr (single factors that need it)
     const double* b;    // Lifted-KKT solve
     double* x;
     const double* f;    // HyKKT solve

@@ -130,6 +130,7 @@ SIGNATURES = {
     "kkt_cg_schur": (I32, [P, P, P, P, P, P, P, P]),
     "kkt_matvec": (I32, [P, P, P, P]),
     "kkt_factor_set_equality_rows": (I32, [P, P, I32]),
+    "kkt_factor_keep_augmented": (I32, [P, I32]),
     "kkt_factor_set_timing": (I32, [P, I32]),
     "kkt_factor_read_timing": (I32, [P, P]),
     "kkt_factor_set_schedule": (I32, [P, I32]),
@@ -332,6 +333,10 @@ def kkt_cg_schur(h, f, g, dx, dy, tol: float = 1e-10, maxit: int = 200, eta_tol:
     return ci.as_dict() if info else None
 
 
+def kkt_factor_keep_augmented(h, enable: bool = True):
+    _err(lib().kkt_factor_keep_augmented(h, 1 if enable else 0))
+
+
 def kkt_factor_set_equality_rows(h, rows):
     r = _i32(rows if rows is not None else [])
     _err(lib().kkt_factor_set_equality_rows(h, _ptr_np(r) if len(r) else None, int(len(r))))
@@ -420,6 +425,9 @@ class Factor:
 
     def cg_schur(self, f, g, dx, dy, tol=1e-10, maxit=200, eta_tol=0.0, info=True, stream=None):
         return kkt_cg_schur(self.h, f, g, dx, dy, tol, maxit, eta_tol, info, stream)
+
+    def keep_augmented(self, enable=True):
+        kkt_factor_keep_augmented(self.h, enable)
 
     def set_equality_rows(self, rows):
         kkt_factor_set_equality_rows(self.h, rows)

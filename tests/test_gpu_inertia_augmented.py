@@ -46,6 +46,7 @@ def host(t):
 
 def augmented_run(kkt, pat, v, r1, r2, r4, **kw):
     f = kkt.Factor(kkt.Symbolic.from_pattern(pat, **kw))
+    f.keep_augmented(True)
     f.refactor(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), dev(v.sigma_s))
     assert f.status()[0] == 0
     dx = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
@@ -150,6 +151,7 @@ def test_inertia_correction_then_augmented(kkt):
     pat, v = indefinite_case()
     print("inertia correction + augmented", flush=True)
     f = kkt.Factor(kkt.Symbolic.from_pattern(pat, ordering=2, nd_leaf=16))
+    f.keep_augmented(True)
     info = f.refactor_inertia(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), dev(v.sigma_s))
     assert info["status"] == 0 and info["delta"] > 0
     r1, r2, r4 = rhs(pat, 3)
@@ -169,6 +171,19 @@ def test_augmented_refused_on_hykkt_factor(kkt):
     pat, v = kktgen.workload("hykkt")
     f = kkt.Factor(kkt.Symbolic.from_pattern(pat))
     f.refactor(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), None, 1e7)
+    z = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
+    zm = torch.zeros(pat.m, dtype=torch.float64, device="cuda")
+    with pytest.raises(kkt.KKTError) as e:
+        f.solve_augmented(z, zm, zm, z.clone(), zm.clone(), zm.clone())
+    assert e.value.status == 3
+
+
+def test_augmented_needs_kept_values(kkt):
+    """Without kkt_factor_keep_augmented the Lifted-KKT refactor keeps no
+    copies, and the augmented solve is refused (STATE)."""
+    pat, v = kktgen.workload("small", instance=2)
+    f = kkt.Factor(kkt.Symbolic.from_pattern(pat))
+    f.refactor(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), dev(v.sigma_s))
     z = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
     zm = torch.zeros(pat.m, dtype=torch.float64, device="cuda")
     with pytest.raises(kkt.KKTError) as e:
