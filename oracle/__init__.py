@@ -13,4 +13,6 @@ Contents:
              with static pivots (condensed Cholesky, saddle-point LDL^T),
              Richardson refinement and the Cholesky + CG HyKKT solve.
   symbolic -- brute-force boolean elimination (column structures of L).
+  ipm     -- primal-dual interior-point method on a convex QP whose Newton
+             steps go through the augmented / condensed KKT systems.
 """

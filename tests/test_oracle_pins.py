@@ -577,3 +577,32 @@ def test_general_hykkt_condensation_and_gamma_independence():
     # slack and multiplier recovery with the inequality rows
     assert D.forward_error(dsv, -r4 - H @ dx) < 1e-10
     assert D.forward_error(dz, -r2 - ds * dsv) < 1e-10
+
+
+def test_qp_ipm_kkt_certificate_and_slsqp():
+    """The oracle's interior-point method on a convex QP (section
+    "INTERIOR-POINT METHOD"): its answer satisfies the QP's KKT conditions
+    (stationarity, primal feasibility, z >= 0, complementarity) to the
+    tolerance, and on a tiny instance matches scipy's SLSQP solution of the
+    same QP (an active-set method, independent of the IPM)."""
+    from scipy.optimize import minimize
+    from oracle import ipm
+    pat = kktgen.nmpc_pattern(4, 2, 1)          # n = 12, m = 8
+    v = kktgen.nmpc_values(pat, kktgen.rng_for(99, 0, 0), 1e-2, 1e2)
+    rng = kktgen.rng_for(99, 1, 0)
+    c = rng.standard_normal(pat.n)
+    u = 0.1 + 0.5 * rng.random(pat.m)
+    W, c, J, u = ipm.qp_from_pattern(pat, v, c, u)
+    x, s, z, info = ipm.qp_ipm(W, c, J, u, np.zeros(pat.n), u.copy(), np.ones(pat.m), tol=1e-10)
+    assert info["status"] == "ok", info
+    Wd, Jd = W.toarray(), J.toarray()
+    assert np.abs(Wd @ x + c + Jd.T @ z).max() <= 1e-8
+    assert (Jd @ x - u).max() <= 1e-9 and z.min() > 0 and s.min() > 0
+    assert abs(s @ z) <= 1e-8 * pat.m
+    active = (z > 1e-6).sum()
+    assert 0 < active < pat.m                    # some constraints bind, some do not
+    res = minimize(lambda y: 0.5 * y @ Wd @ y + c @ y, np.zeros(pat.n), jac=lambda y: Wd @ y + c,
+                   constraints=[dict(type="ineq", fun=lambda y: u - Jd @ y, jac=lambda y: -Jd)],
+                   method="SLSQP", options=dict(ftol=1e-14, maxiter=500))
+    assert res.success
+    assert np.abs(res.x - x).max() <= 1e-6 * (1 + np.abs(x).max())
