@@ -362,6 +362,50 @@ kkt_status kkt_solve_augmented(kkt_factor* f, const double* r1, const double* r2
                                void* stream);
 
 /*
+ * Interior-point outer loop (section "INTERIOR-POINT METHOD": the smoothed KKT
+ * system eq. (smoothkkt) solved by Newton steps, eq. (newtonstep), with a
+ * fraction-to-boundary step) on the convex QP
+ *     min 1/2 x^T W x + c^T x   s.t.   J x <= u
+ * over the factor's pattern (W from its lower triangle, every row of J an
+ * inequality), with slacks s (J x + s = u, s >= 0) and multipliers z. Each
+ * iteration: r1 = W x + c + J^T z, r4 = J x + s - u, gap = s^T z / m; stop when
+ * max(||r1||_inf / (1 + ||c||_inf), ||r4||_inf / (1 + ||u||_inf), gap) <= tol;
+ * else mu = sigma gap, r2 = z - mu / s, D_s = Z S^{-1}; kkt_refactor_inertia
+ * with Sigma_x = 0 and sigma_s = D_s (same analysis), kkt_solve_augmented for
+ * (dx, ds, dz) (eqs. (kkt:augmented), (kkt:condensed)); tau = max(tau_min,
+ * 1 - mu) and the largest alpha_p, alpha_d <= 1 keeping s and z above
+ * (1 - tau) of their current values; x += alpha_p dx, s += alpha_p ds,
+ * z += alpha_d dz. (The paper's solver adds a filter line search; on a convex
+ * QP the fraction-to-boundary steps are kept as they are.)
+ * w_vals, j_vals, c (n), u (m) are device inputs; x (n), s (m), z (m) are
+ * device arrays holding the starting point on entry (s > 0, z > 0) and the
+ * last iterate on return. opts may be NULL (tol 1e-8, maxit 100, sigma 0.1,
+ * tau_min 0.99). Synchronises every iteration. Enables kkt_factor_keep_augmented.
+ * Returns OK, NOT_CONVERGED after maxit iterations, or a refactor / solve error.
+ */
+typedef struct kkt_ipm_opts {
+    double tol;
+    int32_t maxit;
+    double sigma;            /* barrier reduction: mu = sigma * s^T z / m */
+    double tau_min;          /* fraction to the boundary: tau = max(tau_min, 1 - mu) */
+} kkt_ipm_opts;
+
+typedef struct kkt_ipm_info {
+    int32_t status;
+    int32_t iterations;      /* Newton steps taken */
+    double err;              /* the stop measure at exit */
+    double gap;              /* s^T z / m at exit */
+    double r1;               /* ||W x + c + J^T z||_inf at exit */
+    double r4;               /* ||J x + s - u||_inf at exit */
+    double max_delta;        /* largest inertia-correction delta used */
+    int32_t aug_corrections; /* refinement corrections of the augmented solves, summed */
+} kkt_ipm_info;
+
+void kkt_ipm_opts_default(kkt_ipm_opts* o);
+kkt_status kkt_ipm_qp(kkt_factor* f, const double* w_vals, const double* j_vals, const double* c, const double* u,
+                      double* x, double* s, double* z, const kkt_ipm_opts* opts, kkt_ipm_info* info, void* stream);
+
+/*
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): kkt_solve
  * with the same arguments, results (bit for bit) and synchronisation rules,

@@ -97,6 +97,7 @@ struct Engine {
     bool keep_aug = false;                          // Lifted-KKT refactors keep K0, J and Sigma_s (augmented solve)
     bool aug_ready = false;                         // the current factorization kept them
     DevBuf eqmask;                                  // general HyKKT: 1 on the equality rows of J (m ints)
+    DevBuf ipm_ws;                                  // interior-point loop vectors (allocated on first use)
     int n_eq = 0;                                   // equality rows set (0: none)
     // captured refactor + solve (batched form)
     hipGraph_t graph = nullptr;

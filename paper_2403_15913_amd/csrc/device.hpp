@@ -85,6 +85,12 @@ struct AugState {
     int it, maxit, done, revert;
 };
 
+// Interior-point loop record (one problem per factor)
+struct IpmState {
+    double mu, tau, gap, err, r1max, r4max, cn, un, ap, ad, delta, tol, sigma, tau_min;
+    int it, done, status, maxit;
+};
+
 struct InstDev {
     PatDev P;
     // offsets of this instance inside the caller's concatenated arrays

@@ -1848,6 +1848,12 @@ __device__ inline double slots_max(const double* red, int nb, int stride, int k)
     for (int b = threadIdx.x; b < nb; b += blockDim.x) v = fmax(v, red[stride * b + k]);
     return block_max(v);
 }
+// maximum of the negated slots (a minimum, for slots that may all be positive)
+__device__ inline double slots_max_neg(const double* red, int nb, int stride, int k) {
+    double v = -INFINITY;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) v = fmax(v, -red[stride * b + k]);
+    return block_max(v);
+}
 
 // sum_q a[q] * v[idx[q]] over q in [q0, q1), four loads in flight per round,
 // terms added in q order
@@ -2472,6 +2478,199 @@ __global__ __launch_bounds__(256) void k_aug_revert_m(const InstDev* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Interior-point loop (section "INTERIOR-POINT METHOD": the smoothed KKT
+// system eq. (smoothkkt), Newton steps eq. (newtonstep) through the
+// augmented system, fraction-to-boundary steps) on the convex QP
+//   min 1/2 x^T W x + c^T x  s.t.  J x + s = u, s >= 0,
+// multipliers z, D_s = S^{-1} Z. Per iteration (vectors in original numbering):
+//   r1 = W x + c + J^T z, r4 = J x + s - u, gap = s^T z / m,
+//   err = max(||r1|| / (1 + ||c||), ||r4|| / (1 + ||u||), gap) (inf-norms),
+//   mu = sigma gap, r2 = z - mu / s, tau = max(tau_min, 1 - mu),
+//   the Newton step (dx, ds, dz) from the augmented system, the largest
+//   alpha_p, alpha_d <= 1 keeping s and z above (1 - tau) of their values.
+// W x comes from the factor's kept K0 = W + delta I (Sigma_x = 0).
+// Slots: red[4 b + k] for the n-side blocks, red[4 nbn + 4 b + k] for m-side.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int ipm_m0(const InstDev& I) { return 4 * cg_nb(I.P.n); }
+
+// n-side: max |c|; m-side: max |u|; then the record (one workgroup per
+// instance reduces in the second kernel)
+__global__ __launch_bounds__(256) void k_ipm_norm_n(const InstDev* __restrict__ insts, IpmCall P,
+                                                    const WorkItem* __restrict__ items) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    const int j = it.id + threadIdx.x;
+    const double v = block_max(j < I.P.n ? fabs(P.c[j]) : 0.0);
+    if (threadIdx.x == 0) P.red[4 * (it.id >> 8)] = v;
+}
+__global__ __launch_bounds__(256) void k_ipm_norm_m(const InstDev* __restrict__ insts, IpmCall P,
+                                                    const WorkItem* __restrict__ items) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    const int i = it.id + threadIdx.x;
+    const double v = block_max(i < I.P.m ? fabs(P.u[i]) : 0.0);
+    if (threadIdx.x == 0) P.red[ipm_m0(I) + 4 * (it.id >> 8)] = v;
+}
+__global__ __launch_bounds__(256) void k_ipm_init(const InstDev* __restrict__ insts, IpmCall P, double tol, int maxit,
+                                                  double sigma, double tau_min) {
+    const InstDev& I = insts[0];
+    const double cm = slots_max(P.red, cg_nb(I.P.n), 4, 0);
+    const double um = slots_max(P.red + ipm_m0(I), cg_nb(I.P.m), 4, 0);
+    if (threadIdx.x != 0) return;
+    IpmState* S = P.st;
+    S->cn = 1.0 + cm;
+    S->un = 1.0 + um;
+    S->tol = tol;
+    S->maxit = maxit;
+    S->sigma = sigma;
+    S->tau_min = tau_min;
+    S->it = 0;
+    S->done = 0;
+    S->status = 0;
+    S->mu = S->gap = S->err = S->r1max = S->r4max = S->ap = S->ad = S->delta = 0.0;
+}
+
+// D_s = z / s, the slack weights of the refactor
+__global__ __launch_bounds__(256) void k_ipm_dsw(const InstDev* __restrict__ insts, IpmCall P,
+                                                 const WorkItem* __restrict__ items) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    const int i = it.id + threadIdx.x;
+    if (i < I.P.m) P.dsw[i] = P.z[i] / P.s[i];
+}
+
+// r1 = (K0 - delta I) x + c + J^T z
+__global__ __launch_bounds__(256) void k_ipm_res_n(const InstDev* __restrict__ insts, IpmCall P,
+                                                   const WorkItem* __restrict__ items, double delta) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    const int j = it.id + threadIdx.x;
+    double ra = 0.0;
+    if (j < I.P.n) {
+        double s = 0.0;
+        for (int64_t p = I.P.sp_ptr[j]; p < I.P.sp_ptr[j + 1]; p++) s += I.k0csr[p] * P.x[I.P.sp_col[p]];
+        s -= delta * P.x[j];
+        double t = 0.0;
+        for (int q = I.P.jt_ptr[j]; q < I.P.jt_ptr[j + 1]; q++) t += P.jv[I.P.jt_e[q]] * P.z[I.P.jt_row[q]];
+        const double r = s + P.c[j] + t;
+        P.r1[j] = r;
+        ra = fabs(r);
+    }
+    ra = block_max(ra);
+    if (threadIdx.x == 0) P.red[4 * (it.id >> 8)] = ra;
+}
+
+// r4 = J x + s - u, partial s^T z
+__global__ __launch_bounds__(256) void k_ipm_res_m(const InstDev* __restrict__ insts, IpmCall P,
+                                                   const WorkItem* __restrict__ items) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    const int i = it.id + threadIdx.x;
+    double ra = 0.0, sz = 0.0;
+    if (i < I.P.m) {
+        double t = 0.0;
+        for (int p = I.P.j_ptr[i]; p < I.P.j_ptr[i + 1]; p++) t += P.jv[p] * P.x[I.P.j_col[p]];
+        const double r = t + P.s[i] - P.u[i];
+        P.r4[i] = r;
+        ra = fabs(r);
+        sz = P.s[i] * P.z[i];
+    }
+    ra = block_max(ra);
+    sz = block_sum(sz);
+    if (threadIdx.x == 0) {
+        double* sl = P.red + ipm_m0(I) + 4 * (it.id >> 8);
+        sl[0] = ra;
+        sl[1] = sz;
+    }
+}
+
+// the stop test and mu, tau of this iteration
+__global__ __launch_bounds__(256) void k_ipm_decide(const InstDev* __restrict__ insts, IpmCall P, double delta) {
+    const InstDev& I = insts[0];
+    const int nbn = cg_nb(I.P.n), nbm = cg_nb(I.P.m);
+    const double r1 = slots_max(P.red, nbn, 4, 0);
+    const double r4 = slots_max(P.red + ipm_m0(I), nbm, 4, 0);
+    const double sz = slots_sum(P.red + ipm_m0(I), nbm, 4, 1);
+    if (threadIdx.x != 0) return;
+    IpmState* S = P.st;
+    S->r1max = r1;
+    S->r4max = r4;
+    S->delta = fmax(S->delta, delta);
+    S->gap = I.P.m > 0 ? sz / I.P.m : 0.0;
+    S->err = fmax(fmax(r1 / S->cn, r4 / S->un), S->gap);
+    if (S->err <= S->tol) {
+        S->done = 1;
+    } else if (S->it >= S->maxit) {
+        S->done = 1;
+        S->status = 6;  // not converged
+    } else {
+        S->mu = S->sigma * S->gap;
+        S->tau = fmax(S->tau_min, 1.0 - S->mu);
+    }
+}
+
+// r2 = z - mu / s
+__global__ __launch_bounds__(256) void k_ipm_r2(const InstDev* __restrict__ insts, IpmCall P,
+                                                const WorkItem* __restrict__ items) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    const int i = it.id + threadIdx.x;
+    if (i < I.P.m) P.r2[i] = P.z[i] - P.st->mu / P.s[i];
+}
+
+// fraction to the boundary: per block the smallest -tau v / dv over dv < 0
+// (2 when no entry decreases), for s and for z
+__global__ __launch_bounds__(256) void k_ipm_alpha(const InstDev* __restrict__ insts, IpmCall P,
+                                                   const WorkItem* __restrict__ items) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    const int i = it.id + threadIdx.x;
+    const double tau = P.st->tau;
+    double as = 2.0, az = 2.0;
+    if (i < I.P.m) {
+        if (P.ds[i] < 0.0) as = -tau * P.s[i] / P.ds[i];
+        if (P.dz[i] < 0.0) az = -tau * P.z[i] / P.dz[i];
+    }
+    as = -block_max(-as);
+    az = -block_max(-az);
+    if (threadIdx.x == 0) {
+        double* sl = P.red + ipm_m0(I) + 4 * (it.id >> 8);
+        sl[2] = as;
+        sl[3] = az;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ipm_alpha_fin(const InstDev* __restrict__ insts, IpmCall P) {
+    const InstDev& I = insts[0];
+    const int nbm = cg_nb(I.P.m);
+    const double as = -slots_max_neg(P.red + ipm_m0(I), nbm, 4, 2);
+    const double az = -slots_max_neg(P.red + ipm_m0(I), nbm, 4, 3);
+    if (threadIdx.x != 0) return;
+    P.st->ap = fmin(1.0, as);
+    P.st->ad = fmin(1.0, az);
+    P.st->it += 1;
+}
+
+// x += alpha_p dx (n-side blocks); s += alpha_p ds, z += alpha_d dz (m-side)
+__global__ __launch_bounds__(256) void k_ipm_update_n(const InstDev* __restrict__ insts, IpmCall P,
+                                                      const WorkItem* __restrict__ items) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    const int j = it.id + threadIdx.x;
+    if (j < I.P.n) P.x[j] = fma(P.st->ap, P.dx[j], P.x[j]);
+}
+__global__ __launch_bounds__(256) void k_ipm_update_m(const InstDev* __restrict__ insts, IpmCall P,
+                                                      const WorkItem* __restrict__ items) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev& I = insts[it.inst];
+    const int i = it.id + threadIdx.x;
+    if (i < I.P.m) {
+        P.s[i] = fma(P.st->ap, P.ds[i], P.s[i]);
+        P.z[i] = fma(P.st->ad, P.dz[i], P.z[i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // workspace redirection (allocation-free solve): copies of a factor's instance
 // descriptor and front descriptors whose per-solve vectors point into a
 // caller-provided workspace
@@ -2540,6 +2739,31 @@ void launch_aug_revert(const InstDev* insts, const AugCall& A, const WorkItem* n
                        int nm, hipStream_t st) {
     if (nn > 0) k_aug_revert_n<<<nn, kBlock, 0, st>>>(insts, A, ncols);
     if (nm > 0) k_aug_revert_m<<<nm, kBlock, 0, st>>>(insts, A, mrows);
+}
+void launch_ipm_start(const InstDev* insts, const IpmCall& P, const WorkItem* ncols, int nn, const WorkItem* mrows,
+                      int nm, double tol, int maxit, double sigma, double tau_min, hipStream_t st) {
+    if (nn > 0) k_ipm_norm_n<<<nn, kBlock, 0, st>>>(insts, P, ncols);
+    if (nm > 0) k_ipm_norm_m<<<nm, kBlock, 0, st>>>(insts, P, mrows);
+    k_ipm_init<<<1, kBlock, 0, st>>>(insts, P, tol, maxit, sigma, tau_min);
+}
+void launch_ipm_dsw(const InstDev* insts, const IpmCall& P, const WorkItem* mrows, int nm, hipStream_t st) {
+    if (nm > 0) k_ipm_dsw<<<nm, kBlock, 0, st>>>(insts, P, mrows);
+}
+void launch_ipm_residuals(const InstDev* insts, const IpmCall& P, const WorkItem* ncols, int nn, const WorkItem* mrows,
+                          int nm, double delta, hipStream_t st) {
+    if (nn > 0) k_ipm_res_n<<<nn, kBlock, 0, st>>>(insts, P, ncols, delta);
+    if (nm > 0) k_ipm_res_m<<<nm, kBlock, 0, st>>>(insts, P, mrows);
+    k_ipm_decide<<<1, kBlock, 0, st>>>(insts, P, delta);
+}
+void launch_ipm_r2(const InstDev* insts, const IpmCall& P, const WorkItem* mrows, int nm, hipStream_t st) {
+    if (nm > 0) k_ipm_r2<<<nm, kBlock, 0, st>>>(insts, P, mrows);
+}
+void launch_ipm_step(const InstDev* insts, const IpmCall& P, const WorkItem* ncols, int nn, const WorkItem* mrows,
+                     int nm, hipStream_t st) {
+    if (nm > 0) k_ipm_alpha<<<nm, kBlock, 0, st>>>(insts, P, mrows);
+    k_ipm_alpha_fin<<<1, kBlock, 0, st>>>(insts, P);
+    if (nn > 0) k_ipm_update_n<<<nn, kBlock, 0, st>>>(insts, P, ncols);
+    if (nm > 0) k_ipm_update_m<<<nm, kBlock, 0, st>>>(insts, P, mrows);
 }
 void launch_ws_redirect(const InstDev* src_inst, const FrontDesc* src_fd, int nf, const SolveWs& w, hipStream_t st) {
     k_ws_redirect<<<blocks_for(nf > 0 ? nf : 1, 256), 256, 0, st>>>(src_inst, src_fd, nf, w);

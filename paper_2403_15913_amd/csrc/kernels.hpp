@@ -163,4 +163,33 @@ void launch_aug_check(const InstDev* insts, const AugCall& A, const WorkItem* nc
 void launch_aug_revert(const InstDev* insts, const AugCall& A, const WorkItem* ncols, int nn, const WorkItem* mrows,
                        int nm, hipStream_t st);
 
+// Interior-point loop on a convex QP (min 1/2 x^T W x + c^T x, J x <= u) over
+// one factor's pattern; vectors in original numbering (see the kernels)
+struct IpmCall {
+    const double* w;    // W values (lower CSR entry order)
+    const double* jv;   // J values
+    const double* c;    // n
+    const double* u;    // m
+    double* x;          // n
+    double* s;          // m
+    double* z;          // m
+    double* dsw;        // m: D_s = z / s (the refactor's sigma_s)
+    double* r1;         // n
+    double* r2;         // m
+    double* r4;         // m
+    double* dx;         // n
+    double* ds;         // m
+    double* dz;         // m
+    double* red;        // reduction slots (4 per 256-row block of n, then of m)
+    IpmState* st;
+};
+void launch_ipm_start(const InstDev* insts, const IpmCall& P, const WorkItem* ncols, int nn, const WorkItem* mrows,
+                      int nm, double tol, int maxit, double sigma, double tau_min, hipStream_t st);
+void launch_ipm_dsw(const InstDev* insts, const IpmCall& P, const WorkItem* mrows, int nm, hipStream_t st);
+void launch_ipm_residuals(const InstDev* insts, const IpmCall& P, const WorkItem* ncols, int nn, const WorkItem* mrows,
+                          int nm, double delta, hipStream_t st);
+void launch_ipm_r2(const InstDev* insts, const IpmCall& P, const WorkItem* mrows, int nm, hipStream_t st);
+void launch_ipm_step(const InstDev* insts, const IpmCall& P, const WorkItem* ncols, int nn, const WorkItem* mrows,
+                     int nm, hipStream_t st);
+
 }  // namespace kkt

@@ -91,6 +91,18 @@ class AugInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class IpmOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("sigma", C.c_double), ("tau_min", C.c_double)]
+
+
+class IpmInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("err", C.c_double), ("gap", C.c_double),
+                ("r1", C.c_double), ("r4", C.c_double), ("max_delta", C.c_double), ("aug_corrections", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class FactorInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("bad_col", C.c_int32)]
 
@@ -131,6 +143,8 @@ SIGNATURES = {
     "kkt_matvec": (I32, [P, P, P, P]),
     "kkt_factor_set_equality_rows": (I32, [P, P, I32]),
     "kkt_factor_keep_augmented": (I32, [P, I32]),
+    "kkt_ipm_opts_default": (None, [P]),
+    "kkt_ipm_qp": (I32, [P, P, P, P, P, P, P, P, P, P, P]),
     "kkt_factor_set_timing": (I32, [P, I32]),
     "kkt_factor_read_timing": (I32, [P, P]),
     "kkt_factor_set_schedule": (I32, [P, I32]),
@@ -333,6 +347,17 @@ def kkt_cg_schur(h, f, g, dx, dy, tol: float = 1e-10, maxit: int = 200, eta_tol:
     return ci.as_dict() if info else None
 
 
+def kkt_ipm_qp(h, w_vals, j_vals, c, u, x, s, z, tol: float = 1e-8, maxit: int = 100, sigma: float = 0.1,
+               tau_min: float = 0.99, stream=None) -> dict:
+    o = IpmOpts(float(tol), int(maxit), float(sigma), float(tau_min))
+    ii = IpmInfo()
+    st = lib().kkt_ipm_qp(h, _dptr(w_vals), _dptr(j_vals), _dptr(c), _dptr(u), _dptr(x), _dptr(s), _dptr(z),
+                          C.byref(o), C.byref(ii), _stream(stream))
+    if st not in (KKT_OK, 6):
+        _err(st)
+    return ii.as_dict()
+
+
 def kkt_factor_keep_augmented(h, enable: bool = True):
     _err(lib().kkt_factor_keep_augmented(h, 1 if enable else 0))
 
@@ -425,6 +450,9 @@ class Factor:
 
     def cg_schur(self, f, g, dx, dy, tol=1e-10, maxit=200, eta_tol=0.0, info=True, stream=None):
         return kkt_cg_schur(self.h, f, g, dx, dy, tol, maxit, eta_tol, info, stream)
+
+    def ipm_qp(self, w_vals, j_vals, c, u, x, s, z, **kw):
+        return kkt_ipm_qp(self.h, w_vals, j_vals, c, u, x, s, z, **kw)
 
     def keep_augmented(self, enable=True):
         kkt_factor_keep_augmented(self.h, enable)
