@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--autotune", type=int, default=1,
                     help="pick ordering / leaf size by measurement (ignored when --ordering or --nd-leaf is set)")
     ap.add_argument("--hykkt", type=int, default=1, help="also time HyKKT (refactor + Schur CG) at paper scale")
+    ap.add_argument("--ipm", type=int, default=1, help="also time the interior-point loop on a paper-scale QP")
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched workload (0: skip)")
     ap.add_argument("--batch-ordering", type=int, default=2, help="batch ordering when not autotuned")
     ap.add_argument("--batch-nd-leaf", type=int, default=256, help="batch nested-dissection leaf when not autotuned")
@@ -222,6 +223,52 @@ def bench_hykkt(args, kkt, kktgen, torch, dev, opts):
             phase_ms_per_pair={p: round(tm[p]["ms"] / args.steps, 4) for p in tm},
             launches_per_pair={p: round(tm[p]["launches"] / args.steps, 1) for p in tm})
     return out
+
+
+def bench_ipm(args, kkt, kktgen, torch, dev, opts):
+    """Time per interior-point iteration (section "INTERIOR-POINT METHOD") on a convex LQ-MPC QP with
+    the paper-scale distillation-shaped W and J (n=142,000, m=140,000): min 1/2 x^T W x + c^T x,
+    J x <= u, from x = 0, s = u, z = 1 to tol 1e-8. Each iteration is an inertia-corrected refactor with
+    D_s = Z S^{-1}, the augmented solve, and the device vector kernels. The oracle's interior-point
+    method (same algorithm, CPU) is timed for two iterations on the same problem."""
+    from oracle import ipm as oipm
+    pat, _ = kktgen.paper_config()
+    v = kktgen.distillation_values(pat, kktgen.rng_for(1, 0, 0), 1e-2, 1e2)
+    rng = kktgen.rng_for(100, 2, 0)
+    c = rng.standard_normal(pat.n)
+    u = 0.1 + rng.random(pat.m)
+
+    def T(a):
+        return torch.tensor(np.asarray(a), dtype=torch.float64, device=dev)
+
+    fac = kkt.Factor(kkt.Symbolic.from_pattern(pat, **opts))
+    dw, dj, dc, du = T(v.w_vals), T(v.j_vals), T(c), T(u)
+
+    def run():
+        x = torch.zeros(pat.n, dtype=torch.float64, device=dev)
+        s_ = du.clone()
+        z = torch.ones(pat.m, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = fac.ipm_qp(dw, dj, dc, du, x, s_, z, tol=1e-8)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, info
+
+    run()
+    secs, info = run()
+    cpu = None
+    if not args.no_cpu_baseline:
+        W, c2, J, u2 = oipm.qp_from_pattern(pat, v, c, u)
+        t0 = time.perf_counter()
+        _, _, _, oinfo = oipm.qp_ipm(W, c2, J, u2, np.zeros(pat.n), u2.copy(), np.ones(pat.m), tol=1e-8, maxit=2)
+        cs = time.perf_counter() - t0
+        cpu = dict(s_per_iteration=round(cs / max(1, oinfo["iterations"]), 3), iterations_timed=oinfo["iterations"],
+                   cores=1, kind="oracle")
+    its = max(1, info["iterations"])
+    return dict(workload="convex QP, distillation-shaped N=2000 W and J (n=142000, m=140000), J x <= u, tol 1e-8",
+                status=info["status"], iterations=info["iterations"], ms_total=round(1e3 * secs, 3),
+                ms_per_iteration=round(1e3 * secs / its, 3), err=info["err"], max_delta=info["max_delta"],
+                cpu_oracle=cpu)
 
 
 def bench_served(args, kkt, kktgen, torch, dev):
@@ -495,6 +542,7 @@ def main():
                     avg_launch_us=1e3 * tm[dom]["ms"] / max(1, tm[dom]["launches"]))
 
     hykkt = bench_hykkt(args, kkt, kktgen, torch, dev, opts) if args.hykkt and args.workload == "paper" else None
+    ipm_leg = bench_ipm(args, kkt, kktgen, torch, dev, opts) if args.ipm and args.workload == "paper" else None
     batched = bench_batched(args, kkt, kktgen, torch, dev) if args.batch > 0 else None
     served = bench_served(args, kkt, kktgen, torch, dev) if args.serve_requests > 0 else None
 
@@ -528,6 +576,7 @@ def main():
             "symbolic": {k: stats[k] for k in ("nsuper", "levels", "max_rows", "max_cols", "nnz_k", "nnz_l",
                                                "nnz_l_exact", "flops", "flops_exact")},
             "hykkt": hykkt,
+            "ipm": ipm_leg,
             "batched": batched,
             "served": served,
         },
