@@ -533,6 +533,59 @@ kkt_status kkt_batch_set_timing(kkt_batch* b, int32_t enable);
 kkt_status kkt_batch_read_timing(kkt_batch* b, kkt_timing* out);
 
 /*
+ * Stage-structured solver (section "Future Works": the condensed matrix of a
+ * dynamic program is block-banded and can be factorized by a block solver
+ * instead of a general sparse one). For patterns whose variables are
+ * numbered stage by stage (stage k owns [stage_ptr[k], stage_ptr[k+1]), at
+ * most 96 variables), where W couples only variables of the same or
+ * consecutive stages and every row of J spans at most two consecutive
+ * stages, K = W + Sigma_x + J^T Sigma_s J is block tridiagonal,
+ * K = tridiag(E_{k-1}, D_k, E_k^T), and is factored by the block Cholesky
+ * (Riccati) recursion
+ *   Dt_k = D_k - Ls_{k-1} Ls_{k-1}^T,  L_kk = chol(Dt_k),  Ls_k = E_k L_kk^{-T}
+ * with one workgroup per instance walking its stages; K itself is assembled
+ * by the same kernels (same bits) as kkt_factor_refactor. No fill-reducing
+ * ordering is used: vectors stay in the original numbering.
+ *
+ * kkt_stagewise_create: count instances, syms[q] the pattern of instance q
+ * (must outlive the solver), stage_ptrs[q] its nstages[q] + 1 stage starts
+ * (host arrays, copied). Values and vectors are concatenated in instance
+ * order as for kkt_batch (offsets from the patterns' sizes). Errors:
+ * INVALID_ARG (stage_ptr not 0 .. n, an empty stage), PATTERN (a stage
+ * wider than 96, or a position of K coupling stages more than one apart),
+ * OOM. Synchronous.
+ */
+typedef struct kkt_stagewise kkt_stagewise;
+kkt_status kkt_stagewise_create(int32_t count, const kkt_symbolic* const* syms, const int32_t* const* stage_ptrs,
+                                const int32_t* nstages, kkt_stagewise** out);
+void kkt_stagewise_destroy(kkt_stagewise* w);
+
+/* Assembles and factors K of every instance (device arrays in the patterns'
+ * entry order, concatenated). Asynchronous on `stream`; a pivot that is not
+ * positive is reported by kkt_stagewise_status (and by the next solve). */
+kkt_status kkt_stagewise_refactor(kkt_stagewise* w, const double* w_vals, const double* j_vals,
+                                  const double* sigma_x, const double* sigma_s, void* stream);
+
+/* Synchronises the last stream and reports each instance's factor status
+ * (status[q], KKT_OK or KKT_ERR_NOT_SPD) and, on NOT_SPD, the first failed
+ * variable in the original numbering (bad_col[q], else -1); either array
+ * may be NULL. Returns the first failure. */
+kkt_status kkt_stagewise_status(kkt_stagewise* w, int32_t* status, int32_t* bad_col);
+
+/* Solves K x = rhs for every instance with the stop rule of kkt_solve
+ * (componentwise backward error <= tol, at most max_iter corrections, stop
+ * when it fails to halve; ro may be NULL: tol 1e-14, max_iter 10). rhs and x
+ * are device arrays (concatenated, original numbering, no aliasing); infos
+ * (host, one per instance) may be NULL. Synchronises once per refinement
+ * round. Returns NOT_SPD if the factor failed, NOT_CONVERGED if an instance
+ * missed tol. */
+kkt_status kkt_stagewise_solve(kkt_stagewise* w, const double* rhs, double* x, const kkt_refine_opts* ro,
+                               kkt_solve_info* infos, void* stream);
+
+kkt_status kkt_stagewise_set_timing(kkt_stagewise* w, int32_t enable);
+kkt_status kkt_stagewise_read_timing(kkt_stagewise* w, kkt_timing* out);
+
+/*
  * Served form: a request loop over resident sparsity patterns. A registered
  * pattern's analysis stays on the device; each request is a refactor with new
  * values plus a refined solve (the analysis is reused, section "Hybrid linear

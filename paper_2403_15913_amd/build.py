@@ -20,7 +20,8 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall"]
 
 SOURCES = [("kernels.hip", "hip"), ("api.cpp", "hip"), ("server.cpp", "hip"), ("noalloc.cpp", "hip"),
-           ("ipm.cpp", "hip"), ("symbolic.cpp", "host")]
+           ("ipm.cpp", "hip"), ("stagewise.cpp", "hip"),
+           ("symbolic.cpp", "host")]
 
 
 def _run(cmd):

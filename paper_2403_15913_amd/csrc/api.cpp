@@ -19,13 +19,6 @@
 
 using namespace kkt;
 
-// Launch `expr` on stream `st`, bracketed by timer events when timing is on.
-#define TL(ph, expr)                              \
-    do {                                          \
-        if (timer.on) timer.begin(ph, st);        \
-        expr;                                     \
-        if (timer.on) timer.end(st);              \
-    } while (0)
 
 namespace kkt {
 
@@ -263,9 +256,11 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         return fail(KKT_ERR_PATTERN, "a front exceeds the per-workgroup LDS budget");
     const size_t N = (size_t)n_ofs[ninst], M = (size_t)m_ofs[ninst];
     Carver cv(mem, cap);
-    L = cv.take<double>(lo[ninst]);
-    U = cv.take<double>(uo[ninst]);
-    V = cv.take<double>(vo[ninst]);
+    // the stage-structured solver uses the engine for assembly and refinement
+    // only: no supernode panels, update matrices or vectors
+    L = cv.take<double>(assembly_only ? 0 : lo[ninst]);
+    U = cv.take<double>(assembly_only ? 0 : uo[ninst]);
+    V = cv.take<double>(assembly_only ? 0 : vo[ninst]);
     kval = cv.take<double>(ko[ninst]);
     kcsr = cv.take<double>(co[ninst]);
     rpart = cv.take<double>(po[ninst]);
@@ -571,6 +566,19 @@ DepLists Engine::deps() const {
     D.err = dep_ctr + 3 * N + 1;
     D.nitems = N;
     return D;
+}
+
+// the assembly of K alone (the stage-structured solver factors it itself)
+kkt_status Engine::assemble(const Calls& C, hipStream_t st) {
+    last_stream = st;
+    mode = 1;
+    gamma = 0.0;
+    TL(KKT_PHASE_CONTROL, launch_status_init(status, ninst, st));
+    if (C.ss) TL(KKT_PHASE_ASSEMBLE, launch_jscale(di(), C, jitems, n_jitems, st));
+    TL(KKT_PHASE_ASSEMBLE, launch_assemble(di(), C, kitems, n_kitems, st));
+    TL(KKT_PHASE_ASSEMBLE, launch_assemble_heavy(di(), C, hitems, n_hitems, st));
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? KKT_OK : hip_fail(e, "assembly launch");
 }
 
 kkt_status Engine::refactor(const Calls& Cin, hipStream_t st) {

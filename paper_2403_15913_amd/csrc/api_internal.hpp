@@ -19,6 +19,14 @@
 #include "lds_layout.hpp"
 #include "symbolic.hpp"
 
+// Launch `expr` on stream `st`, bracketed by timer events when timing is on.
+#define TL(ph, expr)                              \
+    do {                                          \
+        if (timer.on) timer.begin(ph, st);        \
+        expr;                                     \
+        if (timer.on) timer.end(st);              \
+    } while (0)
+
 namespace kkt {
 
 extern thread_local std::string g_last_error;
@@ -91,6 +99,7 @@ struct Engine {
     std::vector<int> lvl_maxu;                      // widest update part of each level
     bool split_update = true;                       // level schedule: update matrices in their own launch
     bool queue_sched = false;                       // dependency-driven launches (else one launch per level)
+    bool assembly_only = false;                     // no supernodal factor storage (stage-structured solver)
     bool single_storage = false;                    // single factors: K0, J and Sigma_s kept for the HyKKT CG
                                                     // and the augmented-system solve
     double delta_last = 0.0;                        // inertia correction: last delta that made K definite
@@ -141,6 +150,7 @@ struct Engine {
     kkt_status init_owned(const std::vector<const Symbolic*>& s);
     const InstDev* di() const { return dinsts; }
     kkt_status refactor(const Calls& C, hipStream_t st);
+    kkt_status assemble(const Calls& C, hipStream_t st);
     void sweeps(hipStream_t st, int skip_done);
     // Lifted-KKT solve with refinement; infos (ninst entries) filled when non-NULL.
     kkt_status solve(const Calls& C, int maxit, double tol, kkt_solve_info* infos, hipStream_t st);

@@ -2671,6 +2671,256 @@ __global__ __launch_bounds__(256) void k_ipm_update_m(const InstDev* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Stage-structured solver: the condensed matrix of a dynamic program is
+// block-banded (section "Future Works"); with stage-contiguous variables and
+// couplings between consecutive stages only, K is block tridiagonal and is
+// factored here by block cyclic reduction: the stages at odd positions of the
+// active chain are eliminated together (one workgroup each), the rest form
+// the next, half as long, chain. This is a Cholesky factorization of K in
+// the cyclic-reduction order, with dense blocks: per eliminated stage k with
+// active neighbours l and r,
+//   L_k = chol(D_k - pending updates),  L(l,k) = K(l,k) L_k^{-T},
+//   L(r,k) = K(r,k) L_k^{-T},
+// and it leaves to the next level the updates L(l,k) L(l,k)^T (to D_l),
+// L(r,k) L(r,k)^T (to D_r) and the fill K(r,l) = -L(r,k) L(l,k)^T. K itself
+// comes from the general assembly (kcsr), so its entries are the same bits as
+// the supernodal path's.
+// ---------------------------------------------------------------------------
+__global__ void k_fill_f64(double* __restrict__ p, double v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_cr_scatter(const InstDev* __restrict__ insts, CrArrays A,
+                                                    const CrScatter* __restrict__ items, int64_t nitems) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nitems) return;
+    const CrScatter it = items[t];
+    const double v = insts[it.inst].kcsr[it.pos];
+    if (it.dst >= 0) A.D[it.dst] = v;
+    else A.C[-it.dst - 1] = v;
+}
+
+// One row of X L^T = B (L lower, s x s in LDS, column-major): rows of X are
+// independent, each a forward substitution; dot-product form, in place.
+__device__ inline void cr_trsm_row(double* __restrict__ B, int ld, int a, const double* __restrict__ L, int s) {
+    for (int c = 0; c < s; c++) {
+        double acc = B[c * ld + a];
+        for (int c2 = 0; c2 < c; c2++) acc = fma(-B[c2 * ld + a], L[c2 * s + c], acc);
+        B[c * ld + a] = acc / L[c * s + c];
+    }
+}
+
+// One workgroup per eliminated stage of one level. LDS: A (s_k x s_k), then
+// P1 = K(l,k) -> L(l,k) (s_l x s_k), P2 = K(r,k) -> L(r,k) (s_r x s_k), all
+// column-major with the row count as leading dimension.
+__global__ __launch_bounds__(256) void k_cr_factor(const InstDev* __restrict__ insts, CrArrays AR, int task0) {
+    extern __shared__ __align__(16) double sh[];
+    const CrTask T = AR.tasks[task0 + blockIdx.x];
+    const InstDev& I = insts[T.inst];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int sk = T.sk, sl = T.sl, sr = T.sr;
+    double* A = sh;
+    double* P1 = sh + sk * sk;
+    double* P2 = P1 + sl * sk;
+    // D_k minus the updates left by the stages eliminated before it (lower part)
+    const double* Dk = AR.D + T.d;
+    for (int q = tid; q < sk * sk; q += nt) {
+        const int i = q % sk, j = q / sk;
+        if (i < j) continue;
+        double v = Dk[q];
+        for (int u = 0; u < T.npull; u++) v -= AR.U[AR.pulls[T.pull0 + u].u + q];
+        A[q] = v;
+    }
+    // P1 = K(l,k) = K(k,l)^T from the s_k x s_l block (read in its order)
+    if (sl > 0) {
+        const double* S = AR.C + T.kl;
+        for (int q = tid; q < sl * sk; q += nt) {
+            const int b = q % sk, a = q / sk;
+            P1[b * sl + a] = S[q];
+        }
+    }
+    if (sr > 0) {
+        const double* S = AR.C + T.kr;
+        for (int q = tid; q < sr * sk; q += nt) P2[q] = S[q];
+    }
+    __syncthreads();
+    // Cholesky, column by column: the trailing update of step j uses column j
+    // unscaled (divided by the pivot), and column j is scaled in step j + 1,
+    // when no thread reads it; one barrier per column. A pivot that is not
+    // positive and finite is latched and replaced by 1.
+    double dprev = 1.0;
+    for (int j = 0; j < sk; j++) {
+        double d = A[j * sk + j];
+        if (!(d > 0.0) || !isfinite(d)) {
+            if (tid == 0) {
+                atomicMin(&I.status[1], T.var0 + j);
+                atomicMax(&I.status[0], KKT_ST_NOT_SPD);
+            }
+            d = 1.0;
+        }
+        if (j > 0) {
+            const double ls = sqrt(dprev), inv = 1.0 / ls;
+            for (int i = j - 1 + tid; i < sk; i += nt)
+                A[(j - 1) * sk + i] = i == j - 1 ? ls : A[(j - 1) * sk + i] * inv;
+        }
+        const double inv_d = 1.0 / d;
+        const int tr = sk - j - 1;
+        for (int q = tid; q < tr * tr; q += nt) {
+            const int i = j + 1 + q % tr, c = j + 1 + q / tr;
+            if (i < c) continue;
+            A[c * sk + i] = fma(-(A[j * sk + i] * inv_d), A[j * sk + c], A[c * sk + i]);
+        }
+        dprev = d;
+        __syncthreads();
+    }
+    if (tid == 0) A[(sk - 1) * sk + sk - 1] = sqrt(dprev);
+    __syncthreads();
+    double* Lk = AR.D + T.d;
+    for (int q = tid; q < sk * sk; q += nt)
+        if (q % sk >= q / sk) Lk[q] = A[q];
+    // L(l,k) and L(r,k): rows in parallel (P1 rows on waves 0-1, P2 rows on 2-3)
+    if (tid < 128) {
+        if (tid < sl) cr_trsm_row(P1, sl, tid, A, sk);
+    } else if (tid - 128 < sr) {
+        cr_trsm_row(P2, sr, tid - 128, A, sk);
+    }
+    __syncthreads();
+    if (sl > 0)
+        for (int q = tid; q < sl * sk; q += nt) AR.P[T.pl + q] = P1[q];
+    if (sr > 0)
+        for (int q = tid; q < sr * sk; q += nt) AR.P[T.pr + q] = P2[q];
+    // updates for the next level: L(l,k) L(l,k)^T, L(r,k) L(r,k)^T (lower
+    // parts) and the fill -L(r,k) L(l,k)^T
+    const int nul = sl * sl, nur = sr * sr, nf = (sl > 0 && sr > 0) ? sr * sl : 0;
+    for (int q = tid; q < nul + nur + nf; q += nt) {
+        if (q < nul) {
+            const int a = q % sl, b = q / sl;
+            if (a < b) continue;
+            double acc = 0.0;
+            for (int c = 0; c < sk; c++) acc = fma(P1[c * sl + a], P1[c * sl + b], acc);
+            AR.U[T.ul + q] = acc;
+        } else if (q < nul + nur) {
+            const int q2 = q - nul, a = q2 % sr, b = q2 / sr;
+            if (a < b) continue;
+            double acc = 0.0;
+            for (int c = 0; c < sk; c++) acc = fma(P2[c * sr + a], P2[c * sr + b], acc);
+            AR.U[T.ur + q2] = acc;
+        } else {
+            const int q2 = q - nul - nur, a = q2 % sr, b = q2 / sr;
+            double acc = 0.0;
+            for (int c = 0; c < sk; c++) acc = fma(P2[c * sr + a], P1[c * sl + b], acc);
+            AR.C[T.f + q2] = -acc;
+        }
+    }
+}
+
+// Forward solve L y = b, one wavefront per eliminated stage of one level:
+// t_k = b_k - (the L blocks of the earlier-eliminated neighbours times their
+// y), then y_k = L_k^{-1} t_k by substitution (lane i holds rows i and
+// i + 64, the pivot value is broadcast by a lane shuffle). mode 0 reads b,
+// mode 1 the refinement residual (skipping stopped instances).
+__global__ __launch_bounds__(64) void k_cr_fwd(const InstDev* __restrict__ insts, CrArrays AR, int task0, Calls C,
+                                               int mode) {
+    __shared__ double Ls[kCrMaxStage * kCrMaxStage];
+    const CrTask T = AR.tasks[task0 + blockIdx.x];
+    const InstDev& I = insts[T.inst];
+    if (mode == 1 && I.rs->done) return;  // uniform per block
+    const int lane = threadIdx.x, sk = T.sk;
+    const int i0 = lane, i1 = lane + 64;
+    const double* src = mode == 0 ? C.b + T.v0 : I.r + T.var0;
+    double t0 = i0 < sk ? src[i0] : 0.0;
+    double t1 = i1 < sk ? src[i1] : 0.0;
+    for (int u = 0; u < T.npull; u++) {
+        const CrPull Pu = AR.pulls[T.pull0 + u];
+        const double* P = AR.P + Pu.p;  // s_k x s_i
+        const double* y = AR.t + Pu.vi;
+        for (int c = 0; c < Pu.si; c++) {
+            const double yc = y[c];
+            if (i0 < sk) t0 = fma(-P[c * sk + i0], yc, t0);
+            if (i1 < sk) t1 = fma(-P[c * sk + i1], yc, t1);
+        }
+    }
+    const double* Lk = AR.D + T.d;
+    for (int q = lane; q < sk * sk; q += 64) Ls[q] = Lk[q];
+    __syncthreads();
+    for (int j = 0; j < sk; j++) {
+        const double tj = j < 64 ? __shfl(t0, j) : __shfl(t1, j - 64);
+        const double yj = tj / Ls[j * sk + j];
+        if (i0 == j) t0 = yj;
+        else if (i0 > j && i0 < sk) t0 = fma(-Ls[j * sk + i0], yj, t0);
+        if (i1 == j) t1 = yj;
+        else if (i1 > j && i1 < sk) t1 = fma(-Ls[j * sk + i1], yj, t1);
+    }
+    if (i0 < sk) AR.t[T.v0 + i0] = t0;
+    if (i1 < sk) AR.t[T.v0 + i1] = t1;
+}
+
+// Backward solve L^T x = y, levels in reverse: x_k = L_k^{-T} (y_k -
+// L(l,k)^T x_l - L(r,k)^T x_r), the neighbours being eliminated later (their
+// x already in t). x_k goes to t and to the output: mode 0 x = x_k; mode 1
+// xprev = x, x += x_k.
+__global__ __launch_bounds__(64) void k_cr_bwd(const InstDev* __restrict__ insts, CrArrays AR, int task0, Calls C,
+                                               int mode) {
+    __shared__ double Ls[kCrMaxStage * kCrMaxStage];
+    const CrTask T = AR.tasks[task0 + blockIdx.x];
+    const InstDev& I = insts[T.inst];
+    if (mode == 1 && I.rs->done) return;  // uniform per block
+    const int lane = threadIdx.x, sk = T.sk;
+    const int i0 = lane, i1 = lane + 64;
+    double t0 = i0 < sk ? AR.t[T.v0 + i0] : 0.0;
+    double t1 = i1 < sk ? AR.t[T.v0 + i1] : 0.0;
+    if (T.sl > 0) {
+        const double* P = AR.P + T.pl;  // s_l x s_k
+        const double* x = AR.t + T.vl;
+        if (i0 < sk)
+            for (int a = 0; a < T.sl; a++) t0 = fma(-P[i0 * T.sl + a], x[a], t0);
+        if (i1 < sk)
+            for (int a = 0; a < T.sl; a++) t1 = fma(-P[i1 * T.sl + a], x[a], t1);
+    }
+    if (T.sr > 0) {
+        const double* P = AR.P + T.pr;  // s_r x s_k
+        const double* x = AR.t + T.vr;
+        if (i0 < sk)
+            for (int a = 0; a < T.sr; a++) t0 = fma(-P[i0 * T.sr + a], x[a], t0);
+        if (i1 < sk)
+            for (int a = 0; a < T.sr; a++) t1 = fma(-P[i1 * T.sr + a], x[a], t1);
+    }
+    const double* Lk = AR.D + T.d;
+    for (int q = lane; q < sk * sk; q += 64) Ls[q] = Lk[q];
+    __syncthreads();
+    for (int j = sk - 1; j >= 0; j--) {
+        const double tj = j < 64 ? __shfl(t0, j) : __shfl(t1, j - 64);
+        const double xj = tj / Ls[j * sk + j];
+        if (i0 == j) t0 = xj;
+        else if (i0 < j) t0 = fma(-Ls[i0 * sk + j], xj, t0);
+        if (i1 == j) t1 = xj;
+        else if (i1 < j) t1 = fma(-Ls[i1 * sk + j], xj, t1);
+    }
+    double* x = C.x + T.v0;
+    if (i0 < sk) {
+        AR.t[T.v0 + i0] = t0;
+        if (mode == 0) {
+            x[i0] = t0;
+        } else {
+            const double xo = x[i0];
+            I.xprev[T.var0 + i0] = xo;
+            x[i0] = xo + t0;
+        }
+    }
+    if (i1 < sk) {
+        AR.t[T.v0 + i1] = t1;
+        if (mode == 0) {
+            x[i1] = t1;
+        } else {
+            const double xo = x[i1];
+            I.xprev[T.var0 + i1] = xo;
+            x[i1] = xo + t1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // workspace redirection (allocation-free solve): copies of a factor's instance
 // descriptor and front descriptors whose per-solve vectors point into a
 // caller-provided workspace
@@ -2711,6 +2961,8 @@ hipError_t set_kernel_attributes() {
     e = hipFuncSetAttribute((const void*)k_factor_queue, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void*)k_sweeps_queue, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)k_cr_factor, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)k_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
@@ -2764,6 +3016,24 @@ void launch_ipm_step(const InstDev* insts, const IpmCall& P, const WorkItem* nco
     k_ipm_alpha_fin<<<1, kBlock, 0, st>>>(insts, P);
     if (nn > 0) k_ipm_update_n<<<nn, kBlock, 0, st>>>(insts, P, ncols);
     if (nm > 0) k_ipm_update_m<<<nm, kBlock, 0, st>>>(insts, P, mrows);
+}
+void launch_fill_f64(double* p, double v, int64_t n, hipStream_t st) {
+    if (n > 0) k_fill_f64<<<blocks_for(n, kBlock), kBlock, 0, st>>>(p, v, n);
+}
+void launch_cr_scatter(const InstDev* insts, const CrArrays& A, const CrScatter* items, int64_t nitems,
+                       hipStream_t st) {
+    if (nitems > 0) k_cr_scatter<<<blocks_for(nitems, kBlock), kBlock, 0, st>>>(insts, A, items, nitems);
+}
+void launch_cr_factor(const InstDev* insts, const CrArrays& A, int task0, int ntask, size_t lds, hipStream_t st) {
+    if (ntask > 0) k_cr_factor<<<ntask, kBlock, lds, st>>>(insts, A, task0);
+}
+void launch_cr_fwd(const InstDev* insts, const CrArrays& A, int task0, int ntask, const Calls& C, int mode,
+                   hipStream_t st) {
+    if (ntask > 0) k_cr_fwd<<<ntask, 64, 0, st>>>(insts, A, task0, C, mode);
+}
+void launch_cr_bwd(const InstDev* insts, const CrArrays& A, int task0, int ntask, const Calls& C, int mode,
+                   hipStream_t st) {
+    if (ntask > 0) k_cr_bwd<<<ntask, 64, 0, st>>>(insts, A, task0, C, mode);
 }
 void launch_ws_redirect(const InstDev* src_inst, const FrontDesc* src_fd, int nf, const SolveWs& w, hipStream_t st) {
     k_ws_redirect<<<blocks_for(nf > 0 ? nf : 1, 256), 256, 0, st>>>(src_inst, src_fd, nf, w);

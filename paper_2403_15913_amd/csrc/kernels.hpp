@@ -192,4 +192,51 @@ void launch_ipm_r2(const InstDev* insts, const IpmCall& P, const WorkItem* mrows
 void launch_ipm_step(const InstDev* insts, const IpmCall& P, const WorkItem* ncols, int nn, const WorkItem* mrows,
                      int nm, hipStream_t st);
 
+// Stage-structured (block-tridiagonal) K factored by block cyclic reduction:
+// one task per stage, run at the level where the stage is eliminated.
+constexpr int kCrMaxStage = 80;  // widest stage the LDS buffers hold
+struct CrTask {
+    int inst;            // InstDev index (status, refinement records)
+    int sk, sl, sr;      // widths of the stage and of its active left / right neighbours (0: none)
+    int var0;            // first variable of the stage, instance numbering
+    int v0, vl, vr;      // first variables of the stage and the neighbours, concatenated numbering
+    int pull0, npull;    // its entries in the pull list
+    int64_t d;           // D_k, then L_k (s_k x s_k)                     [D]
+    int64_t kl;          // K(k,l) (s_k x s_l): E_{k-1} or a fill block     [C]
+    int64_t kr;          // K(r,k) (s_r x s_k): E_k or a fill block         [C]
+    int64_t pl, pr;      // L(l,k) (s_l x s_k), L(r,k) (s_r x s_k)          [P]
+    int64_t f;           // fill K(r,l) = -L(r,k) L(l,k)^T (s_r x s_l)      [C]
+    int64_t ul, ur;      // L(l,k) L(l,k)^T, L(r,k) L(r,k)^T (lower parts)  [U]
+};
+// one contribution to a stage from a neighbour eliminated at an earlier level
+struct CrPull {
+    int64_t u;           // update block subtracted from D_k (s_k x s_k)    [U]
+    int64_t p;           // the factor block L(k,i) (s_k x s_i)            [P]
+    int vi, si;          // y_i: first variable (concatenated), width
+};
+struct CrArrays {
+    double* D;           // diagonal blocks (column-major), L_k after the factor
+    double* C;           // couplings: the assembled E_k first, then the fill blocks
+    double* P;           // off-diagonal factor blocks
+    double* U;           // symmetric updates
+    double* t;           // solve work vector (concatenated numbering)
+    const CrTask* tasks;
+    const CrPull* pulls;
+};
+// an entry of the assembled K (kcsr, lower positions) and its place in D or C
+struct CrScatter {
+    int inst;            // InstDev index
+    int pos;             // position in the instance's kcsr
+    int64_t dst;         // >= 0: index into D; < 0: -dst - 1 into C
+};
+void launch_fill_f64(double* p, double v, int64_t n, hipStream_t st);
+void launch_cr_scatter(const InstDev* insts, const CrArrays& A, const CrScatter* items, int64_t nitems,
+                       hipStream_t st);
+void launch_cr_factor(const InstDev* insts, const CrArrays& A, int task0, int ntask, size_t lds, hipStream_t st);
+// mode 0: from b; mode 1 (refinement, skips stopped instances): from the residual, x += correction
+void launch_cr_fwd(const InstDev* insts, const CrArrays& A, int task0, int ntask, const Calls& C, int mode,
+                   hipStream_t st);
+void launch_cr_bwd(const InstDev* insts, const CrArrays& A, int task0, int ntask, const Calls& C, int mode,
+                   hipStream_t st);
+
 }  // namespace kkt

@@ -159,6 +159,13 @@ SIGNATURES = {
     "kkt_batch_set_schedule": (I32, [P, I32]),
     "kkt_batch_capture": (I32, [P, P, P, P, P, P, P, P, I32]),
     "kkt_batch_replay": (I32, [P, P, P]),
+    "kkt_stagewise_create": (I32, [I32, P, P, P, P]),
+    "kkt_stagewise_destroy": (None, [P]),
+    "kkt_stagewise_refactor": (I32, [P, P, P, P, P, P]),
+    "kkt_stagewise_status": (I32, [P, P, P]),
+    "kkt_stagewise_solve": (I32, [P, P, P, P, P, P]),
+    "kkt_stagewise_set_timing": (I32, [P, I32]),
+    "kkt_stagewise_read_timing": (I32, [P, P]),
     "kkt_server_opts_default": (None, [P]),
     "kkt_server_create": (I32, [P, P]),
     "kkt_server_register": (I32, [P, P, P]),
@@ -579,6 +586,83 @@ class Batch:
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
             lib().kkt_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# stage-structured solver (block cyclic reduction)
+# ---------------------------------------------------------------------------
+
+def kkt_stagewise_create(sym_handles, stage_ptrs):
+    count = len(sym_handles)
+    sps = [np.ascontiguousarray(sp, dtype=np.int32) for sp in stage_ptrs]
+    arr = (C.c_void_p * count)(*[h.value for h in sym_handles])
+    ptrs = (C.c_void_p * count)(*[sp.ctypes.data for sp in sps])
+    ns = np.array([len(sp) - 1 for sp in sps], dtype=np.int32)
+    h = C.c_void_p()
+    _err(lib().kkt_stagewise_create(count, arr, ptrs, _ptr_np(ns), C.byref(h)))
+    return h
+
+
+def kkt_stagewise_refactor(h, w_vals, j_vals, sigma_x, sigma_s, stream=None):
+    _err(lib().kkt_stagewise_refactor(h, _dptr(w_vals), _dptr(j_vals), _dptr(sigma_x), _dptr(sigma_s),
+                                      _stream(stream)))
+
+
+def kkt_stagewise_status(h, count):
+    st = np.zeros(count, dtype=np.int32)
+    bad = np.zeros(count, dtype=np.int32)
+    lib().kkt_stagewise_status(h, _ptr_np(st), _ptr_np(bad))
+    return st, bad
+
+
+def kkt_stagewise_solve(h, count, b, x, max_iter=10, tol=1e-14, info=True, stream=None):
+    ro = RefineOpts(max_iter, tol)
+    infos = (SolveInfo * count)()
+    st = lib().kkt_stagewise_solve(h, _dptr(b), _dptr(x), C.byref(ro), infos if info else None, _stream(stream))
+    if st not in (KKT_OK, 6):
+        _err(st)
+    return [i.as_dict() for i in infos] if info else None
+
+
+class Stagewise:
+    """Block-tridiagonal K of stage-structured patterns, factored by block cyclic reduction.
+
+    ``stage_ptrs[q]`` holds the stage starts of instance q (0 .. n). Values and
+    vectors are concatenated in instance order, as for :class:`Batch`.
+    """
+
+    def __init__(self, syms, stage_ptrs):
+        self.syms = list(syms)
+        self.count = len(self.syms)
+        self.h = kkt_stagewise_create([s.h for s in self.syms], stage_ptrs)
+
+    def refactor(self, w_vals, j_vals, sigma_x, sigma_s, stream=None):
+        kkt_stagewise_refactor(self.h, w_vals, j_vals, sigma_x, sigma_s, stream)
+
+    def solve(self, b, x, max_iter=10, tol=1e-14, info=True, stream=None):
+        return kkt_stagewise_solve(self.h, self.count, b, x, max_iter, tol, info, stream)
+
+    def status(self):
+        return kkt_stagewise_status(self.h, self.count)
+
+    def set_timing(self, enable=True):
+        _err(lib().kkt_stagewise_set_timing(self.h, 1 if enable else 0))
+
+    def read_timing(self) -> dict:
+        t = Timing()
+        _err(lib().kkt_stagewise_read_timing(self.h, C.byref(t)))
+        return t.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().kkt_stagewise_destroy(self.h)
             self.h = C.c_void_p()
 
     def __del__(self):

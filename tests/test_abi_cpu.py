@@ -174,3 +174,37 @@ def test_empty_and_tiny(kkt):
     assert st_["nsuper"] == 1 and st_["nnz_l"] == 1
     s = kkt.Symbolic(0, 0, np.array([0]), np.zeros(0), np.array([0]), np.zeros(0))
     assert s.stats()["nsuper"] == 0
+
+
+def test_stagewise_rejects_bad_stages(kkt):
+    """The stage-structured solver checks its stage ranges and the block
+    tridiagonal structure on the host, before any device call: INVALID_ARG
+    (1) for ranges that do not cover 0 .. n or hold an empty stage, PATTERN
+    (2) for a stage wider than 80 or a K position coupling stages two apart
+    (a split of each NMPC stage into states and controls puts the dynamics
+    rows x_{k+1} - A x_k - B u_k across three sub-stages)."""
+    import kktgen
+    pat = kktgen.nmpc_pattern(6, 8, 1)
+    s = kkt.Symbolic.from_pattern(pat)
+    st = pat.meta["stage"]
+
+    def code(sp):
+        try:
+            kkt.Stagewise([s], [np.asarray(sp, dtype=np.int32)])
+        except kkt.KKTError as e:
+            return e.status
+        return 0
+
+    assert code([0, 18, 36]) == 1                                  # does not end at n
+    assert code([0, 0, 54]) == 1                                   # empty stage
+    assert code([1, 54]) == 1                                      # does not start at 0
+    split = [0]
+    for k in range(6):
+        split += [k * st + 8, (k + 1) * st]
+    assert code(split) == 2                                        # states / controls split
+    wide = kkt.Symbolic.from_pattern(kktgen.nmpc_pattern(10, 8, 1))
+    try:
+        kkt.Stagewise([wide], [np.array([0, 90], dtype=np.int32)])  # one stage of 90
+        raise AssertionError("accepted a stage of 90")
+    except kkt.KKTError as e:
+        assert e.status == 2
