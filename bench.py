@@ -47,6 +47,7 @@ def parse():
                     help="pick ordering / leaf size by measurement (ignored when --ordering or --nd-leaf is set)")
     ap.add_argument("--hykkt", type=int, default=1, help="also time HyKKT (refactor + Schur CG) at paper scale")
     ap.add_argument("--ipm", type=int, default=1, help="also time the interior-point loop on a paper-scale QP")
+    ap.add_argument("--stagewise", type=int, default=1, help="also time the stage-structured solver (paper + batch)")
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched workload (0: skip)")
     ap.add_argument("--batch-ordering", type=int, default=2, help="batch ordering when not autotuned")
     ap.add_argument("--batch-nd-leaf", type=int, default=256, help="batch nested-dissection leaf when not autotuned")
@@ -168,6 +169,65 @@ def bench_batched(args, kkt, kktgen, torch, dev):
                 plain_pairs_per_s=round(pok / tp, 2), plain_ms=round(1e3 * tp, 3),
                 speedup=round((ok / tg) / max(pok / tp, 1e-12), 2), eta_max=float(etas.max()),
                 passing=f"{ok}/{count}", batched_equals_plain_bitwise=bool(same))
+
+
+def bench_stagewise(args, kkt, kktgen, torch, dev, pat, dvals, plain_ms, batch_eager_ms):
+    """The stage-structured solver (block cyclic reduction over the stages, section "Future Works") on
+    the paper-scale pattern and on the batched NMPC workload, beside the supernodal path's times."""
+    def T(a):
+        return torch.tensor(np.asarray(a), dtype=torch.float64, device=dev)
+
+    def run(W, steps, get, x):
+        def step(i):
+            d = get(i)
+            W.refactor(d["w"], d["j"], d["sx"], d["ss"])
+            return W.solve(d["b"], x)
+        for i in range(2):
+            step(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = [step(i) for i in range(steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        W.set_timing(True)
+        W.read_timing()
+        for i in range(steps):
+            step(i)
+        tm = W.read_timing()
+        W.set_timing(False)
+        etas = np.array([q["eta"] for inf in infos for q in inf])
+        return el / steps, etas, {p: round(tm[p]["ms"] / steps, 4) for p in tm if tm[p]["launches"]}, tm
+
+    out = {}
+    s = pat.meta["stage"]
+    W = kkt.Stagewise([kkt.Symbolic.from_pattern(pat)], [np.arange(0, pat.n + 1, s, dtype=np.int32)])
+    x = torch.zeros(pat.n, dtype=torch.float64, device=dev)
+    sec, etas, ph, tm = run(W, args.steps, lambda i: dvals[i % len(dvals)], x)
+    ok = int((etas <= ETA_GATE).sum())
+    out["paper"] = dict(ms_per_step=round(1e3 * sec, 4), pairs_per_s=round(ok / len(etas) / sec, 2),
+                        passing=f"{ok}/{len(etas)}", eta_max=float(etas.max()), phase_ms_per_step=ph,
+                        factor_launches=tm["factor"]["launches"] // args.steps,
+                        supernodal_ms_per_step=round(plain_ms, 4), speedup_vs_supernodal=round(plain_ms / (1e3 * sec), 3))
+    W.close()
+    if args.batch > 0:
+        shapes = kktgen.batch_shapes(args.batch)
+        pats = [kktgen.nmpc_pattern(*sh) for sh in shapes]
+        vals = [kktgen.nmpc_values(p, kktgen.rng_for(3, q, 1), 1e-6, 1e6) for q, p in enumerate(pats)]
+        cat = dict(w=T(np.concatenate([v.w_vals for v in vals])), j=T(np.concatenate([v.j_vals for v in vals])),
+                   sx=T(np.concatenate([v.sigma_x for v in vals])), ss=T(np.concatenate([v.sigma_s for v in vals])),
+                   b=T(np.concatenate([v.b for v in vals])))
+        W = kkt.Stagewise([kkt.Symbolic.from_pattern(p) for p in pats],
+                          [np.arange(0, p.n + 1, p.meta["stage"], dtype=np.int32) for p in pats])
+        xb = torch.zeros(sum(p.n for p in pats), dtype=torch.float64, device=dev)
+        sec, etas, ph, tm = run(W, 5, lambda i: cat, xb)
+        ok = int(sum(e <= ETA_GATE for e in etas[-len(pats):]))
+        out["batch"] = dict(instances=len(pats), ms_per_batch=round(1e3 * sec, 4), pairs_per_s=round(ok / sec, 2),
+                            passing=f"{ok}/{len(pats)}", eta_max=float(etas.max()), phase_ms_per_batch=ph,
+                            factor_launches=tm["factor"]["launches"] // 5,
+                            supernodal_eager_ms=batch_eager_ms,
+                            speedup_vs_supernodal_eager=round(batch_eager_ms / (1e3 * sec), 3) if batch_eager_ms else None)
+        W.close()
+    return out
 
 
 def bench_hykkt(args, kkt, kktgen, torch, dev, opts):
@@ -545,6 +605,10 @@ def main():
     ipm_leg = bench_ipm(args, kkt, kktgen, torch, dev, opts) if args.ipm and args.workload == "paper" else None
     batched = bench_batched(args, kkt, kktgen, torch, dev) if args.batch > 0 else None
     served = bench_served(args, kkt, kktgen, torch, dev) if args.serve_requests > 0 else None
+    stagewise = None
+    if args.stagewise and args.workload == "paper":
+        stagewise = bench_stagewise(args, kkt, kktgen, torch, dev, pat, dvals, ms_per_step,
+                                    batched["eager_levels_ms"] if batched else None)
 
     out = {
         "metric": "KKT refactor+solves/sec at residual <=1e-10 (batched vs plain); served p50/p99",
@@ -579,6 +643,7 @@ def main():
             "ipm": ipm_leg,
             "batched": batched,
             "served": served,
+            "stagewise": stagewise,
         },
     }
     print(json.dumps(out), flush=True)

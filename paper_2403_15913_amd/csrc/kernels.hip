@@ -2678,13 +2678,15 @@ __global__ __launch_bounds__(256) void k_ipm_update_m(const InstDev* __restrict_
 // active chain are eliminated together (one workgroup each), the rest form
 // the next, half as long, chain. This is a Cholesky factorization of K in
 // the cyclic-reduction order, with dense blocks: per eliminated stage k with
-// active neighbours l and r,
-//   L_k = chol(D_k - pending updates),  L(l,k) = K(l,k) L_k^{-T},
-//   L(r,k) = K(r,k) L_k^{-T},
+// active neighbours l and r, the front [D_k; K(l,k); K(r,k)] is factored,
+//   L_k = chol(D_k),  L(l,k) = K(l,k) L_k^{-T},  L(r,k) = K(r,k) L_k^{-T},
 // and it leaves to the next level the updates L(l,k) L(l,k)^T (to D_l),
-// L(r,k) L(r,k)^T (to D_r) and the fill K(r,l) = -L(r,k) L(l,k)^T. K itself
-// comes from the general assembly (kcsr), so its entries are the same bits as
-// the supernodal path's.
+// L(r,k) L(r,k)^T (to D_r) and the fill K(r,l) = -L(r,k) L(l,k)^T. Every
+// launch also runs one workgroup per stage that stays in the chain, which
+// applies the updates of the previous level to its D (so each stage takes at
+// most two updates, from the level just before). K itself comes from the
+// general assembly (kcsr), so its entries are the same bits as the
+// supernodal path's.
 // ---------------------------------------------------------------------------
 __global__ void k_fill_f64(double* __restrict__ p, double v, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2701,197 +2703,327 @@ __global__ __launch_bounds__(256) void k_cr_scatter(const InstDev* __restrict__ 
     else A.C[-it.dst - 1] = v;
 }
 
-// One row of X L^T = B (L lower, s x s in LDS, column-major): rows of X are
-// independent, each a forward substitution; dot-product form, in place.
-__device__ inline void cr_trsm_row(double* __restrict__ B, int ld, int a, const double* __restrict__ L, int s) {
-    for (int c = 0; c < s; c++) {
-        double acc = B[c * ld + a];
-        for (int c2 = 0; c2 < c; c2++) acc = fma(-B[c2 * ld + a], L[c2 * s + c], acc);
-        B[c * ld + a] = acc / L[c * s + c];
-    }
-}
-
-// One workgroup per eliminated stage of one level. LDS: A (s_k x s_k), then
-// P1 = K(l,k) -> L(l,k) (s_l x s_k), P2 = K(r,k) -> L(r,k) (s_r x s_k), all
-// column-major with the row count as leading dimension.
+// One workgroup per task of one level (NB: stage widths <= 16 NB). A task
+// eliminates its stage or applies the previous level's updates to a stage
+// that stays. Thread (ti, tc) = (tid % 16, tid / 16)
+// holds the front entries of rows ti + 16 a and columns tc + 16 b in
+// registers. The front's rows: [0, s_k) stage k, then l, then r; columns
+// [0, s_k). Right-looking Cholesky, one barrier per column: the owners of
+// column j publish it (unscaled) to LDS, every thread reads the pivot and
+// updates its entries right of j, the owners scale their part of column j.
+// Then the update block Q = P P^T of the rows below (P = [L(l,k); L(r,k)])
+// from LDS, register-tiled the same way (lower half only).
+template <int NB>
 __global__ __launch_bounds__(256) void k_cr_factor(const InstDev* __restrict__ insts, CrArrays AR, int task0) {
+    constexpr int RA = 3 * NB;  // row slots of the front (<= 48 NB rows)
+    constexpr int QA = 2 * NB;  // row / column slots of the update block (<= 32 NB)
+    constexpr int CB = 48 * NB;
     extern __shared__ __align__(16) double sh[];
     const CrTask T = AR.tasks[task0 + blockIdx.x];
-    const InstDev& I = insts[T.inst];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int sk = T.sk, sl = T.sl, sr = T.sr;
-    double* A = sh;
-    double* P1 = sh + sk * sk;
-    double* P2 = P1 + sl * sk;
-    // D_k minus the updates left by the stages eliminated before it (lower part)
-    const double* Dk = AR.D + T.d;
-    for (int q = tid; q < sk * sk; q += nt) {
-        const int i = q % sk, j = q / sk;
-        if (i < j) continue;
-        double v = Dk[q];
-        for (int u = 0; u < T.npull; u++) v -= AR.U[AR.pulls[T.pull0 + u].u + q];
-        A[q] = v;
-    }
-    // P1 = K(l,k) = K(k,l)^T from the s_k x s_l block (read in its order)
-    if (sl > 0) {
-        const double* S = AR.C + T.kl;
-        for (int q = tid; q < sl * sk; q += nt) {
-            const int b = q % sk, a = q / sk;
-            P1[b * sl + a] = S[q];
-        }
-    }
-    if (sr > 0) {
-        const double* S = AR.C + T.kr;
-        for (int q = tid; q < sr * sk; q += nt) P2[q] = S[q];
-    }
-    __syncthreads();
-    // Cholesky, column by column: the trailing update of step j uses column j
-    // unscaled (divided by the pivot), and column j is scaled in step j + 1,
-    // when no thread reads it; one barrier per column. A pivot that is not
-    // positive and finite is latched and replaced by 1.
-    double dprev = 1.0;
-    for (int j = 0; j < sk; j++) {
-        double d = A[j * sk + j];
-        if (!(d > 0.0) || !isfinite(d)) {
-            if (tid == 0) {
-                atomicMin(&I.status[1], T.var0 + j);
-                atomicMax(&I.status[0], KKT_ST_NOT_SPD);
+    const int tid = threadIdx.x, ti = tid & 15, tc = tid >> 4;
+    const int sk = T.sk;
+    const int64_t u0 = T.npull > 0 ? AR.pulls[T.pull0].u : -1;
+    const int64_t u1 = T.npull > 1 ? AR.pulls[T.pull0 + 1].u : -1;
+    double* Dk = AR.D + T.d;
+    if (!T.elim) {
+        // a stage that stays: D_k -= the previous level's updates (lower part)
+        double v[NB][NB], w0[NB][NB], w1[NB][NB];
+#pragma unroll
+        for (int a = 0; a < NB; a++)
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                const int i = ti + 16 * a, c = tc + 16 * b;
+                const bool ok = i < sk && c < sk && i >= c;
+                const int64_t idx = (int64_t)c * sk + i;
+                v[a][b] = ok ? Dk[idx] : 0.0;
+                w0[a][b] = ok && u0 >= 0 ? AR.U[u0 + idx] : 0.0;
+                w1[a][b] = ok && u1 >= 0 ? AR.U[u1 + idx] : 0.0;
             }
-            d = 1.0;
-        }
-        if (j > 0) {
-            const double ls = sqrt(dprev), inv = 1.0 / ls;
-            for (int i = j - 1 + tid; i < sk; i += nt)
-                A[(j - 1) * sk + i] = i == j - 1 ? ls : A[(j - 1) * sk + i] * inv;
-        }
-        const double inv_d = 1.0 / d;
-        const int tr = sk - j - 1;
-        for (int q = tid; q < tr * tr; q += nt) {
-            const int i = j + 1 + q % tr, c = j + 1 + q / tr;
-            if (i < c) continue;
-            A[c * sk + i] = fma(-(A[j * sk + i] * inv_d), A[j * sk + c], A[c * sk + i]);
-        }
-        dprev = d;
-        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < NB; a++)
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                const int i = ti + 16 * a, c = tc + 16 * b;
+                if (i < sk && c < sk && i >= c) Dk[(int64_t)c * sk + i] = (v[a][b] - w0[a][b]) - w1[a][b];
+            }
+        return;
     }
-    if (tid == 0) A[(sk - 1) * sk + sk - 1] = sqrt(dprev);
-    __syncthreads();
-    double* Lk = AR.D + T.d;
-    for (int q = tid; q < sk * sk; q += nt)
-        if (q % sk >= q / sk) Lk[q] = A[q];
-    // L(l,k) and L(r,k): rows in parallel (P1 rows on waves 0-1, P2 rows on 2-3)
-    if (tid < 128) {
-        if (tid < sl) cr_trsm_row(P1, sl, tid, A, sk);
-    } else if (tid - 128 < sr) {
-        cr_trsm_row(P2, sr, tid - 128, A, sk);
-    }
-    __syncthreads();
-    if (sl > 0)
-        for (int q = tid; q < sl * sk; q += nt) AR.P[T.pl + q] = P1[q];
-    if (sr > 0)
-        for (int q = tid; q < sr * sk; q += nt) AR.P[T.pr + q] = P2[q];
-    // updates for the next level: L(l,k) L(l,k)^T, L(r,k) L(r,k)^T (lower
-    // parts) and the fill -L(r,k) L(l,k)^T
-    const int nul = sl * sl, nur = sr * sr, nf = (sl > 0 && sr > 0) ? sr * sl : 0;
-    for (int q = tid; q < nul + nur + nf; q += nt) {
-        if (q < nul) {
-            const int a = q % sl, b = q / sl;
-            if (a < b) continue;
-            double acc = 0.0;
-            for (int c = 0; c < sk; c++) acc = fma(P1[c * sl + a], P1[c * sl + b], acc);
-            AR.U[T.ul + q] = acc;
-        } else if (q < nul + nur) {
-            const int q2 = q - nul, a = q2 % sr, b = q2 / sr;
-            if (a < b) continue;
-            double acc = 0.0;
-            for (int c = 0; c < sk; c++) acc = fma(P2[c * sr + a], P2[c * sr + b], acc);
-            AR.U[T.ur + q2] = acc;
-        } else {
-            const int q2 = q - nul - nur, a = q2 % sr, b = q2 / sr;
-            double acc = 0.0;
-            for (int c = 0; c < sk; c++) acc = fma(P2[c * sr + a], P1[c * sl + b], acc);
-            AR.C[T.f + q2] = -acc;
+    const InstDev& I = insts[T.inst];
+    const int sl = T.sl, sr = T.sr, np = sl + sr, mr = sk + np;
+    // all loads issued before any is used: the rows below the stage (one load
+    // each, K(l,k) = K(k,l)^T and K(r,k)), then D_k and its updates
+    double m[RA][NB];
+#pragma unroll
+    for (int a = 0; a < RA; a++)
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            const int i = ti + 16 * a, c = tc + 16 * b;
+            const bool below = c < sk && i >= sk && i < mr;
+            const int64_t at = i < sk + sl ? T.kl + (int64_t)(i - sk) * sk + c : T.kr + (int64_t)c * sr + (i - sk - sl);
+            m[a][b] = below ? AR.C[at] : 0.0;
         }
+    double dv[NB][NB], w0[NB][NB], w1[NB][NB];
+#pragma unroll
+    for (int a = 0; a < NB; a++)
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            const int i = ti + 16 * a, c = tc + 16 * b;
+            const bool ok = i < sk && c < sk && i >= c;
+            const int64_t idx = (int64_t)c * sk + i;
+            dv[a][b] = ok ? Dk[idx] : 0.0;
+            w0[a][b] = ok && u0 >= 0 ? AR.U[u0 + idx] : 0.0;
+            w1[a][b] = ok && u1 >= 0 ? AR.U[u1 + idx] : 0.0;
+        }
+#pragma unroll
+    for (int a = 0; a < NB; a++)
+#pragma unroll
+        for (int b = 0; b < NB; b++)
+            if (ti + 16 * a < sk) m[a][b] = (dv[a][b] - w0[a][b]) - w1[a][b];
+    // The update of step j touches entry (i, c) with i >= c > j. With i = ti +
+    // 16 a and c = tc + 16 b that is: slot pairs a > b always (given c > j),
+    // a == b when ti >= tc, a < b never; so the pairs are fixed at compile
+    // time and the rest is masked by selects (no branches in the loop).
+    double* colbuf = sh;  // two column buffers of CB rows
+    bool rowok[RA];
+#pragma unroll
+    for (int a = 0; a < RA; a++) rowok[a] = ti + 16 * a < mr;
+    const bool diag_ok = ti >= tc;
+    int par = 0;
+#pragma unroll
+    for (int jb = 0; jb < NB; jb++) {
+        for (int jj = 0; jj < 16; jj++) {
+            const int j = 16 * jb + jj;
+            if (j >= sk) break;
+            double* cb = colbuf + par * CB;
+            if (tc == jj) {
+#pragma unroll
+                for (int a = jb; a < RA; a++) cb[ti + 16 * a] = m[a][jb];
+            }
+            __syncthreads();
+            double d = cb[j];
+            if (!(d > 0.0) || !isfinite(d)) {
+                if (tid == 0) {
+                    atomicMin(&I.status[1], T.var0 + j);
+                    atomicMax(&I.status[0], KKT_ST_NOT_SPD);
+                }
+                d = 1.0;
+            }
+            const double ls = sqrt(d), inv_ls = 1.0 / ls, inv_d = inv_ls * inv_ls;
+            double cv[RA];
+#pragma unroll
+            for (int a = jb; a < RA; a++) {
+                const double v = cb[ti + 16 * a];
+                cv[a] = rowok[a] ? v : 0.0;
+            }
+            if (tc == jj) {
+#pragma unroll
+                for (int a = jb; a < RA; a++) {
+                    const int i = ti + 16 * a;
+                    m[a][jb] = i == j ? ls : (i > j ? m[a][jb] * inv_ls : m[a][jb]);
+                }
+            }
+#pragma unroll
+            for (int b = jb; b < NB; b++) {
+                const int c = tc + 16 * b;
+                const double v = cb[c];
+                const double lc = (c > j && c < sk) ? v * inv_d : 0.0;
+                m[b][b] = fma(-(diag_ok ? cv[b] : 0.0), lc, m[b][b]);
+#pragma unroll
+                for (int a = b + 1; a < RA; a++) m[a][b] = fma(-cv[a], lc, m[a][b]);
+            }
+            par ^= 1;
+        }
+    }
+    // L_k to D (lower), L(l,k) and L(r,k) to P, and P = the rows below into LDS
+    double* Pb = sh + 2 * CB;  // s_k columns of np rows
+#pragma unroll
+    for (int a = 0; a < RA; a++)
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            const int i = ti + 16 * a, c = tc + 16 * b;
+            if (c >= sk || i >= mr) continue;
+            if (i < sk) {
+                if (i >= c) Dk[(int64_t)c * sk + i] = m[a][b];
+            } else {
+                Pb[c * np + (i - sk)] = m[a][b];
+                if (i < sk + sl) AR.P[T.pl + (int64_t)c * sl + (i - sk)] = m[a][b];
+                else AR.P[T.pr + (int64_t)c * sr + (i - sk - sl)] = m[a][b];
+            }
+        }
+    if (np == 0) return;  // uniform: the last stage of its instance
+    __syncthreads();
+    // Q = P P^T, lower half: UL = Q(l, l), UR = Q(r, r), fill F = -Q(r, l)
+    double q[QA][QA];
+#pragma unroll
+    for (int a = 0; a < QA; a++)
+#pragma unroll
+        for (int b = 0; b <= a; b++) q[a][b] = 0.0;
+    // Pb holds s_k np entries plus 32 NB of padding, so these reads stay in
+    // bounds for every slot; slots past np are masked to zero
+    for (int c = 0; c < sk; c++) {
+        double pr[QA], pc[QA];
+#pragma unroll
+        for (int a = 0; a < QA; a++) {
+            const int p = ti + 16 * a;
+            const double v = Pb[c * np + p];
+            pr[a] = p < np ? v : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < QA; b++) {
+            const int p = tc + 16 * b;
+            const double v = Pb[c * np + p];
+            pc[b] = p < np ? v : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < QA; a++)
+#pragma unroll
+            for (int b = 0; b <= a; b++) q[a][b] = fma(pr[a], pc[b], q[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < QA; a++)
+#pragma unroll
+        for (int b = 0; b <= a; b++) {
+            const int p = ti + 16 * a, p2 = tc + 16 * b;
+            if (p >= np || p2 >= np || p < p2) continue;
+            if (p < sl) AR.U[T.ul + (int64_t)p2 * sl + p] = q[a][b];
+            else if (p2 >= sl) AR.U[T.ur + (int64_t)(p2 - sl) * sr + (p - sl)] = q[a][b];
+            else AR.C[T.f + (int64_t)p2 * sr + (p - sl)] = -q[a][b];
+        }
+}
+
+// Stages L_k (s_k x s_k, column-major) into LDS: every thread issues its
+// loads before the first store.
+__device__ inline void cr_stage_block(double* __restrict__ dst, const double* __restrict__ src, int n) {
+    constexpr int PER = (kCrMaxStage * kCrMaxStage + 255) / 256;
+    double v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        const int q = threadIdx.x + 256 * u;
+        v[u] = q < n ? src[q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        const int q = threadIdx.x + 256 * u;
+        if (q < n) dst[q] = v[u];
     }
 }
 
-// Forward solve L y = b, one wavefront per eliminated stage of one level:
-// t_k = b_k - (the L blocks of the earlier-eliminated neighbours times their
-// y), then y_k = L_k^{-1} t_k by substitution (lane i holds rows i and
-// i + 64, the pivot value is broadcast by a lane shuffle). mode 0 reads b,
-// mode 1 the refinement residual (skipping stopped instances).
-__global__ __launch_bounds__(64) void k_cr_fwd(const InstDev* __restrict__ insts, CrArrays AR, int task0, Calls C,
-                                               int mode) {
+// y (s_k rows) -= sum over columns c = g, g + 4, ... of P(:, c) x_c, P
+// column-major with s_k rows: this thread's part for rows r and r + 64
+__device__ inline void cr_matvec_part(const double* __restrict__ P, int rows, int cols,
+                                      const double* __restrict__ x, int r, int g, double& s0, double& s1) {
+    constexpr int U = kCrMaxStage / 4;
+    double xv[U], p0[U], p1[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        const int c = g + 4 * u;
+        xv[u] = c < cols ? x[c] : 0.0;
+        p0[u] = c < cols && r < rows ? P[(int64_t)c * rows + r] : 0.0;
+        p1[u] = c < cols && r + 64 < rows ? P[(int64_t)c * rows + r + 64] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        s0 = fma(p0[u], xv[u], s0);
+        s1 = fma(p1[u], xv[u], s1);
+    }
+}
+
+// this thread's part of (P^T x)(r), (P^T x)(r + 64) over rows a = g, g + 4,
+// ... of P (column-major, prow rows)
+__device__ inline void cr_matvec_t_part(const double* __restrict__ P, int prow, int cols,
+                                        const double* __restrict__ x, int r, int g, double& s0, double& s1) {
+    constexpr int U = kCrMaxStage / 4;
+    double xv[U], p0[U], p1[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        const int a = g + 4 * u;
+        xv[u] = a < prow ? x[a] : 0.0;
+        p0[u] = a < prow && r < cols ? P[(int64_t)r * prow + a] : 0.0;
+        p1[u] = a < prow && r + 64 < cols ? P[(int64_t)(r + 64) * prow + a] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        s0 = fma(p0[u], xv[u], s0);
+        s1 = fma(p1[u], xv[u], s1);
+    }
+}
+
+// Forward solve L y = b, per level: a task eliminating its stage takes t_k -
+// the previous level's contributions, then y_k = L_k^{-1} t_k by
+// substitution in wave 0 (lane i holds rows i and i + 64, the pivot value is
+// broadcast by a lane shuffle, the pivots' reciprocals come from LDS); a
+// task of a stage that stays only subtracts the contributions. On
+// level 0 t_k starts from b (mode 0) or the refinement residual (mode 1,
+// stopped instances skipped); later levels from t.
+__global__ __launch_bounds__(256) void k_cr_fwd(const InstDev* __restrict__ insts, CrArrays AR, int task0,
+                                                Calls C, int mode, int level0) {
     __shared__ double Ls[kCrMaxStage * kCrMaxStage];
+    __shared__ double red[4][128];
+    __shared__ double inv[kCrMaxStage];
     const CrTask T = AR.tasks[task0 + blockIdx.x];
     const InstDev& I = insts[T.inst];
     if (mode == 1 && I.rs->done) return;  // uniform per block
-    const int lane = threadIdx.x, sk = T.sk;
-    const int i0 = lane, i1 = lane + 64;
-    const double* src = mode == 0 ? C.b + T.v0 : I.r + T.var0;
-    double t0 = i0 < sk ? src[i0] : 0.0;
-    double t1 = i1 < sk ? src[i1] : 0.0;
+    const bool elim = T.elim != 0;
+    const int tid = threadIdx.x, r = tid & 63, g = tid >> 6, sk = T.sk;
+    double s0 = 0.0, s1 = 0.0;
     for (int u = 0; u < T.npull; u++) {
         const CrPull Pu = AR.pulls[T.pull0 + u];
-        const double* P = AR.P + Pu.p;  // s_k x s_i
-        const double* y = AR.t + Pu.vi;
-        for (int c = 0; c < Pu.si; c++) {
-            const double yc = y[c];
-            if (i0 < sk) t0 = fma(-P[c * sk + i0], yc, t0);
-            if (i1 < sk) t1 = fma(-P[c * sk + i1], yc, t1);
-        }
+        cr_matvec_part(AR.P + Pu.p, sk, Pu.si, AR.t + Pu.vi, r, g, s0, s1);
     }
-    const double* Lk = AR.D + T.d;
-    for (int q = lane; q < sk * sk; q += 64) Ls[q] = Lk[q];
+    red[g][r] = s0;
+    red[g][r + 64] = s1;
+    if (elim) {
+        cr_stage_block(Ls, AR.D + T.d, sk * sk);
+        if (tid < sk) inv[tid] = 1.0 / AR.D[T.d + (int64_t)tid * sk + tid];
+    }
     __syncthreads();
-    for (int j = 0; j < sk; j++) {
-        const double tj = j < 64 ? __shfl(t0, j) : __shfl(t1, j - 64);
-        const double yj = tj / Ls[j * sk + j];
-        if (i0 == j) t0 = yj;
-        else if (i0 > j && i0 < sk) t0 = fma(-Ls[j * sk + i0], yj, t0);
-        if (i1 == j) t1 = yj;
-        else if (i1 > j && i1 < sk) t1 = fma(-Ls[j * sk + i1], yj, t1);
+    if (tid >= 64) return;
+    const double* src = level0 ? (mode == 0 ? C.b + T.v0 : I.r + T.var0) : AR.t + T.v0;
+    const int i0 = r, i1 = r + 64;
+    double t0 = i0 < sk ? src[i0] - ((red[0][i0] + red[1][i0]) + (red[2][i0] + red[3][i0])) : 0.0;
+    double t1 = i1 < sk ? src[i1] - ((red[0][i1] + red[1][i1]) + (red[2][i1] + red[3][i1])) : 0.0;
+    if (elim) {
+        for (int j = 0; j < sk; j++) {
+            const double tj = j < 64 ? __shfl(t0, j) : __shfl(t1, j - 64);
+            const double yj = tj * inv[j];
+            if (i0 == j) t0 = yj;
+            else if (i0 > j && i0 < sk) t0 = fma(-Ls[j * sk + i0], yj, t0);
+            if (i1 == j) t1 = yj;
+            else if (i1 > j && i1 < sk) t1 = fma(-Ls[j * sk + i1], yj, t1);
+        }
     }
     if (i0 < sk) AR.t[T.v0 + i0] = t0;
     if (i1 < sk) AR.t[T.v0 + i1] = t1;
 }
 
-// Backward solve L^T x = y, levels in reverse: x_k = L_k^{-T} (y_k -
-// L(l,k)^T x_l - L(r,k)^T x_r), the neighbours being eliminated later (their
-// x already in t). x_k goes to t and to the output: mode 0 x = x_k; mode 1
-// xprev = x, x += x_k.
-__global__ __launch_bounds__(64) void k_cr_bwd(const InstDev* __restrict__ insts, CrArrays AR, int task0, Calls C,
-                                               int mode) {
+// Backward solve L^T x = y, levels in reverse, eliminated stages only: x_k =
+// L_k^{-T} (y_k - L(l,k)^T x_l - L(r,k)^T x_r), the neighbours being
+// eliminated later (their x already in t). x_k goes to t and to the output:
+// mode 0 x = x_k; mode 1 xprev = x, x += x_k.
+__global__ __launch_bounds__(256) void k_cr_bwd(const InstDev* __restrict__ insts, CrArrays AR, int task0, Calls C,
+                                                int mode) {
     __shared__ double Ls[kCrMaxStage * kCrMaxStage];
+    __shared__ double red[4][128];
+    __shared__ double inv[kCrMaxStage];
     const CrTask T = AR.tasks[task0 + blockIdx.x];
     const InstDev& I = insts[T.inst];
-    if (mode == 1 && I.rs->done) return;  // uniform per block
-    const int lane = threadIdx.x, sk = T.sk;
-    const int i0 = lane, i1 = lane + 64;
-    double t0 = i0 < sk ? AR.t[T.v0 + i0] : 0.0;
-    double t1 = i1 < sk ? AR.t[T.v0 + i1] : 0.0;
-    if (T.sl > 0) {
-        const double* P = AR.P + T.pl;  // s_l x s_k
-        const double* x = AR.t + T.vl;
-        if (i0 < sk)
-            for (int a = 0; a < T.sl; a++) t0 = fma(-P[i0 * T.sl + a], x[a], t0);
-        if (i1 < sk)
-            for (int a = 0; a < T.sl; a++) t1 = fma(-P[i1 * T.sl + a], x[a], t1);
-    }
-    if (T.sr > 0) {
-        const double* P = AR.P + T.pr;  // s_r x s_k
-        const double* x = AR.t + T.vr;
-        if (i0 < sk)
-            for (int a = 0; a < T.sr; a++) t0 = fma(-P[i0 * T.sr + a], x[a], t0);
-        if (i1 < sk)
-            for (int a = 0; a < T.sr; a++) t1 = fma(-P[i1 * T.sr + a], x[a], t1);
-    }
-    const double* Lk = AR.D + T.d;
-    for (int q = lane; q < sk * sk; q += 64) Ls[q] = Lk[q];
+    if (!T.elim || (mode == 1 && I.rs->done)) return;  // uniform per block
+    const int tid = threadIdx.x, r = tid & 63, g = tid >> 6, sk = T.sk;
+    double s0 = 0.0, s1 = 0.0;
+    if (T.sl > 0) cr_matvec_t_part(AR.P + T.pl, T.sl, sk, AR.t + T.vl, r, g, s0, s1);
+    if (T.sr > 0) cr_matvec_t_part(AR.P + T.pr, T.sr, sk, AR.t + T.vr, r, g, s0, s1);
+    red[g][r] = s0;
+    red[g][r + 64] = s1;
+    cr_stage_block(Ls, AR.D + T.d, sk * sk);
+    if (tid < sk) inv[tid] = 1.0 / AR.D[T.d + (int64_t)tid * sk + tid];
     __syncthreads();
+    if (tid >= 64) return;
+    const int i0 = r, i1 = r + 64;
+    double t0 = i0 < sk ? AR.t[T.v0 + i0] - ((red[0][i0] + red[1][i0]) + (red[2][i0] + red[3][i0])) : 0.0;
+    double t1 = i1 < sk ? AR.t[T.v0 + i1] - ((red[0][i1] + red[1][i1]) + (red[2][i1] + red[3][i1])) : 0.0;
     for (int j = sk - 1; j >= 0; j--) {
         const double tj = j < 64 ? __shfl(t0, j) : __shfl(t1, j - 64);
-        const double xj = tj / Ls[j * sk + j];
+        const double xj = tj * inv[j];
         if (i0 == j) t0 = xj;
         else if (i0 < j) t0 = fma(-Ls[i0 * sk + j], xj, t0);
         if (i1 == j) t1 = xj;
@@ -2962,7 +3094,15 @@ hipError_t set_kernel_attributes() {
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void*)k_sweeps_queue, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)k_cr_factor, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    e = hipFuncSetAttribute((const void*)k_cr_factor<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)k_cr_factor<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)k_cr_factor<3>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)k_cr_factor<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)k_cr_factor<5>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)k_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
@@ -3024,16 +3164,24 @@ void launch_cr_scatter(const InstDev* insts, const CrArrays& A, const CrScatter*
                        hipStream_t st) {
     if (nitems > 0) k_cr_scatter<<<blocks_for(nitems, kBlock), kBlock, 0, st>>>(insts, A, items, nitems);
 }
-void launch_cr_factor(const InstDev* insts, const CrArrays& A, int task0, int ntask, size_t lds, hipStream_t st) {
-    if (ntask > 0) k_cr_factor<<<ntask, kBlock, lds, st>>>(insts, A, task0);
+void launch_cr_factor(const InstDev* insts, const CrArrays& A, int task0, int ntask, int nb, size_t lds,
+                      hipStream_t st) {
+    if (ntask <= 0) return;
+    switch (nb) {
+        case 1: k_cr_factor<1><<<ntask, kBlock, lds, st>>>(insts, A, task0); break;
+        case 2: k_cr_factor<2><<<ntask, kBlock, lds, st>>>(insts, A, task0); break;
+        case 3: k_cr_factor<3><<<ntask, kBlock, lds, st>>>(insts, A, task0); break;
+        case 4: k_cr_factor<4><<<ntask, kBlock, lds, st>>>(insts, A, task0); break;
+        default: k_cr_factor<5><<<ntask, kBlock, lds, st>>>(insts, A, task0); break;
+    }
 }
 void launch_cr_fwd(const InstDev* insts, const CrArrays& A, int task0, int ntask, const Calls& C, int mode,
-                   hipStream_t st) {
-    if (ntask > 0) k_cr_fwd<<<ntask, 64, 0, st>>>(insts, A, task0, C, mode);
+                   int level0, hipStream_t st) {
+    if (ntask > 0) k_cr_fwd<<<ntask, 256, 0, st>>>(insts, A, task0, C, mode, level0);
 }
 void launch_cr_bwd(const InstDev* insts, const CrArrays& A, int task0, int ntask, const Calls& C, int mode,
                    hipStream_t st) {
-    if (ntask > 0) k_cr_bwd<<<ntask, 64, 0, st>>>(insts, A, task0, C, mode);
+    if (ntask > 0) k_cr_bwd<<<ntask, 256, 0, st>>>(insts, A, task0, C, mode);
 }
 void launch_ws_redirect(const InstDev* src_inst, const FrontDesc* src_fd, int nf, const SolveWs& w, hipStream_t st) {
     k_ws_redirect<<<blocks_for(nf > 0 ? nf : 1, 256), 256, 0, st>>>(src_inst, src_fd, nf, w);

@@ -197,10 +197,11 @@ void launch_ipm_step(const InstDev* insts, const IpmCall& P, const WorkItem* nco
 constexpr int kCrMaxStage = 80;  // widest stage the LDS buffers hold
 struct CrTask {
     int inst;            // InstDev index (status, refinement records)
+    int elim;            // 1: the stage is eliminated at this level; 0: it stays
     int sk, sl, sr;      // widths of the stage and of its active left / right neighbours (0: none)
     int var0;            // first variable of the stage, instance numbering
     int v0, vl, vr;      // first variables of the stage and the neighbours, concatenated numbering
-    int pull0, npull;    // its entries in the pull list
+    int pull0, npull;    // its entries in the pull list (at most two, from the previous level)
     int64_t d;           // D_k, then L_k (s_k x s_k)                     [D]
     int64_t kl;          // K(k,l) (s_k x s_l): E_{k-1} or a fill block     [C]
     int64_t kr;          // K(r,k) (s_r x s_k): E_k or a fill block         [C]
@@ -208,7 +209,7 @@ struct CrTask {
     int64_t f;           // fill K(r,l) = -L(r,k) L(l,k)^T (s_r x s_l)      [C]
     int64_t ul, ur;      // L(l,k) L(l,k)^T, L(r,k) L(r,k)^T (lower parts)  [U]
 };
-// one contribution to a stage from a neighbour eliminated at an earlier level
+// one contribution to a stage from a neighbour eliminated at the previous level
 struct CrPull {
     int64_t u;           // update block subtracted from D_k (s_k x s_k)    [U]
     int64_t p;           // the factor block L(k,i) (s_k x s_i)            [P]
@@ -232,10 +233,15 @@ struct CrScatter {
 void launch_fill_f64(double* p, double v, int64_t n, hipStream_t st);
 void launch_cr_scatter(const InstDev* insts, const CrArrays& A, const CrScatter* items, int64_t nitems,
                        hipStream_t st);
-void launch_cr_factor(const InstDev* insts, const CrArrays& A, int task0, int ntask, size_t lds, hipStream_t st);
-// mode 0: from b; mode 1 (refinement, skips stopped instances): from the residual, x += correction
+// one launch per level and width class (nb: widths <= 16 nb): each task
+// eliminates its stage or applies the previous level's updates to a stage
+// that stays (CrTask::elim)
+void launch_cr_factor(const InstDev* insts, const CrArrays& A, int task0, int ntask, int nb, size_t lds,
+                      hipStream_t st);
+// mode 0: from b; mode 1 (refinement, skips stopped instances): from the
+// residual, x += correction; level0: the first level (reads b or r)
 void launch_cr_fwd(const InstDev* insts, const CrArrays& A, int task0, int ntask, const Calls& C, int mode,
-                   hipStream_t st);
+                   int level0, hipStream_t st);
 void launch_cr_bwd(const InstDev* insts, const CrArrays& A, int task0, int ntask, const Calls& C, int mode,
                    hipStream_t st);
 

@@ -13,7 +13,9 @@
 // The result is the Cholesky factor of K in that elimination order, kept as
 // dense blocks: L_k for each stage and L(l,k), L(r,k) for its two active
 // neighbours at its level. Levels are ceil(log2 N) + 1, so the work of a
-// horizon of N stages runs in that many launches of up to N/2 workgroups.
+// horizon of N stages runs in that many launches (one workgroup per stage
+// still in the chain: the eliminated ones factor their front, the others
+// take the updates their eliminated neighbours left on the level before).
 // K is assembled by the general kernels (same bits as the supernodal path),
 // then scattered into the blocks; the refined solve reuses the residual and
 // stop-rule kernels.
@@ -29,14 +31,24 @@
 
 using namespace kkt;
 
+// the tasks of one level and width class (stage widths <= 16 nb), the
+// eliminating ones first
+struct CrClass {
+    int start = 0, nelim = 0, nkept = 0, nb = 1;
+    size_t lds = 0;     // factor LDS bytes
+};
+struct CrLevel {
+    int start = 0, end = 0;  // all tasks of the level
+    std::vector<CrClass> classes;
+};
+
 struct kkt_stagewise {
     Engine eng;                      // assembly, residuals, refinement records
     DevBuf store;                    // D, C, P, U, t, tasks, pulls, scatter list
     CrArrays A{};
     const CrScatter* dscat = nullptr;
     int64_t nscat = 0, nd = 0, ne = 0;
-    std::vector<int> lev_start;      // task ranges per level (levels + 1 entries)
-    std::vector<size_t> lev_lds;     // factor LDS bytes per level
+    std::vector<CrLevel> levels;
     int ninst = 0;
 };
 
@@ -58,40 +70,51 @@ kkt_status check_stages(const Symbolic& S, const int32_t* sp, int N, std::string
     return KKT_OK;
 }
 
-// Builds the elimination schedule of one instance: tasks grouped by level,
-// with their block offsets (running counters nd / nc / np / nu, shared by all
-// instances) and pull lists.
+// Builds the elimination schedule of one instance: per level, the tasks of
+// the stages eliminated there and of the stages that stay, with their block
+// offsets (running counters nc / np / nu, shared by all instances) and the
+// (at most two) contributions each takes from the previous level.
 void schedule_instance(int q, int n_off, const std::vector<int>& sp, const std::vector<int64_t>& dofs,
                        const std::vector<int64_t>& eofs, int64_t& nc, int64_t& np, int64_t& nu,
-                       std::vector<std::vector<StageTask>>& by_level) {
+                       std::vector<std::vector<StageTask>>& elim_lv, std::vector<std::vector<StageTask>>& kept_lv) {
     const int N = (int)sp.size() - 1;
     auto width = [&](int k) { return sp[k + 1] - sp[k]; };
-    std::vector<std::vector<CrPull>> pulls(N);
+    std::vector<std::vector<CrPull>> pulls(N);  // contributions from the previous level
     std::vector<int64_t> f_of(N, -1), ul_of(N, -1), ur_of(N, -1), pl_of(N, -1), pr_of(N, -1);
     std::vector<int> left_prev(N, -1), right_prev(N, -1);  // eliminated neighbours at the previous level
     std::vector<int> active(N);
     for (int k = 0; k < N; k++) active[k] = k;
+    auto base_task = [&](int k) {
+        StageTask st;
+        CrTask& T = st.t;
+        std::memset(&T, 0, sizeof(T));
+        T.inst = q;
+        T.sk = width(k);
+        T.var0 = sp[k];
+        T.v0 = n_off + sp[k];
+        T.d = dofs[k];
+        T.kl = T.kr = T.pl = T.pr = T.f = T.ul = T.ur = -1;
+        st.pulls = pulls[k];
+        T.npull = (int)st.pulls.size();
+        return st;
+    };
     for (int lev = 0; !active.empty(); lev++) {
         const int na = (int)active.size();
-        if ((int)by_level.size() <= lev) by_level.emplace_back();
+        if ((int)elim_lv.size() <= lev) {
+            elim_lv.emplace_back();
+            kept_lv.emplace_back();
+        }
         const int p0 = na == 1 ? 0 : 1;
         for (int p = p0; p < na; p += 2) {
             const int k = active[p];
             const int l = p > 0 ? active[p - 1] : -1;
             const int r = p + 1 < na ? active[p + 1] : -1;
-            StageTask st;
+            StageTask st = base_task(k);
             CrTask& T = st.t;
-            std::memset(&T, 0, sizeof(T));
-            T.inst = q;
-            T.sk = width(k);
             T.sl = l >= 0 ? width(l) : 0;
             T.sr = r >= 0 ? width(r) : 0;
-            T.var0 = sp[k];
-            T.v0 = n_off + sp[k];
             T.vl = l >= 0 ? n_off + sp[l] : 0;
             T.vr = r >= 0 ? n_off + sp[r] : 0;
-            T.d = dofs[k];
-            T.kl = T.kr = T.pl = T.pr = T.f = T.ul = T.ur = -1;
             if (l >= 0) T.kl = lev == 0 ? eofs[k - 1] : f_of[left_prev[k]];
             if (r >= 0) T.kr = lev == 0 ? eofs[k] : f_of[right_prev[k]];
             if (l >= 0) {
@@ -110,15 +133,17 @@ void schedule_instance(int q, int n_off, const std::vector<int>& sp, const std::
                 T.f = f_of[k] = nc;
                 nc += (int64_t)T.sr * T.sl;
             }
-            st.pulls = std::move(pulls[k]);
-            T.npull = (int)st.pulls.size();
-            by_level[lev].push_back(std::move(st));
+            elim_lv[lev].push_back(std::move(st));
         }
         if (na == 1) break;
-        // kept stages: the updates and factor blocks of their eliminated neighbours
+        // stages that stay: a task of their own (previous level's updates; on
+        // the first level the copy of the right-hand side), then the
+        // contributions of their eliminated neighbours for the next level
         std::vector<int> next;
+        for (int p = 0; p < na; p += 2) kept_lv[lev].push_back(base_task(active[p]));
         for (int p = 0; p < na; p += 2) {
             const int k = active[p];
+            pulls[k].clear();
             left_prev[k] = right_prev[k] = -1;
             if (p > 0) {
                 const int il = active[p - 1];  // k is its right neighbour
@@ -201,23 +226,39 @@ extern "C" kkt_status kkt_stagewise_create(int32_t count, const kkt_symbolic* co
     W->ninst = count;
     // the elimination schedule of every instance, tasks grouped by level
     int64_t nc = ne, np = 0, nu = 0;
-    std::vector<std::vector<StageTask>> by_level;
+    std::vector<std::vector<StageTask>> elim_lv, kept_lv;
     for (int q = 0; q < count; q++)
-        schedule_instance(q, (int)W->eng.n_ofs[q], stage_ptr[q], dofs[q], eofs[q], nc, np, nu, by_level);
+        schedule_instance(q, (int)W->eng.n_ofs[q], stage_ptr[q], dofs[q], eofs[q], nc, np, nu, elim_lv, kept_lv);
     std::vector<CrTask> htasks;
     std::vector<CrPull> hpulls;
-    W->lev_start.push_back(0);
-    for (auto& lv : by_level) {
-        size_t lds = 0;
-        for (auto& stt : lv) {
-            CrTask T = stt.t;
-            T.pull0 = (int)hpulls.size();
-            hpulls.insert(hpulls.end(), stt.pulls.begin(), stt.pulls.end());
-            lds = std::max(lds, (size_t)(T.sk * T.sk + (T.sl + T.sr) * T.sk) * sizeof(double));
-            htasks.push_back(T);
+    auto nb_of = [](const CrTask& T) { return (std::max({T.sk, T.sl, T.sr}) + 15) / 16; };
+    for (size_t lv = 0; lv < elim_lv.size(); lv++) {
+        CrLevel L;
+        L.start = (int)htasks.size();
+        for (int nb = 1; nb <= kCrMaxStage / 16; nb++) {
+            CrClass K;
+            K.start = (int)htasks.size();
+            K.nb = nb;
+            int front = 0;
+            for (int pass = 0; pass < 2; pass++)
+                for (auto& stt : pass == 0 ? elim_lv[lv] : kept_lv[lv]) {
+                    CrTask T = stt.t;
+                    if (nb_of(T) != nb) continue;
+                    T.elim = pass == 0;
+                    T.pull0 = (int)hpulls.size();
+                    hpulls.insert(hpulls.end(), stt.pulls.begin(), stt.pulls.end());
+                    front = std::max(front, (T.sl + T.sr) * T.sk);
+                    htasks.push_back(T);
+                    (pass == 0 ? K.nelim : K.nkept)++;
+                }
+            if (K.nelim + K.nkept == 0) continue;
+            // two column buffers of 48 nb rows, then the rows below the stage
+            // (s_k columns of s_l + s_r) with 32 nb entries of padding
+            K.lds = (size_t)(2 * 48 * nb + front + 32 * nb) * sizeof(double);
+            L.classes.push_back(K);
         }
-        W->lev_start.push_back((int)htasks.size());
-        W->lev_lds.push_back(lds);
+        L.end = (int)htasks.size();
+        W->levels.push_back(L);
     }
     const int64_t ntot = W->eng.n_ofs[count];
     // every block a task or pull touches lies inside its array
@@ -296,9 +337,11 @@ extern "C" kkt_status kkt_stagewise_refactor(kkt_stagewise* w, const double* w_v
     TL(KKT_PHASE_ASSEMBLE, launch_fill_f64(w->A.D, 0.0, w->nd, st));
     TL(KKT_PHASE_ASSEMBLE, launch_fill_f64(w->A.C, 0.0, w->ne, st));
     TL(KKT_PHASE_ASSEMBLE, launch_cr_scatter(E.di(), w->A, w->dscat, w->nscat, st));
-    for (size_t l = 0; l + 1 < w->lev_start.size(); l++)
-        TL(KKT_PHASE_FACTOR, launch_cr_factor(E.di(), w->A, w->lev_start[l], w->lev_start[l + 1] - w->lev_start[l],
-                                              w->lev_lds[l], st));
+    // the first level's stages that stay have nothing to update yet
+    for (size_t l = 0; l < w->levels.size(); l++)
+        for (const CrClass& K : w->levels[l].classes)
+            TL(KKT_PHASE_FACTOR,
+               launch_cr_factor(E.di(), w->A, K.start, K.nelim + (l ? K.nkept : 0), K.nb, K.lds, st));
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "stage-structured factor launch");
     E.factored = true;
@@ -328,13 +371,16 @@ namespace {
 void cr_sweeps(kkt_stagewise* w, const Calls& C, int mode, hipStream_t st) {
     Engine& E = w->eng;
     LaunchTimer& timer = E.timer;
-    const int nl = (int)w->lev_start.size() - 1;
-    for (int l = 0; l < nl; l++)
-        TL(KKT_PHASE_FWD, launch_cr_fwd(E.di(), w->A, w->lev_start[l], w->lev_start[l + 1] - w->lev_start[l], C,
-                                        mode, st));
-    for (int l = nl - 1; l >= 0; l--)
-        TL(KKT_PHASE_BWD, launch_cr_bwd(E.di(), w->A, w->lev_start[l], w->lev_start[l + 1] - w->lev_start[l], C,
-                                        mode, st));
+    const int nl = (int)w->levels.size();
+    for (int l = 0; l < nl; l++) {
+        const CrLevel& L = w->levels[l];
+        TL(KKT_PHASE_FWD, launch_cr_fwd(E.di(), w->A, L.start, L.end - L.start, C, mode, l == 0, st));
+    }
+    // the tasks of stages that stay return at once
+    for (int l = nl - 1; l >= 0; l--) {
+        const CrLevel& L = w->levels[l];
+        TL(KKT_PHASE_BWD, launch_cr_bwd(E.di(), w->A, L.start, L.end - L.start, C, mode, st));
+    }
 }
 }  // namespace
 
