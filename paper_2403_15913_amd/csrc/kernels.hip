@@ -2688,6 +2688,23 @@ __global__ __launch_bounds__(256) void k_ipm_update_m(const InstDev* __restrict_
 // general assembly (kcsr), so its entries are the same bits as the
 // supernodal path's.
 // ---------------------------------------------------------------------------
+// 1/d: the hardware reciprocal estimate refined by two steps of Newton's
+// iteration r <- r + r (1 - d r), each of which doubles the correct bits
+__device__ __forceinline__ double recip_f64(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
+
+// the value of v in lane `lane` (uniform), through the scalar unit
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __global__ void k_fill_f64(double* __restrict__ p, double v, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -2779,11 +2796,16 @@ __global__ __launch_bounds__(256) void k_cr_factor(const InstDev* __restrict__ i
 #pragma unroll
         for (int b = 0; b < NB; b++)
             if (ti + 16 * a < sk) m[a][b] = (dv[a][b] - w0[a][b]) - w1[a][b];
-    // The update of step j touches entry (i, c) with i >= c > j. With i = ti +
-    // 16 a and c = tc + 16 b that is: slot pairs a > b always (given c > j),
-    // a == b when ti >= tc, a < b never; so the pairs are fixed at compile
-    // time and the rest is masked by selects (no branches in the loop).
-    double* colbuf = sh;  // two column buffers of CB rows
+    // Right-looking Cholesky in unscaled form: step j subtracts M(i,j)
+    // M(c,j) / M(j,j) from M(i,c), and the columns are scaled by the square
+    // roots of their pivots (kept in LDS) in one pass at the end, which keeps
+    // the square roots off the per-column chain. The update of step j
+    // touches entry (i, c) with i >= c > j. With i = ti + 16 a and c = tc +
+    // 16 b that is: slot pairs a > b always (given c > j), a == b when ti >=
+    // tc, a < b never; so the pairs are fixed at compile time and the rest is
+    // masked by selects (no branches in the loop).
+    double* colbuf = sh;            // two column buffers of CB rows
+    double* piv = sh + 2 * CB;      // the pivots (after substitution of failed ones)
     bool rowok[RA];
 #pragma unroll
     for (int a = 0; a < RA; a++) rowok[a] = ti + 16 * a < mr;
@@ -2800,7 +2822,13 @@ __global__ __launch_bounds__(256) void k_cr_factor(const InstDev* __restrict__ i
                 for (int a = jb; a < RA; a++) cb[ti + 16 * a] = m[a][jb];
             }
             __syncthreads();
+            // every read of the column first, then the pivot
             double d = cb[j];
+            double cv[RA], cc[NB];
+#pragma unroll
+            for (int a = jb; a < RA; a++) cv[a] = cb[ti + 16 * a];
+#pragma unroll
+            for (int b = jb; b < NB; b++) cc[b] = cb[tc + 16 * b];
             if (!(d > 0.0) || !isfinite(d)) {
                 if (tid == 0) {
                     atomicMin(&I.status[1], T.var0 + j);
@@ -2808,25 +2836,14 @@ __global__ __launch_bounds__(256) void k_cr_factor(const InstDev* __restrict__ i
                 }
                 d = 1.0;
             }
-            const double ls = sqrt(d), inv_ls = 1.0 / ls, inv_d = inv_ls * inv_ls;
-            double cv[RA];
+            if (tid == 0) piv[j] = d;
+            const double inv_d = recip_f64(d);
 #pragma unroll
-            for (int a = jb; a < RA; a++) {
-                const double v = cb[ti + 16 * a];
-                cv[a] = rowok[a] ? v : 0.0;
-            }
-            if (tc == jj) {
-#pragma unroll
-                for (int a = jb; a < RA; a++) {
-                    const int i = ti + 16 * a;
-                    m[a][jb] = i == j ? ls : (i > j ? m[a][jb] * inv_ls : m[a][jb]);
-                }
-            }
+            for (int a = jb; a < RA; a++) cv[a] = rowok[a] ? cv[a] : 0.0;
 #pragma unroll
             for (int b = jb; b < NB; b++) {
                 const int c = tc + 16 * b;
-                const double v = cb[c];
-                const double lc = (c > j && c < sk) ? v * inv_d : 0.0;
+                const double lc = (c > j && c < sk) ? cc[b] * inv_d : 0.0;
                 m[b][b] = fma(-(diag_ok ? cv[b] : 0.0), lc, m[b][b]);
 #pragma unroll
                 for (int a = b + 1; a < RA; a++) m[a][b] = fma(-cv[a], lc, m[a][b]);
@@ -2834,8 +2851,21 @@ __global__ __launch_bounds__(256) void k_cr_factor(const InstDev* __restrict__ i
             par ^= 1;
         }
     }
+    __syncthreads();
+    // scale: L(i,c) = M(i,c) / sqrt(d_c) below the diagonal, sqrt(d_c) on it
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        const int c = tc + 16 * b;
+        const double dc = c < sk ? piv[c] : 1.0;
+        const double ls = sqrt(dc), inv_ls = recip_f64(ls);
+#pragma unroll
+        for (int a = 0; a < RA; a++) {
+            const int i = ti + 16 * a;
+            m[a][b] = i == c ? ls : m[a][b] * inv_ls;
+        }
+    }
     // L_k to D (lower), L(l,k) and L(r,k) to P, and P = the rows below into LDS
-    double* Pb = sh + 2 * CB;  // s_k columns of np rows
+    double* Pb = sh + 2 * CB + 16 * NB;  // s_k columns of np rows
 #pragma unroll
     for (int a = 0; a < RA; a++)
 #pragma unroll
@@ -2859,25 +2889,42 @@ __global__ __launch_bounds__(256) void k_cr_factor(const InstDev* __restrict__ i
 #pragma unroll
         for (int b = 0; b <= a; b++) q[a][b] = 0.0;
     // Pb holds s_k np entries plus 32 NB of padding, so these reads stay in
-    // bounds for every slot; slots past np are masked to zero
+    // bounds for every slot; slots past np are masked to zero. The reads of
+    // column c + 1 are issued before the products of column c.
+    bool pok[QA], qok[QA];
+#pragma unroll
+    for (int a = 0; a < QA; a++) {
+        pok[a] = ti + 16 * a < np;
+        qok[a] = tc + 16 * a < np;
+    }
+    double pr[QA], pc[QA];
+#pragma unroll
+    for (int a = 0; a < QA; a++) {
+        pr[a] = Pb[ti + 16 * a];
+        pc[a] = Pb[tc + 16 * a];
+    }
     for (int c = 0; c < sk; c++) {
-        double pr[QA], pc[QA];
+        const int cn = c + 1 < sk ? c + 1 : c;
+        double prn[QA], pcn[QA];
 #pragma unroll
         for (int a = 0; a < QA; a++) {
-            const int p = ti + 16 * a;
-            const double v = Pb[c * np + p];
-            pr[a] = p < np ? v : 0.0;
+            prn[a] = Pb[cn * np + ti + 16 * a];
+            pcn[a] = Pb[cn * np + tc + 16 * a];
         }
 #pragma unroll
-        for (int b = 0; b < QA; b++) {
-            const int p = tc + 16 * b;
-            const double v = Pb[c * np + p];
-            pc[b] = p < np ? v : 0.0;
+        for (int a = 0; a < QA; a++) {
+            pr[a] = pok[a] ? pr[a] : 0.0;
+            pc[a] = qok[a] ? pc[a] : 0.0;
         }
 #pragma unroll
         for (int a = 0; a < QA; a++)
 #pragma unroll
             for (int b = 0; b <= a; b++) q[a][b] = fma(pr[a], pc[b], q[a][b]);
+#pragma unroll
+        for (int a = 0; a < QA; a++) {
+            pr[a] = prn[a];
+            pc[a] = pcn[a];
+        }
     }
 #pragma unroll
     for (int a = 0; a < QA; a++)
@@ -2983,13 +3030,20 @@ __global__ __launch_bounds__(256) void k_cr_fwd(const InstDev* __restrict__ inst
     double t0 = i0 < sk ? src[i0] - ((red[0][i0] + red[1][i0]) + (red[2][i0] + red[3][i0])) : 0.0;
     double t1 = i1 < sk ? src[i1] - ((red[0][i1] + red[1][i1]) + (red[2][i1] + red[3][i1])) : 0.0;
     if (elim) {
+        // column j + 1 of L is read while step j runs (rows clamped into the
+        // block; their values are not used past s_k)
+        const int c0 = min(i0, sk - 1), c1 = min(i1, sk - 1);
+        double l0 = Ls[c0], l1 = Ls[c1], iv = inv[0];
         for (int j = 0; j < sk; j++) {
-            const double tj = j < 64 ? __shfl(t0, j) : __shfl(t1, j - 64);
-            const double yj = tj * inv[j];
-            if (i0 == j) t0 = yj;
-            else if (i0 > j && i0 < sk) t0 = fma(-Ls[j * sk + i0], yj, t0);
-            if (i1 == j) t1 = yj;
-            else if (i1 > j && i1 < sk) t1 = fma(-Ls[j * sk + i1], yj, t1);
+            const int jn = j + 1 < sk ? j + 1 : j;
+            const double l0n = Ls[jn * sk + c0], l1n = Ls[jn * sk + c1], ivn = inv[jn];
+            const double tj = j < 64 ? readlane_f64(t0, j) : readlane_f64(t1, j - 64);
+            const double yj = tj * iv;
+            t0 = i0 == j ? yj : (i0 > j ? fma(-l0, yj, t0) : t0);
+            t1 = i1 == j ? yj : (i1 > j ? fma(-l1, yj, t1) : t1);
+            l0 = l0n;
+            l1 = l1n;
+            iv = ivn;
         }
     }
     if (i0 < sk) AR.t[T.v0 + i0] = t0;
@@ -3021,13 +3075,19 @@ __global__ __launch_bounds__(256) void k_cr_bwd(const InstDev* __restrict__ inst
     const int i0 = r, i1 = r + 64;
     double t0 = i0 < sk ? AR.t[T.v0 + i0] - ((red[0][i0] + red[1][i0]) + (red[2][i0] + red[3][i0])) : 0.0;
     double t1 = i1 < sk ? AR.t[T.v0 + i1] - ((red[0][i1] + red[1][i1]) + (red[2][i1] + red[3][i1])) : 0.0;
+    // row j of L (entries L(j, i), i < j) is read one step ahead
+    const int c0 = min(i0, sk - 1), c1 = min(i1, sk - 1);
+    double l0 = Ls[c0 * sk + sk - 1], l1 = Ls[c1 * sk + sk - 1], iv = inv[sk - 1];
     for (int j = sk - 1; j >= 0; j--) {
-        const double tj = j < 64 ? __shfl(t0, j) : __shfl(t1, j - 64);
-        const double xj = tj * inv[j];
-        if (i0 == j) t0 = xj;
-        else if (i0 < j) t0 = fma(-Ls[i0 * sk + j], xj, t0);
-        if (i1 == j) t1 = xj;
-        else if (i1 < j) t1 = fma(-Ls[i1 * sk + j], xj, t1);
+        const int jn = j > 0 ? j - 1 : 0;
+        const double l0n = Ls[c0 * sk + jn], l1n = Ls[c1 * sk + jn], ivn = inv[jn];
+        const double tj = j < 64 ? readlane_f64(t0, j) : readlane_f64(t1, j - 64);
+        const double xj = tj * iv;
+        t0 = i0 == j ? xj : (i0 < j ? fma(-l0, xj, t0) : t0);
+        t1 = i1 == j ? xj : (i1 < j ? fma(-l1, xj, t1) : t1);
+        l0 = l0n;
+        l1 = l1n;
+        iv = ivn;
     }
     double* x = C.x + T.v0;
     if (i0 < sk) {

@@ -252,9 +252,10 @@ extern "C" kkt_status kkt_stagewise_create(int32_t count, const kkt_symbolic* co
                     (pass == 0 ? K.nelim : K.nkept)++;
                 }
             if (K.nelim + K.nkept == 0) continue;
-            // two column buffers of 48 nb rows, then the rows below the stage
-            // (s_k columns of s_l + s_r) with 32 nb entries of padding
-            K.lds = (size_t)(2 * 48 * nb + front + 32 * nb) * sizeof(double);
+            // two column buffers of 48 nb rows, 16 nb pivots, then the rows
+            // below the stage (s_k columns of s_l + s_r) with 32 nb entries
+            // of padding
+            K.lds = (size_t)(2 * 48 * nb + 16 * nb + front + 32 * nb) * sizeof(double);
             L.classes.push_back(K);
         }
         L.end = (int)htasks.size();
