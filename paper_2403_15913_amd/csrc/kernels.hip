@@ -2741,7 +2741,8 @@ __global__ __launch_bounds__(256) void k_cr_factor(const InstDev* __restrict__ i
     const int sk = T.sk;
     const int64_t u0 = T.npull > 0 ? AR.pulls[T.pull0].u : -1;
     const int64_t u1 = T.npull > 1 ? AR.pulls[T.pull0 + 1].u : -1;
-    double* Dk = AR.D + T.d;
+    const double* Dk = (T.from_work ? AR.L : AR.D) + T.d;
+    double* Lk = AR.L + T.d;
     if (!T.elim) {
         // a stage that stays: D_k -= the previous level's updates (lower part)
         double v[NB][NB], w0[NB][NB], w1[NB][NB];
@@ -2761,7 +2762,7 @@ __global__ __launch_bounds__(256) void k_cr_factor(const InstDev* __restrict__ i
 #pragma unroll
             for (int b = 0; b < NB; b++) {
                 const int i = ti + 16 * a, c = tc + 16 * b;
-                if (i < sk && c < sk && i >= c) Dk[(int64_t)c * sk + i] = (v[a][b] - w0[a][b]) - w1[a][b];
+                if (i < sk && c < sk && i >= c) Lk[(int64_t)c * sk + i] = (v[a][b] - w0[a][b]) - w1[a][b];
             }
         return;
     }
@@ -2864,7 +2865,7 @@ __global__ __launch_bounds__(256) void k_cr_factor(const InstDev* __restrict__ i
             m[a][b] = i == c ? ls : m[a][b] * inv_ls;
         }
     }
-    // L_k to D (lower), L(l,k) and L(r,k) to P, and P = the rows below into LDS
+    // L_k to L (lower), L(l,k) and L(r,k) to P, and P = the rows below into LDS
     double* Pb = sh + 2 * CB + 16 * NB;  // s_k columns of np rows
 #pragma unroll
     for (int a = 0; a < RA; a++)
@@ -2873,7 +2874,7 @@ __global__ __launch_bounds__(256) void k_cr_factor(const InstDev* __restrict__ i
             const int i = ti + 16 * a, c = tc + 16 * b;
             if (c >= sk || i >= mr) continue;
             if (i < sk) {
-                if (i >= c) Dk[(int64_t)c * sk + i] = m[a][b];
+                if (i >= c) Lk[(int64_t)c * sk + i] = m[a][b];
             } else {
                 Pb[c * np + (i - sk)] = m[a][b];
                 if (i < sk + sl) AR.P[T.pl + (int64_t)c * sl + (i - sk)] = m[a][b];
@@ -3020,8 +3021,8 @@ __global__ __launch_bounds__(256) void k_cr_fwd(const InstDev* __restrict__ inst
     red[g][r] = s0;
     red[g][r + 64] = s1;
     if (elim) {
-        cr_stage_block(Ls, AR.D + T.d, sk * sk);
-        if (tid < sk) inv[tid] = 1.0 / AR.D[T.d + (int64_t)tid * sk + tid];
+        cr_stage_block(Ls, AR.L + T.d, sk * sk);
+        if (tid < sk) inv[tid] = 1.0 / AR.L[T.d + (int64_t)tid * sk + tid];
     }
     __syncthreads();
     if (tid >= 64) return;
@@ -3068,8 +3069,8 @@ __global__ __launch_bounds__(256) void k_cr_bwd(const InstDev* __restrict__ inst
     if (T.sr > 0) cr_matvec_t_part(AR.P + T.pr, T.sr, sk, AR.t + T.vr, r, g, s0, s1);
     red[g][r] = s0;
     red[g][r + 64] = s1;
-    cr_stage_block(Ls, AR.D + T.d, sk * sk);
-    if (tid < sk) inv[tid] = 1.0 / AR.D[T.d + (int64_t)tid * sk + tid];
+    cr_stage_block(Ls, AR.L + T.d, sk * sk);
+    if (tid < sk) inv[tid] = 1.0 / AR.L[T.d + (int64_t)tid * sk + tid];
     __syncthreads();
     if (tid >= 64) return;
     const int i0 = r, i1 = r + 64;

@@ -198,11 +198,12 @@ constexpr int kCrMaxStage = 80;  // widest stage the LDS buffers hold
 struct CrTask {
     int inst;            // InstDev index (status, refinement records)
     int elim;            // 1: the stage is eliminated at this level; 0: it stays
+    int from_work;       // 1: the stage's block is read from the work copy in L (updated on an earlier level)
     int sk, sl, sr;      // widths of the stage and of its active left / right neighbours (0: none)
     int var0;            // first variable of the stage, instance numbering
     int v0, vl, vr;      // first variables of the stage and the neighbours, concatenated numbering
     int pull0, npull;    // its entries in the pull list (at most two, from the previous level)
-    int64_t d;           // D_k, then L_k (s_k x s_k)                     [D]
+    int64_t d;           // D_k (s_k x s_k), and its place in L: the updated copy, then L_k  [D, L]
     int64_t kl;          // K(k,l) (s_k x s_l): E_{k-1} or a fill block     [C]
     int64_t kr;          // K(r,k) (s_r x s_k): E_k or a fill block         [C]
     int64_t pl, pr;      // L(l,k) (s_l x s_k), L(r,k) (s_r x s_k)          [P]
@@ -216,7 +217,8 @@ struct CrPull {
     int vi, si;          // y_i: first variable (concatenated), width
 };
 struct CrArrays {
-    double* D;           // diagonal blocks (column-major), L_k after the factor
+    double* D;           // assembled diagonal blocks (column-major); only the scatter writes them
+    double* L;           // same layout: the updated blocks of stages that stay, then L_k
     double* C;           // couplings: the assembled E_k first, then the fill blocks
     double* P;           // off-diagonal factor blocks
     double* U;           // symmetric updates

@@ -44,7 +44,7 @@ struct CrLevel {
 
 struct kkt_stagewise {
     Engine eng;                      // assembly, residuals, refinement records
-    DevBuf store;                    // D, C, P, U, t, tasks, pulls, scatter list
+    DevBuf store;                    // D, L, C, P, U, t, tasks, pulls, scatter list
     CrArrays A{};
     const CrScatter* dscat = nullptr;
     int64_t nscat = 0, nd = 0, ne = 0;
@@ -245,6 +245,9 @@ extern "C" kkt_status kkt_stagewise_create(int32_t count, const kkt_symbolic* co
                     CrTask T = stt.t;
                     if (nb_of(T) != nb) continue;
                     T.elim = pass == 0;
+                    // from the third level on, the block has been updated by
+                    // the stage's own task on an earlier level
+                    T.from_work = lv >= 2;
                     T.pull0 = (int)hpulls.size();
                     hpulls.insert(hpulls.end(), stt.pulls.begin(), stt.pulls.end());
                     front = std::max(front, (T.sl + T.sr) * T.sk);
@@ -285,13 +288,15 @@ extern "C" kkt_status kkt_stagewise_create(int32_t count, const kkt_symbolic* co
         off += std::max<size_t>(bytes, 8);
         return at;
     };
-    const size_t oD = take(nd * 8), oC = take(nc * 8), oP = take(np * 8), oU = take(nu * 8), oT = take(ntot * 8);
+    const size_t oD = take(nd * 8), oL = take(nd * 8), oC = take(nc * 8), oP = take(np * 8), oU = take(nu * 8),
+                 oT = take(ntot * 8);
     const size_t oTk = take(htasks.size() * sizeof(CrTask)), oPl = take(hpulls.size() * sizeof(CrPull));
     const size_t oSc = take(hsc.size() * sizeof(CrScatter));
     hipError_t e = W->store.alloc(off);
     if (e != hipSuccess) return hip_fail(e, "stage-structured storage");
     char* base = (char*)W->store.p;
     W->A.D = (double*)(base + oD);
+    W->A.L = (double*)(base + oL);
     W->A.C = (double*)(base + oC);
     W->A.P = (double*)(base + oP);
     W->A.U = (double*)(base + oU);
@@ -312,6 +317,12 @@ extern "C" kkt_status kkt_stagewise_create(int32_t count, const kkt_symbolic* co
     for (auto& pc : pieces)
         if (pc.bytes && (e = hipMemcpy(base + pc.at, pc.src, pc.bytes, hipMemcpyHostToDevice)) != hipSuccess)
             return hip_fail(e, "stage-structured upload");
+    // the positions of D and E outside K's pattern stay zero: only the
+    // scatter writes these arrays afterwards
+    launch_fill_f64(W->A.D, 0.0, nd, nullptr);
+    launch_fill_f64(W->A.C, 0.0, ne, nullptr);
+    if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(nullptr)) != hipSuccess)
+        return hip_fail(e, "stage-structured initialisation");
     *out = W.release();
     return KKT_OK;
 }
@@ -335,8 +346,6 @@ extern "C" kkt_status kkt_stagewise_refactor(kkt_stagewise* w, const double* w_v
     const kkt_status ks = E.assemble(C, st);
     if (ks) return ks;
     LaunchTimer& timer = E.timer;
-    TL(KKT_PHASE_ASSEMBLE, launch_fill_f64(w->A.D, 0.0, w->nd, st));
-    TL(KKT_PHASE_ASSEMBLE, launch_fill_f64(w->A.C, 0.0, w->ne, st));
     TL(KKT_PHASE_ASSEMBLE, launch_cr_scatter(E.di(), w->A, w->dscat, w->nscat, st));
     // the first level's stages that stay have nothing to update yet
     for (size_t l = 0; l < w->levels.size(); l++)
