@@ -166,3 +166,28 @@ def test_stagewise_failure_isolated(kkt):
     x = torch.zeros(sum(p.n for p in pats), dtype=torch.float64, device="cuda")
     with pytest.raises(kkt.KKTError):
         W.solve(concat(vals, "b"), x)
+
+
+def test_stagewise_state_and_timing(kkt):
+    """A solve before any refactor is refused (STATE); per-launch timers
+    count one factor launch per level and width class, and the timed solve
+    equals the untimed one bit for bit."""
+    pat = kktgen.nmpc_pattern(9, 8, 1)
+    v = kktgen.nmpc_values(pat, kktgen.rng_for(0, 9, 0), 1e-2, 1e2)
+    W = kkt.Stagewise([kkt.Symbolic.from_pattern(pat)], [stages(pat)])
+    x = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(kkt.KKTError) as e:
+        W.solve(dev(v.b), x)
+    assert e.value.status == 3
+    xs = []
+    for timed in (False, True):
+        W.set_timing(timed)
+        W.refactor(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), dev(v.sigma_s))
+        x = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
+        W.solve(dev(v.b), x)
+        xs.append(x.cpu().numpy())
+    t = W.read_timing()
+    print("stagewise timing", t, flush=True)
+    assert t["factor"]["launches"] == 5          # 9 stages: 5 levels, one width class
+    assert t["fwd"]["launches"] >= 5 and t["bwd"]["launches"] >= 5
+    assert np.array_equal(xs[0], xs[1])
