@@ -600,6 +600,13 @@ def main():
                     frac=round(achieved / peak, 5), traffic=measured_traffic(dom, args, opts), traffic_unit="bytes/launch",
                     kernel=kernel, launches_per_step=tm[dom]["launches"] / args.steps,
                     avg_launch_us=1e3 * tm[dom]["ms"] / max(1, tm[dom]["launches"]))
+    if dom == "factor":
+        # the binding roof min(P_mfma, AI * BW), AI = exact flops over the minimal bytes (L written once
+        # and read once: 16 nnz(L))
+        ai = stats["flops_exact"] / (16.0 * stats["nnz_l_exact"])
+        binding = min(PEAK_FP64_TFLOPS, ai * PEAK_HBM_GBS / 1e3)
+        roofline.update(arithmetic_intensity=round(ai, 3), binding_roof=round(binding, 3),
+                        frac_of_binding_roof=round(achieved / binding, 5))
 
     hykkt = bench_hykkt(args, kkt, kktgen, torch, dev, opts) if args.hykkt and args.workload == "paper" else None
     ipm_leg = bench_ipm(args, kkt, kktgen, torch, dev, opts) if args.ipm and args.workload == "paper" else None
