@@ -127,6 +127,8 @@ hipError_t DevPattern::build(const Symbolic& S) {
     UP(b_relnp, rel_np, rel_np, int)
     UP(b_chptr, ch_ptr, ch_ptr, int)
     UP(b_chlist, ch_list, ch_list, int)
+    UP(b_pinvofs, pinv_ofs, pinv_ofs, int64_t)
+    UP(b_pinv, pinv, pinv, int)
     UP(b_ksnptr, k_snptr, k_snptr, int64_t)
     UP(b_kloc, k_loc, k_loc, int)
     UP(b_kw, k_w, k_w, int)
@@ -460,6 +462,7 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
             F.cU[j] = I.U + S.sn_uofs[ch];
             F.cV[j] = I.V + S.sn_vofs[ch];
             F.crl[j] = PD.rel + S.sn_rowofs[ch] + cc;
+            F.cinv[j] = PD.pinv + S.pinv_ofs[F.ch0 + j];
         }
         F.inst = q;
         F.id = k;

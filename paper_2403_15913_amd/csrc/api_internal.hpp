@@ -49,7 +49,7 @@ struct DevBuf {
 // Symbolic arrays of one pattern on the device.
 struct DevPattern {
     PatDev desc{};
-    DevBuf b_col0, b_ncol, b_nrow, b_rowofs, b_lofs, b_uofs, b_vofs, b_rows, b_rel, b_relnp, b_chptr, b_chlist,
+    DevBuf b_col0, b_ncol, b_nrow, b_rowofs, b_lofs, b_uofs, b_vofs, b_rows, b_rel, b_relnp, b_chptr, b_chlist, b_pinvofs, b_pinv,
         b_ksnptr, b_kloc, b_kw, b_kdiag, b_kpptr, b_pa, b_pb, b_jrow, b_perm, b_iperm, b_spptr, b_kcsr, b_spcol,
         b_jptr, b_jcol, b_jtptr, b_jte, b_jtrow, b_jtpptr, b_jtprow, b_jtpe, b_jcolp;
     hipError_t build(const Symbolic& S);

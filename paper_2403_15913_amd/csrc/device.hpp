@@ -29,6 +29,8 @@ struct PatDev {
     const int* rel_np;
     const int* ch_ptr;
     const int* ch_list;
+    const int64_t* pinv_ofs;  // per ch_list entry
+    const int* pinv;          // parent update row -> child update row, or -1
     const int64_t* k_snptr;
     const int* k_loc;
     const int* k_w;
@@ -147,6 +149,7 @@ struct FrontDesc {
     const double* cU[2];    // first two children: update matrices,
     const double* cV[2];    //   update vectors,
     const int* crl[2];      //   relative rows of their update parts,
+    const int* cinv[2];     //   inverse maps (this front's update row -> theirs, or -1),
     int cuc[2], cnb[2];     //   update sizes, and rows mapping into this front's columns
     int r, c, col0, nk;     // rows, columns, first column, entries of K
     int nch, ch0, inst, id; // children, first child in ch_list, instance, supernode

@@ -815,121 +815,89 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const FrontDesc& 
     // panel -> HBM: same layout, contiguous 16-byte stores
     copy_vec(F.L, P, even_up(ld * c), tid, nt);
     if (u == 0 || !fused_update) return;
-    // update matrix U = -L21 L21^T (lower part) on the matrix cores
+    // Update matrix U = -L21 L21^T (lower part) on the matrix cores, with
+    // the children's entries that pass through to it: each lane's places
+    // (a, b) of a tile find a child's entry through the child's inverse row
+    // map (this front's update row -> the child's, or -1), and the entries are
+    // added child by child in child order, the same additions in the same
+    // order as the strip kernel's read-modify-write, with one store per
+    // place. The first two children's values are read before the tile's
+    // matrix-core steps (indices clamped into range, so no load is
+    // predicated); further children are gathered after them.
     double* __restrict__ Us = F.U;
     const int nbu = (u + 15) >> 4;
     const int ntu = nbu * (nbu + 1) / 2;
     const int K4 = (c + 3) & ~3;
+    struct PassChild {
+        const double* Uc;
+        const int* inv;
+        int uc;
+    };
+    auto pass_child = [&](const int k) {
+        PassChild C;
+        if (k < 2) {
+            C.Uc = k ? F.cU[1] : F.cU[0];
+            C.inv = k ? F.cinv[1] : F.cinv[0];
+            C.uc = k ? F.cuc[1] : F.cuc[0];
+        } else {
+            const int ch = __builtin_amdgcn_readfirstlane(chl[ch0 + k]);
+            C.Uc = Ubase + sn_uofs[ch];
+            C.inv = T.pinv + T.pinv_ofs[ch0 + k];
+            C.uc = __builtin_amdgcn_readfirstlane(sn_nrow[ch]) - __builtin_amdgcn_readfirstlane(sn_ncol[ch]);
+        }
+        return C;
+    };
+    // this lane's four values of child C at rows a0 + 4e, column b (lower
+    // places of this front's update matrix only)
+    auto pass_gather = [&](const PassChild& C, const int a0, const int b, double* v, bool* in) {
+        const int ib = C.inv[min(b, u - 1)];
+        int ia[4];
+#pragma unroll
+        for (int e = 0; e < 4; e++) ia[e] = C.inv[min(a0 + 4 * e, u - 1)];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int a = a0 + 4 * e;
+            in[e] = a < u && b <= a && ia[e] >= 0 && ib >= 0;
+            v[e] = C.Uc[(int64_t)max(ib, 0) * C.uc + max(ia[e], 0)];
+        }
+    };
+    PassChild P0 = {}, P1 = {};
+    if (nch > 0) P0 = pass_child(0);
+    if (nch > 1) P1 = pass_child(1);
     for (int t = wave; t < ntu; t += nwave) {
         int ti, tj;
         tri_tile(t, 0, nbu, ti, tj);
-        const d4 acc = tile_abt(P, ld, c + (ti << 4), c + (tj << 4), 0, K4, r, lane);
         const int b = (tj << 4) + (lane & 15);
+        const int a0 = (ti << 4) + (lane >> 4);
+        double v0[4] = {0.0, 0.0, 0.0, 0.0}, v1[4] = {0.0, 0.0, 0.0, 0.0};
+        bool in0[4] = {false, false, false, false}, in1[4] = {false, false, false, false};
+        if (nch > 0) pass_gather(P0, a0, b, v0, in0);
+        if (nch > 1) pass_gather(P1, a0, b, v1, in1);
+        const d4 acc = tile_abt(P, ld, c + (ti << 4), c + (tj << 4), 0, K4, r, lane);
+        double w[4];
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            const int a = (ti << 4) + 4 * e + (lane >> 4);
-            if (a < u && b <= a) Us[(int64_t)b * u + a] = -acc[e];
+            w[e] = -acc[e];
+            if (in0[e]) w[e] += v0[e];
+            if (in1[e]) w[e] += v1[e];
+        }
+        for (int k = 2; k < nch; k++) {
+            double vk[4];
+            bool ink[4];
+            pass_gather(pass_child(k), a0, b, vk, ink);
+#pragma unroll
+            for (int e = 0; e < 4; e++)
+                if (ink[e]) w[e] += vk[e];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int a = a0 + 4 * e;
+            if (a < u && b <= a) Us[(int64_t)b * u + a] = w[e];
         }
     }
+    // every wave is done with the panel in LDS and with its stores before
+    // the caller reuses the LDS or publishes the front
     __syncthreads();
-    // Children's entries that pass through to the update matrix, child by
-    // child (two children can add into the same entry), in batches of PT
-    // entries per thread. Every index is clamped into [0, tot) and entries
-    // that are not kept address a valid place of U_s (the column's
-    // diagonal: rows below nb map into the front's own columns and have no
-    // place in U_s), so all loads are unpredicated. The next batch's child
-    // values and relative indices are loaded before the current batch's
-    // read-modify-write of U_s, so only that one round trip is exposed.
-    constexpr int PT = 8;
-    struct PBatch {
-        double v[PT];
-        int ra[PT], rb[PT];
-        unsigned keep;
-    };
-    auto pt_count = [&](const Child& C) { return ((C.uc - C.nb) * C.uc + PT * nt - 1) / (PT * nt); };
-    auto pt_load = [&](const Child& C, const int bi, PBatch& B) {
-        const int uc = C.uc, nb = C.nb, tot = (uc - nb) * uc;
-        const int64_t base = (int64_t)nb * uc;
-        const int b0 = tid + bi * PT * nt;
-        const int db = nt / uc, da = nt - db * uc;
-        int bq = b0 / uc, aq = b0 - bq * uc;
-        B.keep = 0;
-#pragma unroll
-        for (int k = 0; k < PT; k++) {
-            const int q0 = b0 + k * nt;
-            const int qq = min(q0, tot - 1);
-            const int bcol = min(nb + bq, uc - 1);
-            const bool kp = q0 < tot && aq >= nb + bq;
-            B.keep |= kp ? 1u << k : 0u;
-            const int arow = kp ? aq : bcol;
-            B.v[k] = C.Uc[base + qq];
-            B.ra[k] = C.rl[arow];
-            B.rb[k] = C.rl[bcol];
-            aq += da;
-            bq += db;
-            if (aq >= uc) {
-                aq -= uc;
-                bq++;
-            }
-        }
-    };
-    auto pt_apply = [&](PBatch& B) {
-        double cur[PT];
-        int dst[PT];
-#pragma unroll
-        for (int k = 0; k < PT; k++) {
-            pin(B.ra[k]);
-            pin(B.rb[k]);
-        }
-#pragma unroll
-        for (int k = 0; k < PT; k++) {
-            dst[k] = (B.rb[k] - c) * u + (B.ra[k] - c);
-            cur[k] = Us[dst[k]];
-        }
-#pragma unroll
-        for (int k = 0; k < PT; k++) {
-            pin(B.v[k]);
-            pin(cur[k]);
-        }
-#pragma unroll
-        for (int k = 0; k < PT; k++)
-            if ((B.keep >> k) & 1u) Us[dst[k]] = cur[k] + B.v[k];
-    };
-    {
-        int q = 0, bi = 0, nbq = 0;
-        Child Cq = {};
-        for (; q < nch; q++) {
-            Cq = child_at(q);
-            if ((nbq = pt_count(Cq)) > 0) break;
-        }
-        if (q < nch) {
-            PBatch B0, B1;
-            pt_load(Cq, 0, B0);
-            for (;;) {
-                // the next batch: this child's, else the next child's first
-                int q2 = q, bi2 = bi + 1, nb2 = nbq;
-                Child C2 = Cq;
-                if (bi2 >= nbq) {
-                    bi2 = 0;
-                    for (q2 = q + 1; q2 < nch; q2++) {
-                        C2 = child_at(q2);
-                        if ((nb2 = pt_count(C2)) > 0) break;
-                    }
-                }
-                const bool more = q2 < nch;
-                if (more) pt_load(C2, bi2, B1);
-                pt_apply(B0);
-                if (!more) break;
-                if (q2 != q) __syncthreads();  // the previous child's updates first
-                B0 = B1;
-                q = q2;
-                bi = bi2;
-                nbq = nb2;
-                Cq = C2;
-            }
-        }
-        __syncthreads();
-    }
 }
 
 __global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __restrict__ insts,

@@ -561,6 +561,25 @@ int analyze(int n, int m, const int32_t* wp, const int32_t* wi, const int32_t* j
         }
     }
 
+    // inverse maps: for the child at ch_list position q of front p, the
+    // update row of the child that lands on each update row of p (or -1), so
+    // the entries a child passes through to p's update matrix can be
+    // gathered where p's update matrix is formed
+    S.pinv_ofs.assign(S.ch_list.size() + 1, 0);
+    for (int p = 0; p < ns; p++)
+        for (int q = S.ch_ptr[p]; q < S.ch_ptr[p + 1]; q++)
+            S.pinv_ofs[q + 1] = S.pinv_ofs[q] + (S.sn_nrow[p] - S.sn_ncol[p]);
+    S.pinv.assign(S.pinv_ofs.back(), -1);
+    for (int p = 0; p < ns; p++)
+        for (int q = S.ch_ptr[p]; q < S.ch_ptr[p + 1]; q++) {
+            const int s = S.ch_list[q], cs = S.sn_ncol[s], us = S.sn_nrow[s] - cs, cp = S.sn_ncol[p];
+            for (int k = S.rel_np[s]; k < us; k++) {
+                const int a = S.rel[S.sn_rowofs[s] + cs + k] - cp;
+                if (a < 0 || a >= S.sn_nrow[p] - cp) { err = "internal: pass-through row outside the parent's update"; return ST_INVALID; }
+                S.pinv[S.pinv_ofs[q] + a] = k;
+            }
+        }
+
     // storage offsets and statistics
     S.sn_lofs.assign(ns + 1, 0);
     S.sn_uofs.assign(ns + 1, 0);

@@ -38,6 +38,8 @@ struct Symbolic {
     std::vector<int> rel;                  // rel[rowofs[s]+ncol+a]: local row of update row a in the parent front
     std::vector<int> rel_np;               // update rows of s that fall in the parent's own columns
     std::vector<int> ch_ptr, ch_list;      // children, ascending
+    std::vector<int64_t> pinv_ofs;         // per ch_list entry: its inverse map in pinv
+    std::vector<int> pinv;                 // child's inverse map: parent update row -> child update row, or -1
     std::vector<int> lvl_ptr, lvl_list;    // supernodes grouped by tree level (leaves first)
     int nlevels = 0;
     int64_t lsize = 0, usize = 0, vsize = 0;
