@@ -222,7 +222,6 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     lds_factor = lds_solve = 0;
     int nlev = 0;
     size_t nsn = 0, nnb = 0, nmb = 0, nkb = 0, nup = 0, njb = 0;
-    int max_rows = 0;
     // entries of K with long product lists, assembled 16 lanes per entry
     std::vector<WorkItem> hv;
     for (int q = 0; q < ninst; q++) {
@@ -244,7 +243,6 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         for (int k = 0; k < S.ns; k++) {
             lds_factor = std::max(lds_factor, (size_t)factor_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]));
             lds_solve = std::max(lds_solve, (size_t)solve_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]));
-            max_rows = std::max(max_rows, S.sn_nrow[k]);
             nup += (size_t)(S.sn_nrow[k] - S.sn_ncol[k] + 15) / 16;
         }
         nlev = std::max(nlev, S.nlevels);
@@ -303,7 +301,6 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     dep_nchild = cv.take<int>(nsn);
     dep_ctr = cv.take<int>(3 * nsn + 2);
     upitems = cv.take<StripItem>(nup);
-    split_update = max_rows <= kUpdMaxRows;
     stage = Staging{};
     if (staging) {
         stage.w = cv.take<double>(w_ofs[ninst]);

@@ -951,7 +951,6 @@ constexpr int kUpdThreads = 256;
 __global__ __launch_bounds__(kUpdThreads) void k_update(const InstDev* __restrict__ insts,
                                                        const FrontDesc* __restrict__ fds,
                                                        const StripItem* __restrict__ items) {
-    __shared__ int srel[kUpdMaxRows];
     const StripItem it = items[xcd_block()];
     const FrontDesc& F = fds[it.item];
     const InstDev& I = insts[F.inst];
@@ -962,90 +961,64 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(const InstDev* __restric
     const double* __restrict__ Lp = F.L;
     double* __restrict__ Us = F.U;
     const int tj = it.strip, nbu = (u + 15) >> 4;
-    for (int t = wave; t < nbu - tj; t += nwave) {
-        const int ti = tj + t;
-        const d4 acc = tile_abt_g(Lp, ld, c + (ti << 4), c + (tj << 4), c, r, lane);
-        const int b = (tj << 4) + (lane & 15);
+    const int nch = F.nch;
+    // the children's pass-through entries of each tile place, through their
+    // inverse row maps, added in child order before the one store (the same
+    // additions in the same order as the front kernel's epilogue)
+    auto child_vals = [&](const int k, const int a0, const int b, double* v, bool* in) {
+        const double* Uc;
+        const int* inv;
+        int uc;
+        if (k < 2) {
+            Uc = k ? F.cU[1] : F.cU[0];
+            inv = k ? F.cinv[1] : F.cinv[0];
+            uc = k ? F.cuc[1] : F.cuc[0];
+        } else {
+            const int ch = __builtin_amdgcn_readfirstlane(T.ch_list[F.ch0 + k]);
+            Uc = I.U + T.sn_uofs[ch];
+            inv = T.pinv + T.pinv_ofs[F.ch0 + k];
+            uc = __builtin_amdgcn_readfirstlane(T.sn_nrow[ch]) - __builtin_amdgcn_readfirstlane(T.sn_ncol[ch]);
+        }
+        const int ib = inv[min(b, u - 1)];
+        int ia[4];
+#pragma unroll
+        for (int e = 0; e < 4; e++) ia[e] = inv[min(a0 + 4 * e, u - 1)];
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            const int a = (ti << 4) + 4 * e + (lane >> 4);
-            if (a < u && b <= a) Us[(int64_t)b * u + a] = -acc[e];
+            const int a = a0 + 4 * e;
+            in[e] = a < u && b <= a && ia[e] >= 0 && ib >= 0;
+            v[e] = Uc[(int64_t)max(ib, 0) * uc + max(ia[e], 0)];
         }
-    }
-    __syncthreads();
-    const int b0 = tj << 4, b1 = min(b0 + 16, u);
-    for (int q = 0; q < F.nch; q++) {
-        // the first two children from the front descriptor
-        int uc, nb;
-        const double* __restrict__ Uc;
-        const int* __restrict__ rl;
-        if (q < 2) {
-            uc = q ? F.cuc[1] : F.cuc[0];
-            nb = q ? F.cnb[1] : F.cnb[0];
-            Uc = q ? F.cU[1] : F.cU[0];
-            rl = q ? F.crl[1] : F.crl[0];
-        } else {
-            const int ch = __builtin_amdgcn_readfirstlane(T.ch_list[F.ch0 + q]);
-            const int cc = __builtin_amdgcn_readfirstlane(T.sn_ncol[ch]);
-            uc = __builtin_amdgcn_readfirstlane(T.sn_nrow[ch]) - cc;
-            nb = __builtin_amdgcn_readfirstlane(T.rel_np[ch]);
-            Uc = I.U + T.sn_uofs[ch];
-            rl = T.rel + T.sn_rowofs[ch] + cc;
-        }
-        for (int a = tid; a < uc; a += nt) srel[a] = rl[a] - c;
-        __syncthreads();
-        // child columns nb <= b < uc whose target column lies in [b0, b1):
-        // a contiguous range, since the relative indices increase
-        int blo = nb, bhi;
-        {
-            int lo = nb, hi = uc;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (srel[mid] < b0) lo = mid + 1;
-                else hi = mid;
-            }
-            blo = lo;
-            hi = uc;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (srel[mid] < b1) lo = mid + 1;
-                else hi = mid;
-            }
-            bhi = lo;
-        }
-        blo = __builtin_amdgcn_readfirstlane(blo);
-        bhi = __builtin_amdgcn_readfirstlane(bhi);
-        const int tot = (bhi - blo) * uc;
-        const int64_t base = (int64_t)blo * uc;
-        constexpr int UNR = 16;
-        for (int q0 = tid; q0 < tot; q0 += nt * UNR) {
-            double v[UNR], cur[UNR];
-            int dst[UNR];
-            bool keep[UNR];
+    };
+    for (int t = wave; t < nbu - tj; t += nwave) {
+        const int ti = tj + t;
+        const int b = (tj << 4) + (lane & 15);
+        const int a0 = (ti << 4) + (lane >> 4);
+        double v0[4] = {0.0, 0.0, 0.0, 0.0}, v1[4] = {0.0, 0.0, 0.0, 0.0};
+        bool in0[4] = {false, false, false, false}, in1[4] = {false, false, false, false};
+        if (nch > 0) child_vals(0, a0, b, v0, in0);
+        if (nch > 1) child_vals(1, a0, b, v1, in1);
+        const d4 acc = tile_abt_g(Lp, ld, c + (ti << 4), c + (tj << 4), c, r, lane);
+        double w[4];
 #pragma unroll
-            for (int k = 0; k < UNR; k++) {
-                const int qa = q0 + k * nt;
-                const int qq = min(qa, tot - 1);
-                const int bq = qq / uc;
-                const int b = blo + bq, aq = qq - bq * uc;
-                keep[k] = qa < tot && aq >= b;
-                // not kept: the column's diagonal (rows below nb map into the
-                // front's own columns and have no place in U)
-                const int a = keep[k] ? aq : b;
-                dst[k] = srel[b] * u + srel[a];
-                v[k] = Uc[base + qq];
-                cur[k] = Us[dst[k]];
-            }
-#pragma unroll
-            for (int k = 0; k < UNR; k++) {
-                pin(v[k]);
-                pin(cur[k]);
-            }
-#pragma unroll
-            for (int k = 0; k < UNR; k++)
-                if (keep[k]) Us[dst[k]] = cur[k] + v[k];
+        for (int e = 0; e < 4; e++) {
+            w[e] = -acc[e];
+            if (in0[e]) w[e] += v0[e];
+            if (in1[e]) w[e] += v1[e];
         }
-        __syncthreads();
+        for (int k = 2; k < nch; k++) {
+            double vk[4];
+            bool ink[4];
+            child_vals(k, a0, b, vk, ink);
+#pragma unroll
+            for (int e = 0; e < 4; e++)
+                if (ink[e]) w[e] += vk[e];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int a = a0 + 4 * e;
+            if (a < u && b <= a) Us[(int64_t)b * u + a] = w[e];
+        }
     }
 }
 

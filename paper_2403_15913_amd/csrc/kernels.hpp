@@ -28,7 +28,6 @@ struct Calls {
 };
 
 constexpr int kBlock = 256;
-constexpr int kUpdMaxRows = 4096;  // strip update kernel: largest child update (rows) it stages
 constexpr int kSplitMaxFronts = 48;  // levels with fewer fronts launch their update matrices by strips
 constexpr int kSplitMinRows = 96;    // ... when the level's widest update part has at least this many rows
 constexpr int kResidualSplit = 8;    // residual blocks per 256-row item (two rows per 16-lane group)
