@@ -494,7 +494,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU: this library runs each solve on a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+              "(sharding across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
