@@ -943,10 +943,10 @@ __device__ inline d4 tile_abt_g(const double* __restrict__ Lp, int ld, int i0, i
 }
 
 // One workgroup per 16-column strip of U = -L21 L21^T: the strip's tiles
-// on the matrix cores from the stored panel, then, child by child, the
-// children's update entries that pass through to the strip's columns. Each
-// entry of U receives the same operations, in the same order, as in the
-// factor kernel's fused path, so the two paths agree bitwise.
+// on the matrix cores from the stored panel, with the children's update
+// entries that pass through to them added in the tile epilogue. Each entry
+// of U receives the same operations, in the same order, as in the factor
+// kernel's fused path, so the two paths agree bitwise.
 constexpr int kUpdThreads = 256;
 __global__ __launch_bounds__(kUpdThreads) void k_update(const InstDev* __restrict__ insts,
                                                        const FrontDesc* __restrict__ fds,
