@@ -243,7 +243,8 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         for (int k = 0; k < S.ns; k++) {
             lds_factor = std::max(lds_factor, (size_t)factor_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]));
             lds_solve = std::max(lds_solve, (size_t)solve_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]));
-            nup += (size_t)(S.sn_nrow[k] - S.sn_ncol[k] + 15) / 16;
+            const size_t nbu = (size_t)(S.sn_nrow[k] - S.sn_ncol[k] + 15) / 16;
+            nup += nbu * (nbu + 1) / 2;
         }
         nlev = std::max(nlev, S.nlevels);
         nsn += S.ns;
@@ -398,7 +399,7 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         sw_lvl.push_back((int)sw_part.size());
         lvl_ptr.push_back((int)sn.size());
     }
-    // update-matrix strips of the same fronts, level by level
+    // update-matrix tiles (lower part) of the same fronts, level by level
     std::vector<StripItem> up;
     up.reserve(nup);
     up_ptr.assign(1, 0);
@@ -408,7 +409,9 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
             const Symbolic& S = *s[sn[t].inst];
             const int u = S.sn_nrow[sn[t].id] - S.sn_ncol[sn[t].id];
             lvl_maxu[l] = std::max(lvl_maxu[l], u);
-            for (int k = 0; k < (u + 15) / 16; k++) up.push_back(StripItem{sn[t].inst, sn[t].id, k, t});
+            const int nbu = (u + 15) / 16;
+            for (int tj = 0; tj < nbu; tj++)
+                for (int ti = tj; ti < nbu; ti++) up.push_back(StripItem{sn[t].inst, sn[t].id, (ti << 16) | tj, t});
         }
         up_ptr.push_back((int)up.size());
     }

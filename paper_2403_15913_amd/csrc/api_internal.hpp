@@ -94,7 +94,7 @@ struct Engine {
              *hitems = nullptr;
     FrontDesc* fdesc = nullptr;                     // one per front work item (same order as snitems)
     int *dep_parent = nullptr, *dep_nchild = nullptr, *dep_ctr = nullptr;  // queue scheduling
-    StripItem* upitems = nullptr;                   // update-matrix strips by level (level schedule)
+    StripItem* upitems = nullptr;                   // update-matrix tiles by level (level schedule)
     std::vector<int> up_ptr;
     std::vector<int> lvl_maxu;                      // widest update part of each level
     bool split_update = true;                       // level schedule: update matrices in their own launch

@@ -160,11 +160,11 @@ struct WorkItem {
     int id;   // supernode, or first row of a block
 };
 
-// one 16-column strip of a front's update matrix
+// one 16 x 16 tile (lower part) of a front's update matrix
 struct StripItem {
     int inst;
     int id;     // supernode
-    int strip;  // first column / 16
+    int tile;   // (row block << 16) | column block
     int item;   // the front's work item (index into the front descriptors)
 };
 

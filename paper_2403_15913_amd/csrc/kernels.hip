@@ -942,12 +942,13 @@ __device__ inline d4 tile_abt_g(const double* __restrict__ Lp, int ld, int i0, i
     return acc;
 }
 
-// One workgroup per 16-column strip of U = -L21 L21^T: the strip's tiles
-// on the matrix cores from the stored panel, with the children's update
-// entries that pass through to them added in the tile epilogue. Each entry
-// of U receives the same operations, in the same order, as in the factor
-// kernel's fused path, so the two paths agree bitwise.
-constexpr int kUpdThreads = 256;
+// One wave per 16 x 16 tile of U = -L21 L21^T (lower part), on the matrix
+// cores from the stored panel, with the children's update entries that pass
+// through to it added in the tile epilogue. Each entry of U receives the same
+// operations, in the same order, as in the factor kernel's fused path, so the
+// two paths agree bitwise. (A tile per wave keeps each wave to one round trip
+// for its loads and one matrix-core chain.)
+constexpr int kUpdThreads = 64;
 __global__ __launch_bounds__(kUpdThreads) void k_update(const InstDev* __restrict__ insts,
                                                        const FrontDesc* __restrict__ fds,
                                                        const StripItem* __restrict__ items) {
@@ -957,14 +958,13 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(const InstDev* __restric
     const PatDev& T = I.P;
     const int c = F.c, r = F.r;
     const int u = r - c, ld = r | 1;
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
+    const int lane = threadIdx.x;
     const double* __restrict__ Lp = F.L;
     double* __restrict__ Us = F.U;
-    const int tj = it.strip, nbu = (u + 15) >> 4;
+    const int ti = it.tile >> 16, tj = it.tile & 0xffff;
     const int nch = F.nch;
-    // the children's pass-through entries of each tile place, through their
-    // inverse row maps, added in child order before the one store (the same
-    // additions in the same order as the front kernel's epilogue)
+    // the children's pass-through entries of this lane's places, through
+    // their inverse row maps, added in child order before the one store
     auto child_vals = [&](const int k, const int a0, const int b, double* v, bool* in) {
         const double* Uc;
         const int* inv;
@@ -990,35 +990,32 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(const InstDev* __restric
             v[e] = Uc[(int64_t)max(ib, 0) * uc + max(ia[e], 0)];
         }
     };
-    for (int t = wave; t < nbu - tj; t += nwave) {
-        const int ti = tj + t;
-        const int b = (tj << 4) + (lane & 15);
-        const int a0 = (ti << 4) + (lane >> 4);
-        double v0[4] = {0.0, 0.0, 0.0, 0.0}, v1[4] = {0.0, 0.0, 0.0, 0.0};
-        bool in0[4] = {false, false, false, false}, in1[4] = {false, false, false, false};
-        if (nch > 0) child_vals(0, a0, b, v0, in0);
-        if (nch > 1) child_vals(1, a0, b, v1, in1);
-        const d4 acc = tile_abt_g(Lp, ld, c + (ti << 4), c + (tj << 4), c, r, lane);
-        double w[4];
+    const int b = (tj << 4) + (lane & 15);
+    const int a0 = (ti << 4) + (lane >> 4);
+    double v0[4] = {0.0, 0.0, 0.0, 0.0}, v1[4] = {0.0, 0.0, 0.0, 0.0};
+    bool in0[4] = {false, false, false, false}, in1[4] = {false, false, false, false};
+    if (nch > 0) child_vals(0, a0, b, v0, in0);
+    if (nch > 1) child_vals(1, a0, b, v1, in1);
+    const d4 acc = tile_abt_g(Lp, ld, c + (ti << 4), c + (tj << 4), c, r, lane);
+    double w[4];
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-            w[e] = -acc[e];
-            if (in0[e]) w[e] += v0[e];
-            if (in1[e]) w[e] += v1[e];
-        }
-        for (int k = 2; k < nch; k++) {
-            double vk[4];
-            bool ink[4];
-            child_vals(k, a0, b, vk, ink);
+    for (int e = 0; e < 4; e++) {
+        w[e] = -acc[e];
+        if (in0[e]) w[e] += v0[e];
+        if (in1[e]) w[e] += v1[e];
+    }
+    for (int k = 2; k < nch; k++) {
+        double vk[4];
+        bool ink[4];
+        child_vals(k, a0, b, vk, ink);
 #pragma unroll
-            for (int e = 0; e < 4; e++)
-                if (ink[e]) w[e] += vk[e];
-        }
+        for (int e = 0; e < 4; e++)
+            if (ink[e]) w[e] += vk[e];
+    }
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const int a = a0 + 4 * e;
-            if (a < u && b <= a) Us[(int64_t)b * u + a] = w[e];
-        }
+    for (int e = 0; e < 4; e++) {
+        const int a = a0 + 4 * e;
+        if (a < u && b <= a) Us[(int64_t)b * u + a] = w[e];
     }
 }
 
