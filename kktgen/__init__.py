@@ -12,6 +12,6 @@ and each value set is reproducible on its own.
 from .nmpc import (  # noqa: F401
     SEED_ROOT, Pattern, Values, rng_for, log_uniform,
     nmpc_pattern, nmpc_values, distillation_pattern, distillation_values,
-    dyadic_nmpc_values, batch_shapes, serving_shapes, poisson_arrivals,
+    dyadic_nmpc_values, batch_shapes, serving_shapes, poisson_arrivals, hub_pattern, hub_values,
     workload, small_config, paper_config, hykkt_config,
 )

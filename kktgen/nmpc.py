@@ -235,6 +235,46 @@ def distillation_values(pat: Pattern, rng: np.random.Generator, sigma_lo: float,
 # Workload recipes (sizes and Σ ranges of the benchmark configurations)
 # --------------------------------------------------------------------------
 
+def hub_pattern(k: int, b: int, h1: int, h2: int) -> Pattern:
+    """k independent branches of b variables, each coupled to a hub of h1
+    variables, which is coupled to a root block of h2 (variables numbered
+    branch by branch, then the hub, then the root). W: a dense lower block
+    per branch, hub and root. J: per branch two rows on the branch and the
+    hub; two rows on the hub and the root. In the natural order the hub's
+    supernode has k children."""
+    n = k * b + h1 + h2
+    hub0, root0 = k * b, k * b + h1
+    w_rows = []
+    for base, s in [(i * b, b) for i in range(k)] + [(hub0, h1), (root0, h2)]:
+        for r in range(s):
+            w_rows.append(np.arange(base, base + r + 1))
+    j_rows = []
+    for i in range(k):
+        for _ in range(2):
+            j_rows.append(np.concatenate([np.arange(i * b, (i + 1) * b), np.arange(hub0, hub0 + h1)]))
+    for _ in range(2):
+        j_rows.append(np.arange(hub0, n))
+    wr, wc = _csr_from_rows(w_rows, n)
+    jr, jc = _csr_from_rows(j_rows, n)
+    return Pattern(n, len(j_rows), wr, wc, jr, jc, dict(kind="hub", k=k, b=b, h1=h1, h2=h2))
+
+
+def hub_values(pat: Pattern, rng: np.random.Generator, sigma_lo: float, sigma_hi: float) -> Values:
+    """Draw order: per block W (M ~ N(0,1), M M^T + I), then J ~ N(0,1), then Σx, Σs, b, f, g."""
+    k, b, h1, h2 = (pat.meta[x] for x in ("k", "b", "h1", "h2"))
+    w_parts = []
+    for s in [b] * k + [h1, h2]:
+        M = rng.standard_normal((s, s))
+        w_parts.append(_stage_dense_lower(M @ M.T + np.eye(s)))
+    w_vals = np.concatenate(w_parts)
+    j_vals = rng.standard_normal(pat.nnz_j)
+    assert len(w_vals) == pat.nnz_w
+    return Values(w_vals, j_vals,
+                  log_uniform(rng, sigma_lo, sigma_hi, pat.n),
+                  log_uniform(rng, sigma_lo, sigma_hi, pat.m),
+                  rng.standard_normal(pat.n), rng.standard_normal(pat.n), rng.standard_normal(pat.m))
+
+
 def small_config():
     """Lifted-KKT plain: N=50, nx=8, nu=1 (n=450, m=400), Σ ~ logU[1e-2, 1e2]."""
     return nmpc_pattern(50, 8, 1), (1e-2, 1e2)

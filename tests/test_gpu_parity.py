@@ -428,3 +428,39 @@ def test_hykkt_paper_scale_wide_sigma_eta_stop(kkt):
         assert info["status"] == 0 and info["eta_stop"] == 1, info
         be = D.hykkt_backward_errors(pat, v, host(dx), host(dy), v.f, v.g)
         check_device_eta(info, be)
+
+
+@pytest.mark.parametrize("h2", [40, 100], ids=["fused-update", "tile-update"])
+def test_front_with_many_children(kkt, h2):
+    """Five branches coupled to a hub coupled to a root block, natural order,
+    supernodes of at most 24 columns and no amalgamation: the hub's front
+    has five children and an update part of h2 rows, so the children's
+    pass-through entries take the path for more than two children, in the
+    front kernel's epilogue (40 rows) and in the tile update kernel (100
+    rows, a level of one front). eta <= 1e-10 and forward error <= 1e-8
+    against the oracle (Sigma in [1e-2, 1e2]); the queue schedule bitwise
+    equal to the level schedule."""
+    pat = kktgen.hub_pattern(5, 20, 24, h2)
+    v = kktgen.hub_values(pat, kktgen.rng_for(96, 0, 0), 1e-2, 1e2)
+    sym = kkt.Symbolic.from_pattern(pat, ordering=kkt.ORDER_NATURAL, max_super=24, relax_small=-1, relax_frac=0.0)
+    cp, par, nr = sym.supernodes()
+    nch = np.bincount(par[par >= 0], minlength=len(par))
+    hub = int(nch.argmax())
+    print(f"hub front: {nch[hub]} children, {nr[hub]} rows, {cp[hub + 1] - cp[hub]} columns", flush=True)
+    assert nch[hub] == 5 and nr[hub] - (cp[hub + 1] - cp[hub]) == h2
+    xs = []
+    for sched in (kkt.SCHEDULE_LEVELS, kkt.SCHEDULE_QUEUE):
+        f = kkt.Factor(sym)
+        f.set_schedule(sched)
+        f.refactor(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), dev(v.sigma_s))
+        assert f.status()[0] == 0
+        x = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
+        info = f.solve(dev(v.b), x)
+        assert info["eta"] <= 1e-10
+        xs.append(host(x))
+    K = D.condensed(pat, v, v.sigma_s)
+    assert D.backward_errors(K, xs[0], v.b)["eta"] <= 1e-10
+    xo, oinfo = S.lifted_solve(pat, v, v.b)
+    assert oinfo["spd"]
+    checks.assert_well_conditioned(xs[0], xo)
+    assert np.array_equal(xs[0], xs[1])
