@@ -93,6 +93,7 @@ def bench_batched(args, kkt, kktgen, torch, dev):
     analyze_s = time.perf_counter() - t0
     B = kkt.Batch(syms)
     B.set_schedule(best["schedule"])
+    B.set_update_split(*best.get("split", (48, 96)))
     cat = {f: T(np.concatenate([getattr(v, f) for v in vals])) for f in ("w_vals", "j_vals", "sigma_x", "sigma_s", "b")}
     x = torch.zeros(int(B.ofs["n"][-1]), dtype=torch.float64, device=dev)
     reps = 5
@@ -160,7 +161,8 @@ def bench_batched(args, kkt, kktgen, torch, dev):
                           launches_per_batch=btm["factor"]["launches"] / reps,
                           factor_ms_per_batch=round(1e3 * fac_s, 4))
     return dict(instances=count, sum_n=int(n_ofs[-1]), sum_nnz_l=int(sum(s["nnz_l"] for s in st)),
-                flops_exact=flops, options=opts, schedule=sched_name, roofline=batch_roofline,
+                flops_exact=flops, options=opts, schedule=sched_name,
+                update_split=list(best.get("split", (48, 96))), roofline=batch_roofline,
                 phase_ms_per_batch={p: round(btm[p]["ms"] / reps, 4) for p in btm},
                 autotuned=bool(args.batch_autotune), tune_s=round(tune_s, 2), analyze_s=round(analyze_s, 2),
                 tried=tuned["tried"] if tuned else None, graph_rounds=args.graph_rounds,
@@ -531,6 +533,7 @@ def main():
 
     tuned = None
     opts = dict(ordering=args.ordering, nd_leaf=args.nd_leaf, max_super=args.max_super)
+    split = (48, 96)  # the library's default launch shape of the update matrices
     if args.autotune and not args.ordering and not args.nd_leaf:
         from paper_2403_15913_amd import autotune
         t0 = time.perf_counter()
@@ -540,6 +543,7 @@ def main():
         opts = {k: best[k] for k in ("ordering", "nd_leaf", "max_super")}
         if args.schedule_given is None:
             args.schedule = "queue" if best["schedule"] == kkt.SCHEDULE_QUEUE else "levels"
+        split = tuple(best["split"])
         tuned = dict(seconds=round(time.perf_counter() - t0, 2), tried=tried)
     t0 = time.perf_counter()
     sym = kkt.Symbolic.from_pattern(pat, **opts)
@@ -547,6 +551,7 @@ def main():
     stats = sym.stats()
     fac = kkt.Factor(sym)
     fac.set_schedule(kkt.SCHEDULE_QUEUE if args.schedule == "queue" else kkt.SCHEDULE_LEVELS)
+    fac.set_update_split(*split)
 
     def step(i):
         d = dvals[i % len(dvals)]
@@ -634,7 +639,7 @@ def main():
                                 "Sigma~logU[1e-8,1e8], 10 value sets") if args.workload == "paper"
                    else "lifted-kkt plain, NMPC N=50 nx=8 nu=1 (n=450, m=400)",
                    "mode": "plain", "options": opts, "autotuned": tuned is not None,
-                   "schedule": args.schedule},
+                   "schedule": args.schedule, "update_split": list(split)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail": {

@@ -468,6 +468,21 @@ kkt_status kkt_factor_read_timing(kkt_factor* f, kkt_timing* out);
 kkt_status kkt_factor_set_schedule(kkt_factor* f, int32_t schedule);
 
 /*
+ * Launch shape of the update matrices U = -L21 L21^T of the multifrontal
+ * factorization (section "Hybrid linear solver": the dense kernels of the
+ * supernodal Cholesky), level schedule only: on a tree level with fewer
+ * than max_fronts fronts whose widest update part has at least min_rows
+ * rows, the update matrices are formed by a launch of their own (one wave
+ * per 16 x 16 tile) instead of by each front's workgroup after its panel.
+ * Both ways give every entry the same operations in the same order, so
+ * results are bitwise identical; only the time differs. Defaults 48 and 96;
+ * max_fronts = 0 keeps every update in the front's workgroup. The
+ * autotuner picks them by measurement. INVALID_ARG for negative values.
+ * Host only; applies to launches issued after the call.
+ */
+kkt_status kkt_factor_set_update_split(kkt_factor* f, int32_t max_fronts, int32_t min_rows);
+
+/*
  * Batched form: many independent instances (each with its own pattern; the
  * same symbolic object may appear several times) refactored and solved by
  * the same launches. With the LEVELS schedule every launch covers one tree
@@ -505,6 +520,8 @@ kkt_status kkt_batch_status(kkt_batch* b, int32_t* status, int32_t* bad_col);
 
 /* Launch schedule of the batch (see KKT_SCHEDULE_*). */
 kkt_status kkt_batch_set_schedule(kkt_batch* b, int32_t schedule);
+/* As kkt_factor_set_update_split, for every level of the batch's launches. */
+kkt_status kkt_batch_set_update_split(kkt_batch* b, int32_t max_fronts, int32_t min_rows);
 
 /*
  * Graph form of kkt_batch_refactor + kkt_batch_solve. kkt_batch_capture

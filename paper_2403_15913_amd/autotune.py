@@ -2,19 +2,22 @@
 
 For a pattern (or a batch of patterns) it measures refactor+solve on the
 device for a set of candidate options -- ordering (natural stage order or
-nested dissection), nested-dissection leaf size, widest supernode, and for
-batches the launch schedule (one launch per tree level, or the persistent
-work queue) -- and keeps the fastest candidate whose solves all pass the
-backward-error gate. These options decide the supernode tree the kernels run
-on: the depth of the dependency chain, the front sizes (rows x columns of
-every LDS panel and of the matrix-core tiles), and the total flops.
+nested dissection), nested-dissection leaf size, widest supernode, the launch
+schedule (one launch per tree level, or the persistent work queue) and the
+launch shape of the update matrices (which tree levels form them in a launch
+of their own, one wave per tile) -- and keeps the fastest candidate whose
+solves all pass the backward-error gate. These options decide the supernode
+tree the kernels run on: the depth of the dependency chain, the front sizes
+(rows x columns of every LDS panel and of the matrix-core tiles), the total
+flops, and how the work of each level is spread over the compute units.
 
 Results are cached in a JSON table keyed by a pattern signature, so a
 pattern is tuned once and later analyses reuse the choice:
 
     from paper_2403_15913_amd import autotune
-    opts = autotune.tune_pattern(pat, vals)            # measure (GPU)
-    sym = kkt.Symbolic.from_pattern(pat, **opts)
+    best = autotune.tune_pattern(pat, vals)            # measure (GPU)
+    sym = kkt.Symbolic.from_pattern(pat, **{k: best[k] for k in ("ordering", "nd_leaf", "max_super")})
+    f = kkt.Factor(sym); f.set_schedule(best["schedule"]); f.set_update_split(*best["split"])
 
 Timing uses the library's own calls; nothing here computes any part of the
 solve.
@@ -78,11 +81,17 @@ def _dev(a):
     return torch.tensor(np.asarray(a), dtype=torch.float64, device="cuda")
 
 
-def _time_plain(pat, vals, opts, reps: int, schedule: int = kkt.SCHEDULE_LEVELS):
+# launch shapes of the update matrices (kkt_factor_set_update_split): the
+# default, none split, more levels split, every level split
+SPLITS = ((48, 96), (0, 0), (140, 64), (1 << 30, 0))
+
+
+def _time_plain(pat, vals, opts, reps: int, schedule: int = kkt.SCHEDULE_LEVELS, split=SPLITS[0]):
     import torch
     sym = kkt.Symbolic.from_pattern(pat, **opts)
     f = kkt.Factor(sym)
     f.set_schedule(schedule)
+    f.set_update_split(*split)
     d = [_dev(vals.w_vals), _dev(vals.j_vals), _dev(vals.sigma_x), _dev(vals.sigma_s)]
     b = _dev(vals.b)
     x = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
@@ -123,8 +132,9 @@ def tune_pattern(pat, vals, reps: int = 3, table_path: str | None = DEFAULT_TABL
     """Best options for one pattern (measured on the GPU, cached by signature).
 
     The symbolic candidates are timed under the level schedule; then the best
-    few are timed again under every schedule in `schedules`. The result holds
-    the symbolic options and a "schedule" entry."""
+    few are timed again under every schedule in `schedules`, and the fastest
+    option set under the level schedule with every launch shape in SPLITS.
+    The result holds the symbolic options, a "schedule" and a "split" entry."""
     key = signature(pat)
     table = load_table(table_path) if table_path else {}
     if not force and key in table:
@@ -137,7 +147,7 @@ def tune_pattern(pat, vals, reps: int = 3, table_path: str | None = DEFAULT_TABL
             if log:
                 log(f"{opts}: {e}")
             continue
-        results.append((t, eta, dict(opts, schedule=kkt.SCHEDULE_LEVELS), st))
+        results.append((t, eta, dict(opts, schedule=kkt.SCHEDULE_LEVELS, split=SPLITS[0]), st))
         if log:
             log(f"{opts}: {1e3 * t:.3f} ms, eta {eta:.1e}, levels {st['levels']}, flops {st['flops']:.3g}")
     # other schedules for the three fastest option sets
@@ -148,9 +158,17 @@ def tune_pattern(pat, vals, reps: int = 3, table_path: str | None = DEFAULT_TABL
         for _, _, o, _ in top:
             opts = {k: o[k] for k in ("ordering", "nd_leaf", "max_super")}
             t, eta, st = _time_plain(pat, vals, opts, reps, sched)
-            results.append((t, eta, dict(opts, schedule=sched), st))
+            results.append((t, eta, dict(opts, schedule=sched, split=SPLITS[0]), st))
             if log:
                 log(f"{opts} schedule {sched}: {1e3 * t:.3f} ms, eta {eta:.1e}")
+    # launch shapes of the update matrices for the fastest option set
+    if top:
+        opts = {k: top[0][2][k] for k in ("ordering", "nd_leaf", "max_super")}
+        for split in SPLITS[1:]:
+            t, eta, st = _time_plain(pat, vals, opts, reps, kkt.SCHEDULE_LEVELS, split)
+            results.append((t, eta, dict(opts, schedule=kkt.SCHEDULE_LEVELS, split=split), st))
+            if log:
+                log(f"{opts} split {split}: {1e3 * t:.3f} ms, eta {eta:.1e}")
     ok = [r for r in results if r[1] <= ETA_GATE]
     if not ok:
         raise RuntimeError("no candidate passed the backward-error gate")
@@ -193,4 +211,18 @@ def tune_batch(pats, vals, reps: int = 2, log=None, threads: int = 16) -> dict:
     if not ok:
         raise RuntimeError("no candidate passed the backward-error gate")
     t, eta, best = min(ok, key=lambda r: r[0])
+    best = dict(best, split=SPLITS[0])
+    # launch shapes of the update matrices for the fastest option set
+    if best["schedule"] == kkt.SCHEDULE_LEVELS:
+        opts = {k: best[k] for k in ("ordering", "nd_leaf", "max_super")}
+        B = kkt.Batch(analyze_many(pats, threads, **opts))
+        for split in SPLITS[1:]:
+            B.set_update_split(*split)
+            ts, eta = _time_batch(B, cat, b, x, reps)
+            tried.append((ts, eta, dict(opts, schedule=kkt.SCHEDULE_LEVELS, split=split)))
+            if log:
+                log(f"{opts} split {split}: {1e3 * ts:.3f} ms, eta {eta:.1e}")
+            if eta <= ETA_GATE and ts < t:
+                t, best = ts, dict(opts, schedule=kkt.SCHEDULE_LEVELS, split=split)
+        B.close()
     return dict(best=best, ms=1e3 * t, tried=[dict(options=o, ms=round(1e3 * tt, 3)) for tt, _, o in tried])

@@ -605,12 +605,13 @@ kkt_status Engine::refactor(const Calls& Cin, hipStream_t st) {
         TL(KKT_PHASE_FACTOR, launch_factor_queue(di(), fdesc, D, std::min(D.nitems, 512), lds_factor, st));
     } else {
         // A level with few fronts leaves most compute units idle: its update
-        // matrices then go to a launch of their own with one workgroup per
-        // 16-column strip, where they are large enough to repay the launch.
-        // Wide levels keep them in the factor kernel.
+        // matrices then go to a launch of their own with one wave per 16 x 16
+        // tile, where they are large enough to repay the launch. Wide levels
+        // keep them in the factor kernel. Both paths give every entry the
+        // same operations in the same order.
         for (size_t l = 0; l + 1 < lvl_ptr.size(); l++) {
             const int nf = lvl_ptr[l + 1] - lvl_ptr[l];
-            const bool split = split_update && nf < kSplitMaxFronts && lvl_maxu[l] >= kSplitMinRows;
+            const bool split = split_update && nf < split_max_fronts && lvl_maxu[l] >= split_min_rows;
             TL(KKT_PHASE_FACTOR, launch_factor(di(), fdesc + lvl_ptr[l], nf, lds_factor, split ? 0 : 1, st));
             if (split) TL(KKT_PHASE_FACTOR, launch_update(di(), fdesc, upitems + up_ptr[l], up_ptr[l + 1] - up_ptr[l], st));
         }
@@ -1330,6 +1331,14 @@ kkt_status kkt_factor_set_schedule(kkt_factor* f, int32_t schedule) {
     return KKT_OK;
 }
 
+kkt_status kkt_factor_set_update_split(kkt_factor* f, int32_t max_fronts, int32_t min_rows) {
+    if (!f) return fail(KKT_ERR_INVALID_ARG, "NULL factor");
+    if (max_fronts < 0 || min_rows < 0) return fail(KKT_ERR_INVALID_ARG, "negative split threshold");
+    f->eng.split_max_fronts = max_fronts;
+    f->eng.split_min_rows = min_rows;
+    return KKT_OK;
+}
+
 kkt_status kkt_factor_read_timing(kkt_factor* f, kkt_timing* out) {
     if (!f || !out) return fail(KKT_ERR_INVALID_ARG, "NULL argument");
     return timing_read(f->eng, out);
@@ -1430,6 +1439,14 @@ kkt_status kkt_batch_set_schedule(kkt_batch* b, int32_t schedule) {
     if (schedule != KKT_SCHEDULE_LEVELS && schedule != KKT_SCHEDULE_QUEUE)
         return fail(KKT_ERR_INVALID_ARG, "unknown schedule");
     b->eng.queue_sched = schedule == KKT_SCHEDULE_QUEUE;
+    return KKT_OK;
+}
+
+kkt_status kkt_batch_set_update_split(kkt_batch* b, int32_t max_fronts, int32_t min_rows) {
+    if (!b) return fail(KKT_ERR_INVALID_ARG, "NULL batch");
+    if (max_fronts < 0 || min_rows < 0) return fail(KKT_ERR_INVALID_ARG, "negative split threshold");
+    b->eng.split_max_fronts = max_fronts;
+    b->eng.split_min_rows = min_rows;
     return KKT_OK;
 }
 

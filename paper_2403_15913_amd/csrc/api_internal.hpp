@@ -98,6 +98,8 @@ struct Engine {
     std::vector<int> up_ptr;
     std::vector<int> lvl_maxu;                      // widest update part of each level
     bool split_update = true;                       // level schedule: update matrices in their own launch
+    int split_max_fronts = kSplitMaxFronts;         // ... on levels with fewer fronts than this
+    int split_min_rows = kSplitMinRows;             // ... whose widest update part has at least this many rows
     bool queue_sched = false;                       // dependency-driven launches (else one launch per level)
     bool assembly_only = false;                     // no supernodal factor storage (stage-structured solver)
     bool single_storage = false;                    // single factors: K0, J and Sigma_s kept for the HyKKT CG

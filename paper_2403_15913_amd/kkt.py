@@ -148,6 +148,7 @@ SIGNATURES = {
     "kkt_factor_set_timing": (I32, [P, I32]),
     "kkt_factor_read_timing": (I32, [P, P]),
     "kkt_factor_set_schedule": (I32, [P, I32]),
+    "kkt_factor_set_update_split": (I32, [P, I32, I32]),
     "kkt_batch_create": (I32, [I32, P, P]),
     "kkt_batch_destroy": (None, [P]),
     "kkt_batch_offsets": (I32, [P, P, P, P, P]),
@@ -157,6 +158,7 @@ SIGNATURES = {
     "kkt_batch_set_timing": (I32, [P, I32]),
     "kkt_batch_read_timing": (I32, [P, P]),
     "kkt_batch_set_schedule": (I32, [P, I32]),
+    "kkt_batch_set_update_split": (I32, [P, I32, I32]),
     "kkt_batch_capture": (I32, [P, P, P, P, P, P, P, P, I32]),
     "kkt_batch_replay": (I32, [P, P, P]),
     "kkt_stagewise_create": (I32, [I32, P, P, P, P]),
@@ -392,6 +394,10 @@ def kkt_factor_set_schedule(h, schedule: int):
     _err(lib().kkt_factor_set_schedule(h, int(schedule)))
 
 
+def kkt_factor_set_update_split(h, max_fronts: int, min_rows: int):
+    _err(lib().kkt_factor_set_update_split(h, int(max_fronts), int(min_rows)))
+
+
 # ---------------------------------------------------------------------------
 # handle wrappers
 # ---------------------------------------------------------------------------
@@ -478,6 +484,9 @@ class Factor:
 
     def set_schedule(self, schedule: int):
         kkt_factor_set_schedule(self.h, schedule)
+
+    def set_update_split(self, max_fronts: int, min_rows: int):
+        kkt_factor_set_update_split(self.h, max_fronts, min_rows)
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
@@ -566,6 +575,9 @@ class Batch:
 
     def set_schedule(self, schedule: int):
         kkt_batch_set_schedule(self.h, schedule)
+
+    def set_update_split(self, max_fronts: int, min_rows: int):
+        _err(lib().kkt_batch_set_update_split(self.h, int(max_fronts), int(min_rows)))
 
     def capture(self, w_vals, j_vals, sigma_x, sigma_s, b, x, max_iter=10, tol=1e-14, rounds=2):
         """Record refactor + solve as a graph bound to these arrays (kept alive here)."""

@@ -464,3 +464,35 @@ def test_front_with_many_children(kkt, h2):
     assert oinfo["spd"]
     checks.assert_well_conditioned(xs[0], xo)
     assert np.array_equal(xs[0], xs[1])
+
+
+@pytest.mark.parametrize("nd", [True, False], ids=["nd", "natural"])
+def test_update_split_bitwise(kkt, nd):
+    """The launch shape of the update matrices (every level in the front's
+    workgroup, the default split, every level by tiles) changes no bit of
+    the solution, for a plain factor and for a batch; eta <= 1e-10."""
+    pat = kktgen.distillation_pattern(40)
+    v = kktgen.distillation_values(pat, kktgen.rng_for(1, 40, 0), 1e-8, 1e8)
+    opts = dict(ordering=2, nd_leaf=200) if nd else dict(ordering=1)
+    sym = kkt.Symbolic.from_pattern(pat, **opts)
+    xs = []
+    for split in ((0, 0), (48, 96), (1 << 30, 0)):
+        f = kkt.Factor(sym)
+        f.set_update_split(*split)
+        f.refactor(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), dev(v.sigma_s))
+        x = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
+        info = f.solve(dev(v.b), x)
+        assert info["eta"] <= 1e-10, (split, info)
+        xs.append(host(x))
+        B = kkt.Batch([sym, sym])
+        B.set_update_split(*split)
+        cat = lambda a: dev(np.concatenate([a, a]))
+        B.refactor(cat(v.w_vals), cat(v.j_vals), cat(v.sigma_x), cat(v.sigma_s))
+        xb = torch.zeros(2 * pat.n, dtype=torch.float64, device="cuda")
+        B.solve(cat(v.b), xb)
+        xbh = host(xb)
+        assert np.array_equal(xbh[:pat.n], xs[-1]) and np.array_equal(xbh[pat.n:], xs[-1])
+    print("update split variants: max |dx|", max(np.abs(a - xs[0]).max() for a in xs), flush=True)
+    assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[0], xs[2])
+    with pytest.raises(kkt.KKTError):
+        kkt.Factor(sym).set_update_split(-1, 0)
