@@ -94,6 +94,7 @@ def bench_batched(args, kkt, kktgen, torch, dev):
     B = kkt.Batch(syms)
     B.set_schedule(best["schedule"])
     B.set_update_split(*best.get("split", (48, 96)))
+    B.set_small_fronts(best.get("small", 0))
     cat = {f: T(np.concatenate([getattr(v, f) for v in vals])) for f in ("w_vals", "j_vals", "sigma_x", "sigma_s", "b")}
     x = torch.zeros(int(B.ofs["n"][-1]), dtype=torch.float64, device=dev)
     reps = 5
@@ -162,7 +163,8 @@ def bench_batched(args, kkt, kktgen, torch, dev):
                           factor_ms_per_batch=round(1e3 * fac_s, 4))
     return dict(instances=count, sum_n=int(n_ofs[-1]), sum_nnz_l=int(sum(s["nnz_l"] for s in st)),
                 flops_exact=flops, options=opts, schedule=sched_name,
-                update_split=list(best.get("split", (48, 96))), roofline=batch_roofline,
+                update_split=list(best.get("split", (48, 96))), small_fronts_cols=best.get("small", 0),
+                roofline=batch_roofline,
                 phase_ms_per_batch={p: round(btm[p]["ms"] / reps, 4) for p in btm},
                 autotuned=bool(args.batch_autotune), tune_s=round(tune_s, 2), analyze_s=round(analyze_s, 2),
                 tried=tuned["tried"] if tuned else None, graph_rounds=args.graph_rounds,
@@ -534,6 +536,7 @@ def main():
     tuned = None
     opts = dict(ordering=args.ordering, nd_leaf=args.nd_leaf, max_super=args.max_super)
     split = (48, 96)  # the library's default launch shape of the update matrices
+    small = 0  # the library's default: every front by eight-wave workgroups (column threshold 0)
     if args.autotune and not args.ordering and not args.nd_leaf:
         from paper_2403_15913_amd import autotune
         t0 = time.perf_counter()
@@ -544,6 +547,7 @@ def main():
         if args.schedule_given is None:
             args.schedule = "queue" if best["schedule"] == kkt.SCHEDULE_QUEUE else "levels"
         split = tuple(best["split"])
+        small = int(best.get("small", 0))
         tuned = dict(seconds=round(time.perf_counter() - t0, 2), tried=tried)
     t0 = time.perf_counter()
     sym = kkt.Symbolic.from_pattern(pat, **opts)
@@ -552,6 +556,7 @@ def main():
     fac = kkt.Factor(sym)
     fac.set_schedule(kkt.SCHEDULE_QUEUE if args.schedule == "queue" else kkt.SCHEDULE_LEVELS)
     fac.set_update_split(*split)
+    fac.set_small_fronts(small)
 
     def step(i):
         d = dvals[i % len(dvals)]
@@ -639,7 +644,7 @@ def main():
                                 "Sigma~logU[1e-8,1e8], 10 value sets") if args.workload == "paper"
                    else "lifted-kkt plain, NMPC N=50 nx=8 nu=1 (n=450, m=400)",
                    "mode": "plain", "options": opts, "autotuned": tuned is not None,
-                   "schedule": args.schedule, "update_split": list(split)},
+                   "schedule": args.schedule, "update_split": list(split), "small_fronts_cols": small},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail": {

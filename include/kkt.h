@@ -483,6 +483,20 @@ kkt_status kkt_factor_set_schedule(kkt_factor* f, int32_t schedule);
 kkt_status kkt_factor_set_update_split(kkt_factor* f, int32_t max_fronts, int32_t min_rows);
 
 /*
+ * Workgroup size of the front factorization (section "Hybrid linear solver":
+ * the dense kernels of the supernodal Cholesky), level schedule only: a tree
+ * level whose widest front has at most max_cols columns is factored by
+ * 256-thread workgroups that reserve only that level's LDS (two fit on a
+ * compute unit when the level's fronts need at most 80 KiB); other levels by
+ * 512-thread workgroups. Both give every entry the same operations in the
+ * same order, so results are bitwise identical; only the time differs.
+ * Default 0 (every level by 512 threads); the autotuner picks it by
+ * measurement. INVALID_ARG if negative. Host only; applies to launches
+ * issued after the call.
+ */
+kkt_status kkt_factor_set_small_fronts(kkt_factor* f, int32_t max_cols);
+
+/*
  * Batched form: many independent instances (each with its own pattern; the
  * same symbolic object may appear several times) refactored and solved by
  * the same launches. With the LEVELS schedule every launch covers one tree
@@ -522,6 +536,8 @@ kkt_status kkt_batch_status(kkt_batch* b, int32_t* status, int32_t* bad_col);
 kkt_status kkt_batch_set_schedule(kkt_batch* b, int32_t schedule);
 /* As kkt_factor_set_update_split, for every level of the batch's launches. */
 kkt_status kkt_batch_set_update_split(kkt_batch* b, int32_t max_fronts, int32_t min_rows);
+/* As kkt_factor_set_small_fronts, for every level of the batch's launches. */
+kkt_status kkt_batch_set_small_fronts(kkt_batch* b, int32_t max_cols);
 
 /*
  * Graph form of kkt_batch_refactor + kkt_batch_solve. kkt_batch_capture

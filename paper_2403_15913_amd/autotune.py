@@ -3,9 +3,11 @@
 For a pattern (or a batch of patterns) it measures refactor+solve on the
 device for a set of candidate options -- ordering (natural stage order or
 nested dissection), nested-dissection leaf size, widest supernode, the launch
-schedule (one launch per tree level, or the persistent work queue) and the
+schedule (one launch per tree level, or the persistent work queue), the
 launch shape of the update matrices (which tree levels form them in a launch
-of their own, one wave per tile) -- and keeps the fastest candidate whose
+of their own, one wave per tile) and the workgroup size of the front
+factorization per tree level (four waves for levels of narrow fronts, so
+two can share a compute unit, else eight) -- and keeps the fastest candidate whose
 solves all pass the backward-error gate. These options decide the supernode
 tree the kernels run on: the depth of the dependency chain, the front sizes
 (rows x columns of every LDS panel and of the matrix-core tiles), the total
@@ -18,6 +20,7 @@ pattern is tuned once and later analyses reuse the choice:
     best = autotune.tune_pattern(pat, vals)            # measure (GPU)
     sym = kkt.Symbolic.from_pattern(pat, **{k: best[k] for k in ("ordering", "nd_leaf", "max_super")})
     f = kkt.Factor(sym); f.set_schedule(best["schedule"]); f.set_update_split(*best["split"])
+    f.set_small_fronts(best["small"])
 
 Timing uses the library's own calls; nothing here computes any part of the
 solve.
@@ -84,14 +87,20 @@ def _dev(a):
 # launch shapes of the update matrices (kkt_factor_set_update_split): the
 # default, none split, more levels split, every level split
 SPLITS = ((48, 96), (0, 0), (140, 64), (1 << 30, 0))
+# column thresholds of the four-wave front factorization
+# (kkt_factor_set_small_fronts): none, then levels whose widest front has at
+# most 32, 48 or 64 columns
+SMALLS = (0, 32, 48, 64)
 
 
-def _time_plain(pat, vals, opts, reps: int, schedule: int = kkt.SCHEDULE_LEVELS, split=SPLITS[0]):
+def _time_plain(pat, vals, opts, reps: int, schedule: int = kkt.SCHEDULE_LEVELS, split=SPLITS[0],
+                small: int = SMALLS[0]):
     import torch
     sym = kkt.Symbolic.from_pattern(pat, **opts)
     f = kkt.Factor(sym)
     f.set_schedule(schedule)
     f.set_update_split(*split)
+    f.set_small_fronts(small)
     d = [_dev(vals.w_vals), _dev(vals.j_vals), _dev(vals.sigma_x), _dev(vals.sigma_s)]
     b = _dev(vals.b)
     x = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
@@ -133,8 +142,9 @@ def tune_pattern(pat, vals, reps: int = 3, table_path: str | None = DEFAULT_TABL
 
     The symbolic candidates are timed under the level schedule; then the best
     few are timed again under every schedule in `schedules`, and the fastest
-    option set under the level schedule with every launch shape in SPLITS.
-    The result holds the symbolic options, a "schedule" and a "split" entry."""
+    option set under the level schedule with every launch shape in SPLITS and
+    then every threshold in SMALLS. The result holds the symbolic options and
+    the "schedule", "split" and "small" entries."""
     key = signature(pat)
     table = load_table(table_path) if table_path else {}
     if not force and key in table:
@@ -147,7 +157,7 @@ def tune_pattern(pat, vals, reps: int = 3, table_path: str | None = DEFAULT_TABL
             if log:
                 log(f"{opts}: {e}")
             continue
-        results.append((t, eta, dict(opts, schedule=kkt.SCHEDULE_LEVELS, split=SPLITS[0]), st))
+        results.append((t, eta, dict(opts, schedule=kkt.SCHEDULE_LEVELS, split=SPLITS[0], small=SMALLS[0]), st))
         if log:
             log(f"{opts}: {1e3 * t:.3f} ms, eta {eta:.1e}, levels {st['levels']}, flops {st['flops']:.3g}")
     # other schedules for the three fastest option sets
@@ -158,17 +168,26 @@ def tune_pattern(pat, vals, reps: int = 3, table_path: str | None = DEFAULT_TABL
         for _, _, o, _ in top:
             opts = {k: o[k] for k in ("ordering", "nd_leaf", "max_super")}
             t, eta, st = _time_plain(pat, vals, opts, reps, sched)
-            results.append((t, eta, dict(opts, schedule=sched, split=SPLITS[0]), st))
+            results.append((t, eta, dict(opts, schedule=sched, split=SPLITS[0], small=SMALLS[0]), st))
             if log:
                 log(f"{opts} schedule {sched}: {1e3 * t:.3f} ms, eta {eta:.1e}")
     # launch shapes of the update matrices for the fastest option set
     if top:
         opts = {k: top[0][2][k] for k in ("ordering", "nd_leaf", "max_super")}
+        best_split, t_split = SPLITS[0], top[0][0]
         for split in SPLITS[1:]:
             t, eta, st = _time_plain(pat, vals, opts, reps, kkt.SCHEDULE_LEVELS, split)
-            results.append((t, eta, dict(opts, schedule=kkt.SCHEDULE_LEVELS, split=split), st))
+            results.append((t, eta, dict(opts, schedule=kkt.SCHEDULE_LEVELS, split=split, small=SMALLS[0]), st))
             if log:
                 log(f"{opts} split {split}: {1e3 * t:.3f} ms, eta {eta:.1e}")
+            if eta <= ETA_GATE and t < t_split:
+                best_split, t_split = split, t
+        # workgroup size of the front factorization, at the fastest split
+        for small in SMALLS[1:]:
+            t, eta, st = _time_plain(pat, vals, opts, reps, kkt.SCHEDULE_LEVELS, best_split, small)
+            results.append((t, eta, dict(opts, schedule=kkt.SCHEDULE_LEVELS, split=best_split, small=small), st))
+            if log:
+                log(f"{opts} split {best_split} small {small}: {1e3 * t:.3f} ms, eta {eta:.1e}")
     ok = [r for r in results if r[1] <= ETA_GATE]
     if not ok:
         raise RuntimeError("no candidate passed the backward-error gate")
@@ -197,15 +216,18 @@ def tune_batch(pats, vals, reps: int = 2, log=None, threads: int = 16) -> dict:
     b = _dev(np.concatenate([v.b for v in vals]))
     x = torch.zeros(sum(p.n for p in pats), dtype=torch.float64, device="cuda")
     tried = []
+    # every option set under the level schedule with each workgroup-size
+    # threshold, and under the queue schedule (eight-wave fronts only)
     for opts in batch_candidates(nmax):
         syms = analyze_many(pats, threads, **opts)
         B = kkt.Batch(syms)
-        for sched in (kkt.SCHEDULE_LEVELS, kkt.SCHEDULE_QUEUE):
+        for sched, small in [(kkt.SCHEDULE_LEVELS, sm) for sm in SMALLS] + [(kkt.SCHEDULE_QUEUE, SMALLS[0])]:
             B.set_schedule(sched)
+            B.set_small_fronts(small)
             t, eta = _time_batch(B, cat, b, x, reps)
-            tried.append((t, eta, dict(opts, schedule=sched)))
+            tried.append((t, eta, dict(opts, schedule=sched, small=small)))
             if log:
-                log(f"{opts} schedule {sched}: {1e3 * t:.3f} ms, eta {eta:.1e}")
+                log(f"{opts} schedule {sched} small {small}: {1e3 * t:.3f} ms, eta {eta:.1e}")
         B.close()
     ok = [r for r in tried if r[1] <= ETA_GATE]
     if not ok:
@@ -216,13 +238,14 @@ def tune_batch(pats, vals, reps: int = 2, log=None, threads: int = 16) -> dict:
     if best["schedule"] == kkt.SCHEDULE_LEVELS:
         opts = {k: best[k] for k in ("ordering", "nd_leaf", "max_super")}
         B = kkt.Batch(analyze_many(pats, threads, **opts))
+        B.set_small_fronts(best["small"])
         for split in SPLITS[1:]:
             B.set_update_split(*split)
             ts, eta = _time_batch(B, cat, b, x, reps)
-            tried.append((ts, eta, dict(opts, schedule=kkt.SCHEDULE_LEVELS, split=split)))
+            tried.append((ts, eta, dict(opts, schedule=kkt.SCHEDULE_LEVELS, small=best["small"], split=split)))
             if log:
-                log(f"{opts} split {split}: {1e3 * ts:.3f} ms, eta {eta:.1e}")
+                log(f"{opts} small {best['small']} split {split}: {1e3 * ts:.3f} ms, eta {eta:.1e}")
             if eta <= ETA_GATE and ts < t:
-                t, best = ts, dict(opts, schedule=kkt.SCHEDULE_LEVELS, split=split)
+                t, best = ts, dict(opts, schedule=kkt.SCHEDULE_LEVELS, small=best["small"], split=split)
         B.close()
     return dict(best=best, ms=1e3 * t, tried=[dict(options=o, ms=round(1e3 * tt, 3)) for tt, _, o in tried])

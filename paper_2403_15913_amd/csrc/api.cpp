@@ -404,11 +404,15 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     up.reserve(nup);
     up_ptr.assign(1, 0);
     lvl_maxu.assign(lvl_ptr.size() - 1, 0);
+    lvl_flds.assign(lvl_ptr.size() - 1, 0);
+    lvl_maxc.assign(lvl_ptr.size() - 1, 0);
     for (size_t l = 0; l + 1 < lvl_ptr.size(); l++) {
         for (int t = lvl_ptr[l]; t < lvl_ptr[l + 1]; t++) {
             const Symbolic& S = *s[sn[t].inst];
             const int u = S.sn_nrow[sn[t].id] - S.sn_ncol[sn[t].id];
             lvl_maxu[l] = std::max(lvl_maxu[l], u);
+            lvl_flds[l] = std::max(lvl_flds[l], (size_t)factor_lds_bytes(S.sn_nrow[sn[t].id], S.sn_ncol[sn[t].id]));
+            lvl_maxc[l] = std::max(lvl_maxc[l], S.sn_ncol[sn[t].id]);
             const int nbu = (u + 15) / 16;
             for (int tj = 0; tj < nbu; tj++)
                 for (int ti = tj; ti < nbu; ti++) up.push_back(StripItem{sn[t].inst, sn[t].id, (ti << 16) | tj, t});
@@ -612,7 +616,12 @@ kkt_status Engine::refactor(const Calls& Cin, hipStream_t st) {
         for (size_t l = 0; l + 1 < lvl_ptr.size(); l++) {
             const int nf = lvl_ptr[l + 1] - lvl_ptr[l];
             const bool split = split_update && nf < split_max_fronts && lvl_maxu[l] >= split_min_rows;
-            TL(KKT_PHASE_FACTOR, launch_factor(di(), fdesc + lvl_ptr[l], nf, lds_factor, split ? 0 : 1, st));
+            // levels of narrow fronts: four-wave workgroups sized to the
+            // level's own largest front, so several share a compute unit
+            if (lvl_maxc[l] <= small_front_cols)
+                TL(KKT_PHASE_FACTOR, launch_factor_small(di(), fdesc + lvl_ptr[l], nf, lvl_flds[l], split ? 0 : 1, st));
+            else
+                TL(KKT_PHASE_FACTOR, launch_factor(di(), fdesc + lvl_ptr[l], nf, lds_factor, split ? 0 : 1, st));
             if (split) TL(KKT_PHASE_FACTOR, launch_update(di(), fdesc, upitems + up_ptr[l], up_ptr[l + 1] - up_ptr[l], st));
         }
     }
@@ -1339,6 +1348,13 @@ kkt_status kkt_factor_set_update_split(kkt_factor* f, int32_t max_fronts, int32_
     return KKT_OK;
 }
 
+kkt_status kkt_factor_set_small_fronts(kkt_factor* f, int32_t max_cols) {
+    if (!f) return fail(KKT_ERR_INVALID_ARG, "NULL factor");
+    if (max_cols < 0) return fail(KKT_ERR_INVALID_ARG, "negative column threshold");
+    f->eng.small_front_cols = max_cols;
+    return KKT_OK;
+}
+
 kkt_status kkt_factor_read_timing(kkt_factor* f, kkt_timing* out) {
     if (!f || !out) return fail(KKT_ERR_INVALID_ARG, "NULL argument");
     return timing_read(f->eng, out);
@@ -1447,6 +1463,13 @@ kkt_status kkt_batch_set_update_split(kkt_batch* b, int32_t max_fronts, int32_t 
     if (max_fronts < 0 || min_rows < 0) return fail(KKT_ERR_INVALID_ARG, "negative split threshold");
     b->eng.split_max_fronts = max_fronts;
     b->eng.split_min_rows = min_rows;
+    return KKT_OK;
+}
+
+kkt_status kkt_batch_set_small_fronts(kkt_batch* b, int32_t max_cols) {
+    if (!b) return fail(KKT_ERR_INVALID_ARG, "NULL batch");
+    if (max_cols < 0) return fail(KKT_ERR_INVALID_ARG, "negative column threshold");
+    b->eng.small_front_cols = max_cols;
     return KKT_OK;
 }
 

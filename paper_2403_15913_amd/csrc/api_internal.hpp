@@ -97,6 +97,9 @@ struct Engine {
     StripItem* upitems = nullptr;                   // update-matrix tiles by level (level schedule)
     std::vector<int> up_ptr;
     std::vector<int> lvl_maxu;                      // widest update part of each level
+    std::vector<size_t> lvl_flds;                   // factor LDS of each level's largest front
+    std::vector<int> lvl_maxc;                      // widest front (columns) of each level
+    int small_front_cols = 0;                       // levels whose fronts have at most this many columns: four-wave factor
     bool split_update = true;                       // level schedule: update matrices in their own launch
     int split_max_fronts = kSplitMaxFronts;         // ... on levels with fewer fronts than this
     int split_min_rows = kSplitMinRows;             // ... whose widest update part has at least this many rows

@@ -26,6 +26,12 @@
 
 namespace kkt {
 
+#ifndef KKT_SMALL_WAVES_PER_EU
+#define KKT_SMALL_WAVES_PER_EU 2
+#endif
+#ifndef KKT_SMALL_EU
+#define KKT_SMALL_EU 12
+#endif
 #define KKT_ST_NOT_SPD 4
 #define KKT_ST_NONFINITE 5
 
@@ -413,7 +419,11 @@ __device__ inline void tri_tile(int t, int tj0, int nb, int& ti, int& tj) {
 // cores), then the update matrix U = -L21 L21^T is formed on the matrix cores
 // and the children's pass-through entries are added to it.
 constexpr int kFactorThreads = 512;
-static_assert(kFactorThreads == 512, "the panel schedule assumes eight waves");
+// small fronts: four waves per workgroup, so several fronts share a
+// compute unit (registers for two workgroups per compute unit at least)
+constexpr int kFactorThreadsSmall = 256;
+static_assert(kFactorThreads == 512 && kFactorThreadsSmall == 256,
+              "the panel schedule is written for eight or four waves");
 
 // EU: extend-add entries per thread and batch (register budget of the caller)
 template <int EU>
@@ -763,10 +773,13 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const FrontDesc& 
     // block order. Fronts taller than waves 0-3 can cover, and the
     // persistent queue kernel, take the pivot chain by wave 0 and a
     // separate triangular solve of the rows below (same arithmetic).
-    if (fused_panel && r <= 16 + 4 * 64) {
+    // panel waves: at most four, and at least one wave is left for the
+    // look-ahead update
+    const int maxp = min(4, nwave - 1);
+    if (fused_panel && r <= 16 + maxp * 64) {
         // panel waves: one per 64 rows below the diagonal block (at least
         // one), the rest take the look-ahead update
-        auto npanel = [&](const int kb) { return min(4, max(1, (r - (kb << 4) - 16 + 63) >> 6)); };
+        auto npanel = [&](const int kb) { return min(maxp, max(1, (r - (kb << 4) - 16 + 63) >> 6)); };
         // wave 0, after the barrier that ends panel_block(kb): the factored
         // diagonal block kb into the panel. Nothing reads or writes that block
         // until the panel is copied out (the updates touch the rows below it
@@ -794,9 +807,11 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const FrontDesc& 
         if (wave == 0) flush_diag(nbc - 1);
         __syncthreads();
     } else {
-        // the wave that shares wave 0's SIMD stays out of the look-ahead
-        // update, so the pivot chain has its SIMD to itself
-        const int upd_w = wave - 1 - (wave > 4 ? 1 : 0), upd_n = nwave - 2;
+        // with eight waves, the wave that shares wave 0's SIMD (wave 4) stays
+        // out of the look-ahead update, so the pivot chain has its SIMD to
+        // itself; with four waves, waves 1-3 take it
+        const bool eight = nwave == 8;
+        const int upd_w = wave - 1 - (eight && wave > 4 ? 1 : 0), upd_n = eight ? nwave - 2 : nwave - 1;
         if (wave == 0) diag_block(0);
         __syncthreads();
         trsm_block(0);
@@ -805,7 +820,7 @@ __device__ __forceinline__ void factor_front(const InstDev& I, const FrontDesc& 
             update_tiles(kb, kb + 1, kb + 2, wave, nwave);
             __syncthreads();
             if (wave == 0) diag_block(kb + 1);
-            else if (wave != 4) update_tiles(kb, kb + 2, nbc, upd_w, upd_n);
+            else if (!eight || wave != 4) update_tiles(kb, kb + 2, nbc, upd_w, upd_n);
             __syncthreads();
             trsm_block(kb + 1);
             __syncthreads();
@@ -906,6 +921,16 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(const InstDev* __rest
     __shared__ double invd[16];
     const FrontDesc& F = fds[blockIdx.x];
     factor_front<18>(insts[F.inst], F, P, invd, fused_update != 0, true);
+}
+
+// the same front factorization by four waves (every entry takes the same
+// operations in the same order as in k_factor)
+__global__ __launch_bounds__(kFactorThreadsSmall) __attribute__((amdgpu_waves_per_eu(KKT_SMALL_WAVES_PER_EU)))
+void k_factor_small(const InstDev* __restrict__ insts, const FrontDesc* __restrict__ fds, int fused_update) {
+    extern __shared__ __align__(16) double P[];
+    __shared__ double invd[16];
+    const FrontDesc& F = fds[blockIdx.x];
+    factor_front<KKT_SMALL_EU>(insts[F.inst], F, P, invd, fused_update != 0, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -3087,6 +3112,8 @@ hipError_t set_kernel_attributes() {
     const int lds = kMaxDynLds;
     hipError_t e = hipFuncSetAttribute((const void*)k_factor, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)k_factor_small, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void*)k_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void*)k_factor_queue, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -3214,6 +3241,10 @@ void launch_assemble(const InstDev* insts, const Calls& C, const WorkItem* items
 void launch_factor(const InstDev* insts, const FrontDesc* fds, int nitems, size_t lds, int fused_update,
                    hipStream_t st) {
     if (nitems > 0) k_factor<<<nitems, kFactorThreads, lds, st>>>(insts, fds, fused_update);
+}
+void launch_factor_small(const InstDev* insts, const FrontDesc* fds, int nitems, size_t lds, int fused_update,
+                         hipStream_t st) {
+    if (nitems > 0) k_factor_small<<<nitems, kFactorThreadsSmall, lds, st>>>(insts, fds, fused_update);
 }
 void launch_update(const InstDev* insts, const FrontDesc* fds, const StripItem* items, int nitems, hipStream_t st) {
     if (nitems > 0) k_update<<<nitems, kUpdThreads, 0, st>>>(insts, fds, items);

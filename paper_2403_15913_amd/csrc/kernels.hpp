@@ -99,6 +99,9 @@ void launch_assemble(const InstDev* insts, const Calls& C, const WorkItem* items
 void launch_assemble_heavy(const InstDev* insts, const Calls& C, const WorkItem* items, int nitems, hipStream_t st);
 void launch_factor(const InstDev* insts, const FrontDesc* fds, int nitems, size_t lds, int fused_update,
                    hipStream_t st);
+// the same with four-wave workgroups (lds: the level's own largest front)
+void launch_factor_small(const InstDev* insts, const FrontDesc* fds, int nitems, size_t lds, int fused_update,
+                         hipStream_t st);
 // update matrices by 16-column strips (after the factor launch of the same level)
 void launch_update(const InstDev* insts, const FrontDesc* fds, const StripItem* items, int nitems, hipStream_t st);
 void launch_factor_queue(const InstDev* insts, const FrontDesc* fds, const DepLists& D, int grid, size_t lds,

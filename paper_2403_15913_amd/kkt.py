@@ -149,6 +149,7 @@ SIGNATURES = {
     "kkt_factor_read_timing": (I32, [P, P]),
     "kkt_factor_set_schedule": (I32, [P, I32]),
     "kkt_factor_set_update_split": (I32, [P, I32, I32]),
+    "kkt_factor_set_small_fronts": (I32, [P, I32]),
     "kkt_batch_create": (I32, [I32, P, P]),
     "kkt_batch_destroy": (None, [P]),
     "kkt_batch_offsets": (I32, [P, P, P, P, P]),
@@ -159,6 +160,7 @@ SIGNATURES = {
     "kkt_batch_read_timing": (I32, [P, P]),
     "kkt_batch_set_schedule": (I32, [P, I32]),
     "kkt_batch_set_update_split": (I32, [P, I32, I32]),
+    "kkt_batch_set_small_fronts": (I32, [P, I32]),
     "kkt_batch_capture": (I32, [P, P, P, P, P, P, P, P, I32]),
     "kkt_batch_replay": (I32, [P, P, P]),
     "kkt_stagewise_create": (I32, [I32, P, P, P, P]),
@@ -398,6 +400,10 @@ def kkt_factor_set_update_split(h, max_fronts: int, min_rows: int):
     _err(lib().kkt_factor_set_update_split(h, int(max_fronts), int(min_rows)))
 
 
+def kkt_factor_set_small_fronts(h, max_cols: int):
+    _err(lib().kkt_factor_set_small_fronts(h, int(max_cols)))
+
+
 # ---------------------------------------------------------------------------
 # handle wrappers
 # ---------------------------------------------------------------------------
@@ -487,6 +493,9 @@ class Factor:
 
     def set_update_split(self, max_fronts: int, min_rows: int):
         kkt_factor_set_update_split(self.h, max_fronts, min_rows)
+
+    def set_small_fronts(self, max_cols: int):
+        kkt_factor_set_small_fronts(self.h, max_cols)
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
@@ -578,6 +587,9 @@ class Batch:
 
     def set_update_split(self, max_fronts: int, min_rows: int):
         _err(lib().kkt_batch_set_update_split(self.h, int(max_fronts), int(min_rows)))
+
+    def set_small_fronts(self, max_cols: int):
+        _err(lib().kkt_batch_set_small_fronts(self.h, int(max_cols)))
 
     def capture(self, w_vals, j_vals, sigma_x, sigma_s, b, x, max_iter=10, tol=1e-14, rounds=2):
         """Record refactor + solve as a graph bound to these arrays (kept alive here)."""

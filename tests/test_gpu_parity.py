@@ -496,3 +496,50 @@ def test_update_split_bitwise(kkt, nd):
     assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[0], xs[2])
     with pytest.raises(kkt.KKTError):
         kkt.Factor(sym).set_update_split(-1, 0)
+
+
+@pytest.mark.parametrize("case", ["distillation-nd", "distillation-natural", "nmpc-batch"])
+def test_small_fronts_bitwise(kkt, case):
+    """The four-wave front factorization (levels of narrow fronts; fronts of
+    at most 208 rows take the fused panel path, taller ones the pivot chain
+    plus row-by-row TRSM) changes no bit of the solution against the
+    eight-wave one, for a plain factor and for a batch; every level by four
+    waves, none, and a threshold in between; eta <= 1e-10."""
+    if case == "nmpc-batch":
+        shapes = kktgen.batch_shapes(6)
+        pats = [kktgen.nmpc_pattern(*sh) for sh in shapes]
+        vals = [kktgen.nmpc_values(p, kktgen.rng_for(3, q, 1), 1e-6, 1e6) for q, p in enumerate(pats)]
+        syms = [kkt.Symbolic.from_pattern(p, ordering=2, nd_leaf=64, max_super=48) for p in pats]
+    else:
+        pat = kktgen.distillation_pattern(40)
+        v = kktgen.distillation_values(pat, kktgen.rng_for(1, 40, 0), 1e-8, 1e8)
+        opts = dict(ordering=2, nd_leaf=200) if case.endswith("nd") else dict(ordering=1)
+        pats, vals, syms = [pat], [v], [kkt.Symbolic.from_pattern(pat, **opts)]
+    max_rows = max(s.stats()["max_rows"] for s in syms)
+    print(f"{case}: {len(syms)} instance(s), fronts up to {max_rows} rows", flush=True)
+    xs_plain, xs_batch = [], []
+    for small in (0, 48, 1 << 20):
+        xp = []
+        for pat, v, sym in zip(pats, vals, syms):
+            f = kkt.Factor(sym)
+            f.set_small_fronts(small)
+            f.refactor(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), dev(v.sigma_s))
+            x = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
+            info = f.solve(dev(v.b), x)
+            assert info["eta"] <= 1e-10, (small, info)
+            xp.append(host(x))
+            f.close()
+        xs_plain.append(np.concatenate(xp))
+        B = kkt.Batch(syms)
+        B.set_small_fronts(small)
+        cat = lambda f: dev(np.concatenate([getattr(v, f) for v in vals]))
+        B.refactor(cat("w_vals"), cat("j_vals"), cat("sigma_x"), cat("sigma_s"))
+        xb = torch.zeros(sum(p.n for p in pats), dtype=torch.float64, device="cuda")
+        B.solve(cat("b"), xb)
+        xs_batch.append(host(xb))
+        B.close()
+    for k in range(3):
+        assert np.array_equal(xs_plain[k], xs_plain[0]), k
+        assert np.array_equal(xs_batch[k], xs_plain[0]), k
+    with pytest.raises(kkt.KKTError):
+        kkt.Factor(syms[0]).set_small_fronts(-1)
