@@ -84,6 +84,10 @@ typedef struct kkt_options {
     int32_t max_super;     /* widest supernode in columns (0: 96) */
     int32_t relax_small;   /* supernodes up to this width always amalgamate (0: 16, <0: none) */
     double relax_frac;     /* amalgamation may add up to this fraction of explicit zeros (<0: 0.5) */
+    int32_t front_lds_max; /* LDS bytes one front panel may use (0 or more than 158 KiB: 158 KiB). A
+                              front too tall to fit at one column is a large front: at most 64 columns,
+                              assembled, factored and solved in place in HBM (one workgroup per front
+                              and level, update matrix by one wave per tile); the level schedule only */
 } kkt_options;
 
 typedef struct kkt_symbolic_stats {
@@ -99,6 +103,7 @@ typedef struct kkt_symbolic_stats {
     double flops;          /* dense front work of one factorisation */
     double flops_exact;    /* sum over columns of (column count)^2 */
     double analyze_seconds;
+    int32_t large_fronts;  /* fronts factored and solved in HBM (see kkt_options.front_lds_max) */
 } kkt_symbolic_stats;
 
 typedef struct kkt_refine_opts {

@@ -193,6 +193,10 @@ hipError_t Engine::ensure_pinned(size_t bytes) {
 }
 
 namespace {
+// a front whose panel does not fit the symbolic analysis' LDS budget: factored
+// and solved in place in HBM
+bool is_large(const Symbolic& S, int k) { return front_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]) > S.lds_budget; }
+
 // bump allocator over an arena (256-byte aligned pieces); measures when base is NULL
 struct Carver {
     char* base;
@@ -213,6 +217,7 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     syms = s;
     pat_of = p;
     ninst = (int)s.size();
+    n_large = 0;
     n_ofs.assign(ninst + 1, 0);
     m_ofs.assign(ninst + 1, 0);
     w_ofs.assign(ninst + 1, 0);
@@ -241,8 +246,14 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         // 256-row block of n and of m
         ro[q + 1] = ro[q] + 8 * (int64_t)((S.n + kBlock - 1) / kBlock + (S.m + kBlock - 1) / kBlock) + 4;
         for (int k = 0; k < S.ns; k++) {
-            lds_factor = std::max(lds_factor, (size_t)factor_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]));
-            lds_solve = std::max(lds_solve, (size_t)solve_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]));
+            // large fronts are factored and solved in HBM (no panel in LDS)
+            if (is_large(S, k)) {
+                if (S.sn_ncol[k] > kLargeFrontCols) return fail(KKT_ERR_PATTERN, "large front wider than 64 columns");
+                n_large++;
+            } else {
+                lds_factor = std::max(lds_factor, (size_t)factor_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]));
+                lds_solve = std::max(lds_solve, (size_t)solve_lds_bytes(S.sn_nrow[k], S.sn_ncol[k]));
+            }
             const size_t nbu = (size_t)(S.sn_nrow[k] - S.sn_ncol[k] + 15) / 16;
             nup += nbu * (nbu + 1) / 2;
         }
@@ -362,6 +373,7 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     std::vector<WorkItem> sn, nb, mb, kb, jb;
     sn.reserve(nsn);
     lvl_ptr.assign(1, 0);
+    lvl_large.clear();
     sw_part.clear();
     sw_lvl.assign(1, 0);
     for (int l = 0; l < nlev; l++) {
@@ -377,18 +389,23 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         // they go first and get a launch of their own (launches on one stream
         // run one after the other, so a split pays only for wide levels).
         const int b0 = lvl_ptr.back();
+        // large fronts last in the level (their own launches)
+        const int bl = (int)(std::stable_partition(sn.begin() + b0, sn.end(),
+                                                   [&](const WorkItem& w) { return !is_large(*s[w.inst], w.id); }) -
+                             sn.begin());
+        lvl_large.push_back(bl);
         auto slds = [&](const WorkItem& w) {
             const Symbolic& S = *s[w.inst];
             return (size_t)solve_lds_bytes(S.sn_nrow[w.id], S.sn_ncol[w.id]);
         };
         int nsmall = 0;
-        for (size_t t = b0; t < sn.size(); t++) nsmall += slds(sn[t]) <= kSweepHalfLds;
+        for (int t = b0; t < bl; t++) nsmall += slds(sn[t]) <= kSweepHalfLds;
         int b1 = b0;
-        if (nsmall >= kSweepSplitMin && nsmall < (int)sn.size() - b0)
-            b1 = (int)(std::stable_partition(sn.begin() + b0, sn.end(),
+        if (nsmall >= kSweepSplitMin && nsmall < bl - b0)
+            b1 = (int)(std::stable_partition(sn.begin() + b0, sn.begin() + bl,
                                              [&](const WorkItem& w) { return slds(w) <= kSweepHalfLds; }) -
                        sn.begin());
-        const int b2 = (int)sn.size();
+        const int b2 = bl;
         for (int c = 0; c < 2; c++) {
             const int lo_i = c ? b1 : b0, hi_i = c ? b2 : b1;
             if (hi_i == lo_i) continue;
@@ -403,20 +420,26 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     std::vector<StripItem> up;
     up.reserve(nup);
     up_ptr.assign(1, 0);
+    upl_ptr.clear();
     lvl_maxu.assign(lvl_ptr.size() - 1, 0);
     lvl_flds.assign(lvl_ptr.size() - 1, 0);
     lvl_maxc.assign(lvl_ptr.size() - 1, 0);
+    // per level: the LDS fronts' tiles, then the large fronts' tiles
     for (size_t l = 0; l + 1 < lvl_ptr.size(); l++) {
         for (int t = lvl_ptr[l]; t < lvl_ptr[l + 1]; t++) {
+            if (t == lvl_large[l]) upl_ptr.push_back((int)up.size());
             const Symbolic& S = *s[sn[t].inst];
             const int u = S.sn_nrow[sn[t].id] - S.sn_ncol[sn[t].id];
-            lvl_maxu[l] = std::max(lvl_maxu[l], u);
-            lvl_flds[l] = std::max(lvl_flds[l], (size_t)factor_lds_bytes(S.sn_nrow[sn[t].id], S.sn_ncol[sn[t].id]));
-            lvl_maxc[l] = std::max(lvl_maxc[l], S.sn_ncol[sn[t].id]);
+            if (t < lvl_large[l]) {
+                lvl_maxu[l] = std::max(lvl_maxu[l], u);
+                lvl_flds[l] = std::max(lvl_flds[l], (size_t)factor_lds_bytes(S.sn_nrow[sn[t].id], S.sn_ncol[sn[t].id]));
+                lvl_maxc[l] = std::max(lvl_maxc[l], S.sn_ncol[sn[t].id]);
+            }
             const int nbu = (u + 15) / 16;
             for (int tj = 0; tj < nbu; tj++)
                 for (int ti = tj; ti < nbu; ti++) up.push_back(StripItem{sn[t].inst, sn[t].id, (ti << 16) | tj, t});
         }
+        if (lvl_large[l] == lvl_ptr[l + 1]) upl_ptr.push_back((int)up.size());
         up_ptr.push_back((int)up.size());
     }
     // dependency lists in the same (topological) item order
@@ -589,6 +612,7 @@ kkt_status Engine::assemble(const Calls& C, hipStream_t st) {
 }
 
 kkt_status Engine::refactor(const Calls& Cin, hipStream_t st) {
+    if (queue_sched && n_large > 0) return fail(KKT_ERR_INVALID_ARG, "the queue schedule needs every front in LDS");
     last_stream = st;
     mode = Cin.eqm ? 3 : (Cin.gamma == 0.0 ? 1 : 2);
     gamma = Cin.gamma;
@@ -614,15 +638,25 @@ kkt_status Engine::refactor(const Calls& Cin, hipStream_t st) {
         // keep them in the factor kernel. Both paths give every entry the
         // same operations in the same order.
         for (size_t l = 0; l + 1 < lvl_ptr.size(); l++) {
-            const int nf = lvl_ptr[l + 1] - lvl_ptr[l];
-            const bool split = split_update && nf < split_max_fronts && lvl_maxu[l] >= split_min_rows;
-            // levels of narrow fronts: four-wave workgroups sized to the
-            // level's own largest front, so several share a compute unit
-            if (lvl_maxc[l] <= small_front_cols)
-                TL(KKT_PHASE_FACTOR, launch_factor_small(di(), fdesc + lvl_ptr[l], nf, lvl_flds[l], split ? 0 : 1, st));
-            else
-                TL(KKT_PHASE_FACTOR, launch_factor(di(), fdesc + lvl_ptr[l], nf, lds_factor, split ? 0 : 1, st));
-            if (split) TL(KKT_PHASE_FACTOR, launch_update(di(), fdesc, upitems + up_ptr[l], up_ptr[l + 1] - up_ptr[l], st));
+            const int nf = lvl_large[l] - lvl_ptr[l], nlarge = lvl_ptr[l + 1] - lvl_large[l];
+            if (nf > 0) {
+                const bool split = split_update && nf < split_max_fronts && lvl_maxu[l] >= split_min_rows;
+                // levels of narrow fronts: four-wave workgroups sized to the
+                // level's own largest front, so several share a compute unit
+                if (lvl_maxc[l] <= small_front_cols)
+                    TL(KKT_PHASE_FACTOR,
+                       launch_factor_small(di(), fdesc + lvl_ptr[l], nf, lvl_flds[l], split ? 0 : 1, st));
+                else
+                    TL(KKT_PHASE_FACTOR, launch_factor(di(), fdesc + lvl_ptr[l], nf, lds_factor, split ? 0 : 1, st));
+                if (split)
+                    TL(KKT_PHASE_FACTOR,
+                       launch_update(di(), fdesc, upitems + up_ptr[l], upl_ptr[l] - up_ptr[l], st));
+            }
+            // large fronts: panels factored in HBM, then their update matrices by tiles
+            if (nlarge > 0) {
+                TL(KKT_PHASE_FACTOR, launch_big_factor(di(), fdesc + lvl_large[l], nlarge, st));
+                TL(KKT_PHASE_FACTOR, launch_update(di(), fdesc, upitems + upl_ptr[l], up_ptr[l + 1] - upl_ptr[l], st));
+            }
         }
     }
     if (mode == 2) TL(KKT_PHASE_ASSEMBLE, launch_jcopy(di(), C, jitems, n_jitems, st));
@@ -642,16 +676,22 @@ void Engine::sweeps(hipStream_t st, int skip_done) {
         return;
     }
     const int nl = (int)lvl_ptr.size() - 1;
-    for (int l = 0; l < nl; l++)
+    for (int l = 0; l < nl; l++) {
         for (int k = sw_lvl[l]; k < sw_lvl[l + 1]; k++) {
             const SweepPart& P = sw_part[k];
             TL(KKT_PHASE_FWD, launch_fwd(di(), fdesc + P.begin, P.count, P.lds, skip_done, st));
         }
-    for (int l = nl - 1; l >= 0; l--)
+        if (lvl_large[l] < lvl_ptr[l + 1])
+            TL(KKT_PHASE_FWD, launch_big_fwd(di(), fdesc + lvl_large[l], lvl_ptr[l + 1] - lvl_large[l], skip_done, st));
+    }
+    for (int l = nl - 1; l >= 0; l--) {
+        if (lvl_large[l] < lvl_ptr[l + 1])
+            TL(KKT_PHASE_BWD, launch_big_bwd(fdesc + lvl_large[l], lvl_ptr[l + 1] - lvl_large[l], skip_done, st));
         for (int k = sw_lvl[l]; k < sw_lvl[l + 1]; k++) {
             const SweepPart& P = sw_part[k];
             TL(KKT_PHASE_BWD, launch_bwd(fdesc + P.begin, P.count, P.lds, skip_done, st));
         }
+    }
 }
 
 kkt_status Engine::read_status(int* st_out, int* bad_out) {
@@ -991,6 +1031,7 @@ void kkt_options_default(kkt_options* opt) {
     opt->max_super = 96;
     opt->relax_small = 16;
     opt->relax_frac = 0.5;
+    opt->front_lds_max = 0;
 }
 
 const char* kkt_status_string(kkt_status s) {
@@ -1028,7 +1069,9 @@ kkt_status kkt_symbolic_analyze(int32_t n, int32_t m, const int32_t* w_rowptr, c
     if (so.max_super > 128) return fail(KKT_ERR_INVALID_ARG, "max_super must be <= 128");
     so.relax_small = o.relax_small == 0 ? 16 : (o.relax_small < 0 ? 0 : o.relax_small);
     so.relax_frac = o.relax_frac < 0 ? 0.5 : o.relax_frac;
-    so.lds_bytes = kMaxDynLds;
+    if (o.front_lds_max < 0) return fail(KKT_ERR_INVALID_ARG, "negative front_lds_max");
+    // at least one 16 x 16 block of a front must fit
+    so.lds_bytes = o.front_lds_max == 0 ? kMaxDynLds : std::min(std::max(o.front_lds_max, 4096), kMaxDynLds);
     kkt_symbolic* sym = new (std::nothrow) kkt_symbolic;
     if (!sym) return fail(KKT_ERR_OOM, "host allocation");
     std::string err;
@@ -1068,6 +1111,7 @@ kkt_status kkt_symbolic_get_stats(const kkt_symbolic* sym, kkt_symbolic_stats* o
     out->flops = S.flops;
     out->flops_exact = S.flops_exact;
     out->analyze_seconds = S.analyze_seconds;
+    out->large_fronts = S.n_large;
     return KKT_OK;
 }
 
@@ -1336,6 +1380,8 @@ kkt_status kkt_factor_set_schedule(kkt_factor* f, int32_t schedule) {
     if (!f) return fail(KKT_ERR_INVALID_ARG, "NULL factor");
     if (schedule != KKT_SCHEDULE_LEVELS && schedule != KKT_SCHEDULE_QUEUE)
         return fail(KKT_ERR_INVALID_ARG, "unknown schedule");
+    if (schedule == KKT_SCHEDULE_QUEUE && f->eng.n_large > 0)
+        return fail(KKT_ERR_INVALID_ARG, "the queue schedule needs every front in LDS (this pattern has large fronts)");
     f->eng.queue_sched = schedule == KKT_SCHEDULE_QUEUE;
     return KKT_OK;
 }
@@ -1454,6 +1500,8 @@ kkt_status kkt_batch_set_schedule(kkt_batch* b, int32_t schedule) {
     if (!b) return fail(KKT_ERR_INVALID_ARG, "NULL batch");
     if (schedule != KKT_SCHEDULE_LEVELS && schedule != KKT_SCHEDULE_QUEUE)
         return fail(KKT_ERR_INVALID_ARG, "unknown schedule");
+    if (schedule == KKT_SCHEDULE_QUEUE && b->eng.n_large > 0)
+        return fail(KKT_ERR_INVALID_ARG, "the queue schedule needs every front in LDS (this pattern has large fronts)");
     b->eng.queue_sched = schedule == KKT_SCHEDULE_QUEUE;
     return KKT_OK;
 }

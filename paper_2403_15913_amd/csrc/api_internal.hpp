@@ -96,6 +96,9 @@ struct Engine {
     int *dep_parent = nullptr, *dep_nchild = nullptr, *dep_ctr = nullptr;  // queue scheduling
     StripItem* upitems = nullptr;                   // update-matrix tiles by level (level schedule)
     std::vector<int> up_ptr;
+    std::vector<int> upl_ptr;                       // per level: first tile of its large fronts
+    std::vector<int> lvl_large;                     // per level: first large front (they come last)
+    int n_large = 0;                                // large fronts (panels factored in HBM)
     std::vector<int> lvl_maxu;                      // widest update part of each level
     std::vector<size_t> lvl_flds;                   // factor LDS of each level's largest front
     std::vector<int> lvl_maxc;                      // widest front (columns) of each level

@@ -1045,6 +1045,145 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(const InstDev* __restric
 }
 
 // ---------------------------------------------------------------------------
+// large fronts: panels too tall for a workgroup's LDS (level schedule)
+// ---------------------------------------------------------------------------
+// The panel is assembled and factored in place in its HBM slot by one
+// workgroup per front; the update matrix is then formed by k_update's tiles,
+// which read the stored panel. Each entry of the panel takes the operations
+// of the LDS front kernel's non-fused path in the same order (assembly, the
+// pivot chain of each diagonal block, the row-by-row solve below it, the
+// blocks' updates in block order), so the factor does not depend on where
+// the panel lives. Columns past the panel read as zero, as the zero-padded
+// LDS panel does. Large fronts have at most 64 columns.
+constexpr int kBigThreads = 256;
+constexpr int kBigMaxCols = kLargeFrontCols;
+
+__global__ __launch_bounds__(kBigThreads) void k_big_factor(const InstDev* __restrict__ insts,
+                                                          const FrontDesc* __restrict__ fds) {
+    __shared__ double invd[16];
+    const FrontDesc& F = fds[blockIdx.x];
+    const InstDev& I = insts[F.inst];
+    const PatDev& T = I.P;
+    const int c = F.c, r = F.r, ld = r | 1, col0 = F.col0;
+    double* const P = F.L;
+    int* const status = I.status;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
+    // assembly: zero, the original entries of K, then the children's update
+    // entries whose column maps into the panel, child by child (the entries of
+    // one child are distinct; two children can add into the same entry)
+    const int64_t tot = (int64_t)ld * c;
+    for (int64_t q = tid; q < tot; q += nt) P[q] = 0.0;
+    __syncthreads();
+    for (int q = tid; q < F.nk; q += nt) {
+        const int loc = F.kl[q];
+        P[(int64_t)(loc >> 16) * ld + (loc & 0xffff)] = F.kv[q];
+    }
+    __syncthreads();
+    for (int k = 0; k < F.nch; k++) {
+        const int ch = T.ch_list[F.ch0 + k];
+        const int cc = T.sn_ncol[ch];
+        const int uc = T.sn_nrow[ch] - cc, nb = T.rel_np[ch];
+        const double* const Uc = I.U + T.sn_uofs[ch];
+        const int* const rl = T.rel + T.sn_rowofs[ch] + cc;
+        const int64_t ctot = (int64_t)nb * uc;
+        for (int64_t q = tid; q < ctot; q += nt) {
+            const int b = (int)(q / uc), a = (int)(q - (int64_t)b * uc);
+            if (a >= b) P[(int64_t)rl[b] * ld + rl[a]] += Uc[q];
+        }
+        __syncthreads();
+    }
+    const int nbc = (c + 15) >> 4, nbr = (r + 15) >> 4;
+    for (int kb = 0; kb < nbc; kb++) {
+        const int j0 = kb << 4, w = min(16, c - j0);
+        // diagonal block by wave 0: lane i of each 16-lane row holds row
+        // j0 + i; step j takes the pivot from lane j, scales column j and
+        // updates the later columns by row broadcasts
+        if (wave == 0) {
+            const int i = lane & 15;
+            const bool live = j0 + i < r;
+            const int row = min(j0 + i, r - 1);
+            double a[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) a[k] = (live && k < w) ? P[(int64_t)(j0 + k) * ld + row] : 0.0;
+            unsigned bad = 0;
+            static_for<16>([&](auto J) {
+                constexpr int j = J;
+                if (j < w) {
+                    double d = readfirstlane_d(row_bcast<j>(a[j]));
+                    if (!(d > 0.0) || !isfinite(d)) {
+                        bad |= 1u << j;
+                        d = 1.0;
+                    }
+                    double inv, ljj;
+                    pivot_roots(d, inv, ljj);
+                    a[j] = i == j ? ljj : a[j] * inv;
+                    if (lane == 0) invd[j] = inv;
+                    static_for<16>([&](auto K) {
+                        constexpr int k = K;
+                        if constexpr (k > j) a[k] = fma(-a[j], row_bcast<k>(a[j]), a[k]);
+                    });
+                }
+            });
+            if (bad && lane == 0) {
+                atomicMin(&status[1], col0 + j0 + __builtin_ctz(bad));
+                atomicMax(&status[0], KKT_ST_NOT_SPD);
+            }
+            if (lane < 16 && live) {
+#pragma unroll
+                for (int k = 0; k < 16; k++)
+                    if (k < w && k <= i) P[(int64_t)(j0 + k) * ld + j0 + i] = a[k];
+            }
+        }
+        __syncthreads();
+        // rows below the diagonal block, one per thread: x = p L_kk^{-T}
+        if (tid < w) F.dinv[j0 + tid] = invd[tid];
+        for (int i = j0 + 16 + tid; i < r; i += nt) {
+            double x[16], lc[16], ln[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) x[k] = k < w ? P[(int64_t)(j0 + k) * ld + i] : 0.0;
+#pragma unroll
+            for (int k = 0; k < 16; k++) lc[k] = P[(int64_t)j0 * ld + min(j0 + k, r - 1)];
+#pragma unroll
+            for (int j = 0; j < 16; j++) {
+                if (j + 1 < w) {
+#pragma unroll
+                    for (int k = 0; k < 16; k++) ln[k] = P[(int64_t)(j0 + j + 1) * ld + min(j0 + k, r - 1)];
+                }
+                if (j < w) {
+                    x[j] *= invd[j];
+#pragma unroll
+                    for (int k = j + 1; k < 16; k++) x[k] = fma(-x[j], lc[k], x[k]);
+                }
+#pragma unroll
+                for (int k = 0; k < 16; k++) lc[k] = ln[k];
+            }
+#pragma unroll
+            for (int k = 0; k < 16; k++)
+                if (k < w) P[(int64_t)(j0 + k) * ld + i] = x[k];
+        }
+        __syncthreads();
+        // the later column blocks take block kb's update (matrix cores, one
+        // 16 x 16 tile per wave at a time)
+        if (kb + 1 < nbc) {
+            int ntile = 0;
+            for (int jt = kb + 1; jt < nbc; jt++) ntile += nbr - jt;
+            for (int t = wave; t < ntile; t += nwave) {
+                int ti, tj;
+                tri_tile(t, kb + 1, nbr, ti, tj);
+                const d4 acc = tile_abt(P, ld, ti << 4, tj << 4, j0, 16, r, lane);
+                const int col = (tj << 4) + (lane & 15);
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int row = (ti << 4) + 4 * e + (lane >> 4);
+                    if (col < c && row >= col && row < r) P[(int64_t)col * ld + row] -= acc[e];
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // dependency-driven (persistent) scheduling
 // ---------------------------------------------------------------------------
 // Workgroups take tickets in a topological order of the fronts (children
@@ -1446,6 +1585,96 @@ __device__ __forceinline__ void bwd_front(const FrontDesc& F, double* __restrict
 // CG has stopped (the queued rounds after a stop decision do nothing)
 __device__ __forceinline__ bool front_idle(const FrontDesc& F, int skip) {
     return skip == SKIP_REFINE ? *F.done != 0 : (skip == SKIP_CG ? *F.cgdone != 0 : false);
+}
+
+// Forward sweep of large fronts, one workgroup per front: the c x c triangle
+// is staged in LDS, the children's update vectors are added child by child
+// (the update part in the front's own HBM slot), the triangle is solved by
+// one wave (y_j = w_j / l_jj, then w_i -= l_ij y_j for i > j, in column
+// order) and the update rows take -L21 y by one thread per row (column order).
+__global__ __launch_bounds__(kBigThreads) void k_big_fwd(const InstDev* __restrict__ insts,
+                                                       const FrontDesc* __restrict__ fds, int skip_done) {
+    __shared__ double Ls[kBigMaxCols * (kBigMaxCols + 1)];
+    __shared__ double w[kBigMaxCols], dv[kBigMaxCols];
+    const FrontDesc& F = fds[blockIdx.x];
+    if (front_idle(F, skip_done)) return;
+    const InstDev& I = insts[F.inst];
+    const PatDev& T = I.P;
+    const int c = F.c, r = F.r, u = r - c, ld = r | 1, ldl = c | 1;
+    const double* const P = F.L;
+    double* const V = F.V;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
+    for (int q = tid; q < c * c; q += nt) {
+        const int j = q / c, i = q - j * c;
+        Ls[j * ldl + i] = P[(int64_t)j * ld + i];
+    }
+    if (tid < c) {
+        w[tid] = F.y[tid];
+        dv[tid] = F.dinv[tid];
+    }
+    for (int a = tid; a < u; a += nt) V[a] = 0.0;
+    __syncthreads();
+    for (int k = 0; k < F.nch; k++) {
+        const int ch = T.ch_list[F.ch0 + k];
+        const int cc = T.sn_ncol[ch];
+        const int uc = T.sn_nrow[ch] - cc;
+        const double* const Vc = I.V + T.sn_vofs[ch];
+        const int* const rl = T.rel + T.sn_rowofs[ch] + cc;
+        for (int a = tid; a < uc; a += nt) {
+            const int ra = rl[a];
+            const double v = Vc[a];
+            if (ra < c) w[ra] += v;
+            else V[ra - c] += v;
+        }
+        __syncthreads();
+    }
+    if (tid < 64) {
+        double wi = lane < c ? w[lane] : 0.0;
+        for (int j = 0; j < c; j++) {
+            const double yj = readlane_d(wi, j) * dv[j];
+            if (lane > j && lane < c) wi = fma(-Ls[j * ldl + lane], yj, wi);
+        }
+        if (lane < c) w[lane] = wi * dv[lane];
+    }
+    __syncthreads();
+    for (int a = tid; a < u; a += nt) {
+        double acc = V[a];
+        for (int j = 0; j < c; j++) acc = fma(-P[(int64_t)j * ld + c + a], w[j], acc);
+        V[a] = acc;
+    }
+    if (tid < c) F.y[tid] = w[tid];
+}
+
+// Backward sweep of large fronts: t = y1 - L21^T z by one wave per column
+// (lanes over rows, a fixed butterfly), then the triangle by one wave.
+__global__ __launch_bounds__(kBigThreads) void k_big_bwd(const FrontDesc* __restrict__ fds, int skip_done) {
+    __shared__ double Ls[kBigMaxCols * (kBigMaxCols + 1)];
+    __shared__ double t[kBigMaxCols], dv[kBigMaxCols];
+    const FrontDesc& F = fds[blockIdx.x];
+    if (front_idle(F, skip_done)) return;
+    const int c = F.c, r = F.r, u = r - c, ld = r | 1, ldl = c | 1;
+    const double* const P = F.L;
+    const double* const yb = F.y - F.col0;  // the instance's work vector
+    const int* const rw = F.rw;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
+    for (int q = tid; q < c * c; q += nt) {
+        const int j = q / c, i = q - j * c;
+        Ls[j * ldl + i] = P[(int64_t)j * ld + i];
+    }
+    if (tid < c) dv[tid] = F.dinv[tid];
+    for (int j = wave; j < c; j += nwave) {
+        const double* const col = P + (int64_t)j * ld + c;
+        double s = 0.0;
+        for (int a = lane; a < u; a += 64) s = fma(col[a], yb[rw[a]], s);
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0) t[j] = F.y[j] - s;
+    }
+    __syncthreads();
+    if (tid < 64) {
+        double x0 = lane < c ? t[lane] : 0.0, x1 = 0.0;
+        tri_bwd_wave(Ls, ldl, c, dv, x0, x1, lane);
+        if (lane < c) F.y[lane] = x0;
+    }
 }
 
 __global__ __launch_bounds__(kSolveThreads) void k_fwd(const InstDev* __restrict__ insts,
@@ -3245,6 +3474,15 @@ void launch_factor(const InstDev* insts, const FrontDesc* fds, int nitems, size_
 void launch_factor_small(const InstDev* insts, const FrontDesc* fds, int nitems, size_t lds, int fused_update,
                          hipStream_t st) {
     if (nitems > 0) k_factor_small<<<nitems, kFactorThreadsSmall, lds, st>>>(insts, fds, fused_update);
+}
+void launch_big_factor(const InstDev* insts, const FrontDesc* fds, int nitems, hipStream_t st) {
+    if (nitems > 0) k_big_factor<<<nitems, kBigThreads, 0, st>>>(insts, fds);
+}
+void launch_big_fwd(const InstDev* insts, const FrontDesc* fds, int nitems, int skip_done, hipStream_t st) {
+    if (nitems > 0) k_big_fwd<<<nitems, kBigThreads, 0, st>>>(insts, fds, skip_done);
+}
+void launch_big_bwd(const FrontDesc* fds, int nitems, int skip_done, hipStream_t st) {
+    if (nitems > 0) k_big_bwd<<<nitems, kBigThreads, 0, st>>>(fds, skip_done);
 }
 void launch_update(const InstDev* insts, const FrontDesc* fds, const StripItem* items, int nitems, hipStream_t st) {
     if (nitems > 0) k_update<<<nitems, kUpdThreads, 0, st>>>(insts, fds, items);

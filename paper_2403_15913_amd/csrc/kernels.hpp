@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
+#include "lds_layout.hpp"
 
 namespace kkt {
 
@@ -102,6 +103,12 @@ void launch_factor(const InstDev* insts, const FrontDesc* fds, int nitems, size_
 // the same with four-wave workgroups (lds: the level's own largest front)
 void launch_factor_small(const InstDev* insts, const FrontDesc* fds, int nitems, size_t lds, int fused_update,
                          hipStream_t st);
+// large fronts (panels too tall for LDS, at most kLargeFrontCols columns):
+// assembly and factorization in place in HBM, one workgroup per front (the
+// update matrices then by launch_update), and their sweeps
+void launch_big_factor(const InstDev* insts, const FrontDesc* fds, int nitems, hipStream_t st);
+void launch_big_fwd(const InstDev* insts, const FrontDesc* fds, int nitems, int skip_done, hipStream_t st);
+void launch_big_bwd(const FrontDesc* fds, int nitems, int skip_done, hipStream_t st);
 // update matrices by 16-column strips (after the factor launch of the same level)
 void launch_update(const InstDev* insts, const FrontDesc* fds, const StripItem* items, int nitems, hipStream_t st);
 void launch_factor_queue(const InstDev* insts, const FrontDesc* fds, const DepLists& D, int grid, size_t lds,

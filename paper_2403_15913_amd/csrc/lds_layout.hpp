@@ -21,4 +21,9 @@ inline int64_t solve_lds_bytes(int r, int c) { return ((((int64_t)(r | 1) * c + 
 
 inline int64_t front_lds_bytes(int r, int c) { return std::max(factor_lds_bytes(r, c), solve_lds_bytes(r, c)); }
 
+// A front too tall for the LDS budget even at one column is a large front:
+// factored and solved in HBM, in chunks of at most this many columns (the
+// sweeps stage its c x c triangle in LDS and solve it with one wave).
+constexpr int kLargeFrontCols = 64;
+
 }  // namespace kkt

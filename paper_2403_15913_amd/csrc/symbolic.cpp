@@ -386,7 +386,11 @@ int analyze(int n, int m, const int32_t* wp, const int32_t* wi, const int32_t* j
             int r = nc + f_nupd[p];
             int64_t stored = (int64_t)nc * r - (int64_t)nc * (nc - 1) / 2;
             int64_t zeros = stored - (f_true[c] + f_true[p]);
-            bool ok = nc <= opt.max_super && panel_lds_bytes(r, nc) <= opt.lds_bytes &&
+            // a merged front must fit the LDS budget, or be a large front (too
+            // tall for LDS at any width) of at most kLargeFrontCols columns
+            const bool fits = panel_lds_bytes(r, nc) <= opt.lds_bytes ||
+                              (panel_lds_bytes(r, 1) > opt.lds_bytes && nc <= kLargeFrontCols);
+            bool ok = nc <= opt.max_super && fits &&
                       (nc <= opt.relax_small || (double)zeros <= opt.relax_frac * (double)stored);
             if (!ok) break;
             f_first[p] = f_first[c];
@@ -470,10 +474,13 @@ int analyze(int n, int m, const int32_t* wp, const int32_t* wi, const int32_t* j
                 int rr = r - (a - c0[s]);
                 if (rr >= 65536) { err = "front exceeds 65535 rows"; return ST_PATTERN; }
                 int w = 1;
-                while (a + w <= c1[s] && panel_lds_bytes(rr, w + 1) <= opt.lds_bytes) w++;
-                if (panel_lds_bytes(rr, w) > opt.lds_bytes) {
-                    err = "front of " + std::to_string(rr) + " rows exceeds the per-workgroup LDS budget";
-                    return ST_PATTERN;
+                if (panel_lds_bytes(rr, 1) > opt.lds_bytes) {
+                    // too tall for the LDS budget at any width: a large front
+                    // (factored and solved in HBM), in chunks of up to
+                    // kLargeFrontCols columns
+                    w = std::min(c1[s] - a + 1, kLargeFrontCols);
+                } else {
+                    while (a + w <= c1[s] && panel_lds_bytes(rr, w + 1) <= opt.lds_bytes) w++;
                 }
                 d0.push_back(a);
                 d1.push_back(a + w - 1);
@@ -599,7 +606,9 @@ int analyze(int n, int m, const int32_t* wp, const int32_t* wi, const int32_t* j
         S.max_nrow = std::max(S.max_nrow, r);
         S.max_ncol = std::max(S.max_ncol, c);
         S.max_nupd = std::max(S.max_nupd, u);
+        S.n_large += panel_lds_bytes(r, c) > opt.lds_bytes ? 1 : 0;
     }
+    S.lds_budget = opt.lds_bytes;
     S.lsize = S.sn_lofs[ns];
     S.usize = S.sn_uofs[ns];
     S.vsize = S.sn_vofs[ns];

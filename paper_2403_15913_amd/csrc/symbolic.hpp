@@ -66,6 +66,8 @@ struct Symbolic {
     double flops_exact = 0;    // sum over columns of (column count)^2
     int64_t nnzl_exact = 0;    // nnz(L) of the exact (unpadded) structure, diagonal included
     int max_nrow = 0, max_ncol = 0, max_nupd = 0;
+    int lds_budget = 0;        // LDS a front panel may use; taller fronts are large fronts
+    int n_large = 0;           // large fronts (factored and solved in HBM)
     double analyze_seconds = 0;
 };
 

@@ -34,14 +34,14 @@ class KKTError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("ordering", C.c_int32), ("nd_leaf", C.c_int32), ("max_super", C.c_int32),
-                ("relax_small", C.c_int32), ("relax_frac", C.c_double)]
+                ("relax_small", C.c_int32), ("relax_frac", C.c_double), ("front_lds_max", C.c_int32)]
 
 
 class SymbolicStats(C.Structure):
     _fields_ = [("n", C.c_int32), ("m", C.c_int32), ("nsuper", C.c_int32), ("levels", C.c_int32),
                 ("max_rows", C.c_int32), ("max_cols", C.c_int32), ("nnz_k", C.c_int64), ("nnz_l", C.c_int64),
                 ("nnz_l_exact", C.c_int64), ("n_pairs", C.c_int64), ("flops", C.c_double),
-                ("flops_exact", C.c_double), ("analyze_seconds", C.c_double)]
+                ("flops_exact", C.c_double), ("analyze_seconds", C.c_double), ("large_fronts", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -412,8 +412,8 @@ class Symbolic:
     """Symbolic analysis of one (W, J) pattern (host only)."""
 
     def __init__(self, n, m, w_rowptr, w_colind, j_rowptr, j_colind, ordering=ORDER_AUTO, nd_leaf=0,
-                 max_super=0, relax_small=0, relax_frac=-1.0):
-        opt = Options(ordering, nd_leaf, max_super, relax_small, relax_frac)
+                 max_super=0, relax_small=0, relax_frac=-1.0, front_lds_max=0):
+        opt = Options(ordering, nd_leaf, max_super, relax_small, relax_frac, front_lds_max)
         self.n, self.m = int(n), int(m)
         self.h = kkt_symbolic_analyze(self.n, self.m, w_rowptr, w_colind, j_rowptr, j_colind, opt)
 

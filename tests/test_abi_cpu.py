@@ -208,3 +208,39 @@ def test_stagewise_rejects_bad_stages(kkt):
         raise AssertionError("accepted a stage of 90")
     except kkt.KKTError as e:
         assert e.status == 2
+
+
+def _front_lds(r, c):
+    # LDS of a front panel in the factor and sweep kernels (host layout rule)
+    fac = (r | 1) * ((c + 15) // 16 * 16) * 8 + r * 4 + 16
+    sol = ((((r | 1) * c + 1) // 2 * 2) + r + c) * 8
+    return max(fac, sol)
+
+
+@pytest.mark.parametrize("budget", [8192, 16 * 1024])
+def test_large_fronts_structure(kkt, budget):
+    """Fronts too tall for the LDS budget at one column become large fronts
+    (at most 64 columns, factored in HBM) instead of failing the analysis;
+    the structure still matches brute-force elimination."""
+    pat = kktgen.distillation_pattern(6)
+    s = kkt.Symbolic.from_pattern(pat, ordering=2, nd_leaf=100, front_lds_max=budget)
+    st_ = s.stats()
+    bf = brute_force_nnz(pat, s.perm())
+    assert st_["nnz_l_exact"] == bf["nnz_l"] and st_["flops_exact"] == bf["sum_c2"]
+    check_supernodes(s, bf, pat.n)
+    cp, par, nr = s.supernodes()
+    ncol = np.diff(cp)
+    large = np.array([_front_lds(int(r), int(c)) > budget for r, c in zip(nr, ncol)])
+    assert 0 < large.sum() == st_["large_fronts"] <= st_["nsuper"]
+    assert (ncol[large] <= 64).all()
+    # every other front fits its panel in the budget
+    assert all(_front_lds(int(r), int(c)) <= budget for r, c, lg in zip(nr, ncol, large) if not lg)
+    if budget == 16 * 1024:
+        assert large.sum() < st_["nsuper"]
+
+
+def test_tall_fronts_under_default_budget(kkt):
+    """Stages 700 variables wide give fronts too tall for 158 KiB of LDS at any width."""
+    pat = kktgen.nmpc_pattern(4, 700, 4)
+    st_ = kkt.Symbolic.from_pattern(pat, ordering=2).stats()
+    assert st_["large_fronts"] > 0 and st_["max_rows"] > (158 * 1024) // (16 * 8)
