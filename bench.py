@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--hykkt", type=int, default=1, help="also time HyKKT (refactor + Schur CG) at paper scale")
     ap.add_argument("--ipm", type=int, default=1, help="also time the interior-point loop on a paper-scale QP")
     ap.add_argument("--stagewise", type=int, default=1, help="also time the stage-structured solver (paper + batch)")
+    ap.add_argument("--large-fronts", type=int, default=1, help="also time a pattern whose fronts are too tall for "
+                                                                    "LDS (large-front path)")
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched workload (0: skip)")
     ap.add_argument("--batch-ordering", type=int, default=2, help="batch ordering when not autotuned")
     ap.add_argument("--batch-nd-leaf", type=int, default=256, help="batch nested-dissection leaf when not autotuned")
@@ -59,7 +61,7 @@ def parse():
                     help="only run one plain device copy of this many MiB (HBM counter calibration) and exit")
     ap.add_argument("--serve-requests", type=int, default=10000, help="requests per arrival rate of the served "
                                                                         "workload (0: skip)")
-    ap.add_argument("--serve-rho", default="0.5,0.8,1.2", help="arrival rates as fractions of the plain solver's "
+    ap.add_argument("--serve-rho", default="0.5,0.8,1.2,2.0", help="arrival rates as fractions of the plain solver's "
                                                                  "capacity (comma-separated)")
     args = ap.parse_args()
     args.schedule = args.schedule_given or "levels"
@@ -286,6 +288,48 @@ def bench_hykkt(args, kkt, kktgen, torch, dev, opts):
             eta_max=float(max(i["eta"] for i in infos)), rel_res_max=float(max(i["rel_res"] for i in infos)),
             phase_ms_per_pair={p: round(tm[p]["ms"] / args.steps, 4) for p in tm},
             launches_per_pair={p: round(tm[p]["launches"] / args.steps, 1) for p in tm})
+    return out
+
+
+def bench_large_fronts(args, kkt, kktgen, torch, dev):
+    """Fronts too tall for LDS: NMPC stages 700 variables wide, nested dissection
+    (its separator fronts take the large-front path in HBM), beside natural stage
+    order on the same pattern (every front in LDS)."""
+    pat = kktgen.nmpc_pattern(4, 700, 4)
+    v = kktgen.nmpc_values(pat, kktgen.rng_for(0, 11, 0), 1e-6, 1e6)
+
+    def T(a):
+        return torch.tensor(np.asarray(a), dtype=torch.float64, device=dev)
+
+    d = [T(v.w_vals), T(v.j_vals), T(v.sigma_x), T(v.sigma_s)]
+    b = T(v.b)
+    x = torch.zeros(pat.n, dtype=torch.float64, device=dev)
+    out = dict(workload="NMPC N=4 nx=700 nu=4 (n=2816, m=2800), Sigma~logU[1e-6,1e6]")
+    for name, opts in (("nested_dissection", dict(ordering=kkt.ORDER_ND)), ("natural", dict(ordering=kkt.ORDER_NATURAL))):
+        sym = kkt.Symbolic.from_pattern(pat, **opts)
+        st = sym.stats()
+        f = kkt.Factor(sym)
+
+        def step():
+            f.refactor(*d)
+            return f.solve(b, x)
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            info = step()
+        torch.cuda.synchronize()
+        f.set_timing(True)
+        f.read_timing()
+        step()
+        tm = f.read_timing()
+        f.close()
+        out[name] = dict(ms_per_pair=round(1e3 * (time.perf_counter() - t0) / reps, 3), eta=info["eta"],
+                         large_fronts=st["large_fronts"], max_rows=st["max_rows"], levels=st["levels"],
+                         flops_exact=st["flops_exact"],
+                         phase_ms={k: round(tv["ms"], 4) for k, tv in tm.items() if tv["ms"]})
     return out
 
 
@@ -622,6 +666,7 @@ def main():
     ipm_leg = bench_ipm(args, kkt, kktgen, torch, dev, opts) if args.ipm and args.workload == "paper" else None
     batched = bench_batched(args, kkt, kktgen, torch, dev) if args.batch > 0 else None
     served = bench_served(args, kkt, kktgen, torch, dev) if args.serve_requests > 0 else None
+    large = bench_large_fronts(args, kkt, kktgen, torch, dev) if args.large_fronts else None
     stagewise = None
     if args.stagewise and args.workload == "paper":
         stagewise = bench_stagewise(args, kkt, kktgen, torch, dev, pat, dvals, ms_per_step,
@@ -661,6 +706,7 @@ def main():
             "batched": batched,
             "served": served,
             "stagewise": stagewise,
+            "large_fronts": large,
         },
     }
     print(json.dumps(out), flush=True)
