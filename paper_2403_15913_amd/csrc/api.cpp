@@ -403,9 +403,14 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         int b1 = b0;
         if (nsmall >= kSweepSplitMin && nsmall < bl - b0)
             b1 = (int)(std::stable_partition(sn.begin() + b0, sn.begin() + bl,
-                                             [&](const WorkItem& w) { return slds(w) <= kSweepHalfLds; }) -
+                                             [&](const WorkItem& w) { return slds(w) > kSweepHalfLds; }) -
                        sn.begin());
         const int b2 = bl;
+        // largest fronts first in each launch (and in the level's factor
+        // launch), so the small ones fill the last round
+        auto by_size = [&](const WorkItem& a, const WorkItem& b) { return slds(a) > slds(b); };
+        std::stable_sort(sn.begin() + b0, sn.begin() + b1, by_size);
+        std::stable_sort(sn.begin() + b1, sn.begin() + b2, by_size);
         for (int c = 0; c < 2; c++) {
             const int lo_i = c ? b1 : b0, hi_i = c ? b2 : b1;
             if (hi_i == lo_i) continue;
