@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched workload (0: skip)")
     ap.add_argument("--batch-ordering", type=int, default=2, help="batch ordering when not autotuned")
     ap.add_argument("--batch-nd-leaf", type=int, default=256, help="batch nested-dissection leaf when not autotuned")
+    ap.add_argument("--batch-max-super", type=int, default=48, help="batch widest supernode when not autotuned")
+    ap.add_argument("--batch-small", type=int, default=64,
+                    help="batch four-wave front column threshold when not autotuned")
     ap.add_argument("--batch-autotune", type=int, default=1, help="pick batch options and schedule by measurement")
     ap.add_argument("--graph-rounds", type=int, default=1, help="refinement rounds recorded in the batch graph")
     ap.add_argument("--schedule", dest="schedule_given", default=None, choices=["levels", "queue"],
@@ -86,8 +89,8 @@ def bench_batched(args, kkt, kktgen, torch, dev):
         best = tuned["best"]
     else:
         tuned = None
-        best = dict(ordering=args.batch_ordering, nd_leaf=args.batch_nd_leaf, max_super=96,
-                    schedule=kkt.SCHEDULE_LEVELS)
+        best = dict(ordering=args.batch_ordering, nd_leaf=args.batch_nd_leaf, max_super=args.batch_max_super,
+                    schedule=kkt.SCHEDULE_LEVELS, small=args.batch_small)
     tune_s = time.perf_counter() - t0
     opts = {k: best[k] for k in ("ordering", "nd_leaf", "max_super")}
     t0 = time.perf_counter()
@@ -454,9 +457,10 @@ PHASE_KERNELS = {"factor": "k_factor+k_update", "fwd": "k_fwd", "bwd": "k_bwd", 
                  "residual": "k_residual"}
 
 
-def measured_traffic(phase, args, opts):
+def measured_traffic(phase, args, opts, launches_per_step):
     """HBM bytes per launch of a phase from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE passes scaled by a plain copy's reading), or
+    (FETCH_SIZE and WRITE_SIZE passes scaled by a plain copy's reading): the
+    phase's bytes per refactor there over this run's launches per step, or
     None when the kernels changed since the counters were taken or another
     configuration (workload, schedule, symbolic options) is benchmarked."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
@@ -472,8 +476,11 @@ def measured_traffic(phase, args, opts):
         return None
     if rec.get("kernels_sha256") != sha or rec.get("options") != {k: int(v) for k, v in opts.items()}:
         return None
-    if phase in rec.get("phases", {}):
-        return round(rec["phases"][phase]["bytes_per_launch"])
+    ph = rec.get("phases", {}).get(phase)
+    if ph:
+        if "bytes_per_refactor" in ph:
+            return round(ph["bytes_per_refactor"] / max(1.0, launches_per_step))
+        return round(ph["bytes_per_launch"])
     k = rec.get("per_launch", {}).get(PHASE_KERNELS.get(phase, ""))
     return round(k["fetch_bytes"] + k["write_bytes"]) if k else None
 
@@ -651,7 +658,8 @@ def main():
     if args.schedule == "queue":
         kernel = {"factor": "k_factor_queue", "fwd": "k_sweeps_queue"}.get(dom, kernel)
     roofline = dict(bound=wd["bound"], achieved=round(achieved, 4), peak=peak, unit=wd["unit"],
-                    frac=round(achieved / peak, 5), traffic=measured_traffic(dom, args, opts), traffic_unit="bytes/launch",
+                    frac=round(achieved / peak, 5),
+                    traffic=measured_traffic(dom, args, opts, tm[dom]["launches"] / args.steps), traffic_unit="bytes/launch",
                     kernel=kernel, launches_per_step=tm[dom]["launches"] / args.steps,
                     avg_launch_us=1e3 * tm[dom]["ms"] / max(1, tm[dom]["launches"]))
     if dom == "factor":
