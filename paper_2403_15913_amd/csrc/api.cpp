@@ -429,13 +429,18 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
     lvl_maxu.assign(lvl_ptr.size() - 1, 0);
     lvl_flds.assign(lvl_ptr.size() - 1, 0);
     lvl_maxc.assign(lvl_ptr.size() - 1, 0);
+    lvl_lmaxc.assign(lvl_ptr.size() - 1, 0);
+    lvl_lmaxr.assign(lvl_ptr.size() - 1, 0);
     // per level: the LDS fronts' tiles, then the large fronts' tiles
     for (size_t l = 0; l + 1 < lvl_ptr.size(); l++) {
         for (int t = lvl_ptr[l]; t < lvl_ptr[l + 1]; t++) {
             if (t == lvl_large[l]) upl_ptr.push_back((int)up.size());
             const Symbolic& S = *s[sn[t].inst];
             const int u = S.sn_nrow[sn[t].id] - S.sn_ncol[sn[t].id];
-            if (t < lvl_large[l]) {
+            if (t >= lvl_large[l]) {
+                lvl_lmaxc[l] = std::max(lvl_lmaxc[l], S.sn_ncol[sn[t].id]);
+                lvl_lmaxr[l] = std::max(lvl_lmaxr[l], S.sn_nrow[sn[t].id]);
+            } else {
                 lvl_maxu[l] = std::max(lvl_maxu[l], u);
                 lvl_flds[l] = std::max(lvl_flds[l], (size_t)factor_lds_bytes(S.sn_nrow[sn[t].id], S.sn_ncol[sn[t].id]));
                 lvl_maxc[l] = std::max(lvl_maxc[l], S.sn_ncol[sn[t].id]);
@@ -659,7 +664,8 @@ kkt_status Engine::refactor(const Calls& Cin, hipStream_t st) {
             }
             // large fronts: panels factored in HBM, then their update matrices by tiles
             if (nlarge > 0) {
-                TL(KKT_PHASE_FACTOR, launch_big_factor(di(), fdesc + lvl_large[l], nlarge, st));
+                TL(KKT_PHASE_FACTOR,
+                   launch_big_factor(di(), fdesc + lvl_large[l], nlarge, lvl_lmaxc[l], lvl_lmaxr[l], st));
                 TL(KKT_PHASE_FACTOR, launch_update(di(), fdesc, upitems + upl_ptr[l], up_ptr[l + 1] - upl_ptr[l], st));
             }
         }

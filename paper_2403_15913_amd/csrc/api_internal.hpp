@@ -98,6 +98,7 @@ struct Engine {
     std::vector<int> up_ptr;
     std::vector<int> upl_ptr;                       // per level: first tile of its large fronts
     std::vector<int> lvl_large;                     // per level: first large front (they come last)
+    std::vector<int> lvl_lmaxc, lvl_lmaxr;          // per level: widest and tallest large front
     int n_large = 0;                                // large fronts (panels factored in HBM)
     std::vector<int> lvl_maxu;                      // widest update part of each level
     std::vector<size_t> lvl_flds;                   // factor LDS of each level's largest front

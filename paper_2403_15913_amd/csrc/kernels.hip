@@ -1061,25 +1061,63 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(const InstDev* __restric
 constexpr int kBigThreads = 256;
 constexpr int kBigMaxCols = kLargeFrontCols;
 
-__global__ __launch_bounds__(kBigThreads) void k_big_factor(const InstDev* __restrict__ insts,
-                                                          const FrontDesc* __restrict__ fds) {
-    __shared__ double invd[16];
+// Pivot chain of diagonal block j0 (width w) of a panel in HBM, by one wave:
+// lane i of each 16-lane row ends with row j0 + i of L_kk in a[0 .. i] (and
+// the scaled entries of rows past the block's columns), lanes 0 .. w-1 of
+// invd the pivot reciprocals; the returned mask has bit j set for a failed
+// pivot j (replaced by one).
+__device__ inline unsigned big_diag_chain(const double* P, int ld, int r, int j0, int w, int lane, double* a,
+                                          double* invd) {
+    const int i = lane & 15;
+    const bool live = j0 + i < r;
+    const int row = min(j0 + i, r - 1);
+#pragma unroll
+    for (int k = 0; k < 16; k++) a[k] = (live && k < w) ? P[(int64_t)(j0 + k) * ld + row] : 0.0;
+    unsigned bad = 0;
+    static_for<16>([&](auto J) {
+        constexpr int j = J;
+        if (j < w) {
+            double d = readfirstlane_d(row_bcast<j>(a[j]));
+            if (!(d > 0.0) || !isfinite(d)) {
+                bad |= 1u << j;
+                d = 1.0;
+            }
+            double inv, ljj;
+            pivot_roots(d, inv, ljj);
+            a[j] = i == j ? ljj : a[j] * inv;
+            if (lane == 0) invd[j] = inv;
+            static_for<16>([&](auto K) {
+                constexpr int k = K;
+                if constexpr (k > j) a[k] = fma(-a[j], row_bcast<k>(a[j]), a[k]);
+            });
+        }
+    });
+    return bad;
+}
+
+// Assembly of large fronts: workgroup (f, b) takes column block b of large
+// front f: zeroes its columns, writes K's entries in them, then adds the
+// children's update entries whose column maps into them, child by child
+// (the entries of one child are distinct; a child's update columns mapping
+// into the block are a contiguous range, its relative rows being ascending).
+__global__ __launch_bounds__(kBigThreads) void k_big_init(const InstDev* __restrict__ insts,
+                                                        const FrontDesc* __restrict__ fds) {
     const FrontDesc& F = fds[blockIdx.x];
+    const int c = F.c, r = F.r, ld = r | 1;
+    const int b0 = blockIdx.y << 4;
+    if (b0 >= c) return;
+    const int b1 = min(c, b0 + 16);
     const InstDev& I = insts[F.inst];
     const PatDev& T = I.P;
-    const int c = F.c, r = F.r, ld = r | 1, col0 = F.col0;
     double* const P = F.L;
-    int* const status = I.status;
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
-    // assembly: zero, the original entries of K, then the children's update
-    // entries whose column maps into the panel, child by child (the entries of
-    // one child are distinct; two children can add into the same entry)
-    const int64_t tot = (int64_t)ld * c;
-    for (int64_t q = tid; q < tot; q += nt) P[q] = 0.0;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int64_t q0 = (int64_t)b0 * ld, q1 = (int64_t)b1 * ld;
+    for (int64_t q = q0 + tid; q < q1; q += nt) P[q] = 0.0;
     __syncthreads();
     for (int q = tid; q < F.nk; q += nt) {
         const int loc = F.kl[q];
-        P[(int64_t)(loc >> 16) * ld + (loc & 0xffff)] = F.kv[q];
+        const int col = loc >> 16;
+        if (col >= b0 && col < b1) P[(int64_t)col * ld + (loc & 0xffff)] = F.kv[q];
     }
     __syncthreads();
     for (int k = 0; k < F.nch; k++) {
@@ -1088,101 +1126,123 @@ __global__ __launch_bounds__(kBigThreads) void k_big_factor(const InstDev* __res
         const int uc = T.sn_nrow[ch] - cc, nb = T.rel_np[ch];
         const double* const Uc = I.U + T.sn_uofs[ch];
         const int* const rl = T.rel + T.sn_rowofs[ch] + cc;
-        const int64_t ctot = (int64_t)nb * uc;
+        // child update columns e0 .. e1-1 map into columns b0 .. b1-1
+        int e0 = 0, e1 = nb;
+        {
+            int lo = 0, hi = nb;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (rl[mid] < b0) lo = mid + 1;
+                else hi = mid;
+            }
+            e0 = lo;
+            hi = nb;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (rl[mid] < b1) lo = mid + 1;
+                else hi = mid;
+            }
+            e1 = lo;
+        }
+        const int64_t ctot = (int64_t)(e1 - e0) * uc;
         for (int64_t q = tid; q < ctot; q += nt) {
-            const int b = (int)(q / uc), a = (int)(q - (int64_t)b * uc);
-            if (a >= b) P[(int64_t)rl[b] * ld + rl[a]] += Uc[q];
+            const int b = e0 + (int)(q / uc), a = (int)(q - (int64_t)(b - e0) * uc);
+            if (a >= b) P[(int64_t)rl[b] * ld + rl[a]] += Uc[(int64_t)b * uc + a];
         }
         __syncthreads();
     }
-    const int nbc = (c + 15) >> 4, nbr = (r + 15) >> 4;
-    for (int kb = 0; kb < nbc; kb++) {
-        const int j0 = kb << 4, w = min(16, c - j0);
-        // diagonal block by wave 0: lane i of each 16-lane row holds row
-        // j0 + i; step j takes the pivot from lane j, scales column j and
-        // updates the later columns by row broadcasts
-        if (wave == 0) {
-            const int i = lane & 15;
-            const bool live = j0 + i < r;
-            const int row = min(j0 + i, r - 1);
-            double a[16];
+}
+
+// Rows below diagonal block kb of large fronts: workgroup (f, g) recomputes
+// the block's pivot chain from the panel (every workgroup the same values),
+// then solves rows j0 + 16 + 256 g + tid (x = p L_kk^{-T}, the row-by-row
+// arithmetic of the LDS kernel). The factored block itself is written by
+// k_big_tiles, after every workgroup here has read it.
+__global__ __launch_bounds__(kBigThreads) void k_big_trsm(const FrontDesc* __restrict__ fds, int kb) {
+    __shared__ double Ld[16 * 17];
+    __shared__ double invd[16];
+    const FrontDesc& F = fds[blockIdx.x];
+    const int c = F.c, r = F.r, ld = r | 1;
+    const int j0 = kb << 4;
+    const int rows0 = j0 + 16 + (int)blockIdx.y * kBigThreads;
+    if (j0 >= c || rows0 >= r) return;
+    const int w = min(16, c - j0);
+    double* const P = F.L;
+    const int tid = threadIdx.x, lane = tid & 63;
+    if (tid < 64) {
+        double a[16];
+        big_diag_chain(P, ld, r, j0, w, lane, a, invd);
+        const int i = lane & 15;
+        if (lane < 16) {
 #pragma unroll
-            for (int k = 0; k < 16; k++) a[k] = (live && k < w) ? P[(int64_t)(j0 + k) * ld + row] : 0.0;
-            unsigned bad = 0;
-            static_for<16>([&](auto J) {
-                constexpr int j = J;
-                if (j < w) {
-                    double d = readfirstlane_d(row_bcast<j>(a[j]));
-                    if (!(d > 0.0) || !isfinite(d)) {
-                        bad |= 1u << j;
-                        d = 1.0;
-                    }
-                    double inv, ljj;
-                    pivot_roots(d, inv, ljj);
-                    a[j] = i == j ? ljj : a[j] * inv;
-                    if (lane == 0) invd[j] = inv;
-                    static_for<16>([&](auto K) {
-                        constexpr int k = K;
-                        if constexpr (k > j) a[k] = fma(-a[j], row_bcast<k>(a[j]), a[k]);
-                    });
-                }
-            });
-            if (bad && lane == 0) {
-                atomicMin(&status[1], col0 + j0 + __builtin_ctz(bad));
-                atomicMax(&status[0], KKT_ST_NOT_SPD);
-            }
-            if (lane < 16 && live) {
-#pragma unroll
-                for (int k = 0; k < 16; k++)
-                    if (k < w && k <= i) P[(int64_t)(j0 + k) * ld + j0 + i] = a[k];
-            }
+            for (int k = 0; k < 16; k++) Ld[k * 17 + i] = a[k];  // column k, row j0 + i
         }
-        __syncthreads();
-        // rows below the diagonal block, one per thread: x = p L_kk^{-T}
-        if (tid < w) F.dinv[j0 + tid] = invd[tid];
-        for (int i = j0 + 16 + tid; i < r; i += nt) {
-            double x[16], lc[16], ln[16];
+    }
+    __syncthreads();
+    const int i = rows0 + tid;
+    if (i >= r) return;
+    double x[16], lc[16];
 #pragma unroll
-            for (int k = 0; k < 16; k++) x[k] = k < w ? P[(int64_t)(j0 + k) * ld + i] : 0.0;
+    for (int k = 0; k < 16; k++) x[k] = k < w ? P[(int64_t)(j0 + k) * ld + i] : 0.0;
 #pragma unroll
-            for (int k = 0; k < 16; k++) lc[k] = P[(int64_t)j0 * ld + min(j0 + k, r - 1)];
+    for (int j = 0; j < 16; j++) {
+        if (j < w) {
 #pragma unroll
-            for (int j = 0; j < 16; j++) {
-                if (j + 1 < w) {
+            for (int k = 0; k < 16; k++) lc[k] = Ld[j * 17 + k];
+            x[j] *= invd[j];
 #pragma unroll
-                    for (int k = 0; k < 16; k++) ln[k] = P[(int64_t)(j0 + j + 1) * ld + min(j0 + k, r - 1)];
-                }
-                if (j < w) {
-                    x[j] *= invd[j];
+            for (int k = j + 1; k < 16; k++) x[k] = fma(-x[j], lc[k], x[k]);
+        }
+    }
 #pragma unroll
-                    for (int k = j + 1; k < 16; k++) x[k] = fma(-x[j], lc[k], x[k]);
-                }
-#pragma unroll
-                for (int k = 0; k < 16; k++) lc[k] = ln[k];
-            }
+    for (int k = 0; k < 16; k++)
+        if (k < w) P[(int64_t)(j0 + k) * ld + i] = x[k];
+}
+
+// After k_big_trsm(kb): the later column blocks of large fronts take block
+// kb's update on the matrix cores, one 16 x 16 tile per wave (workgroup
+// (f, h) takes tiles 4h .. 4h+3 of front f), and workgroup (f, 0) writes the
+// factored diagonal block kb, its pivot reciprocals and any failed pivot.
+__global__ __launch_bounds__(kBigThreads) void k_big_tiles(const InstDev* __restrict__ insts,
+                                                         const FrontDesc* __restrict__ fds, int kb) {
+    __shared__ double invd[16];
+    const FrontDesc& F = fds[blockIdx.x];
+    const int c = F.c, r = F.r, ld = r | 1;
+    const int j0 = kb << 4;
+    if (j0 >= c) return;
+    const int w = min(16, c - j0);
+    double* const P = F.L;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (blockIdx.y == 0 && wave == 0) {
+        double a[16];
+        const unsigned bad = big_diag_chain(P, ld, r, j0, w, lane, a, invd);
+        if (bad && lane == 0) {
+            int* const status = insts[F.inst].status;
+            atomicMin(&status[1], F.col0 + j0 + __builtin_ctz(bad));
+            atomicMax(&status[0], KKT_ST_NOT_SPD);
+        }
+        const int i = lane & 15;
+        if (lane < 16 && j0 + i < r) {
 #pragma unroll
             for (int k = 0; k < 16; k++)
-                if (k < w) P[(int64_t)(j0 + k) * ld + i] = x[k];
+                if (k < w && k <= i) P[(int64_t)(j0 + k) * ld + j0 + i] = a[k];
         }
-        __syncthreads();
-        // the later column blocks take block kb's update (matrix cores, one
-        // 16 x 16 tile per wave at a time)
-        if (kb + 1 < nbc) {
-            int ntile = 0;
-            for (int jt = kb + 1; jt < nbc; jt++) ntile += nbr - jt;
-            for (int t = wave; t < ntile; t += nwave) {
-                int ti, tj;
-                tri_tile(t, kb + 1, nbr, ti, tj);
-                const d4 acc = tile_abt(P, ld, ti << 4, tj << 4, j0, 16, r, lane);
-                const int col = (tj << 4) + (lane & 15);
+        if (lane < w) F.dinv[j0 + lane] = invd[lane];
+    }
+    const int nbc = (c + 15) >> 4, nbr = (r + 15) >> 4;
+    if (kb + 1 >= nbc) return;
+    int ntile = 0;
+    for (int jt = kb + 1; jt < nbc; jt++) ntile += nbr - jt;
+    const int t = (int)blockIdx.y * (kBigThreads >> 6) + wave;
+    if (t >= ntile) return;
+    int ti, tj;
+    tri_tile(t, kb + 1, nbr, ti, tj);
+    const d4 acc = tile_abt(P, ld, ti << 4, tj << 4, j0, 16, r, lane);
+    const int col = (tj << 4) + (lane & 15);
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const int row = (ti << 4) + 4 * e + (lane >> 4);
-                    if (col < c && row >= col && row < r) P[(int64_t)col * ld + row] -= acc[e];
-                }
-            }
-            __syncthreads();
-        }
+    for (int e = 0; e < 4; e++) {
+        const int row = (ti << 4) + 4 * e + (lane >> 4);
+        if (col < c && row >= col && row < r) P[(int64_t)col * ld + row] -= acc[e];
     }
 }
 
@@ -3495,8 +3555,19 @@ void launch_factor_small(const InstDev* insts, const FrontDesc* fds, int nitems,
                          hipStream_t st) {
     if (nitems > 0) k_factor_small<<<nitems, kFactorThreadsSmall, lds, st>>>(insts, fds, fused_update);
 }
-void launch_big_factor(const InstDev* insts, const FrontDesc* fds, int nitems, hipStream_t st) {
-    if (nitems > 0) k_big_factor<<<nitems, kBigThreads, 0, st>>>(insts, fds);
+void launch_big_factor(const InstDev* insts, const FrontDesc* fds, int nitems, int max_cols, int max_rows,
+                       hipStream_t st) {
+    if (nitems <= 0) return;
+    const int nbc = (max_cols + 15) / 16, nbr = (max_rows + 15) / 16;
+    k_big_init<<<dim3(nitems, nbc), kBigThreads, 0, st>>>(insts, fds);
+    for (int kb = 0; kb < nbc; kb++) {
+        const int below = max_rows - 16 * kb - 16;
+        if (below > 0) k_big_trsm<<<dim3(nitems, (below + kBigThreads - 1) / kBigThreads), kBigThreads, 0, st>>>(fds, kb);
+        int ntile = 0;
+        for (int jt = kb + 1; jt < nbc; jt++) ntile += nbr - jt;
+        const int wpg = kBigThreads / 64;
+        k_big_tiles<<<dim3(nitems, std::max(1, (ntile + wpg - 1) / wpg)), kBigThreads, 0, st>>>(insts, fds, kb);
+    }
 }
 void launch_big_fwd(const InstDev* insts, const FrontDesc* fds, int nitems, int skip_done, hipStream_t st) {
     if (nitems > 0) k_big_fwd<<<nitems, kBigThreads, 0, st>>>(insts, fds, skip_done);

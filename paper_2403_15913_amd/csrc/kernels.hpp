@@ -104,9 +104,13 @@ void launch_factor(const InstDev* insts, const FrontDesc* fds, int nitems, size_
 void launch_factor_small(const InstDev* insts, const FrontDesc* fds, int nitems, size_t lds, int fused_update,
                          hipStream_t st);
 // large fronts (panels too tall for LDS, at most kLargeFrontCols columns):
-// assembly and factorization in place in HBM, one workgroup per front (the
-// update matrices then by launch_update), and their sweeps
-void launch_big_factor(const InstDev* insts, const FrontDesc* fds, int nitems, hipStream_t st);
+// assembly and factorization in place in HBM (the update matrices then by
+// launch_update), and their sweeps
+// (several workgroups per front: assembly by column block, then per column
+// block the rows below the diagonal block and the later blocks' update;
+// max_cols / max_rows bound the fronts of the launch)
+void launch_big_factor(const InstDev* insts, const FrontDesc* fds, int nitems, int max_cols, int max_rows,
+                       hipStream_t st);
 void launch_big_fwd(const InstDev* insts, const FrontDesc* fds, int nitems, int skip_done, hipStream_t st);
 void launch_big_bwd(const FrontDesc* fds, int nitems, int skip_done, hipStream_t st);
 // update matrices by 16-column strips (after the factor launch of the same level)
