@@ -98,7 +98,7 @@ def bench_batched(args, kkt, kktgen, torch, dev):
     analyze_s = time.perf_counter() - t0
     B = kkt.Batch(syms)
     B.set_schedule(best["schedule"])
-    B.set_update_split(*best.get("split", (48, 96)))
+    B.set_update_split(*best.get("split", (140, 64)))
     B.set_small_fronts(best.get("small", 0))
     cat = {f: T(np.concatenate([getattr(v, f) for v in vals])) for f in ("w_vals", "j_vals", "sigma_x", "sigma_s", "b")}
     x = torch.zeros(int(B.ofs["n"][-1]), dtype=torch.float64, device=dev)
@@ -168,7 +168,7 @@ def bench_batched(args, kkt, kktgen, torch, dev):
                           factor_ms_per_batch=round(1e3 * fac_s, 4))
     return dict(instances=count, sum_n=int(n_ofs[-1]), sum_nnz_l=int(sum(s["nnz_l"] for s in st)),
                 flops_exact=flops, options=opts, schedule=sched_name,
-                update_split=list(best.get("split", (48, 96))), small_fronts_cols=best.get("small", 0),
+                update_split=list(best.get("split", (140, 64))), small_fronts_cols=best.get("small", 0),
                 roofline=batch_roofline,
                 phase_ms_per_batch={p: round(btm[p]["ms"] / reps, 4) for p in btm},
                 autotuned=bool(args.batch_autotune), tune_s=round(tune_s, 2), analyze_s=round(analyze_s, 2),
@@ -586,7 +586,7 @@ def main():
 
     tuned = None
     opts = dict(ordering=args.ordering, nd_leaf=args.nd_leaf, max_super=args.max_super)
-    split = (48, 96)  # the library's default launch shape of the update matrices
+    split = (140, 64)  # the library's default launch shape of the update matrices
     small = 0  # the library's default: every front by eight-wave workgroups (column threshold 0)
     if args.autotune and not args.ordering and not args.nd_leaf:
         from paper_2403_15913_amd import autotune

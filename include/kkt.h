@@ -480,7 +480,7 @@ kkt_status kkt_factor_set_schedule(kkt_factor* f, int32_t schedule);
  * rows, the update matrices are formed by a launch of their own (one wave
  * per 16 x 16 tile) instead of by each front's workgroup after its panel.
  * Both ways give every entry the same operations in the same order, so
- * results are bitwise identical; only the time differs. Defaults 48 and 96;
+ * results are bitwise identical; only the time differs. Defaults 140 and 64;
  * max_fronts = 0 keeps every update in the front's workgroup. The
  * autotuner picks them by measurement. INVALID_ARG for negative values.
  * Host only; applies to launches issued after the call.

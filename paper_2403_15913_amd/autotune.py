@@ -85,8 +85,8 @@ def _dev(a):
 
 
 # launch shapes of the update matrices (kkt_factor_set_update_split): the
-# default, none split, more levels split, every level split
-SPLITS = ((48, 96), (0, 0), (140, 64), (1 << 30, 0))
+# default, none split, fewer levels split, every level split
+SPLITS = ((140, 64), (0, 0), (48, 96), (1 << 30, 0))
 # column thresholds of the four-wave front factorization
 # (kkt_factor_set_small_fronts): none, then levels whose widest front has at
 # most 32, 48 or 64 columns

@@ -29,8 +29,8 @@ struct Calls {
 };
 
 constexpr int kBlock = 256;
-constexpr int kSplitMaxFronts = 48;  // levels with fewer fronts launch their update matrices by strips
-constexpr int kSplitMinRows = 96;    // ... when the level's widest update part has at least this many rows
+constexpr int kSplitMaxFronts = 140;  // levels with fewer fronts launch their update matrices by tiles
+constexpr int kSplitMinRows = 64;     // ... when the level's widest update part has at least this many rows
 constexpr int kResidualSplit = 8;    // residual blocks per 256-row item (two rows per 16-lane group)
 static_assert(16 % kResidualSplit == 0, "a 256-row item splits into whole rows per 16-lane group");
 
