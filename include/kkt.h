@@ -84,10 +84,11 @@ typedef struct kkt_options {
     int32_t max_super;     /* widest supernode in columns (0: 96) */
     int32_t relax_small;   /* supernodes up to this width always amalgamate (0: 16, <0: none) */
     double relax_frac;     /* amalgamation may add up to this fraction of explicit zeros (<0: 0.5) */
-    int32_t front_lds_max; /* LDS bytes one front panel may use (0 or more than 158 KiB: 158 KiB). A
-                              front too tall to fit at one column is a large front: at most 64 columns,
-                              assembled, factored and solved in place in HBM (one workgroup per front
-                              and level, update matrix by one wave per tile); the level schedule only */
+    int32_t front_lds_max; /* LDS bytes one front panel may use (0 or more than 158 KiB: 158 KiB; less
+                              than 4 KiB: 4 KiB). A front too tall to fit at one column is a large
+                              front: at most 64 columns, assembled, factored and solved in place in HBM
+                              by several workgroups per front (its update matrix by one wave per
+                              tile); level schedule only, INVALID_ARG if negative */
 } kkt_options;
 
 typedef struct kkt_symbolic_stats {
@@ -465,8 +466,9 @@ kkt_status kkt_factor_read_timing(kkt_factor* f, kkt_timing* out);
  *           levels (and instances) overlap. A dependency wait that exceeds its
  *           spin bound makes the next status read return KKT_ERR_DEVICE.
  * Both schedules run the same per-front arithmetic in the same order, so
- * results are bitwise identical. The default is LEVELS. Host only; applies
- * to launches issued after the call.
+ * results are bitwise identical. The default is LEVELS. QUEUE is refused
+ * (INVALID_ARG) for patterns with large fronts (kkt_options.front_lds_max).
+ * Host only; applies to launches issued after the call.
  */
 #define KKT_SCHEDULE_LEVELS 0
 #define KKT_SCHEDULE_QUEUE 1
