@@ -114,3 +114,54 @@ def test_batch_shared_symbolic(kkt):
     for q in range(5):
         K = D.condensed(pat, vals[q], vals[q].sigma_s)
         assert D.backward_errors(K, xb[q * pat.n:(q + 1) * pat.n], vals[q].b)["eta"] <= 1e-10
+
+
+def test_autotuned_shapes_applied(kkt):
+    """The batch autotuner's pick (options, schedule, update split, four-wave
+    column threshold) and the single-pattern tuner's pick are valid settings:
+    applied to a batch and to a factor they give eta <= 1e-10 and the same
+    bits as the library's default launch shapes on the same analyses."""
+    from paper_2403_15913_amd import autotune
+    pats, vals = make_batch(8, shrink=4)
+    tuned = autotune.tune_batch(pats, vals, reps=1)
+    best = tuned["best"]
+    print("batch pick", best, flush=True)
+    assert {"ordering", "nd_leaf", "max_super", "schedule", "small", "split"} <= set(best)
+    assert best["small"] in autotune.SMALLS and tuple(best["split"]) in autotune.SPLITS
+    syms = autotune.analyze_many(pats, **{k: best[k] for k in ("ordering", "nd_leaf", "max_super")})
+    cat = [concat(vals, f) for f in ("w_vals", "j_vals", "sigma_x", "sigma_s")]
+    b = concat(vals, "b")
+    xs = []
+    for tuned_shapes in (True, False):
+        B = kkt.Batch(syms)
+        if tuned_shapes:
+            B.set_schedule(best["schedule"])
+            B.set_small_fronts(best["small"])
+            B.set_update_split(*best["split"])
+        B.refactor(*cat)
+        x = torch.zeros(sum(p.n for p in pats), dtype=torch.float64, device="cuda")
+        infos = B.solve(b, x)
+        assert all(i["eta"] <= 1e-10 for i in infos)
+        torch.cuda.synchronize()
+        xs.append(x.cpu().numpy())
+        B.close()
+    assert np.array_equal(xs[0], xs[1])
+    # one pattern
+    pat, v = pats[0], vals[0]
+    pick = autotune.tune_pattern(pat, v, reps=1, table_path=None)
+    print("pattern pick", pick, flush=True)
+    sym = kkt.Symbolic.from_pattern(pat, **{k: pick[k] for k in ("ordering", "nd_leaf", "max_super")})
+    xp = []
+    for tuned_shapes in (True, False):
+        f = kkt.Factor(sym)
+        if tuned_shapes:
+            f.set_schedule(pick["schedule"])
+            f.set_update_split(*pick["split"])
+            f.set_small_fronts(pick["small"])
+        f.refactor(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), dev(v.sigma_s))
+        x = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
+        assert f.solve(dev(v.b), x)["eta"] <= 1e-10
+        torch.cuda.synchronize()
+        xp.append(x.cpu().numpy())
+        f.close()
+    assert np.array_equal(xp[0], xp[1])
