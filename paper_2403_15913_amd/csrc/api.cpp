@@ -386,8 +386,9 @@ kkt_status Engine::place(const std::vector<const Symbolic*>& s, const std::vecto
         // of small fronts runs two workgroups per compute unit. Fronts of one
         // level are independent and their order in the launch is free: where
         // the small fronts alone fill two workgroups on every compute unit,
-        // they go first and get a launch of their own (launches on one stream
-        // run one after the other, so a split pays only for wide levels).
+        // they get a launch of their own after the larger fronts' (launches
+        // on one stream run one after the other, so a split pays only for
+        // wide levels).
         const int b0 = lvl_ptr.back();
         // large fronts last in the level (their own launches)
         const int bl = (int)(std::stable_partition(sn.begin() + b0, sn.end(),
