@@ -163,6 +163,10 @@ def test_error_codes(kkt):
     assert status_of(kkt, n, m, wr, wc, jr, jc, opt=bad) == 1                   # unknown ordering
     wide = kkt.Options(0, 0, 200, 0, -1.0)
     assert status_of(kkt, n, m, wr, wc, jr, jc, opt=wide) == 1                  # max_super > 128
+    neg = kkt.Options(0, 0, 0, 0, -1.0, -1)
+    assert status_of(kkt, n, m, wr, wc, jr, jc, opt=neg) == 1                   # negative front_lds_max
+    tiny = kkt.Options(0, 0, 0, 0, -1.0, 1)
+    assert status_of(kkt, n, m, wr, wc, jr, jc, opt=tiny) == 0                  # raised to 4 KiB
     import ctypes as C
     assert kkt.lib().kkt_symbolic_analyze(n, m, None, None, None, None, None, None) == 1  # NULL out
     assert kkt.lib().kkt_symbolic_get_stats(None, None) == 1
