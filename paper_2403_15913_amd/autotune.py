@@ -205,6 +205,7 @@ def batch_candidates(nmax: int):
     out += [dict(ordering=kkt.ORDER_ND, nd_leaf=leaf, max_super=96) for leaf in (256, 1024) if leaf < nmax]
     # narrower supernodes: smaller fronts, so more of them share a compute unit
     out += [dict(ordering=kkt.ORDER_ND, nd_leaf=256, max_super=ms) for ms in (64, 48) if 256 < nmax]
+    out += [dict(ordering=kkt.ORDER_ND, nd_leaf=leaf, max_super=48) for leaf in (512, 1024) if leaf < nmax]
     return out
 
 
