@@ -316,6 +316,14 @@ def bench_hykkt(args, kkt, kktgen, torch, dev, opts):
             eta_max=float(max(i["eta"] for i in infos)), rel_res_max=float(max(i["rel_res"] for i in infos)),
             phase_ms_per_pair={p: round(tm[p]["ms"] / args.steps, 4) for p in tm},
             launches_per_pair={p: round(tm[p]["launches"] / args.steps, 1) for p in tm})
+        if name == "mid_sigma" and not args.no_cpu_baseline:
+            # the oracle's HyKKT (sparse LDL^T of K_gamma, CG on the Schur
+            # complement) on one core, one value set: context for the GPU time
+            from oracle import sparse as S
+            t0 = time.perf_counter()
+            _, _, oinfo = S.hykkt_cg_solve(pat, vals[0], vals[0].f, vals[0].g, gamma, tol=1e-10, maxit=300)
+            out[name]["cpu_oracle"] = dict(s_per_pair=round(time.perf_counter() - t0, 3), cg_iters=oinfo["iters"],
+                                           status=oinfo["status"], pairs_timed=1, cores=1, kind="oracle")
     return out
 
 
