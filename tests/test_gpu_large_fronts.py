@@ -153,3 +153,64 @@ def test_tall_fronts_default_budget(kkt):
     xo, oinfo = S.lifted_solve(pat, v, v.b)
     assert oinfo["spd"]
     checks.assert_well_conditioned(x, xo)
+
+
+def test_large_fronts_graph_and_served(kkt):
+    """Large fronts through the batch graph (replays with new values and eager
+    work between them equal the eager calls bit for bit) and through the
+    served form (each result equal to the plain solve of its request)."""
+    pats = [kktgen.distillation_pattern(6), kktgen.distillation_pattern(5)]
+    syms = [kkt.Symbolic.from_pattern(pats[0], ordering=2, nd_leaf=100, front_lds_max=8192),
+            kkt.Symbolic.from_pattern(pats[1], ordering=2, nd_leaf=100, front_lds_max=16 * 1024)]
+    assert all(s.stats()["large_fronts"] > 0 for s in syms)
+    sets = [[kktgen.distillation_values(p, kktgen.rng_for(1, 6, 20 + 2 * q + k), 1e-6, 1e6)
+             for q, p in enumerate(pats)] for k in range(2)]
+    cat = lambda vals, f: np.concatenate([getattr(v, f) for v in vals])
+    B = kkt.Batch(syms)
+    n = int(B.ofs["n"][-1])
+    eager = []
+    for vals in sets:
+        B.refactor(*(dev(cat(vals, f)) for f in ("w_vals", "j_vals", "sigma_x", "sigma_s")))
+        x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        B.solve(dev(cat(vals, "b")), x)
+        eager.append(host(x))
+    bufs = {f: dev(cat(sets[0], f)) for f in ("w_vals", "j_vals", "sigma_x", "sigma_s", "b")}
+    xg = torch.full((n,), np.nan, dtype=torch.float64, device="cuda")
+    B.capture(bufs["w_vals"], bufs["j_vals"], bufs["sigma_x"], bufs["sigma_s"], bufs["b"], xg, rounds=1)
+    other = kkt.Factor(syms[1])
+    for rep, k in enumerate((0, 1, 0)):
+        for f in bufs:
+            bufs[f].copy_(dev(cat(sets[k], f)))
+        xg.fill_(np.nan)
+        torch.cuda.synchronize()
+        infos = B.replay()
+        assert all(i["eta"] <= 1e-10 for i in infos)
+        assert np.array_equal(host(xg), eager[k]), rep
+        v1 = sets[1 - k][1]
+        other.refactor(dev(v1.w_vals), dev(v1.j_vals), dev(v1.sigma_x), dev(v1.sigma_s))
+        other.solve(dev(v1.b), torch.zeros(pats[1].n, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+    B.close()
+    # served: each request's result equals its plain solve
+    srv = kkt.Server(hbm_budget=2 << 30, max_wave=4, workers=2)
+    pid = [srv.register(s) for s in syms]
+    reqs = [(q % 2, k) for k in range(2) for q in range(2)] * 2
+    xs, tickets, plain = [], [], []
+    for p, k in reqs:
+        xp, _, f = solve(kkt, syms[p], pats[p], sets[k][p])
+        f.close()
+        plain.append(xp)
+    torch.cuda.synchronize()
+    # the server reads the request's arrays asynchronously: they stay alive until wait
+    held = []
+    for p, k in reqs:
+        v = sets[k][p]
+        x = torch.zeros(pats[p].n, dtype=torch.float64, device="cuda")
+        xs.append(x)
+        held.append([dev(getattr(v, f)) for f in ("w_vals", "j_vals", "sigma_x", "sigma_s", "b")])
+        tickets.append(srv.submit(pid[p], *held[-1], x))
+    res = [srv.wait(t) for t in tickets]
+    assert all(r["status"] == 0 and r["eta"] <= 1e-10 for r in res), res
+    for q in range(len(reqs)):
+        assert np.array_equal(host(xs[q]), plain[q]), q
+    srv.close()
