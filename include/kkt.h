@@ -559,8 +559,10 @@ kkt_status kkt_batch_set_small_fronts(kkt_batch* b, int32_t max_cols);
  * returns as kkt_batch_solve does. Every instance goes through exactly the
  * operations of the two separate calls, so the results are bitwise the same.
  * The caller refreshes the arrays' contents between replays and keeps them
- * allocated while the graph exists. A new capture replaces the old one;
- * kkt_batch_destroy releases it.
+ * allocated while the graph exists. The graph keeps the schedule and launch
+ * shapes (update split, front workgroup size) in effect when it was
+ * recorded; setting them later changes eager calls and later captures only.
+ * A new capture replaces the old one; kkt_batch_destroy releases it.
  * Errors: INVALID_ARG (NULL arrays, x aliasing rhs, bad refinement options,
  * rounds outside 0..max_iter+1), STATE (replay without a capture), HIP.
  */
