@@ -50,6 +50,10 @@ def parse():
     ap.add_argument("--stagewise", type=int, default=1, help="also time the stage-structured solver (paper + batch)")
     ap.add_argument("--large-fronts", type=int, default=1, help="also time a pattern whose fronts are too tall for "
                                                                     "LDS (large-front path)")
+    ap.add_argument("--small", type=int, default=1, help="also time the small NMPC system (n=450): plain, "
+                                                          "one-instance graph and batched")
+    ap.add_argument("--small-pairs", type=int, default=1000, help="plain pairs per value set of the small system")
+    ap.add_argument("--small-batch", type=int, default=256, help="instances of the small system per batch (0: skip)")
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched workload (0: skip)")
     ap.add_argument("--batch-ordering", type=int, default=2, help="batch ordering when not autotuned")
     ap.add_argument("--batch-nd-leaf", type=int, default=256, help="batch nested-dissection leaf when not autotuned")
@@ -357,15 +361,80 @@ def bench_large_fronts(args, kkt, kktgen, torch, dev):
         for _ in range(reps):
             info = step()
         torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        # per-phase kernel time from one more step under the per-launch timers (not in ms_per_pair)
         f.set_timing(True)
         f.read_timing()
         step()
         tm = f.read_timing()
         f.close()
-        out[name] = dict(ms_per_pair=round(1e3 * (time.perf_counter() - t0) / reps, 3), eta=info["eta"],
+        out[name] = dict(ms_per_pair=round(1e3 * sec, 3), eta=info["eta"],
                          large_fronts=st["large_fronts"], max_rows=st["max_rows"], levels=st["levels"],
                          flops_exact=st["flops_exact"],
                          phase_ms={k: round(tv["ms"], 4) for k, tv in tm.items() if tv["ms"]})
+    return out
+
+
+def bench_small(args, kkt, kktgen, torch, dev):
+    """The small NMPC system (N=50, nx=8, nu=1: n=450, m=400, Sigma~logU[1e-2,1e2]) over 10 value
+    sets: the plain solver one pair at a time (eager calls, and the pair replayed as a one-instance
+    batch graph), and `small_batch` instances of the same pattern, each with its own value set,
+    refactored and solved by one graph replay. Launch latency bounds this system; batching is what
+    uses the GPU."""
+    pat, _ = kktgen.small_config()
+    sym = kkt.Symbolic.from_pattern(pat)
+    sets = 10
+
+    def T(a):
+        return torch.tensor(np.asarray(a), dtype=torch.float64, device=dev)
+
+    vals = [kktgen.workload("small", 0, s)[1] for s in range(max(sets, args.small_batch))]
+    dv = [dict(w=T(v.w_vals), j=T(v.j_vals), sx=T(v.sigma_x), ss=T(v.sigma_s), b=T(v.b)) for v in vals[:sets]]
+    f = kkt.Factor(sym)
+    x = torch.zeros(pat.n, dtype=torch.float64, device=dev)
+    for d in dv:
+        f.refactor(d["w"], d["j"], d["sx"], d["ss"])
+        f.solve(d["b"], x)
+    torch.cuda.synchronize()
+    etas = []
+    t0 = time.perf_counter()
+    for d in dv:
+        for _ in range(args.small_pairs):
+            f.refactor(d["w"], d["j"], d["sx"], d["ss"])
+            etas.append(f.solve(d["b"], x)["eta"])
+    torch.cuda.synchronize()
+    tp = (time.perf_counter() - t0) / len(etas)
+    etas = np.array(etas)
+    f.close()
+    out = dict(workload="lifted-kkt plain, NMPC N=50 nx=8 nu=1 (n=450, m=400), Sigma~logU[1e-2,1e2], "
+                        f"{sets} value sets x {args.small_pairs} pairs",
+               plain=dict(pairs_per_s=round(1.0 / tp, 1), ms_per_pair=round(1e3 * tp, 4),
+                          passing=f"{int((etas <= ETA_GATE).sum())}/{etas.size}", eta_max=float(etas.max())))
+
+    def graph_rate(count, reps):
+        B = kkt.Batch([sym] * count)
+        vs = vals[:count]
+        cat = {k: T(np.concatenate([getattr(v, k) for v in vs])) for k in ("w_vals", "j_vals", "sigma_x",
+                                                                              "sigma_s", "b")}
+        xg = torch.zeros(int(B.ofs["n"][-1]), dtype=torch.float64, device=dev)
+        B.capture(cat["w_vals"], cat["j_vals"], cat["sigma_x"], cat["sigma_s"], cat["b"], xg, rounds=1)
+        B.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ok = 0
+        for _ in range(reps):
+            infos = B.replay()
+            ok += sum(i["eta"] <= ETA_GATE for i in infos)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        B.close()
+        return dict(instances=count, ms_per_replay=round(1e3 * sec, 4), pairs_per_s=round(count / sec, 1),
+                    passing=f"{ok}/{count * reps}")
+
+    out["graph_one_instance"] = graph_rate(1, 200)
+    if args.small_batch > 0:
+        out["batched"] = graph_rate(args.small_batch, 20)
+        out["batched_vs_plain"] = round(out["batched"]["pairs_per_s"] / out["plain"]["pairs_per_s"], 2)
     return out
 
 
@@ -708,6 +777,7 @@ def main():
     batched = bench_batched(args, kkt, kktgen, torch, dev) if args.batch > 0 else None
     served = bench_served(args, kkt, kktgen, torch, dev) if args.serve_requests > 0 else None
     large = bench_large_fronts(args, kkt, kktgen, torch, dev) if args.large_fronts else None
+    small_leg = bench_small(args, kkt, kktgen, torch, dev) if args.small else None
     stagewise = None
     if args.stagewise and args.workload == "paper":
         stagewise = bench_stagewise(args, kkt, kktgen, torch, dev, pat, dvals, ms_per_step,
@@ -748,6 +818,7 @@ def main():
             "served": served,
             "stagewise": stagewise,
             "large_fronts": large,
+            "small": small_leg,
         },
     }
     print(json.dumps(out), flush=True)
