@@ -13,5 +13,6 @@ from .nmpc import (  # noqa: F401
     SEED_ROOT, Pattern, Values, rng_for, log_uniform,
     nmpc_pattern, nmpc_values, distillation_pattern, distillation_values,
     dyadic_nmpc_values, batch_shapes, serving_shapes, poisson_arrivals, hub_pattern, hub_values,
+    general_pattern, general_values,
     workload, small_config, paper_config, hykkt_config,
 )

@@ -275,6 +275,54 @@ def hub_values(pat: Pattern, rng: np.random.Generator, sigma_lo: float, sigma_hi
                   rng.standard_normal(pat.n), rng.standard_normal(pat.n), rng.standard_normal(pat.m))
 
 
+# --------------------------------------------------------------------------
+# general sparse patterns (no stage structure)
+# --------------------------------------------------------------------------
+
+def general_pattern(rng: np.random.Generator, n: int, m: int, density: float, row_max: int = 5,
+                    hub_cols: int = 0, hub_frac: float = 0.5) -> Pattern:
+    """Unstructured pattern: W's row i holds its diagonal and each earlier
+    column with probability `density`; J's rows hold 0 .. row_max random
+    columns, plus each of the last `hub_cols` columns with probability
+    `hub_frac` (columns shared by many rows: entries of J^T J with long
+    product lists)."""
+    w_rows = []
+    for i in range(n):
+        lower = np.flatnonzero(rng.random(i) < density) if i else np.zeros(0, np.int64)
+        w_rows.append(np.append(lower, i))
+    hubs = np.arange(n - hub_cols, n) if hub_cols else np.zeros(0, np.int64)
+    j_rows = []
+    for _ in range(m):
+        cols = rng.choice(n, size=min(n, int(rng.integers(0, row_max + 1))), replace=False)
+        if hub_cols:
+            cols = np.concatenate([cols, hubs[rng.random(hub_cols) < hub_frac]])
+        j_rows.append(np.unique(cols))
+    wr, wc = _csr_from_rows(w_rows, n)
+    jr, jc = _csr_from_rows(j_rows, n)
+    return Pattern(n, m, wr, wc, jr, jc, dict(kind="general", density=density, hub_cols=hub_cols))
+
+
+def general_values(pat: Pattern, rng: np.random.Generator, sigma_lo: float, sigma_hi: float) -> Values:
+    """W's off-diagonal entries ~ N(0,1) and each diagonal entry one more than
+    its row's absolute off-diagonal sum over both triangles (so W is
+    symmetric positive definite with eigenvalues >= 1); J ~ N(0,1); then Σx,
+    Σs, b, f, g."""
+    rows = np.repeat(np.arange(pat.n), np.diff(pat.w_rowptr))
+    cols = pat.w_colind
+    off = rows != cols
+    w_vals = np.zeros(pat.nnz_w)
+    w_vals[off] = rng.standard_normal(int(off.sum()))
+    absum = np.zeros(pat.n)
+    np.add.at(absum, rows[off], np.abs(w_vals[off]))
+    np.add.at(absum, cols[off], np.abs(w_vals[off]))
+    w_vals[~off] = absum[rows[~off]] + 1.0
+    j_vals = rng.standard_normal(pat.nnz_j)
+    return Values(w_vals, j_vals,
+                  log_uniform(rng, sigma_lo, sigma_hi, pat.n),
+                  log_uniform(rng, sigma_lo, sigma_hi, pat.m),
+                  rng.standard_normal(pat.n), rng.standard_normal(pat.n), rng.standard_normal(pat.m))
+
+
 def small_config():
     """Lifted-KKT plain: N=50, nx=8, nu=1 (n=450, m=400), Σ ~ logU[1e-2, 1e2]."""
     return nmpc_pattern(50, 8, 1), (1e-2, 1e2)
