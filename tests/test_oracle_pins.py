@@ -207,6 +207,24 @@ def test_small_lifted_vs_numpy(oracle_lib):
     assert ((ev > 0).sum(), (ev < 0).sum()) == (pat.n, pat.m)
 
 
+@pytest.mark.parametrize("n, m, dens, hubs", [(7, 3, 0.5, 0), (40, 30, 0.1, 0), (300, 200, 0.02, 2)])
+def test_general_patterns_vs_numpy(oracle_lib, n, m, dens, hubs):
+    """Unstructured patterns: the generator's W is symmetric positive definite
+    with eigenvalues >= 1 (diagonal dominance), and the oracle's sparse LDL^T
+    solve equals a dense solve of K to rounding."""
+    pat = kktgen.general_pattern(kktgen.rng_for(5, n, 0), n, m, dens, hub_cols=hubs)
+    v = kktgen.general_values(pat, kktgen.rng_for(5, n, 1), 1e-2, 1e2)
+    rows = np.repeat(np.arange(n), np.diff(pat.w_rowptr))
+    assert np.all(pat.w_colind <= rows) and np.all(np.isin(np.arange(n), pat.w_colind[pat.w_colind == rows]))
+    W = sp.coo_matrix((v.w_vals, (rows, pat.w_colind)), shape=(n, n)).toarray()
+    W = W + np.tril(W, -1).T
+    assert np.linalg.eigvalsh(W).min() >= 1.0 - 1e-9
+    K = D.condensed(pat, v, v.sigma_s)
+    x_np = np.linalg.solve(K.toarray(), v.b)
+    xc, info = S.lifted_solve(pat, v, v.b)
+    assert info["spd"] and D.forward_error(xc, x_np) < 1e-12
+
+
 def test_condensation_identity():
     """Augmented 3x3 solve == condensed solve; slack steps recovered as stated."""
     pat, v = kktgen.workload("small", instance=1)
