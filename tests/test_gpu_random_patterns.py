@@ -102,3 +102,37 @@ def test_general_patterns_batched_bitwise(kkt):
     for q in range(len(pats)):
         assert np.array_equal(xbh[ofs[q]:ofs[q + 1]], xs[q]), q
     B.close()
+
+
+# HyKKT needs J of full row rank: every row also holds a column of its own
+HYK_CASES = [(7, 3, 0.5, 0), (40, 30, 0.1, 0), (300, 200, 0.02, 2), (1500, 1200, 0.003, 3)]
+
+
+@pytest.mark.parametrize("gamma", [1e4, 1e7])
+@pytest.mark.parametrize("ci", range(len(HYK_CASES)), ids=[f"n{c[0]}" for c in HYK_CASES])
+def test_general_pattern_hykkt(kkt, ci, gamma):
+    """HyKKT (section "Solution 2: HyKKT") on unstructured patterns: dx and dy
+    within 1e-8 of the saddle-point LDL^T, eta of the 2x2 system <= 1e-10 (the
+    library's own eta within a factor 2 of the oracle's evaluation), CG
+    iterations within one of the oracle's CG on the same K_gamma."""
+    n, m, dens, hubs = HYK_CASES[ci]
+    pat = kktgen.general_pattern(kktgen.rng_for(6, ci, 0), n, m, dens, hub_cols=hubs, own_cols=True)
+    v = kktgen.general_values(pat, kktgen.rng_for(6, ci, 1), 1e-2, 1e2)
+    print(f"general hykkt n={n} m={m} gamma={gamma}", flush=True)
+    dx0, dy0, inn, ok = S.hykkt_saddle_solve(pat, v, v.f, v.g)
+    assert ok and inn == (pat.n, 0, pat.m)
+    f = kkt.Factor(kkt.Symbolic.from_pattern(pat, ordering=2, nd_leaf=64))
+    f.refactor(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), None, gamma)
+    assert f.status()[0] == 0
+    dx = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
+    dy = torch.zeros(pat.m, dtype=torch.float64, device="cuda")
+    info = f.cg_schur(dev(v.f), dev(v.g), dx, dy, tol=1e-10, maxit=300)
+    assert info["status"] == 0, info
+    dxh, dyh = host(dx), host(dy)
+    assert D.forward_error(dxh, dx0) <= 1e-8 and D.forward_error(dyh, dy0) <= 1e-8
+    be = D.hykkt_backward_errors(pat, v, dxh, dyh, v.f, v.g)
+    assert be["eta"] <= 1e-10 and info["eta"] <= 1e-10
+    assert abs(info["eta"] - be["eta"]) <= max(0.5 * be["eta"], 1e-15), (info, be)
+    _, _, oinfo = S.hykkt_cg_solve(pat, v, v.f, v.g, gamma, tol=1e-10, maxit=300)
+    assert abs(info["iters"] - oinfo["iters"]) <= 1, (info["iters"], oinfo["iters"])
+    f.close()
