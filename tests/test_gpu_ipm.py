@@ -37,6 +37,13 @@ def host(t):
 
 
 def qp_case(name):
+    if name.startswith("general"):
+        # unstructured W and J (diagonally dominant W, random J rows with shared columns)
+        n, m, dens, hubs = (300, 200, 0.02, 2) if name == "general300" else (1500, 1200, 0.003, 3)
+        pat = kktgen.general_pattern(kktgen.rng_for(7, n, 0), n, m, dens, hub_cols=hubs)
+        v = kktgen.general_values(pat, kktgen.rng_for(7, n, 1), 1e-2, 1e2)
+        rng = kktgen.rng_for(100, n, 0)
+        return pat, v, rng.standard_normal(n), 0.1 + rng.random(m)
     if name == "small":
         pat, v = kktgen.workload("small")
     else:
@@ -48,7 +55,7 @@ def qp_case(name):
     return pat, v, c, u
 
 
-@pytest.mark.parametrize("name", ["small", "distillation200"])
+@pytest.mark.parametrize("name", ["small", "distillation200", "general300", "general1500"])
 def test_ipm_matches_oracle(kkt, name):
     pat, v, c, u = qp_case(name)
     print(f"ipm {name} n={pat.n} m={pat.m}", flush=True)
