@@ -167,6 +167,49 @@ def test_inertia_correction_then_augmented(kkt):
     assert D.forward_error(z, D.bunch_kaufman(A).solve(p)) <= 1e-8
 
 
+def general_case(n=300):
+    pat = kktgen.general_pattern(kktgen.rng_for(97, n, 0), n, (2 * n) // 3, 0.02, hub_cols=2)
+    return pat, kktgen.general_values(pat, kktgen.rng_for(97, n, 1), 1e-2, 1e2)
+
+
+def test_general_pattern_augmented_and_inertia(kkt):
+    """Unstructured pattern: the augmented solve against Bunch-Kaufman on the
+    3x3 system; then Sigma_x made strongly negative on a random tenth of the
+    variables (K indefinite), the inertia correction's delta and trial count
+    equal the oracle's and the corrected factor solves K + delta I."""
+    pat, v = general_case()
+    r1, r2, r4 = rhs(pat, 11)
+    print(f"general augmented n={pat.n} m={pat.m}", flush=True)
+    info, dx, ds, dz, _ = augmented_run(kkt, pat, v, r1, r2, r4, ordering=2, nd_leaf=64)
+    assert info["status"] == 0, info
+    A = D.lifted_augmented(pat, v)
+    p = -np.concatenate([r1, r2, r4])
+    zs = D.bunch_kaufman(A).solve(p)
+    n, m = pat.n, pat.m
+    checks.assert_well_conditioned(dx, zs[:n], "dx")
+    checks.assert_well_conditioned(ds, zs[n:n + m], "ds")
+    checks.assert_well_conditioned(dz, zs[n + m:], "dz")
+    be = D.backward_errors(A, np.concatenate([dx, ds, dz]), p)
+    assert be["eta"] <= 1e-10 and info["eta"] <= 1e-10
+    # indefinite K
+    K = D.condensed(pat, v, v.sigma_s).toarray()
+    neg = kktgen.rng_for(97, n, 2).choice(n, n // 10, replace=False)
+    v.sigma_x[neg] -= 30.0 + np.linalg.eigvalsh(K).max()
+    print("general inertia correction", flush=True)
+    f = kkt.Factor(kkt.Symbolic.from_pattern(pat, ordering=2, nd_leaf=64))
+    dv = [dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), dev(v.sigma_s)]
+    f.refactor(*dv)
+    assert f.status()[0] == 4  # NOT_SPD without correction
+    ic = f.refactor_inertia(*dv)
+    delta, trials, _ = D.inertia_correction(pat, v)
+    assert ic["status"] == 0 and ic["delta"] == delta and ic["trials"] == len(trials), (ic, trials)
+    Kd = D.condensed(pat, v, v.sigma_s).toarray() + delta * np.eye(n)
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    si = f.solve(dev(v.b), x)
+    assert si["eta"] <= 1e-10
+    assert D.forward_error(host(x), np.linalg.solve(Kd, v.b)) <= 1e-8
+
+
 def test_augmented_refused_on_hykkt_factor(kkt):
     pat, v = kktgen.workload("hykkt")
     f = kkt.Factor(kkt.Symbolic.from_pattern(pat))
