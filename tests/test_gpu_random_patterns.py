@@ -136,3 +136,27 @@ def test_general_pattern_hykkt(kkt, ci, gamma):
     _, _, oinfo = S.hykkt_cg_solve(pat, v, v.f, v.g, gamma, tol=1e-10, maxit=300)
     assert abs(info["iters"] - oinfo["iters"]) <= 1, (info["iters"], oinfo["iters"])
     f.close()
+
+
+def test_general_patterns_served(kkt):
+    """The served form over the unstructured patterns (several requests per
+    pattern, waves of up to 4 on 2 workers): each result equals the plain
+    solve of its request bit for bit."""
+    pats, vals = zip(*(case(ci) for ci in range(len(CASES))))
+    syms = [kkt.Symbolic.from_pattern(p, ordering=2, nd_leaf=64) for p in pats]
+    xs = [plain(kkt, s, p, v)[0] for s, p, v in zip(syms, pats, vals)]
+    srv = kkt.Server(hbm_budget=1 << 30, max_wave=4, workers=2)
+    pid = [srv.register(s) for s in syms]
+    order = [q for _ in range(3) for q in range(len(pats))]
+    # the server reads the request's arrays asynchronously: they stay alive until wait
+    held, outs, tickets = [], [], []
+    for q in order:
+        v = vals[q]
+        held.append([dev(getattr(v, k)) for k in ("w_vals", "j_vals", "sigma_x", "sigma_s", "b")])
+        outs.append(torch.zeros(pats[q].n, dtype=torch.float64, device="cuda"))
+        tickets.append(srv.submit(pid[q], *held[-1], outs[-1]))
+    res = [srv.wait(t) for t in tickets]
+    assert all(r["status"] == 0 and r["eta"] <= 1e-10 for r in res), res
+    for k, q in enumerate(order):
+        assert np.array_equal(host(outs[k]), xs[q]), (k, q)
+    srv.close()
