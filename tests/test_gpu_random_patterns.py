@@ -160,3 +160,36 @@ def test_general_patterns_served(kkt):
     for k, q in enumerate(order):
         assert np.array_equal(host(outs[k]), xs[q]), (k, q)
     srv.close()
+
+
+def test_general_patterns_queue_schedule_bitwise(kkt):
+    """The persistent queue schedule on the unstructured trees (up to 67
+    levels, fronts of up to 979 rows) gives the level schedule's solutions
+    bit for bit, one factor per pattern and all patterns in one batch."""
+    pats, vals = zip(*(case(ci) for ci in range(len(CASES))))
+    syms = [kkt.Symbolic.from_pattern(p, ordering=2, nd_leaf=64) for p in pats]
+    xs = []
+    for s, p, v in zip(syms, pats, vals):
+        f = kkt.Factor(s)
+        out = []
+        for sched in (kkt.SCHEDULE_LEVELS, kkt.SCHEDULE_QUEUE):
+            f.set_schedule(sched)
+            f.refactor(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), dev(v.sigma_s))
+            assert f.status()[0] == 0
+            x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+            assert f.solve(dev(v.b), x)["eta"] <= 1e-10
+            out.append(host(x))
+        assert np.array_equal(out[0], out[1]), p.n
+        xs.append(out[0])
+        f.close()
+    B = kkt.Batch(syms)
+    B.set_schedule(kkt.SCHEDULE_QUEUE)
+    cat = lambda k: dev(np.concatenate([getattr(v, k) for v in vals]))
+    B.refactor(cat("w_vals"), cat("j_vals"), cat("sigma_x"), cat("sigma_s"))
+    xb = torch.zeros(sum(p.n for p in pats), dtype=torch.float64, device="cuda")
+    assert all(i["eta"] <= 1e-10 for i in B.solve(cat("b"), xb))
+    xbh = host(xb)
+    ofs = np.concatenate([[0], np.cumsum([p.n for p in pats])])
+    for q in range(len(pats)):
+        assert np.array_equal(xbh[ofs[q]:ofs[q + 1]], xs[q]), q
+    B.close()
