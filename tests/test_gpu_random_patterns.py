@@ -193,3 +193,27 @@ def test_general_patterns_queue_schedule_bitwise(kkt):
     for q in range(len(pats)):
         assert np.array_equal(xbh[ofs[q]:ofs[q + 1]], xs[q]), q
     B.close()
+
+
+@pytest.mark.parametrize("opts", OPTS[1:], ids=["nd64", "lds16k"])
+def test_general_patterns_launch_shapes_bitwise(kkt, opts):
+    """The per-level launch shapes (four- or eight-wave front kernel, update
+    matrices in the front's workgroup or by tiles) give the same bits on the
+    unstructured trees, whose fronts (up to about 1,000 rows) are far taller
+    than the four-wave kernel's fused panel path (208 rows)."""
+    for ci in (3, 4):
+        pat, v = case(ci)
+        sym = kkt.Symbolic.from_pattern(pat, **opts)
+        xs = []
+        for small, split in ((0, (140, 64)), (1 << 20, (140, 64)), (1 << 20, (0, 0)), (0, (1 << 30, 0))):
+            f = kkt.Factor(sym)
+            f.set_small_fronts(small)
+            f.set_update_split(*split)
+            f.refactor(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), dev(v.sigma_s))
+            assert f.status()[0] == 0
+            x = torch.zeros(pat.n, dtype=torch.float64, device="cuda")
+            assert f.solve(dev(v.b), x)["eta"] <= 1e-10, (small, split)
+            xs.append(host(x))
+            f.close()
+        for k in range(1, len(xs)):
+            assert np.array_equal(xs[0], xs[k]), (pat.n, k)
