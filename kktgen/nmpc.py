@@ -280,23 +280,32 @@ def hub_values(pat: Pattern, rng: np.random.Generator, sigma_lo: float, sigma_hi
 # --------------------------------------------------------------------------
 
 def general_pattern(rng: np.random.Generator, n: int, m: int, density: float, row_max: int = 5,
-                    hub_cols: int = 0, hub_frac: float = 0.5, own_cols: bool = False) -> Pattern:
+                    hub_cols: int = 0, hub_frac: float = 0.5, own_cols: bool = False, band: int = 0) -> Pattern:
     """Unstructured pattern: W's row i holds its diagonal and each earlier
     column with probability `density`; J's rows hold 0 .. row_max random
     columns, plus each of the last `hub_cols` columns with probability
     `hub_frac` (columns shared by many rows: entries of J^T J with long
     product lists). With own_cols (m <= n), row r also holds column q_r of
-    a random permutation q, so J has full row rank for random values."""
+    a random permutation q, so J has full row rank for random values. With
+    band > 0 every entry lies within `band` of the diagonal (W's row i draws
+    from columns i-band .. i-1, J's row from a window of width band at a
+    random place), as on a one-dimensional mesh."""
     w_rows = []
     for i in range(n):
-        lower = np.flatnonzero(rng.random(i) < density) if i else np.zeros(0, np.int64)
+        lo = max(0, i - band) if band else 0
+        lower = lo + np.flatnonzero(rng.random(i - lo) < density) if i > lo else np.zeros(0, np.int64)
         w_rows.append(np.append(lower, i))
     hubs = np.arange(n - hub_cols, n) if hub_cols else np.zeros(0, np.int64)
     assert not own_cols or m <= n
     own = rng.permutation(n)[:m] if own_cols else None
     j_rows = []
     for r in range(m):
-        cols = rng.choice(n, size=min(n, int(rng.integers(0, row_max + 1))), replace=False)
+        k = int(rng.integers(0, row_max + 1))
+        if band:
+            a = int(rng.integers(0, max(1, n - band)))
+            cols = a + rng.choice(min(band, n), size=min(k, band, n), replace=False)
+        else:
+            cols = rng.choice(n, size=min(n, k), replace=False)
         if hub_cols:
             cols = np.concatenate([cols, hubs[rng.random(hub_cols) < hub_frac]])
         if own_cols:

@@ -217,3 +217,25 @@ def test_general_patterns_launch_shapes_bitwise(kkt, opts):
             f.close()
         for k in range(1, len(xs)):
             assert np.array_equal(xs[0], xs[k]), (pat.n, k)
+
+
+@pytest.mark.parametrize("opts", [dict(ordering=1), dict(ordering=2, nd_leaf=200), dict(ordering=0)],
+                         ids=["natural", "nd200", "auto"])
+def test_banded_pattern_at_scale(kkt, opts):
+    """A band-limited unstructured pattern (n = 20,000, m = 16,000, entries
+    within 40 of the diagonal, as on a one-dimensional mesh): the natural
+    order gives a chain of about 255 fronts, nested dissection a tree of
+    about 11 levels; both solve to eta <= 1e-10 and the oracle's solution
+    within 1e-8."""
+    pat = kktgen.general_pattern(kktgen.rng_for(8, 0, 0), 20000, 16000, 0.3, row_max=6, band=40)
+    v = kktgen.general_values(pat, kktgen.rng_for(8, 0, 1), 1e-2, 1e2)
+    sym = kkt.Symbolic.from_pattern(pat, **opts)
+    st_ = sym.stats()
+    print(f"banded n=20000 {opts}: {st_['nsuper']} fronts, {st_['levels']} levels", flush=True)
+    x, info = plain(kkt, sym, pat, v)
+    K = D.condensed(pat, v, v.sigma_s)
+    be = D.backward_errors(K, x, v.b)
+    assert info["eta"] <= 1e-10 and be["eta"] <= 1e-10, (info, be)
+    xo, oinfo = S.lifted_solve(pat, v, v.b)
+    assert oinfo["spd"]
+    checks.assert_well_conditioned(x, xo)
