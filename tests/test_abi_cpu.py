@@ -214,6 +214,21 @@ def test_stagewise_rejects_bad_stages(kkt):
         assert e.status == 2
 
 
+def test_stagewise_banded_pattern_stage_width(kkt):
+    """A band-limited unstructured pattern (entries within 40 of the
+    diagonal) is block tridiagonal over stages at least 40 wide; stages of
+    30 put entries two stages apart: PATTERN (2) on the host."""
+    import kktgen
+    pat = kktgen.general_pattern(kktgen.rng_for(8, 0, 0), 2000, 1600, 0.3, row_max=6, band=40)
+    s = kkt.Symbolic.from_pattern(pat)
+    sp = np.append(np.arange(0, pat.n, 30), pat.n).astype(np.int32)
+    try:
+        kkt.Stagewise([s], [sp])
+        raise AssertionError("accepted stages narrower than the band")
+    except kkt.KKTError as e:
+        assert e.status == 2
+
+
 def _front_lds(r, c):
     # LDS of a front panel in the factor and sweep kernels (host layout rule)
     fac = (r | 1) * ((c + 15) // 16 * 16) * 8 + r * 4 + 16
