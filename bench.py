@@ -68,6 +68,8 @@ def parse():
                     help="only run one plain device copy of this many MiB (HBM counter calibration) and exit")
     ap.add_argument("--serve-requests", type=int, default=10000, help="requests per arrival rate of the served "
                                                                         "workload (0: skip)")
+    ap.add_argument("--serve-workers", type=int, default=2, help="workers (streams) of the continuous-batching "
+                                                                  "server")
     ap.add_argument("--serve-rho", default="0.5,0.8,1.2,2.0", help="arrival rates as fractions of the plain solver's "
                                                                  "capacity (comma-separated)")
     args = ap.parse_args()
@@ -534,7 +536,7 @@ def bench_served(args, kkt, kktgen, torch, dev):
         return {k: (round(st[k] * 1e3, 3) if k.endswith("_s") else round(st[k], 3)) for k in
                 ("p50_s", "p99_s", "mean_queue_s", "mean_service_s", "throughput", "mean_wave")}
 
-    cb = kkt.Server(hbm_budget=16 << 30, max_wave=64, workers=2)
+    cb = kkt.Server(hbm_budget=16 << 30, max_wave=64, workers=args.serve_workers)
     cid = [cb.register(s) for s in syms]
     by_rho = []
     for rho in [float(r) for r in str(args.serve_rho).split(",") if r]:
@@ -550,7 +552,7 @@ def bench_served(args, kkt, kktgen, torch, dev):
     plain.close()
     cb.close()
     return dict(patterns=16, n_range=[min(p.n for p in pats), max(p.n for p in pats)], requests_per_rate=nreq,
-                warmup_discarded=warm, plain_capacity_per_s=round(capacity, 2),
+                warmup_discarded=warm, plain_capacity_per_s=round(capacity, 2), workers=args.serve_workers,
                 units="latencies in ms, throughput in requests/s", by_rho=by_rho)
 
 
