@@ -261,3 +261,39 @@ def test_banded_pattern_stagewise(kkt):
     assert be["eta"] <= 1e-10 and info["eta"] <= 1e-10, (info, be)
     xo, oinfo = S.lifted_solve(pat, v, v.b)
     checks.assert_well_conditioned(xh, xo)
+
+
+WIDE = [(128, 0), (128, 64), (129, 64), (150, 60), (200, 100)]
+
+
+def test_widest_supernodes(kkt):
+    """The widest supernode the library allows (128 columns, max_super = 128):
+    dense W blocks give fronts of 128 columns and 128-150 rows (up to 155 KB
+    of LDS), the widest triangle of the sweeps' one-wave solve (two rows per
+    lane) and 32 matrix-core steps per update tile; each against the oracle,
+    and a batch of all of them bitwise equal to the plain solves."""
+    pats, vals, syms, xs = [], [], [], []
+    for n, m in WIDE:
+        pat = kktgen.general_pattern(kktgen.rng_for(9, n, m), n, m, 1.0)
+        v = kktgen.general_values(pat, kktgen.rng_for(9, n, m + 1), 1e-2, 1e2)
+        sym = kkt.Symbolic.from_pattern(pat, ordering=1, max_super=128)
+        st_ = sym.stats()
+        print(f"dense n={n} m={m}: {st_['nsuper']} fronts, up to {st_['max_cols']} columns", flush=True)
+        assert st_["max_cols"] == 128 or n == 200
+        x, info = plain(kkt, sym, pat, v)
+        K = D.condensed(pat, v, v.sigma_s)
+        be = D.backward_errors(K, x, v.b)
+        assert info["eta"] <= 1e-10 and be["eta"] <= 1e-10, (n, info, be)
+        xo, oinfo = S.lifted_solve(pat, v, v.b)
+        checks.assert_well_conditioned(x, xo, n)
+        pats.append(pat), vals.append(v), syms.append(sym), xs.append(x)
+    B = kkt.Batch(syms)
+    cat = lambda k: dev(np.concatenate([getattr(v, k) for v in vals]))
+    B.refactor(cat("w_vals"), cat("j_vals"), cat("sigma_x"), cat("sigma_s"))
+    xb = torch.zeros(sum(p.n for p in pats), dtype=torch.float64, device="cuda")
+    assert all(i["eta"] <= 1e-10 for i in B.solve(cat("b"), xb))
+    xbh = host(xb)
+    ofs = np.concatenate([[0], np.cumsum([p.n for p in pats])])
+    for q in range(len(pats)):
+        assert np.array_equal(xbh[ofs[q]:ofs[q + 1]], xs[q]), q
+    B.close()
