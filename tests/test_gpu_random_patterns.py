@@ -1,18 +1,23 @@
 """Unstructured sparsity patterns through the HIP path, against the oracle
 (run on an MI355X).
 
-The Lifted-KKT solve of section "Solution 1: Lifted-KKT" applies to any
-sparsity of W and J; these patterns have no stage structure. W: a random
-lower pattern with its diagonal and diagonally dominant values (eigenvalues
->= 1); J: random rows of up to 5 columns (some empty), and in the larger
-cases columns shared by about half the rows (entries of J^T Sigma_s J with
-long product lists, assembled 16 lanes per entry); Sigma ~ logU[1e-2, 1e2].
-Such patterns fill in heavily (n = 1,500: nnz(L) about 0.69 M, fronts of up
-to 979 rows), so they reach supernode shapes the NMPC generators never
-produce; a 16 KiB LDS budget sends the tall fronts through the HBM path.
+The Newton-step solves of sections "Solution 1: Lifted-KKT" and "Solution 2:
+HyKKT" apply to any sparsity of W and J; these patterns have no stage
+structure. W: a random lower pattern with its diagonal and diagonally
+dominant values (eigenvalues >= 1); J: random rows of up to 5 columns (some
+empty), and in the larger cases columns shared by about half the rows
+(entries of J^T Sigma_s J with long product lists, assembled 16 lanes per
+entry); Sigma ~ logU[1e-2, 1e2]. Such patterns fill in heavily (n = 1,500:
+nnz(L) about 0.69 M, fronts of up to 979 rows), so they reach supernode
+shapes the NMPC generators never produce; a 16 KiB LDS budget sends the
+tall fronts through the HBM path. Also here: HyKKT with a full-row-rank J,
+the served form, the queue schedule and the per-level launch shapes on these
+trees, a band-limited pattern at n = 20,000 (also through the
+stage-structured solver), and the widest supernodes allowed (128 columns).
 Tolerances as in test_gpu_parity: eta <= 1e-10 against the oracle's K;
 forward error and entrywise error (|x - x*| <= 1e-8 |x*| + 1e-12 ||x*||_inf)
-<= 1e-8 against the oracle's solution; batched equal to plain bit for bit.
+<= 1e-8 against the oracle's solution; batched, served, queue-schedule and
+launch-shape variants equal to the plain level-schedule solve bit for bit.
 """
 import numpy as np
 import pytest
