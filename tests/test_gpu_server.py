@@ -4,7 +4,8 @@ Gates: every served result has eta <= 1e-10 against the oracle evaluator;
 a request's result is bitwise the same served alone (waves of one) and in a
 mix of many concurrent requests of different patterns (A20's design goal;
 the gate is bitwise); a request that cannot fit the HBM budget is refused
-with BUDGET; statistics count every request.
+with BUDGET; statistics count every request; a request whose factor fails
+(NOT_SPD) fails alone, its wave's other requests unchanged bit for bit.
 """
 import numpy as np
 import pytest
@@ -131,3 +132,57 @@ def test_small_budget_forces_small_waves(kkt):
         K = D.condensed(pats[p], v, v.sigma_s)
         assert D.backward_errors(K, x.cpu().numpy(), v.b)["eta"] <= 1e-10
     srv.close()
+
+
+def test_served_failure_isolated(kkt):
+    """A request whose K is not positive definite (Sigma_x strongly negative on
+    some variables) fails with NOT_SPD (4) alone: the other requests of its
+    waves finish with status 0 and the results they get alone, bit for bit;
+    the server keeps serving afterwards."""
+    pats = patterns(3)
+    syms = [kkt.Symbolic.from_pattern(p) for p in pats]
+    bad_q = 4
+    reqs = [(q % 3, q) for q in range(9)]
+    vals = []
+    for p, q in reqs:
+        v = values(pats[p], p, 200 + q)
+        if q == bad_q:
+            v.sigma_x[: pats[p].n // 4] = -1e9
+        vals.append(v)
+    # alone: waves of one
+    alone = kkt.Server(hbm_budget=2 << 30, max_wave=1, workers=1)
+    pid = [alone.register(s) for s in syms]
+    xa, keep = [], []
+    for (p, q), v in zip(reqs, vals):
+        if q == bad_q:
+            xa.append(None)
+            continue
+        x = torch.zeros(pats[p].n, dtype=torch.float64, device="cuda")
+        keep.append(upload(v))
+        assert alone.wait(alone.submit(pid[p], *keep[-1], x))["status"] == 0
+        xa.append(x.cpu().numpy())
+    alone.close()
+    # mixed: one wave of all nine on one worker, the failing request among them
+    mix = kkt.Server(hbm_budget=2 << 30, max_wave=16, workers=1, linger_us=20000.0)
+    pid = [mix.register(s) for s in syms]
+    xs, tickets, keep = [], [], []
+    for (p, q), v in zip(reqs, vals):
+        x = torch.zeros(pats[p].n, dtype=torch.float64, device="cuda")
+        xs.append(x)
+        keep.append(upload(v))
+        tickets.append(mix.submit(pid[p], *keep[-1], x))
+    res = [mix.wait(t) for t in tickets]
+    for (p, q), r, x, a in zip(reqs, res, xs, xa):
+        if q == bad_q:
+            assert r["status"] == 4, r
+        else:
+            assert r["status"] == 0, (q, r)
+            assert np.array_equal(x.cpu().numpy(), a), q
+    # still serving
+    p, v = 0, values(pats[0], 0, 300)
+    x = torch.zeros(pats[0].n, dtype=torch.float64, device="cuda")
+    keep.append(upload(v))
+    assert mix.wait(mix.submit(pid[p], *keep[-1], x))["status"] == 0
+    K = D.condensed(pats[0], v, v.sigma_s)
+    assert D.backward_errors(K, x.cpu().numpy(), v.b)["eta"] <= 1e-10
+    mix.close()
