@@ -99,6 +99,22 @@ def test_batch_failure_isolated(kkt):
     st, bad = B.status()
     assert st[bad_q] == 4 and all(st[q] == 0 for q in range(count) if q != bad_q)
     assert bad[bad_q] >= 0
+    # the solve still serves the other instances: each equals its plain solve bit for bit
+    x = torch.zeros(sum(p.n for p in pats), dtype=torch.float64, device="cuda")
+    with pytest.raises(kkt.KKTError) as ei:
+        B.solve(concat(vals, "b"), x)
+    assert ei.value.status == 4
+    xb = x.cpu().numpy()
+    o = 0
+    for q, (p, v, sym) in enumerate(zip(pats, vals, syms)):
+        if q != bad_q:
+            f = kkt.Factor(sym)
+            f.refactor(dev(v.w_vals), dev(v.j_vals), dev(v.sigma_x), dev(v.sigma_s))
+            xq = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+            f.solve(dev(v.b), xq)
+            assert np.array_equal(xb[o:o + p.n], xq.cpu().numpy()), q
+            f.close()
+        o += p.n
 
 
 def test_batch_shared_symbolic(kkt):
