@@ -42,8 +42,14 @@ def host(t):
 
 @pytest.mark.parametrize("gamma", [1e4, 1e7])
 @pytest.mark.parametrize("split", ["alternate", "first_half"])
-def test_general_hykkt_matches_oracle(kkt, gamma, split):
-    pat, v = kktgen.workload("small", instance=3)
+@pytest.mark.parametrize("shape", ["nmpc", "unstructured"])
+def test_general_hykkt_matches_oracle(kkt, gamma, split, shape):
+    if shape == "nmpc":
+        pat, v = kktgen.workload("small", instance=3)
+    else:
+        # no stage structure; every row of J holds a column of its own (full row rank)
+        pat = kktgen.general_pattern(kktgen.rng_for(99, 0, 0), 300, 200, 0.02, hub_cols=2, own_cols=True)
+        v = kktgen.general_values(pat, kktgen.rng_for(99, 0, 1), 1e-2, 1e2)
     eq = np.arange(0, pat.m, 2) if split == "alternate" else np.arange(pat.m // 2)
     G, H, dsw, eqi, ineq = D.split_rows(pat, v, eq)
     n, me, mi = pat.n, len(eqi), len(ineq)
@@ -52,7 +58,7 @@ def test_general_hykkt_matches_oracle(kkt, gamma, split):
     fv = -(r1 + H.T @ (dsw * r4 - r2))
     g = np.zeros(pat.m)
     g[eqi] = -r3
-    print(f"general hykkt gamma={gamma} split={split}", flush=True)
+    print(f"general hykkt {shape} gamma={gamma} split={split}", flush=True)
     f = kkt.Factor(kkt.Symbolic.from_pattern(pat, ordering=2, nd_leaf=64))
     f.set_equality_rows(eq)
     with pytest.raises(kkt.KKTError):
