@@ -225,6 +225,21 @@ def test_general_patterns_vs_numpy(oracle_lib, n, m, dens, hubs):
     assert info["spd"] and D.forward_error(xc, x_np) < 1e-12
 
 
+def test_general_generator_structure():
+    """The unstructured generator keeps its promises: with band > 0 every entry
+    of W and J lies within the band, and with own_cols J has full row rank."""
+    pat = kktgen.general_pattern(kktgen.rng_for(8, 0, 0), 2000, 1600, 0.3, row_max=6, band=40)
+    rows = np.repeat(np.arange(pat.n), np.diff(pat.w_rowptr))
+    assert np.all(rows - pat.w_colind <= 40) and np.all(pat.w_colind <= rows)
+    for r in range(pat.m):
+        c = pat.j_colind[pat.j_rowptr[r]:pat.j_rowptr[r + 1]]
+        assert c.size == 0 or c.max() - c.min() < 40
+    pat = kktgen.general_pattern(kktgen.rng_for(6, 2, 0), 300, 200, 0.02, hub_cols=2, own_cols=True)
+    v = kktgen.general_values(pat, kktgen.rng_for(6, 2, 1), 1e-2, 1e2)
+    J = sp.csr_matrix((v.j_vals, pat.j_colind, pat.j_rowptr), shape=(pat.m, pat.n)).toarray()
+    assert np.linalg.matrix_rank(J) == pat.m
+
+
 def test_condensation_identity():
     """Augmented 3x3 solve == condensed solve; slack steps recovered as stated."""
     pat, v = kktgen.workload("small", instance=1)
