@@ -1095,58 +1095,60 @@ __device__ inline unsigned big_diag_chain(const double* P, int ld, int r, int j0
     return bad;
 }
 
-// Assembly of large fronts: workgroup (f, b) takes column block b of large
-// front f: zeroes its columns, writes K's entries in them, then adds the
-// children's update entries whose column maps into them, child by child
-// (the entries of one child are distinct; a child's update columns mapping
-// into the block are a contiguous range, its relative rows being ascending).
+// Assembly of large fronts: workgroup (f, b, z) takes column block b and
+// rows 256 z .. 256 z + 255 of large front f: zeroes that part of its
+// columns, writes K's entries there, then adds the children's update entries
+// that land there, child by child (the entries of one child are distinct; a
+// child's update columns mapping into the block, and its update rows mapping
+// into the row range, are contiguous ranges, its relative rows being
+// ascending). Every entry belongs to one workgroup and takes the same
+// operations in the same order as with whole columns per workgroup.
+constexpr int kBigInitRows = 256;
 __global__ __launch_bounds__(kBigThreads) void k_big_init(const InstDev* __restrict__ insts,
                                                         const FrontDesc* __restrict__ fds) {
     const FrontDesc& F = fds[blockIdx.x];
     const int c = F.c, r = F.r, ld = r | 1;
-    const int b0 = blockIdx.y << 4;
-    if (b0 >= c) return;
-    const int b1 = min(c, b0 + 16);
+    const int b0 = blockIdx.y << 4, r0 = (int)blockIdx.z * kBigInitRows;
+    if (b0 >= c || r0 >= r) return;
+    const int b1 = min(c, b0 + 16), r1 = min(r, r0 + kBigInitRows), nr = r1 - r0;
     const InstDev& I = insts[F.inst];
     const PatDev& T = I.P;
     double* const P = F.L;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int64_t q0 = (int64_t)b0 * ld, q1 = (int64_t)b1 * ld;
-    for (int64_t q = q0 + tid; q < q1; q += nt) P[q] = 0.0;
+    for (int q = tid; q < (b1 - b0) * nr; q += nt) {
+        const int col = b0 + q / nr, row = r0 + (q - (q / nr) * nr);
+        P[(int64_t)col * ld + row] = 0.0;
+    }
     __syncthreads();
     for (int q = tid; q < F.nk; q += nt) {
         const int loc = F.kl[q];
-        const int col = loc >> 16;
-        if (col >= b0 && col < b1) P[(int64_t)col * ld + (loc & 0xffff)] = F.kv[q];
+        const int col = loc >> 16, row = loc & 0xffff;
+        if (col >= b0 && col < b1 && row >= r0 && row < r1) P[(int64_t)col * ld + row] = F.kv[q];
     }
     __syncthreads();
+    // first index of the ascending rl[0 .. n) at or above v
+    auto lower = [](const int* rl, int n, int v) {
+        int lo = 0, hi = n;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (rl[mid] < v) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
     for (int k = 0; k < F.nch; k++) {
         const int ch = T.ch_list[F.ch0 + k];
         const int cc = T.sn_ncol[ch];
         const int uc = T.sn_nrow[ch] - cc, nb = T.rel_np[ch];
         const double* const Uc = I.U + T.sn_uofs[ch];
         const int* const rl = T.rel + T.sn_rowofs[ch] + cc;
-        // child update columns e0 .. e1-1 map into columns b0 .. b1-1
-        int e0 = 0, e1 = nb;
-        {
-            int lo = 0, hi = nb;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (rl[mid] < b0) lo = mid + 1;
-                else hi = mid;
-            }
-            e0 = lo;
-            hi = nb;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (rl[mid] < b1) lo = mid + 1;
-                else hi = mid;
-            }
-            e1 = lo;
-        }
-        const int64_t ctot = (int64_t)(e1 - e0) * uc;
+        // child update columns e0 .. e1-1 map into columns b0 .. b1-1, its
+        // update rows a0 .. a1-1 into rows r0 .. r1-1
+        const int e0 = lower(rl, nb, b0), e1 = lower(rl, nb, b1);
+        const int a0 = lower(rl, uc, r0), a1 = lower(rl, uc, r1), na = a1 - a0;
+        const int64_t ctot = (int64_t)(e1 - e0) * na;
         for (int64_t q = tid; q < ctot; q += nt) {
-            const int b = e0 + (int)(q / uc), a = (int)(q - (int64_t)(b - e0) * uc);
+            const int b = e0 + (int)(q / na), a = a0 + (int)(q - (int64_t)(b - e0) * na);
             if (a >= b) P[(int64_t)rl[b] * ld + rl[a]] += Uc[(int64_t)b * uc + a];
         }
         __syncthreads();
@@ -3559,7 +3561,7 @@ void launch_big_factor(const InstDev* insts, const FrontDesc* fds, int nitems, i
                        hipStream_t st) {
     if (nitems <= 0) return;
     const int nbc = (max_cols + 15) / 16, nbr = (max_rows + 15) / 16;
-    k_big_init<<<dim3(nitems, nbc), kBigThreads, 0, st>>>(insts, fds);
+    k_big_init<<<dim3(nitems, nbc, (max_rows + kBigInitRows - 1) / kBigInitRows), kBigThreads, 0, st>>>(insts, fds);
     for (int kb = 0; kb < nbc; kb++) {
         const int below = max_rows - 16 * kb - 16;
         if (below > 0) k_big_trsm<<<dim3(nitems, (below + kBigThreads - 1) / kBigThreads), kBigThreads, 0, st>>>(fds, kb);
